@@ -1,0 +1,110 @@
+/*
+ * FP64 CPU oracle for the reduced-Newton hot path of a Lipschitz-optimised
+ * neural-subspace solver (Lyu et al., ACM TOG 43(6), 2024).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.  It shares no
+ * source, header, table or helper with the GPU library.
+ *
+ * Everything is float64, row-major, one item at a time (OpenMP over items).
+ * Second derivatives of the decoder are taken by naive forward-over-forward
+ * differentiation, never by the adjoint identity the GPU library uses.
+ */
+#ifndef RS_ORACLE_H
+#define RS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    /* mesh: nv vertices X (nv x 3), ne tets (ne x 4), pinned[v]=1 fixes v at rest */
+    int nv, ne;
+    const double* X;
+    const int* tets;
+    const unsigned char* pinned;
+    /* material: Young's modulus, Poisson ratio, density, gravity vector */
+    double young, poisson, density, gravity[3];
+    /* decoder: r -> L hidden layers of `width` (ELU) -> n_out = 3 nv (linear).
+     * W[l] is (out x in) row-major, b[l] has `out` entries, l = 0..L. */
+    int r, L, width, n_out;
+    const double* const* W;
+    const double* const* b;
+    /* cubature: S elements with weights */
+    int S;
+    const int* cub_elem;
+    const double* cub_w;
+    /* penalty-targeted vertices (stiffness k_c) and force-loaded vertices */
+    int nt;
+    const int* target_vtx;
+    double k_c;
+    int nf;
+    const int* force_vtx;
+} or_problem;
+
+typedef struct {
+    int max_iter;      /* Newton iterations (accepted steps) */
+    int ls_max;        /* backtracking trials per iteration */
+    double c1;         /* Armijo constant */
+    double shrink;     /* step factor per trial */
+    double rel_tol;    /* stop when |g|_inf <= rel_tol |g_0|_inf */
+    double abs_tol;    /* ... or when |g|_inf <= abs_tol */
+    int hess;          /* 0 Gauss-Newton, 1 exact */
+    int proj;          /* 0 clamp eigenvalues, 1 absolute eigenvalues, 2 none */
+    double eig_floor;  /* eigenvalue floor relative to max |eig| */
+} or_opts;
+
+enum { OR_CONVERGED = 0, OR_NOT_DESCENT = 1, OR_LS_MAX = 2, OR_ITER_MAX = 3, OR_NONFINITE = 4 };
+enum { OR_EXACT = 1, OR_ELASTIC_ONLY = 2, OR_ENERGY_ONLY = 4 };
+
+/* material and stable Neo-Hookean density (F is 3x3 row-major) */
+void or_lame(double young, double poisson, double* mu, double* lam);
+double or_psi(const double* F, double mu, double lam);
+void or_pk1(const double* F, double mu, double lam, double* P);
+void or_dpdf(const double* F, double mu, double lam, double* A); /* 9x9, vec = column-major */
+
+/* one tetrahedron: rest corners Xe (4x3), deformed corners xe (4x3) */
+void or_rest(const double* Xe, double* Dminv, double* V);
+double or_elem_energy(const double* Xe, const double* xe, double mu, double lam);
+void or_elem_grad(const double* Xe, const double* xe, double mu, double lam, double* g12);
+void or_elem_hess(const double* Xe, const double* xe, double mu, double lam, double* H144);
+
+void or_lumped_mass(const or_problem* p, double* m);
+
+/* decoder: x (B x nv x 3) deformed positions, J (B x n x r) nullable */
+int or_decode(const or_problem* p, int B, const double* z, double* x, double* J);
+/* second derivatives of the deformed positions, one item: T (n x r x r) */
+int or_decode_hess(const or_problem* p, const double* z, double* T);
+
+/* reduced energy / gradient / Hessian at B latent points.
+ * targets (B x nt x 3) and force (B x 3, applied to each force vertex) nullable. */
+int or_reduced(const or_problem* p, int B, const double* z, const double* targets,
+               const double* force, int flags, double* E, double* g, double* H);
+
+/* reduced projective Newton with backtracking line search, z in/out */
+int or_newton(const or_problem* p, int B, double* z, const double* targets,
+              const double* force, const or_opts* o, int* iters, int* status,
+              double* relgrad, double* E);
+
+/* full-space Newton on the free DOFs over every mesh element (weight 1).
+ * elem_psd=1 projects each 12x12 element Hessian to PSD; else the same
+ * global policy as or_newton.  x (nv x 3) in/out. */
+int or_full_newton(const or_problem* p, double* x, const double* targets,
+                   const double* force, const or_opts* o, int elem_psd,
+                   int* iters, int* status, double* relgrad, double* E);
+/* full-space energy / gradient (nv x 3) at x */
+double or_full_energy(const or_problem* p, const double* x, const double* targets,
+                      const double* force, double* grad);
+
+/* Lipschitz loss of the cubature elastic Hessian over pairs (z1_b, z2_b). */
+int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
+                 double* loss, double* per_pair, int* n_valid, double* lip_max);
+
+/* symmetric eigen-decomposition by cyclic Jacobi (exposed for pins) */
+void or_sym_eig(int n, const double* A, double* evals, double* evecs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,268 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The library's product path never imports
+this module.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE = 0, 1, 2, 3, 4
+EXACT, ELASTIC_ONLY, ENERGY_ONLY = 1, 2, 4
+PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
+
+
+def build(verbose: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    src = os.path.join(HERE, "oracle.c")
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+           "-o", LIB + ".tmp", src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nv", C.c_int), ("ne", C.c_int), ("X", _dp), ("tets", _ip),
+                ("pinned", C.POINTER(C.c_ubyte)),
+                ("young", C.c_double), ("poisson", C.c_double), ("density", C.c_double),
+                ("gravity", C.c_double * 3),
+                ("r", C.c_int), ("L", C.c_int), ("width", C.c_int), ("n_out", C.c_int),
+                ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp)),
+                ("S", C.c_int), ("cub_elem", _ip), ("cub_w", _dp),
+                ("nt", C.c_int), ("target_vtx", _ip), ("k_c", C.c_double),
+                ("nf", C.c_int), ("force_vtx", _ip)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("ls_max", C.c_int), ("c1", C.c_double),
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double),
+                ("hess", C.c_int), ("proj", C.c_int), ("eig_floor", C.c_double)]
+
+
+def default_opts(**kw) -> Opts:
+    d = dict(max_iter=50, ls_max=128, c1=1e-4, shrink=0.5, rel_tol=1e-6, abs_tol=0.0,
+             hess=1, proj=PROJ_CLAMP, eig_floor=1e-8)
+    d.update(kw)
+    return Opts(**d)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.or_psi.restype = C.c_double
+        L.or_elem_energy.restype = C.c_double
+        L.or_full_energy.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --- single-tet / material level --------------------------------------------
+def lame(young, poisson):
+    mu, lam = C.c_double(), C.c_double()
+    lib().or_lame(C.c_double(young), C.c_double(poisson), C.byref(mu), C.byref(lam))
+    return mu.value, lam.value
+
+
+def psi(F, mu, lam):
+    F = _c64(F)
+    return lib().or_psi(_d(F), C.c_double(mu), C.c_double(lam))
+
+
+def pk1(F, mu, lam):
+    F = _c64(F)
+    P = np.zeros(9)
+    lib().or_pk1(_d(F), C.c_double(mu), C.c_double(lam), _d(P))
+    return P.reshape(3, 3)
+
+
+def dpdf(F, mu, lam):
+    F = _c64(F)
+    A = np.zeros(81)
+    lib().or_dpdf(_d(F), C.c_double(mu), C.c_double(lam), _d(A))
+    return A.reshape(9, 9)
+
+
+def rest(Xe):
+    Xe = _c64(Xe)
+    Dminv = np.zeros(9)
+    V = C.c_double()
+    lib().or_rest(_d(Xe), _d(Dminv), C.byref(V))
+    return Dminv.reshape(3, 3), V.value
+
+
+def elem_energy(Xe, xe, mu, lam):
+    Xe, xe = _c64(Xe), _c64(xe)
+    return lib().or_elem_energy(_d(Xe), _d(xe), C.c_double(mu), C.c_double(lam))
+
+
+def elem_grad(Xe, xe, mu, lam):
+    Xe, xe = _c64(Xe), _c64(xe)
+    g = np.zeros(12)
+    lib().or_elem_grad(_d(Xe), _d(xe), C.c_double(mu), C.c_double(lam), _d(g))
+    return g
+
+
+def elem_hess(Xe, xe, mu, lam):
+    Xe, xe = _c64(Xe), _c64(xe)
+    H = np.zeros(144)
+    lib().or_elem_hess(_d(Xe), _d(xe), C.c_double(mu), C.c_double(lam), _d(H))
+    return H.reshape(12, 12)
+
+
+def sym_eig(A):
+    A = _c64(A)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    lib().or_sym_eig(C.c_int(n), _d(A), _d(w), _d(V))
+    return w, V
+
+
+# --- problem level ----------------------------------------------------------
+class Oracle:
+    """Holds one problem (arrays from paper_2409_03807_amd.inputs.Problem)."""
+
+    def __init__(self, p):
+        self.p = p
+        self._keep = []
+        k = self._keep
+        X = _c64(p.X); k.append(X)
+        tets = np.ascontiguousarray(p.tets, dtype=np.int32); k.append(tets)
+        pinned = np.ascontiguousarray(p.pinned, dtype=np.uint8); k.append(pinned)
+        Ws = [_c64(W) for W in p.Ws]; bs = [_c64(b) for b in p.bs]
+        k.extend(Ws); k.extend(bs)
+        Wp = (_dp * len(Ws))(*[_d(W) for W in Ws]); k.append(Wp)
+        bp = (_dp * len(bs))(*[_d(b) for b in bs]); k.append(bp)
+        ce = np.ascontiguousarray(p.cub_elem, dtype=np.int32); k.append(ce)
+        cw = _c64(p.cub_w); k.append(cw)
+        tv = np.ascontiguousarray(p.target_vtx, dtype=np.int32); k.append(tv)
+        fv = np.ascontiguousarray(p.force_vtx, dtype=np.int32); k.append(fv)
+        width = p.hidden[0] if len(p.hidden) else p.r
+        s = _Problem()
+        s.nv, s.ne, s.X, s.tets = X.shape[0], tets.shape[0], _d(X), _i(tets)
+        s.pinned = pinned.ctypes.data_as(C.POINTER(C.c_ubyte))
+        s.young, s.poisson, s.density = p.young, p.poisson, p.density
+        s.gravity = (C.c_double * 3)(*[float(v) for v in p.gravity])
+        s.r, s.L, s.width, s.n_out = p.r, len(p.hidden), width, 3 * X.shape[0]
+        s.W = C.cast(Wp, C.POINTER(_dp))
+        s.b = C.cast(bp, C.POINTER(_dp))
+        s.S, s.cub_elem, s.cub_w = len(ce), _i(ce), _d(cw)
+        s.nt, s.target_vtx, s.k_c = len(tv), _i(tv), p.k_c
+        s.nf, s.force_vtx = len(fv), _i(fv)
+        self.s = s
+
+    @property
+    def r(self):
+        return self.p.r
+
+    def _loads(self, B, targets, force):
+        t = None if targets is None else _c64(targets).reshape(B, -1, 3)
+        f = None if force is None else _c64(force).reshape(B, 3)
+        return t, f, (_d(t) if t is not None else None), (_d(f) if f is not None else None)
+
+    def lumped_mass(self):
+        m = np.zeros(self.p.X.shape[0])
+        lib().or_lumped_mass(C.byref(self.s), _d(m))
+        return m
+
+    def decode(self, z, want_J=True):
+        z = _c64(np.atleast_2d(z))
+        B = z.shape[0]
+        nv = self.p.X.shape[0]
+        x = np.zeros((B, nv, 3))
+        J = np.zeros((B, 3 * nv, self.r)) if want_J else None
+        lib().or_decode(C.byref(self.s), C.c_int(B), _d(z), _d(x), _d(J) if want_J else None)
+        return x, J
+
+    def decode_hess(self, z):
+        z = _c64(z).ravel()
+        T = np.zeros((3 * self.p.X.shape[0], self.r, self.r))
+        lib().or_decode_hess(C.byref(self.s), _d(z), _d(T))
+        return T
+
+    def reduced(self, z, targets=None, force=None, flags=EXACT):
+        z = _c64(np.atleast_2d(z))
+        B = z.shape[0]
+        t, f, tp, fp = self._loads(B, targets, force)
+        E = np.zeros(B)
+        g = np.zeros((B, self.r))
+        H = np.zeros((B, self.r, self.r))
+        lib().or_reduced(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.c_int(flags),
+                         _d(E), _d(g), _d(H))
+        return E, g, H
+
+    def newton(self, z0, targets=None, force=None, opts=None):
+        z = _c64(np.atleast_2d(z0)).copy()
+        B = z.shape[0]
+        t, f, tp, fp = self._loads(B, targets, force)
+        o = opts or default_opts()
+        iters = np.zeros(B, dtype=np.int32)
+        status = np.zeros(B, dtype=np.int32)
+        relg = np.zeros(B)
+        E = np.zeros(B)
+        lib().or_newton(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
+                        _i(status), _d(relg), _d(E))
+        return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
+
+    def full_energy(self, x, targets=None, force=None):
+        x = _c64(x)
+        grad = np.zeros_like(x)
+        t = None if targets is None else _c64(targets)
+        f = None if force is None else _c64(force)
+        E = lib().or_full_energy(C.byref(self.s), _d(x), _d(t) if t is not None else None,
+                                 _d(f) if f is not None else None, _d(grad))
+        return E, grad
+
+    def full_newton(self, x0, targets=None, force=None, opts=None, elem_psd=True):
+        x = _c64(x0).copy()
+        t = None if targets is None else _c64(targets)
+        f = None if force is None else _c64(force)
+        o = opts or default_opts(rel_tol=1e-8, max_iter=200)
+        it, st, rg, E = C.c_int(), C.c_int(), C.c_double(), C.c_double()
+        lib().or_full_newton(C.byref(self.s), _d(x), _d(t) if t is not None else None,
+                             _d(f) if f is not None else None, C.byref(o), C.c_int(int(elem_psd)),
+                             C.byref(it), C.byref(st), C.byref(rg), C.byref(E))
+        return dict(x=x, iters=it.value, status=st.value, relgrad=rg.value, E=E.value)
+
+    def lipschitz(self, z1, z2):
+        z1, z2 = _c64(np.atleast_2d(z1)), _c64(np.atleast_2d(z2))
+        B = z1.shape[0]
+        loss, lipmax = C.c_double(), C.c_double()
+        nval = C.c_int()
+        per = np.zeros(B)
+        lib().or_lipschitz(C.byref(self.s), C.c_int(B), _d(z1), _d(z2), C.byref(loss), _d(per),
+                           C.byref(nval), C.byref(lipmax))
+        return dict(loss=loss.value, per_pair=per, n_valid=nval.value, lip_max=lipmax.value)
