@@ -1,0 +1,229 @@
+/*
+ * rs.h - C ABI of the reduced-Newton hot path of a Lipschitz-optimised
+ * neural-subspace solver for deformable bodies (Lyu, Zhao, Xian, Cen, Cai,
+ * Fang, "Accelerate Neural Subspace-Based Reduced-Order Solver of Deformable
+ * Simulation by Lipschitz Optimization", ACM TOG 43(6), 2024), for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library minimises, for a batch of independent items, the reduced
+ * quasi-static objective of Sec. 3.1 (Eq. form-reduced-space-time-integration
+ * with the inertia term dropped):
+ *
+ *     E(z) = P~(q(z)) - sum_v m_v g.(x_v - X_v) + k_c/2 sum_{v in T} |x_v - t_v|^2
+ *            - sum_{v in F} f.(x_v - X_v),      q(z) = X + m (.) f_theta(z)
+ *
+ * where f_theta is an MLP decoder (ELU hidden layers, linear output; Sec. 3.2),
+ * m masks Dirichlet-fixed vertices, P~ = sum_{e in S} w_e P_e is the cubature
+ * elastic potential (Sec. 4.3, Eq. form-cubature-gradients) of a stable
+ * Neo-Hookean tetrahedral mesh, T are penalty-targeted vertices and F
+ * force-loaded vertices.  It also evaluates the paper's Lipschitz loss of the
+ * cubature elastic Hessian (Sec. 4.1, Eq. form-L-LS-E).
+ *
+ * Conventions
+ *  - Every entry point returns RS_OK (0) or an RS_ERR_* code; the message of
+ *    the last error is available from rs_last_error().  No C++ exception
+ *    crosses the ABI.
+ *  - rs_create() copies every host array it is given; the caller may free
+ *    them on return.  The context owns all device memory it needs, sized for
+ *    max_batch items; no hot-path call allocates device memory.
+ *  - Batch arguments (z, x, J, E, g, H, iters, status, relgrad, loss, ...) are
+ *    DEVICE pointers owned by the caller.  Layouts are row-major and dense.
+ *  - Work is enqueued on `stream` (a hipStream_t cast to void*, NULL for the
+ *    default stream) and is asynchronous, except where an entry point says it
+ *    synchronises.  Argument checks are synchronous.
+ *  - Latent and reduced quantities (z, E, g, H, loss) are always float64.
+ *    Positions and Jacobians returned by rs_decode use the context precision.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+    RS_OK = 0,
+    RS_ERR_ARG = 1,         /* invalid argument (null pointer, size, index out of range) */
+    RS_ERR_HIP = 2,         /* a HIP runtime call or kernel launch failed */
+    RS_ERR_OOM = 3,         /* device allocation failed */
+    RS_ERR_STATE = 4,       /* context not usable */
+    RS_ERR_UNSUPPORTED = 5  /* size or mode outside what this build supports */
+};
+
+/* per-item solver outcomes: the exit conditions of the paper's solver
+ * (Sec. 5 and the convergence-condition discussion of the supplement) */
+enum {
+    RS_CONVERGED = 0,    /* I:   |g|_inf <= rel_tol |g_0|_inf (or <= abs_tol) */
+    RS_NOT_DESCENT = 1,  /* II:  no descent direction (saddle; projection off) */
+    RS_LS_MAX = 2,       /* III: ls_max backtracking trials without sufficient decrease */
+    RS_ITER_MAX = 3,     /* IV:  max_iter Newton steps taken without converging */
+    RS_NONFINITE = 4,    /* energy, gradient or Hessian not finite */
+    RS_RUNNING = -1
+};
+
+/* context precision of the decoder and element physics */
+enum { RS_PREC_F64 = 0, RS_PREC_F32 = 1 };
+
+/* rs_energy_grad_hess flags */
+enum {
+    RS_HESS_EXACT = 1,    /* add the decoder-curvature term sum_k g_k d2q_k/dz2 (else Gauss-Newton) */
+    RS_ELASTIC_ONLY = 2,  /* cubature elastic potential only (no gravity, penalty, forces) */
+    RS_ENERGY_ONLY = 4    /* energy only; g and H may be NULL */
+};
+
+/* Hessian treatment before the Newton solve */
+enum {
+    RS_PROJ_CLAMP = 0, /* eigenvalues below eig_floor*max|eig| raised to that floor */
+    RS_PROJ_ABS = 1,   /* eigenvalues replaced by max(|eig|, eig_floor*max|eig|) */
+    RS_PROJ_NONE = 2   /* no projection: a Hessian that is not positive definite ends the item (RS_NOT_DESCENT) */
+};
+
+/* Tetrahedral mesh: nv vertices X (nv x 3, metres), ne tets (ne x 4 vertex ids,
+ * positively oriented), pinned[v] != 0 fixes vertex v at its rest position. */
+typedef struct {
+    int32_t nv, ne;
+    const double* X;
+    const int32_t* tets;
+    const uint8_t* pinned;
+} rs_mesh;
+
+/* Stable Neo-Hookean material: Young's modulus (Pa), Poisson ratio, density
+ * (kg/m^3) and the gravity vector (m/s^2). */
+typedef struct {
+    double young, poisson, density, gravity[3];
+} rs_material;
+
+/* Decoder f_theta: r -> n_hidden layers of `width` (ELU) -> n_out = 3 nv (linear).
+ * W[l] is (out x in) row-major float64, b[l] has `out` entries, l = 0..n_hidden.
+ * n_hidden = 0 gives a linear decoder (e.g. a PCA basis). */
+typedef struct {
+    int32_t r, n_hidden, width, n_out;
+    const double* const* W;
+    const double* const* b;
+} rs_decoder;
+
+/* Cubature set S: n distinct element ids with non-negative weights (Sec. 4.3). */
+typedef struct {
+    int32_t n;
+    const int32_t* elem;
+    const double* weight;
+} rs_cubature;
+
+/* Penalty-targeted vertices with stiffness k_c (N/m), and force-loaded vertices. */
+typedef struct {
+    int32_t n_target;
+    const int32_t* target_vtx;
+    double k_c;
+    int32_t n_force;
+    const int32_t* force_vtx;
+} rs_constraints;
+
+/* Per-batch loads (DEVICE pointers, float64, either may be NULL):
+ * targets (B x n_target x 3) positions of the targeted vertices; force (B x 3)
+ * the force applied to each force-loaded vertex. */
+typedef struct {
+    const double* targets;
+    const double* force;
+} rs_load;
+
+/* Newton options (host struct).  Defaults from rs_default_opts(). */
+typedef struct {
+    int32_t max_iter;   /* Newton steps, default 50 */
+    int32_t ls_max;     /* backtracking trials per step, default 128 (Sec. 5) */
+    double c1;          /* Armijo constant, default 1e-4 */
+    double shrink;      /* step factor per trial, default 0.5 */
+    double rel_tol;     /* |g|_inf <= rel_tol |g_0|_inf, default 1e-6 */
+    double abs_tol;     /* or |g|_inf <= abs_tol, default 0 */
+    int32_t hess;       /* 1 exact Hessian (default), 0 Gauss-Newton */
+    int32_t proj;       /* RS_PROJ_*, default RS_PROJ_CLAMP */
+    double eig_floor;   /* relative eigenvalue floor, default 1e-8 */
+} rs_solve_opts;
+
+/* Static description of a context (sizes used for work accounting). */
+typedef struct {
+    int32_t prec, r, n_hidden, width, nv, ne, n_cub, n_target, n_force;
+    int32_t rows;       /* rows of the reduced output map: 9 per cubature tet, 3 per target, 1 gravity, 3 force */
+    int32_t rows_pad;   /* rows padded to the GEMM tile */
+    int32_t max_batch;
+} rs_info;
+
+typedef struct rs_ctx rs_ctx;
+
+/* Fill *o with the defaults listed in rs_solve_opts. */
+int rs_default_opts(rs_solve_opts* o);
+
+/* Create a context on the current HIP device.  prec is RS_PREC_F64 or
+ * RS_PREC_F32; max_batch bounds B of every later call (the Lipschitz loss
+ * handles up to max_batch/2 pairs per internal pass).  Requires 1 <= r <= 32,
+ * n_out == 3 nv, every index in range and every cubature tet of positive
+ * volume.  Synchronous.  On failure *out is NULL. */
+int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_decoder* dec,
+              const rs_cubature* cub, const rs_constraints* con, int32_t prec,
+              int32_t max_batch, rs_ctx** out);
+
+/* Release every device and host resource of the context.  NULL is accepted. */
+int rs_destroy(rs_ctx* ctx);
+
+/* Replace the decoder weights (same r, n_hidden, width, n_out).  Synchronous. */
+int rs_set_decoder(rs_ctx* ctx, const rs_decoder* dec);
+
+/* Describe the context. */
+int rs_get_info(const rs_ctx* ctx, rs_info* info);
+
+/* Decoder value and Jacobian (Sec. 3.2: q = f_theta(z)) for B <= max_batch items:
+ * z (B x r) float64; x (B x nv x 3) deformed positions and J (B x 3nv x r)
+ * dq/dz in the context precision (float or double).  Either output may be
+ * NULL.  Pinned vertices stay at rest with zero Jacobian rows. */
+int rs_decode(rs_ctx* ctx, int32_t B, const double* z, void* x, void* J, void* stream);
+
+/* Reduced energy E (B), gradient g = J^T grad_q E (B x r) and Hessian H (B x r x r,
+ * J^T H_q J plus, with RS_HESS_EXACT, the decoder-curvature term) at B latent
+ * points z (B x r) (Sec. 3.1, Sec. 4.3 Eq. form-cubature-gradients and the
+ * cubature Hessian of P~).  E is always evaluated in float64; g and H in the
+ * context precision with float64 accumulation.  Any B >= 0 (processed in
+ * chunks of max_batch). */
+int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* load,
+                        uint32_t flags, double* E, double* g, double* H, void* stream);
+
+/* Projective Newton with backtracking line search (supplement, projective
+ * Newton tests) for B <= max_batch independent items, z (B x r) in/out.
+ * Per item: iters (int32) accepted steps, status (RS_CONVERGED...), relgrad
+ * |g|_inf/|g_0|_inf at exit, E (float64) energy at exit.  The direction is
+ * -H^-1 g with the Cholesky factor of the symmetrised Hessian when it is
+ * positive definite, else with its eigen-projection (opts->proj).  Armijo
+ * backtracking alpha = shrink^j, j < ls_max, on float64 energies.
+ * Synchronises the stream a few times per Newton iteration. */
+int rs_newton_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
+                    const rs_solve_opts* opts, int32_t* iters, int32_t* status,
+                    double* relgrad, double* E, void* stream);
+
+/* Lipschitz loss (Sec. 4.1, Eq. form-L-LS-E) of the exact cubature elastic
+ * Hessian over B pairs (z1_b, z2_b) (each B x r):
+ *   per_pair[b] = |H(z1_b) - H(z2_b)|_F^2 / |z1_b - z2_b|^2   (0 where z1_b == z2_b),
+ *   loss = mean over pairs with z1_b != z2_b, n_valid their count,
+ *   lip_max = max_b sqrt(per_pair[b]) (the max-pair estimator, Eq. form-H-Lipschitz-estimation).
+ * per_pair and lip_max may be NULL.  All outputs are device pointers. */
+int rs_lipschitz_loss(rs_ctx* ctx, int32_t B, const double* z1, const double* z2,
+                      double* loss, double* per_pair, int32_t* n_valid, double* lip_max,
+                      void* stream);
+
+/* Message of the last error on this context ("" if none); a static message
+ * when ctx is NULL. */
+const char* rs_last_error(const rs_ctx* ctx);
+
+/* Kernel timing.  rs_profile(ctx, 1) clears previous records and brackets
+ * every later kernel launch with HIP events on its stream; rs_profile(ctx, 0)
+ * stops recording.  rs_profile_get() synchronises the recorded events and
+ * returns, for kernel kind idx < *n_kinds, its name, launch count, summed
+ * duration and the summed algorithmic HBM bytes and flops of those launches. */
+int rs_profile(rs_ctx* ctx, int32_t enable);
+int rs_profile_get(rs_ctx* ctx, int32_t idx, int32_t* n_kinds, char* name, int32_t name_len,
+                   int32_t* launches, double* total_ms, double* bytes, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RS_H */

@@ -1,0 +1,289 @@
+"""Python binding of librs (include/rs.h): argument marshalling only.
+
+Every step of the reduced-Newton path runs in the HIP library; this module
+checks tensor placement, dtype and contiguity, passes device pointers and the
+current HIP stream, and raises on any error code.  It fails loudly when the
+library has not been built or no GPU is present; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # imported before librs so both share one HIP runtime
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librs.so")
+
+RS_OK, RS_ERR_ARG, RS_ERR_HIP, RS_ERR_OOM, RS_ERR_STATE, RS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
+CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE, RUNNING = 0, 1, 2, 3, 4, -1
+PREC_F64, PREC_F32 = 0, 1
+HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY = 1, 2, 4
+PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("ne", C.c_int32), ("X", _dp), ("tets", _ip),
+                ("pinned", C.POINTER(C.c_uint8))]
+
+
+class _Material(C.Structure):
+    _fields_ = [("young", C.c_double), ("poisson", C.c_double), ("density", C.c_double),
+                ("gravity", C.c_double * 3)]
+
+
+class _Decoder(C.Structure):
+    _fields_ = [("r", C.c_int32), ("n_hidden", C.c_int32), ("width", C.c_int32),
+                ("n_out", C.c_int32), ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp))]
+
+
+class _Cubature(C.Structure):
+    _fields_ = [("n", C.c_int32), ("elem", _ip), ("weight", _dp)]
+
+
+class _Constraints(C.Structure):
+    _fields_ = [("n_target", C.c_int32), ("target_vtx", _ip), ("k_c", C.c_double),
+                ("n_force", C.c_int32), ("force_vtx", _ip)]
+
+
+class _Load(C.Structure):
+    _fields_ = [("targets", C.c_void_p), ("force", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("ls_max", C.c_int32), ("c1", C.c_double),
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double),
+                ("hess", C.c_int32), ("proj", C.c_int32), ("eig_floor", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("r", C.c_int32), ("n_hidden", C.c_int32),
+                ("width", C.c_int32), ("nv", C.c_int32), ("ne", C.c_int32),
+                ("n_cub", C.c_int32), ("n_target", C.c_int32), ("n_force", C.c_int32),
+                ("rows", C.c_int32), ("rows_pad", C.c_int32), ("max_batch", C.c_int32)]
+
+
+# every symbol include/rs.h declares
+SYMBOLS = ["rs_default_opts", "rs_create", "rs_destroy", "rs_set_decoder", "rs_get_info",
+           "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lipschitz_loss",
+           "rs_last_error", "rs_profile", "rs_profile_get"]
+
+_lib = None
+
+
+def load_library():
+    """Load librs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.rs_last_error.restype = C.c_char_p
+        L.rs_last_error.argtypes = [C.c_void_p]
+        for name in SYMBOLS:
+            getattr(L, name)
+        L.rs_create.argtypes = [C.POINTER(_Mesh), C.POINTER(_Material), C.POINTER(_Decoder),
+                                C.POINTER(_Cubature), C.POINTER(_Constraints), C.c_int32, C.c_int32,
+                                C.POINTER(C.c_void_p)]
+        L.rs_destroy.argtypes = [C.c_void_p]
+        L.rs_set_decoder.argtypes = [C.c_void_p, C.POINTER(_Decoder)]
+        L.rs_get_info.argtypes = [C.c_void_p, C.POINTER(Info)]
+        L.rs_decode.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_energy_grad_hess.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.c_uint32,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_newton_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
+                                      C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p]
+        L.rs_lipschitz_loss.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_profile.argtypes = [C.c_void_p, C.c_int32]
+        L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
+                                     C.POINTER(C.c_int32), _dp, _dp, _dp]
+        L.rs_default_opts.argtypes = [C.POINTER(SolveOpts)]
+        _lib = L
+    return _lib
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().rs_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    """Check a caller tensor: on the GPU, given dtype, contiguous (and shape)."""
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Context:
+    """One reduced problem on the current GPU (owns an rs_ctx)."""
+
+    def __init__(self, problem, prec: int = PREC_F64, max_batch: int = 1024):
+        if not torch.cuda.is_available():
+            raise RuntimeError("librs needs a HIP GPU; none is available")
+        L = load_library()
+        p = problem
+        self.p = p
+        self.r = p.r
+        self.prec = prec
+        self.tdtype = torch.float64 if prec == PREC_F64 else torch.float32
+        self.nv, self.n = p.X.shape[0], 3 * p.X.shape[0]
+        self.nt, self.nf = len(p.target_vtx), len(p.force_vtx)
+        keep = []
+
+        def f64(a):
+            a = np.ascontiguousarray(a, dtype=np.float64); keep.append(a); return a
+
+        def i32(a):
+            a = np.ascontiguousarray(a, dtype=np.int32); keep.append(a); return a
+
+        X, tets = f64(p.X), i32(p.tets)
+        pinned = np.ascontiguousarray(p.pinned, dtype=np.uint8); keep.append(pinned)
+        mesh = _Mesh(X.shape[0], tets.shape[0], X.ctypes.data_as(_dp), tets.ctypes.data_as(_ip),
+                     pinned.ctypes.data_as(C.POINTER(C.c_uint8)))
+        mat = _Material(p.young, p.poisson, p.density, (C.c_double * 3)(*[float(v) for v in p.gravity]))
+        dec = self._decoder_struct(p.Ws, p.bs, keep)
+        ce, cw = i32(p.cub_elem), f64(p.cub_w)
+        cub = _Cubature(len(ce), ce.ctypes.data_as(_ip), cw.ctypes.data_as(_dp))
+        tv, fv = i32(p.target_vtx), i32(p.force_vtx)
+        con = _Constraints(len(tv), tv.ctypes.data_as(_ip), p.k_c, len(fv), fv.ctypes.data_as(_ip))
+        ctx = C.c_void_p()
+        rc = L.rs_create(C.byref(mesh), C.byref(mat), C.byref(dec), C.byref(cub), C.byref(con),
+                         prec, max_batch, C.byref(ctx))
+        if rc != RS_OK:
+            raise RuntimeError(f"rs_create failed with code {rc}")
+        self.ctx = ctx
+        self.max_batch = max_batch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def _decoder_struct(self, Ws, bs, keep):
+        Ws = [np.ascontiguousarray(W, dtype=np.float64) for W in Ws]
+        bs = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
+        keep.extend(Ws); keep.extend(bs)
+        Wp = (_dp * len(Ws))(*[W.ctypes.data_as(_dp) for W in Ws])
+        bp = (_dp * len(bs))(*[b.ctypes.data_as(_dp) for b in bs])
+        keep.extend([Wp, bp])
+        width = Ws[0].shape[0] if len(Ws) > 1 else 0
+        return _Decoder(Ws[0].shape[1], len(Ws) - 1, width, Ws[-1].shape[0],
+                        C.cast(Wp, C.POINTER(_dp)), C.cast(bp, C.POINTER(_dp)))
+
+    def __del__(self):
+        if getattr(self, "ctx", None) is not None and _lib is not None:
+            _lib.rs_destroy(self.ctx)
+            self.ctx = None
+
+    def _check(self, rc, what):
+        if rc != RS_OK:
+            msg = load_library().rs_last_error(self.ctx)
+            raise RuntimeError(f"{what} failed (code {rc}): {msg.decode() if msg else ''}")
+
+    def info(self) -> Info:
+        i = Info()
+        self._check(load_library().rs_get_info(self.ctx, C.byref(i)), "rs_get_info")
+        return i
+
+    def set_decoder(self, Ws, bs):
+        keep = []
+        dec = self._decoder_struct(Ws, bs, keep)
+        self._check(load_library().rs_set_decoder(self.ctx, C.byref(dec)), "rs_set_decoder")
+
+    def _load(self, B, targets, force):
+        t = _dev(targets, torch.float64, (B, self.nt, 3), "targets")
+        f = _dev(force, torch.float64, (B, 3), "force")
+        return _Load(t.data_ptr() if t is not None else None, f.data_ptr() if f is not None else None), (t, f)
+
+    def decode(self, z, want_x=True, want_J=True):
+        B = z.shape[0]
+        _dev(z, torch.float64, (B, self.r), "z")
+        x = torch.empty((B, self.nv, 3), dtype=self.tdtype, device=z.device) if want_x else None
+        J = torch.empty((B, self.n, self.r), dtype=self.tdtype, device=z.device) if want_J else None
+        self._check(load_library().rs_decode(self.ctx, B, _ptr(z), _ptr(x), _ptr(J), _stream()), "rs_decode")
+        return x, J
+
+    def energy_grad_hess(self, z, targets=None, force=None, flags=HESS_EXACT):
+        B = z.shape[0]
+        _dev(z, torch.float64, (B, self.r), "z")
+        ld, _keep = self._load(B, targets, force)
+        E = torch.empty(B, dtype=torch.float64, device=z.device)
+        eonly = bool(flags & ENERGY_ONLY)
+        g = None if eonly else torch.empty((B, self.r), dtype=torch.float64, device=z.device)
+        H = None if eonly else torch.empty((B, self.r, self.r), dtype=torch.float64, device=z.device)
+        self._check(load_library().rs_energy_grad_hess(self.ctx, B, _ptr(z), C.byref(ld), flags, _ptr(E),
+                                                       _ptr(g), _ptr(H), _stream()), "rs_energy_grad_hess")
+        return E, g, H
+
+    def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None):
+        """z0 (B x r) float64 on the GPU; returns dict of device tensors.
+        `out` may pass preallocated (z, iters, status, relgrad, E) tensors."""
+        B = z0.shape[0]
+        _dev(z0, torch.float64, (B, self.r), "z0")
+        ld, _keep = self._load(B, targets, force)
+        if out is None:
+            z = z0.clone()
+            iters = torch.empty(B, dtype=torch.int32, device=z0.device)
+            status = torch.empty(B, dtype=torch.int32, device=z0.device)
+            relg = torch.empty(B, dtype=torch.float64, device=z0.device)
+            E = torch.empty(B, dtype=torch.float64, device=z0.device)
+        else:
+            z, iters, status, relg, E = out
+            z.copy_(z0)
+        o = opts or default_opts()
+        self._check(load_library().rs_newton_solve(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), _ptr(iters),
+                                                   _ptr(status), _ptr(relg), _ptr(E), _stream()),
+                    "rs_newton_solve")
+        return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
+
+    def lipschitz_loss(self, z1, z2, want_per_pair=True):
+        B = z1.shape[0]
+        _dev(z1, torch.float64, (B, self.r), "z1")
+        _dev(z2, torch.float64, (B, self.r), "z2")
+        dev = z1.device
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        per = torch.empty(B, dtype=torch.float64, device=dev) if want_per_pair else None
+        nval = torch.empty(1, dtype=torch.int32, device=dev)
+        lmax = torch.empty(1, dtype=torch.float64, device=dev)
+        self._check(load_library().rs_lipschitz_loss(self.ctx, B, _ptr(z1), _ptr(z2), _ptr(loss), _ptr(per),
+                                                     _ptr(nval), _ptr(lmax), _stream()), "rs_lipschitz_loss")
+        return dict(loss=loss, per_pair=per, n_valid=nval, lip_max=lmax)
+
+    # -- kernel timing ------------------------------------------------------
+    def profile(self, enable: bool):
+        self._check(load_library().rs_profile(self.ctx, int(enable)), "rs_profile")
+
+    def profile_read(self):
+        L = load_library()
+        n = C.c_int32()
+        self._check(L.rs_profile_get(self.ctx, -1, C.byref(n), None, 0, None, None, None, None), "rs_profile_get")
+        out = {}
+        name = C.create_string_buffer(64)
+        for i in range(n.value):
+            la, ms, by, fl = C.c_int32(), C.c_double(), C.c_double(), C.c_double()
+            self._check(L.rs_profile_get(self.ctx, i, C.byref(n), name, 64, C.byref(la), C.byref(ms), C.byref(by),
+                                         C.byref(fl)), "rs_profile_get")
+            if la.value:
+                out[name.value.decode()] = dict(launches=la.value, ms=ms.value, bytes=by.value, flops=fl.value)
+        return out

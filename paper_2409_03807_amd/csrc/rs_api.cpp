@@ -1,0 +1,970 @@
+// Host side of the librs C ABI: argument checks, the device layout of one
+// reduced problem, and the batched, device-resident Newton driver.
+//
+// The reduced output map.  Every quantity the reduced objective needs from
+// the decoder output u = W_out h_L + b_out is a linear function of h_L, so the
+// context folds it into one matrix W_big (rows x width) applied to
+// [h_L | dh_L/dz] by a single GEMM per evaluation:
+//   - 9 rows per cubature tet e: the displacement gradient grad u_e = D_e u_e
+//     (D_e the constant 9x12 map of the linear tet, F = I + grad u), so
+//     F_e and K_e = dvecF_e/dz come straight out of the GEMM (Sec. 4.3: only
+//     the cubature tets S are ever evaluated);
+//   - 3 rows per penalty-targeted vertex (its displacement);
+//   - 1 gravity row: sum_v m_v g . u_v over every vertex (lumped masses);
+//   - 3 force rows: the summed displacement of the force-loaded vertices.
+// Pinned vertices have their W_out/b_out rows zeroed (q = X + m (.) f(z)).
+#include "rs_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace rs;
+
+namespace {
+
+int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
+
+enum Kind {
+    K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR, K_LS_CAND,
+    K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
+    K_INIT, K_COUNT
+};
+const char* kKindName[K_COUNT] = {
+    "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir", "ls_candidates",
+    "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
+    "newton_init"};
+
+struct ProfRec {
+    int kind;
+    double bytes, flops;
+    int e0, e1;
+};
+
+}  // namespace
+
+struct rs_ctx {
+    int prec = 0;
+    int f32 = 0;
+    size_t tsz = 8;
+    int r = 0, L = 0, w = 0, nv = 0, ne = 0, S = 0, nt = 0, nf = 0, n_out = 0, nc = 0;
+    int M = 0, Mp = 0, Nfp = 0, max_batch = 0;
+    int in_last = 0, lda0 = 0, lda_h = 0, lda_out = 0, wrows = 0, in_rows = 0;
+    int grav_row = 0, force_row = 0;
+    double mu = 0, lam = 0, k_c = 0;
+    double grav[3] = {0, 0, 0};
+    double density = 0;
+
+    std::vector<double> X, mass, Dminv, vol;
+    std::vector<int> tets, cub_elem, tvtx, fvtx;
+    std::vector<uint8_t> pinned;
+    std::vector<double> cub_w;
+
+    std::vector<void*> allocs;
+    // weights in the context precision (T) and in float64
+    std::vector<void*> W, bh;
+    std::vector<double*> W64, bh64;
+    void* Wbig = nullptr; void* bbig = nullptr; void* WbigT = nullptr;
+    double* Wbig64 = nullptr; double* bbig64 = nullptr;
+    void* Wfull = nullptr; void* bfull = nullptr; void* Xfull = nullptr;
+    double* wV = nullptr; double* Xt = nullptr;
+    // workspace
+    std::vector<void*> pre;       // L x (max_batch x wrows x nc) T
+    void* out = nullptr;          // max_batch x Mp x nc T
+    void* dseed = nullptr;        // max_batch x Mp T
+    void* gbar = nullptr;         // max_batch x in_rows T
+    double *Ew = nullptr, *gw = nullptr, *Hw = nullptr;
+    double *g0 = nullptr, *gnorm = nullptr, *dz = nullptr, *slope = nullptr;
+    int *ls_j0 = nullptr, *active = nullptr, *counters = nullptr;
+    double* zc = nullptr;         // kLsCand*max_batch x r
+    std::vector<double*> pre64;   // L x (kLsCand*max_batch x wrows)
+    double* out64 = nullptr;      // kLsCand*max_batch x Mp
+    double* Ec = nullptr;
+    double* zs = nullptr;         // max_batch x r
+    double* ell = nullptr;        // max_batch
+    double* lacc = nullptr;       // 3
+    int* hcount = nullptr;        // pinned host
+
+    std::string err;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    size_t evnext = 0;
+    std::vector<ProfRec> recs;
+    double kms[K_COUNT] = {0}, kbytes[K_COUNT] = {0}, kflops[K_COUNT] = {0};
+    int klaunch[K_COUNT] = {0};
+    bool aggregated = true;
+};
+
+static const char* kNullCtxMsg = "rs: null context";
+
+static int fail(rs_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+static int hip_fail(rs_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, RS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T> static T* dalloc(rs_ctx* c, size_t n)
+{
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return static_cast<T*>(p);
+}
+
+static void* dalloc_bytes(rs_ctx* c, size_t bytes)
+{
+    void* p = nullptr;
+    if (bytes == 0) bytes = 1;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    c->allocs.push_back(p);
+    return p;
+}
+
+// Launch bracket: records HIP events around the launch when profiling.
+template <class F>
+static int run(rs_ctx* c, int kind, double bytes, double flops, hipStream_t s, F&& f)
+{
+    int e0 = -1, e1 = -1;
+    if (c->prof) {
+        while (c->evpool.size() < c->evnext + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventCreate");
+            c->evpool.push_back(e);
+        }
+        e0 = (int)c->evnext++;
+        e1 = (int)c->evnext++;
+        if (hipEventRecord(c->evpool[e0], s) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventRecord");
+    }
+    hipError_t e = f();
+    if (e != hipSuccess) return hip_fail(c, e, kKindName[kind]);
+    if (c->prof) {
+        if (hipEventRecord(c->evpool[e1], s) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventRecord");
+        c->recs.push_back(ProfRec{kind, bytes, flops, e0, e1});
+        c->aggregated = false;
+    }
+    return RS_OK;
+}
+
+#define RS_TRY(x)                  \
+    do {                           \
+        int rc_ = (x);             \
+        if (rc_ != RS_OK) return rc_; \
+    } while (0)
+
+// ------------------------------------------------------------------ layouts
+static void inv3(const double* M, double* Mi, double* det)
+{
+    double C[9];
+    C[0] = M[4] * M[8] - M[5] * M[7];
+    C[1] = M[5] * M[6] - M[3] * M[8];
+    C[2] = M[3] * M[7] - M[4] * M[6];
+    C[3] = M[2] * M[7] - M[1] * M[8];
+    C[4] = M[0] * M[8] - M[2] * M[6];
+    C[5] = M[1] * M[6] - M[0] * M[7];
+    C[6] = M[1] * M[5] - M[2] * M[4];
+    C[7] = M[2] * M[3] - M[0] * M[5];
+    C[8] = M[0] * M[4] - M[1] * M[3];
+    const double d = M[0] * C[0] + M[1] * C[1] + M[2] * C[2];
+    *det = d;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Mi[3 * i + j] = C[3 * j + i] / d;
+}
+
+static int upload(rs_ctx* c, void* dst, const std::vector<double>& src, int as_f32)
+{
+    hipError_t e;
+    if (as_f32) {
+        std::vector<float> t(src.begin(), src.end());
+        e = hipMemcpy(dst, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice);
+    } else {
+        e = hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
+    return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpy");
+}
+
+// Upload the decoder: hidden layers padded for the GEMM tiles, and the folded
+// output maps (reduced W_big, its transpose, and the full W_out for rs_decode).
+static int load_decoder(rs_ctx* c, const rs_decoder* d)
+{
+    const int r = c->r, w = c->w, L = c->L, in_last = c->in_last;
+    for (int l = 0; l < L; ++l) {
+        const int in = l == 0 ? r : w, lda = l == 0 ? c->lda0 : c->lda_h;
+        std::vector<double> Wp((size_t)c->wrows * lda, 0.0), bp(c->wrows, 0.0);
+        for (int i = 0; i < w; ++i) {
+            for (int j = 0; j < in; ++j) Wp[(size_t)i * lda + j] = d->W[l][(size_t)i * in + j];
+            bp[i] = d->b[l][i];
+        }
+        RS_TRY(upload(c, c->W64[l], Wp, 0));
+        RS_TRY(upload(c, c->bh64[l], bp, 0));
+        if (c->f32) {
+            RS_TRY(upload(c, c->W[l], Wp, 1));
+            RS_TRY(upload(c, c->bh[l], bp, 1));
+        }
+    }
+    // masked output layer
+    const double* Wo = d->W[L];
+    const double* bo = d->b[L];
+    auto wout = [&](int row, int j) { return c->pinned[row / 3] ? 0.0 : Wo[(size_t)row * in_last + j]; };
+    auto bout = [&](int row) { return c->pinned[row / 3] ? 0.0 : bo[row]; };
+
+    const int lda = c->lda_out;
+    std::vector<double> Wb((size_t)c->Mp * lda, 0.0), bb(c->Mp, 0.0);
+    for (int s = 0; s < c->S; ++s) {
+        const int e = c->cub_elem[s];
+        const double* Di = &c->Dminv[9 * (size_t)s];
+        double Dv[4][3];
+        for (int j = 0; j < 3; ++j) {
+            double sum = 0.0;
+            for (int a = 1; a < 4; ++a) {
+                Dv[a][j] = Di[3 * (a - 1) + j];
+                sum += Dv[a][j];
+            }
+            Dv[0][j] = -sum;
+        }
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                const size_t row = 9 * (size_t)s + 3 * j + i;
+                for (int a = 0; a < 4; ++a) {
+                    const int vrow = 3 * c->tets[4 * (size_t)e + a] + i;
+                    const double coef = Dv[a][j];
+                    for (int k = 0; k < in_last; ++k) Wb[row * lda + k] += coef * wout(vrow, k);
+                    bb[row] += coef * bout(vrow);
+                }
+            }
+    }
+    const int prow = 9 * c->S;
+    for (int t = 0; t < c->nt; ++t)
+        for (int i = 0; i < 3; ++i) {
+            const int vrow = 3 * c->tvtx[t] + i;
+            for (int k = 0; k < in_last; ++k) Wb[(size_t)(prow + 3 * t + i) * lda + k] = wout(vrow, k);
+            bb[prow + 3 * t + i] = bout(vrow);
+        }
+    for (int v = 0; v < c->nv; ++v)
+        for (int i = 0; i < 3; ++i) {
+            const double mg = c->mass[v] * c->grav[i];
+            if (mg == 0.0) continue;
+            const int vrow = 3 * v + i;
+            for (int k = 0; k < in_last; ++k) Wb[(size_t)c->grav_row * lda + k] += mg * wout(vrow, k);
+            bb[c->grav_row] += mg * bout(vrow);
+        }
+    for (int t = 0; t < c->nf; ++t)
+        for (int i = 0; i < 3; ++i) {
+            const int vrow = 3 * c->fvtx[t] + i;
+            for (int k = 0; k < in_last; ++k) Wb[(size_t)(c->force_row + i) * lda + k] += wout(vrow, k);
+            bb[c->force_row + i] += bout(vrow);
+        }
+    RS_TRY(upload(c, c->Wbig64, Wb, 0));
+    RS_TRY(upload(c, c->bbig64, bb, 0));
+    if (c->f32) {
+        RS_TRY(upload(c, c->Wbig, Wb, 1));
+        RS_TRY(upload(c, c->bbig, bb, 1));
+    }
+    // transpose for the adjoint product dE/dh_L = W_big^T seeds
+    std::vector<double> WT((size_t)c->in_rows * c->Mp, 0.0);
+    for (int m = 0; m < c->Mp; ++m)
+        for (int k = 0; k < in_last; ++k) WT[(size_t)k * c->Mp + m] = Wb[(size_t)m * lda + k];
+    RS_TRY(upload(c, c->WbigT, WT, c->f32));
+    // full output layer for rs_decode
+    std::vector<double> Wf((size_t)c->Nfp * lda, 0.0), bf(c->n_out, 0.0), Xf(c->n_out);
+    for (int row = 0; row < c->n_out; ++row) {
+        for (int k = 0; k < in_last; ++k) Wf[(size_t)row * lda + k] = wout(row, k);
+        bf[row] = bout(row);
+        Xf[row] = c->X[row];
+    }
+    RS_TRY(upload(c, c->Wfull, Wf, c->f32));
+    RS_TRY(upload(c, c->bfull, bf, c->f32));
+    RS_TRY(upload(c, c->Xfull, Xf, c->f32));
+    return RS_OK;
+}
+
+static int check_decoder(rs_ctx* c, const rs_decoder* d, int nv)
+{
+    if (!d) return fail(c, RS_ERR_ARG, "decoder is NULL");
+    if (d->r < 1 || d->r > kMaxR) return fail(c, RS_ERR_UNSUPPORTED, "decoder r must be in [1, 32]");
+    if (d->n_hidden < 0 || (d->n_hidden > 0 && d->width < 1)) return fail(c, RS_ERR_ARG, "bad decoder depth/width");
+    if (d->n_hidden > kMaxL) return fail(c, RS_ERR_UNSUPPORTED, "at most 8 hidden layers");
+    if (d->n_out != 3 * nv) return fail(c, RS_ERR_ARG, "decoder n_out must be 3 * nv");
+    if (!d->W || !d->b) return fail(c, RS_ERR_ARG, "decoder weights are NULL");
+    for (int l = 0; l <= d->n_hidden; ++l)
+        if (!d->W[l] || !d->b[l]) return fail(c, RS_ERR_ARG, "decoder layer pointer is NULL");
+    return RS_OK;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" int rs_default_opts(rs_solve_opts* o)
+{
+    if (!o) return RS_ERR_ARG;
+    o->max_iter = 50;
+    o->ls_max = 128;
+    o->c1 = 1e-4;
+    o->shrink = 0.5;
+    o->rel_tol = 1e-6;
+    o->abs_tol = 0.0;
+    o->hess = 1;
+    o->proj = RS_PROJ_CLAMP;
+    o->eig_floor = 1e-8;
+    return RS_OK;
+}
+
+extern "C" const char* rs_last_error(const rs_ctx* c) { return c ? c->err.c_str() : kNullCtxMsg; }
+
+static void destroy(rs_ctx* c)
+{
+    for (void* p : c->allocs) (void)hipFree(p);
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    if (c->hcount) (void)hipHostFree(c->hcount);
+    delete c;
+}
+
+extern "C" int rs_destroy(rs_ctx* c)
+{
+    if (c) destroy(c);
+    return RS_OK;
+}
+
+extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_decoder* dec,
+                         const rs_cubature* cub, const rs_constraints* con, int32_t prec,
+                         int32_t max_batch, rs_ctx** out)
+{
+    if (!out) return RS_ERR_ARG;
+    *out = nullptr;
+    rs_ctx* c = new (std::nothrow) rs_ctx();
+    if (!c) return RS_ERR_OOM;
+    auto bail = [&](int code) {
+        // errors at creation cannot be queried from a context: print once
+        std::fprintf(stderr, "rs_create: %s\n", c->err.c_str());
+        destroy(c);
+        return code;
+    };
+    if (!mesh || !mat || !cub || !mesh->X || !mesh->tets || !mesh->pinned)
+        return bail(fail(c, RS_ERR_ARG, "NULL mesh, material or cubature"));
+    if (mesh->nv < 4 || mesh->ne < 1) return bail(fail(c, RS_ERR_ARG, "mesh too small"));
+    if (prec != RS_PREC_F64 && prec != RS_PREC_F32) return bail(fail(c, RS_ERR_UNSUPPORTED, "unknown precision"));
+    if (max_batch < 1) return bail(fail(c, RS_ERR_ARG, "max_batch must be >= 1"));
+    {
+        const int rc = check_decoder(c, dec, mesh->nv);
+        if (rc != RS_OK) return bail(rc);
+    }
+    if (cub->n < 1 || !cub->elem || !cub->weight) return bail(fail(c, RS_ERR_ARG, "empty cubature"));
+    const int nt = con ? con->n_target : 0, nf = con ? con->n_force : 0;
+    if (nt < 0 || nf < 0 || (nt && !con->target_vtx) || (nf && !con->force_vtx))
+        return bail(fail(c, RS_ERR_ARG, "bad constraints"));
+
+    c->prec = prec;
+    c->f32 = prec == RS_PREC_F32;
+    c->tsz = c->f32 ? 4 : 8;
+    c->nv = mesh->nv;
+    c->ne = mesh->ne;
+    c->r = dec->r;
+    c->L = dec->n_hidden;
+    c->w = c->L > 0 ? dec->width : 0;
+    c->n_out = dec->n_out;
+    c->nc = 1 + c->r;
+    c->S = cub->n;
+    c->nt = nt;
+    c->nf = nf;
+    c->k_c = con ? con->k_c : 0.0;
+    c->max_batch = max_batch;
+    c->density = mat->density;
+    for (int i = 0; i < 3; ++i) c->grav[i] = mat->gravity[i];
+    // stable Neo-Hookean: lambda = lambda_Lame + mu (linearises to (E, nu))
+    c->mu = mat->young / (2.0 * (1.0 + mat->poisson));
+    c->lam = mat->young * mat->poisson / ((1.0 + mat->poisson) * (1.0 - 2.0 * mat->poisson)) + c->mu;
+
+    c->X.assign(mesh->X, mesh->X + 3 * (size_t)c->nv);
+    c->tets.assign(mesh->tets, mesh->tets + 4 * (size_t)c->ne);
+    c->pinned.assign(mesh->pinned, mesh->pinned + c->nv);
+    for (int v : c->tets)
+        if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "tet vertex index out of range"));
+    c->cub_elem.assign(cub->elem, cub->elem + c->S);
+    c->cub_w.assign(cub->weight, cub->weight + c->S);
+    for (int s = 0; s < c->S; ++s) {
+        if (c->cub_elem[s] < 0 || c->cub_elem[s] >= c->ne) return bail(fail(c, RS_ERR_ARG, "cubature element out of range"));
+        if (!(c->cub_w[s] >= 0.0)) return bail(fail(c, RS_ERR_ARG, "negative cubature weight"));
+    }
+    if (nt) c->tvtx.assign(con->target_vtx, con->target_vtx + nt);
+    if (nf) c->fvtx.assign(con->force_vtx, con->force_vtx + nf);
+    for (int v : c->tvtx)
+        if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "target vertex out of range"));
+    for (int v : c->fvtx)
+        if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "force vertex out of range"));
+
+    // rest shape: lumped masses over every tet, Dm^-1 and volume per cubature tet
+    c->mass.assign(c->nv, 0.0);
+    for (int e = 0; e < c->ne; ++e) {
+        double Dm[9], Di[9], det;
+        const int* t = &c->tets[4 * (size_t)e];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) Dm[3 * i + k] = c->X[3 * t[k + 1] + i] - c->X[3 * t[0] + i];
+        inv3(Dm, Di, &det);
+        const double V = det / 6.0;
+        for (int a = 0; a < 4; ++a) c->mass[t[a]] += c->density * V / 4.0;
+    }
+    c->Dminv.resize(9 * (size_t)c->S);
+    c->vol.resize(c->S);
+    std::vector<double> wVh(c->S);
+    for (int s = 0; s < c->S; ++s) {
+        double Dm[9], det;
+        const int* t = &c->tets[4 * (size_t)c->cub_elem[s]];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) Dm[3 * i + k] = c->X[3 * t[k + 1] + i] - c->X[3 * t[0] + i];
+        inv3(Dm, &c->Dminv[9 * (size_t)s], &det);
+        if (!(det > 0.0)) return bail(fail(c, RS_ERR_ARG, "cubature tet with non-positive volume"));
+        c->vol[s] = det / 6.0;
+        wVh[s] = c->cub_w[s] * c->vol[s];
+    }
+
+    // sizes
+    c->in_last = c->L > 0 ? c->w : c->r;
+    c->lda0 = round_up(c->r, kTileK);
+    c->lda_h = round_up(std::max(c->w, 1), kTileK);
+    c->lda_out = round_up(c->in_last, kTileK);
+    c->wrows = round_up(std::max(c->w, 1), kTileM);
+    c->in_rows = round_up(c->in_last, kTileM);
+    c->M = 9 * c->S + 3 * c->nt + 4;
+    c->Mp = round_up(c->M, kTileM);
+    c->grav_row = 9 * c->S + 3 * c->nt;
+    c->force_row = c->grav_row + 1;
+    c->Nfp = round_up(c->n_out, kTileM);
+
+    // device allocations
+    const size_t B = (size_t)max_batch, nc = c->nc, ts = c->tsz;
+    const size_t BL = B * kLsCand;
+    bool ok = true;
+    auto need = [&](void* p) { ok = ok && p != nullptr; return p; };
+    c->W.resize(c->L);
+    c->bh.resize(c->L);
+    c->W64.resize(c->L);
+    c->bh64.resize(c->L);
+    c->pre.resize(c->L);
+    c->pre64.resize(c->L);
+    for (int l = 0; l < c->L; ++l) {
+        const int lda = l == 0 ? c->lda0 : c->lda_h;
+        c->W64[l] = (double*)need(dalloc<double>(c, (size_t)c->wrows * lda));
+        c->bh64[l] = (double*)need(dalloc<double>(c, c->wrows));
+        c->W[l] = c->f32 ? need(dalloc_bytes(c, (size_t)c->wrows * lda * ts)) : c->W64[l];
+        c->bh[l] = c->f32 ? need(dalloc_bytes(c, (size_t)c->wrows * ts)) : c->bh64[l];
+        c->pre[l] = need(dalloc_bytes(c, B * c->wrows * nc * ts));
+        c->pre64[l] = (double*)need(dalloc<double>(c, BL * c->wrows));
+    }
+    c->Wbig64 = (double*)need(dalloc<double>(c, (size_t)c->Mp * c->lda_out));
+    c->bbig64 = (double*)need(dalloc<double>(c, c->Mp));
+    c->Wbig = c->f32 ? need(dalloc_bytes(c, (size_t)c->Mp * c->lda_out * ts)) : c->Wbig64;
+    c->bbig = c->f32 ? need(dalloc_bytes(c, (size_t)c->Mp * ts)) : c->bbig64;
+    c->WbigT = need(dalloc_bytes(c, (size_t)c->in_rows * c->Mp * ts));
+    c->Wfull = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * ts));
+    c->bfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
+    c->Xfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
+    c->wV = (double*)need(dalloc<double>(c, c->S));
+    c->Xt = (double*)need(dalloc<double>(c, 3 * (size_t)std::max(c->nt, 1)));
+    c->out = need(dalloc_bytes(c, B * c->Mp * nc * ts));
+    c->dseed = need(dalloc_bytes(c, B * c->Mp * ts));
+    c->gbar = need(dalloc_bytes(c, B * c->in_rows * ts));
+    c->Ew = (double*)need(dalloc<double>(c, B));
+    c->gw = (double*)need(dalloc<double>(c, B * c->r));
+    c->Hw = (double*)need(dalloc<double>(c, B * c->r * c->r));
+    c->g0 = (double*)need(dalloc<double>(c, B));
+    c->gnorm = (double*)need(dalloc<double>(c, B));
+    c->dz = (double*)need(dalloc<double>(c, B * c->r));
+    c->slope = (double*)need(dalloc<double>(c, B));
+    c->ls_j0 = (int*)need(dalloc<int>(c, B));
+    c->active = (int*)need(dalloc<int>(c, B));
+    c->counters = (int*)need(dalloc<int>(c, 4));
+    c->zc = (double*)need(dalloc<double>(c, BL * c->r));
+    c->out64 = (double*)need(dalloc<double>(c, BL * c->Mp));
+    c->Ec = (double*)need(dalloc<double>(c, BL));
+    c->zs = (double*)need(dalloc<double>(c, B * c->r));
+    c->ell = (double*)need(dalloc<double>(c, B));
+    c->lacc = (double*)need(dalloc<double>(c, 4));
+    if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
+    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return bail(fail(c, RS_ERR_OOM, "pinned host allocation failed"));
+
+    if (upload(c, c->wV, wVh, 0) != RS_OK) return bail(RS_ERR_HIP);
+    if (c->nt) {
+        std::vector<double> xt(3 * (size_t)c->nt);
+        for (int t = 0; t < c->nt; ++t)
+            for (int i = 0; i < 3; ++i) xt[3 * t + i] = c->X[3 * c->tvtx[t] + i];
+        if (upload(c, c->Xt, xt, 0) != RS_OK) return bail(RS_ERR_HIP);
+    }
+    if (load_decoder(c, dec) != RS_OK) return bail(RS_ERR_HIP);
+    *out = c;
+    return RS_OK;
+}
+
+extern "C" int rs_set_decoder(rs_ctx* c, const rs_decoder* d)
+{
+    if (!c) return RS_ERR_STATE;
+    RS_TRY(check_decoder(c, d, c->nv));
+    if (d->r != c->r || d->n_hidden != c->L || (c->L && d->width != c->w))
+        return fail(c, RS_ERR_ARG, "decoder shape differs from the context's");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    return load_decoder(c, d);
+}
+
+extern "C" int rs_get_info(const rs_ctx* c, rs_info* info)
+{
+    if (!c || !info) return RS_ERR_ARG;
+    info->prec = c->prec;
+    info->r = c->r;
+    info->n_hidden = c->L;
+    info->width = c->w;
+    info->nv = c->nv;
+    info->ne = c->ne;
+    info->n_cub = c->S;
+    info->n_target = c->nt;
+    info->n_force = c->nf;
+    info->rows = c->M;
+    info->rows_pad = c->Mp;
+    info->max_batch = c->max_batch;
+    return RS_OK;
+}
+
+// ------------------------------------------------------------------ passes
+static double gemm_flops(int rows, int K, int items, int nc) { return 2.0 * rows * K * (double)items * nc; }
+static double gemm_bytes(const rs_ctx* c, size_t ts, int rows, int K, int items, int nc)
+{
+    (void)c;
+    return (double)ts * ((double)rows * K + (double)items * K * nc + (double)items * rows * nc);
+}
+
+// T-precision decoder value + Jacobian, reduced rows, element terms and (exact)
+// the curvature term, for n items whose latent points are z[zmap[i]].
+static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const double* targets,
+                  const double* force, const int* imap, uint32_t flags, double* E, double* g, double* H,
+                  hipStream_t s)
+{
+    const int r = c->r, nc = c->nc;
+    const int f32 = c->f32;
+    const size_t ts = c->tsz;
+    for (int l = 0; l < c->L; ++l) {
+        GemmArgs a{};
+        a.A = c->W[l];
+        a.lda = l == 0 ? c->lda0 : c->lda_h;
+        a.rows = c->w;
+        a.rows_pad = c->wrows;
+        a.K = l == 0 ? r : c->w;
+        a.nc = nc;
+        a.items = n;
+        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
+        a.Y = l == 0 ? nullptr : c->pre[l - 1];
+        a.z = z;
+        a.zmap = zmap;
+        a.r = r;
+        a.bias = c->bh[l];
+        a.out_mode = OUT_PACK;
+        a.C = c->pre[l];
+        RS_TRY(run(c, K_GEMM_HIDDEN, gemm_bytes(c, ts, a.rows, a.K, n, nc), gemm_flops(a.rows, a.K, n, nc), s,
+                   [&] { return launch_gemm(f32, a, s); }));
+    }
+    {
+        GemmArgs a{};
+        a.A = c->Wbig;
+        a.lda = c->lda_out;
+        a.rows = c->M;
+        a.rows_pad = c->Mp;
+        a.K = c->in_last;
+        a.nc = nc;
+        a.items = n;
+        a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
+        a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+        a.z = z;
+        a.zmap = zmap;
+        a.r = r;
+        a.bias = c->bbig;
+        a.out_mode = OUT_PACK;
+        a.C = c->out;
+        RS_TRY(run(c, K_GEMM_OUT, gemm_bytes(c, ts, c->M, a.K, n, nc), gemm_flops(c->M, a.K, n, nc), s,
+                   [&] { return launch_gemm(f32, a, s); }));
+    }
+    const bool exact = (flags & RS_HESS_EXACT) && c->L > 0 && H;
+    {
+        ElemArgs a{};
+        a.out = c->out;
+        a.rows_pad = c->Mp;
+        a.nc = nc;
+        a.r = r;
+        a.S = c->S;
+        a.nt = c->nt;
+        a.nf = c->nf;
+        a.wV = c->wV;
+        a.Xt = c->Xt;
+        a.targets = c->nt ? targets : nullptr;
+        a.force = c->nf ? force : nullptr;
+        a.imap = imap;
+        a.mu = c->mu;
+        a.lam = c->lam;
+        a.k_c = c->k_c;
+        a.elastic_only = (flags & RS_ELASTIC_ONLY) ? 1 : 0;
+        a.grav_row = c->grav_row;
+        a.force_row = c->force_row;
+        a.E = E;
+        a.g = g;
+        a.H = H;
+        a.dseed = exact ? c->dseed : nullptr;
+        const double bytes = (double)n * ((double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) +
+                                          8.0 * (1 + r + r * r));
+        const double flops = (double)n * c->S * (18.0 * r * r + 80.0 * r + 150.0);
+        RS_TRY(run(c, K_ELEM, bytes, flops, s, [&] { return launch_elem(f32, a, n, s); }));
+    }
+    if (exact) {
+        GemmArgs a{};
+        a.A = c->WbigT;
+        a.lda = c->Mp;
+        a.rows = c->in_last;
+        a.rows_pad = c->in_rows;
+        a.K = c->Mp;
+        a.nc = 1;
+        a.items = n;
+        a.in_mode = IN_RAW;
+        a.Y = c->dseed;
+        a.r = r;
+        a.out_mode = OUT_PACK;
+        a.C = c->gbar;
+        RS_TRY(run(c, K_GEMM_ADJ, gemm_bytes(c, ts, c->in_last, c->Mp, n, 1), gemm_flops(c->in_last, c->Mp, n, 1), s,
+                   [&] { return launch_gemm(f32, a, s); }));
+        CurvArgs ca{};
+        for (int l = 0; l < c->L; ++l) {
+            ca.pre[l] = c->pre[l];
+            ca.W[l] = c->W[l];
+        }
+        ca.L = c->L;
+        ca.width = c->w;
+        ca.nc = nc;
+        ca.r = r;
+        ca.pre_rows = c->wrows;
+        ca.lda0 = c->lda0;
+        ca.lda = c->lda_h;
+        ca.gbar = c->gbar;
+        ca.H = H;
+        ca.grev = nullptr;
+        RS_TRY(run(c, K_CURV, (double)n * c->L * c->w * nc * ts,
+                   (double)n * c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w), s,
+                   [&] { return launch_curv(f32, ca, n, s); }));
+    }
+    return RS_OK;
+}
+
+// float64 value-only decoder and energy for n items (line-search energies).
+// Loads of item i come from batch index imap[i / imap_div].
+static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const double* targets,
+                      const double* force, const int* imap, int imap_div, int elastic_only, double* E,
+                      hipStream_t s, int kind_hidden, int kind_out)
+{
+    const int r = c->r;
+    for (int l = 0; l < c->L; ++l) {
+        GemmArgs a{};
+        a.A = c->W64[l];
+        a.lda = l == 0 ? c->lda0 : c->lda_h;
+        a.rows = c->w;
+        a.rows_pad = c->wrows;
+        a.K = l == 0 ? r : c->w;
+        a.nc = 1;
+        a.items = n;
+        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
+        a.Y = l == 0 ? nullptr : c->pre64[l - 1];
+        a.z = z;
+        a.zmap = zmap;
+        a.r = r;
+        a.bias = c->bh64[l];
+        a.out_mode = OUT_PACK;
+        a.C = c->pre64[l];
+        RS_TRY(run(c, kind_hidden, gemm_bytes(c, 8, a.rows, a.K, n, 1), gemm_flops(a.rows, a.K, n, 1), s,
+                   [&] { return launch_gemm(0, a, s); }));
+    }
+    {
+        GemmArgs a{};
+        a.A = c->Wbig64;
+        a.lda = c->lda_out;
+        a.rows = c->M;
+        a.rows_pad = c->Mp;
+        a.K = c->in_last;
+        a.nc = 1;
+        a.items = n;
+        a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
+        a.Y = c->L > 0 ? c->pre64[c->L - 1] : nullptr;
+        a.z = z;
+        a.zmap = zmap;
+        a.r = r;
+        a.bias = c->bbig64;
+        a.out_mode = OUT_PACK;
+        a.C = c->out64;
+        RS_TRY(run(c, kind_out, gemm_bytes(c, 8, c->M, a.K, n, 1), gemm_flops(c->M, a.K, n, 1), s,
+                   [&] { return launch_gemm(0, a, s); }));
+    }
+    EnergyArgs e{};
+    e.out = c->out64;
+    e.rows_pad = c->Mp;
+    e.S = c->S;
+    e.nt = c->nt;
+    e.nf = c->nf;
+    e.wV = c->wV;
+    e.Xt = c->Xt;
+    e.targets = c->nt ? targets : nullptr;
+    e.force = c->nf ? force : nullptr;
+    e.imap = imap;
+    e.imap_div = imap_div;
+    e.mu = c->mu;
+    e.lam = c->lam;
+    e.k_c = c->k_c;
+    e.elastic_only = elastic_only;
+    e.grav_row = c->grav_row;
+    e.force_row = c->force_row;
+    e.E = E;
+    return run(c, K_ENERGY, 8.0 * n * c->M + 8.0 * n, (double)n * c->S * 60.0, s,
+               [&] { return launch_energy(0, e, n, s); });
+}
+
+extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const rs_load* load,
+                                   uint32_t flags, double* E, double* g, double* H, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
+    if (B == 0) return RS_OK;
+    if (!z || !E) return fail(c, RS_ERR_ARG, "z and E must not be NULL");
+    const bool eonly = flags & RS_ENERGY_ONLY;
+    if (!eonly && !g) return fail(c, RS_ERR_ARG, "g must not be NULL unless RS_ENERGY_ONLY");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double* tg = load ? load->targets : nullptr;
+    const double* fo = load ? load->force : nullptr;
+    const int r = c->r;
+    for (int c0 = 0; c0 < B; c0 += c->max_batch) {
+        const int n = std::min(c->max_batch, B - c0);
+        const double* zc = z + (size_t)c0 * r;
+        const double* tgc = tg ? tg + (size_t)c0 * c->nt * 3 : nullptr;
+        const double* foc = fo ? fo + (size_t)c0 * 3 : nullptr;
+        if (!eonly)
+            RS_TRY(eval_T(c, n, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0, g + (size_t)c0 * r,
+                          H ? H + (size_t)c0 * r * r : nullptr, s));
+        if (eonly || c->f32)
+            RS_TRY(energy_f64(c, n, zc, nullptr, tgc, foc, nullptr, 1, (flags & RS_ELASTIC_ONLY) ? 1 : 0, E + c0, s,
+                              K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
+    if (B == 0 || (!x && !J)) return RS_OK;
+    if (!z) return fail(c, RS_ERR_ARG, "z is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int r = c->r, nc = J ? c->nc : 1;
+    const int f32 = c->f32;
+    const size_t ts = c->tsz;
+    for (int l = 0; l < c->L; ++l) {
+        GemmArgs a{};
+        a.A = c->W[l];
+        a.lda = l == 0 ? c->lda0 : c->lda_h;
+        a.rows = c->w;
+        a.rows_pad = c->wrows;
+        a.K = l == 0 ? r : c->w;
+        a.nc = nc;
+        a.items = B;
+        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
+        a.Y = l == 0 ? nullptr : c->pre[l - 1];
+        a.z = z;
+        a.r = r;
+        a.bias = c->bh[l];
+        a.out_mode = OUT_PACK;
+        a.C = c->pre[l];
+        RS_TRY(run(c, K_DECODE_HIDDEN, gemm_bytes(c, ts, a.rows, a.K, B, nc), gemm_flops(a.rows, a.K, B, nc), s,
+                   [&] { return launch_gemm(f32, a, s); }));
+    }
+    GemmArgs a{};
+    a.A = c->Wfull;
+    a.lda = c->lda_out;
+    a.rows = c->n_out;
+    a.rows_pad = c->Nfp;
+    a.K = c->in_last;
+    a.nc = nc;
+    a.items = B;
+    a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
+    a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+    a.z = z;
+    a.r = r;
+    a.bias = c->bfull;
+    a.out_mode = OUT_SPLIT;
+    a.Xo = x;
+    a.Jo = J;
+    a.Xrest = c->Xfull;
+    return run(c, K_DECODE_OUT, gemm_bytes(c, ts, c->n_out, a.K, B, nc), gemm_flops(c->n_out, a.K, B, nc), s,
+               [&] { return launch_gemm(f32, a, s); });
+}
+
+static int read_counter(rs_ctx* c, int idx, hipStream_t s, int* out)
+{
+    hipError_t e = hipMemcpyAsync(c->hcount + idx, c->counters + idx, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+    *out = c->hcount[idx];
+    return RS_OK;
+}
+
+extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
+                               int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
+    if (B == 0) return RS_OK;
+    if (!z || !iters || !status || !relgrad || !E) return fail(c, RS_ERR_ARG, "NULL output pointer");
+    rs_solve_opts def;
+    rs_default_opts(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
+        o->proj < 0 || o->proj > 2)
+        return fail(c, RS_ERR_ARG, "invalid solver options");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double* tg = load ? load->targets : nullptr;
+    const double* fo = load ? load->force : nullptr;
+    const int r = c->r;
+
+    NewtonState st{};
+    st.z = z;
+    st.iters = iters;
+    st.status = status;
+    st.relgrad = relgrad;
+    st.E = E;
+    st.g0 = c->g0;
+    st.gnorm = c->gnorm;
+    st.dz = c->dz;
+    st.slope = c->slope;
+    st.ls_j0 = c->ls_j0;
+    st.active = c->active;
+    st.counters = c->counters;
+    st.gw = c->gw;
+    st.Hw = c->Hw;
+    st.zc = c->zc;
+    st.Ec = c->Ec;
+    NewtonParams p{};
+    p.r = r;
+    p.max_iter = o->max_iter;
+    p.ls_max = o->ls_max;
+    p.proj = o->proj;
+    p.c1 = o->c1;
+    p.shrink = o->shrink;
+    p.rel_tol = o->rel_tol;
+    p.abs_tol = o->abs_tol;
+    p.eig_floor = o->eig_floor;
+    const uint32_t flags = o->hess ? RS_HESS_EXACT : 0;
+
+    RS_TRY(run(c, K_INIT, 0, 0, s, [&] { return launch_newton_init(st, B, s); }));
+    // float64 energy at the start points
+    RS_TRY(energy_f64(c, B, z, nullptr, tg, fo, nullptr, 1, 0, E, s, K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+    for (int outer = 0; outer <= o->max_iter + 1; ++outer) {
+        int n_act = 0;
+        RS_TRY(run(c, K_COMPACT, 8.0 * B, 0, s, [&] { return launch_compact(st, B, s); }));
+        RS_TRY(read_counter(c, 0, s, &n_act));
+        if (n_act == 0) break;
+        RS_TRY(eval_T(c, n_act, z, c->active, tg, fo, c->active, flags, nullptr, c->gw, c->Hw, s));
+        RS_TRY(run(c, K_DIR, 8.0 * n_act * (r + r * r), (double)n_act * r * r * r, s,
+                   [&] { return launch_newton_dir(st, p, n_act, s); }));
+        for (int round = 0; round * kLsCand < o->ls_max + kLsCand; ++round) {
+            RS_TRY(run(c, K_LS_CAND, 8.0 * n_act * kLsCand * r, 0, s,
+                       [&] { return launch_ls_candidates(st, p, n_act, s); }));
+            RS_TRY(energy_f64(c, n_act * kLsCand, c->zc, nullptr, tg, fo, c->active, kLsCand, 0, c->Ec, s,
+                              K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+            RS_TRY(run(c, K_ARMIJO, 8.0 * n_act * kLsCand, 0, s, [&] { return launch_armijo(st, p, n_act, s); }));
+            int searching = 0;
+            RS_TRY(read_counter(c, 1, s, &searching));
+            if (searching == 0) break;
+        }
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,
+                                 double* per_pair, int32_t* n_valid, double* lip_max, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
+    if (!loss || !n_valid || (B > 0 && (!z1 || !z2))) return fail(c, RS_ERR_ARG, "NULL pointer");
+    if (c->max_batch < 2) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz loss needs max_batch >= 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int r = c->r, chunk = c->max_batch / 2;
+    int c0 = 0;
+    do {
+        const int n = std::min(chunk, B - c0);
+        const bool first = c0 == 0, last = c0 + n >= B;
+        if (n > 0) {
+            RS_TRY(run(c, K_LIPSCHITZ, 16.0 * n * r, 0, s, [&] {
+                return launch_stack_pairs(z1 + (size_t)c0 * r, z2 + (size_t)c0 * r, c->zs, n, r, s);
+            }));
+            RS_TRY(eval_T(c, 2 * n, c->zs, nullptr, nullptr, nullptr, nullptr, RS_HESS_EXACT | RS_ELASTIC_ONLY,
+                          nullptr, c->gw, c->Hw, s));
+        }
+        RS_TRY(run(c, K_LIPSCHITZ, 16.0 * n * r * r, 3.0 * n * r * r, s, [&] {
+            return launch_lipschitz(z1 + (size_t)c0 * r, z2 + (size_t)c0 * r, c->Hw, n, r,
+                                    per_pair ? per_pair + c0 : nullptr, c->ell, c->lacc, first, last, loss,
+                                    n_valid, lip_max, s);
+        }));
+        c0 += n;
+    } while (c0 < B);
+    return RS_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+extern "C" int rs_profile(rs_ctx* c, int32_t enable)
+{
+    if (!c) return RS_ERR_STATE;
+    if (enable) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+        c->recs.clear();
+        c->evnext = 0;
+        for (int k = 0; k < K_COUNT; ++k) {
+            c->kms[k] = c->kbytes[k] = c->kflops[k] = 0.0;
+            c->klaunch[k] = 0;
+        }
+        c->aggregated = true;
+    }
+    c->prof = enable != 0;
+    return RS_OK;
+}
+
+extern "C" int rs_profile_get(rs_ctx* c, int32_t idx, int32_t* n_kinds, char* name, int32_t name_len,
+                              int32_t* launches, double* total_ms, double* bytes, double* flops)
+{
+    if (!c) return RS_ERR_STATE;
+    if (!c->aggregated) {
+        for (const ProfRec& rec : c->recs) {
+            hipError_t e = hipEventSynchronize(c->evpool[rec.e1]);
+            if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, c->evpool[rec.e0], c->evpool[rec.e1]);
+            if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+            c->kms[rec.kind] += ms;
+            c->kbytes[rec.kind] += rec.bytes;
+            c->kflops[rec.kind] += rec.flops;
+            c->klaunch[rec.kind] += 1;
+        }
+        c->recs.clear();
+        c->evnext = 0;
+        c->aggregated = true;
+    }
+    if (n_kinds) *n_kinds = K_COUNT;
+    if (idx < 0 || idx >= K_COUNT) return RS_OK;
+    if (name && name_len > 0) {
+        std::strncpy(name, kKindName[idx], (size_t)name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (launches) *launches = c->klaunch[idx];
+    if (total_ms) *total_ms = c->kms[idx];
+    if (bytes) *bytes = c->kbytes[idx];
+    if (flops) *flops = c->kflops[idx];
+    return RS_OK;
+}

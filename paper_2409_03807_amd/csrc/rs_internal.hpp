@@ -1,0 +1,137 @@
+// Internal declarations shared by the host code (rs_api.cpp) and the kernels
+// (rs_kernels.hip).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rs.h"
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rs {
+
+constexpr int kTileM = 64;   // GEMM rows per workgroup
+constexpr int kTileN = 64;   // GEMM columns per workgroup
+constexpr int kTileK = 16;   // GEMM reduction chunk
+constexpr int kMaxR = 32;    // largest latent dimension
+constexpr int kLsCand = 4;   // line-search step lengths evaluated per round
+constexpr int kMaxL = 8;     // largest number of hidden layers
+
+enum InMode { IN_RAW = 0, IN_ELU = 1, IN_LATENT = 2 };
+enum OutMode { OUT_PACK = 0, OUT_SPLIT = 1 };
+
+// C[item] (rows x nc) = A (rows x K) * Y[item] (K x nc) (+ bias on column 0)
+// for `items` items stored item-major.  The column index n = item*nc + c runs
+// over all items, so any nc works with the same 64-column tiles.
+struct GemmArgs {
+    const void* A;        // rows_pad x lda, row-major, zero padded (context precision)
+    int lda;              // >= K, multiple of kTileK
+    int rows;             // valid output rows
+    int rows_pad;         // multiple of kTileM
+    int K;                // reduction length
+    int nc;               // columns per item
+    int items;
+    int in_mode;          // InMode
+    const void* Y;        // IN_RAW / IN_ELU: item-major (K x nc) blocks
+    const double* z;      // IN_LATENT: (.. x r) latent points (always float64)
+    const int* zmap;      // IN_LATENT: item -> row of z (NULL = identity)
+    int r;
+    const void* bias;     // rows, added to column 0 (NULL = none)
+    int out_mode;         // OutMode
+    void* C;              // OUT_PACK: item-major (rows_pad x nc)
+    void* Xo;             // OUT_SPLIT: column 0 -> Xo[item*rows + m] = Xrest[m] + value
+    void* Jo;             // OUT_SPLIT: column c>0 -> Jo[(item*rows + m)*r + c-1]
+    const void* Xrest;
+};
+
+// Per-item cubature elastic, penalty, gravity and force terms from the rows of
+// the reduced output map (energy, gradient, Gauss-Newton Hessian, adjoint seeds).
+struct ElemArgs {
+    const void* out;      // item-major (rows_pad x nc) [value | Jacobian] rows
+    int rows_pad, nc, r;
+    int S, nt, nf;        // cubature tets, targeted vertices, force flag (0/1)
+    const double* wV;     // S: cubature weight times rest volume
+    const double* Xt;     // nt x 3 rest positions of targeted vertices
+    const double* targets;// (B x nt x 3) or NULL
+    const double* force;  // (B x 3) or NULL
+    const int* imap;      // item -> batch index for targets/force (NULL = identity)
+    double mu, lam, k_c;
+    int elastic_only;
+    int grav_row, force_row; // first row of the gravity / force rows
+    double* E;            // items (may be NULL)
+    double* g;            // items x r (may be NULL)
+    double* H;            // items x r x r (may be NULL)
+    void* dseed;          // items x rows_pad adjoint seeds dE/d(row value) (may be NULL)
+};
+
+struct EnergyArgs {
+    const void* out;      // item-major (rows_pad x 1) values
+    int rows_pad;
+    int S, nt, nf;
+    const double* wV;
+    const double* Xt;
+    const double* targets;
+    const double* force;
+    const int* imap;      // item -> batch index for loads
+    int imap_div;         // batch index = imap[item / imap_div] (candidates share loads)
+    double mu, lam, k_c;
+    int elastic_only;
+    int grav_row, force_row;
+    double* E;            // items
+};
+
+// Reverse pass through the hidden layers adding sum_l A_l^T diag(gbar_l s''(a_l)) A_l.
+struct CurvArgs {
+    const void* pre[kMaxL]; // item-major (width x nc) pre-activations [a | A] per hidden layer
+    const void* W[kMaxL];   // hidden weights (width x in), in = r for layer 0
+    const void* gbar;       // items x pre_rows: dE/dh_L
+    int L, width, nc, r;
+    int pre_rows;           // padded rows of a pre-activation block
+    int lda0, lda;          // leading dimensions of W[0] and of W[l>0]
+    double* H;              // items x r x r, accumulated
+    double* grev;           // items x r reverse-mode gradient (may be NULL)
+};
+
+struct NewtonState {
+    double* z;        // B x r (caller)
+    int* iters;       // B (caller)
+    int* status;      // B (caller)
+    double* relgrad;  // B (caller)
+    double* E;        // B (caller) current float64 energy
+    double* g0;       // B
+    double* gnorm;    // B
+    double* dz;       // B x r
+    double* slope;    // B
+    int* ls_j0;       // B
+    int* active;      // B compact list
+    int* counters;    // [0] n_active, [1] n_searching
+    const double* gw; // active x r  (compact)
+    const double* Hw; // active x r x r
+    double* zc;       // active*kLsCand x r candidates
+    const double* Ec; // active*kLsCand energies
+};
+
+struct NewtonParams {
+    int r, max_iter, ls_max, proj;
+    double c1, shrink, rel_tol, abs_tol, eig_floor;
+};
+
+// ----------------------------------------------------------------- launchers
+hipError_t launch_gemm(int f32, const GemmArgs& a, hipStream_t s);
+hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
+hipError_t launch_energy(int f32, const EnergyArgs& a, int items, hipStream_t s);
+hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
+hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
+hipError_t launch_compact(const NewtonState& st, int B, hipStream_t s);
+hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
+hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
+hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s);
+hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H, int B, int r,
+                            double* per_pair, double* ell, double* acc, int first_chunk, int last_chunk,
+                            double* loss, int* n_valid, double* lip_max, hipStream_t s);
+
+}  // namespace rs

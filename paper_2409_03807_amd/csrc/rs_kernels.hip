@@ -1,0 +1,947 @@
+// HIP kernels of the reduced-Newton hot path for gfx950 (MI355X).
+//
+// Data layout: every batch tensor is item-major.  For one item the decoder
+// state of a layer is a (rows x nc) block, nc = 1 + r, whose column 0 is the
+// value (pre-activation a, or output value) and columns 1..r its Jacobian with
+// respect to z (forward mode, Sec. 3.2 decoder with its Jacobian df/dz as in
+// Eq. form-cubature-gradients).  The GEMMs flatten (item, column) into one
+// column index, so any r uses the same 64x64 MFMA tiles.
+#include "rs_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace rs {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc_t = f32x4;
+    __device__ static acc_t mac(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    using acc_t = f64x4;
+    __device__ static acc_t mac(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+// ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
+__device__ inline float elu0(float a) { return a > 0.f ? a : expm1f(a); }
+__device__ inline double elu0(double a) { return a > 0.0 ? a : expm1(a); }
+__device__ inline float elu1(float a) { return a > 0.f ? 1.f : expf(a); }
+__device__ inline double elu1(double a) { return a > 0.0 ? 1.0 : exp(a); }
+__device__ inline double elu2(double a) { return a > 0.0 ? 0.0 : exp(a); }
+
+// ---------------------------------------------------------------------------
+// GEMM: C[item] = A * Y[item] (+ bias on column 0), MFMA 16x16x4, 64x64 tiles.
+// Each of the 4 waves owns 16 rows x 64 columns (four 16x16 accumulators).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
+{
+    __shared__ T As[kTileK][kTileM + 1];
+    __shared__ T Ys[kTileK][kTileN];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * kTileM;
+    const long n0 = (long)blockIdx.y * kTileN;
+    const long ncols = (long)a.items * a.nc;
+    const T* A = static_cast<const T*>(a.A);
+    using acc_t = typename Mfma<T>::acc_t;
+    acc_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+
+    const int arow = tid >> 2, akq = (tid & 3) * 4;
+    const int ynn = tid & 63, ykb = (tid >> 6) * 4;
+    const long yn = n0 + ynn;
+    long yitem = 0;
+    int yc = 0;
+    if (yn < ncols) {
+        yitem = yn / a.nc;
+        yc = (int)(yn - yitem * a.nc);
+    }
+    long zrow = 0;
+    if (a.in_mode == IN_LATENT && yn < ncols) zrow = a.zmap ? a.zmap[yitem] : yitem;
+
+    for (int k0 = 0; k0 < a.K; k0 += kTileK) {
+        {
+            const T* src = A + (size_t)(m0 + arow) * a.lda + k0 + akq;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) As[akq + q][arow] = src[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = k0 + ykb + q;
+            T v = T(0);
+            if (yn < ncols && k < a.K) {
+                if (a.in_mode == IN_LATENT) {
+                    if (yc == 0) v = (T)a.z[zrow * a.r + k];
+                    else v = (k == yc - 1) ? T(1) : T(0);
+                } else {
+                    const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * y_rows + k) * a.nc;
+                    if (a.in_mode == IN_ELU) {
+                        const T av = Yb[0];
+                        v = (yc == 0) ? elu0(av) : T(elu1(av)) * Yb[yc];
+                    } else {
+                        v = Yb[yc];
+                    }
+                }
+            }
+            Ys[ykb + q][ynn] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kTileK / 4; ++kk) {
+            const T av = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T bv = Ys[kk * 4 + (lane >> 4)][t * 16 + (lane & 15)];
+                acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+            }
+        }
+        __syncthreads();
+    }
+
+    const T* bias = static_cast<const T*>(a.bias);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const long n = n0 + t * 16 + (lane & 15);
+        if (n >= ncols) continue;
+        const long item = n / a.nc;
+        const int c = (int)(n - item * a.nc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = m0 + wave * 16 + (lane >> 4) * 4 + v;
+            if (m >= a.rows) continue;
+            T val = acc[t][v];
+            if (c == 0 && bias) val += bias[m];
+            if (a.out_mode == OUT_PACK) {
+                static_cast<T*>(a.C)[((size_t)item * a.rows_pad + m) * a.nc + c] = val;
+            } else if (c == 0) {
+                if (a.Xo) static_cast<T*>(a.Xo)[(size_t)item * a.rows + m] = static_cast<const T*>(a.Xrest)[m] + val;
+            } else if (a.Jo) {
+                static_cast<T*>(a.Jo)[((size_t)item * a.rows + m) * a.r + (c - 1)] = val;
+            }
+        }
+    }
+}
+
+hipError_t launch_gemm(int f32, const GemmArgs& a, hipStream_t s)
+{
+    if (a.items <= 0) return hipSuccess;
+    const long ncols = (long)a.items * a.nc;
+    dim3 grid(a.rows_pad / kTileM, (unsigned)((ncols + kTileN - 1) / kTileN));
+    // Y blocks of hidden layers are stored with their padded row count
+    const int y_rows = a.in_mode == IN_LATENT ? a.K : ((a.K + kTileM - 1) / kTileM) * kTileM;
+    if (f32) hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, s, a, y_rows);
+    else hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, s, a, y_rows);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stable Neo-Hookean density psi = mu/2 (I_C - 3) - mu (J - 1) + lam/2 (J - 1)^2
+// evaluated in terms of the displacement gradient G = F - I, so that no term
+// is a difference of O(1) numbers (float32 keeps its relative precision at
+// small strain):
+//   I_C - 3 = 2 tr G + |G|^2,   J - 1 = tr G + i2(G) + det G,
+//   cof F = (1 + tr G) I - G^T + cof G,
+//   psi = mu/2 |G|^2 - mu (i2(G) + det G) + lam/2 (J - 1)^2,
+//   P = mu (G + G^T - tr G I - cof G) + lam (J - 1) cof F.
+// vec index v = 3 j + i (column-major, G_ij); columns g_j of G, f_j of F.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Snh {
+    T g[3][3];   // g[j][i] = G_ij
+    T f[3][3];   // f[j][i] = F_ij
+    T cof[3][3]; // cof[j][i] = (cof F)_ij
+    T cg[3][3];  // cg[j][i] = (cof G)_ij
+    T jm, psi, s; // J - 1, energy density, lam (J-1) - mu
+
+    __device__ void set(const T* gu, T mu, T lam)
+    {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                g[j][i] = gu[3 * j + i];
+                f[j][i] = g[j][i] + (i == j ? T(1) : T(0));
+            }
+        cross(g[1], g[2], cg[0]);
+        cross(g[2], g[0], cg[1]);
+        cross(g[0], g[1], cg[2]);
+        const T tr = g[0][0] + g[1][1] + g[2][2];
+        const T detg = g[0][0] * cg[0][0] + g[0][1] * cg[0][1] + g[0][2] * cg[0][2];
+        const T i2 = (g[0][0] * g[1][1] - g[1][0] * g[0][1]) + (g[0][0] * g[2][2] - g[2][0] * g[0][2])
+                   + (g[1][1] * g[2][2] - g[2][1] * g[1][2]);
+        T nrm = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                nrm += g[j][i] * g[j][i];
+                cof[j][i] = (i == j ? T(1) + tr : T(0)) - g[i][j] + cg[j][i];
+            }
+        jm = tr + i2 + detg;
+        psi = T(0.5) * mu * nrm - mu * (i2 + detg) + T(0.5) * lam * jm * jm;
+        s = lam * jm - mu;
+    }
+    __device__ static void cross(const T* a, const T* b, T* c)
+    {
+        c[0] = a[1] * b[2] - a[2] * b[1];
+        c[1] = a[2] * b[0] - a[0] * b[2];
+        c[2] = a[0] * b[1] - a[1] * b[0];
+    }
+    // first Piola-Kirchhoff stress, vec layout
+    __device__ void pk1(T mu, T lam, T* P) const
+    {
+        const T tr = g[0][0] + g[1][1] + g[2][2];
+        const T lj = lam * jm;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                P[3 * j + i] = mu * (g[j][i] + g[i][j] - (i == j ? tr : T(0)) - cg[j][i]) + lj * cof[j][i];
+    }
+    // (d2 psi / dF2) v = mu v + lam g (g.v) + s d(cof F)[v], g = vec cof F,
+    // d(cof F)[v] = [v1 x f2 + f1 x v2, v2 x f0 + f2 x v0, v0 x f1 + f0 x v1]
+    __device__ void apply_hess(T mu, T lam, const T* v, T* out) const
+    {
+        T gv = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) gv += cof[j][i] * v[3 * j + i];
+        T d0[3], d1[3], d2[3], t0[3], t1[3];
+        cross(v + 3, f[2], t0); cross(f[1], v + 6, t1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d0[i] = t0[i] + t1[i];
+        cross(v + 6, f[0], t0); cross(f[2], v, t1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d1[i] = t0[i] + t1[i];
+        cross(v, f[1], t0); cross(f[0], v + 3, t1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) d2[i] = t0[i] + t1[i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            out[i] = mu * v[i] + lam * cof[0][i] * gv + s * d0[i];
+            out[3 + i] = mu * v[3 + i] + lam * cof[1][i] * gv + s * d1[i];
+            out[6 + i] = mu * v[6 + i] + lam * cof[2][i] * gv + s * d2[i];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Element kernel: one workgroup per item, RP lanes per cubature tet (lane k
+// owns column k of K_e = dvecF/dz).  Per tet: F, psi, PK1, (d2psi/dF2) K_e[:,k],
+// H[:,k] += w V K_e^T (A K_e[:,k]), g[k] += w V K_e[:,k].P; then the penalty,
+// gravity and force rows.  Contributions are float64-accumulated and reduced
+// in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <typename T, int RP>
+__global__ __launch_bounds__(256) void k_elem(ElemArgs a)
+{
+    constexpr int EPW = 64 / RP;
+    __shared__ T Ks[4][EPW][9][RP];
+    __shared__ double redH[4][RP][RP];
+    __shared__ double redg[4][RP];
+    __shared__ double redE[4];
+    const int item = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int eg = lane / RP, k = lane % RP;
+    const int r = a.r, nc = a.nc;
+    const bool kact = k < r;
+    const T* O = static_cast<const T*>(a.out) + (size_t)item * a.rows_pad * nc;
+    T* dseed = a.dseed ? static_cast<T*>(a.dseed) + (size_t)item * a.rows_pad : nullptr;
+    const int bidx = a.imap ? a.imap[item] : item;
+    const T mu = (T)a.mu, lam = (T)a.lam;
+
+    double Hc[RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) Hc[j] = 0.0;
+    double gk = 0.0, Ee = 0.0;
+    const int per_round = 4 * EPW;
+
+    for (int s0 = 0; s0 < a.S; s0 += per_round) {
+        const int s = s0 + wave * EPW + eg;
+        const bool ok = s < a.S;
+        T gu[9], Kc[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            gu[v] = ok ? O[(size_t)(9 * s + v) * nc] : T(0);
+            Kc[v] = (ok && kact) ? O[(size_t)(9 * s + v) * nc + 1 + k] : T(0);
+            Ks[wave][eg][v][k] = Kc[v];
+        }
+        __syncthreads();
+        if (ok) {
+            Snh<T> m;
+            m.set(gu, mu, lam);
+            T P[9], AK[9];
+            m.pk1(mu, lam, P);
+            m.apply_hess(mu, lam, Kc, AK);
+            const double wV = a.wV[s];
+#pragma unroll
+            for (int j = 0; j < RP; ++j) {
+                if (j < r) {
+                    T h = 0;
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) h += Ks[wave][eg][v][j] * AK[v];
+                    Hc[j] += wV * (double)h;
+                }
+            }
+            T gp = 0;
+#pragma unroll
+            for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
+            gk += wV * (double)gp;
+            if (k == 0) Ee += wV * (double)m.psi;
+            if (dseed)
+                for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+        }
+        __syncthreads();
+    }
+
+    const bool ext = !a.elastic_only;
+    const int prow = 9 * a.S;
+    if (ext && a.targets) {
+        const double* tg = a.targets + (size_t)bidx * a.nt * 3;
+        const double kc = a.k_c;
+        for (int t0 = 0; t0 < a.nt; t0 += per_round) {
+            const int t = t0 + wave * EPW + eg;
+            const bool ok = t < a.nt;
+            T Jc[3];
+            double d[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t row = (size_t)(prow + 3 * t + c);
+                Jc[c] = (ok && kact) ? O[row * nc + 1 + k] : T(0);
+                d[c] = ok ? a.Xt[3 * t + c] + (double)O[row * nc] - tg[3 * t + c] : 0.0;
+                Ks[wave][eg][c][k] = Jc[c];
+            }
+            __syncthreads();
+            if (ok) {
+#pragma unroll
+                for (int j = 0; j < RP; ++j) {
+                    if (j < r) {
+                        T h = 0;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) h += Ks[wave][eg][c][j] * Jc[c];
+                        Hc[j] += kc * (double)h;
+                    }
+                }
+                gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
+                if (k == 0) Ee += 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (dseed)
+                    for (int c = k; c < 3; c += RP) dseed[prow + 3 * t + c] = (T)(kc * d[c]);
+            }
+            __syncthreads();
+        }
+    }
+    if (ext && wave == 0 && eg == 0) {
+        const size_t gr = (size_t)a.grav_row;
+        gk -= kact ? (double)O[gr * nc + 1 + k] : 0.0;
+        if (k == 0) Ee -= (double)O[gr * nc];
+        if (a.force && a.nf) {
+            const double* f = a.force + (size_t)bidx * 3;
+            for (int c = 0; c < 3; ++c) {
+                const size_t fr = (size_t)(a.force_row + c);
+                gk -= kact ? f[c] * (double)O[fr * nc + 1 + k] : 0.0;
+                if (k == 0) Ee -= f[c] * (double)O[fr * nc];
+            }
+        }
+    }
+    if (dseed) {
+        // rows not written above: penalty rows without targets, gravity,
+        // force and padding rows
+        for (int row = prow + tid; row < a.rows_pad; row += 256) {
+            double v = 0.0;
+            if (row < a.grav_row) {
+                if (ext && a.targets) continue;
+            } else if (row == a.grav_row) {
+                v = ext ? -1.0 : 0.0;
+            } else if (row < a.force_row + 3) {
+                v = (ext && a.force && a.nf) ? -a.force[(size_t)bidx * 3 + (row - a.force_row)] : 0.0;
+            }
+            dseed[row] = (T)v;
+        }
+    }
+
+    // reduce over the EPW tets of a wave (lanes k, k+RP, ...) then over waves
+#pragma unroll
+    for (int off = RP; off < 64; off <<= 1) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) Hc[j] += __shfl_xor(Hc[j], off);
+        gk += __shfl_xor(gk, off);
+        Ee += __shfl_xor(Ee, off);
+    }
+    if (eg == 0) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) redH[wave][j][k] = Hc[j];
+        redg[wave][k] = gk;
+        if (k == 0) redE[wave] = Ee;
+    }
+    __syncthreads();
+    for (int p = tid; p < r * r; p += 256) {
+        const int j = p / r, kk = p - j * r;
+        const double h = ((redH[0][j][kk] + redH[1][j][kk]) + redH[2][j][kk]) + redH[3][j][kk];
+        if (a.H) a.H[(size_t)item * r * r + p] = h;
+    }
+    if (tid < r && a.g) a.g[(size_t)item * r + tid] = ((redg[0][tid] + redg[1][tid]) + redg[2][tid]) + redg[3][tid];
+    if (tid == 0 && a.E) a.E[item] = ((redE[0] + redE[1]) + redE[2]) + redE[3];
+}
+
+hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
+{
+    if (items <= 0) return hipSuccess;
+    const int rp = a.r <= 4 ? 4 : a.r <= 8 ? 8 : a.r <= 16 ? 16 : 32;
+    dim3 grid(items), block(256);
+#define RS_ELEM(T, RP) hipLaunchKernelGGL((k_elem<T, RP>), grid, block, 0, s, a)
+    if (f32) {
+        switch (rp) {
+        case 4: RS_ELEM(float, 4); break;
+        case 8: RS_ELEM(float, 8); break;
+        case 16: RS_ELEM(float, 16); break;
+        default: RS_ELEM(float, 32); break;
+        }
+    } else {
+        switch (rp) {
+        case 4: RS_ELEM(double, 4); break;
+        case 8: RS_ELEM(double, 8); break;
+        case 16: RS_ELEM(double, 16); break;
+        default: RS_ELEM(double, 32); break;
+        }
+    }
+#undef RS_ELEM
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Energy-only kernel (float64): one workgroup per item, one thread per tet.
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum256(double v, double* sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    const double out = sh[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(256) void k_energy(EnergyArgs a)
+{
+    __shared__ double sh[256];
+    const int item = blockIdx.x, tid = threadIdx.x;
+    const double* O = static_cast<const double*>(a.out) + (size_t)item * a.rows_pad;
+    const int bi = item / a.imap_div;
+    const int bidx = a.imap ? a.imap[bi] : bi;
+    double acc = 0.0;
+    for (int s = tid; s < a.S; s += 256) {
+        double gu[9];
+#pragma unroll
+        for (int v = 0; v < 9; ++v) gu[v] = O[9 * s + v];
+        Snh<double> m;
+        m.set(gu, a.mu, a.lam);
+        acc += a.wV[s] * m.psi;
+    }
+    if (!a.elastic_only) {
+        if (a.targets) {
+            const double* tg = a.targets + (size_t)bidx * a.nt * 3;
+            for (int t = tid; t < a.nt; t += 256) {
+                double e = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double d = a.Xt[3 * t + c] + O[9 * a.S + 3 * t + c] - tg[3 * t + c];
+                    e += d * d;
+                }
+                acc += 0.5 * a.k_c * e;
+            }
+        }
+        if (tid == 0) {
+            acc -= O[a.grav_row];
+            if (a.force && a.nf)
+                for (int c = 0; c < 3; ++c) acc -= a.force[(size_t)bidx * 3 + c] * O[a.force_row + c];
+        }
+    }
+    const double tot = block_sum256(acc, sh);
+    if (tid == 0) a.E[item] = tot;
+}
+
+hipError_t launch_energy(int f32, const EnergyArgs& a, int items, hipStream_t s)
+{
+    if (f32) return hipErrorInvalidValue; // the line-search energy is always float64
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_energy, dim3(items), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Curvature kernel: reverse pass through the hidden layers (activations are
+// the stored pre-activations) adding sum_l A_l^T diag(gbar_l s''(a_l)) A_l,
+// the second-order term of the exact reduced Hessian.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_curv(CurvArgs a)
+{
+    extern __shared__ double smem[];
+    const int w = a.width, nc = a.nc, r = a.r;
+    double* gh = smem;       // dE/dh_l
+    double* ga = gh + w;     // dE/da_l
+    double* cf = ga + w;     // dE/dh_l * s''(a_l), then scratch
+    T* As = reinterpret_cast<T*>(cf + w); // 64 x nc block of [a | A]
+    const int item = blockIdx.x, tid = threadIdx.x;
+    const T* gbar = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows;
+    for (int u = tid; u < w; u += 256) gh[u] = (double)gbar[u];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = a.L - 1; l >= 0; --l) {
+        const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
+        __syncthreads();
+        for (int u = tid; u < w; u += 256) {
+            const double av = (double)P[(size_t)u * nc];
+            cf[u] = gh[u] * elu2(av);
+            ga[u] = gh[u] * elu1(av);
+        }
+        for (int u0 = 0; u0 < w; u0 += 64) {
+            const int nu = (w - u0) < 64 ? (w - u0) : 64;
+            __syncthreads();
+            for (int e = tid; e < nu * nc; e += 256) As[e] = P[(size_t)u0 * nc + e];
+            __syncthreads();
+            for (int q = 0; q < 4; ++q) {
+                const int p = tid + 256 * q;
+                if (p >= r * r) break;
+                const int j = p / r, kk = p - j * r;
+                double s = 0.0;
+                for (int uu = 0; uu < nu; ++uu)
+                    s += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+        if (l > 0) {
+            const T* W = static_cast<const T*>(a.W[l]);
+            for (int v = tid; v < w; v += 256) {
+                double s = 0.0;
+                for (int u = 0; u < w; ++u) s += (double)W[(size_t)u * a.lda + v] * ga[u];
+                cf[v] = s;
+            }
+            __syncthreads();
+            for (int v = tid; v < w; v += 256) gh[v] = cf[v];
+        } else if (a.grev) {
+            const T* W = static_cast<const T*>(a.W[0]);
+            for (int v = tid; v < r; v += 256) {
+                double s = 0.0;
+                for (int u = 0; u < w; ++u) s += (double)W[(size_t)u * a.lda0 + v] * ga[u];
+                a.grev[(size_t)item * r + v] = s;
+            }
+        }
+    }
+    for (int q = 0; q < 4; ++q) {
+        const int p = tid + 256 * q;
+        if (p < r * r) a.H[(size_t)item * r * r + p] += acc[q];
+    }
+}
+
+hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
+{
+    if (items <= 0 || a.L <= 0) return hipSuccess;
+    const size_t sh = 3 * sizeof(double) * a.width + (f32 ? 4 : 8) * 64 * a.nc;
+    if (f32) hipLaunchKernelGGL(k_curv<float>, dim3(items), dim3(256), sh, s, a);
+    else hipLaunchKernelGGL(k_curv<double>, dim3(items), dim3(256), sh, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Newton control (float64)
+// ---------------------------------------------------------------------------
+__global__ void k_newton_init(NewtonState st, int B)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    st.status[b] = RS_RUNNING;
+    st.iters[b] = 0;
+    st.g0[b] = 0.0;
+    st.relgrad[b] = 0.0;
+    st.ls_j0[b] = 0;
+}
+
+hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_init, dim3((B + 255) / 256), dim3(256), 0, s, st, B);
+    return hipGetLastError();
+}
+
+// Ordered list of the items still running (a block-wide prefix sum per 1024).
+__global__ __launch_bounds__(1024) void k_compact(NewtonState st, int B)
+{
+    __shared__ int sc[1024];
+    const int tid = threadIdx.x;
+    int base_out = 0;
+    for (int base = 0; base < B; base += 1024) {
+        const int b = base + tid;
+        const int flag = (b < B && st.status[b] == RS_RUNNING) ? 1 : 0;
+        sc[tid] = flag;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int v = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += v;
+            __syncthreads();
+        }
+        if (flag) st.active[base_out + sc[tid] - 1] = b;
+        const int tot = sc[1023];
+        __syncthreads();
+        base_out += tot;
+    }
+    if (tid == 0) st.counters[0] = base_out;
+}
+
+hipError_t launch_compact(const NewtonState& st, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, st, B);
+    return hipGetLastError();
+}
+
+// Exit tests and the Newton direction of one item per 64-thread workgroup:
+// Cholesky of the symmetrised Hessian if it is positive definite, else cyclic
+// Jacobi eigen-decomposition and the projected (clamped / absolute)
+// eigenvalues.  All in float64.
+__global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams p)
+{
+    __shared__ double Hs[kMaxR][kMaxR + 1];
+    __shared__ double Ls[kMaxR][kMaxR + 1];
+    __shared__ double Vs[kMaxR][kMaxR + 1];
+    __shared__ double gs[kMaxR], dzs[kMaxR], cs[kMaxR], lam[kMaxR];
+    __shared__ int flag;
+    __shared__ double bc[4];
+    const int i = blockIdx.x, tid = threadIdx.x, r = p.r;
+    const int item = st.active[i];
+    const double* gw = st.gw + (size_t)i * r;
+    const double* Hw = st.Hw + (size_t)i * r * r;
+    for (int q = tid; q < r; q += 64) gs[q] = gw[q];
+    for (int q = tid; q < r * r; q += 64) {
+        const int a = q / r, b = q - a * r;
+        const double h = 0.5 * (Hw[a * r + b] + Hw[b * r + a]);
+        Hs[a][b] = h;
+        Ls[a][b] = h;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double gn = 0.0;
+        int fin = isfinite(st.E[item]) ? 1 : 0;
+        for (int q = 0; q < r; ++q) {
+            gn = fmax(gn, fabs(gs[q]));
+            if (!isfinite(gs[q])) fin = 0;
+        }
+        for (int q = 0; q < r * r; ++q)
+            if (!isfinite(Hw[q])) fin = 0;
+        if (st.iters[item] == 0) st.g0[item] = gn;
+        const double g0 = st.g0[item];
+        st.gnorm[item] = gn;
+        st.relgrad[item] = g0 > 0.0 ? gn / g0 : 0.0;
+        int status = RS_RUNNING;
+        if (!fin) status = RS_NONFINITE;
+        else if (gn <= p.abs_tol || gn <= p.rel_tol * g0) status = RS_CONVERGED;
+        else if (st.iters[item] >= p.max_iter) status = RS_ITER_MAX;
+        if (status != RS_RUNNING) st.status[item] = status;
+        flag = (status == RS_RUNNING) ? 0 : -1;
+    }
+    __syncthreads();
+    if (flag < 0) return;
+
+    // Cholesky, column by column
+    for (int j = 0; j < r; ++j) {
+        if (tid == 0) {
+            double d = Ls[j][j];
+            for (int k = 0; k < j; ++k) d -= Ls[j][k] * Ls[j][k];
+            if (!(d > 0.0) || !isfinite(d)) flag = 1;
+            else Ls[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        if (flag) break;
+        for (int a = j + 1 + tid; a < r; a += 64) {
+            double s = Ls[a][j];
+            for (int k = 0; k < j; ++k) s -= Ls[a][k] * Ls[j][k];
+            Ls[a][j] = s / Ls[j][j];
+        }
+        __syncthreads();
+    }
+    if (!flag) {
+        if (tid == 0) {
+            for (int a = 0; a < r; ++a) {
+                double s = -gs[a];
+                for (int k = 0; k < a; ++k) s -= Ls[a][k] * cs[k];
+                cs[a] = s / Ls[a][a];
+            }
+            for (int a = r - 1; a >= 0; --a) {
+                double s = cs[a];
+                for (int k = a + 1; k < r; ++k) s -= Ls[k][a] * dzs[k];
+                dzs[a] = s / Ls[a][a];
+            }
+        }
+        __syncthreads();
+    } else if (p.proj == RS_PROJ_NONE) {
+        if (tid == 0) st.status[item] = RS_NOT_DESCENT;
+        return;
+    } else {
+        // cyclic Jacobi on Hs (overwritten), eigenvectors in Vs
+        for (int q = tid; q < r * r; q += 64) {
+            const int a = q / r, b = q - a * r;
+            Vs[a][b] = (a == b) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int sweep = 0; sweep < 100; ++sweep) {
+            if (tid == 0) {
+                double off = 0.0, tot = 0.0;
+                for (int a = 0; a < r; ++a)
+                    for (int b = 0; b < r; ++b) {
+                        const double h2 = Hs[a][b] * Hs[a][b];
+                        tot += h2;
+                        if (a != b) off += h2;
+                    }
+                bc[0] = (off <= 1e-30 * tot || off == 0.0) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            if (bc[0] != 0.0) break;
+            for (int pp = 0; pp < r - 1; ++pp)
+                for (int qq = pp + 1; qq < r; ++qq) {
+                    const double apq = Hs[pp][qq];
+                    const double app = Hs[pp][pp], aqq = Hs[qq][qq];
+                    __syncthreads();
+                    if (apq == 0.0) continue;
+                    const double theta = (aqq - app) / (2.0 * apq);
+                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                    if (tid < r) {
+                        const double akp = Hs[tid][pp], akq = Hs[tid][qq];
+                        Hs[tid][pp] = c * akp - sn * akq;
+                        Hs[tid][qq] = sn * akp + c * akq;
+                    }
+                    __syncthreads();
+                    if (tid < r) {
+                        const double apk = Hs[pp][tid], aqk = Hs[qq][tid];
+                        Hs[pp][tid] = c * apk - sn * aqk;
+                        Hs[qq][tid] = sn * apk + c * aqk;
+                        const double vkp = Vs[tid][pp], vkq = Vs[tid][qq];
+                        Vs[tid][pp] = c * vkp - sn * vkq;
+                        Vs[tid][qq] = sn * vkp + c * vkq;
+                    }
+                    __syncthreads();
+                }
+        }
+        if (tid == 0) {
+            double lmax = 0.0;
+            for (int k = 0; k < r; ++k) lmax = fmax(lmax, fabs(Hs[k][k]));
+            const double fl = p.eig_floor * lmax;
+            for (int k = 0; k < r; ++k) {
+                double lk = (p.proj == RS_PROJ_ABS) ? fabs(Hs[k][k]) : Hs[k][k];
+                if (lk < fl) lk = fl;
+                if (!(lk > 0.0)) lk = 1.0;
+                lam[k] = lk;
+            }
+        }
+        __syncthreads();
+        if (tid < r) {
+            double c = 0.0;
+            for (int a = 0; a < r; ++a) c += Vs[a][tid] * gs[a];
+            cs[tid] = c / lam[tid];
+        }
+        __syncthreads();
+        if (tid < r) {
+            double d = 0.0;
+            for (int k = 0; k < r; ++k) d -= Vs[tid][k] * cs[k];
+            dzs[tid] = d;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double slope = 0.0;
+        for (int a = 0; a < r; ++a) slope += gs[a] * dzs[a];
+        if (!(slope < 0.0)) {
+            st.status[item] = RS_NOT_DESCENT;
+        } else {
+            st.slope[item] = slope;
+            st.ls_j0[item] = 0;
+        }
+    }
+    for (int a = tid; a < r; a += 64) st.dz[(size_t)item * r + a] = dzs[a];
+}
+
+hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+{
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_dir, dim3(n_act), dim3(64), 0, s, st, p);
+    return hipGetLastError();
+}
+
+// alpha_j = shrink^j by repeated multiplication (j = ls_j0 + t)
+__device__ inline double step_len(double shrink, int j)
+{
+    double a = 1.0;
+    for (int q = 0; q < j; ++q) a *= shrink;
+    return a;
+}
+
+__global__ void k_ls_candidates(NewtonState st, NewtonParams p, int n_act)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx == 0) st.counters[1] = 0;
+    if (idx >= n_act * kLsCand) return;
+    const int i = idx / kLsCand, t = idx - i * kLsCand;
+    const int item = st.active[i];
+    const double alpha = step_len(p.shrink, st.ls_j0[item] + t);
+    for (int k = 0; k < p.r; ++k)
+        st.zc[(size_t)idx * p.r + k] = st.z[(size_t)item * p.r + k] + alpha * st.dz[(size_t)item * p.r + k];
+}
+
+hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+{
+    const int n = n_act * kLsCand;
+    hipLaunchKernelGGL(k_ls_candidates, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, s,
+                       st, p, n_act);
+    return hipGetLastError();
+}
+
+// Armijo test on the float64 candidate energies: accept the first (largest)
+// step with E(z + a dz) - E(z) <= c1 a g.dz, as sequential backtracking would.
+__global__ void k_armijo(NewtonState st, NewtonParams p, int n_act)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_act) return;
+    const int item = st.active[i];
+    // items that are done, or that accepted a step in an earlier round
+    if (st.status[item] != RS_RUNNING || st.ls_j0[item] < 0) return;
+    const double E0 = st.E[item], slope = st.slope[item];
+    const int j0 = st.ls_j0[item];
+    for (int t = 0; t < kLsCand; ++t) {
+        const int j = j0 + t;
+        if (j >= p.ls_max) break;
+        const double alpha = step_len(p.shrink, j);
+        const double Et = st.Ec[(size_t)i * kLsCand + t];
+        if (isfinite(Et) && Et - E0 <= p.c1 * alpha * slope) {
+            for (int k = 0; k < p.r; ++k)
+                st.z[(size_t)item * p.r + k] = st.zc[((size_t)i * kLsCand + t) * p.r + k];
+            st.E[item] = Et;
+            st.iters[item] += 1;
+            st.ls_j0[item] = -1;
+            return;
+        }
+    }
+    const int jn = j0 + kLsCand;
+    if (jn >= p.ls_max) {
+        st.status[item] = RS_LS_MAX;
+    } else {
+        st.ls_j0[item] = jn;
+        atomicAdd(&st.counters[1], 1);
+    }
+}
+
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+{
+    if (n_act <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_armijo, dim3((n_act + 255) / 256), dim3(256), 0, s, st, p, n_act);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lipschitz loss pieces
+// ---------------------------------------------------------------------------
+__global__ void k_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * r) return;
+    const int b = idx / r, k = idx - b * r;
+    zs[(size_t)(2 * b) * r + k] = z1[idx];
+    zs[(size_t)(2 * b + 1) * r + k] = z2[idx];
+}
+
+hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stack_pairs, dim3((B * r + 255) / 256), dim3(256), 0, s, z1, z2, zs, B, r);
+    return hipGetLastError();
+}
+
+// per pair: |H(z1)-H(z2)|_F^2 / |z1-z2|^2 (pair b's Hessians are items 2b, 2b+1)
+__global__ void k_lip_pairs(const double* z1, const double* z2, const double* H, int B, int r,
+                            double* per_pair, double* ell)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double dz2 = 0.0;
+    for (int k = 0; k < r; ++k) {
+        const double d = z1[(size_t)b * r + k] - z2[(size_t)b * r + k];
+        dz2 += d * d;
+    }
+    double v = -1.0;
+    if (dz2 > 0.0) {
+        const double* H1 = H + (size_t)(2 * b) * r * r;
+        const double* H2 = H1 + (size_t)r * r;
+        double f = 0.0;
+        for (int q = 0; q < r * r; ++q) {
+            const double d = H1[q] - H2[q];
+            f += d * d;
+        }
+        v = f / dz2;
+    }
+    ell[b] = v;
+    if (per_pair) per_pair[b] = v < 0.0 ? 0.0 : v;
+}
+
+// acc = {sum, count, max sqrt}; carried over chunks, finalised on the last one
+__global__ __launch_bounds__(256) void k_lip_reduce(const double* ell, int B, double* acc, int first,
+                                                    int last, double* loss, int* n_valid, double* lip_max)
+{
+    __shared__ double ss[256], sn[256], sm[256];
+    const int tid = threadIdx.x;
+    double s = 0.0, n = 0.0, m = 0.0;
+    for (int b = tid; b < B; b += 256) {
+        const double v = ell[b];
+        if (v >= 0.0) {
+            s += v;
+            n += 1.0;
+            m = fmax(m, sqrt(v));
+        }
+    }
+    ss[tid] = s; sn[tid] = n; sm[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+            ss[tid] += ss[tid + w];
+            sn[tid] += sn[tid + w];
+            sm[tid] = fmax(sm[tid], sm[tid + w]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (first) { acc[0] = 0.0; acc[1] = 0.0; acc[2] = 0.0; }
+        acc[0] += ss[0];
+        acc[1] += sn[0];
+        acc[2] = fmax(acc[2], sm[0]);
+        if (last) {
+            *loss = acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
+            *n_valid = (int)acc[1];
+            if (lip_max) *lip_max = acc[2];
+        }
+    }
+}
+
+hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H, int B, int r,
+                            double* per_pair, double* ell, double* acc, int first_chunk, int last_chunk,
+                            double* loss, int* n_valid, double* lip_max, hipStream_t s)
+{
+    if (B > 0)
+        hipLaunchKernelGGL(k_lip_pairs, dim3((B + 255) / 256), dim3(256), 0, s, z1, z2, H, B, r, per_pair, ell);
+    hipLaunchKernelGGL(k_lip_reduce, dim3(1), dim3(256), 0, s, ell, B, acc, first_chunk, last_chunk, loss,
+                       n_valid, lip_max);
+    return hipGetLastError();
+}
+
+}  // namespace rs
