@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-sample", type=int, default=16, help="oracle solves timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
+    ap.add_argument("--proj", default="clamp", choices=["clamp", "abs"], help="Hessian eigen-projection")
+    ap.add_argument("--eig-floor", type=float, default=1e-8)
     return ap.parse_args()
 
 
@@ -73,7 +75,7 @@ def main():
     out = (torch.empty_like(z0), torch.empty(B, dtype=torch.int32, device=dev),
            torch.empty(B, dtype=torch.int32, device=dev), torch.empty(B, dtype=torch.float64, device=dev),
            torch.empty(B, dtype=torch.float64, device=dev))
-    opts = rb.default_opts()
+    opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor)
     z1, z2 = z0[0::2].contiguous(), z0[1::2].contiguous()
 
     def step():

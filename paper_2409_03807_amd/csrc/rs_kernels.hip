@@ -16,12 +16,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
+// Both take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k; the
+// result rows differ: f32 puts D[4 (lane/16) + v][lane%16] in register v,
+// f64 puts D[lane/16 + 4 v][lane%16] in register v.
 template <> struct Mfma<float> {
     using acc_t = f32x4;
     __device__ static acc_t mac(float a, float b, acc_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct Mfma<double> {
     using acc_t = f64x4;
@@ -29,6 +33,7 @@ template <> struct Mfma<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
 // ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
         const int c = (int)(n - item * a.nc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int m = m0 + wave * 16 + (lane >> 4) * 4 + v;
+            const int m = m0 + wave * 16 + Mfma<T>::row(lane, v);
             if (m >= a.rows) continue;
             T val = acc[t][v];
             if (c == 0 && bias) val += bias[m];
