@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-sample", type=int, default=16, help="oracle solves timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
-    ap.add_argument("--proj", default="clamp", choices=["clamp", "abs"], help="Hessian eigen-projection")
+    ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     return ap.parse_args()
 

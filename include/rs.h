@@ -138,7 +138,7 @@ typedef struct {
     double rel_tol;     /* |g|_inf <= rel_tol |g_0|_inf, default 1e-6 */
     double abs_tol;     /* or |g|_inf <= abs_tol, default 0 */
     int32_t hess;       /* 1 exact Hessian (default), 0 Gauss-Newton */
-    int32_t proj;       /* RS_PROJ_*, default RS_PROJ_CLAMP */
+    int32_t proj;       /* RS_PROJ_*, default RS_PROJ_ABS */
     double eig_floor;   /* relative eigenvalue floor, default 1e-8 */
 } rs_solve_opts;
 

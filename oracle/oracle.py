@@ -56,7 +56,7 @@ class Opts(C.Structure):
 
 def default_opts(**kw) -> Opts:
     d = dict(max_iter=50, ls_max=128, c1=1e-4, shrink=0.5, rel_tol=1e-6, abs_tol=0.0,
-             hess=1, proj=PROJ_CLAMP, eig_floor=1e-8)
+             hess=1, proj=PROJ_ABS, eig_floor=1e-8)
     d.update(kw)
     return Opts(**d)
 

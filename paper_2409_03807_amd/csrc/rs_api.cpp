@@ -39,10 +39,19 @@ const char* kKindName[K_COUNT] = {
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
     "newton_init"};
 
+// One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
+// n = 1 for launches sized on the host, else the device counter `which` of
+// super-step `slot` (copied to a device log while profiling).
 struct ProfRec {
     int kind;
-    double bytes, flops;
+    double b0, b1, f0, f1;
+    int slot, which;
     int e0, e1;
+};
+
+struct Work {
+    double b0 = 0, b1 = 0, f0 = 0, f1 = 0;
+    int slot = -1, which = 0;
 };
 
 }  // namespace
@@ -78,9 +87,11 @@ struct rs_ctx {
     void* dseed = nullptr;        // max_batch x Mp T
     void* gbar = nullptr;         // max_batch x in_rows T
     double *Ew = nullptr, *gw = nullptr, *Hw = nullptr;
-    double *g0 = nullptr, *gnorm = nullptr, *dz = nullptr, *slope = nullptr;
-    int *ls_j0 = nullptr, *active = nullptr, *counters = nullptr;
-    double* zc = nullptr;         // kLsCand*max_batch x r
+    double *g0 = nullptr, *dz = nullptr, *slope = nullptr;
+    int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
+    int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
+    int ksplit = 1;               // K slices of the adjoint GEMM
+    double* zc = nullptr;         // kLsCand*max_batch x r candidates
     std::vector<double*> pre64;   // L x (kLsCand*max_batch x wrows)
     double* out64 = nullptr;      // kLsCand*max_batch x Mp
     double* Ec = nullptr;
@@ -88,6 +99,7 @@ struct rs_ctx {
     double* ell = nullptr;        // max_batch
     double* lacc = nullptr;       // 3
     int* hcount = nullptr;        // pinned host
+    hipEvent_t cnt_ev[2] = {nullptr, nullptr}; // running-count copies, one per parity of the super-step
 
     std::string err;
     // profiling
@@ -98,6 +110,9 @@ struct rs_ctx {
     double kms[K_COUNT] = {0}, kbytes[K_COUNT] = {0}, kflops[K_COUNT] = {0};
     int klaunch[K_COUNT] = {0};
     bool aggregated = true;
+    int* plog = nullptr;          // device log of the Newton counters per super-step
+    int plog_cap = 0, plog_next = 0;
+    int cur_slot = -1;            // super-step whose counters size the current launches
 };
 
 static const char* kNullCtxMsg = "rs: null context";
@@ -133,7 +148,7 @@ static void* dalloc_bytes(rs_ctx* c, size_t bytes)
 
 // Launch bracket: records HIP events around the launch when profiling.
 template <class F>
-static int run(rs_ctx* c, int kind, double bytes, double flops, hipStream_t s, F&& f)
+static int run(rs_ctx* c, int kind, const Work& w, hipStream_t s, F&& f)
 {
     int e0 = -1, e1 = -1;
     if (c->prof) {
@@ -150,7 +165,7 @@ static int run(rs_ctx* c, int kind, double bytes, double flops, hipStream_t s, F
     if (e != hipSuccess) return hip_fail(c, e, kKindName[kind]);
     if (c->prof) {
         if (hipEventRecord(c->evpool[e1], s) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventRecord");
-        c->recs.push_back(ProfRec{kind, bytes, flops, e0, e1});
+        c->recs.push_back(ProfRec{kind, w.b0, w.b1, w.f0, w.f1, w.slot, w.which, e0, e1});
         c->aggregated = false;
     }
     return RS_OK;
@@ -312,7 +327,7 @@ extern "C" int rs_default_opts(rs_solve_opts* o)
     o->rel_tol = 1e-6;
     o->abs_tol = 0.0;
     o->hess = 1;
-    o->proj = RS_PROJ_CLAMP;
+    o->proj = RS_PROJ_ABS;
     o->eig_floor = 1e-8;
     return RS_OK;
 }
@@ -322,8 +337,11 @@ extern "C" const char* rs_last_error(const rs_ctx* c) { return c ? c->err.c_str(
 static void destroy(rs_ctx* c)
 {
     for (void* p : c->allocs) (void)hipFree(p);
+    if (c->plog) (void)hipFree(c->plog);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     if (c->hcount) (void)hipHostFree(c->hcount);
+    for (hipEvent_t e : c->cnt_ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -470,16 +488,21 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->Xt = (double*)need(dalloc<double>(c, 3 * (size_t)std::max(c->nt, 1)));
     c->out = need(dalloc_bytes(c, B * c->Mp * nc * ts));
     c->dseed = need(dalloc_bytes(c, B * c->Mp * ts));
-    c->gbar = need(dalloc_bytes(c, B * c->in_rows * ts));
+    c->ksplit = std::max(1, std::min(kMaxSplit, c->Mp / 160));
+    c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
     c->Ew = (double*)need(dalloc<double>(c, B));
     c->gw = (double*)need(dalloc<double>(c, B * c->r));
     c->Hw = (double*)need(dalloc<double>(c, B * c->r * c->r));
     c->g0 = (double*)need(dalloc<double>(c, B));
-    c->gnorm = (double*)need(dalloc<double>(c, B));
     c->dz = (double*)need(dalloc<double>(c, B * c->r));
     c->slope = (double*)need(dalloc<double>(c, B));
-    c->ls_j0 = (int*)need(dalloc<int>(c, B));
-    c->active = (int*)need(dalloc<int>(c, B));
+    c->ls_j = (int*)need(dalloc<int>(c, B));
+    c->eval_list = (int*)need(dalloc<int>(c, B));
+    c->search_list = (int*)need(dalloc<int>(c, B));
+    c->search_start = (int*)need(dalloc<int>(c, B));
+    c->search_ncand = (int*)need(dalloc<int>(c, B));
+    c->cand_item = (int*)need(dalloc<int>(c, BL));
+    c->cand_j = (int*)need(dalloc<int>(c, BL));
     c->counters = (int*)need(dalloc<int>(c, 4));
     c->zc = (double*)need(dalloc<double>(c, BL * c->r));
     c->out64 = (double*)need(dalloc<double>(c, BL * c->Mp));
@@ -490,6 +513,9 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
     if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return bail(fail(c, RS_ERR_OOM, "pinned host allocation failed"));
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&c->cnt_ev[k], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(c, RS_ERR_HIP, "hipEventCreate"));
 
     if (upload(c, c->wV, wVh, 0) != RS_OK) return bail(RS_ERR_HIP);
     if (c->nt) {
@@ -533,22 +559,51 @@ extern "C" int rs_get_info(const rs_ctx* c, rs_info* info)
 }
 
 // ------------------------------------------------------------------ passes
-static double gemm_flops(int rows, int K, int items, int nc) { return 2.0 * rows * K * (double)items * nc; }
-static double gemm_bytes(const rs_ctx* c, size_t ts, int rows, int K, int items, int nc)
+static Work gemm_work(size_t ts, int rows, int K, int items, int nc, const int* count, int slot, int which)
 {
-    (void)c;
-    return (double)ts * ((double)rows * K + (double)items * K * nc + (double)items * rows * nc);
+    Work w;
+    const double per_item_b = (double)ts * ((double)K * nc + (double)rows * nc);
+    const double per_item_f = 2.0 * rows * K * (double)nc;
+    w.b0 = (double)ts * rows * K;
+    if (count) {
+        w.b1 = per_item_b;
+        w.f1 = per_item_f;
+        w.slot = slot;
+        w.which = which;
+    } else {
+        w.b0 += per_item_b * items;
+        w.f0 = per_item_f * items;
+    }
+    return w;
+}
+
+static Work item_work(double per_b, double per_f, int items, const int* count, int slot, int which)
+{
+    Work w;
+    if (count) {
+        w.b1 = per_b;
+        w.f1 = per_f;
+        w.slot = slot;
+        w.which = which;
+    } else {
+        w.b0 = per_b * items;
+        w.f0 = per_f * items;
+    }
+    return w;
 }
 
 // T-precision decoder value + Jacobian, reduced rows, element terms and (exact)
-// the curvature term, for n items whose latent points are z[zmap[i]].
-static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const double* targets,
+// the curvature term.  `cap` items fit the launch; `count` (device, nullable)
+// holds the actual number.  Item i uses latent point z[zmap[i]] and the loads
+// of batch index imap[i].
+static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const int* zmap, const double* targets,
                   const double* force, const int* imap, uint32_t flags, double* E, double* g, double* H,
                   hipStream_t s)
 {
     const int r = c->r, nc = c->nc;
     const int f32 = c->f32;
     const size_t ts = c->tsz;
+    const int slot = c->cur_slot;
     for (int l = 0; l < c->L; ++l) {
         GemmArgs a{};
         a.A = c->W[l];
@@ -557,17 +612,19 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         a.rows_pad = c->wrows;
         a.K = l == 0 ? r : c->w;
         a.nc = nc;
-        a.items = n;
+        a.items = cap;
+        a.count = count;
         a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
         a.Y = l == 0 ? nullptr : c->pre[l - 1];
+        a.y_rows = c->wrows;
         a.z = z;
         a.zmap = zmap;
         a.r = r;
         a.bias = c->bh[l];
         a.out_mode = OUT_PACK;
         a.C = c->pre[l];
-        RS_TRY(run(c, K_GEMM_HIDDEN, gemm_bytes(c, ts, a.rows, a.K, n, nc), gemm_flops(a.rows, a.K, n, nc), s,
-                   [&] { return launch_gemm(f32, a, s); }));
+        RS_TRY(run(c, K_GEMM_HIDDEN, gemm_work(ts, a.rows, a.K, cap, nc, count, slot, 0), s,
+                   [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
     }
     {
         GemmArgs a{};
@@ -577,17 +634,19 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         a.rows_pad = c->Mp;
         a.K = c->in_last;
         a.nc = nc;
-        a.items = n;
+        a.items = cap;
+        a.count = count;
         a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
         a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+        a.y_rows = c->wrows;
         a.z = z;
         a.zmap = zmap;
         a.r = r;
         a.bias = c->bbig;
         a.out_mode = OUT_PACK;
         a.C = c->out;
-        RS_TRY(run(c, K_GEMM_OUT, gemm_bytes(c, ts, c->M, a.K, n, nc), gemm_flops(c->M, a.K, n, nc), s,
-                   [&] { return launch_gemm(f32, a, s); }));
+        RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, nc, count, slot, 0), s,
+                   [&] { return launch_gemm(f32, ROLE_OUT, a, s); }));
     }
     const bool exact = (flags & RS_HESS_EXACT) && c->L > 0 && H;
     {
@@ -599,6 +658,7 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         a.S = c->S;
         a.nt = c->nt;
         a.nf = c->nf;
+        a.count = count;
         a.wV = c->wV;
         a.Xt = c->Xt;
         a.targets = c->nt ? targets : nullptr;
@@ -614,10 +674,10 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         a.g = g;
         a.H = H;
         a.dseed = exact ? c->dseed : nullptr;
-        const double bytes = (double)n * ((double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) +
-                                          8.0 * (1 + r + r * r));
-        const double flops = (double)n * c->S * (18.0 * r * r + 80.0 * r + 150.0);
-        RS_TRY(run(c, K_ELEM, bytes, flops, s, [&] { return launch_elem(f32, a, n, s); }));
+        // algorithmic bytes: read the item's rows once, write seeds and (E, g, H)
+        const double pb = (double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) + 8.0 * (1 + r + r * r);
+        const double pf = (double)c->S * (18.0 * r * r + 80.0 * r + 150.0);
+        RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_elem(f32, a, cap, s); }));
     }
     if (exact) {
         GemmArgs a{};
@@ -627,19 +687,26 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         a.rows_pad = c->in_rows;
         a.K = c->Mp;
         a.nc = 1;
-        a.items = n;
+        a.items = cap;
+        a.count = count;
         a.in_mode = IN_RAW;
         a.Y = c->dseed;
+        a.y_rows = c->Mp;
         a.r = r;
         a.out_mode = OUT_PACK;
         a.C = c->gbar;
-        RS_TRY(run(c, K_GEMM_ADJ, gemm_bytes(c, ts, c->in_last, c->Mp, n, 1), gemm_flops(c->in_last, c->Mp, n, 1), s,
-                   [&] { return launch_gemm(f32, a, s); }));
+        a.ksplit = c->ksplit;
+        a.split_stride = (size_t)c->max_batch * c->in_rows;
+        RS_TRY(run(c, K_GEMM_ADJ, gemm_work(ts, c->in_last, c->Mp, cap, 1, count, slot, 0), s,
+                   [&] { return launch_gemm(f32, ROLE_ADJ, a, s); }));
         CurvArgs ca{};
         for (int l = 0; l < c->L; ++l) {
             ca.pre[l] = c->pre[l];
             ca.W[l] = c->W[l];
         }
+        ca.gbar = c->gbar;
+        ca.ksplit = c->ksplit;
+        ca.split_stride = (size_t)c->max_batch * c->in_rows;
         ca.L = c->L;
         ca.width = c->w;
         ca.nc = nc;
@@ -647,23 +714,24 @@ static int eval_T(rs_ctx* c, int n, const double* z, const int* zmap, const doub
         ca.pre_rows = c->wrows;
         ca.lda0 = c->lda0;
         ca.lda = c->lda_h;
-        ca.gbar = c->gbar;
+        ca.count = count;
         ca.H = H;
         ca.grev = nullptr;
-        RS_TRY(run(c, K_CURV, (double)n * c->L * c->w * nc * ts,
-                   (double)n * c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w), s,
-                   [&] { return launch_curv(f32, ca, n, s); }));
+        const double pb = (double)c->L * c->w * nc * ts + (double)c->ksplit * c->in_rows * ts + 16.0 * r * r;
+        const double pf = (double)c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w);
+        RS_TRY(run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); }));
     }
     return RS_OK;
 }
 
-// float64 value-only decoder and energy for n items (line-search energies).
-// Loads of item i come from batch index imap[i / imap_div].
-static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const double* targets,
-                      const double* force, const int* imap, int imap_div, int elastic_only, double* E,
-                      hipStream_t s, int kind_hidden, int kind_out)
+// float64 value-only decoder and energy for `cap` items (count on the device
+// when non-NULL).  Item i uses latent point z[i] and the loads of imap[i].
+static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const double* z, const double* targets,
+                      const double* force, const int* imap, int elastic_only, double* E, hipStream_t s,
+                      int kind_hidden, int kind_out)
 {
     const int r = c->r;
+    const int slot = c->cur_slot;
     for (int l = 0; l < c->L; ++l) {
         GemmArgs a{};
         a.A = c->W64[l];
@@ -672,17 +740,18 @@ static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const 
         a.rows_pad = c->wrows;
         a.K = l == 0 ? r : c->w;
         a.nc = 1;
-        a.items = n;
+        a.items = cap;
+        a.count = count;
         a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
         a.Y = l == 0 ? nullptr : c->pre64[l - 1];
+        a.y_rows = c->wrows;
         a.z = z;
-        a.zmap = zmap;
         a.r = r;
         a.bias = c->bh64[l];
         a.out_mode = OUT_PACK;
         a.C = c->pre64[l];
-        RS_TRY(run(c, kind_hidden, gemm_bytes(c, 8, a.rows, a.K, n, 1), gemm_flops(a.rows, a.K, n, 1), s,
-                   [&] { return launch_gemm(0, a, s); }));
+        RS_TRY(run(c, kind_hidden, gemm_work(8, a.rows, a.K, cap, 1, count, slot, which), s,
+                   [&] { return launch_gemm(0, ROLE_HIDDEN, a, s); }));
     }
     {
         GemmArgs a{};
@@ -692,17 +761,18 @@ static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const 
         a.rows_pad = c->Mp;
         a.K = c->in_last;
         a.nc = 1;
-        a.items = n;
+        a.items = cap;
+        a.count = count;
         a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
         a.Y = c->L > 0 ? c->pre64[c->L - 1] : nullptr;
+        a.y_rows = c->wrows;
         a.z = z;
-        a.zmap = zmap;
         a.r = r;
         a.bias = c->bbig64;
         a.out_mode = OUT_PACK;
         a.C = c->out64;
-        RS_TRY(run(c, kind_out, gemm_bytes(c, 8, c->M, a.K, n, 1), gemm_flops(c->M, a.K, n, 1), s,
-                   [&] { return launch_gemm(0, a, s); }));
+        RS_TRY(run(c, kind_out, gemm_work(8, c->M, a.K, cap, 1, count, slot, which), s,
+                   [&] { return launch_gemm(0, ROLE_OUT, a, s); }));
     }
     EnergyArgs e{};
     e.out = c->out64;
@@ -710,12 +780,12 @@ static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const 
     e.S = c->S;
     e.nt = c->nt;
     e.nf = c->nf;
+    e.count = count;
     e.wV = c->wV;
     e.Xt = c->Xt;
     e.targets = c->nt ? targets : nullptr;
     e.force = c->nf ? force : nullptr;
     e.imap = imap;
-    e.imap_div = imap_div;
     e.mu = c->mu;
     e.lam = c->lam;
     e.k_c = c->k_c;
@@ -723,8 +793,8 @@ static int energy_f64(rs_ctx* c, int n, const double* z, const int* zmap, const 
     e.grav_row = c->grav_row;
     e.force_row = c->force_row;
     e.E = E;
-    return run(c, K_ENERGY, 8.0 * n * c->M + 8.0 * n, (double)n * c->S * 60.0, s,
-               [&] { return launch_energy(0, e, n, s); });
+    return run(c, K_ENERGY, item_work(8.0 * c->M + 8.0, (double)c->S * 60.0, cap, count, slot, which), s,
+               [&] { return launch_energy(e, cap, s); });
 }
 
 extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const rs_load* load,
@@ -740,16 +810,17 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
     const double* tg = load ? load->targets : nullptr;
     const double* fo = load ? load->force : nullptr;
     const int r = c->r;
+    c->cur_slot = -1;
     for (int c0 = 0; c0 < B; c0 += c->max_batch) {
         const int n = std::min(c->max_batch, B - c0);
         const double* zc = z + (size_t)c0 * r;
         const double* tgc = tg ? tg + (size_t)c0 * c->nt * 3 : nullptr;
         const double* foc = fo ? fo + (size_t)c0 * 3 : nullptr;
         if (!eonly)
-            RS_TRY(eval_T(c, n, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0, g + (size_t)c0 * r,
-                          H ? H + (size_t)c0 * r * r : nullptr, s));
+            RS_TRY(eval_T(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0,
+                          g + (size_t)c0 * r, H ? H + (size_t)c0 * r * r : nullptr, s));
         if (eonly || c->f32)
-            RS_TRY(energy_f64(c, n, zc, nullptr, tgc, foc, nullptr, 1, (flags & RS_ELASTIC_ONLY) ? 1 : 0, E + c0, s,
+            RS_TRY(energy_f64(c, n, nullptr, 0, zc, tgc, foc, nullptr, (flags & RS_ELASTIC_ONLY) ? 1 : 0, E + c0, s,
                               K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
     }
     return RS_OK;
@@ -776,13 +847,14 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
         a.items = B;
         a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
         a.Y = l == 0 ? nullptr : c->pre[l - 1];
+        a.y_rows = c->wrows;
         a.z = z;
         a.r = r;
         a.bias = c->bh[l];
         a.out_mode = OUT_PACK;
         a.C = c->pre[l];
-        RS_TRY(run(c, K_DECODE_HIDDEN, gemm_bytes(c, ts, a.rows, a.K, B, nc), gemm_flops(a.rows, a.K, B, nc), s,
-                   [&] { return launch_gemm(f32, a, s); }));
+        RS_TRY(run(c, K_DECODE_HIDDEN, gemm_work(ts, a.rows, a.K, B, nc, nullptr, -1, 0), s,
+                   [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
     }
     GemmArgs a{};
     a.A = c->Wfull;
@@ -794,6 +866,7 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.items = B;
     a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
     a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+    a.y_rows = c->wrows;
     a.z = z;
     a.r = r;
     a.bias = c->bfull;
@@ -801,8 +874,40 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.Xo = x;
     a.Jo = J;
     a.Xrest = c->Xfull;
-    return run(c, K_DECODE_OUT, gemm_bytes(c, ts, c->n_out, a.K, B, nc), gemm_flops(c->n_out, a.K, B, nc), s,
-               [&] { return launch_gemm(f32, a, s); });
+    return run(c, K_DECODE_OUT, gemm_work(ts, c->n_out, a.K, B, nc, nullptr, -1, 0), s,
+               [&] { return launch_gemm(f32, ROLE_DECODE, a, s); });
+}
+
+// Copy the current Newton counters to the profile log (profiling only).
+static int log_counters(rs_ctx* c, hipStream_t s)
+{
+    c->cur_slot = -1;
+    if (!c->prof) return RS_OK;
+    if (c->plog_next >= c->plog_cap) {
+        // grow: keep what is logged so far
+        const int cap = std::max(1024, 2 * c->plog_cap);
+        int* np = nullptr;
+        if (hipMalloc(&np, (size_t)cap * 4 * sizeof(int)) != hipSuccess) return fail(c, RS_ERR_OOM, "profile log");
+        if (c->plog) {
+            hipError_t e = hipMemcpyAsync(np, c->plog, (size_t)c->plog_cap * 4 * sizeof(int), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+            (void)hipFree(c->plog);
+        }
+        c->plog = np;
+        c->plog_cap = cap;
+    }
+    c->cur_slot = c->plog_next++;
+    return RS_OK;
+}
+
+static int log_commit(rs_ctx* c, hipStream_t s)
+{
+    if (!c->prof || c->cur_slot < 0) return RS_OK;
+    hipError_t e = hipMemcpyAsync(c->plog + 4 * (size_t)c->cur_slot, c->counters, 4 * sizeof(int),
+                                  hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpyAsync");
 }
 
 static int read_counter(rs_ctx* c, int idx, hipStream_t s, int* out)
@@ -840,11 +945,15 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     st.relgrad = relgrad;
     st.E = E;
     st.g0 = c->g0;
-    st.gnorm = c->gnorm;
     st.dz = c->dz;
     st.slope = c->slope;
-    st.ls_j0 = c->ls_j0;
-    st.active = c->active;
+    st.ls_j = c->ls_j;
+    st.eval_list = c->eval_list;
+    st.search_list = c->search_list;
+    st.search_start = c->search_start;
+    st.search_ncand = c->search_ncand;
+    st.cand_item = c->cand_item;
+    st.cand_j = c->cand_j;
     st.counters = c->counters;
     st.gw = c->gw;
     st.Hw = c->Hw;
@@ -861,29 +970,55 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     p.abs_tol = o->abs_tol;
     p.eig_floor = o->eig_floor;
     const uint32_t flags = o->hess ? RS_HESS_EXACT : 0;
+    int* cnt = c->counters;
 
-    RS_TRY(run(c, K_INIT, 0, 0, s, [&] { return launch_newton_init(st, B, s); }));
-    // float64 energy at the start points
-    RS_TRY(energy_f64(c, B, z, nullptr, tg, fo, nullptr, 1, 0, E, s, K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
-    for (int outer = 0; outer <= o->max_iter + 1; ++outer) {
-        int n_act = 0;
-        RS_TRY(run(c, K_COMPACT, 8.0 * B, 0, s, [&] { return launch_compact(st, B, s); }));
-        RS_TRY(read_counter(c, 0, s, &n_act));
-        if (n_act == 0) break;
-        RS_TRY(eval_T(c, n_act, z, c->active, tg, fo, c->active, flags, nullptr, c->gw, c->Hw, s));
-        RS_TRY(run(c, K_DIR, 8.0 * n_act * (r + r * r), (double)n_act * r * r * r, s,
-                   [&] { return launch_newton_dir(st, p, n_act, s); }));
-        for (int round = 0; round * kLsCand < o->ls_max + kLsCand; ++round) {
-            RS_TRY(run(c, K_LS_CAND, 8.0 * n_act * kLsCand * r, 0, s,
-                       [&] { return launch_ls_candidates(st, p, n_act, s); }));
-            RS_TRY(energy_f64(c, n_act * kLsCand, c->zc, nullptr, tg, fo, c->active, kLsCand, 0, c->Ec, s,
-                              K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
-            RS_TRY(run(c, K_ARMIJO, 8.0 * n_act * kLsCand, 0, s, [&] { return launch_armijo(st, p, n_act, s); }));
-            int searching = 0;
-            RS_TRY(read_counter(c, 1, s, &searching));
-            if (searching == 0) break;
+    c->cur_slot = -1;
+    RS_TRY(run(c, K_INIT, Work{}, s, [&] { return launch_newton_init(st, B, s); }));
+    RS_TRY(energy_f64(c, B, nullptr, 0, z, tg, fo, nullptr, 0, E, s, K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+    // Every super-step either evaluates an item or advances its line search by
+    // at least one trial, so this bounds the loop.  The host runs one
+    // super-step ahead: it launches step k+1 before reading the running count
+    // of step k (counts only fall, so an older count bounds every launch).
+    const long max_steps = (long)(o->max_iter + 1) * (2 + o->ls_max) + 2;
+    int n_run = B;
+    for (long step = 0; step < max_steps; ++step) {
+        RS_TRY(log_counters(c, s));
+        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_eval(st, B, s); }));
+        RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw, c->Hw, s));
+        RS_TRY(run(c, K_DIR, item_work(8.0 * (r + r * r), (double)r * r * r, n_run, cnt + 0, c->cur_slot, 0), s,
+                   [&] { return launch_newton_dir(st, p, n_run, s); }));
+        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_search(st, p, B, s); }));
+        RS_TRY(log_commit(c, s));
+        const int cap_c = n_run * kLsCand;
+        RS_TRY(run(c, K_LS_CAND, item_work(16.0 * r, 2.0 * r, cap_c, cnt + 1, c->cur_slot, 1), s,
+                   [&] { return launch_ls_candidates(st, p, cap_c, s); }));
+        RS_TRY(energy_f64(c, cap_c, cnt + 1, 1, c->zc, tg, fo, c->cand_item, 0, c->Ec, s, K_LS_GEMM_HIDDEN,
+                          K_LS_GEMM_OUT));
+        RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
+                   [&] { return launch_armijo(st, p, n_run, s); }));
+        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_count_running(st, B, s); }));
+        const int par = (int)(step & 1);
+        hipError_t e = hipMemcpyAsync(c->hcount + par, cnt + 3, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(c->cnt_ev[par], s);
+        if (e != hipSuccess) return hip_fail(c, e, "running-count copy");
+        if (step == 0) continue;
+        e = hipEventSynchronize(c->cnt_ev[par ^ 1]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+        const int prev = c->hcount[par ^ 1];  // running after step - 1
+        if (prev == 0) {
+            n_run = 0;
+            break;
         }
+        n_run = prev;
     }
+    if (n_run > 0) {
+        // the bound was reached: settle the last count
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        n_run = std::min(c->hcount[0], c->hcount[1]);
+    }
+    c->cur_slot = -1;
+    if (n_run > 0) return fail(c, RS_ERR_STATE, "Newton loop did not terminate");
     return RS_OK;
 }
 
@@ -896,18 +1031,19 @@ extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const d
     if (c->max_batch < 2) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz loss needs max_batch >= 2");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int r = c->r, chunk = c->max_batch / 2;
+    c->cur_slot = -1;
     int c0 = 0;
     do {
         const int n = std::min(chunk, B - c0);
         const bool first = c0 == 0, last = c0 + n >= B;
         if (n > 0) {
-            RS_TRY(run(c, K_LIPSCHITZ, 16.0 * n * r, 0, s, [&] {
+            RS_TRY(run(c, K_LIPSCHITZ, item_work(16.0 * r, 0, n, nullptr, -1, 0), s, [&] {
                 return launch_stack_pairs(z1 + (size_t)c0 * r, z2 + (size_t)c0 * r, c->zs, n, r, s);
             }));
-            RS_TRY(eval_T(c, 2 * n, c->zs, nullptr, nullptr, nullptr, nullptr, RS_HESS_EXACT | RS_ELASTIC_ONLY,
-                          nullptr, c->gw, c->Hw, s));
+            RS_TRY(eval_T(c, 2 * n, nullptr, c->zs, nullptr, nullptr, nullptr, nullptr,
+                          RS_HESS_EXACT | RS_ELASTIC_ONLY, nullptr, c->gw, c->Hw, s));
         }
-        RS_TRY(run(c, K_LIPSCHITZ, 16.0 * n * r * r, 3.0 * n * r * r, s, [&] {
+        RS_TRY(run(c, K_LIPSCHITZ, item_work(16.0 * r * r, 3.0 * r * r, n, nullptr, -1, 0), s, [&] {
             return launch_lipschitz(z1 + (size_t)c0 * r, z2 + (size_t)c0 * r, c->Hw, n, r,
                                     per_pair ? per_pair + c0 : nullptr, c->ell, c->lacc, first, last, loss,
                                     n_valid, lip_max, s);
@@ -926,6 +1062,7 @@ extern "C" int rs_profile(rs_ctx* c, int32_t enable)
         if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
         c->recs.clear();
         c->evnext = 0;
+        c->plog_next = 0;
         for (int k = 0; k < K_COUNT; ++k) {
             c->kms[k] = c->kbytes[k] = c->kflops[k] = 0.0;
             c->klaunch[k] = 0;
@@ -941,19 +1078,26 @@ extern "C" int rs_profile_get(rs_ctx* c, int32_t idx, int32_t* n_kinds, char* na
 {
     if (!c) return RS_ERR_STATE;
     if (!c->aggregated) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+        std::vector<int> log((size_t)c->plog_next * 4);
+        if (c->plog_next) {
+            e = hipMemcpy(log.data(), c->plog, log.size() * sizeof(int), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
+        }
         for (const ProfRec& rec : c->recs) {
-            hipError_t e = hipEventSynchronize(c->evpool[rec.e1]);
-            if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
             float ms = 0.f;
             e = hipEventElapsedTime(&ms, c->evpool[rec.e0], c->evpool[rec.e1]);
             if (e != hipSuccess) return hip_fail(c, e, "hipEventElapsedTime");
+            const double n = rec.slot >= 0 ? (double)log[4 * (size_t)rec.slot + rec.which] : 0.0;
             c->kms[rec.kind] += ms;
-            c->kbytes[rec.kind] += rec.bytes;
-            c->kflops[rec.kind] += rec.flops;
+            c->kbytes[rec.kind] += rec.b0 + rec.b1 * n;
+            c->kflops[rec.kind] += rec.f0 + rec.f1 * n;
             c->klaunch[rec.kind] += 1;
         }
         c->recs.clear();
         c->evnext = 0;
+        c->plog_next = 0;
         c->aggregated = true;
     }
     if (n_kinds) *n_kinds = K_COUNT;

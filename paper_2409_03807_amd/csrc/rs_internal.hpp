@@ -8,8 +8,6 @@
 
 #include <cstddef>
 #include <cstdint>
-#include <string>
-#include <vector>
 
 namespace rs {
 
@@ -17,11 +15,14 @@ constexpr int kTileM = 64;   // GEMM rows per workgroup
 constexpr int kTileN = 64;   // GEMM columns per workgroup
 constexpr int kTileK = 16;   // GEMM reduction chunk
 constexpr int kMaxR = 32;    // largest latent dimension
-constexpr int kLsCand = 4;   // line-search step lengths evaluated per round
+constexpr int kLsCand = 8;   // step lengths evaluated per line-search round after the first
 constexpr int kMaxL = 8;     // largest number of hidden layers
+constexpr int kMaxSplit = 16;// largest split of the adjoint GEMM's reduction
 
 enum InMode { IN_RAW = 0, IN_ELU = 1, IN_LATENT = 2 };
 enum OutMode { OUT_PACK = 0, OUT_SPLIT = 1 };
+// kernel symbols per GEMM role (so profilers tell them apart)
+enum GemmRole { ROLE_HIDDEN = 0, ROLE_OUT = 1, ROLE_ADJ = 2, ROLE_DECODE = 3 };
 
 // C[item] (rows x nc) = A (rows x K) * Y[item] (K x nc) (+ bias on column 0)
 // for `items` items stored item-major.  The column index n = item*nc + c runs
@@ -33,15 +34,19 @@ struct GemmArgs {
     int rows_pad;         // multiple of kTileM
     int K;                // reduction length
     int nc;               // columns per item
-    int items;
+    int items;            // grid capacity in items
+    const int* count;     // if non-NULL: the actual item count (<= items), read on the device
     int in_mode;          // InMode
-    const void* Y;        // IN_RAW / IN_ELU: item-major (K x nc) blocks
+    const void* Y;        // IN_RAW / IN_ELU: item-major (y_rows x nc) blocks
+    int y_rows;           // rows of one Y block (padded)
     const double* z;      // IN_LATENT: (.. x r) latent points (always float64)
     const int* zmap;      // IN_LATENT: item -> row of z (NULL = identity)
     int r;
     const void* bias;     // rows, added to column 0 (NULL = none)
     int out_mode;         // OutMode
     void* C;              // OUT_PACK: item-major (rows_pad x nc)
+    int ksplit;           // >1: blockIdx.z takes one K slice and writes C + z * split_stride
+    size_t split_stride;  // elements between the partial outputs of two K slices
     void* Xo;             // OUT_SPLIT: column 0 -> Xo[item*rows + m] = Xrest[m] + value
     void* Jo;             // OUT_SPLIT: column c>0 -> Jo[(item*rows + m)*r + c-1]
     const void* Xrest;
@@ -52,7 +57,8 @@ struct GemmArgs {
 struct ElemArgs {
     const void* out;      // item-major (rows_pad x nc) [value | Jacobian] rows
     int rows_pad, nc, r;
-    int S, nt, nf;        // cubature tets, targeted vertices, force flag (0/1)
+    int S, nt, nf;        // cubature tets, targeted vertices, force vertices
+    const int* count;     // actual item count (NULL = grid size)
     const double* wV;     // S: cubature weight times rest volume
     const double* Xt;     // nt x 3 rest positions of targeted vertices
     const double* targets;// (B x nt x 3) or NULL
@@ -71,12 +77,12 @@ struct EnergyArgs {
     const void* out;      // item-major (rows_pad x 1) values
     int rows_pad;
     int S, nt, nf;
+    const int* count;     // actual item count (NULL = grid size)
     const double* wV;
     const double* Xt;
     const double* targets;
     const double* force;
-    const int* imap;      // item -> batch index for loads
-    int imap_div;         // batch index = imap[item / imap_div] (candidates share loads)
+    const int* imap;      // item -> batch index for loads (NULL = identity)
     double mu, lam, k_c;
     int elastic_only;
     int grav_row, force_row;
@@ -85,16 +91,22 @@ struct EnergyArgs {
 
 // Reverse pass through the hidden layers adding sum_l A_l^T diag(gbar_l s''(a_l)) A_l.
 struct CurvArgs {
-    const void* pre[kMaxL]; // item-major (width x nc) pre-activations [a | A] per hidden layer
+    const void* pre[kMaxL]; // item-major (pre_rows x nc) pre-activations [a | A] per hidden layer
     const void* W[kMaxL];   // hidden weights (width x in), in = r for layer 0
-    const void* gbar;       // items x pre_rows: dE/dh_L
+    const void* gbar;       // ksplit partials of items x pre_rows: dE/dh_L
+    int ksplit;
+    size_t split_stride;
     int L, width, nc, r;
     int pre_rows;           // padded rows of a pre-activation block
     int lda0, lda;          // leading dimensions of W[0] and of W[l>0]
+    const int* count;       // actual item count (NULL = grid size)
     double* H;              // items x r x r, accumulated
     double* grev;           // items x r reverse-mode gradient (may be NULL)
 };
 
+// Per-item Newton state.  ls_j[b] < 0: the item needs its gradient and Hessian
+// at z (evaluation phase); ls_j[b] >= 0: it is line-searching and the next
+// trial step is shrink^ls_j[b].
 struct NewtonState {
     double* z;        // B x r (caller)
     int* iters;       // B (caller)
@@ -102,16 +114,20 @@ struct NewtonState {
     double* relgrad;  // B (caller)
     double* E;        // B (caller) current float64 energy
     double* g0;       // B
-    double* gnorm;    // B
     double* dz;       // B x r
     double* slope;    // B
-    int* ls_j0;       // B
-    int* active;      // B compact list
-    int* counters;    // [0] n_active, [1] n_searching
-    const double* gw; // active x r  (compact)
-    const double* Hw; // active x r x r
-    double* zc;       // active*kLsCand x r candidates
-    const double* Ec; // active*kLsCand energies
+    int* ls_j;        // B
+    int* eval_list;   // items in the evaluation phase, in batch order
+    int* search_list; // items line-searching, in batch order
+    int* search_start;// first candidate of each searching item
+    int* search_ncand;// candidates of each searching item
+    int* cand_item;   // candidate -> item
+    int* cand_j;      // candidate -> trial index
+    int* counters;    // [0] n_eval [1] n_cand [2] n_search [3] n_running
+    const double* gw; // eval-list order: g (n_eval x r)
+    const double* Hw; // eval-list order: H (n_eval x r x r)
+    double* zc;       // candidates x r
+    const double* Ec; // candidate energies
 };
 
 struct NewtonParams {
@@ -120,15 +136,17 @@ struct NewtonParams {
 };
 
 // ----------------------------------------------------------------- launchers
-hipError_t launch_gemm(int f32, const GemmArgs& a, hipStream_t s);
+hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
-hipError_t launch_energy(int f32, const EnergyArgs& a, int items, hipStream_t s);
+hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
-hipError_t launch_compact(const NewtonState& st, int B, hipStream_t s);
-hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
-hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s);
+hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
+hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
+hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s);
+hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
+hipError_t launch_count_running(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s);
 hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H, int B, int r,
                             double* per_pair, double* ell, double* acc, int first_chunk, int last_chunk,

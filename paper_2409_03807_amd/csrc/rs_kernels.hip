@@ -46,21 +46,34 @@ __device__ inline double elu2(double a) { return a > 0.0 ? 0.0 : exp(a); }
 // ---------------------------------------------------------------------------
 // GEMM: C[item] = A * Y[item] (+ bias on column 0), MFMA 16x16x4, 64x64 tiles.
 // Each of the 4 waves owns 16 rows x 64 columns (four 16x16 accumulators).
+// The item count may live on the device (blocks past it exit at once), and
+// the reduction may be split over blockIdx.z into partial outputs.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
+template <typename T, int ROLE>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 {
     __shared__ T As[kTileK][kTileM + 1];
     __shared__ T Ys[kTileK][kTileN];
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const long ncols = (long)items * a.nc;
+    const long n0 = (long)blockIdx.y * kTileN;
+    if (n0 >= ncols) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.x * kTileM;
-    const long n0 = (long)blockIdx.y * kTileN;
-    const long ncols = (long)a.items * a.nc;
     const T* A = static_cast<const T*>(a.A);
     using acc_t = typename Mfma<T>::acc_t;
     acc_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+
+    int kbeg = 0, kend = a.K;
+    T* Cout = static_cast<T*>(a.C);
+    if (a.ksplit > 1) {
+        const int kchunk = ((a.K + a.ksplit - 1) / a.ksplit + kTileK - 1) / kTileK * kTileK;
+        kbeg = blockIdx.z * kchunk;
+        kend = min(a.K, kbeg + kchunk);
+        Cout += blockIdx.z * a.split_stride;
+    }
 
     const int arow = tid >> 2, akq = (tid & 3) * 4;
     const int ynn = tid & 63, ykb = (tid >> 6) * 4;
@@ -74,7 +87,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
     long zrow = 0;
     if (a.in_mode == IN_LATENT && yn < ncols) zrow = a.zmap ? a.zmap[yitem] : yitem;
 
-    for (int k0 = 0; k0 < a.K; k0 += kTileK) {
+    for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
         {
             const T* src = A + (size_t)(m0 + arow) * a.lda + k0 + akq;
 #pragma unroll
@@ -84,12 +97,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
         for (int q = 0; q < 4; ++q) {
             const int k = k0 + ykb + q;
             T v = T(0);
-            if (yn < ncols && k < a.K) {
+            if (yn < ncols && k < kend) {
                 if (a.in_mode == IN_LATENT) {
                     if (yc == 0) v = (T)a.z[zrow * a.r + k];
                     else v = (k == yc - 1) ? T(1) : T(0);
                 } else {
-                    const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * y_rows + k) * a.nc;
+                    const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * a.y_rows + k) * a.nc;
                     if (a.in_mode == IN_ELU) {
                         const T av = Yb[0];
                         v = (yc == 0) ? elu0(av) : T(elu1(av)) * Yb[yc];
@@ -113,7 +126,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
         __syncthreads();
     }
 
-    const T* bias = static_cast<const T*>(a.bias);
+    const T* bias = (a.ksplit > 1 && blockIdx.z > 0) ? nullptr : static_cast<const T*>(a.bias);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const long n = n0 + t * 16 + (lane & 15);
@@ -127,7 +140,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
             T val = acc[t][v];
             if (c == 0 && bias) val += bias[m];
             if (a.out_mode == OUT_PACK) {
-                static_cast<T*>(a.C)[((size_t)item * a.rows_pad + m) * a.nc + c] = val;
+                Cout[((size_t)item * a.rows_pad + m) * a.nc + c] = val;
             } else if (c == 0) {
                 if (a.Xo) static_cast<T*>(a.Xo)[(size_t)item * a.rows + m] = static_cast<const T*>(a.Xrest)[m] + val;
             } else if (a.Jo) {
@@ -137,15 +150,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a, int y_rows)
     }
 }
 
-hipError_t launch_gemm(int f32, const GemmArgs& a, hipStream_t s)
+template <typename T>
+static void gemm_dispatch(int role, dim3 grid, const GemmArgs& a, hipStream_t s)
+{
+    switch (role) {
+    case ROLE_HIDDEN: hipLaunchKernelGGL((k_gemm<T, ROLE_HIDDEN>), grid, dim3(256), 0, s, a); break;
+    case ROLE_OUT: hipLaunchKernelGGL((k_gemm<T, ROLE_OUT>), grid, dim3(256), 0, s, a); break;
+    case ROLE_ADJ: hipLaunchKernelGGL((k_gemm<T, ROLE_ADJ>), grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_gemm<T, ROLE_DECODE>), grid, dim3(256), 0, s, a); break;
+    }
+}
+
+hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
 {
     if (a.items <= 0) return hipSuccess;
     const long ncols = (long)a.items * a.nc;
-    dim3 grid(a.rows_pad / kTileM, (unsigned)((ncols + kTileN - 1) / kTileN));
-    // Y blocks of hidden layers are stored with their padded row count
-    const int y_rows = a.in_mode == IN_LATENT ? a.K : ((a.K + kTileM - 1) / kTileM) * kTileM;
-    if (f32) hipLaunchKernelGGL(k_gemm<float>, grid, dim3(256), 0, s, a, y_rows);
-    else hipLaunchKernelGGL(k_gemm<double>, grid, dim3(256), 0, s, a, y_rows);
+    dim3 grid(a.rows_pad / kTileM, (unsigned)((ncols + kTileN - 1) / kTileN), a.ksplit > 1 ? a.ksplit : 1);
+    if (f32) gemm_dispatch<float>(role, grid, a, s);
+    else gemm_dispatch<double>(role, grid, a, s);
     return hipGetLastError();
 }
 
@@ -240,23 +262,36 @@ struct Snh {
         }
     }
 };
-
 // ---------------------------------------------------------------------------
 // Element kernel: one workgroup per item, RP lanes per cubature tet (lane k
-// owns column k of K_e = dvecF/dz).  Per tet: F, psi, PK1, (d2psi/dF2) K_e[:,k],
-// H[:,k] += w V K_e^T (A K_e[:,k]), g[k] += w V K_e[:,k].P; then the penalty,
-// gravity and force rows.  Contributions are float64-accumulated and reduced
-// in a fixed order (deterministic).
+// owns column k of K_e = dvecF/dz).  The rows of EPR consecutive tets form one
+// contiguous span of the item's block; it is staged in LDS with 16-byte loads,
+// the next span prefetched into registers while the current one is used.
+// Per tet: F, psi, PK1, (d2psi/dF2) K_e[:,k], H[:,k] += w V K_e^T (A K_e[:,k]),
+// g[k] += w V K_e[:,k].P; then the penalty, gravity and force rows.
+// Contributions are float64-accumulated and reduced in a fixed order.
 // ---------------------------------------------------------------------------
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
+constexpr int kElemTile = 2880;  // max over RP of (tets per round) * 9 * (1 + r) values
+constexpr int kElemPrefetch = 6; // 16-byte vectors per thread per round (f64 worst case)
+
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 {
-    constexpr int EPW = 64 / RP;
-    __shared__ T Ks[4][EPW][9][RP];
+    constexpr int EPW = 64 / RP;   // tets per wave per round
+    constexpr int EPR = 4 * EPW;   // tets per round
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    __shared__ __align__(16) T tile[kElemTile];
+    __shared__ T Kp[4][EPW][3][RP];
     __shared__ double redH[4][RP][RP];
     __shared__ double redg[4][RP];
     __shared__ double redE[4];
     const int item = blockIdx.x;
+    if (a.count && item >= *a.count) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int eg = lane / RP, k = lane % RP;
     const int r = a.r, nc = a.nc;
@@ -270,20 +305,44 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 #pragma unroll
     for (int j = 0; j < RP; ++j) Hc[j] = 0.0;
     double gk = 0.0, Ee = 0.0;
-    const int per_round = 4 * EPW;
 
-    for (int s0 = 0; s0 < a.S; s0 += per_round) {
-        const int s = s0 + wave * EPW + eg;
-        const bool ok = s < a.S;
-        T gu[9], Kc[9];
+    const int span = 9 * nc;                 // values per tet
+    const int rounds = (a.S + EPR - 1) / EPR;
+    V pre[kElemPrefetch];
+    int npre = 0;
+    auto prefetch = [&](int rd) {
+        const int s0 = rd * EPR;
+        const int nt = min(EPR, a.S - s0);
+        const int nvec = (nt * span + VN - 1) / VN; // stays inside the item block (>= 4 spare rows)
+        const V* src = reinterpret_cast<const V*>(O + (size_t)s0 * span);
+        npre = 0;
 #pragma unroll
-        for (int v = 0; v < 9; ++v) {
-            gu[v] = ok ? O[(size_t)(9 * s + v) * nc] : T(0);
-            Kc[v] = (ok && kact) ? O[(size_t)(9 * s + v) * nc + 1 + k] : T(0);
-            Ks[wave][eg][v][k] = Kc[v];
+        for (int q = 0; q < kElemPrefetch; ++q) {
+            const int vi = tid + 256 * q;
+            if (vi < nvec) pre[q] = src[vi];
+        }
+        npre = nvec;
+    };
+    if (rounds > 0) prefetch(0);
+    for (int rd = 0; rd < rounds; ++rd) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kElemPrefetch; ++q) {
+            const int vi = tid + 256 * q;
+            if (vi < npre) reinterpret_cast<V*>(tile)[vi] = pre[q];
         }
         __syncthreads();
-        if (ok) {
+        if (rd + 1 < rounds) prefetch(rd + 1);
+        const int el = wave * EPW + eg;
+        const int s = rd * EPR + el;
+        if (s < a.S) {
+            const T* row = tile + el * span;
+            T gu[9], Kc[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                gu[v] = row[v * nc];
+                Kc[v] = kact ? row[v * nc + 1 + k] : T(0);
+            }
             Snh<T> m;
             m.set(gu, mu, lam);
             T P[9], AK[9];
@@ -295,7 +354,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 if (j < r) {
                     T h = 0;
 #pragma unroll
-                    for (int v = 0; v < 9; ++v) h += Ks[wave][eg][v][j] * AK[v];
+                    for (int v = 0; v < 9; ++v) h += row[v * nc + 1 + j] * AK[v];
                     Hc[j] += wV * (double)h;
                 }
             }
@@ -307,11 +366,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             if (dseed)
                 for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
         }
-        __syncthreads();
     }
 
     const bool ext = !a.elastic_only;
     const int prow = 9 * a.S;
+    const int per_round = 4 * EPW;
     if (ext && a.targets) {
         const double* tg = a.targets + (size_t)bidx * a.nt * 3;
         const double kc = a.k_c;
@@ -325,7 +384,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 const size_t row = (size_t)(prow + 3 * t + c);
                 Jc[c] = (ok && kact) ? O[row * nc + 1 + k] : T(0);
                 d[c] = ok ? a.Xt[3 * t + c] + (double)O[row * nc] - tg[3 * t + c] : 0.0;
-                Ks[wave][eg][c][k] = Jc[c];
+                Kp[wave][eg][c][k] = Jc[c];
             }
             __syncthreads();
             if (ok) {
@@ -334,7 +393,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                     if (j < r) {
                         T h = 0;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) h += Ks[wave][eg][c][j] * Jc[c];
+                        for (int c = 0; c < 3; ++c) h += Kp[wave][eg][c][j] * Jc[c];
                         Hc[j] += kc * (double)h;
                     }
                 }
@@ -403,6 +462,8 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     const int rp = a.r <= 4 ? 4 : a.r <= 8 ? 8 : a.r <= 16 ? 16 : 32;
+    // one round's tile must fit the staging buffer and the prefetch registers
+    if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
     dim3 grid(items), block(256);
 #define RS_ELEM(T, RP) hipLaunchKernelGGL((k_elem<T, RP>), grid, block, 0, s, a)
     if (f32) {
@@ -445,9 +506,9 @@ __global__ __launch_bounds__(256) void k_energy(EnergyArgs a)
 {
     __shared__ double sh[256];
     const int item = blockIdx.x, tid = threadIdx.x;
+    if (a.count && item >= *a.count) return;
     const double* O = static_cast<const double*>(a.out) + (size_t)item * a.rows_pad;
-    const int bi = item / a.imap_div;
-    const int bidx = a.imap ? a.imap[bi] : bi;
+    const int bidx = a.imap ? a.imap[item] : item;
     double acc = 0.0;
     for (int s = tid; s < a.S; s += 256) {
         double gu[9];
@@ -479,31 +540,36 @@ __global__ __launch_bounds__(256) void k_energy(EnergyArgs a)
     if (tid == 0) a.E[item] = tot;
 }
 
-hipError_t launch_energy(int f32, const EnergyArgs& a, int items, hipStream_t s)
+hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 {
-    if (f32) return hipErrorInvalidValue; // the line-search energy is always float64
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_energy, dim3(items), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Curvature kernel: reverse pass through the hidden layers (activations are
+// Curvature kernel: reverse pass through the hidden layers (activations from
 // the stored pre-activations) adding sum_l A_l^T diag(gbar_l s''(a_l)) A_l,
-// the second-order term of the exact reduced Hessian.
+// the second-order term of the exact reduced Hessian.  dE/dh_L is the sum of
+// the adjoint GEMM's K-slice partials, taken in slice order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 {
     extern __shared__ double smem[];
+    const int item = blockIdx.x, tid = threadIdx.x;
+    if (a.count && item >= *a.count) return;
     const int w = a.width, nc = a.nc, r = a.r;
     double* gh = smem;       // dE/dh_l
     double* ga = gh + w;     // dE/da_l
     double* cf = ga + w;     // dE/dh_l * s''(a_l), then scratch
     T* As = reinterpret_cast<T*>(cf + w); // 64 x nc block of [a | A]
-    const int item = blockIdx.x, tid = threadIdx.x;
-    const T* gbar = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows;
-    for (int u = tid; u < w; u += 256) gh[u] = (double)gbar[u];
+    for (int u = tid; u < w; u += 256) {
+        double s = 0.0;
+        for (int z = 0; z < a.ksplit; ++z)
+            s += (double)static_cast<const T*>(a.gbar)[z * a.split_stride + (size_t)item * a.pre_rows + u];
+        gh[u] = s;
+    }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int l = a.L - 1; l >= 0; --l) {
         const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
@@ -563,7 +629,10 @@ hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Newton control (float64)
+// Newton control (float64).  Each item is either in the evaluation phase
+// (ls_j < 0: needs g and H at z) or line-searching (ls_j >= 0).  One
+// super-step evaluates every item of the first kind and the next trial steps
+// of every item of the second kind; the lists are rebuilt on the device.
 // ---------------------------------------------------------------------------
 __global__ void k_newton_init(NewtonState st, int B)
 {
@@ -573,7 +642,7 @@ __global__ void k_newton_init(NewtonState st, int B)
     st.iters[b] = 0;
     st.g0[b] = 0.0;
     st.relgrad[b] = 0.0;
-    st.ls_j0[b] = 0;
+    st.ls_j[b] = -1;
 }
 
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s)
@@ -583,51 +652,104 @@ hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s)
     return hipGetLastError();
 }
 
-// Ordered list of the items still running (a block-wide prefix sum per 1024).
-__global__ __launch_bounds__(1024) void k_compact(NewtonState st, int B)
+// inclusive block-wide prefix sum over 1024 threads
+__device__ inline int block_scan1024(int v, int* sc)
+{
+    const int tid = threadIdx.x;
+    sc[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int x = tid >= off ? sc[tid - off] : 0;
+        __syncthreads();
+        sc[tid] += x;
+        __syncthreads();
+    }
+    const int out = sc[tid];
+    return out;
+}
+
+__global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B)
 {
     __shared__ int sc[1024];
     const int tid = threadIdx.x;
-    int base_out = 0;
-    for (int base = 0; base < B; base += 1024) {
-        const int b = base + tid;
-        const int flag = (b < B && st.status[b] == RS_RUNNING) ? 1 : 0;
-        sc[tid] = flag;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int v = tid >= off ? sc[tid - off] : 0;
-            __syncthreads();
-            sc[tid] += v;
-            __syncthreads();
-        }
-        if (flag) st.active[base_out + sc[tid] - 1] = b;
+    int base = 0;
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int b = b0 + tid;
+        const int f = (b < B && st.status[b] == RS_RUNNING && st.ls_j[b] < 0) ? 1 : 0;
+        const int inc = block_scan1024(f, sc);
+        if (f) st.eval_list[base + inc - 1] = b;
         const int tot = sc[1023];
         __syncthreads();
-        base_out += tot;
+        base += tot;
     }
-    if (tid == 0) st.counters[0] = base_out;
+    if (tid == 0) st.counters[0] = base;
 }
 
-hipError_t launch_compact(const NewtonState& st, int B, hipStream_t s)
+hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, st, B);
+    hipLaunchKernelGGL(k_compact_eval, dim3(1), dim3(1024), 0, s, st, B);
+    return hipGetLastError();
+}
+
+// Candidate list: an item on its first trial evaluates alpha = 1 only (the
+// Newton step is usually accepted); later rounds evaluate kLsCand steps.
+__global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonParams p, int B)
+{
+    __shared__ int sc[1024];
+    const int tid = threadIdx.x;
+    int base_s = 0, base_c = 0;
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int b = b0 + tid;
+        int f = 0, nc = 0, j = 0;
+        if (b < B && st.status[b] == RS_RUNNING && st.ls_j[b] >= 0) {
+            j = st.ls_j[b];
+            f = 1;
+            nc = min(j == 0 ? 1 : kLsCand, p.ls_max - j);
+        }
+        const int inc = block_scan1024((f << 16) | nc, sc);
+        const int ps = base_s + (inc >> 16) - 1, pc = base_c + (inc & 0xffff) - nc;
+        if (f) {
+            st.search_list[ps] = b;
+            st.search_start[ps] = pc;
+            st.search_ncand[ps] = nc;
+            for (int t = 0; t < nc; ++t) {
+                st.cand_item[pc + t] = b;
+                st.cand_j[pc + t] = j + t;
+            }
+        }
+        const int tot = sc[1023];
+        __syncthreads();
+        base_s += tot >> 16;
+        base_c += tot & 0xffff;
+    }
+    if (tid == 0) {
+        st.counters[1] = base_c;
+        st.counters[2] = base_s;
+    }
+}
+
+hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact_search, dim3(1), dim3(1024), 0, s, st, p, B);
     return hipGetLastError();
 }
 
 // Exit tests and the Newton direction of one item per 64-thread workgroup:
-// Cholesky of the symmetrised Hessian if it is positive definite, else cyclic
-// Jacobi eigen-decomposition and the projected (clamped / absolute)
-// eigenvalues.  All in float64.
+// Cholesky of the symmetrised Hessian if it is positive definite, else a
+// Jacobi eigen-decomposition (parallel ordering: the r/2 disjoint rotations
+// of one round-robin step are applied together) and the projected (clamped /
+// absolute) eigenvalues.  All in float64.
 __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams p)
 {
     __shared__ double Hs[kMaxR][kMaxR + 1];
     __shared__ double Ls[kMaxR][kMaxR + 1];
     __shared__ double Vs[kMaxR][kMaxR + 1];
     __shared__ double gs[kMaxR], dzs[kMaxR], cs[kMaxR], lam[kMaxR];
-    __shared__ int flag;
-    __shared__ double bc[4];
+    __shared__ double rc[kMaxR / 2], rs_[kMaxR / 2];
+    __shared__ int rp[kMaxR / 2], rq[kMaxR / 2];
     const int i = blockIdx.x, tid = threadIdx.x, r = p.r;
-    const int item = st.active[i];
+    if (i >= st.counters[0]) return;
+    const int item = st.eval_list[i];
     const double* gw = st.gw + (size_t)i * r;
     const double* Hw = st.Hw + (size_t)i * r * r;
     for (int q = tid; q < r; q += 64) gs[q] = gw[q];
@@ -638,109 +760,150 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
         Ls[a][b] = h;
     }
     __syncthreads();
-    if (tid == 0) {
+    {
+        // exit tests, all lanes in parallel (max and min are exact, so every
+        // lane ends with the same values; lane 0's are used anyway)
         double gn = 0.0;
-        int fin = isfinite(st.E[item]) ? 1 : 0;
-        for (int q = 0; q < r; ++q) {
+        int fin = 1;
+        for (int q = tid; q < r; q += 64) {
             gn = fmax(gn, fabs(gs[q]));
             if (!isfinite(gs[q])) fin = 0;
         }
-        for (int q = 0; q < r * r; ++q)
-            if (!isfinite(Hw[q])) fin = 0;
-        if (st.iters[item] == 0) st.g0[item] = gn;
-        const double g0 = st.g0[item];
-        st.gnorm[item] = gn;
-        st.relgrad[item] = g0 > 0.0 ? gn / g0 : 0.0;
+        for (int q = tid; q < r * r; q += 64)
+            if (!isfinite(Hs[q / r][q % r])) fin = 0;
+        for (int o = 32; o > 0; o >>= 1) {
+            gn = fmax(gn, __shfl_xor(gn, o));
+            fin = min(fin, __shfl_xor(fin, o));
+        }
+        gn = __shfl(gn, 0);
+        fin = __shfl(fin, 0) && isfinite(st.E[item]);
+        const int it = st.iters[item];
+        const double g0 = (it == 0) ? gn : st.g0[item];
         int status = RS_RUNNING;
         if (!fin) status = RS_NONFINITE;
         else if (gn <= p.abs_tol || gn <= p.rel_tol * g0) status = RS_CONVERGED;
-        else if (st.iters[item] >= p.max_iter) status = RS_ITER_MAX;
-        if (status != RS_RUNNING) st.status[item] = status;
-        flag = (status == RS_RUNNING) ? 0 : -1;
+        else if (it >= p.max_iter) status = RS_ITER_MAX;
+        if (tid == 0) {
+            if (it == 0) st.g0[item] = gn;
+            st.relgrad[item] = g0 > 0.0 ? gn / g0 : 0.0;
+            if (status != RS_RUNNING) st.status[item] = status;
+        }
+        if (status != RS_RUNNING) return;
     }
-    __syncthreads();
-    if (flag < 0) return;
 
-    // Cholesky, column by column
+    // right-looking Cholesky of the symmetrised Hessian (lower factor in Ls)
+    int chol_ok = 1;
     for (int j = 0; j < r; ++j) {
-        if (tid == 0) {
-            double d = Ls[j][j];
-            for (int k = 0; k < j; ++k) d -= Ls[j][k] * Ls[j][k];
-            if (!(d > 0.0) || !isfinite(d)) flag = 1;
-            else Ls[j][j] = sqrt(d);
-        }
+        const double d = Ls[j][j];
         __syncthreads();
-        if (flag) break;
-        for (int a = j + 1 + tid; a < r; a += 64) {
-            double s = Ls[a][j];
-            for (int k = 0; k < j; ++k) s -= Ls[a][k] * Ls[j][k];
-            Ls[a][j] = s / Ls[j][j];
+        if (!(d > 0.0) || !isfinite(d)) {
+            chol_ok = 0;
+            break;
+        }
+        const double ljj = sqrt(d);
+        if (tid == 0) Ls[j][j] = ljj;
+        for (int a = j + 1 + tid; a < r; a += 64) Ls[a][j] /= ljj;
+        __syncthreads();
+        const int m = r - j - 1;
+        for (int w = tid; w < m * m; w += 64) {
+            const int a = j + 1 + w / m, b = j + 1 + w % m;
+            if (b <= a) Ls[a][b] -= Ls[a][j] * Ls[b][j];
         }
         __syncthreads();
     }
-    if (!flag) {
-        if (tid == 0) {
-            for (int a = 0; a < r; ++a) {
-                double s = -gs[a];
-                for (int k = 0; k < a; ++k) s -= Ls[a][k] * cs[k];
-                cs[a] = s / Ls[a][a];
-            }
-            for (int a = r - 1; a >= 0; --a) {
-                double s = cs[a];
-                for (int k = a + 1; k < r; ++k) s -= Ls[k][a] * dzs[k];
-                dzs[a] = s / Ls[a][a];
-            }
-        }
+    if (chol_ok) {
+        // L y = -g, then L^T dz = y, one column per step
+        for (int q = tid; q < r; q += 64) cs[q] = -gs[q];
         __syncthreads();
+        for (int j = 0; j < r; ++j) {
+            const double yj = cs[j] / Ls[j][j];
+            __syncthreads();
+            if (tid == 0) cs[j] = yj;
+            for (int a = j + 1 + tid; a < r; a += 64) cs[a] -= Ls[a][j] * yj;
+            __syncthreads();
+        }
+        for (int j = r - 1; j >= 0; --j) {
+            const double dj = cs[j] / Ls[j][j];
+            __syncthreads();
+            if (tid == 0) dzs[j] = dj;
+            for (int a = tid; a < j; a += 64) cs[a] -= Ls[j][a] * dj;
+            __syncthreads();
+        }
     } else if (p.proj == RS_PROJ_NONE) {
         if (tid == 0) st.status[item] = RS_NOT_DESCENT;
         return;
     } else {
-        // cyclic Jacobi on Hs (overwritten), eigenvectors in Vs
         for (int q = tid; q < r * r; q += 64) {
             const int a = q / r, b = q - a * r;
             Vs[a][b] = (a == b) ? 1.0 : 0.0;
         }
-        __syncthreads();
-        for (int sweep = 0; sweep < 100; ++sweep) {
-            if (tid == 0) {
-                double off = 0.0, tot = 0.0;
-                for (int a = 0; a < r; ++a)
-                    for (int b = 0; b < r; ++b) {
-                        const double h2 = Hs[a][b] * Hs[a][b];
-                        tot += h2;
-                        if (a != b) off += h2;
-                    }
-                bc[0] = (off <= 1e-30 * tot || off == 0.0) ? 1.0 : 0.0;
-            }
+        const int n2 = (r + 1) & ~1; // players of the round-robin (one dummy if r is odd)
+        const int P = n2 / 2;
+        for (int sweep = 0; sweep < 40; ++sweep) {
             __syncthreads();
-            if (bc[0] != 0.0) break;
-            for (int pp = 0; pp < r - 1; ++pp)
-                for (int qq = pp + 1; qq < r; ++qq) {
-                    const double apq = Hs[pp][qq];
-                    const double app = Hs[pp][pp], aqq = Hs[qq][qq];
-                    __syncthreads();
-                    if (apq == 0.0) continue;
-                    const double theta = (aqq - app) / (2.0 * apq);
-                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                    const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
-                    if (tid < r) {
-                        const double akp = Hs[tid][pp], akq = Hs[tid][qq];
-                        Hs[tid][pp] = c * akp - sn * akq;
-                        Hs[tid][qq] = sn * akp + c * akq;
+            double off = 0.0, tot = 0.0;
+            for (int q = tid; q < r * r; q += 64) {
+                const int a = q / r, b = q - a * r;
+                const double h2 = Hs[a][b] * Hs[a][b];
+                tot += h2;
+                if (a != b) off += h2;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                off += __shfl_xor(off, o);
+                tot += __shfl_xor(tot, o);
+            }
+            // lane 0 decides for the whole wave (barriers follow)
+            off = __shfl(off, 0);
+            tot = __shfl(tot, 0);
+            if (off <= 1e-30 * tot || off == 0.0) break;
+            for (int step = 0; step < n2 - 1; ++step) {
+                if (tid < P) {
+                    const int m1 = tid, m2 = n2 - 1 - tid;
+                    const int a = m1 == 0 ? 0 : ((m1 - 1 + step) % (n2 - 1)) + 1;
+                    const int b = ((m2 - 1 + step) % (n2 - 1)) + 1;
+                    const int pp = a < b ? a : b, qq = a < b ? b : a;
+                    double c = 1.0, sn = 0.0;
+                    if (qq < r) {
+                        const double apq = Hs[pp][qq];
+                        if (apq != 0.0) {
+                            const double theta = (Hs[qq][qq] - Hs[pp][pp]) / (2.0 * apq);
+                            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                            c = 1.0 / sqrt(t * t + 1.0);
+                            sn = t * c;
+                        }
                     }
-                    __syncthreads();
-                    if (tid < r) {
-                        const double apk = Hs[pp][tid], aqk = Hs[qq][tid];
-                        Hs[pp][tid] = c * apk - sn * aqk;
-                        Hs[qq][tid] = sn * apk + c * aqk;
-                        const double vkp = Vs[tid][pp], vkq = Vs[tid][qq];
-                        Vs[tid][pp] = c * vkp - sn * vkq;
-                        Vs[tid][qq] = sn * vkp + c * vkq;
-                    }
-                    __syncthreads();
+                    rp[tid] = pp;
+                    rq[tid] = qq;
+                    rc[tid] = c;
+                    rs_[tid] = sn;
                 }
+                __syncthreads();
+                for (int w = tid; w < P * r; w += 64) { // rows p, q
+                    const int pr = w / r, col = w - pr * r;
+                    const int pp = rp[pr], qq = rq[pr];
+                    if (qq >= r) continue;
+                    const double c = rc[pr], sn = rs_[pr];
+                    const double apk = Hs[pp][col], aqk = Hs[qq][col];
+                    Hs[pp][col] = c * apk - sn * aqk;
+                    Hs[qq][col] = sn * apk + c * aqk;
+                }
+                __syncthreads();
+                for (int w = tid; w < P * r; w += 64) { // columns p, q and eigenvectors
+                    const int pr = w / r, row = w - pr * r;
+                    const int pp = rp[pr], qq = rq[pr];
+                    if (qq >= r) continue;
+                    const double c = rc[pr], sn = rs_[pr];
+                    const double akp = Hs[row][pp], akq = Hs[row][qq];
+                    Hs[row][pp] = c * akp - sn * akq;
+                    Hs[row][qq] = sn * akp + c * akq;
+                    const double vkp = Vs[row][pp], vkq = Vs[row][qq];
+                    Vs[row][pp] = c * vkp - sn * vkq;
+                    Vs[row][qq] = sn * vkp + c * vkq;
+                }
+                __syncthreads();
+            }
         }
+        __syncthreads();
         if (tid == 0) {
             double lmax = 0.0;
             for (int k = 0; k < r; ++k) lmax = fmax(lmax, fabs(Hs[k][k]));
@@ -771,22 +934,24 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
         for (int a = 0; a < r; ++a) slope += gs[a] * dzs[a];
         if (!(slope < 0.0)) {
             st.status[item] = RS_NOT_DESCENT;
+        } else if (p.ls_max <= 0) {
+            st.status[item] = RS_LS_MAX;
         } else {
             st.slope[item] = slope;
-            st.ls_j0[item] = 0;
+            st.ls_j[item] = 0;
         }
     }
     for (int a = tid; a < r; a += 64) st.dz[(size_t)item * r + a] = dzs[a];
 }
 
-hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
-    if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_dir, dim3(n_act), dim3(64), 0, s, st, p);
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_dir, dim3(cap), dim3(64), 0, s, st, p);
     return hipGetLastError();
 }
 
-// alpha_j = shrink^j by repeated multiplication (j = ls_j0 + t)
+// alpha_j = shrink^j by repeated multiplication
 __device__ inline double step_len(double shrink, int j)
 {
     double a = 1.0;
@@ -794,64 +959,73 @@ __device__ inline double step_len(double shrink, int j)
     return a;
 }
 
-__global__ void k_ls_candidates(NewtonState st, NewtonParams p, int n_act)
+__global__ void k_ls_candidates(NewtonState st, NewtonParams p)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx == 0) st.counters[1] = 0;
-    if (idx >= n_act * kLsCand) return;
-    const int i = idx / kLsCand, t = idx - i * kLsCand;
-    const int item = st.active[i];
-    const double alpha = step_len(p.shrink, st.ls_j0[item] + t);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= st.counters[1]) return;
+    const int item = st.cand_item[c];
+    const double alpha = step_len(p.shrink, st.cand_j[c]);
     for (int k = 0; k < p.r; ++k)
-        st.zc[(size_t)idx * p.r + k] = st.z[(size_t)item * p.r + k] + alpha * st.dz[(size_t)item * p.r + k];
+        st.zc[(size_t)c * p.r + k] = st.z[(size_t)item * p.r + k] + alpha * st.dz[(size_t)item * p.r + k];
 }
 
-hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
-    const int n = n_act * kLsCand;
-    hipLaunchKernelGGL(k_ls_candidates, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, s,
-                       st, p, n_act);
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ls_candidates, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
     return hipGetLastError();
 }
 
 // Armijo test on the float64 candidate energies: accept the first (largest)
 // step with E(z + a dz) - E(z) <= c1 a g.dz, as sequential backtracking would.
-__global__ void k_armijo(NewtonState st, NewtonParams p, int n_act)
+__global__ void k_armijo(NewtonState st, NewtonParams p)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_act) return;
-    const int item = st.active[i];
-    // items that are done, or that accepted a step in an earlier round
-    if (st.status[item] != RS_RUNNING || st.ls_j0[item] < 0) return;
+    if (i >= st.counters[2]) return;
+    const int item = st.search_list[i];
+    const int start = st.search_start[i], nc = st.search_ncand[i];
     const double E0 = st.E[item], slope = st.slope[item];
-    const int j0 = st.ls_j0[item];
-    for (int t = 0; t < kLsCand; ++t) {
-        const int j = j0 + t;
-        if (j >= p.ls_max) break;
-        const double alpha = step_len(p.shrink, j);
-        const double Et = st.Ec[(size_t)i * kLsCand + t];
+    const int j0 = st.ls_j[item];
+    for (int t = 0; t < nc; ++t) {
+        const double alpha = step_len(p.shrink, j0 + t);
+        const double Et = st.Ec[start + t];
         if (isfinite(Et) && Et - E0 <= p.c1 * alpha * slope) {
-            for (int k = 0; k < p.r; ++k)
-                st.z[(size_t)item * p.r + k] = st.zc[((size_t)i * kLsCand + t) * p.r + k];
+            for (int k = 0; k < p.r; ++k) st.z[(size_t)item * p.r + k] = st.zc[(size_t)(start + t) * p.r + k];
             st.E[item] = Et;
             st.iters[item] += 1;
-            st.ls_j0[item] = -1;
+            st.ls_j[item] = -1;
             return;
         }
     }
-    const int jn = j0 + kLsCand;
-    if (jn >= p.ls_max) {
-        st.status[item] = RS_LS_MAX;
-    } else {
-        st.ls_j0[item] = jn;
-        atomicAdd(&st.counters[1], 1);
-    }
+    const int jn = j0 + nc;
+    if (jn >= p.ls_max) st.status[item] = RS_LS_MAX;
+    else st.ls_j[item] = jn;
 }
 
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int n_act, hipStream_t s)
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
-    if (n_act <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_armijo, dim3((n_act + 255) / 256), dim3(256), 0, s, st, p, n_act);
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_armijo, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B)
+{
+    __shared__ int sc[1024];
+    int n = 0;
+    for (int b = threadIdx.x; b < B; b += 1024) n += st.status[b] == RS_RUNNING ? 1 : 0;
+    sc[threadIdx.x] = n;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st.counters[3] = sc[0];
+}
+
+hipError_t launch_count_running(const NewtonState& st, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_running, dim3(1), dim3(1024), 0, s, st, B);
     return hipGetLastError();
 }
 
