@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -83,13 +85,30 @@ def main():
         lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False)
         return res, lip
 
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    dominant = None
     if not args.no_profile:
+        # a profiled pass picks the dominant kernel kind; the timed region then
+        # brackets only that kind with HIP events (one event pair per launch)
         ctx.profile(True)
+        step()
+        ctx.profile(False)
+        warm = ctx.profile_read()
+        dominant = max(warm.items(), key=lambda kv: kv[1]["ms"])[0]
+        ctx.profile(True, kinds=[dominant])
     conv = 0
     iters = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         res, lip = step()
@@ -119,7 +138,7 @@ def main():
             roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": kind,
                     "avg_us": avg_s * 1e6, "launches": rec["launches"]}
-        roof["kernels"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in prof.items()}
+        roof["kernels_warm_pass"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in warm.items()}
 
     cpu = None
     if args.cpu_sample > 0:

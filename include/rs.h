@@ -214,12 +214,14 @@ int rs_lipschitz_loss(rs_ctx* ctx, int32_t B, const double* z1, const double* z2
  * when ctx is NULL. */
 const char* rs_last_error(const rs_ctx* ctx);
 
-/* Kernel timing.  rs_profile(ctx, 1) clears previous records and brackets
- * every later kernel launch with HIP events on its stream; rs_profile(ctx, 0)
- * stops recording.  rs_profile_get() synchronises the recorded events and
- * returns, for kernel kind idx < *n_kinds, its name, launch count, summed
- * duration and the summed algorithmic HBM bytes and flops of those launches. */
-int rs_profile(rs_ctx* ctx, int32_t enable);
+/* Kernel timing.  rs_profile(ctx, 1, mask) clears previous records and
+ * brackets every later launch of the kernel kinds in `mask` (bit k = kind k,
+ * 0 = every kind) with HIP events on its stream; rs_profile(ctx, 0, 0) stops
+ * recording.  rs_profile_get() synchronises the device and returns, for kernel
+ * kind idx < *n_kinds, its name, launch count, summed duration and the summed
+ * algorithmic HBM bytes and flops of those launches (idx < 0 only sets
+ * *n_kinds). */
+int rs_profile(rs_ctx* ctx, int32_t enable, uint32_t kind_mask);
 int rs_profile_get(rs_ctx* ctx, int32_t idx, int32_t* n_kinds, char* name, int32_t name_len,
                    int32_t* launches, double* total_ms, double* bytes, double* flops);
 

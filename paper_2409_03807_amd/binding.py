@@ -100,7 +100,7 @@ def load_library():
                                       C.c_void_p, C.c_void_p]
         L.rs_lipschitz_loss.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.rs_profile.argtypes = [C.c_void_p, C.c_int32]
+        L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
         L.rs_default_opts.argtypes = [C.POINTER(SolveOpts)]
@@ -271,8 +271,26 @@ class Context:
         return dict(loss=loss, per_pair=per, n_valid=nval, lip_max=lmax)
 
     # -- kernel timing ------------------------------------------------------
-    def profile(self, enable: bool):
-        self._check(load_library().rs_profile(self.ctx, int(enable)), "rs_profile")
+    def kind_names(self):
+        L = load_library()
+        n = C.c_int32()
+        self._check(L.rs_profile_get(self.ctx, -1, C.byref(n), None, 0, None, None, None, None), "rs_profile_get")
+        name = C.create_string_buffer(64)
+        out = []
+        for i in range(n.value):
+            self._check(L.rs_profile_get(self.ctx, i, C.byref(n), name, 64, None, None, None, None),
+                        "rs_profile_get")
+            out.append(name.value.decode())
+        return out
+
+    def profile(self, enable: bool, kinds=None):
+        """Bracket launches with HIP events; `kinds` (names) limits which."""
+        mask = 0
+        if kinds:
+            names = self.kind_names()
+            for k in kinds:
+                mask |= 1 << names.index(k)
+        self._check(load_library().rs_profile(self.ctx, int(enable), mask), "rs_profile")
 
     def profile_read(self):
         L = load_library()

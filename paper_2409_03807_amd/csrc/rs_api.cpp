@@ -32,12 +32,12 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR, K_LS_CAND,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_COUNT
+    K_INIT, K_ACTIVATE, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir", "ls_candidates",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
-    "newton_init"};
+    "newton_init", "activate"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -83,6 +83,8 @@ struct rs_ctx {
     double* wV = nullptr; double* Xt = nullptr;
     // workspace
     std::vector<void*> pre;       // L x (max_batch x wrows x nc) T
+    void* act = nullptr;          // max_batch x wrows x nc T: [h_L | J_L] of the last hidden layer
+    double* act64 = nullptr;      // kLsCand*max_batch x wrows: h_L for the line search
     void* out = nullptr;          // max_batch x Mp x nc T
     void* dseed = nullptr;        // max_batch x Mp T
     void* gbar = nullptr;         // max_batch x in_rows T
@@ -104,6 +106,7 @@ struct rs_ctx {
     std::string err;
     // profiling
     bool prof = false;
+    uint32_t prof_mask = 0;       // kinds recorded (0 = all)
     std::vector<hipEvent_t> evpool;
     size_t evnext = 0;
     std::vector<ProfRec> recs;
@@ -146,25 +149,31 @@ static void* dalloc_bytes(rs_ctx* c, size_t bytes)
     return p;
 }
 
-// Launch bracket: records HIP events around the launch when profiling.
+// Launch bracket: when profiling this kind, the next kernel launch records a
+// pair of timing events as part of its own dispatch.
 template <class F>
 static int run(rs_ctx* c, int kind, const Work& w, hipStream_t s, F&& f)
 {
     int e0 = -1, e1 = -1;
-    if (c->prof) {
+    const bool rec = c->prof && (c->prof_mask == 0 || (c->prof_mask >> kind) & 1u);
+    if (rec) {
         while (c->evpool.size() < c->evnext + 2) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventCreate");
+            // timing-only events: no system-scope fence
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+                return fail(c, RS_ERR_HIP, "hipEventCreate");
             c->evpool.push_back(e);
         }
-        e0 = (int)c->evnext++;
-        e1 = (int)c->evnext++;
-        if (hipEventRecord(c->evpool[e0], s) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventRecord");
+        e0 = (int)c->evnext;
+        e1 = (int)c->evnext + 1;
+        set_launch_events(c->evpool[e0], c->evpool[e1]);
     }
     hipError_t e = f();
+    const bool launched = rec && !launch_events_pending();
+    set_launch_events(nullptr, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, kKindName[kind]);
-    if (c->prof) {
-        if (hipEventRecord(c->evpool[e1], s) != hipSuccess) return fail(c, RS_ERR_HIP, "hipEventRecord");
+    if (launched) {
+        c->evnext += 2;
         c->recs.push_back(ProfRec{kind, w.b0, w.b1, w.f0, w.f1, w.slot, w.which, e0, e1});
         c->aggregated = false;
     }
@@ -487,6 +496,8 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->wV = (double*)need(dalloc<double>(c, c->S));
     c->Xt = (double*)need(dalloc<double>(c, 3 * (size_t)std::max(c->nt, 1)));
     c->out = need(dalloc_bytes(c, B * c->Mp * nc * ts));
+    c->act = need(dalloc_bytes(c, B * c->wrows * nc * ts));
+    c->act64 = (double*)need(dalloc<double>(c, BL * c->wrows));
     c->dseed = need(dalloc_bytes(c, B * c->Mp * ts));
     c->ksplit = std::max(1, std::min(kMaxSplit, c->Mp / 160));
     c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
@@ -592,6 +603,16 @@ static Work item_work(double per_b, double per_f, int items, const int* count, i
     return w;
 }
 
+// [h_L | J_L] of the last hidden layer, computed once for the output map
+static int activate(rs_ctx* c, int f32, const void* pre, void* act, int nc, int cap, const int* count, int which,
+                    hipStream_t s)
+{
+    const size_t ts = f32 ? 4 : 8;
+    const double pb = 2.0 * ts * (double)c->w * nc;
+    return run(c, K_ACTIVATE, item_work(pb, 3.0 * c->w * nc, cap, count, c->cur_slot, which), s,
+               [&] { return launch_activate(f32, pre, act, c->w, c->wrows, nc, cap, count, s); });
+}
+
 // T-precision decoder value + Jacobian, reduced rows, element terms and (exact)
 // the curvature term.  `cap` items fit the launch; `count` (device, nullable)
 // holds the actual number.  Item i uses latent point z[zmap[i]] and the loads
@@ -626,6 +647,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         RS_TRY(run(c, K_GEMM_HIDDEN, gemm_work(ts, a.rows, a.K, cap, nc, count, slot, 0), s,
                    [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
     }
+    if (c->L > 0) RS_TRY(activate(c, f32, c->pre[c->L - 1], c->act, nc, cap, count, 0, s));
     {
         GemmArgs a{};
         a.A = c->Wbig;
@@ -636,8 +658,8 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.nc = nc;
         a.items = cap;
         a.count = count;
-        a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
-        a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+        a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+        a.Y = c->L > 0 ? c->act : nullptr;
         a.y_rows = c->wrows;
         a.z = z;
         a.zmap = zmap;
@@ -753,6 +775,7 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
         RS_TRY(run(c, kind_hidden, gemm_work(8, a.rows, a.K, cap, 1, count, slot, which), s,
                    [&] { return launch_gemm(0, ROLE_HIDDEN, a, s); }));
     }
+    if (c->L > 0) RS_TRY(activate(c, 0, c->pre64[c->L - 1], c->act64, 1, cap, count, which, s));
     {
         GemmArgs a{};
         a.A = c->Wbig64;
@@ -763,8 +786,8 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
         a.nc = 1;
         a.items = cap;
         a.count = count;
-        a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
-        a.Y = c->L > 0 ? c->pre64[c->L - 1] : nullptr;
+        a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+        a.Y = c->L > 0 ? c->act64 : nullptr;
         a.y_rows = c->wrows;
         a.z = z;
         a.r = r;
@@ -856,6 +879,7 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
         RS_TRY(run(c, K_DECODE_HIDDEN, gemm_work(ts, a.rows, a.K, B, nc, nullptr, -1, 0), s,
                    [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
     }
+    if (c->L > 0) RS_TRY(activate(c, f32, c->pre[c->L - 1], c->act, nc, B, nullptr, 0, s));
     GemmArgs a{};
     a.A = c->Wfull;
     a.lda = c->lda_out;
@@ -864,8 +888,8 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.K = c->in_last;
     a.nc = nc;
     a.items = B;
-    a.in_mode = c->L > 0 ? IN_ELU : IN_LATENT;
-    a.Y = c->L > 0 ? c->pre[c->L - 1] : nullptr;
+    a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+    a.Y = c->L > 0 ? c->act : nullptr;
     a.y_rows = c->wrows;
     a.z = z;
     a.r = r;
@@ -900,14 +924,6 @@ static int log_counters(rs_ctx* c, hipStream_t s)
     }
     c->cur_slot = c->plog_next++;
     return RS_OK;
-}
-
-static int log_commit(rs_ctx* c, hipStream_t s)
-{
-    if (!c->prof || c->cur_slot < 0) return RS_OK;
-    hipError_t e = hipMemcpyAsync(c->plog + 4 * (size_t)c->cur_slot, c->counters, 4 * sizeof(int),
-                                  hipMemcpyDeviceToDevice, s);
-    return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpyAsync");
 }
 
 static int read_counter(rs_ctx* c, int idx, hipStream_t s, int* out)
@@ -987,8 +1003,8 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
         RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw, c->Hw, s));
         RS_TRY(run(c, K_DIR, item_work(8.0 * (r + r * r), (double)r * r * r, n_run, cnt + 0, c->cur_slot, 0), s,
                    [&] { return launch_newton_dir(st, p, n_run, s); }));
+        st.plog = c->cur_slot >= 0 ? c->plog + 4 * (size_t)c->cur_slot : nullptr;
         RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_search(st, p, B, s); }));
-        RS_TRY(log_commit(c, s));
         const int cap_c = n_run * kLsCand;
         RS_TRY(run(c, K_LS_CAND, item_work(16.0 * r, 2.0 * r, cap_c, cnt + 1, c->cur_slot, 1), s,
                    [&] { return launch_ls_candidates(st, p, cap_c, s); }));
@@ -1054,7 +1070,7 @@ extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const d
 }
 
 // ------------------------------------------------------------------ profiling
-extern "C" int rs_profile(rs_ctx* c, int32_t enable)
+extern "C" int rs_profile(rs_ctx* c, int32_t enable, uint32_t kind_mask)
 {
     if (!c) return RS_ERR_STATE;
     if (enable) {
@@ -1070,6 +1086,7 @@ extern "C" int rs_profile(rs_ctx* c, int32_t enable)
         c->aggregated = true;
     }
     c->prof = enable != 0;
+    c->prof_mask = kind_mask;
     return RS_OK;
 }
 

@@ -13,7 +13,7 @@ namespace rs {
 
 constexpr int kTileM = 64;   // GEMM rows per workgroup
 constexpr int kTileN = 64;   // GEMM columns per workgroup
-constexpr int kTileK = 16;   // GEMM reduction chunk
+constexpr int kTileK = 32;   // GEMM reduction chunk (also the padding of every lda)
 constexpr int kMaxR = 32;    // largest latent dimension
 constexpr int kLsCand = 8;   // step lengths evaluated per line-search round after the first
 constexpr int kMaxL = 8;     // largest number of hidden layers
@@ -128,6 +128,7 @@ struct NewtonState {
     const double* Hw; // eval-list order: H (n_eval x r x r)
     double* zc;       // candidates x r
     const double* Ec; // candidate energies
+    int* plog;        // profiling only: this super-step's counters [0..2] are copied here (may be NULL)
 };
 
 struct NewtonParams {
@@ -136,7 +137,12 @@ struct NewtonParams {
 };
 
 // ----------------------------------------------------------------- launchers
+// arm timing events for the next kernel launch (recorded by the dispatch)
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
 hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s);
+hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
+                           const int* count, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);

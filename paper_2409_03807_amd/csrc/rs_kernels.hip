@@ -10,7 +10,30 @@
 
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 namespace rs {
+
+// Launch events armed by the profiler for the next launch only: the events
+// are recorded by the dispatch itself (no marker packets between kernels).
+static thread_local hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
+void set_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    g_launch_ev[0] = start;
+    g_launch_ev[1] = stop;
+}
+bool launch_events_pending() { return g_launch_ev[0] != nullptr; }
+
+#define RS_LAUNCH(kernel, grid, block, shm, stream, ...)                                          \
+    do {                                                                                         \
+        if (g_launch_ev[0]) {                                                                    \
+            hipEvent_t e0_ = g_launch_ev[0], e1_ = g_launch_ev[1];                               \
+            g_launch_ev[0] = g_launch_ev[1] = nullptr;                                           \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, e0_, e1_, 0, __VA_ARGS__);   \
+        } else {                                                                                 \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                   \
+        }                                                                                        \
+    } while (0)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -36,6 +59,10 @@ template <> struct Mfma<double> {
     __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+
 // ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
 __device__ inline float elu0(float a) { return a > 0.f ? a : expm1f(a); }
 __device__ inline double elu0(double a) { return a > 0.0 ? a : expm1(a); }
@@ -52,19 +79,30 @@ __device__ inline double elu2(double a) { return a > 0.0 ? 0.0 : exp(a); }
 template <typename T, int ROLE>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 {
-    __shared__ T As[kTileK][kTileM + 1];
-    __shared__ T Ys[kTileK][kTileN];
+    static_assert(kTileK == 32, "tile loads assume 32-deep chunks");
+    // An MFMA sums over k, so any order of k works if A and B agree: lane
+    // group g = lane/16 takes k in [8g, 8g+8) of each chunk, which lets every
+    // lane read its 8 A values and 8 B values per tile with 16-byte LDS loads.
+    // Rows are padded by 16 bytes so 8 consecutive rows hit distinct banks.
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int LD = kTileK + VN;
+    __shared__ __align__(16) T As[kTileM * LD];
+    __shared__ __align__(16) T Ys[kTileN * LD];
+    // column counts stay far below 2^31 (items * nc), so 32-bit index math
     const int items = a.count ? min(*a.count, a.items) : a.items;
-    const long ncols = (long)items * a.nc;
-    const long n0 = (long)blockIdx.y * kTileN;
+    const int ncols = items * a.nc;
+    const int n0 = blockIdx.y * kTileN;
     if (n0 >= ncols) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
     const int m0 = blockIdx.x * kTileM;
     const T* A = static_cast<const T*>(a.A);
     using acc_t = typename Mfma<T>::acc_t;
     acc_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    const unsigned ncu = (unsigned)a.nc;
 
     int kbeg = 0, kend = a.K;
     T* Cout = static_cast<T*>(a.C);
@@ -75,34 +113,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
         Cout += blockIdx.z * a.split_stride;
     }
 
-    const int arow = tid >> 2, akq = (tid & 3) * 4;
-    const int ynn = tid & 63, ykb = (tid >> 6) * 4;
-    const long yn = n0 + ynn;
-    long yitem = 0;
-    int yc = 0;
-    if (yn < ncols) {
-        yitem = yn / a.nc;
-        yc = (int)(yn - yitem * a.nc);
+    // global -> registers: 8 consecutive k of one A row / one Y column per thread
+    const int arow = tid >> 2, akq = (tid & 3) * 8;
+    const int ynn = tid & 63, ykb = (tid >> 6) * 8;
+    const int yn = n0 + ynn;
+    const bool ycol = yn < ncols;
+    int yitem = 0, yc = 0;
+    if (ycol) {
+        yitem = (int)((unsigned)yn / ncu);
+        yc = yn - yitem * a.nc;
     }
     long zrow = 0;
-    if (a.in_mode == IN_LATENT && yn < ncols) zrow = a.zmap ? a.zmap[yitem] : yitem;
+    if (a.in_mode == IN_LATENT && ycol) zrow = a.zmap ? a.zmap[yitem] : yitem;
+    const T* Ycol = (a.in_mode != IN_LATENT && ycol)
+                        ? static_cast<const T*>(a.Y) + (size_t)yitem * a.y_rows * a.nc : nullptr;
 
-    for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
-        {
-            const T* src = A + (size_t)(m0 + arow) * a.lda + k0 + akq;
+    V ra[8 / VN];
+    T ry[8];
+    auto load = [&](int k0) {
+        const V* src = reinterpret_cast<const V*>(A + (size_t)(m0 + arow) * a.lda + k0 + akq);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) As[akq + q][arow] = src[q];
-        }
+        for (int q = 0; q < 8 / VN; ++q) ra[q] = src[q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             const int k = k0 + ykb + q;
             T v = T(0);
-            if (yn < ncols && k < kend) {
+            if (ycol && k < kend) {
                 if (a.in_mode == IN_LATENT) {
                     if (yc == 0) v = (T)a.z[zrow * a.r + k];
                     else v = (k == yc - 1) ? T(1) : T(0);
                 } else {
-                    const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * a.y_rows + k) * a.nc;
+                    const T* Yb = Ycol + (size_t)k * a.nc;
                     if (a.in_mode == IN_ELU) {
                         const T av = Yb[0];
                         v = (yc == 0) ? elu0(av) : T(elu1(av)) * Yb[yc];
@@ -111,28 +152,64 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
                     }
                 }
             }
-            Ys[ykb + q][ynn] = v;
+            ry[q] = v;
         }
-        __syncthreads();
+    };
+
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
+        {
+            V* da = reinterpret_cast<V*>(As + arow * LD + akq);
 #pragma unroll
-        for (int kk = 0; kk < kTileK / 4; ++kk) {
-            const T av = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+            for (int q = 0; q < 8 / VN; ++q) da[q] = ra[q];
+            V* dy = reinterpret_cast<V*>(Ys + ynn * LD + ykb);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const T bv = Ys[kk * 4 + (lane >> 4)][t * 16 + (lane & 15)];
-                acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+            for (int q = 0; q < 8 / VN; ++q) {
+                V w;
+                T* wp = reinterpret_cast<T*>(&w);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+                dy[q] = w;
             }
         }
+        __syncthreads();
+        if (k0 + kTileK < kend) load(k0 + kTileK);
+        T af[8], bf[4][8];
+        {
+            const V* sa = reinterpret_cast<const V*>(As + (wave * 16 + li) * LD + 8 * lg);
+#pragma unroll
+            for (int q = 0; q < 8 / VN; ++q) {
+                const V w = sa[q];
+                const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) af[q * VN + e] = wp[e];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LD + 8 * lg);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const V w = sb[q];
+                    const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[kk], bf[t][kk], acc[t]);
         __syncthreads();
     }
 
     const T* bias = (a.ksplit > 1 && blockIdx.z > 0) ? nullptr : static_cast<const T*>(a.bias);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const long n = n0 + t * 16 + (lane & 15);
+        const int n = n0 + t * 16 + li;
         if (n >= ncols) continue;
-        const long item = n / a.nc;
-        const int c = (int)(n - item * a.nc);
+        const int item = (int)((unsigned)n / ncu);
+        const int c = n - item * a.nc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int m = m0 + wave * 16 + Mfma<T>::row(lane, v);
@@ -154,10 +231,10 @@ template <typename T>
 static void gemm_dispatch(int role, dim3 grid, const GemmArgs& a, hipStream_t s)
 {
     switch (role) {
-    case ROLE_HIDDEN: hipLaunchKernelGGL((k_gemm<T, ROLE_HIDDEN>), grid, dim3(256), 0, s, a); break;
-    case ROLE_OUT: hipLaunchKernelGGL((k_gemm<T, ROLE_OUT>), grid, dim3(256), 0, s, a); break;
-    case ROLE_ADJ: hipLaunchKernelGGL((k_gemm<T, ROLE_ADJ>), grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_gemm<T, ROLE_DECODE>), grid, dim3(256), 0, s, a); break;
+    case ROLE_HIDDEN: RS_LAUNCH((k_gemm<T, ROLE_HIDDEN>), grid, dim3(256), 0, s, a); break;
+    case ROLE_OUT: RS_LAUNCH((k_gemm<T, ROLE_OUT>), grid, dim3(256), 0, s, a); break;
+    case ROLE_ADJ: RS_LAUNCH((k_gemm<T, ROLE_ADJ>), grid, dim3(256), 0, s, a); break;
+    default: RS_LAUNCH((k_gemm<T, ROLE_DECODE>), grid, dim3(256), 0, s, a); break;
     }
 }
 
@@ -168,6 +245,39 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
     dim3 grid(a.rows_pad / kTileM, (unsigned)((ncols + kTileN - 1) / kTileN), a.ksplit > 1 ? a.ksplit : 1);
     if (f32) gemm_dispatch<float>(role, grid, a, s);
     else gemm_dispatch<double>(role, grid, a, s);
+    return hipGetLastError();
+}
+
+// [h | J] = [ELU(a) | ELU'(a) A] for every (item, row) of a pre-activation
+// block, computed once before the output map reads it from every row tile.
+template <typename T>
+__global__ __launch_bounds__(256) void k_activate(const T* pre, T* act, int rows, int rows_pad, int nc,
+                                                  int items_cap, const int* count)
+{
+    const int items = count ? min(*count, items_cap) : items_cap;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x; // (item, row)
+    if (idx >= items * rows) return;
+    const int item = idx / rows, m = idx - item * rows;
+    const T* src = pre + ((size_t)item * rows_pad + m) * nc;
+    T* dst = act + ((size_t)item * rows_pad + m) * nc;
+    const T av = src[0];
+    const T d = T(elu1(av));
+    dst[0] = elu0(av);
+    for (int c = 1; c < nc; ++c) dst[c] = d * src[c];
+}
+
+hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
+                           const int* count, hipStream_t s)
+{
+    if (items_cap <= 0) return hipSuccess;
+    const long n = (long)items_cap * rows;
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (f32)
+        RS_LAUNCH(k_activate<float>, grid, dim3(256), 0, s, static_cast<const float*>(pre),
+                           static_cast<float*>(act), rows, rows_pad, nc, items_cap, count);
+    else
+        RS_LAUNCH(k_activate<double>, grid, dim3(256), 0, s, static_cast<const double*>(pre),
+                           static_cast<double*>(act), rows, rows_pad, nc, items_cap, count);
     return hipGetLastError();
 }
 
@@ -271,9 +381,6 @@ struct Snh {
 // g[k] += w V K_e[:,k].P; then the penalty, gravity and force rows.
 // Contributions are float64-accumulated and reduced in a fixed order.
 // ---------------------------------------------------------------------------
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 
 constexpr int kElemTile = 2880;  // max over RP of (tets per round) * 9 * (1 + r) values
 constexpr int kElemPrefetch = 6; // 16-byte vectors per thread per round (f64 worst case)
@@ -465,7 +572,7 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
     // one round's tile must fit the staging buffer and the prefetch registers
     if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
     dim3 grid(items), block(256);
-#define RS_ELEM(T, RP) hipLaunchKernelGGL((k_elem<T, RP>), grid, block, 0, s, a)
+#define RS_ELEM(T, RP) RS_LAUNCH((k_elem<T, RP>), grid, block, 0, s, a)
     if (f32) {
         switch (rp) {
         case 4: RS_ELEM(float, 4); break;
@@ -543,7 +650,7 @@ __global__ __launch_bounds__(256) void k_energy(EnergyArgs a)
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_energy, dim3(items), dim3(256), 0, s, a);
+    RS_LAUNCH(k_energy, dim3(items), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -553,6 +660,44 @@ hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 // the second-order term of the exact reduced Hessian.  dE/dh_L is the sum of
 // the adjoint GEMM's K-slice partials, taken in slice order.
 // ---------------------------------------------------------------------------
+// y[v] = sum_u W[u][v] x[u] for v < nout (W row stride ld), all 256 threads:
+// each output is split over ns = 256 / nout slices of u with 4 independent
+// partial sums (loads in flight), the slices summed in order through LDS.
+template <typename T>
+__device__ void matvec_t(const T* W, int ld, int nin, int nout, const double* x, double* y, double* part)
+{
+    const int tid = threadIdx.x;
+    const int ns = nout >= 256 ? 1 : 256 / nout;
+    for (int v0 = 0; v0 < nout; v0 += 256) {
+        const int v = v0 + tid % min(nout - v0, 256);
+        const int q = nout - v0 >= 256 ? 0 : tid / nout;
+        const bool act = q < ns && (nout - v0 >= 256 || tid < ns * nout);
+        const int len = (nin + ns - 1) / ns;
+        const int u0 = q * len, u1 = min(nin, u0 + len);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (act) {
+            int u = u0;
+            for (; u + 4 <= u1; u += 4) {
+                s0 += (double)W[(size_t)u * ld + v] * x[u];
+                s1 += (double)W[(size_t)(u + 1) * ld + v] * x[u + 1];
+                s2 += (double)W[(size_t)(u + 2) * ld + v] * x[u + 2];
+                s3 += (double)W[(size_t)(u + 3) * ld + v] * x[u + 3];
+            }
+            for (; u < u1; ++u) s0 += (double)W[(size_t)u * ld + v] * x[u];
+            part[tid] = (s0 + s1) + (s2 + s3);
+        }
+        __syncthreads();
+        if (nout - v0 >= 256) {
+            y[v0 + tid] = part[tid];
+        } else if (tid < nout - v0) {
+            double t = 0.0;
+            for (int qq = 0; qq < ns; ++qq) t += part[qq * nout + tid];
+            y[v0 + tid] = t;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 {
@@ -562,12 +707,14 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     const int w = a.width, nc = a.nc, r = a.r;
     double* gh = smem;       // dE/dh_l
     double* ga = gh + w;     // dE/da_l
-    double* cf = ga + w;     // dE/dh_l * s''(a_l), then scratch
-    T* As = reinterpret_cast<T*>(cf + w); // 64 x nc block of [a | A]
+    double* cf = ga + w;     // dE/dh_l * s''(a_l)
+    double* part = cf + w;   // 256 partial sums
+    T* As = reinterpret_cast<T*>(part + 256); // 64 x nc block of [a | A]
     for (int u = tid; u < w; u += 256) {
         double s = 0.0;
-        for (int z = 0; z < a.ksplit; ++z)
-            s += (double)static_cast<const T*>(a.gbar)[z * a.split_stride + (size_t)item * a.pre_rows + u];
+        const T* gp = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows + u;
+#pragma unroll 4
+        for (int z = 0; z < a.ksplit; ++z) s += (double)gp[z * a.split_stride];
         gh[u] = s;
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -588,29 +735,22 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
                 const int p = tid + 256 * q;
                 if (p >= r * r) break;
                 const int j = p / r, kk = p - j * r;
-                double s = 0.0;
-                for (int uu = 0; uu < nu; ++uu)
-                    s += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
-                acc[q] += s;
+                double s0 = 0.0, s1 = 0.0;
+                int uu = 0;
+                for (; uu + 2 <= nu; uu += 2) {
+                    s0 += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
+                    s1 += cf[u0 + uu + 1] * (double)As[(uu + 1) * nc + 1 + j] * (double)As[(uu + 1) * nc + 1 + kk];
+                }
+                if (uu < nu) s0 += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
+                acc[q] += s0 + s1;
             }
         }
         __syncthreads();
         if (l > 0) {
-            const T* W = static_cast<const T*>(a.W[l]);
-            for (int v = tid; v < w; v += 256) {
-                double s = 0.0;
-                for (int u = 0; u < w; ++u) s += (double)W[(size_t)u * a.lda + v] * ga[u];
-                cf[v] = s;
-            }
-            __syncthreads();
-            for (int v = tid; v < w; v += 256) gh[v] = cf[v];
+            matvec_t(static_cast<const T*>(a.W[l]), a.lda, w, w, ga, gh, part);
         } else if (a.grev) {
-            const T* W = static_cast<const T*>(a.W[0]);
-            for (int v = tid; v < r; v += 256) {
-                double s = 0.0;
-                for (int u = 0; u < w; ++u) s += (double)W[(size_t)u * a.lda0 + v] * ga[u];
-                a.grev[(size_t)item * r + v] = s;
-            }
+            matvec_t(static_cast<const T*>(a.W[0]), a.lda0, w, r, ga, cf, part);
+            for (int v = tid; v < r; v += 256) a.grev[(size_t)item * r + v] = cf[v];
         }
     }
     for (int q = 0; q < 4; ++q) {
@@ -622,9 +762,9 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
 {
     if (items <= 0 || a.L <= 0) return hipSuccess;
-    const size_t sh = 3 * sizeof(double) * a.width + (f32 ? 4 : 8) * 64 * a.nc;
-    if (f32) hipLaunchKernelGGL(k_curv<float>, dim3(items), dim3(256), sh, s, a);
-    else hipLaunchKernelGGL(k_curv<double>, dim3(items), dim3(256), sh, s, a);
+    const size_t sh = sizeof(double) * (3 * a.width + 256) + (f32 ? 4 : 8) * 64 * a.nc;
+    if (f32) RS_LAUNCH(k_curv<float>, dim3(items), dim3(256), sh, s, a);
+    else RS_LAUNCH(k_curv<double>, dim3(items), dim3(256), sh, s, a);
     return hipGetLastError();
 }
 
@@ -648,7 +788,7 @@ __global__ void k_newton_init(NewtonState st, int B)
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_init, dim3((B + 255) / 256), dim3(256), 0, s, st, B);
+    RS_LAUNCH(k_newton_init, dim3((B + 255) / 256), dim3(256), 0, s, st, B);
     return hipGetLastError();
 }
 
@@ -687,7 +827,7 @@ __global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B)
 
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact_eval, dim3(1), dim3(1024), 0, s, st, B);
+    RS_LAUNCH(k_compact_eval, dim3(1), dim3(1024), 0, s, st, B);
     return hipGetLastError();
 }
 
@@ -725,12 +865,17 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
     if (tid == 0) {
         st.counters[1] = base_c;
         st.counters[2] = base_s;
+        if (st.plog) {
+            st.plog[0] = st.counters[0];
+            st.plog[1] = base_c;
+            st.plog[2] = base_s;
+        }
     }
 }
 
 hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact_search, dim3(1), dim3(1024), 0, s, st, p, B);
+    RS_LAUNCH(k_compact_search, dim3(1), dim3(1024), 0, s, st, p, B);
     return hipGetLastError();
 }
 
@@ -947,7 +1092,7 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_dir, dim3(cap), dim3(64), 0, s, st, p);
+    RS_LAUNCH(k_newton_dir, dim3(cap), dim3(64), 0, s, st, p);
     return hipGetLastError();
 }
 
@@ -972,7 +1117,7 @@ __global__ void k_ls_candidates(NewtonState st, NewtonParams p)
 hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ls_candidates, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
+    RS_LAUNCH(k_ls_candidates, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
     return hipGetLastError();
 }
 
@@ -1005,7 +1150,7 @@ __global__ void k_armijo(NewtonState st, NewtonParams p)
 hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
 {
     if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_armijo, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
+    RS_LAUNCH(k_armijo, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
     return hipGetLastError();
 }
 
@@ -1025,7 +1170,7 @@ __global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B)
 
 hipError_t launch_count_running(const NewtonState& st, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_count_running, dim3(1), dim3(1024), 0, s, st, B);
+    RS_LAUNCH(k_count_running, dim3(1), dim3(1024), 0, s, st, B);
     return hipGetLastError();
 }
 
@@ -1044,7 +1189,7 @@ __global__ void k_stack_pairs(const double* z1, const double* z2, double* zs, in
 hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stack_pairs, dim3((B * r + 255) / 256), dim3(256), 0, s, z1, z2, zs, B, r);
+    RS_LAUNCH(k_stack_pairs, dim3((B * r + 255) / 256), dim3(256), 0, s, z1, z2, zs, B, r);
     return hipGetLastError();
 }
 
@@ -1117,8 +1262,8 @@ hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H,
                             double* loss, int* n_valid, double* lip_max, hipStream_t s)
 {
     if (B > 0)
-        hipLaunchKernelGGL(k_lip_pairs, dim3((B + 255) / 256), dim3(256), 0, s, z1, z2, H, B, r, per_pair, ell);
-    hipLaunchKernelGGL(k_lip_reduce, dim3(1), dim3(256), 0, s, ell, B, acc, first_chunk, last_chunk, loss,
+        RS_LAUNCH(k_lip_pairs, dim3((B + 255) / 256), dim3(256), 0, s, z1, z2, H, B, r, per_pair, ell);
+    RS_LAUNCH(k_lip_reduce, dim3(1), dim3(256), 0, s, ell, B, acc, first_chunk, last_chunk, loss,
                        n_valid, lip_max);
     return hipGetLastError();
 }

@@ -277,6 +277,12 @@ def test_profile_records_kernels():
     prof = ctx.profile_read()
     for k in ("gemm_out", "elem", "newton_dir", "energy_f64"):
         assert prof[k]["launches"] > 0 and prof[k]["ms"] > 0
+    # only the requested kind is bracketed
+    ctx.profile(True, kinds=["elem"])
+    ctx.newton_solve(torch.zeros((2, p.r), dtype=torch.float64, device=DEV))
+    ctx.profile(False)
+    prof = ctx.profile_read()
+    assert set(prof) == {"elem"} and prof["elem"]["bytes"] > 0
 
 
 # ------------------------------------------------------------------- full size
