@@ -93,6 +93,7 @@ struct rs_ctx {
     int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
     int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
     int ksplit = 1;               // K slices of the adjoint GEMM
+    int n_cu = 256;               // compute units of the device (persistent launch sizes)
     double* zc = nullptr;         // kLsCand*max_batch x r candidates
     std::vector<double*> pre64;   // L x (kLsCand*max_batch x wrows)
     double* out64 = nullptr;      // kLsCand*max_batch x Mp
@@ -500,6 +501,12 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->act64 = (double*)need(dalloc<double>(c, BL * c->wrows));
     c->dseed = need(dalloc_bytes(c, B * c->Mp * ts));
     c->ksplit = std::max(1, std::min(kMaxSplit, c->Mp / 160));
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            c->n_cu = ncu;
+    }
     c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
     c->Ew = (double*)need(dalloc<double>(c, B));
     c->gw = (double*)need(dalloc<double>(c, B * c->r));
@@ -613,6 +620,71 @@ static int activate(rs_ctx* c, int f32, const void* pre, void* act, int nc, int 
                [&] { return launch_activate(f32, pre, act, c->w, c->wrows, nc, cap, count, s); });
 }
 
+// Hidden layers for `cap` items: pre-activations into pre[] (T path) and the
+// last layer's activation into act.  One fused launch when its tiles fit,
+// else one GEMM per layer and an activation pass.
+static int hidden_layers(rs_ctx* c, int f32, int nc, int cap, const int* count, int which, const double* z,
+                         const int* zmap, void* const* pre, void* act, const void* const* W, const void* const* bh,
+                         int kind, hipStream_t s)
+{
+    if (c->L == 0) return RS_OK;
+    const size_t ts = f32 ? 4 : 8;
+    const int slot = c->cur_slot;
+    if (mlp_fits(f32, nc, c->r, c->wrows)) {
+        MlpArgs m{};
+        for (int l = 0; l < c->L; ++l) {
+            m.W[l] = W[l];
+            m.b[l] = bh[l];
+            m.pre[l] = pre ? pre[l] : nullptr;
+        }
+        m.act = act;
+        m.L = c->L;
+        m.w = c->w;
+        m.wrows = c->wrows;
+        m.r = c->r;
+        m.nc = nc;
+        m.lda0 = c->lda0;
+        m.lda = c->lda_h;
+        m.items = cap;
+        m.count = count;
+        m.z = z;
+        m.zmap = zmap;
+        double pb = 0, pf = 0;
+        for (int l = 0; l < c->L; ++l) {
+            const int K = l == 0 ? c->r : c->w;
+            pf += 2.0 * c->w * K * nc;
+            pb += ts * (double)c->w * nc * (pre ? 1 : 0);
+        }
+        pb += ts * (double)c->w * nc + 8.0 * c->r;
+        Work wk = item_work(pb, pf, cap, count, slot, which);
+        for (int l = 0; l < c->L; ++l) wk.b0 += ts * (double)c->w * (l == 0 ? c->r : c->w);
+        return run(c, kind, wk, s, [&] { return launch_mlp(f32, m, s); });
+    }
+    for (int l = 0; l < c->L; ++l) {
+        GemmArgs a{};
+        a.A = W[l];
+        a.lda = l == 0 ? c->lda0 : c->lda_h;
+        a.rows = c->w;
+        a.rows_pad = c->wrows;
+        a.K = l == 0 ? c->r : c->w;
+        a.nc = nc;
+        a.items = cap;
+        a.count = count;
+        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
+        a.Y = l == 0 ? nullptr : pre[l - 1];
+        a.y_rows = c->wrows;
+        a.z = z;
+        a.zmap = zmap;
+        a.r = c->r;
+        a.bias = bh[l];
+        a.out_mode = OUT_PACK;
+        a.C = pre[l];
+        RS_TRY(run(c, kind, gemm_work(ts, a.rows, a.K, cap, nc, count, slot, which), s,
+                   [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
+    }
+    return activate(c, f32, pre[c->L - 1], act, nc, cap, count, which, s);
+}
+
 // T-precision decoder value + Jacobian, reduced rows, element terms and (exact)
 // the curvature term.  `cap` items fit the launch; `count` (device, nullable)
 // holds the actual number.  Item i uses latent point z[zmap[i]] and the loads
@@ -625,29 +697,8 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
     const int f32 = c->f32;
     const size_t ts = c->tsz;
     const int slot = c->cur_slot;
-    for (int l = 0; l < c->L; ++l) {
-        GemmArgs a{};
-        a.A = c->W[l];
-        a.lda = l == 0 ? c->lda0 : c->lda_h;
-        a.rows = c->w;
-        a.rows_pad = c->wrows;
-        a.K = l == 0 ? r : c->w;
-        a.nc = nc;
-        a.items = cap;
-        a.count = count;
-        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
-        a.Y = l == 0 ? nullptr : c->pre[l - 1];
-        a.y_rows = c->wrows;
-        a.z = z;
-        a.zmap = zmap;
-        a.r = r;
-        a.bias = c->bh[l];
-        a.out_mode = OUT_PACK;
-        a.C = c->pre[l];
-        RS_TRY(run(c, K_GEMM_HIDDEN, gemm_work(ts, a.rows, a.K, cap, nc, count, slot, 0), s,
-                   [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
-    }
-    if (c->L > 0) RS_TRY(activate(c, f32, c->pre[c->L - 1], c->act, nc, cap, count, 0, s));
+    RS_TRY(hidden_layers(c, f32, nc, cap, count, 0, z, zmap, c->pre.data(), c->act, c->W.data(), c->bh.data(),
+                         K_GEMM_HIDDEN, s));
     {
         GemmArgs a{};
         a.A = c->Wbig;
@@ -658,7 +709,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.nc = nc;
         a.items = cap;
         a.count = count;
-        a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+        a.in_mode = c->L > 0 ? IN_RAW_T : IN_LATENT;
         a.Y = c->L > 0 ? c->act : nullptr;
         a.y_rows = c->wrows;
         a.z = z;
@@ -667,8 +718,10 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.bias = c->bbig;
         a.out_mode = OUT_PACK;
         a.C = c->out;
-        RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, nc, count, slot, 0), s,
-                   [&] { return launch_gemm(f32, ROLE_OUT, a, s); }));
+        RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, nc, count, slot, 0), s, [&] {
+            return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_OUT, a, 8 * c->n_cu, s)
+                                         : launch_gemm(f32, ROLE_OUT, a, s);
+        }));
     }
     const bool exact = (flags & RS_HESS_EXACT) && c->L > 0 && H;
     {
@@ -754,28 +807,12 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
 {
     const int r = c->r;
     const int slot = c->cur_slot;
-    for (int l = 0; l < c->L; ++l) {
-        GemmArgs a{};
-        a.A = c->W64[l];
-        a.lda = l == 0 ? c->lda0 : c->lda_h;
-        a.rows = c->w;
-        a.rows_pad = c->wrows;
-        a.K = l == 0 ? r : c->w;
-        a.nc = 1;
-        a.items = cap;
-        a.count = count;
-        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
-        a.Y = l == 0 ? nullptr : c->pre64[l - 1];
-        a.y_rows = c->wrows;
-        a.z = z;
-        a.r = r;
-        a.bias = c->bh64[l];
-        a.out_mode = OUT_PACK;
-        a.C = c->pre64[l];
-        RS_TRY(run(c, kind_hidden, gemm_work(8, a.rows, a.K, cap, 1, count, slot, which), s,
-                   [&] { return launch_gemm(0, ROLE_HIDDEN, a, s); }));
+    {
+        std::vector<void*> pre64(c->pre64.begin(), c->pre64.end());
+        std::vector<const void*> W64(c->W64.begin(), c->W64.end()), b64(c->bh64.begin(), c->bh64.end());
+        RS_TRY(hidden_layers(c, 0, 1, cap, count, which, z, nullptr, mlp_fits(0, 1, c->r, c->wrows) ? nullptr : pre64.data(),
+                             c->act64, W64.data(), b64.data(), kind_hidden, s));
     }
-    if (c->L > 0) RS_TRY(activate(c, 0, c->pre64[c->L - 1], c->act64, 1, cap, count, which, s));
     {
         GemmArgs a{};
         a.A = c->Wbig64;
@@ -786,7 +823,7 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
         a.nc = 1;
         a.items = cap;
         a.count = count;
-        a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+        a.in_mode = c->L > 0 ? IN_RAW_T : IN_LATENT;
         a.Y = c->L > 0 ? c->act64 : nullptr;
         a.y_rows = c->wrows;
         a.z = z;
@@ -794,8 +831,9 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
         a.bias = c->bbig64;
         a.out_mode = OUT_PACK;
         a.C = c->out64;
-        RS_TRY(run(c, kind_out, gemm_work(8, c->M, a.K, cap, 1, count, slot, which), s,
-                   [&] { return launch_gemm(0, ROLE_OUT, a, s); }));
+        RS_TRY(run(c, kind_out, gemm_work(8, c->M, a.K, cap, 1, count, slot, which), s, [&] {
+            return gemm_p_fits(0, a.K) ? launch_gemm_p(0, ROLE_OUT, a, 8 * c->n_cu, s) : launch_gemm(0, ROLE_OUT, a, s);
+        }));
     }
     EnergyArgs e{};
     e.out = c->out64;
@@ -859,27 +897,9 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     const int r = c->r, nc = J ? c->nc : 1;
     const int f32 = c->f32;
     const size_t ts = c->tsz;
-    for (int l = 0; l < c->L; ++l) {
-        GemmArgs a{};
-        a.A = c->W[l];
-        a.lda = l == 0 ? c->lda0 : c->lda_h;
-        a.rows = c->w;
-        a.rows_pad = c->wrows;
-        a.K = l == 0 ? r : c->w;
-        a.nc = nc;
-        a.items = B;
-        a.in_mode = l == 0 ? IN_LATENT : IN_ELU;
-        a.Y = l == 0 ? nullptr : c->pre[l - 1];
-        a.y_rows = c->wrows;
-        a.z = z;
-        a.r = r;
-        a.bias = c->bh[l];
-        a.out_mode = OUT_PACK;
-        a.C = c->pre[l];
-        RS_TRY(run(c, K_DECODE_HIDDEN, gemm_work(ts, a.rows, a.K, B, nc, nullptr, -1, 0), s,
-                   [&] { return launch_gemm(f32, ROLE_HIDDEN, a, s); }));
-    }
-    if (c->L > 0) RS_TRY(activate(c, f32, c->pre[c->L - 1], c->act, nc, B, nullptr, 0, s));
+    c->cur_slot = -1;
+    RS_TRY(hidden_layers(c, f32, nc, B, nullptr, 0, z, nullptr, c->pre.data(), c->act, c->W.data(), c->bh.data(),
+                         K_DECODE_HIDDEN, s));
     GemmArgs a{};
     a.A = c->Wfull;
     a.lda = c->lda_out;
@@ -888,7 +908,7 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.K = c->in_last;
     a.nc = nc;
     a.items = B;
-    a.in_mode = c->L > 0 ? IN_RAW : IN_LATENT;
+    a.in_mode = c->L > 0 ? IN_RAW_T : IN_LATENT;
     a.Y = c->L > 0 ? c->act : nullptr;
     a.y_rows = c->wrows;
     a.z = z;
@@ -898,8 +918,10 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.Xo = x;
     a.Jo = J;
     a.Xrest = c->Xfull;
-    return run(c, K_DECODE_OUT, gemm_work(ts, c->n_out, a.K, B, nc, nullptr, -1, 0), s,
-               [&] { return launch_gemm(f32, ROLE_DECODE, a, s); });
+    return run(c, K_DECODE_OUT, gemm_work(ts, c->n_out, a.K, B, nc, nullptr, -1, 0), s, [&] {
+        return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_DECODE, a, 8 * c->n_cu, s)
+                                     : launch_gemm(f32, ROLE_DECODE, a, s);
+    });
 }
 
 // Copy the current Newton counters to the profile log (profiling only).

@@ -19,7 +19,10 @@ constexpr int kLsCand = 8;   // step lengths evaluated per line-search round aft
 constexpr int kMaxL = 8;     // largest number of hidden layers
 constexpr int kMaxSplit = 16;// largest split of the adjoint GEMM's reduction
 
-enum InMode { IN_RAW = 0, IN_ELU = 1, IN_LATENT = 2 };
+// IN_RAW: item-major (y_rows x nc) blocks; IN_RAW_T: item-major (nc x y_rows)
+// blocks (k contiguous, the layout of a layer activation); IN_ELU: IN_RAW
+// pre-activations activated on load; IN_LATENT: [z | I] built from z.
+enum InMode { IN_RAW = 0, IN_ELU = 1, IN_LATENT = 2, IN_RAW_T = 3 };
 enum OutMode { OUT_PACK = 0, OUT_SPLIT = 1 };
 // kernel symbols per GEMM role (so profilers tell them apart)
 enum GemmRole { ROLE_HIDDEN = 0, ROLE_OUT = 1, ROLE_ADJ = 2, ROLE_DECODE = 3 };
@@ -50,6 +53,21 @@ struct GemmArgs {
     void* Xo;             // OUT_SPLIT: column 0 -> Xo[item*rows + m] = Xrest[m] + value
     void* Jo;             // OUT_SPLIT: column c>0 -> Jo[(item*rows + m)*r + c-1]
     const void* Xrest;
+};
+
+// All hidden layers of the decoder for blocks of whole items: value and (nc > 1)
+// forward-mode Jacobian, [a | A] pre-activations per layer and the final
+// activation [h | J] = [ELU(a) | ELU'(a) A] of the last layer.
+struct MlpArgs {
+    const void* W[kMaxL];   // wrows x lda (lda0 for layer 0), zero padded
+    const void* b[kMaxL];   // wrows
+    void* pre[kMaxL];       // item-major (wrows x nc) pre-activations per layer (NULL = not kept)
+    void* act;              // item-major (nc x wrows) activation of the last layer (k contiguous)
+    int L, w, wrows, r, nc, lda0, lda;
+    int items;              // grid capacity in items
+    const int* count;       // actual item count (NULL = items)
+    const double* z;        // latent points (float64)
+    const int* zmap;        // item -> row of z (NULL = identity)
 };
 
 // Per-item cubature elastic, penalty, gravity and force terms from the rows of
@@ -141,6 +159,11 @@ struct NewtonParams {
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
 hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s);
+// persistent variant for IN_RAW / IN_LATENT inputs with K a supported multiple of 32
+hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks, hipStream_t s);
+bool gemm_p_fits(int f32, int K);
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s);
+bool mlp_fits(int f32, int nc, int r, int wrows); // the fused kernel's LDS and tiling limits
 hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
                            const int* count, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);

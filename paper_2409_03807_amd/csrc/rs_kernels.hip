@@ -127,6 +127,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
     if (a.in_mode == IN_LATENT && ycol) zrow = a.zmap ? a.zmap[yitem] : yitem;
     const T* Ycol = (a.in_mode != IN_LATENT && ycol)
                         ? static_cast<const T*>(a.Y) + (size_t)yitem * a.y_rows * a.nc : nullptr;
+    const T* Ytr = (a.in_mode == IN_RAW_T && ycol)
+                       ? static_cast<const T*>(a.Y) + ((size_t)yitem * a.nc + yc) * a.y_rows : nullptr;
 
     V ra[8 / VN];
     T ry[8];
@@ -142,6 +144,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
                 if (a.in_mode == IN_LATENT) {
                     if (yc == 0) v = (T)a.z[zrow * a.r + k];
                     else v = (k == yc - 1) ? T(1) : T(0);
+                } else if (a.in_mode == IN_RAW_T) {
+                    v = Ytr[k];
                 } else {
                     const T* Yb = Ycol + (size_t)k * a.nc;
                     if (a.in_mode == IN_ELU) {
@@ -227,6 +231,396 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent output-map GEMM (IN_RAW / IN_LATENT inputs, OUT_PACK / OUT_SPLIT):
+// a workgroup keeps its 64 rows of A for the whole K in registers (loaded once
+// from L2) and walks the column tiles g, g + G, g + 2G, ...; each 32-deep
+// chunk of the input tile goes through a double-buffered LDS pipeline with
+// the next chunk prefetched into registers behind the MFMAs (one barrier per
+// chunk).  KCH = K / 32 chunks.
+// ---------------------------------------------------------------------------
+template <typename T, int ROLE, int KCH>
+__global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int LD = kTileK + VN;
+    __shared__ __align__(16) T Ys[2][kTileN * LD];
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const int ncols = items * a.nc;
+    const int ntiles = (ncols + kTileN - 1) / kTileN;
+    const int g = blockIdx.y;
+    if (g >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m0 = blockIdx.x * kTileM;
+    const unsigned ncu = (unsigned)a.nc;
+    using acc_t = typename Mfma<T>::acc_t;
+
+    // A fragments for every chunk: row m0 + 16 wave + li, k = 32 c + 8 lg .. + 7
+    T af[KCH][8];
+    {
+        const T* A = static_cast<const T*>(a.A) + (size_t)(m0 + wave * 16 + li) * a.lda + 8 * lg;
+#pragma unroll
+        for (int c = 0; c < KCH; ++c) {
+            const V* src = reinterpret_cast<const V*>(A + c * kTileK);
+#pragma unroll
+            for (int q = 0; q < 8 / VN; ++q) {
+                const V w = src[q];
+                const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = wp[e];
+            }
+        }
+    }
+
+    // input tile loads: thread owns column ynn of the tile and 8 consecutive k
+    const int ynn = tid & 63, ykb = (tid >> 6) * 8;
+    T ry[8];
+    auto load = [&](int ct, int c) {
+        const int yn = ct * kTileN + ynn;
+        const int k0 = c * kTileK + ykb;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ry[q] = T(0);
+        if (yn < ncols) {
+            const int yitem = (int)((unsigned)yn / ncu);
+            const int yc = yn - yitem * a.nc;
+            if (a.in_mode == IN_LATENT) {
+                const long zr = a.zmap ? a.zmap[yitem] : yitem;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int k = k0 + q;
+                    if (k < a.K) ry[q] = (yc == 0) ? (T)a.z[zr * a.r + k] : ((k == yc - 1) ? T(1) : T(0));
+                }
+            } else if (a.in_mode == IN_RAW_T) {
+                const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * a.nc + yc) * a.y_rows + k0;
+                if (k0 + 8 <= a.K) {
+                    const V* v8 = reinterpret_cast<const V*>(Yb);
+#pragma unroll
+                    for (int q = 0; q < 8 / VN; ++q) {
+                        const V w = v8[q];
+                        const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                        for (int e = 0; e < VN; ++e) ry[q * VN + e] = wp[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (k0 + q < a.K) ry[q] = Yb[q];
+                }
+            } else {
+                const T* Yb = static_cast<const T*>(a.Y) + ((size_t)yitem * a.y_rows + k0) * a.nc + yc;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k0 + q < a.K) ry[q] = Yb[(size_t)q * a.nc];
+            }
+        }
+    };
+    auto store = [&](int buf) {
+        V* dy = reinterpret_cast<V*>(&Ys[buf][ynn * LD + ykb]);
+#pragma unroll
+        for (int q = 0; q < 8 / VN; ++q) {
+            V w;
+            T* wp = reinterpret_cast<T*>(&w);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+            dy[q] = w;
+        }
+    };
+
+    const T* bias = static_cast<const T*>(a.bias);
+    T* Cout = static_cast<T*>(a.C);
+    acc_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+
+    int ct = g, c = 0, buf = 0;
+    load(ct, 0);
+    store(0);
+    __syncthreads();
+    for (;;) {
+        // next (tile, chunk) of this workgroup
+        int nct = ct, nchk = c + 1;
+        if (nchk == KCH) {
+            nchk = 0;
+            nct = ct + groups;
+        }
+        const bool more = nct < ntiles;
+        if (more) load(nct, nchk);
+        {
+            T bf[4][8];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const V* sb = reinterpret_cast<const V*>(&Ys[buf][(t * 16 + li) * LD + 8 * lg]);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const V w = sb[q];
+                    const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < KCH; ++cc) {
+                if (cc != c) continue;
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[cc][kk], bf[t][kk], acc[t]);
+            }
+        }
+        if (c == KCH - 1) {
+            // epilogue of tile ct
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n = ct * kTileN + t * 16 + li;
+                if (n < ncols) {
+                    const int item = (int)((unsigned)n / ncu);
+                    const int cidx = n - item * a.nc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = m0 + wave * 16 + Mfma<T>::row(lane, v);
+                        if (m >= a.rows) continue;
+                        T val = acc[t][v];
+                        if (cidx == 0 && bias) val += bias[m];
+                        if (a.out_mode == OUT_PACK) {
+                            Cout[((size_t)item * a.rows_pad + m) * a.nc + cidx] = val;
+                        } else if (cidx == 0) {
+                            if (a.Xo)
+                                static_cast<T*>(a.Xo)[(size_t)item * a.rows + m] =
+                                    static_cast<const T*>(a.Xrest)[m] + val;
+                        } else if (a.Jo) {
+                            static_cast<T*>(a.Jo)[((size_t)item * a.rows + m) * a.r + (cidx - 1)] = val;
+                        }
+                    }
+                }
+                acc[t] = acc_t{0, 0, 0, 0};
+            }
+        }
+        if (!more) break;
+        store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        ct = nct;
+        c = nchk;
+    }
+}
+
+// Same contract with the whole K of the next column tile prefetched into
+// registers (thread: one column, K/4 consecutive k) while the current tile,
+// resident in LDS, feeds the MFMAs: the load latency hides behind a full
+// tile of MFMAs.  Used when the tile fits 64 KB of LDS.
+template <typename T, int ROLE, int KCH, int INM, int OUTM>
+__global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int KT = KCH * kTileK;   // K of a tile
+    constexpr int LD = KT + VN;
+    constexpr int PER = KT / 4;        // k per thread (4 thread groups per column)
+    __shared__ __align__(16) T Ys[kTileN * LD];
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const int ncols = items * a.nc;
+    const int ntiles = (ncols + kTileN - 1) / kTileN;
+    const int g = blockIdx.y;
+    if (g >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m0 = blockIdx.x * kTileM;
+    const int nc = a.nc;
+    const unsigned ncu = (unsigned)nc;
+    using acc_t = typename Mfma<T>::acc_t;
+
+    T af[KCH][8];
+    {
+        const T* A = static_cast<const T*>(a.A) + (size_t)(m0 + wave * 16 + li) * a.lda + 8 * lg;
+#pragma unroll
+        for (int c = 0; c < KCH; ++c) {
+            const V* src = reinterpret_cast<const V*>(A + c * kTileK);
+#pragma unroll
+            for (int q = 0; q < 8 / VN; ++q) {
+                const V w = src[q];
+                const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = wp[e];
+            }
+        }
+    }
+    // the lane's 4 output rows do not change from tile to tile
+    int mrow[4];
+    T brow[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        mrow[v] = m0 + wave * 16 + Mfma<T>::row(lane, v);
+        brow[v] = (a.bias && mrow[v] < a.rows) ? static_cast<const T*>(a.bias)[mrow[v]] : T(0);
+    }
+
+    const int ynn = tid & 63, ykb = (tid >> 6) * PER;
+    T ry[PER];
+    auto load = [&](int ct) {
+        const int yn = ct * kTileN + ynn;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) ry[q] = T(0);
+        if (yn < ncols) {
+            const int yitem = (int)((unsigned)yn / ncu);
+            const int yc = yn - yitem * nc;
+            if constexpr (INM == IN_LATENT) {
+                const long zr = a.zmap ? a.zmap[yitem] : yitem;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int k = ykb + q;
+                    if (k < a.K) ry[q] = (yc == 0) ? (T)a.z[zr * a.r + k] : ((k == yc - 1) ? T(1) : T(0));
+                }
+            } else {
+                // IN_RAW_T with K a multiple of the tile depth: one contiguous run
+                const V* vp = reinterpret_cast<const V*>(static_cast<const T*>(a.Y) +
+                                                         ((size_t)yitem * nc + yc) * a.y_rows + ykb);
+#pragma unroll
+                for (int q = 0; q < PER / VN; ++q) {
+                    const V w = vp[q];
+                    const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) ry[q * VN + e] = wp[e];
+                }
+            }
+        }
+    };
+    auto store = [&]() {
+        V* dy = reinterpret_cast<V*>(&Ys[ynn * LD + ykb]);
+#pragma unroll
+        for (int q = 0; q < PER / VN; ++q) {
+            V w;
+            T* wp = reinterpret_cast<T*>(&w);
+#pragma unroll
+            for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+            dy[q] = w;
+        }
+    };
+
+    T* Cout = static_cast<T*>(a.C);
+    load(g);
+    for (int ct = g; ct < ntiles; ct += groups) {
+        __syncthreads(); // the previous tile's LDS reads are done
+        store();
+        __syncthreads();
+        if (ct + groups < ntiles) load(ct + groups);
+        acc_t acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < KCH; ++c) {
+            T bf[4][8];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const V* sb = reinterpret_cast<const V*>(&Ys[(t * 16 + li) * LD + c * kTileK + 8 * lg]);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const V w = sb[q];
+                    const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[c][kk], bf[t][kk], acc[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int n = ct * kTileN + t * 16 + li;
+            if (n >= ncols) continue;
+            const int item = (int)((unsigned)n / ncu);
+            const int cidx = n - item * nc;
+            if constexpr (OUTM == OUT_PACK) {
+                T* base = Cout + (size_t)item * a.rows_pad * nc + cidx;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (mrow[v] < a.rows) base[(size_t)mrow[v] * nc] = acc[t][v] + (cidx == 0 ? brow[v] : T(0));
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = mrow[v];
+                    if (m >= a.rows) continue;
+                    const T val = acc[t][v] + (cidx == 0 ? brow[v] : T(0));
+                    if (cidx == 0) {
+                        if (a.Xo)
+                            static_cast<T*>(a.Xo)[(size_t)item * a.rows + m] = static_cast<const T*>(a.Xrest)[m] + val;
+                    } else if (a.Jo) {
+                        static_cast<T*>(a.Jo)[((size_t)item * a.rows + m) * a.r + (cidx - 1)] = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int ROLE>
+static hipError_t gemm_p_dispatch(const GemmArgs& a, int groups, hipStream_t s)
+{
+    const int kch = (a.K + kTileK - 1) / kTileK;
+    dim3 grid(a.rows_pad / kTileM, groups);
+    const size_t tile = (size_t)kTileN * (kch * kTileK + Vec16<T>::n) * sizeof(T);
+    // fast variant: whole-K tiles, raw transposed input (K a multiple of 32) or latent input
+    const bool fast_in = (a.in_mode == IN_RAW_T && a.K % kTileK == 0) || a.in_mode == IN_LATENT;
+    if (tile <= 64 * 1024 && fast_in) {
+#define RS_P2(KC)                                                                                         \
+    do {                                                                                                  \
+        if (a.in_mode == IN_LATENT) {                                                                     \
+            if (a.out_mode == OUT_PACK)                                                                   \
+                RS_LAUNCH((k_gemm_p2<T, ROLE, KC, IN_LATENT, OUT_PACK>), grid, dim3(256), 0, s, a, groups); \
+            else                                                                                          \
+                RS_LAUNCH((k_gemm_p2<T, ROLE, KC, IN_LATENT, OUT_SPLIT>), grid, dim3(256), 0, s, a, groups); \
+        } else {                                                                                          \
+            if (a.out_mode == OUT_PACK)                                                                   \
+                RS_LAUNCH((k_gemm_p2<T, ROLE, KC, IN_RAW_T, OUT_PACK>), grid, dim3(256), 0, s, a, groups); \
+            else                                                                                          \
+                RS_LAUNCH((k_gemm_p2<T, ROLE, KC, IN_RAW_T, OUT_SPLIT>), grid, dim3(256), 0, s, a, groups); \
+        }                                                                                                 \
+        return hipGetLastError();                                                                         \
+    } while (0)
+        switch (kch) {
+        case 1: RS_P2(1);
+        case 2: RS_P2(2);
+        case 4: RS_P2(4);
+        default: break;
+        }
+#undef RS_P2
+    }
+    switch (kch) {
+    case 1: RS_LAUNCH((k_gemm_p<T, ROLE, 1>), grid, dim3(256), 0, s, a, groups); break;
+    case 2: RS_LAUNCH((k_gemm_p<T, ROLE, 2>), grid, dim3(256), 0, s, a, groups); break;
+    case 4: RS_LAUNCH((k_gemm_p<T, ROLE, 4>), grid, dim3(256), 0, s, a, groups); break;
+    case 8: RS_LAUNCH((k_gemm_p<T, ROLE, 8>), grid, dim3(256), 0, s, a, groups); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// persistent kernel for the output maps when K is a supported chunk count
+bool gemm_p_fits(int f32, int K)
+{
+    const int kch = (K + kTileK - 1) / kTileK;
+    return (kch == 1 || kch == 2 || kch == 4 || (kch == 8 && f32));
+}
+
+hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks, hipStream_t s)
+{
+    if (a.items <= 0) return hipSuccess;
+    if (a.in_mode == IN_ELU || a.ksplit > 1) return hipErrorInvalidValue;
+    const int rt = a.rows_pad / kTileM;
+    const int ntiles = (a.items * a.nc + kTileN - 1) / kTileN;
+    int groups = (target_blocks + rt - 1) / rt;
+    if (groups > ntiles) groups = ntiles;
+    if (groups < 1) groups = 1;
+    if (f32) {
+        if (role == ROLE_DECODE) return gemm_p_dispatch<float, ROLE_DECODE>(a, groups, s);
+        return gemm_p_dispatch<float, ROLE_OUT>(a, groups, s);
+    }
+    if (role == ROLE_DECODE) return gemm_p_dispatch<double, ROLE_DECODE>(a, groups, s);
+    return gemm_p_dispatch<double, ROLE_OUT>(a, groups, s);
+}
+
 template <typename T>
 static void gemm_dispatch(int role, dim3 grid, const GemmArgs& a, hipStream_t s)
 {
@@ -248,6 +642,178 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fused hidden layers.  A workgroup owns CT*16 columns holding whole items
+// (IB = CT*16 / nc of them); their layer input lives in LDS as [column][k]
+// (k contiguous), each wave owns RT*16 output rows.  Weights come straight
+// from L2 into registers (8 consecutive k per lane, permuted-k MFMA order as
+// in k_gemm), the next 32-deep chunk prefetched behind the MFMAs.  After a
+// layer the pre-activations go to global memory and, activated, replace the
+// LDS input of the next layer.
+// ---------------------------------------------------------------------------
+template <typename T, int CT, int RT>
+__global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int NP = CT * 16;
+    extern __shared__ __align__(16) unsigned char mlp_smem[];
+    T* Ys = reinterpret_cast<T*>(mlp_smem);
+    const int nc = a.nc;
+    const int IB = NP / nc;
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const int item0 = blockIdx.x * IB;
+    if (item0 >= items) return;
+    const int nitems = min(IB, items - item0);
+    const int ncols = nitems * nc;
+    // rows of a column: every k of the layer-0 input and every (padded) output row
+    const int LDY = max((a.r + kTileK - 1) / kTileK * kTileK, a.wrows) + VN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    using acc_t = typename Mfma<T>::acc_t;
+
+    // layer-0 input [z | I]
+    {
+        const int kp = (a.r + kTileK - 1) / kTileK * kTileK;
+        for (int e = tid; e < NP * kp; e += 256) {
+            const int n = e / kp, k = e - n * kp;
+            T v = T(0);
+            if (n < ncols && k < a.r) {
+                const int i = n / nc, c = n - i * nc;
+                const long zr = a.zmap ? a.zmap[item0 + i] : item0 + i;
+                v = (c == 0) ? (T)a.z[zr * a.r + k] : ((k == c - 1) ? T(1) : T(0));
+            }
+            Ys[n * LDY + k] = v;
+        }
+    }
+    for (int l = 0; l < a.L; ++l) {
+        const int K = l == 0 ? a.r : a.w;
+        const int kp = (K + kTileK - 1) / kTileK * kTileK;
+        const int lda = l == 0 ? a.lda0 : a.lda;
+        const T* W = static_cast<const T*>(a.W[l]);
+        __syncthreads();
+        acc_t acc[RT][CT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int t = 0; t < CT; ++t) acc[i][t] = acc_t{0, 0, 0, 0};
+        V wa[RT][8 / VN];
+        auto loadw = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const V* src = reinterpret_cast<const V*>(W + (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) wa[i][q] = src[q];
+            }
+        };
+        loadw(0);
+        for (int k0 = 0; k0 < kp; k0 += kTileK) {
+            T af[RT][8];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const T* wp = reinterpret_cast<const T*>(&wa[i][q]);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) af[i][q * VN + e] = wp[e];
+                }
+            if (k0 + kTileK < kp) loadw(k0 + kTileK);
+            T bf[CT][8];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const V w = sb[q];
+                    const T* wp = reinterpret_cast<const T*>(&w);
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                }
+            }
+            // k-step outermost: RT*CT independent accumulators between dependent MFMAs
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                for (int t = 0; t < CT; ++t)
+#pragma unroll
+                    for (int i = 0; i < RT; ++i) acc[i][t] = Mfma<T>::mac(af[i][kk], bf[t][kk], acc[i][t]);
+        }
+        __syncthreads(); // every wave is done reading this layer's input
+        const T* bias = static_cast<const T*>(a.b[l]);
+        T* pre = static_cast<T*>(a.pre[l]);
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            const int n = t * 16 + li;
+            const int i = n / nc, c = n - i * nc;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = wave * RT * 16 + rt * 16 + Mfma<T>::row(lane, v);
+                    T val = acc[rt][t][v];
+                    if (c == 0) val += bias[m];
+                    Ys[n * LDY + m] = val;
+                    if (pre && n < ncols) pre[((size_t)(item0 + i) * a.wrows + m) * nc + c] = val;
+                }
+        }
+        __syncthreads();
+        // activation in place, one thread per (item, row): ELU' of the value
+        // column scales the item's Jacobian columns, then the value column
+        for (int e = tid; e < nitems * a.wrows; e += 256) {
+            const int i = e / a.wrows, m = e - i * a.wrows;
+            T* col = Ys + (i * nc) * LDY + m;
+            const T av = col[0];
+            const T d = T(elu1(av));
+            for (int c = 1; c < nc; ++c) col[c * LDY] *= d;
+            col[0] = elu0(av);
+        }
+    }
+    __syncthreads();
+    // activation out as (nc x wrows) per item: consecutive threads, consecutive rows
+    T* act = static_cast<T*>(a.act) + (size_t)item0 * nc * a.wrows;
+    for (int e = tid; e < ncols * a.wrows; e += 256) {
+        const int n = e / a.wrows, m = e - n * a.wrows;
+        act[e] = Ys[n * LDY + m];
+    }
+}
+
+template <typename T, int CT>
+static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
+{
+    const int np = CT * 16;
+    const int ib = np / a.nc;
+    if (ib < 1) return hipErrorInvalidValue;
+    const int rt = a.wrows / 64;
+    const int kr = (a.r + kTileK - 1) / kTileK * kTileK;
+    const int ldy = (kr > a.wrows ? kr : a.wrows) + Vec16<T>::n;
+    const size_t sh = (size_t)np * ldy * sizeof(T);
+    if (sh > 64 * 1024) return hipErrorInvalidValue;
+    dim3 grid((a.items + ib - 1) / ib);
+    switch (rt) {
+    case 1: RS_LAUNCH((k_mlp<T, CT, 1>), grid, dim3(256), sh, s, a); break;
+    case 2: RS_LAUNCH((k_mlp<T, CT, 2>), grid, dim3(256), sh, s, a); break;
+    case 4: RS_LAUNCH((k_mlp<T, CT, 4>), grid, dim3(256), sh, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool mlp_fits(int f32, int nc, int r, int wrows)
+{
+    const int np = nc > 1 ? 80 : 16;
+    const int kr = (r + kTileK - 1) / kTileK * kTileK;
+    const size_t ldy = (size_t)(kr > wrows ? kr : wrows) + (f32 ? 4 : 2);
+    const int rt = wrows / 64;
+    return np / nc >= 1 && (rt == 1 || rt == 2 || rt == 4) && np * ldy * (f32 ? 4 : 8) <= 64 * 1024;
+}
+
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s)
+{
+    if (a.items <= 0 || a.L <= 0) return hipSuccess;
+    if (a.nc > 1) return f32 ? mlp_dispatch<float, 5>(a, s) : mlp_dispatch<double, 5>(a, s);
+    return f32 ? mlp_dispatch<float, 1>(a, s) : mlp_dispatch<double, 1>(a, s);
+}
+
 // [h | J] = [ELU(a) | ELU'(a) A] for every (item, row) of a pre-activation
 // block, computed once before the output map reads it from every row tile.
 template <typename T>
@@ -259,11 +825,11 @@ __global__ __launch_bounds__(256) void k_activate(const T* pre, T* act, int rows
     if (idx >= items * rows) return;
     const int item = idx / rows, m = idx - item * rows;
     const T* src = pre + ((size_t)item * rows_pad + m) * nc;
-    T* dst = act + ((size_t)item * rows_pad + m) * nc;
+    T* dst = act + (size_t)item * nc * rows_pad + m;   // (nc x rows_pad) per item
     const T av = src[0];
     const T d = T(elu1(av));
     dst[0] = elu0(av);
-    for (int c = 1; c < nc; ++c) dst[c] = d * src[c];
+    for (int c = 1; c < nc; ++c) dst[(size_t)c * rows_pad] = d * src[c];
 }
 
 hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
@@ -408,9 +974,10 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     const int bidx = a.imap ? a.imap[item] : item;
     const T mu = (T)a.mu, lam = (T)a.lam;
 
-    double Hc[RP];
+    double Hc[RP];  // column layout: lane (tet, k) holds H[0..r)[k] (VALU path)
 #pragma unroll
     for (int j = 0; j < RP; ++j) Hc[j] = 0.0;
+    double Hm[4] = {0.0, 0.0, 0.0, 0.0}; // MFMA result layout (RP == 16 path)
     double gk = 0.0, Ee = 0.0;
 
     const int span = 9 * nc;                 // values per tet
@@ -442,6 +1009,47 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         if (rd + 1 < rounds) prefetch(rd + 1);
         const int el = wave * EPW + eg;
         const int s = rd * EPR + el;
+        if constexpr (RP == 16) {
+            // Gauss-Newton block on the matrix cores: lanes (tet eg, column k)
+            // hold K_e[v][k] and wV (A K_e)[v][k], exactly the A / B operands of
+            // a 16x16x4 MFMA whose 4-deep reduction runs over the wave's 4 tets.
+            T Kc[9], AK[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) {
+                Kc[v] = T(0);
+                AK[v] = T(0);
+            }
+            if (s < a.S) {
+                const T* row = tile + el * span;
+                T gu[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    gu[v] = row[v * nc];
+                    Kc[v] = kact ? row[v * nc + 1 + k] : T(0);
+                }
+                Snh<T> m;
+                m.set(gu, mu, lam);
+                T P[9];
+                m.pk1(mu, lam, P);
+                m.apply_hess(mu, lam, Kc, AK);
+                const double wV = a.wV[s];
+                T gp = 0;
+#pragma unroll
+                for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
+                gk += wV * (double)gp;
+                if (k == 0) Ee += wV * (double)m.psi;
+                if (dseed)
+                    for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+                const T wt = (T)wV;
+#pragma unroll
+                for (int v = 0; v < 9; ++v) AK[v] *= wt;
+            }
+            typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
+#pragma unroll
+            for (int v = 0; v < 9; ++v) hacc = Mfma<T>::mac(Kc[v], AK[v], hacc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
+        } else {
         if (s < a.S) {
             const T* row = tile + el * span;
             T gu[9], Kc[9];
@@ -473,6 +1081,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             if (dseed)
                 for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
         }
+        }
     }
 
     const bool ext = !a.elastic_only;
@@ -494,14 +1103,24 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 Kp[wave][eg][c][k] = Jc[c];
             }
             __syncthreads();
+            if constexpr (RP == 16) {
+                typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
+                const T kt = (T)kc;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hacc = Mfma<T>::mac(Jc[c], kt * Jc[c], hacc);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
+            }
             if (ok) {
+                if constexpr (RP != 16) {
 #pragma unroll
-                for (int j = 0; j < RP; ++j) {
-                    if (j < r) {
-                        T h = 0;
+                    for (int j = 0; j < RP; ++j) {
+                        if (j < r) {
+                            T h = 0;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) h += Kp[wave][eg][c][j] * Jc[c];
-                        Hc[j] += kc * (double)h;
+                            for (int c = 0; c < 3; ++c) h += Kp[wave][eg][c][j] * Jc[c];
+                            Hc[j] += kc * (double)h;
+                        }
                     }
                 }
                 gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
@@ -544,14 +1163,21 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     // reduce over the EPW tets of a wave (lanes k, k+RP, ...) then over waves
 #pragma unroll
     for (int off = RP; off < 64; off <<= 1) {
+        if constexpr (RP != 16) {
 #pragma unroll
-        for (int j = 0; j < RP; ++j) Hc[j] += __shfl_xor(Hc[j], off);
+            for (int j = 0; j < RP; ++j) Hc[j] += __shfl_xor(Hc[j], off);
+        }
         gk += __shfl_xor(gk, off);
         Ee += __shfl_xor(Ee, off);
     }
-    if (eg == 0) {
+    if constexpr (RP == 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) redH[wave][Mfma<T>::row(lane, q)][lane & 15] = Hm[q];
+    } else if (eg == 0) {
 #pragma unroll
         for (int j = 0; j < RP; ++j) redH[wave][j][k] = Hc[j];
+    }
+    if (eg == 0) {
         redg[wave][k] = gk;
         if (k == 0) redE[wave] = Ee;
     }
@@ -568,7 +1194,8 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
-    const int rp = a.r <= 4 ? 4 : a.r <= 8 ? 8 : a.r <= 16 ? 16 : 32;
+    // r <= 16: the MFMA path (16 columns per tet); r <= 32: 32 lanes per tet (VALU)
+    const int rp = a.r <= 16 ? 16 : 32;
     // one round's tile must fit the staging buffer and the prefetch registers
     if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
     dim3 grid(items), block(256);
