@@ -1506,6 +1506,103 @@ hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, i
     return hipGetLastError();
 }
 
+// Parallel Jacobi eigen-decomposition of a symmetric n2 x n2 matrix (n2 even,
+// n2 <= 16) held in registers of one wave (Brent-Luk layout).  The indices are
+// paired by slot: slot k pairs (t_k, b_k), and one step rotates all n2/2 pairs
+// at once.  Lane (I, J) = (lane / 8, lane % 8) holds the 2x2 block of rows
+// {t_I, b_I} and columns {t_J, b_J} of the matrix, and of V the rows
+// {2I, 2I+1} (fixed coordinates) and columns {t_J, b_J}.  After each step the
+// indices move one slot along the circle t_1 -> t_2 -> ... -> t_{m-1} ->
+// b_{m-1} -> ... -> b_0 -> t_1 (t_0 stays), the round-robin order in which all
+// pairs meet once per n2 - 1 steps; a row moves only between lanes I +- 1 and a
+// column only between lanes J +- 1.  On return Hs[k][k] holds the eigenvalue of
+// slot k and column k of Vs its eigenvector (k < n2).  Rows and columns >= r
+// are zero (a dummy index when r is odd: its rotations are the identity).
+__device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], int r, int n2, int tid)
+{
+    const int m = n2 / 2;
+    const int I = tid >> 3, J = tid & 7;
+    const bool act = I < m && J < m;
+    auto hget = [&](int a, int b) { return (act && a < r && b < r) ? Hs[a][b] : 0.0; };
+    double htt = hget(2 * I, 2 * J), htb = hget(2 * I, 2 * J + 1);
+    double hbt = hget(2 * I + 1, 2 * J), hbb = hget(2 * I + 1, 2 * J + 1);
+    double v00 = (act && I == J) ? 1.0 : 0.0, v01 = 0.0, v10 = 0.0, v11 = v00;
+    const int dI = I * 9, dJ = J * 9; // lanes of the diagonal blocks (I, I) and (J, J)
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double tot = act ? htt * htt + htb * htb + hbt * hbt + hbb * hbb : 0.0;
+        double off = (I == J) ? (act ? htb * htb + hbt * hbt : 0.0) : tot;
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            tot += __shfl_xor(tot, o);
+        }
+        off = __shfl(off, 0); // one decision for the whole wave
+        tot = __shfl(tot, 0);
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int step = 0; step < n2 - 1; ++step) {
+            double c = 1.0, sn = 0.0;
+            if (I == J && htb != 0.0) {
+                const double theta = (hbb - htt) / (2.0 * htb);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                c = 1.0 / sqrt(t * t + 1.0);
+                sn = t * c;
+            }
+            const double cI = __shfl(c, dI), sI = __shfl(sn, dI);
+            const double cJ = __shfl(c, dJ), sJ = __shfl(sn, dJ);
+            // rows: [t; b] <- [[c, -s], [s, c]] [t; b] with slot I's rotation
+            const double rt0 = cI * htt - sI * hbt, rt1 = cI * htb - sI * hbb;
+            const double rb0 = sI * htt + cI * hbt, rb1 = sI * htb + cI * hbb;
+            // columns (and V's columns) with slot J's rotation
+            htt = cJ * rt0 - sJ * rt1;
+            htb = sJ * rt0 + cJ * rt1;
+            hbt = cJ * rb0 - sJ * rb1;
+            hbb = sJ * rb0 + cJ * rb1;
+            if (I == J) htb = hbt = 0.0; // the annihilated pair
+            {
+                const double a0 = cJ * v00 - sJ * v01, a1 = sJ * v00 + cJ * v01;
+                const double b0 = cJ * v10 - sJ * v11, b1 = sJ * v10 + cJ * v11;
+                v00 = a0; v01 = a1; v10 = b0; v11 = b1;
+            }
+            if (m == 1) continue;
+            // move the rows: new t_I <- old t_{I-1} (I >= 2) or old b_0 (I == 1);
+            // new b_I <- old b_{I+1} (I < m-1) or old t_{m-1} (I == m-1)
+            {
+                const double d0 = (I == 0) ? hbt : htt, d1 = (I == 0) ? hbb : htb;
+                const double up0 = __shfl(d0, tid - 8), up1 = __shfl(d1, tid - 8);
+                const double dn0 = __shfl(hbt, tid + 8), dn1 = __shfl(hbb, tid + 8);
+                const double nb0 = (I == m - 1) ? htt : dn0, nb1 = (I == m - 1) ? htb : dn1;
+                if (I != 0) { htt = up0; htb = up1; }
+                hbt = nb0; hbb = nb1;
+            }
+            // move the columns the same way along J (H and V)
+            {
+                const double d0 = (J == 0) ? htb : htt, d1 = (J == 0) ? hbb : hbt;
+                const double e0 = (J == 0) ? v01 : v00, e1 = (J == 0) ? v11 : v10;
+                const double lf0 = __shfl(d0, tid - 1), lf1 = __shfl(d1, tid - 1);
+                const double lv0 = __shfl(e0, tid - 1), lv1 = __shfl(e1, tid - 1);
+                const double rt_0 = __shfl(htb, tid + 1), rt_1 = __shfl(hbb, tid + 1);
+                const double rv0 = __shfl(v01, tid + 1), rv1 = __shfl(v11, tid + 1);
+                const bool last = (J == m - 1);
+                const double nb0 = last ? htt : rt_0, nb1 = last ? hbt : rt_1;
+                const double nv0 = last ? v00 : rv0, nv1 = last ? v10 : rv1;
+                if (J != 0) { htt = lf0; hbt = lf1; v00 = lv0; v10 = lv1; }
+                htb = nb0; hbb = nb1; v01 = nv0; v11 = nv1;
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {
+        if (I == J) {
+            Hs[2 * J][2 * J] = htt;
+            Hs[2 * J + 1][2 * J + 1] = hbb;
+        }
+        Vs[2 * I][2 * J] = v00;
+        Vs[2 * I][2 * J + 1] = v01;
+        Vs[2 * I + 1][2 * J] = v10;
+        Vs[2 * I + 1][2 * J + 1] = v11;
+    }
+    __syncthreads();
+}
+
 // Exit tests and the Newton direction of one item per 64-thread workgroup:
 // Cholesky of the symmetrised Hessian if it is positive definite, else a
 // Jacobi eigen-decomposition (parallel ordering: the r/2 disjoint rotations
@@ -1605,82 +1702,88 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
         if (tid == 0) st.status[item] = RS_NOT_DESCENT;
         return;
     } else {
-        for (int q = tid; q < r * r; q += 64) {
-            const int a = q / r, b = q - a * r;
-            Vs[a][b] = (a == b) ? 1.0 : 0.0;
-        }
         const int n2 = (r + 1) & ~1; // players of the round-robin (one dummy if r is odd)
-        const int P = n2 / 2;
-        for (int sweep = 0; sweep < 40; ++sweep) {
-            __syncthreads();
-            double off = 0.0, tot = 0.0;
+        int ns = r;                  // eigen slots
+        if (n2 <= 16) {
+            jacobi_wave(Hs, Vs, r, n2, tid);
+            ns = n2;
+        } else {
             for (int q = tid; q < r * r; q += 64) {
                 const int a = q / r, b = q - a * r;
-                const double h2 = Hs[a][b] * Hs[a][b];
-                tot += h2;
-                if (a != b) off += h2;
+                Vs[a][b] = (a == b) ? 1.0 : 0.0;
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                off += __shfl_xor(off, o);
-                tot += __shfl_xor(tot, o);
-            }
-            // lane 0 decides for the whole wave (barriers follow)
-            off = __shfl(off, 0);
-            tot = __shfl(tot, 0);
-            if (off <= 1e-30 * tot || off == 0.0) break;
-            for (int step = 0; step < n2 - 1; ++step) {
-                if (tid < P) {
-                    const int m1 = tid, m2 = n2 - 1 - tid;
-                    const int a = m1 == 0 ? 0 : ((m1 - 1 + step) % (n2 - 1)) + 1;
-                    const int b = ((m2 - 1 + step) % (n2 - 1)) + 1;
-                    const int pp = a < b ? a : b, qq = a < b ? b : a;
-                    double c = 1.0, sn = 0.0;
-                    if (qq < r) {
-                        const double apq = Hs[pp][qq];
-                        if (apq != 0.0) {
-                            const double theta = (Hs[qq][qq] - Hs[pp][pp]) / (2.0 * apq);
-                            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                            c = 1.0 / sqrt(t * t + 1.0);
-                            sn = t * c;
+            const int P = n2 / 2;
+            for (int sweep = 0; sweep < 40; ++sweep) {
+                __syncthreads();
+                double off = 0.0, tot = 0.0;
+                for (int q = tid; q < r * r; q += 64) {
+                    const int a = q / r, b = q - a * r;
+                    const double h2 = Hs[a][b] * Hs[a][b];
+                    tot += h2;
+                    if (a != b) off += h2;
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    off += __shfl_xor(off, o);
+                    tot += __shfl_xor(tot, o);
+                }
+                // lane 0 decides for the whole wave (barriers follow)
+                off = __shfl(off, 0);
+                tot = __shfl(tot, 0);
+                if (off <= 1e-30 * tot || off == 0.0) break;
+                for (int step = 0; step < n2 - 1; ++step) {
+                    if (tid < P) {
+                        const int m1 = tid, m2 = n2 - 1 - tid;
+                        const int a = m1 == 0 ? 0 : ((m1 - 1 + step) % (n2 - 1)) + 1;
+                        const int b = ((m2 - 1 + step) % (n2 - 1)) + 1;
+                        const int pp = a < b ? a : b, qq = a < b ? b : a;
+                        double c = 1.0, sn = 0.0;
+                        if (qq < r) {
+                            const double apq = Hs[pp][qq];
+                            if (apq != 0.0) {
+                                const double theta = (Hs[qq][qq] - Hs[pp][pp]) / (2.0 * apq);
+                                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                                c = 1.0 / sqrt(t * t + 1.0);
+                                sn = t * c;
+                            }
                         }
+                        rp[tid] = pp;
+                        rq[tid] = qq;
+                        rc[tid] = c;
+                        rs_[tid] = sn;
                     }
-                    rp[tid] = pp;
-                    rq[tid] = qq;
-                    rc[tid] = c;
-                    rs_[tid] = sn;
+                    __syncthreads();
+                    for (int w = tid; w < P * r; w += 64) { // rows p, q
+                        const int pr = w / r, col = w - pr * r;
+                        const int pp = rp[pr], qq = rq[pr];
+                        if (qq >= r) continue;
+                        const double c = rc[pr], sn = rs_[pr];
+                        const double apk = Hs[pp][col], aqk = Hs[qq][col];
+                        Hs[pp][col] = c * apk - sn * aqk;
+                        Hs[qq][col] = sn * apk + c * aqk;
+                    }
+                    __syncthreads();
+                    for (int w = tid; w < P * r; w += 64) { // columns p, q and eigenvectors
+                        const int pr = w / r, row = w - pr * r;
+                        const int pp = rp[pr], qq = rq[pr];
+                        if (qq >= r) continue;
+                        const double c = rc[pr], sn = rs_[pr];
+                        const double akp = Hs[row][pp], akq = Hs[row][qq];
+                        Hs[row][pp] = c * akp - sn * akq;
+                        Hs[row][qq] = sn * akp + c * akq;
+                        const double vkp = Vs[row][pp], vkq = Vs[row][qq];
+                        Vs[row][pp] = c * vkp - sn * vkq;
+                        Vs[row][qq] = sn * vkp + c * vkq;
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-                for (int w = tid; w < P * r; w += 64) { // rows p, q
-                    const int pr = w / r, col = w - pr * r;
-                    const int pp = rp[pr], qq = rq[pr];
-                    if (qq >= r) continue;
-                    const double c = rc[pr], sn = rs_[pr];
-                    const double apk = Hs[pp][col], aqk = Hs[qq][col];
-                    Hs[pp][col] = c * apk - sn * aqk;
-                    Hs[qq][col] = sn * apk + c * aqk;
-                }
-                __syncthreads();
-                for (int w = tid; w < P * r; w += 64) { // columns p, q and eigenvectors
-                    const int pr = w / r, row = w - pr * r;
-                    const int pp = rp[pr], qq = rq[pr];
-                    if (qq >= r) continue;
-                    const double c = rc[pr], sn = rs_[pr];
-                    const double akp = Hs[row][pp], akq = Hs[row][qq];
-                    Hs[row][pp] = c * akp - sn * akq;
-                    Hs[row][qq] = sn * akp + c * akq;
-                    const double vkp = Vs[row][pp], vkq = Vs[row][qq];
-                    Vs[row][pp] = c * vkp - sn * vkq;
-                    Vs[row][qq] = sn * vkp + c * vkq;
-                }
-                __syncthreads();
             }
         }
         __syncthreads();
         if (tid == 0) {
             double lmax = 0.0;
-            for (int k = 0; k < r; ++k) lmax = fmax(lmax, fabs(Hs[k][k]));
+            for (int k = 0; k < ns; ++k) lmax = fmax(lmax, fabs(Hs[k][k]));
             const double fl = p.eig_floor * lmax;
-            for (int k = 0; k < r; ++k) {
+            for (int k = 0; k < ns; ++k) {
                 double lk = (p.proj == RS_PROJ_ABS) ? fabs(Hs[k][k]) : Hs[k][k];
                 if (lk < fl) lk = fl;
                 if (!(lk > 0.0)) lk = 1.0;
@@ -1688,7 +1791,7 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
             }
         }
         __syncthreads();
-        if (tid < r) {
+        if (tid < ns) {
             double c = 0.0;
             for (int a = 0; a < r; ++a) c += Vs[a][tid] * gs[a];
             cs[tid] = c / lam[tid];
@@ -1696,7 +1799,7 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
         __syncthreads();
         if (tid < r) {
             double d = 0.0;
-            for (int k = 0; k < r; ++k) d -= Vs[tid][k] * cs[k];
+            for (int k = 0; k < ns; ++k) d -= Vs[tid][k] * cs[k];
             dzs[tid] = d;
         }
         __syncthreads();

@@ -215,6 +215,39 @@ def test_newton_gauss_newton_and_abs_projection():
         assert relerr(r["E"][:, None], ores["E"][:, None], tau=1e-6 * energy_scale(p)).max() < 1e-9
 
 
+@pytest.mark.parametrize("r", [5, 7, 16, 20])
+def test_newton_projection_across_latent_sizes(r):
+    """Indefinite starts force the eigen-projection: odd r (the round-robin gets
+    a dummy index), the register-resident Jacobi (r <= 16) and the LDS one (r > 16)."""
+    # hidden layers wider than r and 36 free DOFs keep the reduced Hessian well posed
+    p = I.make_problem(f"proj{r}", 3, 1, 1, r, [32, 32], 16, bend=True, bias_scale=0.3)
+    o = O.Oracle(p)
+    rng = np.random.default_rng(17 + r)
+    Z = rng.normal(scale=1.5, size=(64, r))
+    tg, fo = I.loads_for(p, 64)
+    H = o.reduced(Z, tg, fo)[2]
+    indef = [b for b in range(64) if np.linalg.eigvalsh(0.5 * (H[b] + H[b].T)).min() < 0][:4]
+    assert len(indef) >= 2
+    sel = np.array(indef)
+    z0 = Z[sel]
+    tgs = None if tg is None else tg[sel]
+    fos = None if fo is None else fo[sel]
+    # the projected Newton steps themselves (the eigen-decompositions differ
+    # only by rounding, so the first iterates agree to rounding)
+    for k in (1, 3):
+        r_, ores, _ = _compare_newton(p, rb.PREC_F64, z0, tgs, fos, dict(max_iter=k))
+        assert np.array_equal(r_["status"], ores["status"])
+        assert np.array_equal(r_["iters"], ores["iters"])
+        assert relerr(r_["z"], ores["z"]).max() < 1e-9
+    # whole solves: a trajectory that wanders through indefinite regions for
+    # tens of steps amplifies rounding, so judge the end point by stationarity
+    r_, ores, o = _compare_newton(p, rb.PREC_F64, z0, tgs, fos, dict(max_iter=200))
+    assert np.all(r_["status"] == rb.CONVERGED)
+    g0 = np.abs(o.reduced(z0, tgs, fos)[1]).max(axis=1)
+    gg = o.reduced(r_["z"], tgs, fos)[1]
+    assert np.all(np.abs(gg).max(axis=1) <= 2e-6 * g0)
+
+
 def test_identity_decoder_linear_path():
     """No hidden layer (a linear decoder selecting every free DOF, r = 24)."""
     p = I.make_problem("ident", 2, 1, 1, 1, [], 10 ** 9)
