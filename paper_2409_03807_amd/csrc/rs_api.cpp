@@ -102,6 +102,7 @@ struct rs_ctx {
     double* ell = nullptr;        // max_batch
     double* lacc = nullptr;       // 3
     int* hcount = nullptr;        // pinned host
+    int* hcount_dev = nullptr;    // device address of hcount
     hipEvent_t cnt_ev[2] = {nullptr, nullptr}; // running-count copies, one per parity of the super-step
 
     std::string err;
@@ -529,8 +530,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->ell = (double*)need(dalloc<double>(c, B));
     c->lacc = (double*)need(dalloc<double>(c, 4));
     if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
-    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocMapped) != hipSuccess)
         return bail(fail(c, RS_ERR_OOM, "pinned host allocation failed"));
+    c->hcount[0] = c->hcount[1] = 0;
+    if (hipHostGetDevicePointer((void**)&c->hcount_dev, c->hcount, 0) != hipSuccess)
+        return bail(fail(c, RS_ERR_HIP, "hipHostGetDevicePointer"));
     for (int k = 0; k < 2; ++k)
         if (hipEventCreateWithFlags(&c->cnt_ev[k], hipEventDisableTiming) != hipSuccess)
             return bail(fail(c, RS_ERR_HIP, "hipEventCreate"));
@@ -948,16 +952,6 @@ static int log_counters(rs_ctx* c, hipStream_t s)
     return RS_OK;
 }
 
-static int read_counter(rs_ctx* c, int idx, hipStream_t s, int* out)
-{
-    hipError_t e = hipMemcpyAsync(c->hcount + idx, c->counters + idx, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-    *out = c->hcount[idx];
-    return RS_OK;
-}
-
 extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
                                int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
 {
@@ -1034,15 +1028,15 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
                           K_LS_GEMM_OUT));
         RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
                    [&] { return launch_armijo(st, p, n_run, s); }));
-        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_count_running(st, B, s); }));
         const int par = (int)(step & 1);
-        hipError_t e = hipMemcpyAsync(c->hcount + par, cnt + 3, sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipEventRecord(c->cnt_ev[par], s);
+        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_count_running(st, B, c->hcount_dev + par, s); }));
+        // the event's system-scope release makes the kernel's store to host memory visible
+        hipError_t e = hipEventRecord(c->cnt_ev[par], s);
         if (e != hipSuccess) return hip_fail(c, e, "running-count copy");
         if (step == 0) continue;
         e = hipEventSynchronize(c->cnt_ev[par ^ 1]);
         if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-        const int prev = c->hcount[par ^ 1];  // running after step - 1
+        const int prev = *(volatile int*)(c->hcount + (par ^ 1)); // running after step - 1
         if (prev == 0) {
             n_run = 0;
             break;
@@ -1053,7 +1047,7 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
         // the bound was reached: settle the last count
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-        n_run = std::min(c->hcount[0], c->hcount[1]);
+        n_run = std::min(*(volatile int*)c->hcount, *(volatile int*)(c->hcount + 1));
     }
     c->cur_slot = -1;
     if (n_run > 0) return fail(c, RS_ERR_STATE, "Newton loop did not terminate");

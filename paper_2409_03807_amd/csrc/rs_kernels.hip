@@ -59,9 +59,12 @@ template <> struct Mfma<double> {
     __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
+// 16-byte vectors as clang native vectors (element access stays in registers)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec16<float> { using type = f32x4; static constexpr int n = 4; };
+template <> struct Vec16<double> { using type = f64x2; static constexpr int n = 2; };
 
 // ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
 __device__ inline float elu0(float a) { return a > 0.f ? a : expm1f(a); }
@@ -170,9 +173,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 #pragma unroll
             for (int q = 0; q < 8 / VN; ++q) {
                 V w;
-                T* wp = reinterpret_cast<T*>(&w);
 #pragma unroll
-                for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+                for (int e = 0; e < VN; ++e) w[e] = ry[q * VN + e];
                 dy[q] = w;
             }
         }
@@ -184,9 +186,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 #pragma unroll
             for (int q = 0; q < 8 / VN; ++q) {
                 const V w = sa[q];
-                const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                for (int e = 0; e < VN; ++e) af[q * VN + e] = wp[e];
+                for (int e = 0; e < VN; ++e) af[q * VN + e] = w[e];
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -194,9 +195,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 #pragma unroll
                 for (int q = 0; q < 8 / VN; ++q) {
                     const V w = sb[q];
-                    const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
                 }
             }
         }
@@ -267,9 +267,8 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 #pragma unroll
             for (int q = 0; q < 8 / VN; ++q) {
                 const V w = src[q];
-                const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = wp[e];
+                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = w[e];
             }
         }
     }
@@ -299,9 +298,8 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 #pragma unroll
                     for (int q = 0; q < 8 / VN; ++q) {
                         const V w = v8[q];
-                        const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                        for (int e = 0; e < VN; ++e) ry[q * VN + e] = wp[e];
+                        for (int e = 0; e < VN; ++e) ry[q * VN + e] = w[e];
                     }
                 } else {
 #pragma unroll
@@ -321,9 +319,8 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 #pragma unroll
         for (int q = 0; q < 8 / VN; ++q) {
             V w;
-            T* wp = reinterpret_cast<T*>(&w);
 #pragma unroll
-            for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+            for (int e = 0; e < VN; ++e) w[e] = ry[q * VN + e];
             dy[q] = w;
         }
     };
@@ -355,9 +352,8 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 #pragma unroll
                 for (int q = 0; q < 8 / VN; ++q) {
                     const V w = sb[q];
-                    const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
                 }
             }
 #pragma unroll
@@ -440,9 +436,8 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 #pragma unroll
             for (int q = 0; q < 8 / VN; ++q) {
                 const V w = src[q];
-                const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = wp[e];
+                for (int e = 0; e < VN; ++e) af[c][q * VN + e] = w[e];
             }
         }
     }
@@ -478,9 +473,8 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 #pragma unroll
                 for (int q = 0; q < PER / VN; ++q) {
                     const V w = vp[q];
-                    const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) ry[q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) ry[q * VN + e] = w[e];
                 }
             }
         }
@@ -490,9 +484,8 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 #pragma unroll
         for (int q = 0; q < PER / VN; ++q) {
             V w;
-            T* wp = reinterpret_cast<T*>(&w);
 #pragma unroll
-            for (int e = 0; e < VN; ++e) wp[e] = ry[q * VN + e];
+            for (int e = 0; e < VN; ++e) w[e] = ry[q * VN + e];
             dy[q] = w;
         }
     };
@@ -516,9 +509,8 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 #pragma unroll
                 for (int q = 0; q < 8 / VN; ++q) {
                     const V w = sb[q];
-                    const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
                 }
             }
 #pragma unroll
@@ -713,9 +705,8 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
             for (int i = 0; i < RT; ++i)
 #pragma unroll
                 for (int q = 0; q < 8 / VN; ++q) {
-                    const T* wp = reinterpret_cast<const T*>(&wa[i][q]);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) af[i][q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) af[i][q * VN + e] = wa[i][q][e];
                 }
             if (k0 + kTileK < kp) loadw(k0 + kTileK);
             T bf[CT][8];
@@ -725,9 +716,8 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
 #pragma unroll
                 for (int q = 0; q < 8 / VN; ++q) {
                     const V w = sb[q];
-                    const T* wp = reinterpret_cast<const T*>(&w);
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = wp[e];
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
                 }
             }
             // k-step outermost: RT*CT independent accumulators between dependent MFMAs
@@ -1038,8 +1028,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
                 gk += wV * (double)gp;
                 if (k == 0) Ee += wV * (double)m.psi;
-                if (dseed)
-                    for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+                if (dseed) {
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) // lane k writes v = k (mod RP); v static keeps P in registers
+                        if (v % RP == k) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+                }
                 const T wt = (T)wV;
 #pragma unroll
                 for (int v = 0; v < 9; ++v) AK[v] *= wt;
@@ -1078,8 +1071,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
             gk += wV * (double)gp;
             if (k == 0) Ee += wV * (double)m.psi;
-            if (dseed)
-                for (int v = k; v < 9; v += RP) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+            if (dseed) {
+#pragma unroll
+                for (int v = 0; v < 9; ++v)
+                    if (v % RP == k) dseed[9 * s + v] = (T)(wV * (double)P[v]);
+            }
         }
         }
     }
@@ -1125,8 +1121,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 }
                 gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
                 if (k == 0) Ee += 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                if (dseed)
-                    for (int c = k; c < 3; c += RP) dseed[prow + 3 * t + c] = (T)(kc * d[c]);
+                if (dseed) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (c % RP == k) dseed[prow + 3 * t + c] = (T)(kc * d[c]);
+                }
             }
             __syncthreads();
         }
@@ -1884,7 +1883,8 @@ hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, 
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B)
+// Items still running; also stored to `host` (mapped pinned memory, may be NULL).
+__global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B, int* host)
 {
     __shared__ int sc[1024];
     int n = 0;
@@ -1895,12 +1895,15 @@ __global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B)
         if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) st.counters[3] = sc[0];
+    if (threadIdx.x == 0) {
+        st.counters[3] = sc[0];
+        if (host) *host = sc[0];
+    }
 }
 
-hipError_t launch_count_running(const NewtonState& st, int B, hipStream_t s)
+hipError_t launch_count_running(const NewtonState& st, int B, int* host, hipStream_t s)
 {
-    RS_LAUNCH(k_count_running, dim3(1), dim3(1024), 0, s, st, B);
+    RS_LAUNCH(k_count_running, dim3(1), dim3(1024), 0, s, st, B, host);
     return hipGetLastError();
 }
 
