@@ -52,6 +52,30 @@ def recorded_traffic(kind, workload):
     return None
 
 
+# the bound of each launch kind: contractions on the matrix cores, the r x r
+# solves on the float64 vector ALUs, everything else on HBM bandwidth
+MFMA_KINDS = {"gemm_hidden", "gemm_out", "gemm_adjoint", "decode_hidden", "decode_out"}
+MFMA_F64_KINDS = {"ls_gemm_hidden", "ls_gemm_out"}
+ALU_F64_KINDS = {"newton_dir"}
+VALU_F64_PEAK_TFLOPS = 78.6
+
+
+def kernel_roofline(kind, rec, dtype):
+    """Achieved rate of one launch kind (algorithmic bytes or flops over its
+    summed event-timed duration) against the peak of its bound."""
+    secs = rec["ms"] * 1e-3
+    if kind in MFMA_KINDS or kind in MFMA_F64_KINDS:
+        peak = MFMA_PEAK_TFLOPS["f64" if kind in MFMA_F64_KINDS else dtype]
+        ach = rec["flops"] / secs / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
+    if kind in ALU_F64_KINDS:
+        ach = rec["flops"] / secs / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": VALU_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / VALU_F64_PEAK_TFLOPS}
+    ach = rec["bytes"] / secs / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,21 +179,20 @@ def main():
     roof = None
     if prof:
         kind, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
-        avg_s = rec["ms"] / rec["launches"] * 1e-3
-        if kind.startswith("gemm") or kind.startswith("ls_gemm") or kind.startswith("decode"):
-            peak_dtype = "f64" if kind.startswith("ls_") else dtype
-            ach = rec["flops"] / rec["launches"] / avg_s / 1e12
-            roof = {"bound": "mfma", "achieved": ach, "peak": MFMA_PEAK_TFLOPS[peak_dtype], "unit": "TFLOP/s",
-                    "frac": ach / MFMA_PEAK_TFLOPS[peak_dtype], "traffic": None, "kernel": kind,
-                    "avg_us": avg_s * 1e6, "launches": rec["launches"]}
-        else:
-            ach = rec["bytes"] / rec["launches"] / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": kind,
-                    "avg_us": avg_s * 1e6, "launches": rec["launches"]}
+        roof = kernel_roofline(kind, rec, dtype)
+        roof["kernel"] = kind
+        roof["avg_us"] = rec["ms"] / rec["launches"] * 1e3
+        roof["launches"] = rec["launches"]
         roof["algorithmic_bytes"] = rec["bytes"] / rec["launches"]
+        roof["algorithmic_flops"] = rec["flops"] / rec["launches"]
         roof["traffic"] = recorded_traffic(kind, f"{name}_b{B}")
-        roof["kernels_warm_pass"] = {k: {"ms": round(v["ms"], 3), "launches": v["launches"]} for k, v in warm.items()}
+        # every kind of the profiled warm pass against its own bound
+        roof["kernels_warm_pass"] = {}
+        for k, v in warm.items():
+            kr = kernel_roofline(k, v, dtype)
+            roof["kernels_warm_pass"][k] = {"ms": round(v["ms"], 3), "launches": v["launches"], "bound": kr["bound"],
+                                            "achieved": round(kr["achieved"], 2), "unit": kr["unit"],
+                                            "frac": round(kr["frac"], 4)}
 
     cpu = None
     if args.cpu_sample > 0:

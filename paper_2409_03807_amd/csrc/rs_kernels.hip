@@ -10,6 +10,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <type_traits>
+
 #include <hip/hip_ext.h>
 
 namespace rs {
@@ -930,32 +933,133 @@ struct Snh {
 };
 // ---------------------------------------------------------------------------
 // Element kernel: one workgroup per item, RP lanes per cubature tet (lane k
-// owns column k of K_e = dvecF/dz).  The rows of EPR consecutive tets form one
-// contiguous span of the item's block; it is staged in LDS with 16-byte loads,
-// the next span prefetched into registers while the current one is used.
+// owns column k of K_e = dvecF/dz).  The item's rows are streamed through a
+// three-slot LDS ring by direct global->LDS loads (16 bytes per lane): one
+// round is EPR tets (9 rows each), then EPR penalty targets (3 rows each);
+// two rounds are in flight while one is used.
 // Per tet: F, psi, PK1, (d2psi/dF2) K_e[:,k], H[:,k] += w V K_e^T (A K_e[:,k]),
 // g[k] += w V K_e[:,k].P; then the penalty, gravity and force rows.
 // Contributions are float64-accumulated and reduced in a fixed order.
 // ---------------------------------------------------------------------------
 
 constexpr int kElemTile = 2880;  // max over RP of (tets per round) * 9 * (1 + r) values
-constexpr int kElemPrefetch = 6; // 16-byte vectors per thread per round (f64 worst case)
+
+typedef const void __attribute__((address_space(1)))* gas_ptr;
+typedef void __attribute__((address_space(3)))* las_ptr;
+
+// s_waitcnt: at most N vector-memory operations outstanding and no LDS ones
+template <int N>
+__device__ inline void wait_vm_lgkm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4));
+}
+
+// LDS reads and writes of the element ring in inline asm.  The compiler
+// conservatively waits for every direct global->LDS load in flight before any
+// LDS access it sees; these blocks are invisible to that analysis, so reading
+// one ring slot does not wait for the loads filling the other two.  Each block
+// waits for its own LDS operations before it ends (its results are complete
+// when it returns); the ring's explicit vmcnt wait and barrier order them
+// against the direct loads.
+__device__ inline unsigned lds_addr(const void* p)
+{
+    return static_cast<unsigned>(reinterpret_cast<uintptr_t>((las_ptr)(const_cast<void*>(p))));
+}
+
+template <typename T>
+__device__ inline void lds_read9(const T* p, int stride, T (&o)[9])
+{
+    const unsigned st = (unsigned)(stride * (int)sizeof(T));
+    const unsigned a0 = lds_addr(p), a1 = a0 + st, a2 = a1 + st, a3 = a2 + st, a4 = a3 + st, a5 = a4 + st,
+                   a6 = a5 + st, a7 = a6 + st, a8 = a7 + st;
+    if constexpr (sizeof(T) == 4) {
+        asm volatile("ds_read_b32 %0, %9\n\tds_read_b32 %1, %10\n\tds_read_b32 %2, %11\n\t"
+                     "ds_read_b32 %3, %12\n\tds_read_b32 %4, %13\n\tds_read_b32 %5, %14\n\t"
+                     "ds_read_b32 %6, %15\n\tds_read_b32 %7, %16\n\tds_read_b32 %8, %17\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]),
+                       "=&v"(o[7]), "=&v"(o[8])
+                     : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7), "v"(a8)
+                     : "memory");
+    } else {
+        asm volatile("ds_read_b64 %0, %9\n\tds_read_b64 %1, %10\n\tds_read_b64 %2, %11\n\t"
+                     "ds_read_b64 %3, %12\n\tds_read_b64 %4, %13\n\tds_read_b64 %5, %14\n\t"
+                     "ds_read_b64 %6, %15\n\tds_read_b64 %7, %16\n\tds_read_b64 %8, %17\n\t"
+                     "s_waitcnt lgkmcnt(0)"
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]),
+                       "=&v"(o[7]), "=&v"(o[8])
+                     : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7), "v"(a8)
+                     : "memory");
+    }
+}
+
+template <typename T>
+__device__ inline void lds_read3(const T* p, int stride, T (&o)[3])
+{
+    const unsigned st = (unsigned)(stride * (int)sizeof(T));
+    const unsigned a0 = lds_addr(p), a1 = a0 + st, a2 = a1 + st;
+    if constexpr (sizeof(T) == 4)
+        asm volatile("ds_read_b32 %0, %3\n\tds_read_b32 %1, %4\n\tds_read_b32 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2])
+                     : "v"(a0), "v"(a1), "v"(a2)
+                     : "memory");
+    else
+        asm volatile("ds_read_b64 %0, %3\n\tds_read_b64 %1, %4\n\tds_read_b64 %2, %5\n\ts_waitcnt lgkmcnt(0)"
+                     : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2])
+                     : "v"(a0), "v"(a1), "v"(a2)
+                     : "memory");
+}
+
+__device__ inline double lds_read_f64(const double* p)
+{
+    double o;
+    asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(o) : "v"(lds_addr(p)) : "memory");
+    return o;
+}
+
+// Global store of one value in inline asm (a plain vector store).  Inside
+// the element ring these keep the compiler's view of outstanding vector-memory
+// operations to loads only, so that its own waits count exactly instead of
+// falling back to waiting for everything (which would drain the ring).
+template <typename T>
+__device__ inline void global_store_asm(T* p, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        asm volatile("global_store_dword %0, %1, off" : : "v"(p), "v"(v) : "memory");
+    else
+        asm volatile("global_store_dwordx2 %0, %1, off" : : "v"(p), "v"(v) : "memory");
+}
+
+template <typename T>
+struct ElemRing {
+    static constexpr int VN = 16 / (int)sizeof(T);
+    // direct loads per wave per round: the slot holds a round plus the
+    // misalignment of its first value
+    static constexpr int NI = (kElemTile + VN + 256 * VN - 1) / (256 * VN);
+    static constexpr int SLOT = 256 * NI * VN; // values per slot
+};
 
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 {
-    constexpr int EPW = 64 / RP;   // tets per wave per round
-    constexpr int EPR = 4 * EPW;   // tets per round
-    using V = typename Vec16<T>::type;
-    constexpr int VN = Vec16<T>::n;
-    __shared__ __align__(16) T tile[kElemTile];
-    __shared__ T Kp[4][EPW][3][RP];
-    __shared__ double redH[4][RP][RP];
-    __shared__ double redg[4][RP];
-    __shared__ double redE[4];
+    constexpr int EPW = 64 / RP;   // tets (or targets) per wave per round
+    constexpr int EPR = 4 * EPW;   // per round
+    constexpr int VN = ElemRing<T>::VN;
+    constexpr int NI = ElemRing<T>::NI;
+    constexpr int SLOT = ElemRing<T>::SLOT;
+    // side inputs per round: wV of its tets (2 EPR words), or the rest
+    // positions and targets of its targeted vertices (12 EPR words)
+    constexpr int NS = (12 * EPR + 255) / 256; // direct 4-byte loads per wave per round
+    constexpr int SIDEW = 256 * NS;            // words per side slot
+    __shared__ __align__(16) T ring0[SLOT];
+    __shared__ __align__(16) T ring1[SLOT];
+    __shared__ __align__(16) T ring2[SLOT];
+    __shared__ __align__(16) double side0[SIDEW / 2], side1[SIDEW / 2], side2[SIDEW / 2];
     const int item = blockIdx.x;
     if (a.count && item >= *a.count) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int eg = lane / RP, k = lane % RP;
     const int r = a.r, nc = a.nc;
     const bool kact = k < r;
@@ -963,6 +1067,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     T* dseed = a.dseed ? static_cast<T*>(a.dseed) + (size_t)item * a.rows_pad : nullptr;
     const int bidx = a.imap ? a.imap[item] : item;
     const T mu = (T)a.mu, lam = (T)a.lam;
+    const bool ext = !a.elastic_only;
+    const int prow = 9 * a.S;
+    const double* tg = (ext && a.targets) ? a.targets + (size_t)bidx * a.nt * 3 : nullptr;
+    const double kc = a.k_c;
+    const int el = wave * EPW + eg;
 
     double Hc[RP];  // column layout: lane (tet, k) holds H[0..r)[k] (VALU path)
 #pragma unroll
@@ -970,48 +1079,145 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     double Hm[4] = {0.0, 0.0, 0.0, 0.0}; // MFMA result layout (RP == 16 path)
     double gk = 0.0, Ee = 0.0;
 
-    const int span = 9 * nc;                 // values per tet
-    const int rounds = (a.S + EPR - 1) / EPR;
-    V pre[kElemPrefetch];
-    int npre = 0;
-    auto prefetch = [&](int rd) {
-        const int s0 = rd * EPR;
-        const int nt = min(EPR, a.S - s0);
-        const int nvec = (nt * span + VN - 1) / VN; // stays inside the item block (>= 4 spare rows)
-        const V* src = reinterpret_cast<const V*>(O + (size_t)s0 * span);
-        npre = 0;
-#pragma unroll
-        for (int q = 0; q < kElemPrefetch; ++q) {
-            const int vi = tid + 256 * q;
-            if (vi < nvec) pre[q] = src[vi];
+    const int span = 9 * nc;
+    const int tet_rounds = (a.S + EPR - 1) / EPR;
+    const int pen_rounds = tg ? (a.nt + EPR - 1) / EPR : 0;
+    const int rounds = tet_rounds + pen_rounds;
+    // value range [v0, v1) of round rd within the item block
+    auto range = [&](int rd, int& v0, int& v1) {
+        if (rd < tet_rounds) {
+            const int s0 = rd * EPR;
+            v0 = s0 * span;
+            v1 = min(a.S, s0 + EPR) * span;
+        } else {
+            const int t0 = (rd - tet_rounds) * EPR;
+            v0 = (prow + 3 * t0) * nc;
+            v1 = (prow + 3 * min(a.nt, t0 + EPR)) * nc;
         }
-        npre = nvec;
     };
-    if (rounds > 0) prefetch(0);
-    for (int rd = 0; rd < rounds; ++rd) {
-        __syncthreads();
+    auto ring_of = [&](auto sl) -> T* {
+        constexpr int S = decltype(sl)::value;
+        if constexpr (S == 0) return ring0;
+        else if constexpr (S == 1) return ring1;
+        else return ring2;
+    };
+    auto side_of = [&](auto sl) -> double* {
+        constexpr int S = decltype(sl)::value;
+        if constexpr (S == 0) return side0;
+        else if constexpr (S == 1) return side1;
+        else return side2;
+    };
+    // Every wave issues exactly NI direct loads per round (lanes past the
+    // range re-load its first vector into the unused tail of the slot), so the
+    // vmcnt bookkeeping below holds for the ring's own loads.
+    // The side inputs of the round (wV, or rest positions then targets, as
+    // 4-byte words) go to the slot's side area the same way, NS loads per wave.
+    auto issue = [&](auto sl, int rd) {
+        int v0, v1;
+        range(rd, v0, v1);
+        const int a0 = v0 & ~(VN - 1);
+        const int nvec = (v1 - a0 + VN - 1) / VN; // >= 1; the block has >= 4 rows past the penalty rows
+        T* slot = ring_of(sl);
 #pragma unroll
-        for (int q = 0; q < kElemPrefetch; ++q) {
-            const int vi = tid + 256 * q;
-            if (vi < npre) reinterpret_cast<V*>(tile)[vi] = pre[q];
+        for (int i = 0; i < NI; ++i) {
+            const int vb = (wave * NI + i) * 64;
+            const int vi = min(vb + lane, nvec - 1);
+            __builtin_amdgcn_global_load_lds((gas_ptr)(O + a0 + (size_t)vi * VN), (las_ptr)(slot + (size_t)vb * VN),
+                                             16, 0, 0);
         }
-        __syncthreads();
-        if (rd + 1 < rounds) prefetch(rd + 1);
-        const int el = wave * EPW + eg;
-        const int s = rd * EPR + el;
-        if constexpr (RP == 16) {
-            // Gauss-Newton block on the matrix cores: lanes (tet eg, column k)
-            // hold K_e[v][k] and wV (A K_e)[v][k], exactly the A / B operands of
-            // a 16x16x4 MFMA whose 4-deep reduction runs over the wave's 4 tets.
-            T Kc[9], AK[9];
+        if (rd < tet_rounds) {
+            const int s0 = rd * EPR;
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(a.wV);
 #pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                Kc[v] = T(0);
-                AK[v] = T(0);
+            for (int i = 0; i < NS; ++i) {
+                const int wb = (wave * NS + i) * 64;
+                const int j = min(2 * s0 + wb + lane, 2 * a.S - 1);
+                __builtin_amdgcn_global_load_lds((gas_ptr)(w + j), (las_ptr)(reinterpret_cast<uint32_t*>(side_of(sl)) + wb),
+                                                 4, 0, 0);
             }
-            if (s < a.S) {
+        } else {
+            const int t0 = (rd - tet_rounds) * EPR;
+            const uint32_t* xw = reinterpret_cast<const uint32_t*>(a.Xt + 3 * t0);
+            const uint32_t* tw = reinterpret_cast<const uint32_t*>(tg + 3 * t0);
+            const int nw = 6 * (a.nt - t0); // words left in each array
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                const int wb = (wave * NS + i) * 64;
+                const int j = wb + lane;
+                const uint32_t* g = j < 6 * EPR ? xw + min(j, nw - 1) : tw + min(j - 6 * EPR, nw - 1);
+                __builtin_amdgcn_global_load_lds((gas_ptr)g, (las_ptr)(reinterpret_cast<uint32_t*>(side_of(sl)) + wb),
+                                                 4, 0, 0);
+            }
+        }
+    };
+    // one round read from slot SL; round rd + 2 is issued into slot SL + 2
+    auto body = [&](auto sl, int rd) {
+        constexpr int SL = decltype(sl)::value;
+        using NextSlot = std::integral_constant<int, (SL + 2) % 3>;
+        // Round rd has landed once at most NI + NS vector-memory operations
+        // are outstanding: loads complete in order, and round rd + 1's
+        // NI + NS loads were issued after round rd's (the stores in between
+        // can only lower the count).  The barrier then makes every wave's part
+        // visible and frees the slot of round rd - 1.
+        if (rd + 1 < rounds)
+            wait_vm_lgkm<NI + NS>();
+        else
+            wait_vm_lgkm<0>();
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (rd + 2 < rounds) issue(NextSlot{}, rd + 2);
+        int v0, v1;
+        range(rd, v0, v1);
+        const T* tile = ring_of(sl) + (v0 - (v0 & ~(VN - 1)));
+        const double* sd = side_of(sl);
+        if (rd < tet_rounds) {
+            const int s = rd * EPR + el;
+            if constexpr (RP == 16) {
+                // Gauss-Newton block on the matrix cores: lanes (tet eg, column k)
+                // hold K_e[v][k] and wV (A K_e)[v][k], exactly the A / B operands of
+                // a 16x16x4 MFMA whose 4-deep reduction runs over the wave's 4 tets.
+                T Kc[9], AK[9];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    Kc[v] = T(0);
+                    AK[v] = T(0);
+                }
+                if (s < a.S) {
+                    const T* row = tile + el * span;
+                    T gu[9], kr[9];
+                    lds_read9(row, nc, gu);
+                    lds_read9(row + 1 + (kact ? k : 0), nc, kr);
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) Kc[v] = kact ? kr[v] : T(0);
+                    Snh<T> m;
+                    m.set(gu, mu, lam);
+                    T P[9];
+                    m.pk1(mu, lam, P);
+                    m.apply_hess(mu, lam, Kc, AK);
+                    const double wV = lds_read_f64(sd + el);
+                    T gp = 0;
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
+                    gk += wV * (double)gp;
+                    if (k == 0) Ee += wV * (double)m.psi;
+                    if (dseed) {
+#pragma unroll
+                        for (int v = 0; v < 9; ++v) // lane k writes v = k (mod RP); v static keeps P in registers
+                            if (v % RP == k) global_store_asm(dseed + 9 * s + v, (T)(wV * (double)P[v]));
+                    }
+                    const T wt = (T)wV;
+#pragma unroll
+                    for (int v = 0; v < 9; ++v) AK[v] *= wt;
+                }
+                typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
+#pragma unroll
+                for (int v = 0; v < 9; ++v) hacc = Mfma<T>::mac(Kc[v], AK[v], hacc);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
+            } else if (s < a.S) {
                 const T* row = tile + el * span;
-                T gu[9];
+                T gu[9], Kc[9];
 #pragma unroll
                 for (int v = 0; v < 9; ++v) {
                     gu[v] = row[v * nc];
@@ -1019,10 +1225,19 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 }
                 Snh<T> m;
                 m.set(gu, mu, lam);
-                T P[9];
+                T P[9], AK[9];
                 m.pk1(mu, lam, P);
                 m.apply_hess(mu, lam, Kc, AK);
-                const double wV = a.wV[s];
+                const double wV = sd[el];
+#pragma unroll
+                for (int j = 0; j < RP; ++j) {
+                    if (j < r) {
+                        T h = 0;
+#pragma unroll
+                        for (int v = 0; v < 9; ++v) h += row[v * nc + 1 + j] * AK[v];
+                        Hc[j] += wV * (double)h;
+                    }
+                }
                 T gp = 0;
 #pragma unroll
                 for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
@@ -1030,75 +1245,36 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 if (k == 0) Ee += wV * (double)m.psi;
                 if (dseed) {
 #pragma unroll
-                    for (int v = 0; v < 9; ++v) // lane k writes v = k (mod RP); v static keeps P in registers
+                    for (int v = 0; v < 9; ++v)
                         if (v % RP == k) dseed[9 * s + v] = (T)(wV * (double)P[v]);
                 }
-                const T wt = (T)wV;
-#pragma unroll
-                for (int v = 0; v < 9; ++v) AK[v] *= wt;
             }
-            typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
-#pragma unroll
-            for (int v = 0; v < 9; ++v) hacc = Mfma<T>::mac(Kc[v], AK[v], hacc);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
         } else {
-        if (s < a.S) {
-            const T* row = tile + el * span;
-            T gu[9], Kc[9];
-#pragma unroll
-            for (int v = 0; v < 9; ++v) {
-                gu[v] = row[v * nc];
-                Kc[v] = kact ? row[v * nc + 1 + k] : T(0);
-            }
-            Snh<T> m;
-            m.set(gu, mu, lam);
-            T P[9], AK[9];
-            m.pk1(mu, lam, P);
-            m.apply_hess(mu, lam, Kc, AK);
-            const double wV = a.wV[s];
-#pragma unroll
-            for (int j = 0; j < RP; ++j) {
-                if (j < r) {
-                    T h = 0;
-#pragma unroll
-                    for (int v = 0; v < 9; ++v) h += row[v * nc + 1 + j] * AK[v];
-                    Hc[j] += wV * (double)h;
-                }
-            }
-            T gp = 0;
-#pragma unroll
-            for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
-            gk += wV * (double)gp;
-            if (k == 0) Ee += wV * (double)m.psi;
-            if (dseed) {
-#pragma unroll
-                for (int v = 0; v < 9; ++v)
-                    if (v % RP == k) dseed[9 * s + v] = (T)(wV * (double)P[v]);
-            }
-        }
-        }
-    }
-
-    const bool ext = !a.elastic_only;
-    const int prow = 9 * a.S;
-    const int per_round = 4 * EPW;
-    if (ext && a.targets) {
-        const double* tg = a.targets + (size_t)bidx * a.nt * 3;
-        const double kc = a.k_c;
-        for (int t0 = 0; t0 < a.nt; t0 += per_round) {
-            const int t = t0 + wave * EPW + eg;
+            // penalty k_c/2 |x_t - target_t|^2 of EPR targeted vertices
+            const int t = (rd - tet_rounds) * EPR + el;
             const bool ok = t < a.nt;
+            const T* row = tile + 3 * el * nc;
             T Jc[3];
             double d[3];
+            if constexpr (RP == 16) {
+                T jr[3], xv[3];
+                double xr[3], tr[3];
+                lds_read3(row, nc, xv);
+                lds_read3(row + 1 + (kact ? k : 0), nc, jr);
+                lds_read3(sd + 3 * el, 1, xr);
+                lds_read3(sd + 3 * EPR + 3 * el, 1, tr);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const size_t row = (size_t)(prow + 3 * t + c);
-                Jc[c] = (ok && kact) ? O[row * nc + 1 + k] : T(0);
-                d[c] = ok ? a.Xt[3 * t + c] + (double)O[row * nc] - tg[3 * t + c] : 0.0;
-                Kp[wave][eg][c][k] = Jc[c];
+                for (int c = 0; c < 3; ++c) {
+                    Jc[c] = (ok && kact) ? jr[c] : T(0);
+                    d[c] = ok ? xr[c] + (double)xv[c] - tr[c] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    Jc[c] = (ok && kact) ? row[c * nc + 1 + k] : T(0);
+                    d[c] = ok ? sd[3 * el + c] + (double)row[c * nc] - sd[3 * EPR + 3 * el + c] : 0.0;
+                }
             }
-            __syncthreads();
             if constexpr (RP == 16) {
                 typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
                 const T kt = (T)kc;
@@ -1114,7 +1290,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                         if (j < r) {
                             T h = 0;
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) h += Kp[wave][eg][c][j] * Jc[c];
+                            for (int c = 0; c < 3; ++c) h += row[c * nc + 1 + j] * Jc[c];
                             Hc[j] += kc * (double)h;
                         }
                     }
@@ -1124,12 +1300,20 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 if (dseed) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        if (c % RP == k) dseed[prow + 3 * t + c] = (T)(kc * d[c]);
+                        if (c % RP == k) global_store_asm(dseed + prow + 3 * t + c, (T)(kc * d[c]));
                 }
             }
-            __syncthreads();
         }
+    };
+
+    if (rounds > 0) issue(std::integral_constant<int, 0>{}, 0);
+    if (rounds > 1) issue(std::integral_constant<int, 1>{}, 1);
+    for (int rd = 0; rd < rounds; rd += 3) {
+        body(std::integral_constant<int, 0>{}, rd);
+        if (rd + 1 < rounds) body(std::integral_constant<int, 1>{}, rd + 1);
+        if (rd + 2 < rounds) body(std::integral_constant<int, 2>{}, rd + 2);
     }
+
     if (ext && wave == 0 && eg == 0) {
         const size_t gr = (size_t)a.grav_row;
         gk -= kact ? (double)O[gr * nc + 1 + k] : 0.0;
@@ -1149,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         for (int row = prow + tid; row < a.rows_pad; row += 256) {
             double v = 0.0;
             if (row < a.grav_row) {
-                if (ext && a.targets) continue;
+                if (tg) continue;
             } else if (row == a.grav_row) {
                 v = ext ? -1.0 : 0.0;
             } else if (row < a.force_row + 3) {
@@ -1159,7 +1343,9 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         }
     }
 
-    // reduce over the EPW tets of a wave (lanes k, k+RP, ...) then over waves
+    // reduce over the EPW tets of a wave (lanes k, k+RP, ...), then over the
+    // waves in order: wave 0 keeps the running sum, waves 1..3 pass theirs
+    // through the (now idle) first ring slot in turn
 #pragma unroll
     for (int off = RP; off < 64; off <<= 1) {
         if constexpr (RP != 16) {
@@ -1169,25 +1355,51 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         gk += __shfl_xor(gk, off);
         Ee += __shfl_xor(Ee, off);
     }
-    if constexpr (RP == 16) {
+    double* red = reinterpret_cast<double*>(ring0); // [RP][RP] H, [RP] g, [1] E
+    static_assert((RP * RP + RP + 1) * sizeof(double) <= SLOT * sizeof(T), "reduction fits one slot");
+    for (int w = 1; w < 4; ++w) {
+        __syncthreads();
+        if (wave == w) {
+            if constexpr (RP == 16) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) redH[wave][Mfma<T>::row(lane, q)][lane & 15] = Hm[q];
-    } else if (eg == 0) {
+                for (int q = 0; q < 4; ++q) red[q * 64 + lane] = Hm[q];
+            } else if (eg == 0) {
 #pragma unroll
-        for (int j = 0; j < RP; ++j) redH[wave][j][k] = Hc[j];
+                for (int j = 0; j < RP; ++j) red[j * RP + k] = Hc[j];
+            }
+            if (eg == 0) red[RP * RP + k] = gk;
+            if (lane == 0) red[RP * RP + RP] = Ee;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            if constexpr (RP == 16) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Hm[q] += red[q * 64 + lane];
+            } else {
+#pragma unroll
+                for (int j = 0; j < RP; ++j) Hc[j] += red[j * RP + k];
+            }
+            gk += red[RP * RP + k];
+            Ee += red[RP * RP + RP];
+        }
     }
-    if (eg == 0) {
-        redg[wave][k] = gk;
-        if (k == 0) redE[wave] = Ee;
+    if (wave == 0) {
+        if constexpr (RP == 16) {
+            if (a.H) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = Mfma<T>::row(lane, q), kk = lane & 15;
+                    if (j < r && kk < r) a.H[(size_t)item * r * r + j * r + kk] = Hm[q];
+                }
+            }
+        } else if (eg == 0 && kact && a.H) {
+#pragma unroll
+            for (int j = 0; j < RP; ++j)
+                if (j < r) a.H[(size_t)item * r * r + j * r + k] = Hc[j];
+        }
+        if (eg == 0 && kact && a.g) a.g[(size_t)item * r + k] = gk;
+        if (lane == 0 && a.E) a.E[item] = Ee;
     }
-    __syncthreads();
-    for (int p = tid; p < r * r; p += 256) {
-        const int j = p / r, kk = p - j * r;
-        const double h = ((redH[0][j][kk] + redH[1][j][kk]) + redH[2][j][kk]) + redH[3][j][kk];
-        if (a.H) a.H[(size_t)item * r * r + p] = h;
-    }
-    if (tid < r && a.g) a.g[(size_t)item * r + tid] = ((redg[0][tid] + redg[1][tid]) + redg[2][tid]) + redg[3][tid];
-    if (tid == 0 && a.E) a.E[item] = ((redE[0] + redE[1]) + redE[2]) + redE[3];
 }
 
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
