@@ -320,6 +320,7 @@ static int check_decoder(rs_ctx* c, const rs_decoder* d, int nv)
     if (d->r < 1 || d->r > kMaxR) return fail(c, RS_ERR_UNSUPPORTED, "decoder r must be in [1, 32]");
     if (d->n_hidden < 0 || (d->n_hidden > 0 && d->width < 1)) return fail(c, RS_ERR_ARG, "bad decoder depth/width");
     if (d->n_hidden > kMaxL) return fail(c, RS_ERR_UNSUPPORTED, "at most 8 hidden layers");
+    if (d->n_hidden > 0 && d->width > kMaxWidth) return fail(c, RS_ERR_UNSUPPORTED, "decoder width must be at most 256");
     if (d->n_out != 3 * nv) return fail(c, RS_ERR_ARG, "decoder n_out must be 3 * nv");
     if (!d->W || !d->b) return fail(c, RS_ERR_ARG, "decoder weights are NULL");
     for (int l = 0; l <= d->n_hidden; ++l)

@@ -18,6 +18,7 @@ constexpr int kMaxR = 32;    // largest latent dimension
 constexpr int kLsCand = 8;   // step lengths evaluated per line-search round after the first
 constexpr int kMaxL = 8;     // largest number of hidden layers
 constexpr int kMaxSplit = 16;// largest split of the adjoint GEMM's reduction
+constexpr int kMaxWidth = 256;// widest hidden layer
 
 // IN_RAW: item-major (y_rows x nc) blocks; IN_RAW_T: item-major (nc x y_rows)
 // blocks (k contiguous, the layout of a layer activation); IN_ELU: IN_RAW

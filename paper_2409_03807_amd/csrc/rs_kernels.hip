@@ -1498,111 +1498,168 @@ hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 // the second-order term of the exact reduced Hessian.  dE/dh_L is the sum of
 // the adjoint GEMM's K-slice partials, taken in slice order.
 // ---------------------------------------------------------------------------
-// y[v] = sum_u W[u][v] x[u] for v < nout (W row stride ld), all 256 threads:
-// each output is split over ns = 256 / nout slices of u with 4 independent
-// partial sums (loads in flight), the slices summed in order through LDS.
-template <typename T>
-__device__ void matvec_t(const T* W, int ld, int nin, int nout, const double* x, double* y, double* part)
-{
-    const int tid = threadIdx.x;
-    const int ns = nout >= 256 ? 1 : 256 / nout;
-    for (int v0 = 0; v0 < nout; v0 += 256) {
-        const int v = v0 + tid % min(nout - v0, 256);
-        const int q = nout - v0 >= 256 ? 0 : tid / nout;
-        const bool act = q < ns && (nout - v0 >= 256 || tid < ns * nout);
-        const int len = (nin + ns - 1) / ns;
-        const int u0 = q * len, u1 = min(nin, u0 + len);
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        if (act) {
-            int u = u0;
-            for (; u + 4 <= u1; u += 4) {
-                s0 += (double)W[(size_t)u * ld + v] * x[u];
-                s1 += (double)W[(size_t)(u + 1) * ld + v] * x[u + 1];
-                s2 += (double)W[(size_t)(u + 2) * ld + v] * x[u + 2];
-                s3 += (double)W[(size_t)(u + 3) * ld + v] * x[u + 3];
-            }
-            for (; u < u1; ++u) s0 += (double)W[(size_t)u * ld + v] * x[u];
-            part[tid] = (s0 + s1) + (s2 + s3);
-        }
-        __syncthreads();
-        if (nout - v0 >= 256) {
-            y[v0 + tid] = part[tid];
-        } else if (tid < nout - v0) {
-            double t = 0.0;
-            for (int qq = 0; qq < ns; ++qq) t += part[qq * nout + tid];
-            y[v0 + tid] = t;
-        }
-        __syncthreads();
-    }
-}
+// Reverse pass through the hidden layers, one workgroup per item (width
+// w <= 256).  Per layer l, from the last: cf = gbar_l * s''(a_l) and
+// ga = gbar_l * s'(a_l); then H += A^T diag(cf) A on the matrix cores, wave q
+// taking the 4-row steps t = q, q + 4, ... (lane (c, kq) holds A[u][c] for
+// u = 4t + kq: the A operand of A^T and, scaled by cf[u], the B operand of
+// diag(cf) A), float64 totals per layer, the four waves' sums added in order
+// at the end; and gbar_{l-1} = W_l^T ga, thread (slice, vq) summing rows
+// v of its slice of W_l into 4 adjacent outputs (16-byte loads, all of a
+// slice in flight at once), the 8 slices added in order.
+constexpr int kCurvMaxW = kMaxWidth;
 
-template <typename T>
+template <typename T, int RT>
 __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 {
     extern __shared__ double smem[];
-    const int item = blockIdx.x, tid = threadIdx.x;
+    const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (a.count && item >= *a.count) return;
     const int w = a.width, nc = a.nc, r = a.r;
-    double* gh = smem;       // dE/dh_l
-    double* ga = gh + w;     // dE/da_l
-    double* cf = ga + w;     // dE/dh_l * s''(a_l)
-    double* part = cf + w;   // 256 partial sums
-    T* As = reinterpret_cast<T*>(part + 256); // 64 x nc block of [a | A]
+    double* gh = smem;          // dE/dh_l
+    double* ga = gh + w;        // dE/da_l
+    double* cf = ga + w;        // dE/dh_l * s''(a_l)
+    const int pw = w > r ? w : r; // outputs of W_l^T ga: w, or r for the first layer
+    double* part = cf + w;        // [8 slices][pw] partial sums of W_l^T ga
+    double* red = part + 8 * pw;  // [4 waves][RT][RT][4][64] per-wave H partials
+    const int c = lane & 15, kq = lane >> 4;
     for (int u = tid; u < w; u += 256) {
-        double s = 0.0;
+        double sum = 0.0;
         const T* gp = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows + u;
 #pragma unroll 4
-        for (int z = 0; z < a.ksplit; ++z) s += (double)gp[z * a.split_stride];
-        gh[u] = s;
+        for (int z = 0; z < a.ksplit; ++z) sum += (double)gp[z * a.split_stride];
+        gh[u] = sum;
     }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    using acc_t = typename Mfma<T>::acc_t;
+    using V4 = T __attribute__((ext_vector_type(4)));
+    double Hd[RT][RT][4];
+#pragma unroll
+    for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < RT; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Hd[ti][tj][v] = 0.0;
+    const int slice = tid >> 5, vq = tid & 31;
+    const int rows_per = (w + 7) / 8;
     for (int l = a.L - 1; l >= 0; --l) {
         const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
-        __syncthreads();
+        __syncthreads(); // gh of this layer visible; cf, ga, part free
         for (int u = tid; u < w; u += 256) {
             const double av = (double)P[(size_t)u * nc];
             cf[u] = gh[u] * elu2(av);
             ga[u] = gh[u] * elu1(av);
         }
-        for (int u0 = 0; u0 < w; u0 += 64) {
-            const int nu = (w - u0) < 64 ? (w - u0) : 64;
-            __syncthreads();
-            for (int e = tid; e < nu * nc; e += 256) As[e] = P[(size_t)u0 * nc + e];
-            __syncthreads();
-            for (int q = 0; q < 4; ++q) {
-                const int p = tid + 256 * q;
-                if (p >= r * r) break;
-                const int j = p / r, kk = p - j * r;
-                double s0 = 0.0, s1 = 0.0;
-                int uu = 0;
-                for (; uu + 2 <= nu; uu += 2) {
-                    s0 += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
-                    s1 += cf[u0 + uu + 1] * (double)As[(uu + 1) * nc + 1 + j] * (double)As[(uu + 1) * nc + 1 + kk];
+        __syncthreads();
+        {
+            acc_t acc[RT][RT];
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < RT; ++tj) acc[ti][tj] = acc_t{0, 0, 0, 0};
+            const int nt = (w + 3) / 4;
+#pragma unroll 4
+            for (int t = wave; t < nt; t += 4) {
+                const int u = 4 * t + kq;
+                const bool uok = u < w;
+                const T cfu = uok ? (T)cf[u] : T(0);
+                T av[RT], bv[RT];
+#pragma unroll
+                for (int ti = 0; ti < RT; ++ti) {
+                    const int col = 16 * ti + c;
+                    const T x = (uok && col < r) ? P[(size_t)u * nc + 1 + col] : T(0);
+                    av[ti] = x;
+                    bv[ti] = cfu * x;
                 }
-                if (uu < nu) s0 += cf[u0 + uu] * (double)As[uu * nc + 1 + j] * (double)As[uu * nc + 1 + kk];
-                acc[q] += s0 + s1;
+#pragma unroll
+                for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < RT; ++tj) acc[ti][tj] = Mfma<T>::mac(av[ti], bv[tj], acc[ti][tj]);
             }
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < RT; ++tj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Hd[ti][tj][v] += (double)acc[ti][tj][v];
+        }
+        if (l == 0 && !a.grev) break;
+        // gbar_{l-1}[u'] = sum_v W_l[v][u'] ga[v] over the w outputs v of layer l
+        const int in = l == 0 ? r : w;
+        const int ld = l == 0 ? a.lda0 : a.lda;
+        const T* Wl = static_cast<const T*>(a.W[l]);
+        const int v0 = slice * rows_per, v1 = min(w, v0 + rows_per);
+#pragma unroll
+        for (int cg = 0; cg < kCurvMaxW / 128; ++cg) {
+            const int u0 = 128 * cg + 4 * vq; // 4 adjacent outputs; ld is a multiple of 32 and zero padded
+            if (128 * cg >= in) break;
+            double sacc[4] = {0.0, 0.0, 0.0, 0.0};
+            if (u0 < in) {
+                constexpr int RB = 8; // rows in flight
+                for (int vb = v0; vb < v1; vb += RB) {
+                    V4 x[RB];
+#pragma unroll
+                    for (int b = 0; b < RB; ++b)
+                        if (vb + b < v1) x[b] = *reinterpret_cast<const V4*>(Wl + (size_t)(vb + b) * ld + u0);
+#pragma unroll
+                    for (int b = 0; b < RB; ++b)
+                        if (vb + b < v1) {
+                            const double g = ga[vb + b];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) sacc[e] += (double)x[b][e] * g;
+                        }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (u0 + e < in) part[slice * pw + u0 + e] = sacc[e];
         }
         __syncthreads();
-        if (l > 0) {
-            matvec_t(static_cast<const T*>(a.W[l]), a.lda, w, w, ga, gh, part);
-        } else if (a.grev) {
-            matvec_t(static_cast<const T*>(a.W[0]), a.lda0, w, r, ga, cf, part);
-            for (int v = tid; v < r; v += 256) a.grev[(size_t)item * r + v] = cf[v];
+        for (int u = tid; u < in; u += 256) {
+            double o = 0.0;
+            for (int q = 0; q < 8; ++q) o += part[q * pw + u];
+            if (l > 0) gh[u] = o;
+            else a.grev[(size_t)item * r + u] = o;
         }
     }
-    for (int q = 0; q < 4; ++q) {
-        const int p = tid + 256 * q;
-        if (p < r * r) a.H[(size_t)item * r * r + p] += acc[q];
+    // the four waves' partial sums, added in wave order
+    __syncthreads();
+#pragma unroll
+    for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < RT; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(((wave * RT + ti) * RT + tj) * 4 + v) * 64 + lane] = Hd[ti][tj][v];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < RT; ++tj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    auto at = [&](int q) { return red[(((q * RT + ti) * RT + tj) * 4 + v) * 64 + lane]; };
+                    const double h = ((at(0) + at(1)) + at(2)) + at(3);
+                    const int row = 16 * ti + Mfma<T>::row(lane, v), col = 16 * tj + c;
+                    if (row < r && col < r) a.H[(size_t)item * r * r + row * r + col] += h;
+                }
     }
 }
 
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
 {
     if (items <= 0 || a.L <= 0) return hipSuccess;
-    const size_t sh = sizeof(double) * (3 * a.width + 256) + (f32 ? 4 : 8) * 64 * a.nc;
-    if (f32) RS_LAUNCH(k_curv<float>, dim3(items), dim3(256), sh, s, a);
-    else RS_LAUNCH(k_curv<double>, dim3(items), dim3(256), sh, s, a);
+    if (a.r > kMaxR) return hipErrorInvalidValue;
+    if (a.width > kCurvMaxW) return hipErrorInvalidValue;
+    const int rt = a.r <= 16 ? 1 : 2;
+    const size_t pw = (size_t)(a.width > a.r ? a.width : a.r);
+    const size_t sh = sizeof(double) * (3 * (size_t)a.width + 8 * pw + 4 * rt * rt * 4 * 64);
+    if (rt == 1) {
+        if (f32) RS_LAUNCH((k_curv<float, 1>), dim3(items), dim3(256), sh, s, a);
+        else RS_LAUNCH((k_curv<double, 1>), dim3(items), dim3(256), sh, s, a);
+    } else {
+        if (f32) RS_LAUNCH((k_curv<float, 2>), dim3(items), dim3(256), sh, s, a);
+        else RS_LAUNCH((k_curv<double, 2>), dim3(items), dim3(256), sh, s, a);
+    }
     return hipGetLastError();
 }
 
