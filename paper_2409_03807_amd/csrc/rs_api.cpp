@@ -784,6 +784,10 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
             ca.pre[l] = c->pre[l];
             ca.W[l] = c->W[l];
         }
+        // the fused hidden-layer kernel keeps (nc x wrows) blocks, the per-layer path (wrows x nc)
+        const bool fused = mlp_fits(f32, nc, c->r, c->wrows);
+        ca.pre_su = fused ? 1 : nc;
+        ca.pre_sc = fused ? c->wrows : 1;
         ca.gbar = c->gbar;
         ca.ksplit = c->ksplit;
         ca.split_stride = (size_t)c->max_batch * c->in_rows;

@@ -62,7 +62,7 @@ struct GemmArgs {
 struct MlpArgs {
     const void* W[kMaxL];   // wrows x lda (lda0 for layer 0), zero padded
     const void* b[kMaxL];   // wrows
-    void* pre[kMaxL];       // item-major (wrows x nc) pre-activations per layer (NULL = not kept)
+    void* pre[kMaxL];       // item-major (nc x wrows) pre-activations per layer (NULL = not kept)
     void* act;              // item-major (nc x wrows) activation of the last layer (k contiguous)
     int L, w, wrows, r, nc, lda0, lda;
     int items;              // grid capacity in items
@@ -110,7 +110,8 @@ struct EnergyArgs {
 
 // Reverse pass through the hidden layers adding sum_l A_l^T diag(gbar_l s''(a_l)) A_l.
 struct CurvArgs {
-    const void* pre[kMaxL]; // item-major (pre_rows x nc) pre-activations [a | A] per hidden layer
+    const void* pre[kMaxL]; // item-major pre-activation blocks [a | A] per hidden layer (pre_rows * nc per item)
+    int pre_su, pre_sc;     // element (unit u, column c) of a block at u * pre_su + c * pre_sc
     const void* W[kMaxL];   // hidden weights (width x in), in = r for layer 0
     const void* gbar;       // ksplit partials of items x pre_rows: dE/dh_L
     int ksplit;

@@ -643,12 +643,13 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
 // (k contiguous), each wave owns RT*16 output rows.  Weights come straight
 // from L2 into registers (8 consecutive k per lane, permuted-k MFMA order as
 // in k_gemm), the next 32-deep chunk prefetched behind the MFMAs.  After a
-// layer the pre-activations go to global memory and, activated, replace the
-// LDS input of the next layer.
+// layer the pre-activations go to global memory as (nc x wrows) blocks per
+// item and, activated, replace the LDS input of the next layer.
 // ---------------------------------------------------------------------------
-template <typename T, int CT, int RT>
-__global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
+template <typename T, int CT, int RT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
 {
+    constexpr int NTH = 64 * NW; // NW waves of RT * 16 output rows each
     using V = typename Vec16<T>::type;
     constexpr int VN = Vec16<T>::n;
     constexpr int NP = CT * 16;
@@ -656,13 +657,14 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
     T* Ys = reinterpret_cast<T*>(mlp_smem);
     const int nc = a.nc;
     const int IB = NP / nc;
+    // rows of a column: every k of the layer-0 input and every (padded) output row
+    const int LDY = max((a.r + kTileK - 1) / kTileK * kTileK, a.wrows) + VN;
+    T* dact = Ys + NP * LDY; // ELU'(a) of each (item, row) of the current layer
     const int items = a.count ? min(*a.count, a.items) : a.items;
     const int item0 = blockIdx.x * IB;
     if (item0 >= items) return;
     const int nitems = min(IB, items - item0);
     const int ncols = nitems * nc;
-    // rows of a column: every k of the layer-0 input and every (padded) output row
-    const int LDY = max((a.r + kTileK - 1) / kTileK * kTileK, a.wrows) + VN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     using acc_t = typename Mfma<T>::acc_t;
@@ -670,7 +672,7 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
     // layer-0 input [z | I]
     {
         const int kp = (a.r + kTileK - 1) / kTileK * kTileK;
-        for (int e = tid; e < NP * kp; e += 256) {
+        for (int e = tid; e < NP * kp; e += NTH) {
             const int n = e / kp, k = e - n * kp;
             T v = T(0);
             if (n < ncols && k < a.r) {
@@ -737,34 +739,59 @@ __global__ __launch_bounds__(256) void k_mlp(MlpArgs a)
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
             const int n = t * 16 + li;
-            const int i = n / nc, c = n - i * nc;
+            const bool vcol = n % nc == 0;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int m = wave * RT * 16 + rt * 16 + Mfma<T>::row(lane, v);
                     T val = acc[rt][t][v];
-                    if (c == 0) val += bias[m];
+                    if (vcol) val += bias[m];
                     Ys[n * LDY + m] = val;
-                    if (pre && n < ncols) pre[((size_t)(item0 + i) * a.wrows + m) * nc + c] = val;
                 }
         }
         __syncthreads();
-        // activation in place, one thread per (item, row): ELU' of the value
-        // column scales the item's Jacobian columns, then the value column
-        for (int e = tid; e < nitems * a.wrows; e += 256) {
-            const int i = e / a.wrows, m = e - i * a.wrows;
-            T* col = Ys + (i * nc) * LDY + m;
-            const T av = col[0];
-            const T d = T(elu1(av));
-            for (int c = 1; c < nc; ++c) col[c * LDY] *= d;
-            col[0] = elu0(av);
+        // Activation [ELU(a) | ELU'(a) A] in place, the pre-activations stored
+        // on the way in the same (column, row) order as the tile (consecutive
+        // threads, consecutive rows).  First the value column of each (item,
+        // row), keeping ELU'(a) in dact; then every Jacobian column.
+        const int wr = a.wrows;
+        T* pre_blk = pre ? pre + (size_t)item0 * nc * wr : nullptr;
+        for (int e = tid; e < nitems * wr; e += NTH) {
+            const int i = e / wr, m = e - i * wr;
+            const int n = i * nc;
+            const T av = Ys[n * LDY + m];
+            if (pre_blk) pre_blk[(size_t)n * wr + m] = av;
+            dact[e] = T(elu1(av));
+            Ys[n * LDY + m] = T(elu0(av));
+        }
+        __syncthreads();
+        if (nc > 1) {
+            const int G = NTH / wr; // column groups (wr = 16 RT NW, so NTH / wr = 4 / RT)
+            const int m = tid % wr, g = tid / wr;
+            if (g < G) {
+                int i = g / nc, c = g - i * nc;
+                const int di = G / nc, dc = G - di * nc;
+                for (int n = g; n < ncols; n += G) {
+                    if (c != 0) {
+                        const T x = Ys[n * LDY + m];
+                        if (pre_blk) pre_blk[(size_t)n * wr + m] = x;
+                        Ys[n * LDY + m] = dact[i * wr + m] * x;
+                    }
+                    i += di;
+                    c += dc;
+                    if (c >= nc) {
+                        c -= nc;
+                        ++i;
+                    }
+                }
+            }
         }
     }
     __syncthreads();
     // activation out as (nc x wrows) per item: consecutive threads, consecutive rows
     T* act = static_cast<T*>(a.act) + (size_t)item0 * nc * a.wrows;
-    for (int e = tid; e < ncols * a.wrows; e += 256) {
+    for (int e = tid; e < ncols * a.wrows; e += NTH) {
         const int n = e / a.wrows, m = e - n * a.wrows;
         act[e] = Ys[n * LDY + m];
     }
@@ -779,13 +806,14 @@ static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
     const int rt = a.wrows / 64;
     const int kr = (a.r + kTileK - 1) / kTileK * kTileK;
     const int ldy = (kr > a.wrows ? kr : a.wrows) + Vec16<T>::n;
-    const size_t sh = (size_t)np * ldy * sizeof(T);
+    const size_t sh = ((size_t)np * ldy + (size_t)ib * a.wrows) * sizeof(T);
     if (sh > 64 * 1024) return hipErrorInvalidValue;
     dim3 grid((a.items + ib - 1) / ib);
+    // waves of 16 output rows (two rows tiles per wave at width 256)
     switch (rt) {
-    case 1: RS_LAUNCH((k_mlp<T, CT, 1>), grid, dim3(256), sh, s, a); break;
-    case 2: RS_LAUNCH((k_mlp<T, CT, 2>), grid, dim3(256), sh, s, a); break;
-    case 4: RS_LAUNCH((k_mlp<T, CT, 4>), grid, dim3(256), sh, s, a); break;
+    case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4>), grid, dim3(256), sh, s, a); break;
+    case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8>), grid, dim3(512), sh, s, a); break;
+    case 4: RS_LAUNCH((k_mlp<T, CT, 2, 8>), grid, dim3(512), sh, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -797,7 +825,8 @@ bool mlp_fits(int f32, int nc, int r, int wrows)
     const int kr = (r + kTileK - 1) / kTileK * kTileK;
     const size_t ldy = (size_t)(kr > wrows ? kr : wrows) + (f32 ? 4 : 2);
     const int rt = wrows / 64;
-    return np / nc >= 1 && (rt == 1 || rt == 2 || rt == 4) && np * ldy * (f32 ? 4 : 8) <= 64 * 1024;
+    return np / nc >= 1 && (rt == 1 || rt == 2 || rt == 4) &&
+           (np * ldy + (size_t)(np / nc) * wrows) * (f32 ? 4 : 8) <= 64 * 1024;
 }
 
 hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s)
@@ -1516,6 +1545,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (a.count && item >= *a.count) return;
     const int w = a.width, nc = a.nc, r = a.r;
+    const int su = a.pre_su, sc = a.pre_sc;
     double* gh = smem;          // dE/dh_l
     double* ga = gh + w;        // dE/da_l
     double* cf = ga + w;        // dE/dh_l * s''(a_l)
@@ -1545,7 +1575,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
         const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
         __syncthreads(); // gh of this layer visible; cf, ga, part free
         for (int u = tid; u < w; u += 256) {
-            const double av = (double)P[(size_t)u * nc];
+            const double av = (double)P[(size_t)u * su];
             cf[u] = gh[u] * elu2(av);
             ga[u] = gh[u] * elu1(av);
         }
@@ -1566,7 +1596,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 #pragma unroll
                 for (int ti = 0; ti < RT; ++ti) {
                     const int col = 16 * ti + c;
-                    const T x = (uok && col < r) ? P[(size_t)u * nc + 1 + col] : T(0);
+                    const T x = (uok && col < r) ? P[(size_t)u * su + (size_t)(1 + col) * sc] : T(0);
                     av[ti] = x;
                     bv[ti] = cfu * x;
                 }
