@@ -195,7 +195,10 @@ int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* 
  * -H^-1 g with the Cholesky factor of the symmetrised Hessian when it is
  * positive definite, else with its eigen-projection (opts->proj).  Armijo
  * backtracking alpha = shrink^j, j < ls_max, on float64 energies.
- * Synchronises the stream a few times per Newton iteration. */
+ * The host enqueues one super-step (evaluate, direction, line-search round)
+ * ahead and waits on one event per super-step to read how many items are
+ * still running; the call returns once every item has exited, with at most
+ * the last super-step's work still in flight on `stream`. */
 int rs_newton_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
                     const rs_solve_opts* opts, int32_t* iters, int32_t* status,
                     double* relgrad, double* E, void* stream);
