@@ -1804,6 +1804,22 @@ hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, i
     return hipGetLastError();
 }
 
+// Lane l receives lane l - 1's value (dpp_from_prev) or lane l + 1's
+// (dpp_from_next) within its 16-lane row (DPP row_shr:1 / row_shl:1); the
+// first / last lane of a row keeps its own value.
+__device__ inline double dpp_from_prev(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x111, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x111, 0xF, 0xF, false));
+}
+__device__ inline double dpp_from_next(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x101, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x101, 0xF, 0xF, false));
+}
+
 // Parallel Jacobi eigen-decomposition of a symmetric n2 x n2 matrix (n2 even,
 // n2 <= 16) held in registers of one wave (Brent-Luk layout).  The indices are
 // paired by slot: slot k pairs (t_k, b_k), and one step rotates all n2/2 pairs
@@ -1839,8 +1855,11 @@ __device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], in
         for (int step = 0; step < n2 - 1; ++step) {
             double c = 1.0, sn = 0.0;
             if (I == J && htb != 0.0) {
-                const double theta = (hbb - htt) / (2.0 * htb);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                // smaller root of t^2 + 2 theta t - 1 = 0, theta = d / (2 a_pq),
+                // written as t = 2 a_pq / (d + sgn(d) sqrt(d^2 + 4 a_pq^2))
+                const double d = hbb - htt, two_apq = 2.0 * htb;
+                const double root = sqrt(d * d + two_apq * two_apq);
+                const double t = two_apq / (d >= 0.0 ? d + root : d - root);
                 c = 1.0 / sqrt(t * t + 1.0);
                 sn = t * c;
             }
@@ -1871,14 +1890,15 @@ __device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], in
                 if (I != 0) { htt = up0; htb = up1; }
                 hbt = nb0; hbb = nb1;
             }
-            // move the columns the same way along J (H and V)
+            // move the columns the same way along J (H and V): lanes J +- 1
+            // share a 16-lane DPP row, so these are row shifts
             {
                 const double d0 = (J == 0) ? htb : htt, d1 = (J == 0) ? hbb : hbt;
                 const double e0 = (J == 0) ? v01 : v00, e1 = (J == 0) ? v11 : v10;
-                const double lf0 = __shfl(d0, tid - 1), lf1 = __shfl(d1, tid - 1);
-                const double lv0 = __shfl(e0, tid - 1), lv1 = __shfl(e1, tid - 1);
-                const double rt_0 = __shfl(htb, tid + 1), rt_1 = __shfl(hbb, tid + 1);
-                const double rv0 = __shfl(v01, tid + 1), rv1 = __shfl(v11, tid + 1);
+                const double lf0 = dpp_from_prev(d0), lf1 = dpp_from_prev(d1);
+                const double lv0 = dpp_from_prev(e0), lv1 = dpp_from_prev(e1);
+                const double rt_0 = dpp_from_next(htb), rt_1 = dpp_from_next(hbb);
+                const double rv0 = dpp_from_next(v01), rv1 = dpp_from_next(v11);
                 const bool last = (J == m - 1);
                 const double nb0 = last ? htt : rt_0, nb1 = last ? hbt : rt_1;
                 const double nv0 = last ? v00 : rv0, nv1 = last ? v10 : rv1;
