@@ -65,7 +65,9 @@ def kernel_roofline(kind, rec, dtype):
     summed event-timed duration) against the peak of its bound."""
     secs = rec["ms"] * 1e-3
     if kind in MFMA_KINDS or kind in MFMA_F64_KINDS:
-        peak = MFMA_PEAK_TFLOPS["f64" if kind in MFMA_F64_KINDS else dtype]
+        # BF16 contexts run only the forward decoder products in BF16; the adjoint product stays float32
+        kd = "f64" if kind in MFMA_F64_KINDS else ("f32" if dtype == "bf16" and kind == "gemm_adjoint" else dtype)
+        peak = MFMA_PEAK_TFLOPS[kd]
         ach = rec["flops"] / secs / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak}
     if kind in ALU_F64_KINDS:
@@ -111,8 +113,9 @@ def main():
     name = args.config
     p = I.config(name)
     B = args.batch or {"c1": 1024, "c2": 1024, "c3": 4096}[name]
-    prec = rb.PREC_F64 if name == "c1" else rb.PREC_F32
-    dtype = "f64" if prec == rb.PREC_F64 else "f32"
+    # c1 float64, c2 float32, c3 the BF16 decoder variant of c2
+    prec = {"c1": rb.PREC_F64, "c2": rb.PREC_F32, "c3": rb.PREC_BF16}[name]
+    dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     ctx = rb.Context(p, prec=prec, max_batch=B)
     info = ctx.info()
     dev = "cuda:0"

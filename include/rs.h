@@ -32,7 +32,8 @@
  *    default stream) and is asynchronous, except where an entry point says it
  *    synchronises.  Argument checks are synchronous.
  *  - Latent and reduced quantities (z, E, g, H, loss) are always float64.
- *    Positions and Jacobians returned by rs_decode use the context precision.
+ *    Positions and Jacobians returned by rs_decode use the context precision
+ *    (float32 for RS_PREC_BF16 contexts).
  */
 #ifndef RS_H
 #define RS_H
@@ -64,8 +65,15 @@ enum {
     RS_RUNNING = -1
 };
 
-/* context precision of the decoder and element physics */
-enum { RS_PREC_F64 = 0, RS_PREC_F32 = 1 };
+/* Context precision of the decoder and element physics.
+ * RS_PREC_BF16 is the precision variant of the float32 context: the forward
+ * decoder products (hidden layers and output map) take BF16 operands on the
+ * matrix cores with float32 accumulation (weights converted from float64 with
+ * round-to-nearest-even, each layer input rounded to BF16); pre-activations,
+ * element physics, adjoint and curvature run in float32 exactly as in a
+ * float32 context; reduced quantities, the r x r solve and the line-search
+ * energies stay float64.  It needs at least one hidden layer. */
+enum { RS_PREC_F64 = 0, RS_PREC_F32 = 1, RS_PREC_BF16 = 2 };
 
 /* rs_energy_grad_hess flags */
 enum {
@@ -155,8 +163,8 @@ typedef struct rs_ctx rs_ctx;
 /* Fill *o with the defaults listed in rs_solve_opts. */
 int rs_default_opts(rs_solve_opts* o);
 
-/* Create a context on the current HIP device.  prec is RS_PREC_F64 or
- * RS_PREC_F32; max_batch bounds B of every later call (the Lipschitz loss
+/* Create a context on the current HIP device.  prec is RS_PREC_F64,
+ * RS_PREC_F32 or RS_PREC_BF16; max_batch bounds B of every later call (the Lipschitz loss
  * handles up to max_batch/2 pairs per internal pass).  Requires 1 <= r <= 32,
  * n_out == 3 nv, every index in range and every cubature tet of positive
  * volume.  Synchronous.  On failure *out is NULL. */

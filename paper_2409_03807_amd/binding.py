@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "librs.so")
 
 RS_OK, RS_ERR_ARG, RS_ERR_HIP, RS_ERR_OOM, RS_ERR_STATE, RS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
 CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE, RUNNING = 0, 1, 2, 3, 4, -1
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY = 1, 2, 4
 PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
 

@@ -78,6 +78,12 @@ struct rs_ctx {
     std::vector<void*> W, bh;
     std::vector<double*> W64, bh64;
     void* Wbig = nullptr; void* bbig = nullptr; void* WbigT = nullptr;
+    // BF16 contexts: BF16 copies of the forward GEMM weights (everything else
+    // as in a float32 context)
+    int bf16 = 0;
+    std::vector<void*> W16;
+    void* Wbig16 = nullptr;
+    void* Wfull16 = nullptr;
     double* Wbig64 = nullptr; double* bbig64 = nullptr;
     void* Wfull = nullptr; void* bfull = nullptr; void* Xfull = nullptr;
     double* wV = nullptr; double* Xt = nullptr;
@@ -219,6 +225,35 @@ static int upload(rs_ctx* c, void* dst, const std::vector<double>& src, int as_f
     return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpy");
 }
 
+// float64 -> bfloat16, round to nearest even.  Through float when that is
+// exact; when float rounding lands on a bfloat16 midpoint the float64 value
+// decides the direction, so the result is the correctly rounded one.
+static uint16_t bf16_rne(double x)
+{
+    const float f = (float)x;
+    uint32_t u;
+    std::memcpy(&u, &f, sizeof(u));
+    uint32_t hi = u >> 16;
+    const uint32_t lo = u & 0xFFFFu;
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(hi | ((u & 0x7FFFFFu) ? 0x40u : 0u)); // inf, nan
+    bool up;
+    if (lo > 0x8000u) up = true;
+    else if (lo < 0x8000u) up = false;
+    else {
+        const double ax = std::fabs(x), af = std::fabs((double)f);
+        up = ax > af ? true : ax < af ? false : (hi & 1u) != 0;
+    }
+    return (uint16_t)(up ? hi + 1 : hi);
+}
+
+static int upload_bf16(rs_ctx* c, void* dst, const std::vector<double>& src)
+{
+    std::vector<uint16_t> t(src.size());
+    for (size_t i = 0; i < src.size(); ++i) t[i] = bf16_rne(src[i]);
+    hipError_t e = hipMemcpy(dst, t.data(), t.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+    return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpy");
+}
+
 // Upload the decoder: hidden layers padded for the GEMM tiles, and the folded
 // output maps (reduced W_big, its transpose, and the full W_out for rs_decode).
 static int load_decoder(rs_ctx* c, const rs_decoder* d)
@@ -237,6 +272,7 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
             RS_TRY(upload(c, c->W[l], Wp, 1));
             RS_TRY(upload(c, c->bh[l], bp, 1));
         }
+        if (c->bf16) RS_TRY(upload_bf16(c, c->W16[l], Wp));
     }
     // masked output layer
     const double* Wo = d->W[L];
@@ -296,6 +332,7 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
         RS_TRY(upload(c, c->Wbig, Wb, 1));
         RS_TRY(upload(c, c->bbig, bb, 1));
     }
+    if (c->bf16) RS_TRY(upload_bf16(c, c->Wbig16, Wb));
     // transpose for the adjoint product dE/dh_L = W_big^T seeds
     std::vector<double> WT((size_t)c->in_rows * c->Mp, 0.0);
     for (int m = 0; m < c->Mp; ++m)
@@ -309,6 +346,7 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
         Xf[row] = c->X[row];
     }
     RS_TRY(upload(c, c->Wfull, Wf, c->f32));
+    if (c->bf16) RS_TRY(upload_bf16(c, c->Wfull16, Wf));
     RS_TRY(upload(c, c->bfull, bf, c->f32));
     RS_TRY(upload(c, c->Xfull, Xf, c->f32));
     return RS_OK;
@@ -380,7 +418,8 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     if (!mesh || !mat || !cub || !mesh->X || !mesh->tets || !mesh->pinned)
         return bail(fail(c, RS_ERR_ARG, "NULL mesh, material or cubature"));
     if (mesh->nv < 4 || mesh->ne < 1) return bail(fail(c, RS_ERR_ARG, "mesh too small"));
-    if (prec != RS_PREC_F64 && prec != RS_PREC_F32) return bail(fail(c, RS_ERR_UNSUPPORTED, "unknown precision"));
+    if (prec != RS_PREC_F64 && prec != RS_PREC_F32 && prec != RS_PREC_BF16)
+        return bail(fail(c, RS_ERR_UNSUPPORTED, "unknown precision"));
     if (max_batch < 1) return bail(fail(c, RS_ERR_ARG, "max_batch must be >= 1"));
     {
         const int rc = check_decoder(c, dec, mesh->nv);
@@ -392,7 +431,8 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
         return bail(fail(c, RS_ERR_ARG, "bad constraints"));
 
     c->prec = prec;
-    c->f32 = prec == RS_PREC_F32;
+    c->f32 = prec != RS_PREC_F64;
+    c->bf16 = prec == RS_PREC_BF16;
     c->tsz = c->f32 ? 4 : 8;
     c->nv = mesh->nv;
     c->ne = mesh->ne;
@@ -494,6 +534,18 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->bbig = c->f32 ? need(dalloc_bytes(c, (size_t)c->Mp * ts)) : c->bbig64;
     c->WbigT = need(dalloc_bytes(c, (size_t)c->in_rows * c->Mp * ts));
     c->Wfull = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * ts));
+    if (c->bf16) {
+        // BF16 operands need the fused hidden-layer kernel and a K that fills 32-deep chunks
+        if (c->L == 0 || !mlp_fits(1, (int)nc, c->r, c->wrows) || !mlp_fits(1, 1, c->r, c->wrows))
+            return bail(fail(c, RS_ERR_UNSUPPORTED, "BF16 contexts need hidden layers that fit the fused kernel"));
+        c->W16.resize(c->L);
+        for (int l = 0; l < c->L; ++l) {
+            const int lda = l == 0 ? c->lda0 : c->lda_h;
+            c->W16[l] = need(dalloc_bytes(c, (size_t)c->wrows * lda * 2));
+        }
+        c->Wbig16 = need(dalloc_bytes(c, (size_t)c->Mp * c->lda_out * 2));
+        c->Wfull16 = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * 2));
+    }
     c->bfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
     c->Xfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
     c->wV = (double*)need(dalloc<double>(c, c->S));
@@ -635,6 +687,9 @@ static int hidden_layers(rs_ctx* c, int f32, int nc, int cap, const int* count, 
     if (c->L == 0) return RS_OK;
     const size_t ts = f32 ? 4 : 8;
     const int slot = c->cur_slot;
+    // BF16 contexts run the float path with BF16 weights
+    const int bf = f32 && c->bf16;
+    if (bf) W = c->W16.data();
     if (mlp_fits(f32, nc, c->r, c->wrows)) {
         MlpArgs m{};
         for (int l = 0; l < c->L; ++l) {
@@ -663,8 +718,9 @@ static int hidden_layers(rs_ctx* c, int f32, int nc, int cap, const int* count, 
         pb += ts * (double)c->w * nc + 8.0 * c->r;
         Work wk = item_work(pb, pf, cap, count, slot, which);
         for (int l = 0; l < c->L; ++l) wk.b0 += ts * (double)c->w * (l == 0 ? c->r : c->w);
-        return run(c, kind, wk, s, [&] { return launch_mlp(f32, m, s); });
+        return run(c, kind, wk, s, [&] { return launch_mlp(f32, m, s, bf); });
     }
+    if (bf) return fail(c, RS_ERR_UNSUPPORTED, "BF16 hidden layers need the fused kernel");
     for (int l = 0; l < c->L; ++l) {
         GemmArgs a{};
         a.A = W[l];
@@ -723,7 +779,13 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.bias = c->bbig;
         a.out_mode = OUT_PACK;
         a.C = c->out;
+        if (c->bf16) {
+            // whole 32-deep chunks: W_big columns and activation rows past the width are zero
+            a.A = c->Wbig16;
+            a.K = c->lda_out;
+        }
         RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, nc, count, slot, 0), s, [&] {
+            if (c->bf16) return launch_gemm_p_bf16(ROLE_OUT, a, 8 * c->n_cu, s);
             return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_OUT, a, 8 * c->n_cu, s)
                                          : launch_gemm(f32, ROLE_OUT, a, s);
         }));
@@ -927,7 +989,12 @@ extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J
     a.Xo = x;
     a.Jo = J;
     a.Xrest = c->Xfull;
+    if (c->bf16) {
+        a.A = c->Wfull16;
+        a.K = c->lda_out;
+    }
     return run(c, K_DECODE_OUT, gemm_work(ts, c->n_out, a.K, B, nc, nullptr, -1, 0), s, [&] {
+        if (c->bf16) return launch_gemm_p_bf16(ROLE_DECODE, a, 8 * c->n_cu, s);
         return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_DECODE, a, 8 * c->n_cu, s)
                                      : launch_gemm(f32, ROLE_DECODE, a, s);
     });

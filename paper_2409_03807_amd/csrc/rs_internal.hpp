@@ -164,7 +164,12 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s);
 // persistent variant for IN_RAW / IN_LATENT inputs with K a supported multiple of 32
 hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks, hipStream_t s);
 bool gemm_p_fits(int f32, int K);
-hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s);
+// bf16: BF16 weights, the float32 layer input split into a BF16 pair (f32 must be set; FP32 accumulation,
+// pre-activations and activation)
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16 = 0);
+// persistent output map with BF16 A and transposed float32 input (IN_RAW_T, split into a BF16 pair), FP32
+// accumulation and output
+hipError_t launch_gemm_p_bf16(int role, const GemmArgs& a, int target_blocks, hipStream_t s);
 bool mlp_fits(int f32, int nc, int r, int wrows); // the fused kernel's LDS and tiling limits
 hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
                            const int* count, hipStream_t s);

@@ -68,6 +68,30 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = f32x4; static constexpr int n = 4; };
 template <> struct Vec16<double> { using type = f64x2; static constexpr int n = 2; };
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One 32-deep chunk of a 16x16 product in BF16 with FP32 accumulation:
+// lane (i + 16 g) supplies A[i][8g .. 8g+7] and B[8g .. 8g+7][i], which is the
+// permuted-k fragment every GEMM here holds per 32-deep chunk.
+__device__ inline f32x4 mfma_bf16_chunk(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight float32 values as a BF16 pair: hi = bf16(x), lo = bf16(x - hi), so
+// hi + lo carries x to about 16 significant bits and the products with a
+// BF16 operand lose only that operand's rounding.
+__device__ inline void split_bf16(f32x4 x0, f32x4 x1, bf16x8& hi, bf16x8& lo)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const __bf16 h0 = (__bf16)x0[e], h1 = (__bf16)x1[e];
+        hi[e] = h0;
+        hi[4 + e] = h1;
+        lo[e] = (__bf16)(x0[e] - (float)h0);
+        lo[4 + e] = (__bf16)(x1[e] - (float)h1);
+    }
+}
 
 // ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
 __device__ inline float elu0(float a) { return a > 0.f ? a : expm1f(a); }
@@ -550,6 +574,157 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
     }
 }
 
+// Persistent output map with BF16 operands (FP32 accumulation and output):
+// the workgroup's 64 x K tile of A stays in registers as BF16 fragments; the
+// transposed float32 activation tile is split into a BF16 pair (hi, lo) on
+// its way into LDS, and each 32-deep chunk is two 16x16x32 BF16 MFMAs per
+// 16-column tile.  Same tiling, prefetch and epilogue as k_gemm_p2.
+template <int ROLE, int KCH, int OUTM>
+__global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
+{
+    constexpr int KT = KCH * kTileK;
+    constexpr int LD = KT + 8;   // BF16 elements per LDS row (16-byte pad)
+    constexpr int PER = KT / 4;  // k per thread (4 thread groups per column)
+    __shared__ __align__(16) __bf16 Yh[kTileN * LD];
+    __shared__ __align__(16) __bf16 Yl[kTileN * LD];
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const int ncols = items * a.nc;
+    const int ntiles = (ncols + kTileN - 1) / kTileN;
+    const int g = blockIdx.y;
+    if (g >= ntiles) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m0 = blockIdx.x * kTileM;
+    const int nc = a.nc;
+    const unsigned ncu = (unsigned)nc;
+
+    bf16x8 af[KCH];
+    {
+        const __bf16* A = static_cast<const __bf16*>(a.A) + (size_t)(m0 + wave * 16 + li) * a.lda + 8 * lg;
+#pragma unroll
+        for (int c = 0; c < KCH; ++c) af[c] = *reinterpret_cast<const bf16x8*>(A + c * kTileK);
+    }
+    int mrow[4];
+    float brow[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        mrow[v] = m0 + wave * 16 + Mfma<float>::row(lane, v);
+        brow[v] = (a.bias && mrow[v] < a.rows) ? static_cast<const float*>(a.bias)[mrow[v]] : 0.f;
+    }
+
+    const int ynn = tid & 63, ykb = (tid >> 6) * PER;
+    f32x4 ry[PER / 4];
+    auto load = [&](int ct) {
+        const int yn = ct * kTileN + ynn;
+        if (yn < ncols) {
+            const int yitem = (int)((unsigned)yn / ncu);
+            const int yc = yn - yitem * nc;
+            const f32x4* vp = reinterpret_cast<const f32x4*>(static_cast<const float*>(a.Y) +
+                                                             ((size_t)yitem * nc + yc) * a.y_rows + ykb);
+#pragma unroll
+            for (int q = 0; q < PER / 4; ++q) ry[q] = vp[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < PER / 4; ++q) ry[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto store = [&]() {
+        bf16x8* dh = reinterpret_cast<bf16x8*>(&Yh[ynn * LD + ykb]);
+        bf16x8* dl = reinterpret_cast<bf16x8*>(&Yl[ynn * LD + ykb]);
+#pragma unroll
+        for (int q = 0; q < PER / 8; ++q) {
+            bf16x8 h, l;
+            split_bf16(ry[2 * q], ry[2 * q + 1], h, l);
+            dh[q] = h;
+            dl[q] = l;
+        }
+    };
+
+    float* Cout = static_cast<float*>(a.C);
+    load(g);
+    for (int ct = g; ct < ntiles; ct += groups) {
+        __syncthreads(); // the previous tile's LDS reads are done
+        store();
+        __syncthreads();
+        if (ct + groups < ntiles) load(ct + groups);
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < KCH; ++c)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int off = (t * 16 + li) * LD + c * kTileK + 8 * lg;
+                const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Yh[off]);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Yl[off]);
+                acc[t] = mfma_bf16_chunk(af[c], bh, acc[t]);
+                acc[t] = mfma_bf16_chunk(af[c], bl, acc[t]);
+            }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int n = ct * kTileN + t * 16 + li;
+            if (n >= ncols) continue;
+            const int item = (int)((unsigned)n / ncu);
+            const int cidx = n - item * nc;
+            if constexpr (OUTM == OUT_PACK) {
+                float* base = Cout + (size_t)item * a.rows_pad * nc + cidx;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (mrow[v] < a.rows) base[(size_t)mrow[v] * nc] = acc[t][v] + (cidx == 0 ? brow[v] : 0.f);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = mrow[v];
+                    if (m >= a.rows) continue;
+                    const float val = acc[t][v] + (cidx == 0 ? brow[v] : 0.f);
+                    if (cidx == 0) {
+                        if (a.Xo)
+                            static_cast<float*>(a.Xo)[(size_t)item * a.rows + m] = static_cast<const float*>(a.Xrest)[m] + val;
+                    } else if (a.Jo) {
+                        static_cast<float*>(a.Jo)[((size_t)item * a.rows + m) * a.r + (cidx - 1)] = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_gemm_p_bf16(int role, const GemmArgs& a, int target_blocks, hipStream_t s)
+{
+    if (a.items <= 0) return hipSuccess;
+    if (a.in_mode != IN_RAW_T || a.K % kTileK != 0 || a.ksplit > 1) return hipErrorInvalidValue;
+    const int kch = a.K / kTileK;
+    const int rt = a.rows_pad / kTileM;
+    const int ntiles = (a.items * a.nc + kTileN - 1) / kTileN;
+    int groups = (target_blocks + rt - 1) / rt;
+    if (groups > ntiles) groups = ntiles;
+    if (groups < 1) groups = 1;
+    dim3 grid(rt, groups);
+#define RS_PB(R, KC)                                                                                     \
+    do {                                                                                                 \
+        if (a.out_mode == OUT_PACK) RS_LAUNCH((k_gemm_p2_bf16<R, KC, OUT_PACK>), grid, dim3(256), 0, s, a, groups); \
+        else RS_LAUNCH((k_gemm_p2_bf16<R, KC, OUT_SPLIT>), grid, dim3(256), 0, s, a, groups);            \
+        return hipGetLastError();                                                                        \
+    } while (0)
+    if (role == ROLE_DECODE) {
+        switch (kch) {
+        case 1: RS_PB(ROLE_DECODE, 1);
+        case 2: RS_PB(ROLE_DECODE, 2);
+        case 4: RS_PB(ROLE_DECODE, 4);
+        case 8: RS_PB(ROLE_DECODE, 8);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (kch) {
+    case 1: RS_PB(ROLE_OUT, 1);
+    case 2: RS_PB(ROLE_OUT, 2);
+    case 4: RS_PB(ROLE_OUT, 4);
+    case 8: RS_PB(ROLE_OUT, 8);
+    default: return hipErrorInvalidValue;
+    }
+#undef RS_PB
+}
+
 template <typename T, int ROLE>
 static hipError_t gemm_p_dispatch(const GemmArgs& a, int groups, hipStream_t s)
 {
@@ -646,9 +821,14 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
 // layer the pre-activations go to global memory as (nc x wrows) blocks per
 // item and, activated, replace the LDS input of the next layer.
 // ---------------------------------------------------------------------------
-template <typename T, int CT, int RT, int NW>
+template <typename T, int CT, int RT, int NW, typename OP = T>
 __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
 {
+    // OP: type of the weights and of the MFMA operands (T, or BF16: weights in
+    // BF16 and the FP32 layer input split into a BF16 pair as its fragments are
+    // read, two MFMAs per chunk)
+    constexpr bool BF = std::is_same<OP, __bf16>::value;
+    static_assert(!BF || std::is_same<T, float>::value, "BF16 operands accumulate in float");
     constexpr int NTH = 64 * NW; // NW waves of RT * 16 output rows each
     using V = typename Vec16<T>::type;
     constexpr int VN = Vec16<T>::n;
@@ -687,13 +867,41 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
         const int K = l == 0 ? a.r : a.w;
         const int kp = (K + kTileK - 1) / kTileK * kTileK;
         const int lda = l == 0 ? a.lda0 : a.lda;
-        const T* W = static_cast<const T*>(a.W[l]);
         __syncthreads();
         acc_t acc[RT][CT];
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int t = 0; t < CT; ++t) acc[i][t] = acc_t{0, 0, 0, 0};
+        if constexpr (BF) {
+            const __bf16* W = static_cast<const __bf16*>(a.W[l]);
+            bf16x8 wb[RT];
+            auto loadw = [&](int k0) {
+#pragma unroll
+                for (int i = 0; i < RT; ++i)
+                    wb[i] = *reinterpret_cast<const bf16x8*>(W + (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg);
+            };
+            loadw(0);
+            for (int k0 = 0; k0 < kp; k0 += kTileK) {
+                bf16x8 ab[RT];
+#pragma unroll
+                for (int i = 0; i < RT; ++i) ab[i] = wb[i];
+                if (k0 + kTileK < kp) loadw(k0 + kTileK);
+#pragma unroll
+                for (int t = 0; t < CT; ++t) {
+                    const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
+                    const V x0 = sb[0], x1 = sb[1];
+                    bf16x8 bh, bl;
+                    split_bf16(x0, x1, bh, bl);
+#pragma unroll
+                    for (int i = 0; i < RT; ++i) {
+                        acc[i][t] = mfma_bf16_chunk(ab[i], bh, acc[i][t]);
+                        acc[i][t] = mfma_bf16_chunk(ab[i], bl, acc[i][t]);
+                    }
+                }
+            }
+        } else {
+        const T* W = static_cast<const T*>(a.W[l]);
         V wa[RT][8 / VN];
         auto loadw = [&](int k0) {
 #pragma unroll
@@ -732,6 +940,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
                 for (int t = 0; t < CT; ++t)
 #pragma unroll
                     for (int i = 0; i < RT; ++i) acc[i][t] = Mfma<T>::mac(af[i][kk], bf[t][kk], acc[i][t]);
+        }
         }
         __syncthreads(); // every wave is done reading this layer's input
         const T* bias = static_cast<const T*>(a.b[l]);
@@ -797,7 +1006,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
     }
 }
 
-template <typename T, int CT>
+template <typename T, int CT, typename OP = T>
 static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
 {
     const int np = CT * 16;
@@ -811,9 +1020,9 @@ static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
     dim3 grid((a.items + ib - 1) / ib);
     // waves of 16 output rows (two rows tiles per wave at width 256)
     switch (rt) {
-    case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4>), grid, dim3(256), sh, s, a); break;
-    case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8>), grid, dim3(512), sh, s, a); break;
-    case 4: RS_LAUNCH((k_mlp<T, CT, 2, 8>), grid, dim3(512), sh, s, a); break;
+    case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4, OP>), grid, dim3(256), sh, s, a); break;
+    case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8, OP>), grid, dim3(512), sh, s, a); break;
+    case 4: RS_LAUNCH((k_mlp<T, CT, 2, 8, OP>), grid, dim3(512), sh, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -829,9 +1038,13 @@ bool mlp_fits(int f32, int nc, int r, int wrows)
            (np * ldy + (size_t)(np / nc) * wrows) * (f32 ? 4 : 8) <= 64 * 1024;
 }
 
-hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s)
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16)
 {
     if (a.items <= 0 || a.L <= 0) return hipSuccess;
+    if (bf16) {
+        if (!f32) return hipErrorInvalidValue;
+        return a.nc > 1 ? mlp_dispatch<float, 5, __bf16>(a, s) : mlp_dispatch<float, 1, __bf16>(a, s);
+    }
     if (a.nc > 1) return f32 ? mlp_dispatch<float, 5>(a, s) : mlp_dispatch<double, 5>(a, s);
     return f32 ? mlp_dispatch<float, 1>(a, s) : mlp_dispatch<double, 1>(a, s);
 }

@@ -25,7 +25,7 @@ if not torch.cuda.is_available():
 from paper_2409_03807_amd import binding as rb  # noqa: E402
 
 DEV = "cuda:0"
-TOL = {rb.PREC_F64: 1e-10, rb.PREC_F32: 1e-4}
+TOL = {rb.PREC_F64: 1e-10, rb.PREC_F32: 1e-4, rb.PREC_BF16: 2e-2}
 
 
 def energy_scale(p):
@@ -130,6 +130,10 @@ def test_argument_errors():
         ctx.newton_solve(z)
     with pytest.raises(TypeError):
         ctx.energy_grad_hess(z.float())
+    # a BF16 context needs hidden layers for its BF16 products
+    q = I.make_problem("lin", 2, 1, 1, 4, [], 8)
+    with pytest.raises(RuntimeError):
+        rb.Context(q, prec=rb.PREC_BF16, max_batch=4)
 
 
 # ------------------------------------------------------------------- Newton
@@ -284,6 +288,79 @@ def test_lipschitz(name, prec):
     assert relerr(per[:, None], ores["per_pair"][:, None], tau=1e-300).max() < 10 * tol
     assert abs(res["loss"].item() - ores["loss"]) <= 10 * tol * ores["loss"]
     assert abs(res["lip_max"].item() - ores["lip_max"]) <= 10 * tol * ores["lip_max"]
+
+
+# ------------------------------------------------------------------- BF16 decoder
+@pytest.mark.parametrize("name", ["tinyb", "c1", "c2"])
+def test_bf16_decode(name):
+    """BF16 decoder products (float32 accumulation) against the float64 oracle at the BF16 bar."""
+    p = problem(name)
+    B = 5
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=8)
+    z = I.latent_batch(B, p.r)
+    x, J = ctx.decode(t64(z))
+    assert x.dtype == torch.float32 and J.dtype == torch.float32
+    xo, Jo = O.Oracle(p).decode(z)
+    tol = TOL[rb.PREC_BF16]
+    assert relerr(x.cpu().numpy() - p.X, xo - p.X, tau=1e-3).max() < tol
+    assert relerr(J.cpu().numpy(), Jo).max() < tol
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("flags", [rb.HESS_EXACT, rb.HESS_EXACT | rb.ELASTIC_ONLY])
+def test_bf16_energy_grad_hess(name, flags):
+    p = problem(name)
+    B = 5
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=8)
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=flags)
+    oflags = O.EXACT | (O.ELASTIC_ONLY if flags & rb.ELASTIC_ONLY else 0)
+    Eo, go, Ho = O.Oracle(p).reduced(z, tg, fo, flags=oflags)
+    tol = TOL[rb.PREC_BF16]
+    # the energy is evaluated with the float64 decoder
+    assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    assert relerr(g.cpu().numpy(), go).max() < tol
+    assert relerr(H.cpu().numpy(), Ho).max() < tol
+
+
+def test_bf16_full_size_sampled():
+    """c3: BF16 decoder at B = 4096 in the launch configuration of the benchmark, sampled items."""
+    p = problem("c3")
+    B = 4096
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo))
+    idx = np.array([0, 1, 17, B // 2 + 3, B - 1])
+    Eo, go, Ho = O.Oracle(p).reduced(z[idx], tg[idx], None)
+    tol = TOL[rb.PREC_BF16]
+    assert relerr(g.cpu().numpy()[idx], go).max() < tol
+    assert relerr(H.cpu().numpy()[idx], Ho).max() < tol
+    assert relerr(E.cpu().numpy()[idx, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    assert torch.isfinite(H).all()
+
+
+def test_bf16_newton_exit_points():
+    """BF16 search directions against float64 line-search energies: a solve ends
+    converged on its own gradient or at the line-search limit once the BF16
+    directions stop being descent directions of the exact energy.  The exit
+    point is then stationary for the oracle to the level the BF16 weights set
+    (measured on c2: about 2e-4 median, 1.3e-3 max, relative to |g_0|), and its
+    reported energy is the exact one."""
+    p = problem("c2")
+    B = 16
+    z0 = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    res = ctx.newton_solve(t64(z0), t64(tg), t64(fo))
+    st = res["status"].cpu().numpy()
+    assert np.all(np.isin(st, [rb.CONVERGED, rb.LS_MAX]))
+    o = O.Oracle(p)
+    g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
+    Eg, gg, _ = o.reduced(res["z"].cpu().numpy(), tg, fo)
+    assert np.all(np.abs(gg).max(axis=1) <= 1e-2 * g0)
+    assert relerr(res["E"].cpu().numpy()[:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
 
 
 # ------------------------------------------------------------------- misc
