@@ -733,7 +733,7 @@ static hipError_t gemm_p_dispatch(const GemmArgs& a, int groups, hipStream_t s)
     const size_t tile = (size_t)kTileN * (kch * kTileK + Vec16<T>::n) * sizeof(T);
     // fast variant: whole-K tiles, raw transposed input (K a multiple of 32) or latent input
     const bool fast_in = (a.in_mode == IN_RAW_T && a.K % kTileK == 0) || a.in_mode == IN_LATENT;
-    if (tile <= 64 * 1024 && fast_in) {
+    if (tile <= 80 * 1024 && fast_in) { // gfx950: up to 160 KB of LDS per workgroup
 #define RS_P2(KC)                                                                                         \
     do {                                                                                                  \
         if (a.in_mode == IN_LATENT) {                                                                     \
