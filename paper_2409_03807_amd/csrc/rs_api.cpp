@@ -30,12 +30,12 @@ namespace {
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 
 enum Kind {
-    K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR, K_LS_CAND,
+    K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
     K_INIT, K_ACTIVATE, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
-    "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir", "ls_candidates",
+    "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
     "newton_init", "activate"};
 
@@ -1079,29 +1079,28 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     c->cur_slot = -1;
     RS_TRY(run(c, K_INIT, Work{}, s, [&] { return launch_newton_init(st, B, s); }));
     RS_TRY(energy_f64(c, B, nullptr, 0, z, tg, fo, nullptr, 0, E, s, K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+    RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_eval(st, B, s); }));
     // Every super-step either evaluates an item or advances its line search by
     // at least one trial, so this bounds the loop.  The host runs one
     // super-step ahead: it launches step k+1 before reading the running count
     // of step k (counts only fall, so an older count bounds every launch).
+    // Each super-step ends with the Armijo kernel, which also builds the next
+    // evaluation list and writes the running count to mapped host memory.
     const long max_steps = (long)(o->max_iter + 1) * (2 + o->ls_max) + 2;
     int n_run = B;
     for (long step = 0; step < max_steps; ++step) {
         RS_TRY(log_counters(c, s));
-        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_eval(st, B, s); }));
         RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw, c->Hw, s));
         RS_TRY(run(c, K_DIR, item_work(8.0 * (r + r * r), (double)r * r * r, n_run, cnt + 0, c->cur_slot, 0), s,
                    [&] { return launch_newton_dir(st, p, n_run, s); }));
         st.plog = c->cur_slot >= 0 ? c->plog + 4 * (size_t)c->cur_slot : nullptr;
         RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_search(st, p, B, s); }));
         const int cap_c = n_run * kLsCand;
-        RS_TRY(run(c, K_LS_CAND, item_work(16.0 * r, 2.0 * r, cap_c, cnt + 1, c->cur_slot, 1), s,
-                   [&] { return launch_ls_candidates(st, p, cap_c, s); }));
         RS_TRY(energy_f64(c, cap_c, cnt + 1, 1, c->zc, tg, fo, c->cand_item, 0, c->Ec, s, K_LS_GEMM_HIDDEN,
                           K_LS_GEMM_OUT));
-        RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
-                   [&] { return launch_armijo(st, p, n_run, s); }));
         const int par = (int)(step & 1);
-        RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_count_running(st, B, c->hcount_dev + par, s); }));
+        RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
+                   [&] { return launch_armijo(st, p, B, c->hcount_dev + par, s); }));
         // the event's system-scope release makes the kernel's store to host memory visible
         hipError_t e = hipEventRecord(c->cnt_ev[par], s);
         if (e != hipSuccess) return hip_fail(c, e, "running-count copy");

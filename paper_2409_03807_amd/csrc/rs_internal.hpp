@@ -179,11 +179,11 @@ hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
+// search list, candidate list and candidate points zc
 hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s);
-hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
-// also writes the count to `host` (device address of mapped pinned memory, may be NULL)
-hipError_t launch_count_running(const NewtonState& st, int B, int* host, hipStream_t s);
+// Armijo test, then the next evaluation list and the running count, also written to `host` (device address
+// of mapped pinned memory, may be NULL)
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, int* host, hipStream_t s);
 hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s);
 hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H, int B, int r,
                             double* per_pair, double* ell, double* acc, int first_chunk, int last_chunk,

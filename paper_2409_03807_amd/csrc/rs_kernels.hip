@@ -1930,33 +1930,39 @@ hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s)
     return hipGetLastError();
 }
 
-// inclusive block-wide prefix sum over 1024 threads
-__device__ inline int block_scan1024(int v, int* sc)
+// Inclusive prefix sum over a 1024-thread workgroup (wave scans, then the 16
+// wave totals); `total` receives the sum.  sc: 16 ints of LDS, free again
+// after the next barrier.
+__device__ inline int block_scan1024(int v, int* sc, int& total)
 {
-    const int tid = threadIdx.x;
-    sc[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int x = tid >= off ? sc[tid - off] : 0;
-        __syncthreads();
-        sc[tid] += x;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int x = __shfl_up(v, off, 64);
+        if (lane >= off) v += x;
     }
-    const int out = sc[tid];
-    return out;
+    if (lane == 63) sc[wv] = v;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int q = 0; q < 16; ++q) {
+        const int t = sc[q];
+        before += q < wv ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    return before + v;
 }
 
 __global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B)
 {
-    __shared__ int sc[1024];
+    __shared__ int sc[16];
     const int tid = threadIdx.x;
     int base = 0;
     for (int b0 = 0; b0 < B; b0 += 1024) {
         const int b = b0 + tid;
         const int f = (b < B && st.status[b] == RS_RUNNING && st.ls_j[b] < 0) ? 1 : 0;
-        const int inc = block_scan1024(f, sc);
+        int tot;
+        const int inc = block_scan1024(f, sc, tot);
         if (f) st.eval_list[base + inc - 1] = b;
-        const int tot = sc[1023];
         __syncthreads();
         base += tot;
     }
@@ -1969,12 +1975,25 @@ hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s)
     return hipGetLastError();
 }
 
-// Candidate list: an item on its first trial evaluates alpha = 1 only (the
-// Newton step is usually accepted); later rounds evaluate kLsCand steps.
+// alpha_j = shrink^j by repeated multiplication
+__device__ inline double step_len(double shrink, int j)
+{
+    double a = 1.0;
+    for (int q = 0; q < j; ++q) a *= shrink;
+    return a;
+}
+
+// Candidate list and candidate points in one workgroup: an item on its first
+// trial evaluates alpha = 1 only (the Newton step is usually accepted); later
+// rounds evaluate kLsCand steps.  zc[c] = z[item] + alpha_j dz[item], written
+// per chunk of 1024 items with consecutive threads on consecutive coordinates.
 __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonParams p, int B)
 {
-    __shared__ int sc[1024];
-    const int tid = threadIdx.x;
+    constexpr int NB = 16; // coordinates per thread and batch (loads issued before stores)
+    __shared__ int sc[16];
+    __shared__ int it_b[1024], it_c[1024], it_j[1024]; // chunk search entry: item, first chunk candidate, trial
+    __shared__ short cl[1024 * kLsCand];                // chunk candidate -> chunk search entry
+    const int tid = threadIdx.x, r = p.r;
     int base_s = 0, base_c = 0;
     for (int b0 = 0; b0 < B; b0 += 1024) {
         const int b = b0 + tid;
@@ -1984,19 +2003,47 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
             f = 1;
             nc = min(j == 0 ? 1 : kLsCand, p.ls_max - j);
         }
-        const int inc = block_scan1024((f << 16) | nc, sc);
-        const int ps = base_s + (inc >> 16) - 1, pc = base_c + (inc & 0xffff) - nc;
+        int tot;
+        const int inc = block_scan1024((f << 16) | nc, sc, tot);
+        const int ls = (inc >> 16) - 1, lc = (inc & 0xffff) - nc;
         if (f) {
-            st.search_list[ps] = b;
-            st.search_start[ps] = pc;
-            st.search_ncand[ps] = nc;
+            st.search_list[base_s + ls] = b;
+            st.search_start[base_s + ls] = base_c + lc;
+            st.search_ncand[base_s + ls] = nc;
+            it_b[ls] = b;
+            it_c[ls] = lc;
+            it_j[ls] = j;
             for (int t = 0; t < nc; ++t) {
-                st.cand_item[pc + t] = b;
-                st.cand_j[pc + t] = j + t;
+                st.cand_item[base_c + lc + t] = b;
+                st.cand_j[base_c + lc + t] = j + t;
+                cl[lc + t] = (short)ls;
             }
         }
-        const int tot = sc[1023];
         __syncthreads();
+        const int ne = (tot & 0xffff) * r;
+        double* zc = st.zc + (size_t)base_c * r;
+        for (int e0 = 0; e0 < ne; e0 += 1024 * NB) {
+            double zv[NB], dv[NB];
+            int jv[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = e0 + q * 1024 + tid;
+                zv[q] = dv[q] = 0.0;
+                jv[q] = 0;
+                if (e < ne) {
+                    const int c = e / r, k = e - c * r, li = cl[c];
+                    zv[q] = st.z[(size_t)it_b[li] * r + k];
+                    dv[q] = st.dz[(size_t)it_b[li] * r + k];
+                    jv[q] = it_j[li] + c - it_c[li];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = e0 + q * 1024 + tid;
+                if (e < ne) zc[e] = zv[q] + step_len(p.shrink, jv[q]) * dv[q];
+            }
+        }
+        __syncthreads(); // the chunk's LDS tables are reused
         base_s += tot >> 16;
         base_c += tot & 0xffff;
     }
@@ -2357,85 +2404,93 @@ hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int c
     return hipGetLastError();
 }
 
-// alpha_j = shrink^j by repeated multiplication
-__device__ inline double step_len(double shrink, int j)
-{
-    double a = 1.0;
-    for (int q = 0; q < j; ++q) a *= shrink;
-    return a;
-}
-
-__global__ void k_ls_candidates(NewtonState st, NewtonParams p)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= st.counters[1]) return;
-    const int item = st.cand_item[c];
-    const double alpha = step_len(p.shrink, st.cand_j[c]);
-    for (int k = 0; k < p.r; ++k)
-        st.zc[(size_t)c * p.r + k] = st.z[(size_t)item * p.r + k] + alpha * st.dz[(size_t)item * p.r + k];
-}
-
-hipError_t launch_ls_candidates(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
-{
-    if (cap <= 0) return hipSuccess;
-    RS_LAUNCH(k_ls_candidates, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
-    return hipGetLastError();
-}
-
 // Armijo test on the float64 candidate energies: accept the first (largest)
 // step with E(z + a dz) - E(z) <= c1 a g.dz, as sequential backtracking would.
-__global__ void k_armijo(NewtonState st, NewtonParams p)
+// End of a super-step in one workgroup: the Armijo test of every searching
+// item over its candidates (first acceptable step length, in order), then
+// the evaluation list of the next super-step and the count of items still
+// running (also stored to `host`, mapped pinned memory, may be NULL).
+__global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p, int B, int* host)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= st.counters[2]) return;
-    const int item = st.search_list[i];
-    const int start = st.search_start[i], nc = st.search_ncand[i];
-    const double E0 = st.E[item], slope = st.slope[item];
-    const int j0 = st.ls_j[item];
-    for (int t = 0; t < nc; ++t) {
-        const double alpha = step_len(p.shrink, j0 + t);
-        const double Et = st.Ec[start + t];
-        if (isfinite(Et) && Et - E0 <= p.c1 * alpha * slope) {
-            for (int k = 0; k < p.r; ++k) st.z[(size_t)item * p.r + k] = st.zc[(size_t)(start + t) * p.r + k];
-            st.E[item] = Et;
-            st.iters[item] += 1;
-            st.ls_j[item] = -1;
-            return;
+    constexpr int NB = 16;
+    __shared__ int sc[16];
+    __shared__ int acc_item[1024], acc_cand[1024]; // accepted candidate per chunk search entry (-1: none)
+    const int tid = threadIdx.x, r = p.r;
+    const int ns = st.counters[2];
+    for (int i0 = 0; i0 < ns; i0 += 1024) {
+        const int i = i0 + tid;
+        int item = -1, cand = -1;
+        if (i < ns) {
+            item = st.search_list[i];
+            const int start = st.search_start[i], nc = st.search_ncand[i];
+            const double E0 = st.E[item], slope = st.slope[item];
+            const int j0 = st.ls_j[item];
+            for (int t = 0; t < nc && cand < 0; ++t) {
+                const double alpha = step_len(p.shrink, j0 + t);
+                const double Et = st.Ec[start + t];
+                if (isfinite(Et) && Et - E0 <= p.c1 * alpha * slope) {
+                    cand = start + t;
+                    st.E[item] = Et;
+                    st.iters[item] += 1;
+                    st.ls_j[item] = -1;
+                }
+            }
+            if (cand < 0) {
+                const int jn = j0 + nc;
+                if (jn >= p.ls_max) st.status[item] = RS_LS_MAX;
+                else st.ls_j[item] = jn;
+            }
         }
-    }
-    const int jn = j0 + nc;
-    if (jn >= p.ls_max) st.status[item] = RS_LS_MAX;
-    else st.ls_j[item] = jn;
-}
-
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s)
-{
-    if (cap <= 0) return hipSuccess;
-    RS_LAUNCH(k_armijo, dim3((cap + 255) / 256), dim3(256), 0, s, st, p);
-    return hipGetLastError();
-}
-
-// Items still running; also stored to `host` (mapped pinned memory, may be NULL).
-__global__ __launch_bounds__(1024) void k_count_running(NewtonState st, int B, int* host)
-{
-    __shared__ int sc[1024];
-    int n = 0;
-    for (int b = threadIdx.x; b < B; b += 1024) n += st.status[b] == RS_RUNNING ? 1 : 0;
-    sc[threadIdx.x] = n;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sc[threadIdx.x] += sc[threadIdx.x + w];
+        acc_item[tid] = item;
+        acc_cand[tid] = cand;
+        __syncthreads();
+        // accepted points, consecutive threads on consecutive coordinates
+        const int ne = min(1024, ns - i0) * r;
+        for (int e0 = 0; e0 < ne; e0 += 1024 * NB) {
+            double v[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = e0 + q * 1024 + tid;
+                v[q] = 0.0;
+                if (e < ne) {
+                    const int li = e / r, cnd = acc_cand[li];
+                    if (cnd >= 0) v[q] = st.zc[(size_t)cnd * r + e - li * r];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int e = e0 + q * 1024 + tid;
+                if (e < ne) {
+                    const int li = e / r;
+                    if (acc_cand[li] >= 0) st.z[(size_t)acc_item[li] * r + e - li * r] = v[q];
+                }
+            }
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        st.counters[3] = sc[0];
-        if (host) *host = sc[0];
+    __syncthreads(); // statuses and trial indices of this super-step are final
+    int base = 0, running = 0;
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int b = b0 + tid;
+        const int run = (b < B && st.status[b] == RS_RUNNING) ? 1 : 0;
+        const int f = (run && st.ls_j[b] < 0) ? 1 : 0;
+        int tot;
+        const int inc = block_scan1024((f << 16) | run, sc, tot);
+        if (f) st.eval_list[base + (inc >> 16) - 1] = b;
+        __syncthreads();
+        base += tot >> 16;
+        running += tot & 0xffff;
+    }
+    if (tid == 0) {
+        st.counters[0] = base;
+        st.counters[3] = running;
+        if (host) *host = running;
     }
 }
 
-hipError_t launch_count_running(const NewtonState& st, int B, int* host, hipStream_t s)
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, int* host, hipStream_t s)
 {
-    RS_LAUNCH(k_count_running, dim3(1), dim3(1024), 0, s, st, B, host);
+    RS_LAUNCH(k_armijo, dim3(1), dim3(1024), 0, s, st, p, B, host);
     return hipGetLastError();
 }
 
