@@ -718,7 +718,7 @@ static int hidden_layers(rs_ctx* c, int f32, int nc, int cap, const int* count, 
         pb += ts * (double)c->w * nc + 8.0 * c->r;
         Work wk = item_work(pb, pf, cap, count, slot, which);
         for (int l = 0; l < c->L; ++l) wk.b0 += ts * (double)c->w * (l == 0 ? c->r : c->w);
-        return run(c, kind, wk, s, [&] { return launch_mlp(f32, m, s, bf); });
+        return run(c, kind, wk, s, [&] { return launch_mlp(f32, m, s, bf, c->n_cu); });
     }
     if (bf) return fail(c, RS_ERR_UNSUPPORTED, "BF16 hidden layers need the fused kernel");
     for (int l = 0; l < c->L; ++l) {

@@ -166,7 +166,8 @@ hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks
 bool gemm_p_fits(int f32, int K);
 // bf16: BF16 weights, the float32 layer input split into a BF16 pair (f32 must be set; FP32 accumulation,
 // pre-activations and activation)
-hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16 = 0);
+// n_cu: compute units (a small batch takes fewer items per workgroup)
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16, int n_cu);
 // persistent output map with BF16 A and transposed float32 input (IN_RAW_T, split into a BF16 pair), FP32
 // accumulation and output
 hipError_t launch_gemm_p_bf16(int role, const GemmArgs& a, int target_blocks, hipStream_t s);

@@ -812,6 +812,43 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+// Global store of one value in inline asm (a plain vector store).  The
+// compiler does not count these among its outstanding vector-memory
+// operations, so its own waits for loads count exactly (vector loads complete
+// in order) instead of falling back to waiting for every store as well.
+// Used only for results that the kernel never reads back.
+template <typename T>
+__device__ inline void global_store_asm(T* p, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        asm volatile("global_store_dword %0, %1, off" : : "v"(p), "v"(v) : "memory");
+    else
+        asm volatile("global_store_dwordx2 %0, %1, off" : : "v"(p), "v"(v) : "memory");
+}
+
+// Workgroup barrier for LDS traffic only: this wave's LDS operations complete
+// (lgkmcnt 0, vector-memory count untouched), then s_barrier.  Global stores
+// may still be in flight; callers read nothing back that another wave of the
+// workgroup stored to global memory.
+__device__ inline void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // Fused hidden layers.  A workgroup owns CT*16 columns holding whole items
 // (IB = CT*16 / nc of them); their layer input lives in LDS as [column][k]
@@ -821,7 +858,7 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
 // layer the pre-activations go to global memory as (nc x wrows) blocks per
 // item and, activated, replace the LDS input of the next layer.
 // ---------------------------------------------------------------------------
-template <typename T, int CT, int RT, int NW, typename OP = T>
+template <typename T, int CT, int RT, int NW, typename OP = T, int PF = 1>
 __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
 {
     // OP: type of the weights and of the MFMA operands (T, or BF16: weights in
@@ -839,7 +876,8 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
     const int IB = NP / nc;
     // rows of a column: every k of the layer-0 input and every (padded) output row
     const int LDY = max((a.r + kTileK - 1) / kTileK * kTileK, a.wrows) + VN;
-    T* dact = Ys + NP * LDY; // ELU'(a) of each (item, row) of the current layer
+    T* dact = Ys + NP * LDY;        // ELU'(a) of each (item, row) of the current layer
+    T* bias_s = dact + IB * a.wrows; // every layer's bias (L x wrows), staged once
     const int items = a.count ? min(*a.count, a.items) : a.items;
     const int item0 = blockIdx.x * IB;
     if (item0 >= items) return;
@@ -849,6 +887,10 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
     const int li = lane & 15, lg = lane >> 4;
     using acc_t = typename Mfma<T>::acc_t;
 
+    for (int e = tid; e < a.L * a.wrows; e += NTH) {
+        const int l = e / a.wrows;
+        bias_s[e] = static_cast<const T*>(a.b[l])[e - l * a.wrows];
+    }
     // layer-0 input [z | I]
     {
         const int kp = (a.r + kTileK - 1) / kTileK * kTileK;
@@ -863,87 +905,93 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
             Ys[n * LDY + k] = v;
         }
     }
-    for (int l = 0; l < a.L; ++l) {
-        const int K = l == 0 ? a.r : a.w;
-        const int kp = (K + kTileK - 1) / kTileK * kTileK;
+    // Weights stream straight into registers in k-blocks of PF 32-deep chunks:
+    // chunk u of a block is consumed, then its registers take chunk u of the
+    // next block (the same layer's next k-block or the next layer's first),
+    // so PF chunks are in flight behind the products.
+    V wa[PF][RT][8 / VN];
+    bf16x8 wb[PF][RT];
+    auto loadw = [&](int l, int k0, auto u) {
         const int lda = l == 0 ? a.lda0 : a.lda;
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            const size_t off = (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg;
+            if constexpr (BF) {
+                wb[u][i] = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(a.W[l]) + off);
+            } else {
+                const V* src = reinterpret_cast<const V*>(static_cast<const T*>(a.W[l]) + off);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) wa[u][i][q] = src[q];
+            }
+        }
+    };
+    auto kpad = [&](int l) { return ((l == 0 ? a.r : a.w) + kTileK - 1) / kTileK * kTileK; };
+    // chunks past the end of the weights re-read the last one (loads stay
+    // unconditional, so no register merges wait on them)
+    static_for<PF>([&](auto u) { loadw(0, min((int)u * kTileK, kpad(0) - kTileK), u); });
+    for (int l = 0; l < a.L; ++l) {
+        const int kp = kpad(l);
+        lds_barrier();
         acc_t acc[RT][CT];
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int t = 0; t < CT; ++t) acc[i][t] = acc_t{0, 0, 0, 0};
-        if constexpr (BF) {
-            const __bf16* W = static_cast<const __bf16*>(a.W[l]);
-            bf16x8 wb[RT];
-            auto loadw = [&](int k0) {
+        for (int kb = 0; kb < kp; kb += PF * kTileK) {
+            // the k-block whose chunks replace this one's
+            const bool same = kb + PF * kTileK < kp;
+            const int nl = same ? l : min(l + 1, a.L - 1), nkb = same ? kb + PF * kTileK : 0;
+            const int nkp = kpad(nl);
+            static_for<PF>([&](auto u) {
+                const int k0 = kb + u * kTileK;
+                const int nk = min(nkb + (int)u * kTileK, nkp - kTileK);
+                if (k0 >= kp) { // past this layer's end: the registers only take the next chunk
+                    loadw(nl, nk, u);
+                    return;
+                }
+                if constexpr (BF) {
+                    bf16x8 ab[RT];
 #pragma unroll
-                for (int i = 0; i < RT; ++i)
-                    wb[i] = *reinterpret_cast<const bf16x8*>(W + (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg);
-            };
-            loadw(0);
-            for (int k0 = 0; k0 < kp; k0 += kTileK) {
-                bf16x8 ab[RT];
+                    for (int i = 0; i < RT; ++i) ab[i] = wb[u][i];
+                    loadw(nl, nk, u);
 #pragma unroll
-                for (int i = 0; i < RT; ++i) ab[i] = wb[i];
-                if (k0 + kTileK < kp) loadw(k0 + kTileK);
+                    for (int t = 0; t < CT; ++t) {
+                        const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
+                        const V x0 = sb[0], x1 = sb[1];
+                        bf16x8 bh, bl;
+                        split_bf16(x0, x1, bh, bl);
 #pragma unroll
-                for (int t = 0; t < CT; ++t) {
-                    const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
-                    const V x0 = sb[0], x1 = sb[1];
-                    bf16x8 bh, bl;
-                    split_bf16(x0, x1, bh, bl);
-#pragma unroll
-                    for (int i = 0; i < RT; ++i) {
-                        acc[i][t] = mfma_bf16_chunk(ab[i], bh, acc[i][t]);
-                        acc[i][t] = mfma_bf16_chunk(ab[i], bl, acc[i][t]);
+                        for (int i = 0; i < RT; ++i) {
+                            acc[i][t] = mfma_bf16_chunk(ab[i], bh, acc[i][t]);
+                            acc[i][t] = mfma_bf16_chunk(ab[i], bl, acc[i][t]);
+                        }
                     }
+                } else {
+                    T bf[CT][8];
+#pragma unroll
+                    for (int t = 0; t < CT; ++t) {
+                        const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
+#pragma unroll
+                        for (int q = 0; q < 8 / VN; ++q) {
+                            const V w = sb[q];
+#pragma unroll
+                            for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
+                        }
+                    }
+                    // k-step outermost: RT*CT independent accumulators between dependent MFMAs;
+                    // the chunk's registers are refilled once its products are issued
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                        for (int t = 0; t < CT; ++t)
+#pragma unroll
+                            for (int i = 0; i < RT; ++i)
+                                acc[i][t] = Mfma<T>::mac(wa[u][i][kk / VN][kk % VN], bf[t][kk], acc[i][t]);
+                    loadw(nl, nk, u);
                 }
-            }
-        } else {
-        const T* W = static_cast<const T*>(a.W[l]);
-        V wa[RT][8 / VN];
-        auto loadw = [&](int k0) {
-#pragma unroll
-            for (int i = 0; i < RT; ++i) {
-                const V* src = reinterpret_cast<const V*>(W + (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg);
-#pragma unroll
-                for (int q = 0; q < 8 / VN; ++q) wa[i][q] = src[q];
-            }
-        };
-        loadw(0);
-        for (int k0 = 0; k0 < kp; k0 += kTileK) {
-            T af[RT][8];
-#pragma unroll
-            for (int i = 0; i < RT; ++i)
-#pragma unroll
-                for (int q = 0; q < 8 / VN; ++q) {
-#pragma unroll
-                    for (int e = 0; e < VN; ++e) af[i][q * VN + e] = wa[i][q][e];
-                }
-            if (k0 + kTileK < kp) loadw(k0 + kTileK);
-            T bf[CT][8];
-#pragma unroll
-            for (int t = 0; t < CT; ++t) {
-                const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
-#pragma unroll
-                for (int q = 0; q < 8 / VN; ++q) {
-                    const V w = sb[q];
-#pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
-                }
-            }
-            // k-step outermost: RT*CT independent accumulators between dependent MFMAs
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                for (int t = 0; t < CT; ++t)
-#pragma unroll
-                    for (int i = 0; i < RT; ++i) acc[i][t] = Mfma<T>::mac(af[i][kk], bf[t][kk], acc[i][t]);
+            });
         }
-        }
-        __syncthreads(); // every wave is done reading this layer's input
-        const T* bias = static_cast<const T*>(a.b[l]);
+        lds_barrier(); // every wave is done reading this layer's input
         T* pre = static_cast<T*>(a.pre[l]);
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
@@ -955,11 +1003,11 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
                 for (int v = 0; v < 4; ++v) {
                     const int m = wave * RT * 16 + rt * 16 + Mfma<T>::row(lane, v);
                     T val = acc[rt][t][v];
-                    if (vcol) val += bias[m];
+                    if (vcol) val += bias_s[l * a.wrows + m];
                     Ys[n * LDY + m] = val;
                 }
         }
-        __syncthreads();
+        lds_barrier();
         // Activation [ELU(a) | ELU'(a) A] in place, the pre-activations stored
         // on the way in the same (column, row) order as the tile (consecutive
         // threads, consecutive rows).  First the value column of each (item,
@@ -970,11 +1018,11 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
             const int i = e / wr, m = e - i * wr;
             const int n = i * nc;
             const T av = Ys[n * LDY + m];
-            if (pre_blk) pre_blk[(size_t)n * wr + m] = av;
+            if (pre_blk) global_store_asm(pre_blk + (size_t)n * wr + m, av);
             dact[e] = T(elu1(av));
             Ys[n * LDY + m] = T(elu0(av));
         }
-        __syncthreads();
+        lds_barrier();
         if (nc > 1) {
             const int G = NTH / wr; // column groups (wr = 16 RT NW, so NTH / wr = 4 / RT)
             const int m = tid % wr, g = tid / wr;
@@ -984,7 +1032,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
                 for (int n = g; n < ncols; n += G) {
                     if (c != 0) {
                         const T x = Ys[n * LDY + m];
-                        if (pre_blk) pre_blk[(size_t)n * wr + m] = x;
+                        if (pre_blk) global_store_asm(pre_blk + (size_t)n * wr + m, x);
                         Ys[n * LDY + m] = dact[i * wr + m] * x;
                     }
                     i += di;
@@ -997,7 +1045,7 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     // activation out as (nc x wrows) per item: consecutive threads, consecutive rows
     T* act = static_cast<T*>(a.act) + (size_t)item0 * nc * a.wrows;
     for (int e = tid; e < ncols * a.wrows; e += NTH) {
@@ -1005,6 +1053,8 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
         act[e] = Ys[n * LDY + m];
     }
 }
+
+constexpr size_t kMlpLds = 128 * 1024; // gfx950: up to 160 KB of LDS per workgroup
 
 template <typename T, int CT, typename OP = T>
 static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
@@ -1015,13 +1065,16 @@ static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
     const int rt = a.wrows / 64;
     const int kr = (a.r + kTileK - 1) / kTileK * kTileK;
     const int ldy = (kr > a.wrows ? kr : a.wrows) + Vec16<T>::n;
-    const size_t sh = ((size_t)np * ldy + (size_t)ib * a.wrows) * sizeof(T);
-    if (sh > 64 * 1024) return hipErrorInvalidValue;
+    const size_t sh = ((size_t)np * ldy + (size_t)(ib + a.L) * a.wrows) * sizeof(T);
+    if (sh > kMlpLds) return hipErrorInvalidValue;
     dim3 grid((a.items + ib - 1) / ib);
-    // waves of 16 output rows (two rows tiles per wave at width 256)
+    // waves of 16 output rows (two rows tiles per wave at width 256); the
+    // value-only variants (few products per chunk) keep a whole 128-deep
+    // k-block of weights in flight
+    constexpr int PF = CT == 1 ? 4 : 1;
     switch (rt) {
-    case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4, OP>), grid, dim3(256), sh, s, a); break;
-    case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8, OP>), grid, dim3(512), sh, s, a); break;
+    case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4, OP, CT == 1 ? 2 : 1>), grid, dim3(256), sh, s, a); break;
+    case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8, OP, PF>), grid, dim3(512), sh, s, a); break;
     case 4: RS_LAUNCH((k_mlp<T, CT, 2, 8, OP>), grid, dim3(512), sh, s, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -1035,17 +1088,31 @@ bool mlp_fits(int f32, int nc, int r, int wrows)
     const size_t ldy = (size_t)(kr > wrows ? kr : wrows) + (f32 ? 4 : 2);
     const int rt = wrows / 64;
     return np / nc >= 1 && (rt == 1 || rt == 2 || rt == 4) &&
-           (np * ldy + (size_t)(np / nc) * wrows) * (f32 ? 4 : 8) <= 64 * 1024;
+           (np * ldy + (size_t)(np / nc + kMaxL) * wrows) * (f32 ? 4 : 8) <= kMlpLds;
 }
 
-hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16)
+template <typename T, typename OP = T>
+static hipError_t mlp_dispatch_jac(const MlpArgs& a, int n_cu, hipStream_t s)
+{
+    // items per workgroup: the most of 4, 2, 1 that still gives every compute
+    // unit a workgroup (a workgroup runs its layers on one compute unit, so
+    // a small batch is spread thin rather than queued on a few)
+    int ib = 4;
+    while (ib > 1 && (a.items + ib - 1) / ib < n_cu) ib >>= 1;
+    const int cols = ib * a.nc;
+    if (cols <= 32) return mlp_dispatch<T, 2, OP>(a, s);
+    if (cols <= 48) return mlp_dispatch<T, 3, OP>(a, s);
+    return mlp_dispatch<T, 5, OP>(a, s);
+}
+
+hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16, int n_cu)
 {
     if (a.items <= 0 || a.L <= 0) return hipSuccess;
     if (bf16) {
         if (!f32) return hipErrorInvalidValue;
-        return a.nc > 1 ? mlp_dispatch<float, 5, __bf16>(a, s) : mlp_dispatch<float, 1, __bf16>(a, s);
+        return a.nc > 1 ? mlp_dispatch_jac<float, __bf16>(a, n_cu, s) : mlp_dispatch<float, 1, __bf16>(a, s);
     }
-    if (a.nc > 1) return f32 ? mlp_dispatch<float, 5>(a, s) : mlp_dispatch<double, 5>(a, s);
+    if (a.nc > 1) return f32 ? mlp_dispatch_jac<float>(a, n_cu, s) : mlp_dispatch_jac<double>(a, n_cu, s);
     return f32 ? mlp_dispatch<float, 1>(a, s) : mlp_dispatch<double, 1>(a, s);
 }
 
@@ -1258,19 +1325,6 @@ __device__ inline double lds_read_f64(const double* p)
     double o;
     asm volatile("ds_read_b64 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(o) : "v"(lds_addr(p)) : "memory");
     return o;
-}
-
-// Global store of one value in inline asm (a plain vector store).  Inside
-// the element ring these keep the compiler's view of outstanding vector-memory
-// operations to loads only, so that its own waits count exactly instead of
-// falling back to waiting for everything (which would drain the ring).
-template <typename T>
-__device__ inline void global_store_asm(T* p, T v)
-{
-    if constexpr (sizeof(T) == 4)
-        asm volatile("global_store_dword %0, %1, off" : : "v"(p), "v"(v) : "memory");
-    else
-        asm volatile("global_store_dwordx2 %0, %1, off" : : "v"(p), "v"(v) : "memory");
 }
 
 template <typename T>
