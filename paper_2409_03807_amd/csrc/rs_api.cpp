@@ -583,13 +583,14 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->ell = (double*)need(dalloc<double>(c, B));
     c->lacc = (double*)need(dalloc<double>(c, 4));
     if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
-    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocMapped) != hipSuccess)
+    // coherent: the kernel's system-scope store lands in host memory without a cache flush
+    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return bail(fail(c, RS_ERR_OOM, "pinned host allocation failed"));
     c->hcount[0] = c->hcount[1] = 0;
     if (hipHostGetDevicePointer((void**)&c->hcount_dev, c->hcount, 0) != hipSuccess)
         return bail(fail(c, RS_ERR_HIP, "hipHostGetDevicePointer"));
     for (int k = 0; k < 2; ++k)
-        if (hipEventCreateWithFlags(&c->cnt_ev[k], hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&c->cnt_ev[k], hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess)
             return bail(fail(c, RS_ERR_HIP, "hipEventCreate"));
 
     if (upload(c, c->wV, wVh, 0) != RS_OK) return bail(RS_ERR_HIP);
@@ -1101,7 +1102,7 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
         const int par = (int)(step & 1);
         RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
                    [&] { return launch_armijo(st, p, B, c->hcount_dev + par, s); }));
-        // the event's system-scope release makes the kernel's store to host memory visible
+        // the count reaches host memory by the kernel's own system-scope store; the event only marks completion
         hipError_t e = hipEventRecord(c->cnt_ev[par], s);
         if (e != hipSuccess) return hip_fail(c, e, "running-count copy");
         if (step == 0) continue;

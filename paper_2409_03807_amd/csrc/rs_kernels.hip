@@ -2463,7 +2463,7 @@ hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int c
 // End of a super-step in one workgroup: the Armijo test of every searching
 // item over its candidates (first acceptable step length, in order), then
 // the evaluation list of the next super-step and the count of items still
-// running (also stored to `host`, mapped pinned memory, may be NULL).
+// running (also stored to `host`, coherent mapped host memory, with a system-scope store; may be NULL).
 __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p, int B, int* host)
 {
     constexpr int NB = 16;
@@ -2538,7 +2538,7 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     if (tid == 0) {
         st.counters[0] = base;
         st.counters[3] = running;
-        if (host) *host = running;
+        if (host) __hip_atomic_store(host, running, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
