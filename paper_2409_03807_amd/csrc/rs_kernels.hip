@@ -2235,8 +2235,42 @@ __device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], in
     __syncthreads();
 }
 
+__device__ inline double readlane_f64(double x, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Solve H x = -g (r <= 16) by Gauss-Jordan elimination without pivoting,
+// lane a (mod 16) holding row a of [H | -g] in registers, the pivot row
+// broadcast from its lane at each step; rows past r are identity rows.  For a
+// symmetric H the pivots are the squares of the Cholesky diagonal, so every
+// pivot is positive exactly when H is positive definite: returns 0 (x
+// undefined) at the first pivot that is not, else 1 with x = x_a.
+__device__ inline int gauss_jordan16(const double (*Hs)[kMaxR + 1], const double* gs, int r, int tid, double& x)
+{
+    const int a = tid & 15;
+    double h[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) h[k] = (a < r && k < r) ? Hs[a][k] : (a == k ? 1.0 : 0.0);
+    double b = a < r ? -gs[a] : 0.0, diag = 1.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const double piv = readlane_f64(h[j], j);
+        if (!(piv > 0.0) || !isfinite(piv)) return 0; // wave-uniform
+        const double f = (a == j) ? 0.0 : h[j] / piv;
+        if (a == j) diag = piv;
+        b -= f * readlane_f64(b, j);
+#pragma unroll
+        for (int k = j + 1; k < 16; ++k) h[k] -= f * readlane_f64(h[k], j);
+    }
+    x = b / diag;
+    return 1;
+}
+
 // Exit tests and the Newton direction of one item per 64-thread workgroup:
-// Cholesky of the symmetrised Hessian if it is positive definite, else a
+// the solve with the symmetrised Hessian if it is positive definite
+// (Cholesky, or for r <= 16 the equivalent Gauss-Jordan test), else a
 // Jacobi eigen-decomposition (parallel ordering: the r/2 disjoint rotations
 // of one round-robin step are applied together) and the projected (clamped /
 // absolute) eigenvalues.  All in float64.
@@ -2292,44 +2326,54 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
         if (status != RS_RUNNING) return;
     }
 
-    // right-looking Cholesky of the symmetrised Hessian (lower factor in Ls)
     int chol_ok = 1;
-    for (int j = 0; j < r; ++j) {
-        const double d = Ls[j][j];
+    if (r <= 16) {
+        // registers and lane broadcasts (no LDS round trips, no barriers)
+        double x;
+        chol_ok = gauss_jordan16(Hs, gs, r, tid, x);
+        if (chol_ok && tid < r) dzs[tid] = x;
         __syncthreads();
-        if (!(d > 0.0) || !isfinite(d)) {
-            chol_ok = 0;
-            break;
+    } else {
+        // right-looking Cholesky of the symmetrised Hessian (lower factor in Ls)
+        for (int j = 0; j < r; ++j) {
+            const double d = Ls[j][j];
+            __syncthreads();
+            if (!(d > 0.0) || !isfinite(d)) {
+                chol_ok = 0;
+                break;
+            }
+            const double ljj = sqrt(d);
+            if (tid == 0) Ls[j][j] = ljj;
+            for (int a = j + 1 + tid; a < r; a += 64) Ls[a][j] /= ljj;
+            __syncthreads();
+            const int m = r - j - 1;
+            for (int w = tid; w < m * m; w += 64) {
+                const int a = j + 1 + w / m, b = j + 1 + w % m;
+                if (b <= a) Ls[a][b] -= Ls[a][j] * Ls[b][j];
+            }
+            __syncthreads();
         }
-        const double ljj = sqrt(d);
-        if (tid == 0) Ls[j][j] = ljj;
-        for (int a = j + 1 + tid; a < r; a += 64) Ls[a][j] /= ljj;
-        __syncthreads();
-        const int m = r - j - 1;
-        for (int w = tid; w < m * m; w += 64) {
-            const int a = j + 1 + w / m, b = j + 1 + w % m;
-            if (b <= a) Ls[a][b] -= Ls[a][j] * Ls[b][j];
+        if (chol_ok) {
+            // L y = -g, then L^T dz = y, one column per step
+            for (int q = tid; q < r; q += 64) cs[q] = -gs[q];
+            __syncthreads();
+            for (int j = 0; j < r; ++j) {
+                const double yj = cs[j] / Ls[j][j];
+                __syncthreads();
+                if (tid == 0) cs[j] = yj;
+                for (int a = j + 1 + tid; a < r; a += 64) cs[a] -= Ls[a][j] * yj;
+                __syncthreads();
+            }
+            for (int j = r - 1; j >= 0; --j) {
+                const double dj = cs[j] / Ls[j][j];
+                __syncthreads();
+                if (tid == 0) dzs[j] = dj;
+                for (int a = tid; a < j; a += 64) cs[a] -= Ls[j][a] * dj;
+                __syncthreads();
+            }
         }
-        __syncthreads();
     }
     if (chol_ok) {
-        // L y = -g, then L^T dz = y, one column per step
-        for (int q = tid; q < r; q += 64) cs[q] = -gs[q];
-        __syncthreads();
-        for (int j = 0; j < r; ++j) {
-            const double yj = cs[j] / Ls[j][j];
-            __syncthreads();
-            if (tid == 0) cs[j] = yj;
-            for (int a = j + 1 + tid; a < r; a += 64) cs[a] -= Ls[a][j] * yj;
-            __syncthreads();
-        }
-        for (int j = r - 1; j >= 0; --j) {
-            const double dj = cs[j] / Ls[j][j];
-            __syncthreads();
-            if (tid == 0) dzs[j] = dj;
-            for (int a = tid; a < j; a += 64) cs[a] -= Ls[j][a] * dj;
-            __syncthreads();
-        }
     } else if (p.proj == RS_PROJ_NONE) {
         if (tid == 0) st.status[item] = RS_NOT_DESCENT;
         return;
