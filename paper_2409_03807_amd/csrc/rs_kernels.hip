@@ -836,6 +836,22 @@ __device__ inline void global_store_asm(T* p, T v)
         asm volatile("global_store_dwordx2 %0, %1, off" : : "v"(p), "v"(v) : "memory");
 }
 
+// The same store without a memory clobber: the compiler may move other
+// memory operations across it (for results nothing in the kernel reads).
+template <typename T>
+__device__ inline void global_store_free(T* p, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        asm volatile("global_store_dword %0, %1, off" : : "v"(p), "v"(v));
+    else
+        asm volatile("global_store_dwordx2 %0, %1, off" : : "v"(p), "v"(v));
+}
+
+__device__ inline void global_store_free4(float* p, f32x4 v)
+{
+    asm volatile("global_store_dwordx4 %0, %1, off" : : "v"(p), "v"(v));
+}
+
 // Workgroup barrier for LDS traffic only: this wave's LDS operations complete
 // (lgkmcnt 0, vector-memory count untouched), then s_barrier.  Global stores
 // may still be in flight; callers read nothing back that another wave of the
@@ -886,6 +902,15 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     using acc_t = typename Mfma<T>::acc_t;
+    // item (within the workgroup) of each of this lane's columns, and whether it is a value column
+    int icol[CT];
+    bool vcol[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        const int n = t * 16 + li;
+        icol[t] = min(n / nc, IB - 1);
+        vcol[t] = n < ncols && n == icol[t] * nc;
+    }
 
     for (int e = tid; e < a.L * a.wrows; e += NTH) {
         const int l = e / a.wrows;
@@ -992,60 +1017,69 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
             });
         }
         lds_barrier(); // every wave is done reading this layer's input
+        // Activation [ELU(a) | ELU'(a) A] of the wave's own rows, straight
+        // from the accumulators: a row's value and Jacobian columns all sit in
+        // this wave, so ELU'(a) reaches the Jacobian columns through the wave's
+        // own LDS rows (dact) with no workgroup barrier.  The pre-activations
+        // go out as (nc x wrows) blocks per item.
+        const int wr = a.wrows;
         T* pre = static_cast<T*>(a.pre[l]);
+        T* pre_blk = pre ? pre + (size_t)item0 * nc * wr : nullptr;
+        const T* bias_l = bias_s + l * wr;
+        // value columns: bias, then ELU.  With Jacobian columns only a few
+        // lanes hold value columns, so their pre-activations are parked in
+        // dact and ELU, ELU' taken one (item, row) per lane, all lanes busy.
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
-            const int n = t * 16 + li;
-            const bool vcol = n % nc == 0;
+            if (!vcol[t]) continue;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int m = wave * RT * 16 + rt * 16 + Mfma<T>::row(lane, v);
-                    T val = acc[rt][t][v];
-                    if (vcol) val += bias_s[l * a.wrows + m];
-                    Ys[n * LDY + m] = val;
+                    const T av = acc[rt][t][v] + bias_l[m];
+                    acc[rt][t][v] = av;
+                    if (nc > 1) dact[icol[t] * wr + m] = av;
+                    else Ys[(t * 16 + li) * LDY + m] = T(elu0(av));
                 }
         }
-        lds_barrier();
-        // Activation [ELU(a) | ELU'(a) A] in place, the pre-activations stored
-        // on the way in the same (column, row) order as the tile (consecutive
-        // threads, consecutive rows).  First the value column of each (item,
-        // row), keeping ELU'(a) in dact; then every Jacobian column.
-        const int wr = a.wrows;
-        T* pre_blk = pre ? pre + (size_t)item0 * nc * wr : nullptr;
-        for (int e = tid; e < nitems * wr; e += NTH) {
-            const int i = e / wr, m = e - i * wr;
-            const int n = i * nc;
-            const T av = Ys[n * LDY + m];
-            if (pre_blk) global_store_asm(pre_blk + (size_t)n * wr + m, av);
-            dact[e] = T(elu1(av));
-            Ys[n * LDY + m] = T(elu0(av));
-        }
-        lds_barrier();
         if (nc > 1) {
-            const int G = NTH / wr; // column groups (wr = 16 RT NW, so NTH / wr = 4 / RT)
-            const int m = tid % wr, g = tid / wr;
-            if (g < G) {
-                int i = g / nc, c = g - i * nc;
-                const int di = G / nc, dc = G - di * nc;
-                for (int n = g; n < ncols; n += G) {
-                    if (c != 0) {
-                        const T x = Ys[n * LDY + m];
-                        if (pre_blk) global_store_asm(pre_blk + (size_t)n * wr + m, x);
-                        Ys[n * LDY + m] = dact[i * wr + m] * x;
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); // this wave's dact rows are written
+            for (int e = lane; e < nitems * RT * 16; e += 64) {
+                const int i = e / (RT * 16), m = wave * RT * 16 + (e - i * RT * 16);
+                const T av = dact[i * wr + m];
+                dact[i * wr + m] = T(elu1(av));
+                Ys[i * nc * LDY + m] = T(elu0(av));
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); // ELU' of the wave's rows is in dact
+        }
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            const int n = t * 16 + li;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int mb = wave * RT * 16 + rt * 16;
+                if (!vcol[t]) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = mb + Mfma<T>::row(lane, v);
+                        Ys[n * LDY + m] = n < ncols ? dact[icol[t] * wr + m] * acc[rt][t][v] : T(0);
                     }
-                    i += di;
-                    c += dc;
-                    if (c >= nc) {
-                        c -= nc;
-                        ++i;
+                }
+                if (pre_blk && n < ncols) {
+                    T* pp = pre_blk + (size_t)n * wr + mb;
+                    if constexpr (std::is_same<T, float>::value) {
+                        // rows 4 (lane / 16) + v: four consecutive rows
+                        global_store_free4(pp + 4 * lg, f32x4{acc[rt][t][0], acc[rt][t][1], acc[rt][t][2], acc[rt][t][3]});
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) global_store_free(pp + Mfma<T>::row(lane, v), acc[rt][t][v]);
                     }
                 }
             }
         }
+        lds_barrier(); // the layer's activation is complete
     }
-    lds_barrier();
     // activation out as (nc x wrows) per item: consecutive threads, consecutive rows
     T* act = static_cast<T*>(a.act) + (size_t)item0 * nc * a.wrows;
     for (int e = tid; e < ncols * a.wrows; e += NTH) {
@@ -1075,7 +1109,11 @@ static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
     switch (rt) {
     case 1: RS_LAUNCH((k_mlp<T, CT, 1, 4, OP, CT == 1 ? 2 : 1>), grid, dim3(256), sh, s, a); break;
     case 2: RS_LAUNCH((k_mlp<T, CT, 1, 8, OP, PF>), grid, dim3(512), sh, s, a); break;
-    case 4: RS_LAUNCH((k_mlp<T, CT, 2, 8, OP>), grid, dim3(512), sh, s, a); break;
+    case 4:
+        // (float64 with five column tiles at this width exceeds the LDS budget)
+        if constexpr (std::is_same<T, double>::value && CT == 5) return hipErrorInvalidValue;
+        else RS_LAUNCH((k_mlp<T, CT, 2, 8, OP>), grid, dim3(512), sh, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1095,10 +1133,11 @@ template <typename T, typename OP = T>
 static hipError_t mlp_dispatch_jac(const MlpArgs& a, int n_cu, hipStream_t s)
 {
     // items per workgroup: the most of 4, 2, 1 that still gives every compute
-    // unit a workgroup (a workgroup runs its layers on one compute unit, so
-    // a small batch is spread thin rather than queued on a few)
+    // unit two workgroups (a workgroup runs its layers on one compute unit;
+    // a second one overlaps its products with the first one's activation
+    // pass, and a small batch is spread thin rather than queued on a few)
     int ib = 4;
-    while (ib > 1 && (a.items + ib - 1) / ib < n_cu) ib >>= 1;
+    while (ib > 1 && (a.items + ib - 1) / ib < 2 * n_cu) ib >>= 1;
     const int cols = ib * a.nc;
     if (cols <= 32) return mlp_dispatch<T, 2, OP>(a, s);
     if (cols <= 48) return mlp_dispatch<T, 3, OP>(a, s);
