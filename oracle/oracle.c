@@ -697,6 +697,122 @@ int or_newton(const or_problem* p, int B, double* z, const double* targets, cons
 }
 
 /* ------------------------------------------------------------------------- */
+/* reduced L-BFGS (the paper's main solver, Sec. 5): limited-memory BFGS      */
+/* inverse-Hessian products by the two-loop recursion (Nocedal and Wright,   */
+/* Numerical Optimization, Alg. 7.4), the Armijo backtracking of or_newton.  */
+/* ------------------------------------------------------------------------- */
+static double dot(const double* a, const double* b, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+void or_lbfgs_dir(int r, int npair, const double* S, const double* Y, const double* g, double* d)
+{
+    double* q = (double*)malloc(sizeof(double) * r);
+    double* alpha = (double*)malloc(sizeof(double) * (npair > 0 ? npair : 1));
+    for (int k = 0; k < r; ++k) q[k] = g[k];
+    /* newest pair first */
+    for (int i = npair - 1; i >= 0; --i) {
+        const double* si = S + (size_t)i * r;
+        const double* yi = Y + (size_t)i * r;
+        alpha[i] = dot(si, q, r) / dot(yi, si, r);
+        for (int k = 0; k < r; ++k) q[k] -= alpha[i] * yi[k];
+    }
+    double gamma = 1.0;
+    if (npair > 0) {
+        const double* sn = S + (size_t)(npair - 1) * r;
+        const double* yn = Y + (size_t)(npair - 1) * r;
+        gamma = dot(sn, yn, r) / dot(yn, yn, r);
+    }
+    for (int k = 0; k < r; ++k) q[k] *= gamma;
+    /* oldest pair first */
+    for (int i = 0; i < npair; ++i) {
+        const double* si = S + (size_t)i * r;
+        const double* yi = Y + (size_t)i * r;
+        const double beta = dot(yi, q, r) / dot(yi, si, r);
+        for (int k = 0; k < r; ++k) q[k] += si[k] * (alpha[i] - beta);
+    }
+    for (int k = 0; k < r; ++k) d[k] = -q[k];
+    free(q); free(alpha);
+}
+
+static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, const double* tgt,
+                       const double* f, const or_lbfgs_opts* o, int* iters, int* status,
+                       double* relgrad, double* Eout)
+{
+    int r = p->r, m = o->history;
+    double* g = (double*)malloc(sizeof(double) * r);
+    double* gold = (double*)malloc(sizeof(double) * r);
+    double* dz = (double*)malloc(sizeof(double) * r);
+    double* zt = (double*)malloc(sizeof(double) * r);
+    double* S = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * r);
+    double* Y = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * r);
+    double E;
+    int npair = 0;
+    item_eval(p, rd, z, tgt, f, 0, &E, g, NULL);
+    double g0 = inf_norm(g, r), gn = g0;
+    int it = 0, st;
+    for (;;) {
+        if (!isfinite(E) || !finite_vec(g, r)) { st = OR_NONFINITE; break; }
+        gn = inf_norm(g, r);
+        if (gn <= o->abs_tol || gn <= o->rel_tol * g0) { st = OR_CONVERGED; break; }
+        if (it >= o->max_iter) { st = OR_ITER_MAX; break; }
+        or_lbfgs_dir(r, npair, S, Y, g, dz);
+        const double slope = dot(g, dz, r);
+        if (!(slope < 0.0)) { st = OR_NOT_DESCENT; break; }
+        double alpha = 1.0, Et = 0.0;
+        int ok = 0;
+        for (int t = 0; t < o->ls_max; ++t) {
+            for (int k = 0; k < r; ++k) zt[k] = z[k] + alpha * dz[k];
+            item_eval(p, rd, zt, tgt, f, OR_ENERGY_ONLY, &Et, NULL, NULL);
+            if (isfinite(Et) && Et - E <= o->c1 * alpha * slope) { ok = 1; break; }
+            alpha *= o->shrink;
+        }
+        if (!ok) { st = OR_LS_MAX; break; }
+        /* s = z_new - z, y = g_new - g; the pair is kept only when s'y > 0
+         * (curvature condition: Armijo backtracking does not enforce it) */
+        double s_new[32], y_new[32];
+        for (int k = 0; k < r; ++k) s_new[k] = zt[k] - z[k];
+        memcpy(gold, g, sizeof(double) * r);
+        memcpy(z, zt, sizeof(double) * r);
+        ++it;
+        item_eval(p, rd, z, tgt, f, 0, &E, g, NULL);
+        for (int k = 0; k < r; ++k) y_new[k] = g[k] - gold[k];
+        if (m > 0 && dot(s_new, y_new, r) > 0.0) {
+            if (npair == m) { /* drop the oldest */
+                memmove(S, S + r, sizeof(double) * (size_t)(m - 1) * r);
+                memmove(Y, Y + r, sizeof(double) * (size_t)(m - 1) * r);
+                --npair;
+            }
+            memcpy(S + (size_t)npair * r, s_new, sizeof(double) * r);
+            memcpy(Y + (size_t)npair * r, y_new, sizeof(double) * r);
+            ++npair;
+        }
+    }
+    *iters = it;
+    *status = st;
+    *relgrad = g0 > 0.0 ? gn / g0 : 0.0;
+    *Eout = E;
+    free(g); free(gold); free(dz); free(zt); free(S); free(Y);
+}
+
+int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const double* force,
+             const or_lbfgs_opts* o, int* iters, int* status, double* relgrad, double* E)
+{
+    if (p->r > 32 || o->history < 0) return 1;
+    rest_data rd;
+    rest_build(p, &rd);
+#pragma omp parallel for schedule(dynamic)
+    for (int bi = 0; bi < B; ++bi)
+        item_lbfgs(p, &rd, z + (size_t)bi * p->r, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
+                   force ? force + (size_t)bi * 3 : NULL, o, iters + bi, status + bi, relgrad + bi, E + bi);
+    rest_free(&rd);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* full-space judge: Newton on the free vertex DOFs over every mesh element   */
 /* ------------------------------------------------------------------------- */
 static double full_energy(const or_problem* p, const rest_data* rd, const double* x,

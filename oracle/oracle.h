@@ -55,6 +55,16 @@ typedef struct {
     double eig_floor;  /* eigenvalue floor relative to max |eig| */
 } or_opts;
 
+typedef struct {
+    int max_iter;      /* accepted steps (exit IV) */
+    int ls_max;        /* backtracking trials per iteration (exit III) */
+    int history;       /* (s, y) pairs kept */
+    double c1;         /* Armijo constant */
+    double shrink;     /* step factor per trial */
+    double rel_tol;    /* stop when |g|_inf <= rel_tol |g_0|_inf */
+    double abs_tol;    /* ... or when |g|_inf <= abs_tol */
+} or_lbfgs_opts;
+
 enum { OR_CONVERGED = 0, OR_NOT_DESCENT = 1, OR_LS_MAX = 2, OR_ITER_MAX = 3, OR_NONFINITE = 4 };
 enum { OR_EXACT = 1, OR_ELASTIC_ONLY = 2, OR_ENERGY_ONLY = 4 };
 
@@ -86,6 +96,17 @@ int or_reduced(const or_problem* p, int B, const double* z, const double* target
 int or_newton(const or_problem* p, int B, double* z, const double* targets,
               const double* force, const or_opts* o, int* iters, int* status,
               double* relgrad, double* E);
+
+/* L-BFGS direction d = -H g by the two-loop recursion over npair (s, y)
+ * pairs stored oldest first (rows of S, Y, each r long), H_0 = gamma I with
+ * gamma = s'y / y'y of the newest pair (1 without pairs).  Exposed for pins. */
+void or_lbfgs_dir(int r, int npair, const double* S, const double* Y, const double* g, double* d);
+
+/* reduced L-BFGS with the same backtracking line search and exits as
+ * or_newton (gradient only), z in/out */
+int or_lbfgs(const or_problem* p, int B, double* z, const double* targets,
+             const double* force, const or_lbfgs_opts* o, int* iters, int* status,
+             double* relgrad, double* E);
 
 /* full-space Newton on the free DOFs over every mesh element (weight 1).
  * elem_psd=1 projects each 12x12 element Hessian to PSD; else the same

@@ -61,6 +61,29 @@ def default_opts(**kw) -> Opts:
     return Opts(**d)
 
 
+class LbfgsOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("ls_max", C.c_int), ("history", C.c_int), ("c1", C.c_double),
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double)]
+
+
+def default_lbfgs_opts(**kw) -> LbfgsOpts:
+    """Exits as in the paper's Sec. 5 (128 line-search trials, 1024 iterations); 10 pairs kept."""
+    d = dict(max_iter=1024, ls_max=128, history=10, c1=1e-4, shrink=0.5, rel_tol=1e-6, abs_tol=0.0)
+    d.update(kw)
+    return LbfgsOpts(**d)
+
+
+def lbfgs_dir(S, Y, g):
+    """Two-loop L-BFGS direction -H g for pairs S, Y (npair x r, oldest first)."""
+    g = _c64(g)
+    r = g.shape[0]
+    S = _c64(np.asarray(S, dtype=np.float64).reshape(-1, r))
+    Y = _c64(np.asarray(Y, dtype=np.float64).reshape(-1, r))
+    d = np.zeros(r)
+    lib().or_lbfgs_dir(C.c_int(r), C.c_int(S.shape[0]), _d(S), _d(Y), _d(g), _d(d))
+    return d
+
+
 _lib = None
 
 
@@ -235,6 +258,21 @@ class Oracle:
         E = np.zeros(B)
         lib().or_newton(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
                         _i(status), _d(relg), _d(E))
+        return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
+
+    def lbfgs(self, z0, targets=None, force=None, opts=None):
+        z = _c64(np.atleast_2d(z0)).copy()
+        B = z.shape[0]
+        t, f, tp, fp = self._loads(B, targets, force)
+        o = opts or default_lbfgs_opts()
+        iters = np.zeros(B, dtype=np.int32)
+        status = np.zeros(B, dtype=np.int32)
+        relg = np.zeros(B)
+        E = np.zeros(B)
+        rc = lib().or_lbfgs(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
+                            _i(status), _d(relg), _d(E))
+        if rc:
+            raise ValueError("or_lbfgs: r > 32 or negative history")
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
     def full_energy(self, x, targets=None, force=None):
