@@ -150,6 +150,18 @@ typedef struct {
     double eig_floor;   /* relative eigenvalue floor, default 1e-8 */
 } rs_solve_opts;
 
+/* L-BFGS options (host struct).  Defaults from rs_default_lbfgs_opts(). */
+#define RS_MAX_HISTORY 16
+typedef struct {
+    int32_t max_iter;   /* accepted steps (exit IV), default 1024 (Sec. 5) */
+    int32_t ls_max;     /* backtracking trials per step (exit III), default 128 (Sec. 5) */
+    int32_t history;    /* (s, y) pairs kept, 0 .. RS_MAX_HISTORY, default 10 */
+    double c1;          /* Armijo constant, default 1e-4 */
+    double shrink;      /* step factor per trial, default 0.5 */
+    double rel_tol;     /* |g|_inf <= rel_tol |g_0|_inf, default 1e-6 */
+    double abs_tol;     /* or |g|_inf <= abs_tol, default 0 */
+} rs_lbfgs_opts;
+
 /* Static description of a context (sizes used for work accounting). */
 typedef struct {
     int32_t prec, r, n_hidden, width, nv, ne, n_cub, n_target, n_force;
@@ -162,6 +174,8 @@ typedef struct rs_ctx rs_ctx;
 
 /* Fill *o with the defaults listed in rs_solve_opts. */
 int rs_default_opts(rs_solve_opts* o);
+/* Fill *o with the defaults listed in rs_lbfgs_opts. */
+int rs_default_lbfgs_opts(rs_lbfgs_opts* o);
 
 /* Create a context on the current HIP device.  prec is RS_PREC_F64,
  * RS_PREC_F32 or RS_PREC_BF16; max_batch bounds B of every later call (the Lipschitz loss
@@ -210,6 +224,21 @@ int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* 
 int rs_newton_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
                     const rs_solve_opts* opts, int32_t* iters, int32_t* status,
                     double* relgrad, double* E, void* stream);
+
+/* L-BFGS with backtracking line search (Sec. 5: the paper's solver for its
+ * main results, with exits I converged, II saddle / not a descent direction,
+ * III 128 line-search trials, IV iteration limit), for B <= max_batch
+ * independent items, z (B x r) in/out, outputs as rs_newton_solve.  The
+ * direction is the two-loop recursion over the last opts->history pairs
+ * s = z_{k+1} - z_k, y = g_{k+1} - g_k (a pair is kept only when s.y > 0),
+ * with H_0 = (s.y / y.y) I of the newest pair, and -g without pairs.  Only
+ * the gradient is evaluated (no Hessian).  Armijo backtracking as in
+ * rs_newton_solve, on float64 energies.  The history lives in the context
+ * (allocated by rs_create for max_batch items), so one solve at a time per
+ * context. */
+int rs_lbfgs_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
+                   const rs_lbfgs_opts* opts, int32_t* iters, int32_t* status,
+                   double* relgrad, double* E, void* stream);
 
 /* Lipschitz loss (Sec. 4.1, Eq. form-L-LS-E) of the exact cubature elastic
  * Hessian over B pairs (z1_b, z2_b) (each B x r):

@@ -60,6 +60,14 @@ class SolveOpts(C.Structure):
                 ("hess", C.c_int32), ("proj", C.c_int32), ("eig_floor", C.c_double)]
 
 
+class LbfgsOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("ls_max", C.c_int32), ("history", C.c_int32), ("c1", C.c_double),
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double)]
+
+
+MAX_HISTORY = 16
+
+
 class Info(C.Structure):
     _fields_ = [("prec", C.c_int32), ("r", C.c_int32), ("n_hidden", C.c_int32),
                 ("width", C.c_int32), ("nv", C.c_int32), ("ne", C.c_int32),
@@ -68,9 +76,9 @@ class Info(C.Structure):
 
 
 # every symbol include/rs.h declares
-SYMBOLS = ["rs_default_opts", "rs_create", "rs_destroy", "rs_set_decoder", "rs_get_info",
-           "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lipschitz_loss",
-           "rs_last_error", "rs_profile", "rs_profile_get"]
+SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy", "rs_set_decoder",
+           "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
+           "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get"]
 
 _lib = None
 
@@ -98,6 +106,9 @@ def load_library():
         L.rs_newton_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
                                       C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]
+        L.rs_lbfgs_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
+                                     C.POINTER(LbfgsOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]
         L.rs_lipschitz_loss.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
@@ -111,6 +122,14 @@ def load_library():
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     load_library().rs_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_lbfgs_opts(**kw) -> LbfgsOpts:
+    o = LbfgsOpts()
+    load_library().rs_default_lbfgs_opts(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -239,6 +258,13 @@ class Context:
     def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None):
         """z0 (B x r) float64 on the GPU; returns dict of device tensors.
         `out` may pass preallocated (z, iters, status, relgrad, E) tensors."""
+        return self._solve("rs_newton_solve", z0, targets, force, opts or default_opts(), out)
+
+    def lbfgs_solve(self, z0, targets=None, force=None, opts: LbfgsOpts | None = None, out=None):
+        """As newton_solve, with the L-BFGS solver."""
+        return self._solve("rs_lbfgs_solve", z0, targets, force, opts or default_lbfgs_opts(), out)
+
+    def _solve(self, fn, z0, targets, force, o, out):
         B = z0.shape[0]
         _dev(z0, torch.float64, (B, self.r), "z0")
         ld, _keep = self._load(B, targets, force)
@@ -251,10 +277,8 @@ class Context:
         else:
             z, iters, status, relg, E = out
             z.copy_(z0)
-        o = opts or default_opts()
-        self._check(load_library().rs_newton_solve(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), _ptr(iters),
-                                                   _ptr(status), _ptr(relg), _ptr(E), _stream()),
-                    "rs_newton_solve")
+        self._check(getattr(load_library(), fn)(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), _ptr(iters),
+                                                _ptr(status), _ptr(relg), _ptr(E), _stream()), fn)
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
     def lipschitz_loss(self, z1, z2, want_per_pair=True):

@@ -32,12 +32,12 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_ACTIVATE, K_COUNT
+    K_INIT, K_ACTIVATE, K_LBFGS, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
-    "newton_init", "activate"};
+    "newton_init", "activate", "lbfgs_dir"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -96,6 +96,7 @@ struct rs_ctx {
     void* gbar = nullptr;         // max_batch x in_rows T
     double *Ew = nullptr, *gw = nullptr, *Hw = nullptr;
     double *g0 = nullptr, *dz = nullptr, *slope = nullptr;
+    LbfgsState lb{};              // L-BFGS history, max_batch items
     int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
     int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
     int ksplit = 1;               // K slices of the adjoint GEMM
@@ -382,6 +383,19 @@ extern "C" int rs_default_opts(rs_solve_opts* o)
     return RS_OK;
 }
 
+extern "C" int rs_default_lbfgs_opts(rs_lbfgs_opts* o)
+{
+    if (!o) return RS_ERR_ARG;
+    o->max_iter = 1024;
+    o->ls_max = 128;
+    o->history = 10;
+    o->c1 = 1e-4;
+    o->shrink = 0.5;
+    o->rel_tol = 1e-6;
+    o->abs_tol = 0.0;
+    return RS_OK;
+}
+
 extern "C" const char* rs_last_error(const rs_ctx* c) { return c ? c->err.c_str() : kNullCtxMsg; }
 
 static void destroy(rs_ctx* c)
@@ -568,6 +582,13 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->g0 = (double*)need(dalloc<double>(c, B));
     c->dz = (double*)need(dalloc<double>(c, B * c->r));
     c->slope = (double*)need(dalloc<double>(c, B));
+    c->lb.S = (double*)need(dalloc<double>(c, B * RS_MAX_HISTORY * c->r));
+    c->lb.Y = (double*)need(dalloc<double>(c, B * RS_MAX_HISTORY * c->r));
+    c->lb.sy = (double*)need(dalloc<double>(c, B * RS_MAX_HISTORY));
+    c->lb.npair = (int*)need(dalloc<int>(c, B));
+    c->lb.head = (int*)need(dalloc<int>(c, B));
+    c->lb.zprev = (double*)need(dalloc<double>(c, B * c->r));
+    c->lb.gprev = (double*)need(dalloc<double>(c, B * c->r));
     c->ls_j = (int*)need(dalloc<int>(c, B));
     c->eval_list = (int*)need(dalloc<int>(c, B));
     c->search_list = (int*)need(dalloc<int>(c, B));
@@ -1025,19 +1046,12 @@ static int log_counters(rs_ctx* c, hipStream_t s)
     return RS_OK;
 }
 
-extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
-                               int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+// Batched reduced solve (Newton or L-BFGS) fully on the device: evaluation,
+// direction, line-search rounds and exits per item, with the host launching
+// one super-step ahead.
+static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, const NewtonParams& p, uint32_t flags,
+                       bool lbfgs, int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
 {
-    if (!c) return RS_ERR_STATE;
-    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
-    if (B == 0) return RS_OK;
-    if (!z || !iters || !status || !relgrad || !E) return fail(c, RS_ERR_ARG, "NULL output pointer");
-    rs_solve_opts def;
-    rs_default_opts(&def);
-    if (!o) o = &def;
-    if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
-        o->proj < 0 || o->proj > 2)
-        return fail(c, RS_ERR_ARG, "invalid solver options");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double* tg = load ? load->targets : nullptr;
     const double* fo = load ? load->force : nullptr;
@@ -1064,17 +1078,6 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     st.Hw = c->Hw;
     st.zc = c->zc;
     st.Ec = c->Ec;
-    NewtonParams p{};
-    p.r = r;
-    p.max_iter = o->max_iter;
-    p.ls_max = o->ls_max;
-    p.proj = o->proj;
-    p.c1 = o->c1;
-    p.shrink = o->shrink;
-    p.rel_tol = o->rel_tol;
-    p.abs_tol = o->abs_tol;
-    p.eig_floor = o->eig_floor;
-    const uint32_t flags = o->hess ? RS_HESS_EXACT : 0;
     int* cnt = c->counters;
 
     c->cur_slot = -1;
@@ -1087,13 +1090,20 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     // of step k (counts only fall, so an older count bounds every launch).
     // Each super-step ends with the Armijo kernel, which also builds the next
     // evaluation list and writes the running count to mapped host memory.
-    const long max_steps = (long)(o->max_iter + 1) * (2 + o->ls_max) + 2;
+    const long max_steps = (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
     int n_run = B;
     for (long step = 0; step < max_steps; ++step) {
         RS_TRY(log_counters(c, s));
-        RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw, c->Hw, s));
-        RS_TRY(run(c, K_DIR, item_work(8.0 * (r + r * r), (double)r * r * r, n_run, cnt + 0, c->cur_slot, 0), s,
-                   [&] { return launch_newton_dir(st, p, n_run, s); }));
+        RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw,
+                      lbfgs ? nullptr : c->Hw, s));
+        if (lbfgs) {
+            const double m = p.hist;
+            RS_TRY(run(c, K_LBFGS, item_work(8.0 * (5 * r + 2 * m * r), 8.0 * m * r, n_run, cnt + 0, c->cur_slot, 0),
+                       s, [&] { return launch_lbfgs_dir(st, p, c->lb, n_run, s); }));
+        } else {
+            RS_TRY(run(c, K_DIR, item_work(8.0 * (r + r * r), (double)r * r * r, n_run, cnt + 0, c->cur_slot, 0),
+                       s, [&] { return launch_newton_dir(st, p, n_run, s); }));
+        }
         st.plog = c->cur_slot >= 0 ? c->plog + 4 * (size_t)c->cur_slot : nullptr;
         RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_search(st, p, B, s); }));
         const int cap_c = n_run * kLsCand;
@@ -1122,8 +1132,59 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
         n_run = std::min(*(volatile int*)c->hcount, *(volatile int*)(c->hcount + 1));
     }
     c->cur_slot = -1;
-    if (n_run > 0) return fail(c, RS_ERR_STATE, "Newton loop did not terminate");
+    if (n_run > 0) return fail(c, RS_ERR_STATE, "solver loop did not terminate");
     return RS_OK;
+}
+
+extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
+                               int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
+    if (B == 0) return RS_OK;
+    if (!z || !iters || !status || !relgrad || !E) return fail(c, RS_ERR_ARG, "NULL output pointer");
+    rs_solve_opts def;
+    rs_default_opts(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
+        o->proj < 0 || o->proj > 2)
+        return fail(c, RS_ERR_ARG, "invalid solver options");
+    NewtonParams p{};
+    p.r = c->r;
+    p.max_iter = o->max_iter;
+    p.ls_max = o->ls_max;
+    p.proj = o->proj;
+    p.c1 = o->c1;
+    p.shrink = o->shrink;
+    p.rel_tol = o->rel_tol;
+    p.abs_tol = o->abs_tol;
+    p.eig_floor = o->eig_floor;
+    return solve_batch(c, B, z, load, p, o->hess ? RS_HESS_EXACT : 0, false, iters, status, relgrad, E, stream);
+}
+
+extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_lbfgs_opts* o,
+                              int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
+    if (B == 0) return RS_OK;
+    if (!z || !iters || !status || !relgrad || !E) return fail(c, RS_ERR_ARG, "NULL output pointer");
+    rs_lbfgs_opts def;
+    rs_default_lbfgs_opts(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->ls_max < 0 || o->history < 0 || o->history > RS_MAX_HISTORY ||
+        !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0))
+        return fail(c, RS_ERR_ARG, "invalid solver options");
+    NewtonParams p{};
+    p.r = c->r;
+    p.max_iter = o->max_iter;
+    p.ls_max = o->ls_max;
+    p.hist = o->history;
+    p.c1 = o->c1;
+    p.shrink = o->shrink;
+    p.rel_tol = o->rel_tol;
+    p.abs_tol = o->abs_tol;
+    return solve_batch(c, B, z, load, p, 0, true, iters, status, relgrad, E, stream);
 }
 
 extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,

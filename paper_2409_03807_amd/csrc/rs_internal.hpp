@@ -154,6 +154,18 @@ struct NewtonState {
 struct NewtonParams {
     int r, max_iter, ls_max, proj;
     double c1, shrink, rel_tol, abs_tol, eig_floor;
+    int hist;         // L-BFGS: pairs kept (<= RS_MAX_HISTORY)
+};
+
+// Per-item L-BFGS history: a ring of RS_MAX_HISTORY (s, y) pairs per item.
+struct LbfgsState {
+    double* S;        // B x RS_MAX_HISTORY x r
+    double* Y;        // B x RS_MAX_HISTORY x r
+    double* sy;       // B x RS_MAX_HISTORY: s.y of each pair
+    int* npair;       // B: pairs held
+    int* head;        // B: ring slot of the oldest pair
+    double* zprev;    // B x r: z where the last direction was taken
+    double* gprev;    // B x r: the gradient there
 };
 
 // ----------------------------------------------------------------- launchers
@@ -180,6 +192,9 @@ hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
+// L-BFGS: exit tests, history update and the two-loop direction (same outputs as launch_newton_dir)
+hipError_t launch_lbfgs_dir(const NewtonState& st, const NewtonParams& p, const LbfgsState& h, int cap,
+                            hipStream_t s);
 // search list, candidate list and candidate points zc
 hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s);
 // Armijo test, then the next evaluation list and the running count, also written to `host` (device address

@@ -2541,6 +2541,143 @@ hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int c
     return hipGetLastError();
 }
 
+// Sum over the wave; every lane ends with the same value (the butterfly adds
+// the same pairs in every lane, and addition is commutative).
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// L-BFGS direction of one item per 64-thread workgroup, lane k holding
+// component k: the exit tests of k_newton_dir, then the pair of the step just
+// accepted (s = z - z_prev, y = g - g_prev, kept only when s.y > 0, the oldest
+// dropped when the ring is full), then the two-loop recursion
+//   q = g; for pairs newest first: a_i = s_i.q / s_i.y_i, q -= a_i y_i;
+//   q *= s_n.y_n / y_n.y_n (newest pair; 1 without pairs);
+//   for pairs oldest first: b = y_i.q / s_i.y_i, q += (a_i - b) s_i;
+// and dz = -q.  All in float64.
+__global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p, LbfgsState h)
+{
+    constexpr int M = RS_MAX_HISTORY;
+    const int i = blockIdx.x, lane = threadIdx.x, r = p.r;
+    if (i >= st.counters[0]) return;
+    const int item = st.eval_list[i];
+    const bool kl = lane < r;
+    const double g = kl ? st.gw[(size_t)i * r + lane] : 0.0;
+    double gn = kl ? fabs(g) : 0.0;
+    int fin = kl ? (isfinite(g) ? 1 : 0) : 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        gn = fmax(gn, __shfl_xor(gn, o));
+        fin = min(fin, __shfl_xor(fin, o));
+    }
+    fin = fin && isfinite(st.E[item]);
+    const int it = st.iters[item];
+    const double g0 = (it == 0) ? gn : st.g0[item];
+    int status = RS_RUNNING;
+    if (!fin) status = RS_NONFINITE;
+    else if (gn <= p.abs_tol || gn <= p.rel_tol * g0) status = RS_CONVERGED;
+    else if (it >= p.max_iter) status = RS_ITER_MAX;
+    if (lane == 0) {
+        if (it == 0) st.g0[item] = gn;
+        st.relgrad[item] = g0 > 0.0 ? gn / g0 : 0.0;
+        if (status != RS_RUNNING) st.status[item] = status;
+    }
+    if (status != RS_RUNNING) return;
+
+    const int m = p.hist;
+    const size_t hb = (size_t)item * M;
+    const double zk = kl ? st.z[(size_t)item * r + lane] : 0.0;
+    int np = (it == 0) ? 0 : h.npair[item];
+    int head = (it == 0) ? 0 : h.head[item];
+    if (it > 0 && m > 0) {
+        const double sv = kl ? zk - h.zprev[(size_t)item * r + lane] : 0.0;
+        const double yv = kl ? g - h.gprev[(size_t)item * r + lane] : 0.0;
+        const double sy = wave_sum(sv * yv);
+        if (sy > 0.0) {
+            int slot;
+            if (np < m) {
+                slot = head + np;
+                if (slot >= m) slot -= m;
+                ++np;
+            } else {
+                slot = head;
+                head = head + 1 == m ? 0 : head + 1;
+            }
+            if (kl) {
+                h.S[(hb + slot) * r + lane] = sv;
+                h.Y[(hb + slot) * r + lane] = yv;
+            }
+            if (lane == 0) h.sy[hb + slot] = sy;
+        }
+    }
+    // the item's pairs, oldest first, in registers
+    double sj[M], yj[M], syj[M], aj[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        int slot = head + j;
+        if (slot >= m) slot -= m;
+        const bool in = j < np;
+        sj[j] = (in && kl) ? h.S[(hb + slot) * r + lane] : 0.0;
+        yj[j] = (in && kl) ? h.Y[(hb + slot) * r + lane] : 0.0;
+        syj[j] = in ? h.sy[hb + slot] : 1.0;
+        aj[j] = 0.0;
+    }
+    double q = g;
+#pragma unroll
+    for (int j = M - 1; j >= 0; --j) {
+        if (j >= np) continue;
+        aj[j] = wave_sum(sj[j] * q) / syj[j];
+        q -= aj[j] * yj[j];
+    }
+    if (np > 0) {
+        double yy = 0.0, syn = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (j == np - 1) {
+                yy = wave_sum(yj[j] * yj[j]);
+                syn = syj[j];
+            }
+        q *= syn / yy;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (j >= np) continue;
+        const double b = wave_sum(yj[j] * q) / syj[j];
+        q += sj[j] * (aj[j] - b);
+    }
+    const double d = kl ? -q : 0.0;
+    const double slope = wave_sum(g * d);
+    if (lane == 0) {
+        h.npair[item] = np;
+        h.head[item] = head;
+        if (!(slope < 0.0)) {
+            st.status[item] = RS_NOT_DESCENT;
+        } else if (p.ls_max <= 0) {
+            st.status[item] = RS_LS_MAX;
+        } else {
+            st.slope[item] = slope;
+            st.ls_j[item] = 0;
+        }
+    }
+    if (kl) {
+        st.dz[(size_t)item * r + lane] = d;
+        h.zprev[(size_t)item * r + lane] = zk;
+        h.gprev[(size_t)item * r + lane] = g;
+    }
+}
+
+hipError_t launch_lbfgs_dir(const NewtonState& st, const NewtonParams& p, const LbfgsState& h, int cap,
+                            hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    if (p.hist < 0 || p.hist > RS_MAX_HISTORY || p.r > 64) return hipErrorInvalidValue;
+    RS_LAUNCH(k_lbfgs_dir, dim3(cap), dim3(64), 0, s, st, p, h);
+    return hipGetLastError();
+}
+
 // Armijo test on the float64 candidate energies: accept the first (largest)
 // step with E(z + a dz) - E(z) <= c1 a g.dz, as sequential backtracking would.
 // End of a super-step in one workgroup: the Armijo test of every searching

@@ -48,6 +48,14 @@ def test_default_opts_and_errors_on_host(lib):
     assert lib.rs_default_opts(C.byref(o)) == 0
     assert (o.max_iter, o.ls_max, o.c1, o.shrink, o.rel_tol, o.hess) == (50, 128, 1e-4, 0.5, 1e-6, 1)
     assert lib.rs_default_opts(None) == 1
+    from paper_2409_03807_amd.binding import LbfgsOpts, MAX_HISTORY
+    lo = LbfgsOpts()
+    assert lib.rs_default_lbfgs_opts(C.byref(lo)) == 0
+    # the paper's exits (Sec. 5): 128 line-search trials, 1024 iterations
+    assert (lo.max_iter, lo.ls_max, lo.history, lo.c1, lo.shrink, lo.rel_tol) == (1024, 128, 10, 1e-4, 0.5, 1e-6)
+    assert lib.rs_default_lbfgs_opts(None) == 1
+    hdr = open(os.path.join(ROOT, "include", "rs.h")).read()
+    assert f"#define RS_MAX_HISTORY {MAX_HISTORY}" in hdr
     lib.rs_last_error.restype = C.c_char_p
     lib.rs_last_error.argtypes = [C.c_void_p]
     assert lib.rs_last_error(None) == b"rs: null context"
@@ -59,4 +67,5 @@ def test_default_opts_and_errors_on_host(lib):
     assert lib.rs_destroy(None) == 0
     # calls on a NULL context report an unusable context
     assert lib.rs_newton_solve(None, 0, None, None, None, None, None, None, None, None) == 4
+    assert lib.rs_lbfgs_solve(None, 0, None, None, None, None, None, None, None, None) == 4
     assert lib.rs_energy_grad_hess(None, 0, None, None, 0, None, None, None, None) == 4

@@ -410,3 +410,86 @@ def test_full_size_sampled(name, B):
     assert relerr(H.cpu().numpy()[idx], Ho).max() < 1e-4
     assert relerr(E.cpu().numpy()[idx, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
     assert torch.isfinite(H).all()
+
+
+# ------------------------------------------------------------------- L-BFGS
+def _compare_lbfgs(p, prec, z0, tg=None, fo=None, opts_kw=None):
+    opts_kw = opts_kw or {}
+    ctx = rb.Context(p, prec=prec, max_batch=max(len(z0), 2))
+    res = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo), opts=rb.default_lbfgs_opts(**opts_kw))
+    o = O.Oracle(p)
+    ores = o.lbfgs(z0, tg, fo, opts=O.default_lbfgs_opts(**opts_kw))
+    r = {k: v.cpu().numpy() for k, v in res.items()}
+    return r, ores, o
+
+
+@pytest.mark.parametrize("name", ["c1", "tinyb"])
+@pytest.mark.parametrize("history", [0, 1, 10, 16])
+def test_lbfgs_float64_first_iterates_match_oracle(name, history):
+    """The first L-BFGS steps (history update, two-loop direction, Armijo) to rounding."""
+    p = problem(name)
+    B = 6
+    z0 = np.vstack([np.zeros((1, p.r)), I.latent_batch(B - 1, p.r)])
+    tg, fo = I.loads_for(p, B)
+    for k in (1, 3, 8):
+        r, ores, _ = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo, dict(max_iter=k, history=history))
+        assert np.array_equal(r["status"], ores["status"])
+        assert np.array_equal(r["iters"], ores["iters"])
+        assert relerr(r["z"], ores["z"], tau=1e-3).max() < 1e-9
+        assert relerr(r["E"][:, None], ores["E"][:, None], tau=1e-6 * energy_scale(p)).max() < 1e-9
+
+
+@pytest.mark.parametrize("name", ["c1", "tinyb"])
+def test_lbfgs_float64_solves_converge_like_oracle(name):
+    p = problem(name)
+    B = 6
+    z0 = np.vstack([np.zeros((1, p.r)), I.latent_batch(B - 1, p.r)])
+    tg, fo = I.loads_for(p, B)
+    r, ores, o = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo)
+    assert np.all(r["status"] == rb.CONVERGED) and np.all(ores["status"] == O.CONVERGED)
+    # whole trajectories of tens of steps amplify rounding: judge the end point
+    g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
+    Eg, gg, _ = o.reduced(r["z"], tg, fo)
+    assert np.all(np.abs(gg).max(axis=1) <= 1e-6 * g0 * (1 + 1e-6))
+    assert relerr(r["E"][:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    same = np.abs(r["E"] - ores["E"]) <= 1e-8 * np.abs(ores["E"]) + 1e-9 * energy_scale(p)
+    assert same.mean() >= 0.8
+    assert np.abs(r["iters"][same] - ores["iters"][same]).max() <= max(3, 0.1 * ores["iters"].max())
+
+
+def test_lbfgs_float32_c2_stationary_for_oracle():
+    p = problem("c2")
+    B = 8
+    z0 = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    ctx = rb.Context(p, prec=rb.PREC_F32, max_batch=B)
+    res = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo))
+    r = {k: v.cpu().numpy() for k, v in res.items()}
+    o = O.Oracle(p)
+    assert np.all(np.isin(r["status"], [rb.CONVERGED, rb.LS_MAX]))
+    assert (r["status"] == rb.CONVERGED).mean() >= 0.75
+    g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
+    Eg, gg, _ = o.reduced(r["z"], tg, fo)
+    conv = r["status"] == rb.CONVERGED
+    assert np.all(np.abs(gg[conv]).max(axis=1) <= 1e-4 * g0[conv])
+    assert relerr(r["E"][:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+
+
+def test_lbfgs_forced_statuses_and_errors():
+    p = problem("tinyb")
+    z0 = I.latent_batch(1, p.r)
+    tg, fo = I.loads_for(p, 1, twist_deg=[120.0])
+    r, ores, _ = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo, dict(max_iter=0))
+    assert r["status"][0] == rb.ITER_MAX == ores["status"][0] and r["iters"][0] == 0
+    r, ores, _ = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo, dict(ls_max=0))
+    assert r["status"][0] == rb.LS_MAX == ores["status"][0]
+    zn = z0.copy(); zn[0, 1] = np.nan
+    r, ores, _ = _compare_lbfgs(p, rb.PREC_F64, zn, tg, fo)
+    assert r["status"][0] == rb.NONFINITE == ores["status"][0]
+    ctx = rb.Context(p, prec=rb.PREC_F64, max_batch=2)
+    with pytest.raises(RuntimeError, match="invalid solver options"):
+        ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo), opts=rb.default_lbfgs_opts(history=rb.MAX_HISTORY + 1))
+    # the history lives in the context: a second solve from the same start repeats the first
+    a = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo))
+    b = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo))
+    assert torch.equal(a["z"], b["z"]) and torch.equal(a["iters"], b["iters"])
