@@ -85,8 +85,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--batch", type=int, default=0, help="override the batch size")
-    ap.add_argument("--cpu-sample", type=int, default=320, help="oracle solves timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="oracle solves timed for cpu_baseline (0 = skip; default 320 Newton, 64 L-BFGS)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
+    ap.add_argument("--solver", default="newton", choices=["newton", "lbfgs"],
+                    help="projective Newton (default) or L-BFGS (the paper's main solver)")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -127,6 +130,8 @@ def main():
            torch.empty(B, dtype=torch.int32, device=dev), torch.empty(B, dtype=torch.float64, device=dev),
            torch.empty(B, dtype=torch.float64, device=dev))
     opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor)
+    lbfgs = args.solver == "lbfgs"
+    lopts = rb.default_lbfgs_opts()
     z1, z2 = z0[0::2].contiguous(), z0[1::2].contiguous()
 
     # per-step bookkeeping stays on the device (no host sync inside the timed
@@ -135,7 +140,10 @@ def main():
     iter_acc = torch.zeros((), dtype=torch.int64, device=dev)
 
     def step():
-        res = ctx.newton_solve(z0, tg, fo, opts=opts, out=out)
+        if lbfgs:
+            res = ctx.lbfgs_solve(z0, tg, fo, opts=lopts, out=out)
+        else:
+            res = ctx.newton_solve(z0, tg, fo, opts=opts, out=out)
         lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False)
         conv_acc.add_((res["status"] == rb.CONVERGED).sum())
         iter_acc.add_(res["iters"].sum())
@@ -198,18 +206,21 @@ def main():
                                             "frac": round(kr["frac"], 4)}
 
     cpu = None
+    if args.cpu_sample < 0:
+        args.cpu_sample = 64 if lbfgs else 320
     if args.cpu_sample > 0:
         from oracle import oracle as O
         n = min(args.cpu_sample, B)
         o = O.Oracle(p)
         zs = z0[:n].cpu().numpy()
         t1 = time.perf_counter()
-        ores = o.newton(zs, tg_np[:n] if tg_np is not None else None, fo_np[:n] if fo_np is not None else None)
+        solve = o.lbfgs if lbfgs else o.newton
+        ores = solve(zs, tg_np[:n] if tg_np is not None else None, fo_np[:n] if fo_np is not None else None)
         cdt = time.perf_counter() - t1
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
         cores = min(cores, len(os.sched_getaffinity(0)))
         cpu = {"value": int((ores["status"] == O.CONVERGED).sum()) / cdt, "unit": "solves/s", "cores": cores,
-               "kind": "oracle", "sample": f"{n} float64 oracle Newton solves of the same workload "
+               "kind": "oracle", "sample": f"{n} float64 oracle {'L-BFGS' if lbfgs else 'Newton'} solves of the same workload "
                                           f"(first {n} start points), {cdt:.1f} s"}
 
     line = {
@@ -229,7 +240,7 @@ def main():
             "workload": f"{name}: {p.meta['nx']}x{p.meta['ny']}x{p.meta['nz']} beam, nv={p.nv}, ne={p.ne}, "
                         f"r={p.r}, hidden={p.hidden}, |S|={len(p.cub_elem)}, B={B}, plain (untrained Glorot) "
                         f"decoder, twist 0-180 deg penalty targets",
-            "batch": B, "rows": info.rows, "subspace": "plain",
+            "batch": B, "rows": info.rows, "subspace": "plain", "solver": args.solver,
         },
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},

@@ -79,7 +79,9 @@ enum { RS_PREC_F64 = 0, RS_PREC_F32 = 1, RS_PREC_BF16 = 2 };
 enum {
     RS_HESS_EXACT = 1,    /* add the decoder-curvature term sum_k g_k d2q_k/dz2 (else Gauss-Newton) */
     RS_ELASTIC_ONLY = 2,  /* cubature elastic potential only (no gravity, penalty, forces) */
-    RS_ENERGY_ONLY = 4    /* energy only; g and H may be NULL */
+    RS_ENERGY_ONLY = 4,   /* energy only; g and H may be NULL */
+    RS_GRAD_REVERSE = 8   /* g by reverse mode (a value pass, then the adjoint pass back through the
+                             decoder) instead of forward-mode Jacobian columns; H must be NULL */
 };
 
 /* Hessian treatment before the Newton solve */
@@ -206,7 +208,9 @@ int rs_decode(rs_ctx* ctx, int32_t B, const double* z, void* x, void* J, void* s
  * points z (B x r) (Sec. 3.1, Sec. 4.3 Eq. form-cubature-gradients and the
  * cubature Hessian of P~).  E is always evaluated in float64; g and H in the
  * context precision with float64 accumulation.  Any B >= 0 (processed in
- * chunks of max_batch). */
+ * chunks of max_batch).  With RS_GRAD_REVERSE (float32 and float64 contexts
+ * with hidden layers) g = J^T grad_q E is formed backwards, never forming J;
+ * other contexts fall back to the forward mode. */
 int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* load,
                         uint32_t flags, double* E, double* g, double* H, void* stream);
 
@@ -232,7 +236,8 @@ int rs_newton_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
  * direction is the two-loop recursion over the last opts->history pairs
  * s = z_{k+1} - z_k, y = g_{k+1} - g_k (a pair is kept only when s.y > 0),
  * with H_0 = (s.y / y.y) I of the newest pair, and -g without pairs.  Only
- * the gradient is evaluated (no Hessian).  Armijo backtracking as in
+ * the gradient is evaluated (no Hessian), by reverse mode where
+ * RS_GRAD_REVERSE applies.  Armijo backtracking as in
  * rs_newton_solve, on float64 energies.  The history lives in the context
  * (allocated by rs_create for max_batch items), so one solve at a time per
  * context. */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "librs.so")
 RS_OK, RS_ERR_ARG, RS_ERR_HIP, RS_ERR_OOM, RS_ERR_STATE, RS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
 CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE, RUNNING = 0, 1, 2, 3, 4, -1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
-HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY = 1, 2, 4
+HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY, GRAD_REVERSE = 1, 2, 4, 8
 PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -250,7 +250,8 @@ class Context:
         E = torch.empty(B, dtype=torch.float64, device=z.device)
         eonly = bool(flags & ENERGY_ONLY)
         g = None if eonly else torch.empty((B, self.r), dtype=torch.float64, device=z.device)
-        H = None if eonly else torch.empty((B, self.r, self.r), dtype=torch.float64, device=z.device)
+        H = None if eonly or (flags & GRAD_REVERSE) else torch.empty((B, self.r, self.r), dtype=torch.float64,
+                                                                         device=z.device)
         self._check(load_library().rs_energy_grad_hess(self.ctx, B, _ptr(z), C.byref(ld), flags, _ptr(E),
                                                        _ptr(g), _ptr(H), _stream()), "rs_energy_grad_hess")
         return E, g, H

@@ -892,6 +892,118 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
     return RS_OK;
 }
 
+// The gradient g = J^T grad_q E by reverse mode: a value pass of the decoder
+// (pre-activations kept), the value rows of the output map, the element
+// kernel for E and the adjoint seeds d = dE/d(row), W_big^T d, and the
+// reverse pass back through the hidden layers.  No Jacobian column is formed.
+static bool grad_reverse_ok(const rs_ctx* c) { return c->L > 0 && !c->bf16 && mlp_fits(c->f32, 1, c->r, c->wrows); }
+
+static int eval_grad_rev(rs_ctx* c, int cap, const int* count, const double* z, const int* zmap,
+                         const double* targets, const double* force, const int* imap, uint32_t flags, double* E,
+                         double* g, hipStream_t s)
+{
+    const int r = c->r;
+    const int f32 = c->f32;
+    const size_t ts = c->tsz;
+    const int slot = c->cur_slot;
+    RS_TRY(hidden_layers(c, f32, 1, cap, count, 0, z, zmap, c->pre.data(), c->act, c->W.data(), c->bh.data(),
+                         K_GEMM_HIDDEN, s));
+    {
+        GemmArgs a{};
+        a.A = c->Wbig;
+        a.lda = c->lda_out;
+        a.rows = c->M;
+        a.rows_pad = c->Mp;
+        a.K = c->in_last;
+        a.nc = 1;
+        a.items = cap;
+        a.count = count;
+        a.in_mode = IN_RAW_T;
+        a.Y = c->act;
+        a.y_rows = c->wrows;
+        a.r = r;
+        a.bias = c->bbig;
+        a.out_mode = OUT_PACK;
+        a.C = c->out;
+        RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, 1, count, slot, 0), s, [&] {
+            return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_OUT, a, 8 * c->n_cu, s)
+                                         : launch_gemm(f32, ROLE_OUT, a, s);
+        }));
+    }
+    {
+        ElemArgs a{};
+        a.out = c->out;
+        a.rows_pad = c->Mp;
+        a.nc = 1;
+        a.r = 0;
+        a.S = c->S;
+        a.nt = c->nt;
+        a.nf = c->nf;
+        a.count = count;
+        a.wV = c->wV;
+        a.Xt = c->Xt;
+        a.targets = c->nt ? targets : nullptr;
+        a.force = c->nf ? force : nullptr;
+        a.imap = imap;
+        a.mu = c->mu;
+        a.lam = c->lam;
+        a.k_c = c->k_c;
+        a.elastic_only = (flags & RS_ELASTIC_ONLY) ? 1 : 0;
+        a.grav_row = c->grav_row;
+        a.force_row = c->force_row;
+        a.E = E;
+        a.dseed = c->dseed;
+        const double pb = (double)c->M * ts + (double)c->Mp * ts + 8.0;
+        const double pf = (double)c->S * 150.0;
+        RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_elem(f32, a, cap, s); }));
+    }
+    {
+        GemmArgs a{};
+        a.A = c->WbigT;
+        a.lda = c->Mp;
+        a.rows = c->in_last;
+        a.rows_pad = c->in_rows;
+        a.K = c->Mp;
+        a.nc = 1;
+        a.items = cap;
+        a.count = count;
+        a.in_mode = IN_RAW;
+        a.Y = c->dseed;
+        a.y_rows = c->Mp;
+        a.r = r;
+        a.out_mode = OUT_PACK;
+        a.C = c->gbar;
+        a.ksplit = c->ksplit;
+        a.split_stride = (size_t)c->max_batch * c->in_rows;
+        RS_TRY(run(c, K_GEMM_ADJ, gemm_work(ts, c->in_last, c->Mp, cap, 1, count, slot, 0), s,
+                   [&] { return launch_gemm(f32, ROLE_ADJ, a, s); }));
+    }
+    CurvArgs ca{};
+    for (int l = 0; l < c->L; ++l) {
+        ca.pre[l] = c->pre[l];
+        ca.W[l] = c->W[l];
+    }
+    // value-only blocks of the fused kernel: unit u at u (one column)
+    ca.pre_su = 1;
+    ca.pre_sc = c->wrows;
+    ca.gbar = c->gbar;
+    ca.ksplit = c->ksplit;
+    ca.split_stride = (size_t)c->max_batch * c->in_rows;
+    ca.L = c->L;
+    ca.width = c->w;
+    ca.nc = 1;
+    ca.r = r;
+    ca.pre_rows = c->wrows;
+    ca.lda0 = c->lda0;
+    ca.lda = c->lda_h;
+    ca.count = count;
+    ca.H = nullptr;
+    ca.grev = g;
+    const double pb = (double)c->L * c->w * ts + (double)c->ksplit * c->in_rows * ts + 8.0 * r;
+    const double pf = (double)c->L * 2.0 * c->w * c->w;
+    return run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); });
+}
+
 // float64 value-only decoder and energy for `cap` items (count on the device
 // when non-NULL).  Item i uses latent point z[i] and the loads of imap[i].
 static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const double* z, const double* targets,
@@ -960,6 +1072,8 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
     if (!z || !E) return fail(c, RS_ERR_ARG, "z and E must not be NULL");
     const bool eonly = flags & RS_ENERGY_ONLY;
     if (!eonly && !g) return fail(c, RS_ERR_ARG, "g must not be NULL unless RS_ENERGY_ONLY");
+    if ((flags & RS_GRAD_REVERSE) && H) return fail(c, RS_ERR_ARG, "RS_GRAD_REVERSE takes H == NULL");
+    const bool rev = (flags & RS_GRAD_REVERSE) && grad_reverse_ok(c);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double* tg = load ? load->targets : nullptr;
     const double* fo = load ? load->force : nullptr;
@@ -970,7 +1084,10 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
         const double* zc = z + (size_t)c0 * r;
         const double* tgc = tg ? tg + (size_t)c0 * c->nt * 3 : nullptr;
         const double* foc = fo ? fo + (size_t)c0 * 3 : nullptr;
-        if (!eonly)
+        if (!eonly && rev)
+            RS_TRY(eval_grad_rev(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0,
+                                 g + (size_t)c0 * r, s));
+        else if (!eonly)
             RS_TRY(eval_T(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0,
                           g + (size_t)c0 * r, H ? H + (size_t)c0 * r * r : nullptr, s));
         if (eonly || c->f32)
@@ -1094,8 +1211,11 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
     int n_run = B;
     for (long step = 0; step < max_steps; ++step) {
         RS_TRY(log_counters(c, s));
-        RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw,
-                      lbfgs ? nullptr : c->Hw, s));
+        if (lbfgs && grad_reverse_ok(c))
+            RS_TRY(eval_grad_rev(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw, s));
+        else
+            RS_TRY(eval_T(c, n_run, cnt + 0, z, c->eval_list, tg, fo, c->eval_list, flags, nullptr, c->gw,
+                          lbfgs ? nullptr : c->Hw, s));
         if (lbfgs) {
             const double m = p.hist;
             RS_TRY(run(c, K_LBFGS, item_work(8.0 * (5 * r + 2 * m * r), 8.0 * m * r, n_run, cnt + 0, c->cur_slot, 0),

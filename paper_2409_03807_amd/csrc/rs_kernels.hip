@@ -1740,8 +1740,9 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
-    // r <= 16: the MFMA path (16 columns per tet); r <= 32: 32 lanes per tet (VALU)
-    const int rp = a.r <= 16 ? 16 : 32;
+    // r <= 16: the MFMA path (16 columns per tet); r <= 32: 32 lanes per tet (VALU);
+    // r == 0 (value rows only: energy and adjoint seeds): 4 lanes per tet, 64 tets a round
+    const int rp = a.r == 0 ? 4 : a.r <= 16 ? 16 : 32;
     // one round's tile must fit the staging buffer and the prefetch registers
     if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
     dim3 grid(items), block(256);
@@ -1886,7 +1887,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             ga[u] = gh[u] * elu1(av);
         }
         __syncthreads();
-        {
+        if (a.H) {
             acc_t acc[RT][RT];
 #pragma unroll
             for (int ti = 0; ti < RT; ++ti)
@@ -1957,6 +1958,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             else a.grev[(size_t)item * r + u] = o;
         }
     }
+    if (!a.H) return; // gradient only
     // the four waves' partial sums, added in wave order
     __syncthreads();
 #pragma unroll

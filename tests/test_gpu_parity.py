@@ -493,3 +493,20 @@ def test_lbfgs_forced_statuses_and_errors():
     a = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo))
     b = ctx.lbfgs_solve(t64(z0), t64(tg), t64(fo))
     assert torch.equal(a["z"], b["z"]) and torch.equal(a["iters"], b["iters"])
+
+
+@pytest.mark.parametrize("name,prec", [("tinyb", rb.PREC_F64), ("c1", rb.PREC_F64), ("c2", rb.PREC_F32),
+                                       ("c2", rb.PREC_F64), ("tinyb", rb.PREC_F32)])
+@pytest.mark.parametrize("flags", [0, rb.ELASTIC_ONLY])
+def test_reverse_mode_gradient(name, prec, flags):
+    """g = J^T grad_q E formed backwards (value pass, adjoint seeds, reverse pass) against the oracle."""
+    p = problem(name)
+    B = 7
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    ctx = rb.Context(p, prec=prec, max_batch=4)  # B > max_batch: chunked, ragged last chunk
+    E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=flags | rb.GRAD_REVERSE)
+    assert H is None
+    Eo, go, _ = O.Oracle(p).reduced(z, tg, fo, flags=O.ELASTIC_ONLY if flags else 0)
+    assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    assert relerr(g.cpu().numpy(), go).max() < TOL[prec]
