@@ -808,7 +808,9 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         }
         RS_TRY(run(c, K_GEMM_OUT, gemm_work(ts, c->M, a.K, cap, nc, count, slot, 0), s, [&] {
             if (c->bf16) return launch_gemm_p_bf16(ROLE_OUT, a, 8 * c->n_cu, s);
-            return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_OUT, a, 8 * c->n_cu, s)
+            // twelve workgroups per compute unit: the best of 3..12 per CU measured for the
+            // 2560 x 128 map at B = 1024 (fewer leave the A-fragment loads exposed)
+            return gemm_p_fits(f32, a.K) ? launch_gemm_p(f32, ROLE_OUT, a, 12 * c->n_cu, s)
                                          : launch_gemm(f32, ROLE_OUT, a, s);
         }));
     }

@@ -1412,6 +1412,9 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 #pragma unroll
     for (int j = 0; j < RP; ++j) Hc[j] = 0.0;
     double Hm[4] = {0.0, 0.0, 0.0, 0.0}; // MFMA result layout (RP == 16 path)
+    // the RP == 16 path accumulates H on the matrix cores across all of the
+    // wave's rounds (4 tets or targets per MFMA step), in T; Hm takes it at the end
+    typename Mfma<T>::acc_t hsum = {0, 0, 0, 0};
     double gk = 0.0, Ee = 0.0;
 
     const int span = 9 * nc;
@@ -1535,21 +1538,20 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 #pragma unroll
                     for (int v = 0; v < 9; ++v) gp += Kc[v] * P[v];
                     gk += wV * (double)gp;
-                    if (k == 0) Ee += wV * (double)m.psi;
-                    if (dseed) {
-#pragma unroll
-                        for (int v = 0; v < 9; ++v) // lane k writes v = k (mod RP); v static keeps P in registers
-                            if (v % RP == k) global_store_asm(dseed + 9 * s + v, (T)(wV * (double)P[v]));
-                    }
+                    Ee += k == 0 ? wV * (double)m.psi : 0.0;
                     const T wt = (T)wV;
+                    if (dseed) {
+                        // lane k < 9 writes seed v = k (a select chain keeps P in registers)
+                        T pv = P[0];
+#pragma unroll
+                        for (int v = 1; v < 9; ++v) pv = k == v ? P[v] : pv;
+                        if (k < 9) global_store_asm(dseed + 9 * s + k, wt * pv);
+                    }
 #pragma unroll
                     for (int v = 0; v < 9; ++v) AK[v] *= wt;
                 }
-                typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
 #pragma unroll
-                for (int v = 0; v < 9; ++v) hacc = Mfma<T>::mac(Kc[v], AK[v], hacc);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
+                for (int v = 0; v < 9; ++v) hsum = Mfma<T>::mac(Kc[v], AK[v], hsum);
             } else if (s < a.S) {
                 const T* row = tile + el * span;
                 T gu[9], Kc[9];
@@ -1611,12 +1613,9 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 }
             }
             if constexpr (RP == 16) {
-                typename Mfma<T>::acc_t hacc = {0, 0, 0, 0};
                 const T kt = (T)kc;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) hacc = Mfma<T>::mac(Jc[c], kt * Jc[c], hacc);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Hm[q] += (double)hacc[q];
+                for (int c = 0; c < 3; ++c) hsum = Mfma<T>::mac(Jc[c], kt * Jc[c], hsum);
             }
             if (ok) {
                 if constexpr (RP != 16) {
@@ -1631,11 +1630,10 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                     }
                 }
                 gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
-                if (k == 0) Ee += 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-                if (dseed) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        if (c % RP == k) global_store_asm(dseed + prow + 3 * t + c, (T)(kc * d[c]));
+                Ee += k == 0 ? 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0;
+                if (dseed && k < 3) {
+                    const double dv = k == 0 ? d[0] : k == 1 ? d[1] : d[2];
+                    global_store_asm(dseed + prow + 3 * t + k, (T)(kc * dv));
                 }
             }
         }
@@ -1678,6 +1676,10 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         }
     }
 
+    if constexpr (RP == 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Hm[q] = (double)hsum[q];
+    }
     // reduce over the EPW tets of a wave (lanes k, k+RP, ...), then over the
     // waves in order: wave 0 keeps the running sum, waves 1..3 pass theirs
     // through the (now idle) first ring slot in turn
