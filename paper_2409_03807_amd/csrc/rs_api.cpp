@@ -97,6 +97,8 @@ struct rs_ctx {
     double *Ew = nullptr, *gw = nullptr, *Hw = nullptr;
     double *g0 = nullptr, *dz = nullptr, *slope = nullptr;
     LbfgsState lb{};              // L-BFGS history, max_batch items
+    double* Hpart = nullptr;      // 2 n_cu x r x r: element-kernel partials when an item's rounds are split
+    double* gpart = nullptr;      // 2 n_cu x r
     int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
     int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
     int ksplit = 1;               // K slices of the adjoint GEMM
@@ -576,6 +578,8 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
             c->n_cu = ncu;
     }
     c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
+    c->Hpart = (double*)need(dalloc<double>(c, (size_t)2 * c->n_cu * c->r * c->r));
+    c->gpart = (double*)need(dalloc<double>(c, (size_t)2 * c->n_cu * c->r));
     c->Ew = (double*)need(dalloc<double>(c, B));
     c->gw = (double*)need(dalloc<double>(c, B * c->r));
     c->Hw = (double*)need(dalloc<double>(c, B * c->r * c->r));
@@ -815,6 +819,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         }));
     }
     const bool exact = (flags & RS_HESS_EXACT) && c->L > 0 && H;
+    int split = 1;
     {
         ElemArgs a{};
         a.out = c->out;
@@ -840,6 +845,20 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.g = g;
         a.H = H;
         a.dseed = exact ? c->dseed : nullptr;
+        // A small batch splits each item's rounds over several workgroups (the
+        // curvature pass sums their partial g and H), so that the element
+        // kernel's per-item latency does not set the launch's duration.
+        a.parts = 1;
+        if (exact && !E && g && cap > 0) {
+            const int parts = std::min(8, 2 * c->n_cu / cap);
+            if (parts > 1) {
+                a.parts = parts;
+                a.part_stride = cap;
+                a.g = c->gpart;
+                a.H = c->Hpart;
+            }
+        }
+        split = a.parts;
         // algorithmic bytes: read the item's rows once, write seeds and (E, g, H)
         const double pb = (double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) + 8.0 * (1 + r + r * r);
         const double pf = (double)c->S * (18.0 * r * r + 80.0 * r + 150.0);
@@ -887,6 +906,13 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         ca.count = count;
         ca.H = H;
         ca.grev = nullptr;
+        if (split > 1) {
+            ca.parts = split;
+            ca.part_stride = cap;
+            ca.Hp = c->Hpart;
+            ca.gp = c->gpart;
+            ca.g = g;
+        }
         const double pb = (double)c->L * c->w * nc * ts + (double)c->ksplit * c->in_rows * ts + 16.0 * r * r;
         const double pf = (double)c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w);
         RS_TRY(run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); }));
@@ -955,6 +981,7 @@ static int eval_grad_rev(rs_ctx* c, int cap, const int* count, const double* z, 
         a.force_row = c->force_row;
         a.E = E;
         a.dseed = c->dseed;
+        a.parts = 1;
         const double pb = (double)c->M * ts + (double)c->Mp * ts + 8.0;
         const double pf = (double)c->S * 150.0;
         RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_elem(f32, a, cap, s); }));

@@ -90,6 +90,8 @@ struct ElemArgs {
     double* g;            // items x r (may be NULL)
     double* H;            // items x r x r (may be NULL)
     void* dseed;          // items x rows_pad adjoint seeds dE/d(row value) (may be NULL)
+    int parts;            // workgroups per item (>= 1): each takes a run of the item's rounds
+    int part_stride;      // parts > 1: g and H of part p of item i at slot p * part_stride + i (E must be NULL)
 };
 
 struct EnergyArgs {
@@ -122,6 +124,12 @@ struct CurvArgs {
     const int* count;       // actual item count (NULL = grid size)
     double* H;              // items x r x r, accumulated
     double* grev;           // items x r reverse-mode gradient (may be NULL)
+    // parts > 1: H and g come as element-kernel partials (slot p * part_stride + i) that are summed
+    // in part order into H (before the curvature term is added) and g
+    int parts, part_stride;
+    const double* Hp;
+    const double* gp;
+    double* g;
 };
 
 // Per-item Newton state.  ls_j[b] < 0: the item needs its gradient and Hessian

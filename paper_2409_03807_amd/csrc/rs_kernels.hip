@@ -1391,7 +1391,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     __shared__ __align__(16) T ring1[SLOT];
     __shared__ __align__(16) T ring2[SLOT];
     __shared__ __align__(16) double side0[SIDEW / 2], side1[SIDEW / 2], side2[SIDEW / 2];
-    const int item = blockIdx.x;
+    const int item = blockIdx.x / a.parts, part = blockIdx.x - item * a.parts;
     if (a.count && item >= *a.count) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1421,6 +1421,9 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     const int tet_rounds = (a.S + EPR - 1) / EPR;
     const int pen_rounds = tg ? (a.nt + EPR - 1) / EPR : 0;
     const int rounds = tet_rounds + pen_rounds;
+    // this workgroup's run of the item's rounds
+    const int per = (rounds + a.parts - 1) / a.parts;
+    const int rbeg = min(rounds, part * per), rend = min(rounds, rbeg + per);
     // value range [v0, v1) of round rd within the item block
     auto range = [&](int rd, int& v0, int& v1) {
         if (rd < tet_rounds) {
@@ -1497,14 +1500,14 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         // NI + NS loads were issued after round rd's (the stores in between
         // can only lower the count).  The barrier then makes every wave's part
         // visible and frees the slot of round rd - 1.
-        if (rd + 1 < rounds)
+        if (rd + 1 < rend)
             wait_vm_lgkm<NI + NS>();
         else
             wait_vm_lgkm<0>();
         asm volatile("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        if (rd + 2 < rounds) issue(NextSlot{}, rd + 2);
+        if (rd + 2 < rend) issue(NextSlot{}, rd + 2);
         int v0, v1;
         range(rd, v0, v1);
         const T* tile = ring_of(sl) + (v0 - (v0 & ~(VN - 1)));
@@ -1639,15 +1642,15 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         }
     };
 
-    if (rounds > 0) issue(std::integral_constant<int, 0>{}, 0);
-    if (rounds > 1) issue(std::integral_constant<int, 1>{}, 1);
-    for (int rd = 0; rd < rounds; rd += 3) {
+    if (rend > rbeg) issue(std::integral_constant<int, 0>{}, rbeg);
+    if (rend > rbeg + 1) issue(std::integral_constant<int, 1>{}, rbeg + 1);
+    for (int rd = rbeg; rd < rend; rd += 3) {
         body(std::integral_constant<int, 0>{}, rd);
-        if (rd + 1 < rounds) body(std::integral_constant<int, 1>{}, rd + 1);
-        if (rd + 2 < rounds) body(std::integral_constant<int, 2>{}, rd + 2);
+        if (rd + 1 < rend) body(std::integral_constant<int, 1>{}, rd + 1);
+        if (rd + 2 < rend) body(std::integral_constant<int, 2>{}, rd + 2);
     }
 
-    if (ext && wave == 0 && eg == 0) {
+    if (ext && part == 0 && wave == 0 && eg == 0) {
         const size_t gr = (size_t)a.grav_row;
         gk -= kact ? (double)O[gr * nc + 1 + k] : 0.0;
         if (k == 0) Ee -= (double)O[gr * nc];
@@ -1660,7 +1663,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             }
         }
     }
-    if (dseed) {
+    if (dseed && part == 0) {
         // rows not written above: penalty rows without targets, gravity,
         // force and padding rows
         for (int row = prow + tid; row < a.rows_pad; row += 256) {
@@ -1721,20 +1724,21 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         }
     }
     if (wave == 0) {
+        const size_t slot = (size_t)part * a.part_stride + item; // = item with one part
         if constexpr (RP == 16) {
             if (a.H) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int j = Mfma<T>::row(lane, q), kk = lane & 15;
-                    if (j < r && kk < r) a.H[(size_t)item * r * r + j * r + kk] = Hm[q];
+                    if (j < r && kk < r) a.H[slot * r * r + j * r + kk] = Hm[q];
                 }
             }
         } else if (eg == 0 && kact && a.H) {
 #pragma unroll
             for (int j = 0; j < RP; ++j)
-                if (j < r) a.H[(size_t)item * r * r + j * r + k] = Hc[j];
+                if (j < r) a.H[slot * r * r + j * r + k] = Hc[j];
         }
-        if (eg == 0 && kact && a.g) a.g[(size_t)item * r + k] = gk;
+        if (eg == 0 && kact && a.g) a.g[slot * r + k] = gk;
         if (lane == 0 && a.E) a.E[item] = Ee;
     }
 }
@@ -1742,13 +1746,16 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
+    if (a.parts > 1 && (a.E || a.part_stride < items)) return hipErrorInvalidValue;
+    ElemArgs b = a;
+    if (b.parts < 1) b.parts = 1;
     // r <= 16: the MFMA path (16 columns per tet); r <= 32: 32 lanes per tet (VALU);
     // r == 0 (value rows only: energy and adjoint seeds): 4 lanes per tet, 64 tets a round
     const int rp = a.r == 0 ? 4 : a.r <= 16 ? 16 : 32;
     // one round's tile must fit the staging buffer and the prefetch registers
     if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
-    dim3 grid(items), block(256);
-#define RS_ELEM(T, RP) RS_LAUNCH((k_elem<T, RP>), grid, block, 0, s, a)
+    dim3 grid(items * b.parts), block(256);
+#define RS_ELEM(T, RP) RS_LAUNCH((k_elem<T, RP>), grid, block, 0, s, b)
     if (f32) {
         switch (rp) {
         case 4: RS_ELEM(float, 4); break;
@@ -1960,6 +1967,11 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             else a.grev[(size_t)item * r + u] = o;
         }
     }
+    if (a.parts > 1 && tid < r) {
+        double gs = 0.0;
+        for (int q = 0; q < a.parts; ++q) gs += a.gp[((size_t)q * a.part_stride + item) * r + tid];
+        a.g[(size_t)item * r + tid] = gs;
+    }
     if (!a.H) return; // gradient only
     // the four waves' partial sums, added in wave order
     __syncthreads();
@@ -1980,7 +1992,17 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
                     auto at = [&](int q) { return red[(((q * RT + ti) * RT + tj) * 4 + v) * 64 + lane]; };
                     const double h = ((at(0) + at(1)) + at(2)) + at(3);
                     const int row = 16 * ti + Mfma<T>::row(lane, v), col = 16 * tj + c;
-                    if (row < r && col < r) a.H[(size_t)item * r * r + row * r + col] += h;
+                    if (row < r && col < r) {
+                        const size_t e = (size_t)row * r + col;
+                        if (a.parts > 1) {
+                            // the element kernel's partials, in part order, then the curvature
+                            double hs = 0.0;
+                            for (int q = 0; q < a.parts; ++q) hs += a.Hp[((size_t)q * a.part_stride + item) * r * r + e];
+                            a.H[(size_t)item * r * r + e] = hs + h;
+                        } else {
+                            a.H[(size_t)item * r * r + e] += h;
+                        }
+                    }
                 }
     }
 }
