@@ -802,11 +802,127 @@ static void gemm_dispatch(int role, dim3 grid, const GemmArgs& a, hipStream_t s)
     }
 }
 
+// Adjoint product C[z] = A * Y over the K slice z for one-column items
+// (IN_RAW, nc = 1, OUT_PACK): every global load of the workgroup's slice (KS
+// 32-deep chunks) is issued at once, so its latency is paid once rather than
+// once per chunk; the chunks then pass through a double-buffered LDS tile.
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void k_gemm_adj(GemmArgs a)
+{
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
+    constexpr int LD = kTileK + VN;
+    __shared__ __align__(16) T As[2][kTileM * LD];
+    __shared__ __align__(16) T Ys[2][kTileN * LD];
+    const int items = a.count ? min(*a.count, a.items) : a.items;
+    const int n0 = blockIdx.y * kTileN;
+    if (n0 >= items) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int m0 = blockIdx.x * kTileM;
+    const int kbeg = blockIdx.z * KS * kTileK, kend = min(a.K, kbeg + KS * kTileK);
+    const T* A = static_cast<const T*>(a.A);
+    const T* Y = static_cast<const T*>(a.Y);
+    const int arow = tid >> 2, akq = (tid & 3) * 8;
+    const int ynn = tid & 63, ykb = (tid >> 6) * 8;
+    const bool ycol = n0 + ynn < items;
+    V ra[KS][8 / VN], ry[KS][8 / VN];
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+        const int k0 = kbeg + c * kTileK;
+        const bool in = k0 < kend; // K is a multiple of the chunk, so a chunk is whole or absent
+        const V* sa = reinterpret_cast<const V*>(A + (size_t)(m0 + arow) * a.lda + (in ? k0 : 0) + akq);
+        const V* sy = reinterpret_cast<const V*>(Y + (size_t)(ycol ? n0 + ynn : 0) * a.y_rows + (in ? k0 : 0) + ykb);
+#pragma unroll
+        for (int q = 0; q < 8 / VN; ++q) {
+            ra[c][q] = sa[q];
+            ry[c][q] = sy[q];
+        }
+    }
+    using acc_t = typename Mfma<T>::acc_t;
+    acc_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < KS; ++c) {
+        if (kbeg + c * kTileK >= kend) break;
+        T* as = As[c & 1];
+        T* ys = Ys[c & 1];
+#pragma unroll
+        for (int q = 0; q < 8 / VN; ++q) {
+            reinterpret_cast<V*>(as + arow * LD + akq)[q] = ra[c][q];
+            V w = ry[c][q];
+            if (!ycol) w = V{};
+            reinterpret_cast<V*>(ys + ynn * LD + ykb)[q] = w;
+        }
+        __syncthreads();
+        T af[8], bf[4][8];
+        {
+            const V* sa = reinterpret_cast<const V*>(as + (wave * 16 + li) * LD + 8 * lg);
+#pragma unroll
+            for (int q = 0; q < 8 / VN; ++q) {
+                const V w = sa[q];
+#pragma unroll
+                for (int e = 0; e < VN; ++e) af[q * VN + e] = w[e];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const V* sb = reinterpret_cast<const V*>(ys + (t * 16 + li) * LD + 8 * lg);
+#pragma unroll
+                for (int q = 0; q < 8 / VN; ++q) {
+                    const V w = sb[q];
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[kk], bf[t][kk], acc[t]);
+    }
+    T* Cout = static_cast<T*>(a.C) + blockIdx.z * a.split_stride;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int item = n0 + t * 16 + li;
+        if (item >= items) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = m0 + wave * 16 + Mfma<T>::row(lane, v);
+            if (m < a.rows) Cout[(size_t)item * a.rows_pad + m] = acc[t][v];
+        }
+    }
+}
+
+template <typename T>
+static hipError_t gemm_adj_dispatch(const GemmArgs& a, dim3 grid, int ks, hipStream_t s)
+{
+    switch (ks) {
+    case 1: RS_LAUNCH((k_gemm_adj<T, 1>), grid, dim3(256), 0, s, a); break;
+    case 2: RS_LAUNCH((k_gemm_adj<T, 2>), grid, dim3(256), 0, s, a); break;
+    case 3: RS_LAUNCH((k_gemm_adj<T, 3>), grid, dim3(256), 0, s, a); break;
+    case 4: RS_LAUNCH((k_gemm_adj<T, 4>), grid, dim3(256), 0, s, a); break;
+    case 5: RS_LAUNCH((k_gemm_adj<T, 5>), grid, dim3(256), 0, s, a); break;
+    case 6: RS_LAUNCH((k_gemm_adj<T, 6>), grid, dim3(256), 0, s, a); break;
+    case 7: RS_LAUNCH((k_gemm_adj<T, 7>), grid, dim3(256), 0, s, a); break;
+    case 8: RS_LAUNCH((k_gemm_adj<T, 8>), grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s)
 {
     if (a.items <= 0) return hipSuccess;
     const long ncols = (long)a.items * a.nc;
     dim3 grid(a.rows_pad / kTileM, (unsigned)((ncols + kTileN - 1) / kTileN), a.ksplit > 1 ? a.ksplit : 1);
+    if (role == ROLE_ADJ && a.nc == 1 && a.in_mode == IN_RAW && a.out_mode == OUT_PACK && a.K % kTileK == 0 &&
+        a.y_rows % 8 == 0 && a.lda % 8 == 0) {
+        // the slice of a K split: the same chunk count as the generic kernel's
+        const int ks = a.ksplit > 1 ? a.ksplit : 1;
+        const int kchunk = ((a.K + ks - 1) / ks + kTileK - 1) / kTileK;
+        if (kchunk <= 8) return f32 ? gemm_adj_dispatch<float>(a, grid, kchunk, s) : gemm_adj_dispatch<double>(a, grid, kchunk, s);
+    }
     if (f32) gemm_dispatch<float>(role, grid, a, s);
     else gemm_dispatch<double>(role, grid, a, s);
     return hipGetLastError();
@@ -1892,8 +2008,10 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
         __syncthreads(); // gh of this layer visible; cf, ga, part free
         for (int u = tid; u < w; u += 256) {
             const double av = (double)P[(size_t)u * su];
-            cf[u] = gh[u] * elu2(av);
-            ga[u] = gh[u] * elu1(av);
+            // s'(a) and s''(a) share exp(a) for a <= 0 (1 and 0 above)
+            const double ex = exp(fmin(av, 0.0));
+            cf[u] = av > 0.0 ? 0.0 : gh[u] * ex;
+            ga[u] = av > 0.0 ? gh[u] : gh[u] * ex;
         }
         __syncthreads();
         if (a.H) {
