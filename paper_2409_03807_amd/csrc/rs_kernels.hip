@@ -1984,7 +1984,21 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     const int pw = w > r ? w : r; // outputs of W_l^T ga: w, or r for the first layer
     double* part = cf + w;        // [8 slices][pw] partial sums of W_l^T ga
     double* red = part + 8 * pw;  // [4 waves][RT][RT][4][64] per-wave H partials
+    double* hpart = red + 4 * RT * RT * 4 * 64; // parts > 1: the element kernel's H summed over parts
     const int c = lane & 15, kq = lane >> 4;
+    if (a.parts > 1) {
+        // summed here, at the start, so that the loads overlap the layer loop
+        for (int e = tid; e < r * r; e += 256) {
+            double hs = 0.0;
+            for (int q = 0; q < a.parts; ++q) hs += a.Hp[((size_t)q * a.part_stride + item) * r * r + e];
+            hpart[e] = hs;
+        }
+        if (tid < r) {
+            double gs = 0.0;
+            for (int q = 0; q < a.parts; ++q) gs += a.gp[((size_t)q * a.part_stride + item) * r + tid];
+            a.g[(size_t)item * r + tid] = gs;
+        }
+    }
     for (int u = tid; u < w; u += 256) {
         double sum = 0.0;
         const T* gp = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows + u;
@@ -2085,11 +2099,6 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             else a.grev[(size_t)item * r + u] = o;
         }
     }
-    if (a.parts > 1 && tid < r) {
-        double gs = 0.0;
-        for (int q = 0; q < a.parts; ++q) gs += a.gp[((size_t)q * a.part_stride + item) * r + tid];
-        a.g[(size_t)item * r + tid] = gs;
-    }
     if (!a.H) return; // gradient only
     // the four waves' partial sums, added in wave order
     __syncthreads();
@@ -2113,10 +2122,8 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
                     if (row < r && col < r) {
                         const size_t e = (size_t)row * r + col;
                         if (a.parts > 1) {
-                            // the element kernel's partials, in part order, then the curvature
-                            double hs = 0.0;
-                            for (int q = 0; q < a.parts; ++q) hs += a.Hp[((size_t)q * a.part_stride + item) * r * r + e];
-                            a.H[(size_t)item * r * r + e] = hs + h;
+                            // the element kernel's partials (summed in part order), then the curvature
+                            a.H[(size_t)item * r * r + e] = hpart[e] + h;
                         } else {
                             a.H[(size_t)item * r * r + e] += h;
                         }
@@ -2132,7 +2139,7 @@ hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
     if (a.width > kCurvMaxW) return hipErrorInvalidValue;
     const int rt = a.r <= 16 ? 1 : 2;
     const size_t pw = (size_t)(a.width > a.r ? a.width : a.r);
-    const size_t sh = sizeof(double) * (3 * (size_t)a.width + 8 * pw + 4 * rt * rt * 4 * 64);
+    const size_t sh = sizeof(double) * (3 * (size_t)a.width + 8 * pw + 4 * rt * rt * 4 * 64 + (size_t)a.r * a.r);
     if (rt == 1) {
         if (f32) RS_LAUNCH((k_curv<float, 1>), dim3(items), dim3(256), sh, s, a);
         else RS_LAUNCH((k_curv<double, 1>), dim3(items), dim3(256), sh, s, a);
