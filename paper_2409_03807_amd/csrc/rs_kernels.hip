@@ -2701,6 +2701,29 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+// DPP move of a double within 16-lane rows (ctrl: a DPP control word)
+template <int CTRL>
+__device__ inline double dpp_f64(double x)
+{
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false));
+}
+
+// Sum of lanes 0..15 (the other lanes' values are ignored), the same in every
+// lane: within each 16-lane row, pairs (quad_perm 1,0,3,2), quads (quad_perm
+// 2,3,0,1), half rows (row_half_mirror) and rows (row_mirror) are added, all
+// in DPP; row 0's total is then read out of lane 0.
+__device__ inline double row0_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                            __builtin_amdgcn_readlane(__double2loint(v), 0));
+}
+
 // L-BFGS direction of one item per 64-thread workgroup, lane k holding
 // component k: the exit tests of k_newton_dir, then the pair of the step just
 // accepted (s = z - z_prev, y = g - g_prev, kept only when s.y > 0, the oldest
@@ -2716,6 +2739,8 @@ __global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p
     if (i >= st.counters[0]) return;
     const int item = st.eval_list[i];
     const bool kl = lane < r;
+    // lanes 0..15 hold every component when r <= 16: row-local DPP sums
+    auto vsum = [&](double x) { return r <= 16 ? row0_sum(x) : wave_sum(x); };
     const double g = kl ? st.gw[(size_t)i * r + lane] : 0.0;
     double gn = kl ? fabs(g) : 0.0;
     int fin = kl ? (isfinite(g) ? 1 : 0) : 1;
@@ -2746,7 +2771,7 @@ __global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p
     if (it > 0 && m > 0) {
         const double sv = kl ? zk - h.zprev[(size_t)item * r + lane] : 0.0;
         const double yv = kl ? g - h.gprev[(size_t)item * r + lane] : 0.0;
-        const double sy = wave_sum(sv * yv);
+        const double sy = vsum(sv * yv);
         if (sy > 0.0) {
             int slot;
             if (np < m) {
@@ -2780,7 +2805,7 @@ __global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p
 #pragma unroll
     for (int j = M - 1; j >= 0; --j) {
         if (j >= np) continue;
-        aj[j] = wave_sum(sj[j] * q) / syj[j];
+        aj[j] = vsum(sj[j] * q) / syj[j];
         q -= aj[j] * yj[j];
     }
     if (np > 0) {
@@ -2788,7 +2813,7 @@ __global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p
 #pragma unroll
         for (int j = 0; j < M; ++j)
             if (j == np - 1) {
-                yy = wave_sum(yj[j] * yj[j]);
+                yy = vsum(yj[j] * yj[j]);
                 syn = syj[j];
             }
         q *= syn / yy;
@@ -2796,11 +2821,11 @@ __global__ __launch_bounds__(64) void k_lbfgs_dir(NewtonState st, NewtonParams p
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         if (j >= np) continue;
-        const double b = wave_sum(yj[j] * q) / syj[j];
+        const double b = vsum(yj[j] * q) / syj[j];
         q += sj[j] * (aj[j] - b);
     }
     const double d = kl ? -q : 0.0;
-    const double slope = wave_sum(g * d);
+    const double slope = vsum(g * d);
     if (lane == 0) {
         h.npair[item] = np;
         h.head[item] = head;
