@@ -510,3 +510,57 @@ def test_reverse_mode_gradient(name, prec, flags):
     Eo, go, _ = O.Oracle(p).reduced(z, tg, fo, flags=O.ELASTIC_ONLY if flags else 0)
     assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
     assert relerr(g.cpu().numpy(), go).max() < TOL[prec]
+
+
+# ------------------------------------------------------------------- largest sizes
+MAXCASES = {
+    # the largest latent size (32: the 32-lane element path, two-tile curvature, LDS Jacobi) and width 256
+    "r32w256": dict(nx=4, ny=2, nz=1, r=32, hidden=[256, 256], n_cub=40),
+    # the most hidden layers (8)
+    "l8": dict(nx=3, ny=1, nz=1, r=12, hidden=[64] * 8, n_cub=15),
+}
+
+
+def max_problem(name):
+    c = MAXCASES[name]
+    return I.make_problem(name, c["nx"], c["ny"], c["nz"], c["r"], c["hidden"], c["n_cub"], bend=True,
+                          bias_scale=0.3)
+
+
+@pytest.mark.parametrize("name", sorted(MAXCASES))
+@pytest.mark.parametrize("prec", [rb.PREC_F64, rb.PREC_F32])
+def test_largest_sizes_evaluation(name, prec):
+    p = max_problem(name)
+    B = 5
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    ctx = rb.Context(p, prec=prec, max_batch=8)
+    o = O.Oracle(p)
+    tol = TOL[prec]
+    x, J = ctx.decode(t64(z))
+    xo, Jo = o.decode(z)
+    assert relerr(x.cpu().numpy() - p.X, xo - p.X, tau=1e-3).max() < tol
+    assert relerr(J.cpu().numpy(), Jo).max() < tol
+    E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo))
+    Eo, go, Ho = o.reduced(z, tg, fo, flags=O.EXACT)
+    assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    assert relerr(g.cpu().numpy(), go).max() < tol
+    assert relerr(H.cpu().numpy(), Ho).max() < tol
+    Er, gr, _ = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=rb.GRAD_REVERSE)
+    assert relerr(gr.cpu().numpy(), go).max() < tol
+
+
+@pytest.mark.parametrize("name", sorted(MAXCASES))
+def test_largest_sizes_solvers(name):
+    """Newton steps and L-BFGS steps at the largest sizes against the oracle's (float64)."""
+    p = max_problem(name)
+    B = 4
+    z0 = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    for k in (1, 2):
+        r, ores, _ = _compare_newton(p, rb.PREC_F64, z0, tg, fo, dict(max_iter=k))
+        assert np.array_equal(r["status"], ores["status"]) and np.array_equal(r["iters"], ores["iters"])
+        assert relerr(r["z"], ores["z"], tau=1e-3).max() < 1e-8
+        r, ores, _ = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo, dict(max_iter=2 * k))
+        assert np.array_equal(r["status"], ores["status"]) and np.array_equal(r["iters"], ores["iters"])
+        assert relerr(r["z"], ores["z"], tau=1e-3).max() < 1e-8
