@@ -2324,6 +2324,27 @@ __device__ inline double dpp_from_next(double x)
                             __builtin_amdgcn_update_dpp(lo, lo, 0x101, 0xF, 0xF, false));
 }
 
+// 1/sqrt(x) and 1/x for positive normal x: the hardware estimate refined by two
+// Newton steps (y <- y (3 - x y^2) / 2 and y <- y (2 - x y)), each of which
+// squares the relative error.
+__device__ inline double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double h = 0.5 * x * y;
+        y = fma(y, fma(-h, y, 0.5), y);
+    }
+    return y;
+}
+__device__ inline double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
 // Parallel Jacobi eigen-decomposition of a symmetric n2 x n2 matrix (n2 even,
 // n2 <= 16) held in registers of one wave (Brent-Luk layout).  The indices are
 // paired by slot: slot k pairs (t_k, b_k), and one step rotates all n2/2 pairs
@@ -2361,10 +2382,13 @@ __device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], in
             if (I == J && htb != 0.0) {
                 // smaller root of t^2 + 2 theta t - 1 = 0, theta = d / (2 a_pq),
                 // written as t = 2 a_pq / (d + sgn(d) sqrt(d^2 + 4 a_pq^2))
+                // (reciprocal square roots and reciprocals from the hardware
+                // estimates refined by two Newton steps: a short dependent chain)
                 const double d = hbb - htt, two_apq = 2.0 * htb;
-                const double root = sqrt(d * d + two_apq * two_apq);
-                const double t = two_apq / (d >= 0.0 ? d + root : d - root);
-                c = 1.0 / sqrt(t * t + 1.0);
+                const double x = d * d + two_apq * two_apq;
+                const double root = x * rsq_nr(x);
+                const double t = two_apq * rcp_nr(d >= 0.0 ? d + root : d - root);
+                c = rsq_nr(t * t + 1.0);
                 sn = t * c;
             }
             const double cI = __shfl(c, dI), sI = __shfl(sn, dI);
