@@ -51,7 +51,7 @@ enum {
     RS_ERR_HIP = 2,         /* a HIP runtime call or kernel launch failed */
     RS_ERR_OOM = 3,         /* device allocation failed */
     RS_ERR_STATE = 4,       /* context not usable */
-    RS_ERR_UNSUPPORTED = 5  /* size or mode outside what this build supports */
+    RS_ERR_UNSUPPORTED = 5  /* size or mode outside what the library supports */
 };
 
 /* per-item solver outcomes: the exit conditions of the paper's solver

@@ -813,7 +813,7 @@ int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const
 }
 
 /* ------------------------------------------------------------------------- */
-/* full-space judge: Newton on the free vertex DOFs over every mesh element   */
+/* full-space reference: Newton on the free vertex DOFs over every mesh element */
 /* ------------------------------------------------------------------------- */
 static double full_energy(const or_problem* p, const rest_data* rd, const double* x,
                           const double* tgt, const double* f, double* grad)

@@ -244,7 +244,7 @@ def test_newton_projection_across_latent_sizes(r):
         assert np.array_equal(r_["iters"], ores["iters"])
         assert relerr(r_["z"], ores["z"]).max() < 1e-9
     # whole solves: a trajectory that wanders through indefinite regions for
-    # tens of steps amplifies rounding, so judge the end point by stationarity
+    # tens of steps amplifies rounding, so compare the end points by stationarity
     r_, ores, o = _compare_newton(p, rb.PREC_F64, z0, tgs, fos, dict(max_iter=200))
     assert np.all(r_["status"] == rb.CONVERGED)
     g0 = np.abs(o.reduced(z0, tgs, fos)[1]).max(axis=1)
@@ -447,7 +447,7 @@ def test_lbfgs_float64_solves_converge_like_oracle(name):
     tg, fo = I.loads_for(p, B)
     r, ores, o = _compare_lbfgs(p, rb.PREC_F64, z0, tg, fo)
     assert np.all(r["status"] == rb.CONVERGED) and np.all(ores["status"] == O.CONVERGED)
-    # whole trajectories of tens of steps amplify rounding: judge the end point
+    # whole trajectories of tens of steps amplify rounding: compare the end points
     g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
     Eg, gg, _ = o.reduced(r["z"], tg, fo)
     assert np.all(np.abs(gg).max(axis=1) <= 1e-6 * g0 * (1 + 1e-6))

@@ -1,5 +1,5 @@
 """Pins of the oracle's decoder, reduced objective, Newton solver, full-space
-judge and Lipschitz loss.
+reference and Lipschitz loss.
 
 Every check compares the oracle against something other than itself:
 finite differences of a lower-order quantity, the full-space formulation (an
@@ -138,7 +138,7 @@ def test_identity_decoder_matches_full_space(oracle_mod):
 
 
 # --------------------------------------------------------------------------- Newton
-def test_newton_c1_converges_and_judge(oracle_mod):
+def test_newton_c1_converges_and_full_space_reference(oracle_mod):
     p = I.config("c1")
     o = oracle_mod.Oracle(p)
     z0 = np.vstack([np.zeros(p.r), I.latent_batch(3, p.r)])
@@ -153,10 +153,10 @@ def test_newton_c1_converges_and_judge(oracle_mod):
     for b in range(len(z0)):
         w = np.linalg.eigvalsh(0.5 * (Hs[b] + Hs[b].T))
         assert w.min() > -1e-8 * np.abs(w).max()
-    # full-space judge started from q(z*) cannot end above the reduced energy
+    # the full-space reference started from q(z*) cannot end above the reduced energy
     x, _ = o.decode(res["z"][:1], want_J=False)
     full = o.full_newton(x[0])
-    # FP64 energy differences stop the judge's line search near relgrad 1e-7
+    # FP64 energy differences stop the reference solve's line search near relgrad 1e-7
     assert full["status"] in (oracle_mod.CONVERGED, oracle_mod.LS_MAX)
     assert full["relgrad"] <= 1e-6
     assert full["E"] <= res["E"][0] + 1e-12 * abs(res["E"][0])
