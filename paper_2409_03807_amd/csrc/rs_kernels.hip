@@ -2227,17 +2227,25 @@ __device__ inline double step_len(double shrink, int j)
     return a;
 }
 
-// Candidate list and candidate points in one workgroup: an item on its first
-// trial evaluates alpha = 1 only (the Newton step is usually accepted); later
-// rounds evaluate kLsCand steps.  zc[c] = z[item] + alpha_j dz[item], written
-// per chunk of 1024 items with consecutive threads on consecutive coordinates.
+// Candidate list and candidate points: an item on its first trial evaluates
+// alpha = 1 only (the Newton step is usually accepted); later rounds evaluate
+// kLsCand steps.  zc[c] = z[item] + alpha_j dz[item], written per chunk of 1024
+// items with consecutive threads on consecutive coordinates.  Every workgroup
+// of the grid runs the same prefix sums (the state they read is not written
+// here); workgroup 0 alone writes the lists, and the candidate points of a
+// chunk are split over the workgroups.  A search entry's step lengths are one
+// running product (alpha_{j+1} = alpha_j * shrink), the same roundings as
+// backtracking from alpha = 1.
+constexpr int kSearchWgs = 8;
 __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonParams p, int B)
 {
-    constexpr int NB = 16; // coordinates per thread and batch (loads issued before stores)
+    constexpr int NB = 8;  // coordinates per thread and batch (loads issued before stores)
     __shared__ int sc[16];
-    __shared__ int it_b[1024], it_c[1024], it_j[1024]; // chunk search entry: item, first chunk candidate, trial
-    __shared__ short cl[1024 * kLsCand];                // chunk candidate -> chunk search entry
+    __shared__ int it_b[1024];                  // chunk search entry -> item
+    __shared__ short cl[1024 * kLsCand];        // chunk candidate -> chunk search entry
+    __shared__ double ca[1024 * kLsCand];       // chunk candidate -> step length
     const int tid = threadIdx.x, r = p.r;
+    const bool lead = blockIdx.x == 0;
     int base_s = 0, base_c = 0;
     for (int b0 = 0; b0 < B; b0 += 1024) {
         const int b = b0 + tid;
@@ -2251,47 +2259,50 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
         const int inc = block_scan1024((f << 16) | nc, sc, tot);
         const int ls = (inc >> 16) - 1, lc = (inc & 0xffff) - nc;
         if (f) {
-            st.search_list[base_s + ls] = b;
-            st.search_start[base_s + ls] = base_c + lc;
-            st.search_ncand[base_s + ls] = nc;
+            if (lead) {
+                st.search_list[base_s + ls] = b;
+                st.search_start[base_s + ls] = base_c + lc;
+                st.search_ncand[base_s + ls] = nc;
+            }
             it_b[ls] = b;
-            it_c[ls] = lc;
-            it_j[ls] = j;
+            double a = step_len(p.shrink, j);
             for (int t = 0; t < nc; ++t) {
-                st.cand_item[base_c + lc + t] = b;
-                st.cand_j[base_c + lc + t] = j + t;
+                if (lead) {
+                    st.cand_item[base_c + lc + t] = b;
+                    st.cand_j[base_c + lc + t] = j + t;
+                }
                 cl[lc + t] = (short)ls;
+                ca[lc + t] = a;
+                a *= p.shrink;
             }
         }
         __syncthreads();
         const int ne = (tot & 0xffff) * r;
         double* zc = st.zc + (size_t)base_c * r;
-        for (int e0 = 0; e0 < ne; e0 += 1024 * NB) {
-            double zv[NB], dv[NB];
-            int jv[NB];
+        for (int e0 = blockIdx.x * 1024 * NB; e0 < ne; e0 += gridDim.x * 1024 * NB) {
+            double zv[NB], dv[NB], av[NB];
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int e = e0 + q * 1024 + tid;
-                zv[q] = dv[q] = 0.0;
-                jv[q] = 0;
+                zv[q] = dv[q] = av[q] = 0.0;
                 if (e < ne) {
-                    const int c = e / r, k = e - c * r, li = cl[c];
-                    zv[q] = st.z[(size_t)it_b[li] * r + k];
-                    dv[q] = st.dz[(size_t)it_b[li] * r + k];
-                    jv[q] = it_j[li] + c - it_c[li];
+                    const int c = e / r, k = e - c * r, it = it_b[cl[c]];
+                    zv[q] = st.z[(size_t)it * r + k];
+                    dv[q] = st.dz[(size_t)it * r + k];
+                    av[q] = ca[c];
                 }
             }
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int e = e0 + q * 1024 + tid;
-                if (e < ne) zc[e] = zv[q] + step_len(p.shrink, jv[q]) * dv[q];
+                if (e < ne) zc[e] = zv[q] + av[q] * dv[q];
             }
         }
         __syncthreads(); // the chunk's LDS tables are reused
         base_s += tot >> 16;
         base_c += tot & 0xffff;
     }
-    if (tid == 0) {
+    if (lead && tid == 0) {
         st.counters[1] = base_c;
         st.counters[2] = base_s;
         if (st.plog) {
@@ -2304,7 +2315,7 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
 
 hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s)
 {
-    RS_LAUNCH(k_compact_search, dim3(1), dim3(1024), 0, s, st, p, B);
+    RS_LAUNCH(k_compact_search, dim3(kSearchWgs), dim3(1024), 0, s, st, p, B);
     return hipGetLastError();
 }
 
@@ -2899,9 +2910,14 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
             const int start = st.search_start[i], nc = st.search_ncand[i];
             const double E0 = st.E[item], slope = st.slope[item];
             const int j0 = st.ls_j[item];
-            for (int t = 0; t < nc && cand < 0; ++t) {
-                const double alpha = step_len(p.shrink, j0 + t);
-                const double Et = st.Ec[start + t];
+            double Ev[kLsCand]; // all candidate energies in flight at once
+#pragma unroll
+            for (int t = 0; t < kLsCand; ++t) Ev[t] = t < nc ? st.Ec[start + t] : 0.0;
+            double alpha = step_len(p.shrink, j0);
+#pragma unroll
+            for (int t = 0; t < kLsCand; ++t, alpha *= p.shrink) {
+                if (t >= nc || cand >= 0) break;
+                const double Et = Ev[t];
                 if (isfinite(Et) && Et - E0 <= p.c1 * alpha * slope) {
                     cand = start + t;
                     st.E[item] = Et;
