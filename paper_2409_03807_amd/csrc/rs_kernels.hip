@@ -469,40 +469,48 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
         }
     }
     // the lane's 4 output rows do not change from tile to tile
-    int mrow[4];
+    int mrow[4], rowoff[4];
     T brow[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         mrow[v] = m0 + wave * 16 + Mfma<T>::row(lane, v);
+        rowoff[v] = mrow[v] * nc;
         brow[v] = (a.bias && mrow[v] < a.rows) ? static_cast<const T*>(a.bias)[mrow[v]] : T(0);
     }
+    const int step_q = 16 / nc, step_r = 16 - step_q * nc; // 16 columns on as (items, columns)
+    const size_t item_stride = (size_t)a.rows_pad * nc;
 
     const int ynn = tid & 63, ykb = (tid >> 6) * PER;
     T ry[PER];
     auto load = [&](int ct) {
-        const int yn = ct * kTileN + ynn;
+        if constexpr (INM == IN_LATENT) {
+            const int yn = ct * kTileN + ynn;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) ry[q] = T(0);
-        if (yn < ncols) {
-            const int yitem = (int)((unsigned)yn / ncu);
-            const int yc = yn - yitem * nc;
-            if constexpr (INM == IN_LATENT) {
+            for (int q = 0; q < PER; ++q) ry[q] = T(0);
+            if (yn < ncols) {
+                const int yitem = (int)((unsigned)yn / ncu);
+                const int yc = yn - yitem * nc;
                 const long zr = a.zmap ? a.zmap[yitem] : yitem;
 #pragma unroll
                 for (int q = 0; q < PER; ++q) {
                     const int k = ykb + q;
                     if (k < a.K) ry[q] = (yc == 0) ? (T)a.z[zr * a.r + k] : ((k == yc - 1) ? T(1) : T(0));
                 }
-            } else {
-                // IN_RAW_T with K a multiple of the tile depth: one contiguous run
-                const V* vp = reinterpret_cast<const V*>(static_cast<const T*>(a.Y) +
-                                                         ((size_t)yitem * nc + yc) * a.y_rows + ykb);
+            }
+        } else {
+            // IN_RAW_T with K a multiple of the tile depth: one contiguous run.
+            // Columns past the end load the last column (their products are
+            // never stored), so the loads need no predicate.
+            const int yn = min(ct * kTileN + ynn, ncols - 1);
+            const int yitem = (int)((unsigned)yn / ncu);
+            const int yc = yn - yitem * nc;
+            const V* vp = reinterpret_cast<const V*>(static_cast<const T*>(a.Y) +
+                                                     ((size_t)yitem * nc + yc) * a.y_rows + ykb);
 #pragma unroll
-                for (int q = 0; q < PER / VN; ++q) {
-                    const V w = vp[q];
+            for (int q = 0; q < PER / VN; ++q) {
+                const V w = vp[q];
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) ry[q * VN + e] = w[e];
-                }
+                for (int e = 0; e < VN; ++e) ry[q * VN + e] = w[e];
             }
         }
     };
@@ -545,18 +553,41 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[c][kk], bf[t][kk], acc[t]);
         }
+        if constexpr (OUTM == OUT_PACK) {
+            // the lane's column n0 + 16 t as (item, cidx), stepped from t = 0;
+            // full tiles (every row below rows, every column below ncols) store
+            // without predicates
+            const int n0 = ct * kTileN + li;
+            const bool full = m0 + kTileM <= a.rows && (ct + 1) * kTileN <= ncols;
+            int item = (int)((unsigned)n0 / ncu);
+            int cidx = n0 - item * nc;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int n = ct * kTileN + t * 16 + li;
-            if (n >= ncols) continue;
-            const int item = (int)((unsigned)n / ncu);
-            const int cidx = n - item * nc;
-            if constexpr (OUTM == OUT_PACK) {
-                T* base = Cout + (size_t)item * a.rows_pad * nc + cidx;
+            for (int t = 0; t < 4; ++t) {
+                if (t > 0) {
+                    item += step_q;
+                    cidx += step_r;
+                    if (cidx >= nc) {
+                        cidx -= nc;
+                        ++item;
+                    }
+                }
+                T* base = Cout + (size_t)item * item_stride + cidx;
+                if (full) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (mrow[v] < a.rows) base[(size_t)mrow[v] * nc] = acc[t][v] + (cidx == 0 ? brow[v] : T(0));
-            } else {
+                    for (int v = 0; v < 4; ++v) base[rowoff[v]] = acc[t][v] + (cidx == 0 ? brow[v] : T(0));
+                } else if (n0 + 16 * t < ncols) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (mrow[v] < a.rows) base[rowoff[v]] = acc[t][v] + (cidx == 0 ? brow[v] : T(0));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n = ct * kTileN + t * 16 + li;
+                if (n >= ncols) continue;
+                const int item = (int)((unsigned)n / ncu);
+                const int cidx = n - item * nc;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int m = mrow[v];
@@ -1368,6 +1399,35 @@ struct Snh {
             for (int i = 0; i < 3; ++i)
                 P[3 * j + i] = mu * (g[j][i] + g[i][j] - (i == j ? tr : T(0)) - cg[j][i]) + lj * cof[j][i];
     }
+    // (d2 psi / dF2) v with mu, lam and s scaled by the caller (one weight for
+    // the element folded into the three scalars); the columns of d(cof F)[v]
+    // as single fused chains
+    __device__ void apply_hess_w(T wmu, T wlam, T ws, const T* v, T* out) const
+    {
+        T gv = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) gv = fma(cof[j][i], v[3 * j + i], gv);
+        const T t = wlam * gv;
+        const T* v0 = v;
+        const T* v1 = v + 3;
+        const T* v2 = v + 6;
+        // column j of d(cof F)[v]: v_{j+1} x f_{j+2} + f_{j+1} x v_{j+2}
+        auto dcol = [&](const T* va, const T* fb, const T* fa, const T* vb, int i) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+            T d = va[i1] * fb[i2];
+            d = fma(-va[i2], fb[i1], d);
+            d = fma(fa[i1], vb[i2], d);
+            return fma(-fa[i2], vb[i1], d);
+        };
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            out[i] = fma(ws, dcol(v1, f[2], f[1], v2, i), fma(t, cof[0][i], wmu * v0[i]));
+            out[3 + i] = fma(ws, dcol(v2, f[0], f[2], v0, i), fma(t, cof[1][i], wmu * v1[i]));
+            out[6 + i] = fma(ws, dcol(v0, f[1], f[0], v1, i), fma(t, cof[2][i], wmu * v2[i]));
+        }
+    }
     // (d2 psi / dF2) v = mu v + lam g (g.v) + s d(cof F)[v], g = vec cof F,
     // d(cof F)[v] = [v1 x f2 + f1 x v2, v2 x f0 + f2 x v0, v0 x f1 + f0 x v1]
     __device__ void apply_hess(T mu, T lam, const T* v, T* out) const
@@ -1406,7 +1466,11 @@ struct Snh {
 // Contributions are float64-accumulated and reduced in a fixed order.
 // ---------------------------------------------------------------------------
 
-constexpr int kElemTile = 2880;  // max over RP of (tets per round) * 9 * (1 + r) values
+// values staged per round: (tets per round) * 9 * (1 + r) at most; the
+// two-column path (RP == 8, 32 tets a round, r <= 16) needs the larger tile
+constexpr int kElemTile = 2880;
+constexpr int kElemTile8 = 32 * 9 * 17;
+constexpr int elem_tile(int rp) { return rp == 8 ? kElemTile8 : kElemTile; }
 
 typedef const void __attribute__((address_space(1)))* gas_ptr;
 typedef void __attribute__((address_space(3)))* las_ptr;
@@ -1475,6 +1539,36 @@ __device__ inline void lds_read3(const T* p, int stride, T (&o)[3])
                      : "memory");
 }
 
+// nine floats 17 apart (one column of nine rows of 17), and two such columns
+// eight apart, from one address register with immediate offsets
+__device__ inline void lds_read9_s17(const float* p, float (&o)[9])
+{
+    asm volatile("ds_read_b32 %0, %9\n\tds_read_b32 %1, %9 offset:68\n\tds_read_b32 %2, %9 offset:136\n\t"
+                 "ds_read_b32 %3, %9 offset:204\n\tds_read_b32 %4, %9 offset:272\n\tds_read_b32 %5, %9 offset:340\n\t"
+                 "ds_read_b32 %6, %9 offset:408\n\tds_read_b32 %7, %9 offset:476\n\tds_read_b32 %8, %9 offset:544\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(o[0]), "=&v"(o[1]), "=&v"(o[2]), "=&v"(o[3]), "=&v"(o[4]), "=&v"(o[5]), "=&v"(o[6]),
+                   "=&v"(o[7]), "=&v"(o[8])
+                 : "v"(lds_addr(p))
+                 : "memory");
+}
+
+__device__ inline void lds_read18_s17(const float* p, float (&a)[9], float (&b)[9])
+{
+    asm volatile("ds_read_b32 %0, %18\n\tds_read_b32 %1, %18 offset:68\n\tds_read_b32 %2, %18 offset:136\n\t"
+                 "ds_read_b32 %3, %18 offset:204\n\tds_read_b32 %4, %18 offset:272\n\tds_read_b32 %5, %18 offset:340\n\t"
+                 "ds_read_b32 %6, %18 offset:408\n\tds_read_b32 %7, %18 offset:476\n\tds_read_b32 %8, %18 offset:544\n\t"
+                 "ds_read_b32 %9, %18 offset:32\n\tds_read_b32 %10, %18 offset:100\n\tds_read_b32 %11, %18 offset:168\n\t"
+                 "ds_read_b32 %12, %18 offset:236\n\tds_read_b32 %13, %18 offset:304\n\tds_read_b32 %14, %18 offset:372\n\t"
+                 "ds_read_b32 %15, %18 offset:440\n\tds_read_b32 %16, %18 offset:508\n\tds_read_b32 %17, %18 offset:576\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a[0]), "=&v"(a[1]), "=&v"(a[2]), "=&v"(a[3]), "=&v"(a[4]), "=&v"(a[5]), "=&v"(a[6]),
+                   "=&v"(a[7]), "=&v"(a[8]), "=&v"(b[0]), "=&v"(b[1]), "=&v"(b[2]), "=&v"(b[3]), "=&v"(b[4]),
+                   "=&v"(b[5]), "=&v"(b[6]), "=&v"(b[7]), "=&v"(b[8])
+                 : "v"(lds_addr(p))
+                 : "memory");
+}
+
 __device__ inline double lds_read_f64(const double* p)
 {
     double o;
@@ -1482,23 +1576,48 @@ __device__ inline double lds_read_f64(const double* p)
     return o;
 }
 
-template <typename T>
+template <typename T, int RP>
 struct ElemRing {
     static constexpr int VN = 16 / (int)sizeof(T);
     // direct loads per wave per round: the slot holds a round plus the
     // misalignment of its first value
-    static constexpr int NI = (kElemTile + VN + 256 * VN - 1) / (256 * VN);
+    static constexpr int NI = (elem_tile(RP) + VN + 256 * VN - 1) / (256 * VN);
     static constexpr int SLOT = 256 * NI * VN; // values per slot
 };
+
+// Two-column element lanes (8 per tet): lane 8 t + c of a wave holds columns
+// c and c + 8 of tet t, so a 16-lane row holds tets 2q and 2q + 1.  The MFMA
+// operand of tet 2q (column j in lane j of the row) keeps lanes j < 8 and
+// takes lanes j >= 8 from the second column of lane j - 8 (row shift right
+// by 8, upper two banks); the operand of tet 2q + 1 keeps lanes j >= 8 and
+// takes lanes j < 8 from the first column of lane j + 8 (row shift left by 8,
+// lower two banks).
+template <int CTRL, int BANKS>
+__device__ inline float dpp_keep(float old, float src)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, 0xF, BANKS, false));
+}
+template <int CTRL, int BANKS>
+__device__ inline double dpp_keep(double old, double src)
+{
+    const int ohi = __double2hiint(old), olo = __double2loint(old);
+    const int shi = __double2hiint(src), slo = __double2loint(src);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(ohi, shi, CTRL, 0xF, BANKS, false),
+                            __builtin_amdgcn_update_dpp(olo, slo, CTRL, 0xF, BANKS, false));
+}
+template <typename T>
+__device__ inline T pair_even(T first, T second) { return dpp_keep<0x118, 0xC>(first, second); }
+template <typename T>
+__device__ inline T pair_odd(T first, T second) { return dpp_keep<0x108, 0x3>(second, first); }
 
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 {
     constexpr int EPW = 64 / RP;   // tets (or targets) per wave per round
     constexpr int EPR = 4 * EPW;   // per round
-    constexpr int VN = ElemRing<T>::VN;
-    constexpr int NI = ElemRing<T>::NI;
-    constexpr int SLOT = ElemRing<T>::SLOT;
+    constexpr int VN = ElemRing<T, RP>::VN;
+    constexpr int NI = ElemRing<T, RP>::NI;
+    constexpr int SLOT = ElemRing<T, RP>::SLOT;
     // side inputs per round: wV of its tets (2 EPR words), or the rest
     // positions and targets of its targeted vertices (12 EPR words)
     constexpr int NS = (12 * EPR + 255) / 256; // direct 4-byte loads per wave per round
@@ -1514,6 +1633,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     const int eg = lane / RP, k = lane % RP;
     const int r = a.r, nc = a.nc;
     const bool kact = k < r;
+    const bool kact2 = RP == 8 && k + 8 < r; // second column of the two-column path
     const T* O = static_cast<const T*>(a.out) + (size_t)item * a.rows_pad * nc;
     T* dseed = a.dseed ? static_cast<T*>(a.dseed) + (size_t)item * a.rows_pad : nullptr;
     const int bidx = a.imap ? a.imap[item] : item;
@@ -1527,11 +1647,12 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     double Hc[RP];  // column layout: lane (tet, k) holds H[0..r)[k] (VALU path)
 #pragma unroll
     for (int j = 0; j < RP; ++j) Hc[j] = 0.0;
-    double Hm[4] = {0.0, 0.0, 0.0, 0.0}; // MFMA result layout (RP == 16 path)
-    // the RP == 16 path accumulates H on the matrix cores across all of the
+    double Hm[4] = {0.0, 0.0, 0.0, 0.0}; // MFMA result layout (RP == 16 and 8 paths)
+    // the MFMA paths accumulate H on the matrix cores across all of the
     // wave's rounds (4 tets or targets per MFMA step), in T; Hm takes it at the end
+    constexpr bool MF = RP == 16 || RP == 8;
     typename Mfma<T>::acc_t hsum = {0, 0, 0, 0};
-    double gk = 0.0, Ee = 0.0;
+    double gk = 0.0, gk2 = 0.0, Ee = 0.0;
 
     const int span = 9 * nc;
     const int tet_rounds = (a.S + EPR - 1) / EPR;
@@ -1671,6 +1792,50 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 }
 #pragma unroll
                 for (int v = 0; v < 9; ++v) hsum = Mfma<T>::mac(Kc[v], AK[v], hsum);
+            } else if constexpr (RP == 8) {
+                // r == 16 (rows of 17 values): lane c holds columns c and c + 8,
+                // and F, psi and P are formed once for both.  A lane past the
+                // end of S repeats the round's last tet with weight zero, so
+                // every lane runs the same code and adds nothing.
+                const bool sok = s < a.S;
+                const int elc = sok ? el : a.S - 1 - rd * EPR;
+                const T* row = tile + elc * (9 * 17);
+                T gu[9], K0[9], K1[9];
+                lds_read9_s17(row, gu);
+                lds_read18_s17(row + 1 + k, K0, K1);
+                const double wv = lds_read_f64(sd + el);
+                const double wV = sok ? wv : 0.0;
+                Snh<T> m;
+                m.set(gu, mu, lam);
+                T P[9];
+                m.pk1(mu, lam, P);
+                const T wt = (T)wV;
+                T A0[9], A1[9];
+                const T wmu = wt * mu, wlam = wt * lam, ws = wt * m.s;
+                m.apply_hess_w(wmu, wlam, ws, K0, A0);
+                m.apply_hess_w(wmu, wlam, ws, K1, A1);
+                T gp0 = 0, gp1 = 0;
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    gp0 += K0[v] * P[v];
+                    gp1 += K1[v] * P[v];
+                }
+                gk += wV * (double)gp0;
+                gk2 += wV * (double)gp1;
+                Ee += k == 0 ? wV * (double)m.psi : 0.0;
+                if (dseed && sok) {
+                    // lane c writes seed c; lane 0 also seed 8
+                    T pv = P[0];
+#pragma unroll
+                    for (int v = 1; v < 8; ++v) pv = k == v ? P[v] : pv;
+                    global_store_asm(dseed + 9 * s + k, wt * pv);
+                    if (k == 0) global_store_asm(dseed + 9 * s + 8, wt * P[8]);
+                }
+#pragma unroll
+                for (int v = 0; v < 9; ++v) {
+                    hsum = Mfma<T>::mac(pair_even(K0[v], K1[v]), pair_even(A0[v], A1[v]), hsum);
+                    hsum = Mfma<T>::mac(pair_odd(K0[v], K1[v]), pair_odd(A0[v], A1[v]), hsum);
+                }
             } else if (s < a.S) {
                 const T* row = tile + el * span;
                 T gu[9], Kc[9];
@@ -1710,13 +1875,19 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             const int t = (rd - tet_rounds) * EPR + el;
             const bool ok = t < a.nt;
             const T* row = tile + 3 * el * nc;
-            T Jc[3];
+            T Jc[3], J2[3] = {T(0), T(0), T(0)};
             double d[3];
-            if constexpr (RP == 16) {
+            if constexpr (MF) {
                 T jr[3], xv[3];
                 double xr[3], tr[3];
                 lds_read3(row, nc, xv);
                 lds_read3(row + 1 + (kact ? k : 0), nc, jr);
+                if constexpr (RP == 8) {
+                    T jr2[3];
+                    lds_read3(row + 1 + (kact2 ? k + 8 : 0), nc, jr2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) J2[c] = (ok && kact2) ? jr2[c] : T(0);
+                }
                 lds_read3(sd + 3 * el, 1, xr);
                 lds_read3(sd + 3 * EPR + 3 * el, 1, tr);
 #pragma unroll
@@ -1735,9 +1906,17 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 const T kt = (T)kc;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) hsum = Mfma<T>::mac(Jc[c], kt * Jc[c], hsum);
+            } else if constexpr (RP == 8) {
+                const T kt = (T)kc;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T pe = pair_even(Jc[c], J2[c]), po = pair_odd(Jc[c], J2[c]);
+                    hsum = Mfma<T>::mac(pe, kt * pe, hsum);
+                    hsum = Mfma<T>::mac(po, kt * po, hsum);
+                }
             }
             if (ok) {
-                if constexpr (RP != 16) {
+                if constexpr (!MF) {
 #pragma unroll
                     for (int j = 0; j < RP; ++j) {
                         if (j < r) {
@@ -1749,6 +1928,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                     }
                 }
                 gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
+                if constexpr (RP == 8) gk2 += kc * ((double)J2[0] * d[0] + (double)J2[1] * d[1] + (double)J2[2] * d[2]);
                 Ee += k == 0 ? 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0;
                 if (dseed && k < 3) {
                     const double dv = k == 0 ? d[0] : k == 1 ? d[1] : d[2];
@@ -1769,12 +1949,14 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
     if (ext && part == 0 && wave == 0 && eg == 0) {
         const size_t gr = (size_t)a.grav_row;
         gk -= kact ? (double)O[gr * nc + 1 + k] : 0.0;
+        gk2 -= kact2 ? (double)O[gr * nc + 9 + k] : 0.0;
         if (k == 0) Ee -= (double)O[gr * nc];
         if (a.force && a.nf) {
             const double* f = a.force + (size_t)bidx * 3;
             for (int c = 0; c < 3; ++c) {
                 const size_t fr = (size_t)(a.force_row + c);
                 gk -= kact ? f[c] * (double)O[fr * nc + 1 + k] : 0.0;
+                gk2 -= kact2 ? f[c] * (double)O[fr * nc + 9 + k] : 0.0;
                 if (k == 0) Ee -= f[c] * (double)O[fr * nc];
             }
         }
@@ -1795,7 +1977,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
         }
     }
 
-    if constexpr (RP == 16) {
+    if constexpr (MF) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) Hm[q] = (double)hsum[q];
     }
@@ -1809,39 +1991,45 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
             for (int j = 0; j < RP; ++j) Hc[j] += __shfl_xor(Hc[j], off);
         }
         gk += __shfl_xor(gk, off);
+        if constexpr (RP == 8) gk2 += __shfl_xor(gk2, off);
         Ee += __shfl_xor(Ee, off);
     }
-    double* red = reinterpret_cast<double*>(ring0); // [RP][RP] H, [RP] g, [1] E
-    static_assert((RP * RP + RP + 1) * sizeof(double) <= SLOT * sizeof(T), "reduction fits one slot");
+    // [HN] H (MFMA layout on the MFMA paths), [GN] g, [1] E
+    constexpr int HN = MF ? 256 : RP * RP, GN = RP == 8 ? 16 : RP;
+    double* red = reinterpret_cast<double*>(ring0);
+    static_assert((HN + GN + 1) * sizeof(double) <= SLOT * sizeof(T), "reduction fits one slot");
     for (int w = 1; w < 4; ++w) {
         __syncthreads();
         if (wave == w) {
-            if constexpr (RP == 16) {
+            if constexpr (MF) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) red[q * 64 + lane] = Hm[q];
             } else if (eg == 0) {
 #pragma unroll
                 for (int j = 0; j < RP; ++j) red[j * RP + k] = Hc[j];
             }
-            if (eg == 0) red[RP * RP + k] = gk;
-            if (lane == 0) red[RP * RP + RP] = Ee;
+            if (eg == 0) red[HN + k] = gk;
+            if constexpr (RP == 8)
+                if (eg == 0) red[HN + 8 + k] = gk2;
+            if (lane == 0) red[HN + GN] = Ee;
         }
         __syncthreads();
         if (wave == 0) {
-            if constexpr (RP == 16) {
+            if constexpr (MF) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) Hm[q] += red[q * 64 + lane];
             } else {
 #pragma unroll
                 for (int j = 0; j < RP; ++j) Hc[j] += red[j * RP + k];
             }
-            gk += red[RP * RP + k];
-            Ee += red[RP * RP + RP];
+            gk += red[HN + k];
+            if constexpr (RP == 8) gk2 += red[HN + 8 + k];
+            Ee += red[HN + GN];
         }
     }
     if (wave == 0) {
         const size_t slot = (size_t)part * a.part_stride + item; // = item with one part
-        if constexpr (RP == 16) {
+        if constexpr (MF) {
             if (a.H) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -1855,6 +2043,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 if (j < r) a.H[slot * r * r + j * r + k] = Hc[j];
         }
         if (eg == 0 && kact && a.g) a.g[slot * r + k] = gk;
+        if (eg == 0 && kact2 && a.g) a.g[slot * r + k + 8] = gk2;
         if (lane == 0 && a.E) a.E[item] = Ee;
     }
 }
@@ -1865,11 +2054,13 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
     if (a.parts > 1 && (a.E || a.part_stride < items)) return hipErrorInvalidValue;
     ElemArgs b = a;
     if (b.parts < 1) b.parts = 1;
-    // r <= 16: the MFMA path (16 columns per tet); r <= 32: 32 lanes per tet (VALU);
+    // r <= 16: the MFMA paths (FP32 with r == 16: 8 lanes per tet with two
+    // columns each, 32 tets a round; otherwise 16 lanes per tet); r <= 32: 32
+    // lanes per tet (VALU);
     // r == 0 (value rows only: energy and adjoint seeds): 4 lanes per tet, 64 tets a round
-    const int rp = a.r == 0 ? 4 : a.r <= 16 ? 16 : 32;
+    const int rp = a.r == 0 ? 4 : (f32 && a.r == 16) ? 8 : a.r <= 16 ? 16 : 32;
     // one round's tile must fit the staging buffer and the prefetch registers
-    if ((256 / rp) * 9 * a.nc > kElemTile) return hipErrorInvalidValue;
+    if ((256 / rp) * 9 * a.nc > elem_tile(rp) || (rp == 8 && a.nc != 17)) return hipErrorInvalidValue;
     dim3 grid(items * b.parts), block(256);
 #define RS_ELEM(T, RP) RS_LAUNCH((k_elem<T, RP>), grid, block, 0, s, b)
     if (f32) {
@@ -1882,7 +2073,6 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
     } else {
         switch (rp) {
         case 4: RS_ELEM(double, 4); break;
-        case 8: RS_ELEM(double, 8); break;
         case 16: RS_ELEM(double, 16); break;
         default: RS_ELEM(double, 32); break;
         }

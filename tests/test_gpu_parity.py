@@ -109,6 +109,25 @@ def test_energy_only_and_chunking(name, prec):
     assert relerr(H.cpu().numpy(), Ho).max() < TOL[prec]
 
 
+@pytest.mark.parametrize("n_cub", [16, 45, 100])
+@pytest.mark.parametrize("flags", [rb.HESS_EXACT, 0])
+def test_element_two_column_path_ragged_rounds(n_cub, flags):
+    """r = 16 in float32 runs 8 lanes per tet with two columns each, 32 tets a
+    round: cubature sets that end inside a round, and small batches whose items
+    are split over several workgroups."""
+    p = I.make_problem(f"two{n_cub}", 6, 2, 2, 16, [32, 32], n_cub, bend=True, bias_scale=0.3)
+    o = O.Oracle(p)
+    for B in (3, 40):
+        ctx = rb.Context(p, prec=rb.PREC_F32, max_batch=B)
+        z = I.latent_batch(B, p.r)
+        tg, fo = I.loads_for(p, B)
+        E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=flags)
+        Eo, go, Ho = o.reduced(z, tg, fo, flags=O.EXACT if flags & rb.HESS_EXACT else 0)
+        assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+        assert relerr(g.cpu().numpy(), go).max() < TOL[rb.PREC_F32]
+        assert relerr(H.cpu().numpy(), Ho).max() < TOL[rb.PREC_F32]
+
+
 def test_empty_batch_is_a_no_op():
     p = problem("tiny")
     ctx = rb.Context(p, prec=rb.PREC_F64, max_batch=4)
