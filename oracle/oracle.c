@@ -951,6 +951,91 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
 /* ------------------------------------------------------------------------- */
 /* Lipschitz loss of the cubature elastic Hessian                            */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* Parameter gradient of the summed reduced energy (Sec. 3.2's potential     */
+/* loss): one item at a time, serially, accumulated in item order.           */
+/* ------------------------------------------------------------------------- */
+int or_energy_param_grad(const or_problem* p, int B, const double* z, const double* targets,
+                         const double* force, int flags, double* E, double* grad)
+{
+    const int r = p->r, w = p->width, L = p->L, n = p->n_out;
+    const int nin_out = L > 0 ? w : r;
+    /* offsets of W_l and b_l in the packed gradient */
+    size_t* offW = (size_t*)malloc(sizeof(size_t) * (L + 1));
+    size_t* offb = (size_t*)malloc(sizeof(size_t) * (L + 1));
+    size_t off = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int in = l == 0 ? r : w, out = l == L ? n : w;
+        offW[l] = off;
+        off += (size_t)out * in;
+        offb[l] = off;
+        off += out;
+    }
+    memset(grad, 0, sizeof(double) * off);
+    rest_data rd;
+    rest_build(p, &rd);
+    const int cap = w > r ? w : r;
+    /* pre-activations a_l and activations h_l of every layer (h_0 = z) */
+    double* A = (double*)malloc(sizeof(double) * (size_t)(L > 0 ? L : 1) * w);
+    double* Hs = (double*)malloc(sizeof(double) * (size_t)(L + 1) * cap);
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* gq = (double*)malloc(sizeof(double) * n);
+    double* gb = (double*)malloc(sizeof(double) * cap);
+    double* gb2 = (double*)malloc(sizeof(double) * cap);
+    for (int bi = 0; bi < B; ++bi) {
+        const double* zb = z + (size_t)bi * r;
+        for (int k = 0; k < r; ++k) Hs[k] = zb[k];
+        for (int l = 0; l < L; ++l) {
+            const int in = l == 0 ? r : w;
+            const double* hin = Hs + (size_t)l * cap;
+            for (int i = 0; i < w; ++i) {
+                double a = p->b[l][i];
+                for (int j = 0; j < in; ++j) a += p->W[l][(size_t)i * in + j] * hin[j];
+                A[(size_t)l * w + i] = a;
+                Hs[(size_t)(l + 1) * cap + i] = elu(a);
+            }
+        }
+        const double* hL = Hs + (size_t)L * cap;
+        for (int row = 0; row < n; ++row) {
+            double u = p->b[L][row];
+            for (int j = 0; j < nin_out; ++j) u += p->W[L][(size_t)row * nin_out + j] * hL[j];
+            x[row] = p->X[row] + (p->pinned[row / 3] ? 0.0 : u);
+        }
+        const double Eb = q_energy(p, &rd, x, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
+                                   force ? force + (size_t)bi * 3 : NULL, flags & OR_ELASTIC_ONLY, gq);
+        if (E) E[bi] = Eb;
+        /* output layer: dE/du_row = gq_row on free rows (pinned rows do not move) */
+        for (int j = 0; j < nin_out; ++j) gb[j] = 0.0;
+        for (int row = 0; row < n; ++row) {
+            if (p->pinned[row / 3]) continue;
+            const double gr = gq[row];
+            for (int j = 0; j < nin_out; ++j) {
+                grad[offW[L] + (size_t)row * nin_out + j] += gr * hL[j];
+                gb[j] += p->W[L][(size_t)row * nin_out + j] * gr;
+            }
+            grad[offb[L] + row] += gr;
+        }
+        /* hidden layers, last to first: delta_l = dE/dh_l * elu'(a_l) */
+        for (int l = L - 1; l >= 0; --l) {
+            const int in = l == 0 ? r : w;
+            const double* hin = Hs + (size_t)l * cap;
+            for (int j = 0; j < in; ++j) gb2[j] = 0.0;
+            for (int i = 0; i < w; ++i) {
+                const double d = gb[i] * elu1(A[(size_t)l * w + i]);
+                for (int j = 0; j < in; ++j) {
+                    grad[offW[l] + (size_t)i * in + j] += d * hin[j];
+                    gb2[j] += p->W[l][(size_t)i * in + j] * d;
+                }
+                grad[offb[l] + i] += d;
+            }
+            for (int j = 0; j < in; ++j) gb[j] = gb2[j];
+        }
+    }
+    free(A); free(Hs); free(x); free(gq); free(gb); free(gb2); free(offW); free(offb);
+    rest_free(&rd);
+    return 0;
+}
+
 int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
                  double* loss, double* per_pair, int* n_valid, double* lip_max)
 {

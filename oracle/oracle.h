@@ -122,6 +122,15 @@ double or_full_energy(const or_problem* p, const double* x, const double* target
 int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
                  double* loss, double* per_pair, int* n_valid, double* lip_max);
 
+/* Gradient of sum_b E(z_b) with respect to every decoder parameter (the
+ * potential loss of the unsupervised subspace construction, Sec. 3.2), by
+ * the chain rule written out: dE/dq at q(z_b), then back through the output
+ * layer and the hidden layers.  grad: packed W_1, b_1, ..., W_L, b_L, W_out,
+ * b_out, each W row-major (out x in); overwritten.  E: per-item energies
+ * (nullable).  flags: OR_ELASTIC_ONLY. */
+int or_energy_param_grad(const or_problem* p, int B, const double* z, const double* targets,
+                         const double* force, int flags, double* E, double* grad);
+
 /* symmetric eigen-decomposition by cyclic Jacobi (exposed for pins) */
 void or_sym_eig(int n, const double* A, double* evals, double* evecs);
 

@@ -295,6 +295,33 @@ class Oracle:
                              C.byref(it), C.byref(st), C.byref(rg), C.byref(E))
         return dict(x=x, iters=it.value, status=st.value, relgrad=rg.value, E=E.value)
 
+    def param_shapes(self):
+        """(W, b) shapes of every decoder layer, output layer last."""
+        p = self.p
+        dims = [p.r] + list(p.hidden) + [3 * p.X.shape[0]]
+        return [((dims[l + 1], dims[l]), (dims[l + 1],)) for l in range(len(dims) - 1)]
+
+    def unpack_params(self, flat):
+        """Split a packed parameter vector (W_1, b_1, ..., W_out, b_out) into arrays."""
+        out, off = [], 0
+        for (ws, bs) in self.param_shapes():
+            nw, nb = ws[0] * ws[1], bs[0]
+            out.append((flat[off:off + nw].reshape(ws), flat[off + nw:off + nw + nb]))
+            off += nw + nb
+        assert off == flat.size
+        return out
+
+    def energy_param_grad(self, z, targets=None, force=None, flags=0):
+        """Gradient of sum_b E(z_b) with respect to the packed decoder parameters."""
+        z = _c64(np.atleast_2d(z))
+        B = z.shape[0]
+        t, f, tp, fp = self._loads(B, targets, force)
+        n = sum(ws[0] * ws[1] + bs[0] for ws, bs in self.param_shapes())
+        E = np.zeros(B)
+        grad = np.zeros(n)
+        lib().or_energy_param_grad(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.c_int(flags), _d(E), _d(grad))
+        return E, grad
+
     def lipschitz(self, z1, z2):
         z1, z2 = _c64(np.atleast_2d(z1)), _c64(np.atleast_2d(z2))
         B = z1.shape[0]
