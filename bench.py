@@ -16,6 +16,10 @@ reductions, r x r solve, line-search energies and convergence test.
 
 Metric: converged reduced solves per second (items ending with
 |g|_inf <= 1e-6 |g_0|_inf), whole job, inputs resident in HBM.
+
+--path param_grad times instead the gradient of the summed cubature energy of
+the batch with respect to every decoder parameter (the potential loss of the
+unsupervised subspace construction), in items per second.
 """
 import argparse
 import glob
@@ -56,7 +60,7 @@ def recorded_traffic(kind, workload):
 # solves on the float64 vector ALUs, everything else on HBM bandwidth
 MFMA_KINDS = {"gemm_hidden", "gemm_out", "gemm_adjoint", "decode_hidden", "decode_out"}
 MFMA_F64_KINDS = {"ls_gemm_hidden", "ls_gemm_out"}
-ALU_F64_KINDS = {"newton_dir"}
+ALU_F64_KINDS = {"newton_dir", "param_grad"}
 VALU_F64_PEAK_TFLOPS = 78.6
 
 
@@ -90,6 +94,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
     ap.add_argument("--solver", default="newton", choices=["newton", "lbfgs"],
                     help="projective Newton (default) or L-BFGS (the paper's main solver)")
+    ap.add_argument("--path", default="solve", choices=["solve", "param_grad"],
+                    help="solve: the reduced solves (default); param_grad: the decoder-parameter gradient of the "
+                         "summed cubature energy over the batch (the potential loss of unsupervised training)")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -139,7 +146,13 @@ def main():
     conv_acc = torch.zeros((), dtype=torch.int64, device=dev)
     iter_acc = torch.zeros((), dtype=torch.int64, device=dev)
 
+    pgrad = args.path == "param_grad"
+
     def step():
+        if pgrad:
+            E, g, grad = ctx.energy_param_grad(z0, tg, fo, want_g=False)
+            conv_acc.add_(B)
+            return {"status": torch.zeros(B, dtype=torch.int32, device=dev), "grad": grad}, None
         if lbfgs:
             res = ctx.lbfgs_solve(z0, tg, fo, opts=lopts, out=out)
         else:
@@ -208,7 +221,17 @@ def main():
     cpu = None
     if args.cpu_sample < 0:
         args.cpu_sample = 64 if lbfgs else 320
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 and pgrad:
+        from oracle import oracle as O
+        n = min(args.cpu_sample, B)
+        o = O.Oracle(p)
+        t1 = time.perf_counter()
+        o.energy_param_grad(z0[:n].cpu().numpy(), tg_np[:n] if tg_np is not None else None,
+                            fo_np[:n] if fo_np is not None else None)
+        cdt = time.perf_counter() - t1
+        cpu = {"value": n / cdt, "unit": "items/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} items of the same batch through the float64 oracle's chain rule (serial), {cdt:.1f} s"}
+    elif args.cpu_sample > 0:
         from oracle import oracle as O
         n = min(args.cpu_sample, B)
         o = O.Oracle(p)
@@ -224,9 +247,10 @@ def main():
                                           f"(first {n} start points), {cdt:.1f} s"}
 
     line = {
-        "metric": "converged reduced solves/s at rel. grad 1e-6, Lipschitz vs plain subspace",
+        "metric": ("potential-loss parameter-gradient items/s" if pgrad else
+                   "converged reduced solves/s at rel. grad 1e-6, Lipschitz vs plain subspace"),
         "value": conv / dt,
-        "unit": "solves/s",
+        "unit": "items/s" if pgrad else "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -240,12 +264,13 @@ def main():
             "workload": f"{name}: {p.meta['nx']}x{p.meta['ny']}x{p.meta['nz']} beam, nv={p.nv}, ne={p.ne}, "
                         f"r={p.r}, hidden={p.hidden}, |S|={len(p.cub_elem)}, B={B}, plain (untrained Glorot) "
                         f"decoder, twist 0-180 deg penalty targets",
-            "batch": B, "rows": info.rows, "subspace": "plain", "solver": args.solver,
+            "batch": B, "rows": info.rows, "subspace": "plain", "solver": "none" if pgrad else args.solver,
+            "path": args.path,
         },
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
         "mean_iters": mean_iters,
-        "lipschitz_loss": float(lip["loss"].item()),
+        "lipschitz_loss": None if pgrad else float(lip["loss"].item()),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

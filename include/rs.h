@@ -214,6 +214,29 @@ int rs_decode(rs_ctx* ctx, int32_t B, const double* z, void* x, void* J, void* s
 int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* load,
                         uint32_t flags, double* E, double* g, double* H, void* stream);
 
+/* Number of decoder parameters: sum over the layers (output layer last) of
+ * out x in weights plus out biases, the length of rs_energy_param_grad's
+ * gradient.  Errors: RS_ERR_STATE (NULL ctx), RS_ERR_ARG (NULL n). */
+int rs_param_count(const rs_ctx* ctx, int64_t* n);
+
+/* Gradient of sum_b E(z_b) over B latent points with respect to every
+ * decoder parameter theta: the potential loss of the unsupervised subspace
+ * construction (Sec. 3.2, Eq. form-vanilla-unsupervised-construction; its
+ * expectation over z taken as the caller's sample sum), differentiated by
+ * reverse mode through the cubature energy, the output layer and the hidden
+ * layers, with the hidden activations recomputed from their pre-activations.
+ * grad (device, float64, rs_param_count values) is overwritten, packed as
+ * W_1, b_1, ..., W_L, b_L, W_out, b_out with each W row-major (out x in) as
+ * in rs_decoder; rows of pinned vertices in W_out and b_out get zero.  Sums over
+ * items are float64.  E (B, float64) and g = dE/dz (B x r) are per item and may
+ * be NULL.  z (B x r) float64 device; any B >= 0 (chunks of max_batch; B = 0
+ * gives a zero gradient).  flags: 0 or RS_ELASTIC_ONLY.  The library owns
+ * its workspace; the caller owns every pointer argument.  Errors: RS_ERR_ARG
+ * (NULL grad or z, other flags), RS_ERR_UNSUPPORTED (BF16 contexts, no
+ * hidden layers, or hidden layers outside what the fused kernel supports). */
+int rs_energy_param_grad(rs_ctx* ctx, int32_t B, const double* z, const rs_load* load, uint32_t flags,
+                         double* E, double* g, double* grad, void* stream);
+
 /* Projective Newton with backtracking line search (supplement, projective
  * Newton tests) for B <= max_batch independent items, z (B x r) in/out.
  * Per item: iters (int32) accepted steps, status (RS_CONVERGED...), relgrad

@@ -78,7 +78,8 @@ class Info(C.Structure):
 # every symbol include/rs.h declares
 SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy", "rs_set_decoder",
            "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
-           "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get"]
+           "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
+           "rs_energy_param_grad"]
 
 _lib = None
 
@@ -111,6 +112,9 @@ def load_library():
                                      C.c_void_p, C.c_void_p]
         L.rs_lipschitz_loss.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.rs_energy_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.c_uint32,
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -230,6 +234,43 @@ class Context:
         dec = self._decoder_struct(Ws, bs, keep)
         self._check(load_library().rs_set_decoder(self.ctx, C.byref(dec)), "rs_set_decoder")
 
+    def param_shapes(self):
+        """(W, b) shapes of every decoder layer, output layer last (the packed gradient's order)."""
+        dims = [self.r] + list(self.p.hidden) + [self.n]
+        return [((dims[l + 1], dims[l]), (dims[l + 1],)) for l in range(len(dims) - 1)]
+
+    def param_count(self) -> int:
+        n = C.c_int64()
+        self._check(load_library().rs_param_count(self.ctx, C.byref(n)), "rs_param_count")
+        return n.value
+
+    def unpack_params(self, flat):
+        """Views of a packed parameter vector as [(W, b), ...], output layer last."""
+        out, off = [], 0
+        for ws, bs in self.param_shapes():
+            nw, nb = ws[0] * ws[1], bs[0]
+            out.append((flat[off:off + nw].view(*ws), flat[off + nw:off + nw + nb]))
+            off += nw + nb
+        return out
+
+    def set_decoder_flat(self, theta):
+        """Load the decoder from a packed parameter vector (any device; copied to the host)."""
+        parts = self.unpack_params(theta.detach().to("cpu", torch.float64))
+        self.set_decoder([W.numpy() for W, _ in parts], [b.numpy() for _, b in parts])
+
+    def energy_param_grad(self, z, targets=None, force=None, flags=0, want_E=True, want_g=True):
+        """(E (B), g = dE/dz (B x r), grad) with grad the packed gradient of sum_b E(z_b)
+        with respect to the decoder parameters (float64 device tensors; E, g may be None)."""
+        B = z.shape[0]
+        _dev(z, torch.float64, (B, self.r), "z")
+        ld, _keep = self._load(B, targets, force)
+        E = torch.empty(B, dtype=torch.float64, device=z.device) if want_E else None
+        g = torch.empty((B, self.r), dtype=torch.float64, device=z.device) if want_g else None
+        grad = torch.empty(self.param_count(), dtype=torch.float64, device=z.device)
+        self._check(load_library().rs_energy_param_grad(self.ctx, B, _ptr(z), C.byref(ld), flags, _ptr(E), _ptr(g),
+                                                        _ptr(grad), _stream()), "rs_energy_param_grad")
+        return E, g, grad
+
     def _load(self, B, targets, force):
         t = _dev(targets, torch.float64, (B, self.nt, 3), "targets")
         f = _dev(force, torch.float64, (B, 3), "force")
@@ -330,3 +371,24 @@ class Context:
             if la.value:
                 out[name.value.decode()] = dict(launches=la.value, ms=ms.value, bytes=by.value, flops=fl.value)
         return out
+
+
+class CubatureEnergy(torch.autograd.Function):
+    """sum_b E(z_b; theta): the summed cubature energy (the potential loss of
+    the unsupervised subspace construction, Sec. 3.2) as a differentiable
+    function of the latent points z and of the packed decoder parameters
+    theta.  Forward loads theta into the context and runs the library's
+    reverse pass once; backward scales the saved gradients.  Usage:
+    CubatureEnergy.apply(ctx, z, theta, targets, force, flags)."""
+
+    @staticmethod
+    def forward(fctx, rs_context, z, theta, targets=None, force=None, flags=0):
+        rs_context.set_decoder_flat(theta)
+        E, g, grad = rs_context.energy_param_grad(z.detach(), targets, force, flags)
+        fctx.save_for_backward(g, grad)
+        return E.sum()
+
+    @staticmethod
+    def backward(fctx, gout):
+        g, grad = fctx.saved_tensors
+        return None, gout * g, gout * grad, None, None, None

@@ -32,12 +32,12 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_ACTIVATE, K_LBFGS, K_COUNT
+    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
-    "newton_init", "activate", "lbfgs_dir"};
+    "newton_init", "activate", "lbfgs_dir", "param_grad"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -110,6 +110,17 @@ struct rs_ctx {
     double* zs = nullptr;         // max_batch x r
     double* ell = nullptr;        // max_batch
     double* lacc = nullptr;       // 3
+    // parameter gradients (rs_energy_param_grad)
+    double* delta = nullptr;      // max_batch x L x w: dE/da_l per item
+    double* dWbig = nullptr;      // M x in_last, float64: dE/dW_big summed over items
+    double* dbbig = nullptr;      // M
+    double* ppart = nullptr;      // kParamSlices partial sums of the largest parameter product
+    size_t ppart_cap = 0;
+    int* fold_ptr = nullptr;      // n_out + 1: CSR of the output-layer fold by W_out row
+    int* fold_row = nullptr;      // W_big row of each entry
+    double* fold_coef = nullptr;  // its coefficient
+    std::vector<size_t> offW, offb; // packed offsets of W_l, b_l (output layer last)
+    size_t n_params = 0;
     int* hcount = nullptr;        // pinned host
     int* hcount_dev = nullptr;    // device address of hcount
     hipEvent_t cnt_ev[2] = {nullptr, nullptr}; // running-count copies, one per parity of the super-step
@@ -259,6 +270,23 @@ static int upload_bf16(rs_ctx* c, void* dst, const std::vector<double>& src)
 
 // Upload the decoder: hidden layers padded for the GEMM tiles, and the folded
 // output maps (reduced W_big, its transpose, and the full W_out for rs_decode).
+// Shape-function gradients of cubature tet s: F = sum_a x_a Dv[a]^T, with
+// Dv[1..3] the rows of Dm^-1 and Dv[0] = -(Dv[1] + Dv[2] + Dv[3]).
+static void tet_shape_grads(const rs_ctx* c, int s, double Dv[4][3])
+{
+    const double* Di = &c->Dminv[9 * (size_t)s];
+    for (int j = 0; j < 3; ++j) {
+        double sum = 0.0;
+        for (int a = 1; a < 4; ++a) {
+            Dv[a][j] = Di[3 * (a - 1) + j];
+            sum += Dv[a][j];
+        }
+        Dv[0][j] = -sum;
+    }
+}
+
+static int build_fold(rs_ctx* c);
+
 static int load_decoder(rs_ctx* c, const rs_decoder* d)
 {
     const int r = c->r, w = c->w, L = c->L, in_last = c->in_last;
@@ -287,16 +315,8 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
     std::vector<double> Wb((size_t)c->Mp * lda, 0.0), bb(c->Mp, 0.0);
     for (int s = 0; s < c->S; ++s) {
         const int e = c->cub_elem[s];
-        const double* Di = &c->Dminv[9 * (size_t)s];
         double Dv[4][3];
-        for (int j = 0; j < 3; ++j) {
-            double sum = 0.0;
-            for (int a = 1; a < 4; ++a) {
-                Dv[a][j] = Di[3 * (a - 1) + j];
-                sum += Dv[a][j];
-            }
-            Dv[0][j] = -sum;
-        }
+        tet_shape_grads(c, s, Dv);
         for (int j = 0; j < 3; ++j)
             for (int i = 0; i < 3; ++i) {
                 const size_t row = 9 * (size_t)s + 3 * j + i;
@@ -607,6 +627,14 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->zs = (double*)need(dalloc<double>(c, B * c->r));
     c->ell = (double*)need(dalloc<double>(c, B));
     c->lacc = (double*)need(dalloc<double>(c, 4));
+    c->delta = (double*)need(dalloc<double>(c, B * std::max(c->L, 1) * std::max(c->w, 1)));
+    c->dWbig = (double*)need(dalloc<double>(c, (size_t)c->M * c->in_last));
+    c->dbbig = (double*)need(dalloc<double>(c, c->M));
+    {
+        const size_t mn = std::max((size_t)c->M * c->in_last, (size_t)std::max(c->w, 1) * std::max(c->r, c->w));
+        c->ppart_cap = (size_t)kParamSlices * (mn + std::max(c->M, c->w));
+        c->ppart = (double*)need(dalloc<double>(c, c->ppart_cap));
+    }
     if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
     // coherent: the kernel's system-scope store lands in host memory without a cache flush
     if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
@@ -626,7 +654,69 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
         if (upload(c, c->Xt, xt, 0) != RS_OK) return bail(RS_ERR_HIP);
     }
     if (load_decoder(c, dec) != RS_OK) return bail(RS_ERR_HIP);
+    {
+        const int rc = build_fold(c);
+        if (rc != RS_OK) return bail(rc);
+    }
     *out = c;
+    return RS_OK;
+}
+
+// The output-layer fold W_big = C W_out (rows of the cubature deformation
+// gradients, targets, gravity and forces; pinned rows of W_out excluded) as a
+// CSR of C^T by W_out row, so that dE/dW_out = C^T dE/dW_big.
+static int build_fold(rs_ctx* c)
+{
+    std::vector<std::vector<std::pair<int, double>>> by(c->n_out);
+    auto add = [&](int vrow, int brow, double coef) {
+        if (!c->pinned[vrow / 3] && coef != 0.0) by[vrow].push_back({brow, coef});
+    };
+    for (int s = 0; s < c->S; ++s) {
+        const int e = c->cub_elem[s];
+        double Dv[4][3];
+        tet_shape_grads(c, s, Dv);
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i)
+                for (int a = 0; a < 4; ++a) add(3 * c->tets[4 * (size_t)e + a] + i, 9 * s + 3 * j + i, Dv[a][j]);
+    }
+    for (int t = 0; t < c->nt; ++t)
+        for (int i = 0; i < 3; ++i) add(3 * c->tvtx[t] + i, 9 * c->S + 3 * t + i, 1.0);
+    for (int v = 0; v < c->nv; ++v)
+        for (int i = 0; i < 3; ++i) add(3 * v + i, c->grav_row, c->mass[v] * c->grav[i]);
+    for (int t = 0; t < c->nf; ++t)
+        for (int i = 0; i < 3; ++i) add(3 * c->fvtx[t] + i, c->force_row + i, 1.0);
+    std::vector<int> ptr(c->n_out + 1, 0), row;
+    std::vector<double> coef;
+    for (int n = 0; n < c->n_out; ++n) {
+        for (const auto& pc : by[n]) {
+            row.push_back(pc.first);
+            coef.push_back(pc.second);
+        }
+        ptr[n + 1] = (int)row.size();
+    }
+    if (row.empty()) {
+        row.push_back(0);
+        coef.push_back(0.0);
+    }
+    c->fold_ptr = (int*)dalloc<int>(c, ptr.size());
+    c->fold_row = (int*)dalloc<int>(c, row.size());
+    c->fold_coef = (double*)dalloc<double>(c, coef.size());
+    if (!c->fold_ptr || !c->fold_row || !c->fold_coef) return fail(c, RS_ERR_OOM, "device allocation failed");
+    if (hipMemcpy(c->fold_ptr, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->fold_row, row.data(), row.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->fold_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, RS_ERR_HIP, "hipMemcpy");
+    size_t off = 0;
+    c->offW.assign(c->L + 1, 0);
+    c->offb.assign(c->L + 1, 0);
+    for (int l = 0; l <= c->L; ++l) {
+        const int in = l == 0 ? c->r : c->w, out = l == c->L ? c->n_out : c->w;
+        c->offW[l] = off;
+        off += (size_t)out * in;
+        c->offb[l] = off;
+        off += out;
+    }
+    c->n_params = off;
     return RS_OK;
 }
 
@@ -928,7 +1018,7 @@ static bool grad_reverse_ok(const rs_ctx* c) { return c->L > 0 && !c->bf16 && ml
 
 static int eval_grad_rev(rs_ctx* c, int cap, const int* count, const double* z, const int* zmap,
                          const double* targets, const double* force, const int* imap, uint32_t flags, double* E,
-                         double* g, hipStream_t s)
+                         double* g, hipStream_t s, double* delta = nullptr)
 {
     const int r = c->r;
     const int f32 = c->f32;
@@ -1028,6 +1118,7 @@ static int eval_grad_rev(rs_ctx* c, int cap, const int* count, const double* z, 
     ca.count = count;
     ca.H = nullptr;
     ca.grev = g;
+    ca.delta = delta;
     const double pb = (double)c->L * c->w * ts + (double)c->ksplit * c->in_rows * ts + 8.0 * r;
     const double pf = (double)c->L * 2.0 * c->w * c->w;
     return run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); });
@@ -1124,6 +1215,97 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
                               K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
     }
     return RS_OK;
+}
+
+extern "C" int rs_param_count(const rs_ctx* c, int64_t* n)
+{
+    if (!c) return RS_ERR_STATE;
+    if (!n) return RS_ERR_ARG;
+    *n = (int64_t)c->n_params;
+    return RS_OK;
+}
+
+extern "C" int rs_energy_param_grad(rs_ctx* c, int32_t B, const double* z, const rs_load* load, uint32_t flags,
+                                    double* E, double* g, double* grad, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B must be >= 0");
+    if (!grad) return fail(c, RS_ERR_ARG, "grad is NULL");
+    if (B > 0 && !z) return fail(c, RS_ERR_ARG, "z is NULL");
+    if (flags & ~(uint32_t)RS_ELASTIC_ONLY) return fail(c, RS_ERR_ARG, "flags other than RS_ELASTIC_ONLY");
+    if (!grad_reverse_ok(c))
+        return fail(c, RS_ERR_UNSUPPORTED,
+                    "parameter gradients need hidden layers that fit the fused kernel and a float32 or float64 context");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double* tg = load ? load->targets : nullptr;
+    const double* fo = load ? load->force : nullptr;
+    const int r = c->r, w = c->w, L = c->L, f32 = c->f32;
+    c->cur_slot = -1;
+    if (B == 0) return run(c, K_PARAM_GRAD, item_work(0, 0, 1, nullptr, -1, 0), s,
+                           [&] { return launch_fill_zero(grad, c->n_params, s); });
+    for (int c0 = 0; c0 < B; c0 += c->max_batch) {
+        const int n = std::min(c->max_batch, B - c0);
+        const double* zc = z + (size_t)c0 * r;
+        const double* tgc = tg ? tg + (size_t)c0 * c->nt * 3 : nullptr;
+        const double* foc = fo ? fo + (size_t)c0 * 3 : nullptr;
+        RS_TRY(eval_grad_rev(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, (E && !f32) ? E + c0 : nullptr,
+                             g ? g + (size_t)c0 * r : nullptr, s, c->delta));
+        if (E && f32)
+            RS_TRY(energy_f64(c, n, nullptr, 0, zc, tgc, foc, nullptr, (flags & RS_ELASTIC_ONLY) ? 1 : 0, E + c0, s,
+                              K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
+        const int acc = c0 > 0;
+        // dE/dW_big = sum_b seeds_b h_L,b^T (folded back to W_out below)
+        ParamOuterArgs o{};
+        o.X = c->dseed;
+        o.x_f64 = !f32;
+        o.x_stride = c->Mp;
+        o.Y = c->act;
+        o.y_mode = PO_Y_RAW;
+        o.y_stride = c->wrows;
+        o.B = n;
+        o.M = c->M;
+        o.N = c->in_last;
+        o.out = c->dWbig;
+        o.ldo = c->in_last;
+        o.outb = c->dbbig;
+        o.accumulate = acc;
+        o.part = c->ppart;
+        o.part_cap = c->ppart_cap;
+        const double ts = (double)c->tsz;
+        RS_TRY(run(c, K_PARAM_GRAD, item_work(ts * (c->Mp + c->wrows), 2.0 * c->M * c->in_last, n, nullptr, -1, 0), s,
+                   [&] { return launch_param_outer(f32, o, s); }));
+        // hidden layers: dE/dW_l = sum_b delta_l,b h_{l-1},b^T with h_{l-1} = ELU(a_{l-1}) recomputed (h_0 = z)
+        for (int l = 0; l < L; ++l) {
+            ParamOuterArgs h{};
+            h.X = c->delta + (size_t)l * w;
+            h.x_f64 = 1;
+            h.x_stride = (size_t)L * w;
+            if (l == 0) {
+                h.Y = zc;
+                h.y_mode = PO_Y_F64;
+                h.y_stride = r;
+            } else {
+                h.Y = c->pre[l - 1];
+                h.y_mode = PO_Y_ELU;
+                h.y_stride = c->wrows;
+            }
+            h.B = n;
+            h.M = w;
+            h.N = l == 0 ? r : w;
+            h.out = grad + c->offW[l];
+            h.ldo = h.N;
+            h.outb = grad + c->offb[l];
+            h.accumulate = acc;
+            h.part = c->ppart;
+            h.part_cap = c->ppart_cap;
+            RS_TRY(run(c, K_PARAM_GRAD, item_work(8.0 * w + ts * h.N, 2.0 * w * h.N, n, nullptr, -1, 0), s,
+                       [&] { return launch_param_outer(f32, h, s); }));
+        }
+    }
+    return run(c, K_PARAM_GRAD, item_work(0, 0, 1, nullptr, -1, 0), s, [&] {
+        return launch_unfold(c->dWbig, c->dbbig, c->in_last, c->fold_ptr, c->fold_row, c->fold_coef, c->n_out,
+                             grad + c->offW[L], grad + c->offb[L], s);
+    });
 }
 
 extern "C" int rs_decode(rs_ctx* c, int32_t B, const double* z, void* x, void* J, void* stream)

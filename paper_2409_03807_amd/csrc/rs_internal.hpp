@@ -124,6 +124,7 @@ struct CurvArgs {
     const int* count;       // actual item count (NULL = grid size)
     double* H;              // items x r x r, accumulated
     double* grev;           // items x r reverse-mode gradient (may be NULL)
+    double* delta;          // items x L x width: dE/da_l of every layer (may be NULL)
     // parts > 1: H and g come as element-kernel partials (slot p * part_stride + i) that are summed
     // in part order into H (before the curvature term is added) and g
     int parts, part_stride;
@@ -131,6 +132,29 @@ struct CurvArgs {
     const double* gp;
     double* g;
 };
+
+// Batched outer products for parameter gradients: out[m][n] (+)= sum over
+// the B items of X_b[m] * Y_b[n] (float64 accumulation), and outb[m] (+)= sum
+// of X_b[m].  X is T (x_f64 = 0) or float64; Y is T, T through ELU, or float64.
+enum { PO_Y_RAW = 0, PO_Y_ELU = 1, PO_Y_F64 = 2 };
+struct ParamOuterArgs {
+    const void* X;
+    int x_f64;
+    size_t x_stride; // element m of item b at X[b * x_stride + m]
+    const void* Y;
+    int y_mode;
+    size_t y_stride;
+    int B, M, N;
+    double* out;
+    int ldo;
+    double* outb; // may be NULL
+    int accumulate;
+    // item slices summed separately into part ([slice][M][N], then [slice][M]
+    // for the bias sums) and added in slice order; part_cap values available
+    double* part;
+    size_t part_cap;
+};
+constexpr int kParamSlices = 8; // partial sums the workspace holds for the largest parameter product
 
 // Per-item Newton state.  ls_j[b] < 0: the item needs its gradient and Hessian
 // at z (evaluation phase); ls_j[b] >= 0: it is line-searching and the next
@@ -197,6 +221,12 @@ hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int ro
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
+hipError_t launch_param_outer(int f32, const ParamOuterArgs& a, hipStream_t s);
+// dW[n][k] = sum_j coef[j] * src[row[j]][k] and db[n] = sum_j coef[j] * srcb[row[j]]
+// over j in [ptr[n], ptr[n+1]): the transpose of a sparse row fold, n < rows
+hipError_t launch_unfold(const double* src, const double* srcb, int ncols, const int* ptr, const int* row,
+                         const double* coef, int rows, double* dW, double* db, hipStream_t s);
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);

@@ -2216,6 +2216,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             const double ex = exp(fmin(av, 0.0));
             cf[u] = av > 0.0 ? 0.0 : gh[u] * ex;
             ga[u] = av > 0.0 ? gh[u] : gh[u] * ex;
+            if (a.delta) a.delta[((size_t)item * a.L + l) * w + u] = ga[u];
         }
         __syncthreads();
         if (a.H) {
@@ -2320,6 +2321,190 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
                     }
                 }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Parameter gradients of a summed objective: batched outer products of an
+// adjoint (per item, per output) with a layer input (per item, per input),
+// summed over the items in float64; 64 x 64 output tiles, items staged 32 at
+// a time through LDS, each thread 4 x 4 outputs.
+// ---------------------------------------------------------------------------
+template <typename TX, typename TY, int YM>
+__global__ __launch_bounds__(256) void k_param_outer(ParamOuterArgs a, int nslice, int bper)
+{
+    constexpr int TB = 32;
+    __shared__ double xs[TB][64 + 1];
+    __shared__ double ys[TB][64 + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64, sl = blockIdx.z;
+    const int bbeg = sl * bper, bend = min(a.B, bbeg + bper);
+    const TX* X = static_cast<const TX*>(a.X);
+    const TY* Y = static_cast<const TY*>(a.Y);
+    double acc[4][4], accb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        accb[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    }
+    for (int b0 = bbeg; b0 < bend; b0 += TB) {
+        __syncthreads();
+        for (int e = tid; e < TB * 64; e += 256) {
+            const int bb = e >> 6, q = e & 63, b = b0 + bb;
+            double xv = 0.0, yv = 0.0;
+            if (b < bend && m0 + q < a.M) xv = (double)X[(size_t)b * a.x_stride + m0 + q];
+            if (b < bend && n0 + q < a.N) {
+                yv = (double)Y[(size_t)b * a.y_stride + n0 + q];
+                if (YM == PO_Y_ELU) yv = yv > 0.0 ? yv : expm1(yv);
+            }
+            xs[bb][q] = xv;
+            ys[bb][q] = yv;
+        }
+        __syncthreads();
+        const int nb = min(TB, bend - b0);
+        for (int bb = 0; bb < nb; ++bb) {
+            double xv[4], yv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                xv[i] = xs[bb][ty * 4 + i];
+                yv[i] = ys[bb][tx * 4 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                accb[i] += xv[i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(xv[i], yv[j], acc[i][j]);
+            }
+        }
+    }
+    // one slice: straight into the result; several: into the slice's partials
+    double* po = nslice > 1 ? a.part + (size_t)sl * a.M * a.N : nullptr;
+    double* pb = nslice > 1 ? a.part + (size_t)nslice * a.M * a.N + (size_t)sl * a.M : nullptr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + ty * 4 + i;
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + tx * 4 + j;
+            if (n >= a.N) continue;
+            if (po) {
+                po[(size_t)m * a.N + n] = acc[i][j];
+            } else {
+                double* o = a.out + (size_t)m * a.ldo + n;
+                *o = a.accumulate ? *o + acc[i][j] : acc[i][j];
+            }
+        }
+        if (a.outb && blockIdx.x == 0 && tx == 0) {
+            if (pb) pb[m] = accb[i];
+            else a.outb[m] = a.accumulate ? a.outb[m] + accb[i] : accb[i];
+        }
+    }
+}
+
+// the slices' partial sums added in slice order (then the bias sums)
+__global__ __launch_bounds__(256) void k_param_reduce(ParamOuterArgs a, int nslice)
+{
+    const size_t mn = (size_t)a.M * a.N;
+    const size_t tot = mn + (a.outb ? (size_t)a.M : 0);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        if (e < mn) {
+            // eight loads in flight, added in slice order
+            int q = 0;
+            for (; q + 8 <= nslice; q += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = a.part[(size_t)(q + u) * mn + e];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sum += v[u];
+            }
+            for (; q < nslice; ++q) sum += a.part[(size_t)q * mn + e];
+            const size_t m = e / a.N, n = e - m * a.N;
+            double* o = a.out + m * a.ldo + n;
+            *o = a.accumulate ? *o + sum : sum;
+        } else {
+            const size_t m = e - mn;
+            for (int q = 0; q < nslice; ++q) sum += a.part[(size_t)nslice * mn + (size_t)q * a.M + m];
+            a.outb[m] = a.accumulate ? a.outb[m] + sum : sum;
+        }
+    }
+}
+
+hipError_t launch_param_outer(int f32, const ParamOuterArgs& a, hipStream_t s)
+{
+    if (a.B <= 0 || a.M <= 0 || a.N <= 0) return hipSuccess;
+    // item slices: about 1024 workgroups, each slice at least 8 items, within
+    // the partial-sum workspace
+    const int tiles = ((a.N + 63) / 64) * ((a.M + 63) / 64);
+    int nslice = std::max(1, std::min({(1024 + tiles - 1) / tiles, (a.B + 7) / 8, 32}));
+    nslice = std::min<size_t>(nslice, a.part_cap / ((size_t)a.M * a.N + a.M));
+    nslice = std::max(nslice, 1);
+    const int bper = (a.B + nslice - 1) / nslice;
+    dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, nslice), block(256);
+#define RS_PO(TX, TY, YM) RS_LAUNCH((k_param_outer<TX, TY, YM>), grid, block, 0, s, a, nslice, bper)
+    if (a.x_f64) {
+        if (a.y_mode == PO_Y_F64) RS_PO(double, double, PO_Y_F64);
+        else if (f32) {
+            if (a.y_mode == PO_Y_ELU) RS_PO(double, float, PO_Y_ELU);
+            else RS_PO(double, float, PO_Y_RAW);
+        } else {
+            if (a.y_mode == PO_Y_ELU) RS_PO(double, double, PO_Y_ELU);
+            else RS_PO(double, double, PO_Y_RAW);
+        }
+    } else {
+        if (!f32) return hipErrorInvalidValue; // a T adjoint is float64 only in a float64 context (x_f64)
+        if (a.y_mode == PO_Y_ELU) RS_PO(float, float, PO_Y_ELU);
+        else if (a.y_mode == PO_Y_RAW) RS_PO(float, float, PO_Y_RAW);
+        else RS_PO(float, double, PO_Y_F64);
+    }
+#undef RS_PO
+    if (nslice > 1) {
+        const size_t tot = (size_t)a.M * a.N + (a.outb ? (size_t)a.M : 0);
+        const size_t blocks = std::min<size_t>((tot + 255) / 256, 4096);
+        RS_LAUNCH(k_param_reduce, dim3((unsigned)blocks), dim3(256), 0, s, a, nslice);
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(128) void k_unfold(const double* src, const double* srcb, int ncols, const int* ptr,
+                                                const int* row, const double* coef, int rows, double* dW, double* db)
+{
+    const int n = blockIdx.x;
+    if (n >= rows) return;
+    const int j0 = ptr[n], j1 = ptr[n + 1];
+    for (int k = threadIdx.x; k < ncols; k += blockDim.x) {
+        double sum = 0.0;
+        for (int j = j0; j < j1; ++j) sum = fma(coef[j], src[(size_t)row[j] * ncols + k], sum);
+        dW[(size_t)n * ncols + k] = sum;
+    }
+    if (threadIdx.x == 0) {
+        double sb = 0.0;
+        for (int j = j0; j < j1; ++j) sb = fma(coef[j], srcb[row[j]], sb);
+        db[n] = sb;
+    }
+}
+
+hipError_t launch_unfold(const double* src, const double* srcb, int ncols, const int* ptr, const int* row,
+                         const double* coef, int rows, double* dW, double* db, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    RS_LAUNCH(k_unfold, dim3(rows), dim3(128), 0, s, src, srcb, ncols, ptr, row, coef, rows, dW, db);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_zero(double* p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    RS_LAUNCH(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)

@@ -69,3 +69,6 @@ def test_default_opts_and_errors_on_host(lib):
     assert lib.rs_newton_solve(None, 0, None, None, None, None, None, None, None, None) == 4
     assert lib.rs_lbfgs_solve(None, 0, None, None, None, None, None, None, None, None) == 4
     assert lib.rs_energy_grad_hess(None, 0, None, None, 0, None, None, None, None) == 4
+    assert lib.rs_energy_param_grad(None, 0, None, None, 0, None, None, None, None) == 4
+    n = C.c_int64(-1)
+    assert lib.rs_param_count(None, C.byref(n)) == 4 and n.value == -1

@@ -382,6 +382,99 @@ def test_bf16_newton_exit_points():
     assert relerr(res["E"].cpu().numpy()[:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
 
 
+# ------------------------------------------------------ parameter gradient
+def _layer_errs(ctx, grad, go):
+    """Per-layer relative errors (W and b, flattened) of a packed gradient."""
+    errs = []
+    o = O.Oracle(ctx.p)
+    for (gW, gb), (oW, ob) in zip(ctx.unpack_params(grad.cpu()), o.unpack_params(go)):
+        for a, b in ((gW.numpy().ravel(), oW.ravel()), (gb.numpy(), ob)):
+            errs.append(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    return errs
+
+
+@pytest.mark.parametrize("name,prec", [("tinyb", rb.PREC_F64), ("tinyb", rb.PREC_F32), ("c1", rb.PREC_F64),
+                                       ("c2", rb.PREC_F32)])
+@pytest.mark.parametrize("flags", [0, rb.ELASTIC_ONLY])
+def test_energy_param_grad(name, prec, flags):
+    """dE/dtheta of the summed energy (Sec. 3.2's potential loss) against the
+    oracle's hand-applied chain rule, layer by layer."""
+    p = problem(name)
+    B = 5
+    ctx = rb.Context(p, prec=prec, max_batch=8)
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    E, g, grad = ctx.energy_param_grad(t64(z), t64(tg), t64(fo), flags=flags)
+    assert grad.numel() == ctx.param_count()
+    o = O.Oracle(p)
+    oflags = O.ELASTIC_ONLY if flags & rb.ELASTIC_ONLY else 0
+    Eo, go = o.energy_param_grad(z, tg, fo, flags=oflags)
+    _, gzo, _ = o.reduced(z, tg, fo, flags=oflags)
+    assert relerr(E.cpu().numpy()[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+    assert relerr(g.cpu().numpy(), gzo).max() < TOL[prec]
+    assert max(_layer_errs(ctx, grad, go)) < TOL[prec]
+
+
+def test_energy_param_grad_chunks_and_empty_batch():
+    """B above max_batch accumulates over chunks (ragged last chunk); B = 0 gives zeros."""
+    p = problem("tinyb")
+    ctx = rb.Context(p, prec=rb.PREC_F64, max_batch=4)
+    B = 11
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    E, g, grad = ctx.energy_param_grad(t64(z), t64(tg), t64(fo))
+    Eo, go = O.Oracle(p).energy_param_grad(z, tg, fo)
+    assert max(_layer_errs(ctx, grad, go)) < 1e-10
+    grad.fill_(7.0)
+    ld, _ = ctx._load(0, None, None)
+    rc = rb.load_library().rs_energy_param_grad(ctx.ctx, 0, None, rb.C.byref(ld), 0, None, None, rb._ptr(grad),
+                                                rb._stream())
+    assert rc == rb.RS_OK
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(grad).item() == 0
+
+
+def test_energy_param_grad_errors():
+    p = problem("tinyb")
+    ctx = rb.Context(p, prec=rb.PREC_F64, max_batch=4)
+    z = t64(I.latent_batch(2, p.r))
+    with pytest.raises(RuntimeError, match="code 1"):
+        ctx.energy_param_grad(z, flags=rb.HESS_EXACT)
+    bctx = rb.Context(problem("c1"), prec=rb.PREC_BF16, max_batch=4)
+    with pytest.raises(RuntimeError, match="code 5"):
+        bctx.energy_param_grad(t64(I.latent_batch(2, 8)))
+
+
+def test_cubature_energy_autograd_function():
+    """torch.autograd through the library's reverse pass: theta.grad and z.grad
+    against the oracle, and a directional finite difference of the GPU's own
+    float64 energy along a random parameter direction."""
+    p = problem("tinyb")
+    ctx = rb.Context(p, prec=rb.PREC_F64, max_batch=8)
+    o = O.Oracle(p)
+    B = 4
+    zn = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    theta0 = torch.cat([torch.cat([torch.tensor(W).ravel(), torch.tensor(b)]) for W, b in zip(p.Ws, p.bs)])
+    theta = theta0.to(DEV).clone().requires_grad_(True)
+    z = t64(zn).requires_grad_(True)
+    loss = rb.CubatureEnergy.apply(ctx, z, theta, t64(tg), t64(fo), 0)
+    loss.backward()
+    Eo, go = o.energy_param_grad(zn, tg, fo)
+    _, gzo, _ = o.reduced(zn, tg, fo, flags=0)
+    assert abs(loss.item() - Eo.sum()) <= 1e-10 * abs(Eo).sum()
+    assert max(_layer_errs(ctx, theta.grad.detach(), go)) < 1e-10
+    assert relerr(z.grad.cpu().numpy(), gzo).max() < 1e-10
+    d = torch.tensor(np.random.default_rng(3).normal(size=theta0.numel()), dtype=torch.float64, device=DEV)
+    h = 1e-6
+    with torch.no_grad():
+        Ep = rb.CubatureEnergy.apply(ctx, z, theta + h * d, t64(tg), t64(fo), 0).item()
+        Em = rb.CubatureEnergy.apply(ctx, z, theta - h * d, t64(tg), t64(fo), 0).item()
+    fd = (Ep - Em) / (2 * h)
+    an = float((theta.grad * d).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
 # ------------------------------------------------------------------- misc
 def test_set_decoder_matches_fresh_context():
     p = problem("tinyb")
