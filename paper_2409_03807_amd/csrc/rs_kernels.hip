@@ -1456,8 +1456,10 @@ struct Snh {
     }
 };
 // ---------------------------------------------------------------------------
-// Element kernel: one workgroup per item, RP lanes per cubature tet (lane k
-// owns column k of K_e = dvecF/dz).  The item's rows are streamed through a
+// Element kernel: one workgroup per item (or a run of its rounds, when a small
+// batch splits items), RP lanes per cubature tet: lane k owns column k of
+// K_e = dvecF/dz, or with RP == 8 (r == 16) columns k and k + 8.  The item's
+// rows are streamed through a
 // three-slot LDS ring by direct global->LDS loads (16 bytes per lane): one
 // round is EPR tets (9 rows each), then EPR penalty targets (3 rows each);
 // two rounds are in flight while one is used.
