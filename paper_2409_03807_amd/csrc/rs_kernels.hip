@@ -3380,30 +3380,34 @@ hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, in
     return hipGetLastError();
 }
 
-// per pair: |H(z1)-H(z2)|_F^2 / |z1-z2|^2 (pair b's Hessians are items 2b, 2b+1)
-__global__ void k_lip_pairs(const double* z1, const double* z2, const double* H, int B, int r,
-                            double* per_pair, double* ell)
+// per pair: |H(z1)-H(z2)|_F^2 / |z1-z2|^2 (pair b's Hessians are items 2b, 2b+1);
+// one wave per pair, lanes over the entries (coalesced), a fixed butterfly sum
+__global__ __launch_bounds__(256) void k_lip_pairs(const double* z1, const double* z2, const double* H, int B, int r,
+                                                   double* per_pair, double* ell)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= B) return;
-    double dz2 = 0.0;
-    for (int k = 0; k < r; ++k) {
+    double dz2 = 0.0, f = 0.0;
+    for (int k = lane; k < r; k += 64) {
         const double d = z1[(size_t)b * r + k] - z2[(size_t)b * r + k];
         dz2 += d * d;
     }
-    double v = -1.0;
-    if (dz2 > 0.0) {
-        const double* H1 = H + (size_t)(2 * b) * r * r;
-        const double* H2 = H1 + (size_t)r * r;
-        double f = 0.0;
-        for (int q = 0; q < r * r; ++q) {
-            const double d = H1[q] - H2[q];
-            f += d * d;
-        }
-        v = f / dz2;
+    const double* H1 = H + (size_t)(2 * b) * r * r;
+    const double* H2 = H1 + (size_t)r * r;
+    for (int q = lane; q < r * r; q += 64) {
+        const double d = H1[q] - H2[q];
+        f += d * d;
     }
-    ell[b] = v;
-    if (per_pair) per_pair[b] = v < 0.0 ? 0.0 : v;
+    for (int o = 32; o > 0; o >>= 1) {
+        dz2 += __shfl_xor(dz2, o);
+        f += __shfl_xor(f, o);
+    }
+    if (lane == 0) {
+        const double v = dz2 > 0.0 ? f / dz2 : -1.0;
+        ell[b] = v;
+        if (per_pair) per_pair[b] = v < 0.0 ? 0.0 : v;
+    }
 }
 
 // acc = {sum, count, max sqrt}; carried over chunks, finalised on the last one
@@ -3449,7 +3453,7 @@ hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H,
                             double* loss, int* n_valid, double* lip_max, hipStream_t s)
 {
     if (B > 0)
-        RS_LAUNCH(k_lip_pairs, dim3((B + 255) / 256), dim3(256), 0, s, z1, z2, H, B, r, per_pair, ell);
+        RS_LAUNCH(k_lip_pairs, dim3((B + 3) / 4), dim3(256), 0, s, z1, z2, H, B, r, per_pair, ell);
     RS_LAUNCH(k_lip_reduce, dim3(1), dim3(256), 0, s, ell, B, acc, first_chunk, last_chunk, loss,
                        n_valid, lip_max);
     return hipGetLastError();
