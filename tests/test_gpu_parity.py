@@ -660,6 +660,10 @@ def test_largest_sizes_evaluation(name, prec):
     assert relerr(H.cpu().numpy(), Ho).max() < tol
     Er, gr, _ = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=rb.GRAD_REVERSE)
     assert relerr(gr.cpu().numpy(), go).max() < tol
+    # decoder-parameter gradient at the widest layers and the deepest decoder
+    _, _, grad = ctx.energy_param_grad(t64(z), t64(tg), t64(fo))
+    _, pgo = o.energy_param_grad(z, tg, fo)
+    assert max(_layer_errs(ctx, grad, pgo)) < tol
 
 
 @pytest.mark.parametrize("name", sorted(MAXCASES))
