@@ -2733,6 +2733,12 @@ __device__ inline double rcp_nr(double x)
     return y;
 }
 
+// Jacobi sweeps stop once the squared off-diagonal norm is below this
+// fraction of the squared Frobenius norm: off-diagonal entries at 1e-12 of the
+// matrix leave eigenvalue errors of order 1e-24 relative (second order) and
+// eigenvector errors of order 1e-12, far inside what the projected step needs.
+constexpr double kJacobiTol = 1e-24;
+
 // Parallel Jacobi eigen-decomposition of a symmetric n2 x n2 matrix (n2 even,
 // n2 <= 16) held in registers of one wave (Brent-Luk layout).  The indices are
 // paired by slot: slot k pairs (t_k, b_k), and one step rotates all n2/2 pairs
@@ -2764,7 +2770,7 @@ __device__ void jacobi_wave(double (*Hs)[kMaxR + 1], double (*Vs)[kMaxR + 1], in
         }
         off = __shfl(off, 0); // one decision for the whole wave
         tot = __shfl(tot, 0);
-        if (off <= 1e-30 * tot || off == 0.0) break;
+        if (off <= kJacobiTol * tot || off == 0.0) break;
         for (int step = 0; step < n2 - 1; ++step) {
             double c = 1.0, sn = 0.0;
             if (I == J && htb != 0.0) {
@@ -3007,7 +3013,7 @@ __global__ __launch_bounds__(64) void k_newton_dir(NewtonState st, NewtonParams 
                 // lane 0 decides for the whole wave (barriers follow)
                 off = __shfl(off, 0);
                 tot = __shfl(tot, 0);
-                if (off <= 1e-30 * tot || off == 0.0) break;
+                if (off <= kJacobiTol * tot || off == 0.0) break;
                 for (int step = 0; step < n2 - 1; ++step) {
                     if (tid < P) {
                         const int m1 = tid, m2 = n2 - 1 - tid;
