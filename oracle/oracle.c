@@ -483,8 +483,23 @@ static int finite_vec(const double* a, int n)
     return 1;
 }
 
+/* per-element projection to positive semi-definite: the 12x12 element
+ * Hessian's negative eigenvalues set to zero (Jacobi eigen-decomposition) */
+static void psd_clamp12(double* He)
+{
+    double lam[12], Vv[144];
+    or_sym_eig(12, He, lam, Vv);
+    for (int u = 0; u < 12; ++u)
+        for (int v = 0; v < 12; ++v) {
+            double s = 0.0;
+            for (int k = 0; k < 12; ++k) s += Vv[u * 12 + k] * fmax(lam[k], 0.0) * Vv[v * 12 + k];
+            He[u * 12 + v] = s;
+        }
+}
+
 /* E, g_r = J^T gq and H_r = sum_e w_e J_e^T H_e J_e + k_c sum_t J_t^T J_t
- * (+ sum_k gq_k d2q_k/dz2 when exact) at one latent point */
+ * (+ sum_k gq_k d2q_k/dz2 when exact) at one latent point; with OR_ELEM_PSD
+ * each element Hessian H_e is first projected to positive semi-definite */
 static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
                       const double* tgt, const double* f, int flags, double* E,
                       double* g, double* H)
@@ -515,6 +530,7 @@ static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
             double xe[12];
             gather(p, e, x, xe);
             elem_hess_dm(rd->Dminv + 9 * e, rd->V[e], xe, rd->mu, rd->lam, He);
+            if (flags & OR_ELEM_PSD) psd_clamp12(He);
             for (int a = 0; a < 4; ++a)
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < r; ++k)
@@ -633,6 +649,11 @@ static int newton_dir(int n, const double* H, const double* g, int proj, double 
     return rc;
 }
 
+int or_newton_dir(int n, const double* H, const double* g, int proj, double eig_floor, double* dz)
+{
+    return newton_dir(n, H, g, proj, eig_floor, dz);
+}
+
 static double inf_norm(const double* a, int n)
 {
     double m = 0.0;
@@ -749,6 +770,8 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
     double* zt = (double*)malloc(sizeof(double) * r);
     double* S = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * r);
     double* Y = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * r);
+    double* s_new = (double*)malloc(sizeof(double) * r);
+    double* y_new = (double*)malloc(sizeof(double) * r);
     double E;
     int npair = 0;
     item_eval(p, rd, z, tgt, f, 0, &E, g, NULL);
@@ -773,7 +796,6 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
         if (!ok) { st = OR_LS_MAX; break; }
         /* s = z_new - z, y = g_new - g; the pair is kept only when s'y > 0
          * (curvature condition: Armijo backtracking does not enforce it) */
-        double s_new[32], y_new[32];
         for (int k = 0; k < r; ++k) s_new[k] = zt[k] - z[k];
         memcpy(gold, g, sizeof(double) * r);
         memcpy(z, zt, sizeof(double) * r);
@@ -795,13 +817,13 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
     *status = st;
     *relgrad = g0 > 0.0 ? gn / g0 : 0.0;
     *Eout = E;
-    free(g); free(gold); free(dz); free(zt); free(S); free(Y);
+    free(g); free(gold); free(dz); free(zt); free(S); free(Y); free(s_new); free(y_new);
 }
 
 int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const double* force,
              const or_lbfgs_opts* o, int* iters, int* status, double* relgrad, double* E)
 {
-    if (p->r > 32 || o->history < 0) return 1;
+    if (o->history < 0) return 1;
     rest_data rd;
     rest_build(p, &rd);
 #pragma omp parallel for schedule(dynamic)
@@ -882,7 +904,7 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
     double* H = (double*)malloc(sizeof(double) * (size_t)nf * nf);
     double* dz = (double*)malloc(sizeof(double) * nf);
     double* xt = (double*)malloc(sizeof(double) * n);
-    double He[144], lam[12], Vv[144];
+    double He[144];
     double E = 0.0, g0 = 0.0, gn = 0.0;
     int it = 0, st;
     for (;;) {
@@ -899,15 +921,7 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
             double xe[12];
             gather(p, e, x, xe);
             elem_hess_dm(rd.Dminv + 9 * e, rd.V[e], xe, rd.mu, rd.lam, He);
-            if (elem_psd) { /* clamp negative element eigenvalues to zero */
-                or_sym_eig(12, He, lam, Vv);
-                for (int u = 0; u < 12; ++u)
-                    for (int v = 0; v < 12; ++v) {
-                        double s = 0.0;
-                        for (int k = 0; k < 12; ++k) s += Vv[u * 12 + k] * fmax(lam[k], 0.0) * Vv[v * 12 + k];
-                        He[u * 12 + v] = s;
-                    }
-            }
+            if (elem_psd) psd_clamp12(He);
             for (int u = 0; u < 12; ++u) {
                 int ru = idx[3 * p->tets[4 * e + u / 3] + u % 3];
                 if (ru < 0) continue;

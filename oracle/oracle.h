@@ -66,7 +66,7 @@ typedef struct {
 } or_lbfgs_opts;
 
 enum { OR_CONVERGED = 0, OR_NOT_DESCENT = 1, OR_LS_MAX = 2, OR_ITER_MAX = 3, OR_NONFINITE = 4 };
-enum { OR_EXACT = 1, OR_ELASTIC_ONLY = 2, OR_ENERGY_ONLY = 4 };
+enum { OR_EXACT = 1, OR_ELASTIC_ONLY = 2, OR_ENERGY_ONLY = 4, OR_ELEM_PSD = 8 };
 
 /* material and stable Neo-Hookean density (F is 3x3 row-major) */
 void or_lame(double young, double poisson, double* mu, double* lam);
@@ -91,6 +91,12 @@ int or_decode_hess(const or_problem* p, const double* z, double* T);
  * targets (B x nt x 3) and force (B x 3, applied to each force vertex) nullable. */
 int or_reduced(const or_problem* p, int B, const double* z, const double* targets,
                const double* force, int flags, double* E, double* g, double* H);
+
+/* Newton direction of one item: dz = -H^-1 g with the Cholesky factor of the
+ * symmetrised H when it is positive definite, else with its eigen-projection
+ * (proj 0: eigenvalues raised to eig_floor * max|eig|; 1: replaced by
+ * max(|eig|, eig_floor * max|eig|); 2: none, returns 1).  Exposed for pins. */
+int or_newton_dir(int n, const double* H, const double* g, int proj, double eig_floor, double* dz);
 
 /* reduced projective Newton with backtracking line search, z in/out */
 int or_newton(const or_problem* p, int B, double* z, const double* targets,

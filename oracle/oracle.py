@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
 CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE = 0, 1, 2, 3, 4
-EXACT, ELASTIC_ONLY, ENERGY_ONLY = 1, 2, 4
+EXACT, ELASTIC_ONLY, ENERGY_ONLY, ELEM_PSD = 1, 2, 4, 8
 PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
 
 
@@ -165,6 +165,16 @@ def elem_hess(Xe, xe, mu, lam):
     return H.reshape(12, 12)
 
 
+def newton_dir(H, g, proj=PROJ_ABS, eig_floor=1e-8):
+    """(dz, rc): the Newton direction of or_newton for one item (rc = 1: no
+    direction, an indefinite H without projection)."""
+    H, g = _c64(H), _c64(g)
+    n = g.shape[0]
+    dz = np.zeros(n)
+    rc = lib().or_newton_dir(C.c_int(n), _d(H), _d(g), C.c_int(proj), C.c_double(eig_floor), _d(dz))
+    return dz, rc
+
+
 def sym_eig(A):
     A = _c64(A)
     n = A.shape[0]
@@ -272,7 +282,7 @@ class Oracle:
         rc = lib().or_lbfgs(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
                             _i(status), _d(relg), _d(E))
         if rc:
-            raise ValueError("or_lbfgs: r > 32 or negative history")
+            raise ValueError("or_lbfgs: negative history")
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
     def full_energy(self, x, targets=None, force=None):
