@@ -666,7 +666,7 @@ static void item_newton(const or_problem* p, const rest_data* rd, double* z, con
                         double* relgrad, double* Eout)
 {
     int r = p->r;
-    int flags = o->hess ? OR_EXACT : 0;
+    int flags = ((o->hess & 1) ? OR_EXACT : 0) | ((o->hess & 2) ? OR_ELEM_PSD : 0);
     double* g = (double*)malloc(sizeof(double) * r);
     double* H = (double*)malloc(sizeof(double) * r * r);
     double* dz = (double*)malloc(sizeof(double) * r);
@@ -1091,5 +1091,437 @@ int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
     if (lip_max) *lip_max = mx;
     free(ell); free(valid);
     rest_free(&rd);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Decoder-parameter gradient of the Lipschitz loss (Sec. 4.1, Eq.            */
+/* form-L-LS-E; Sec. 4.2: elastic term only, cubature Hessian of Sec. 4.3).   */
+/*                                                                           */
+/* With D_b = H(z1_b) - H(z2_b), H the exact cubature elastic Hessian, and    */
+/* l_b = |D_b|_F^2 / |z1_b - z2_b|^2, the loss mean_b l_b has the gradient    */
+/*   sum_b <C_b, dH(z1_b)/dtheta> - <C_b, dH(z2_b)/dtheta>,                   */
+/*   C_b = 2 D_b / (|z1_b - z2_b|^2 n_valid).                                 */
+/* <C, H(z)> = sum_kq C_kq d2 P~(q(z)) / dz_k dz_q is differentiated by the   */
+/* chain rule written out: forward, the value h_l, Jacobian J_l and the       */
+/* C-contracted second derivative S_l = sum_kq C_kq d2 h_l / dz_k dz_q of     */
+/* every layer (and of the output rows); per cubature element the contracted  */
+/* Hessian tr(C K^T A(F) K) + P(F) : Fdd, K = dvecF/dz, Fdd = C-contracted    */
+/* second derivative of F; backward, the adjoints of (h, J, S) down to the    */
+/* first layer.  The derivative of A = d2 psi / dF2 with respect to F is      */
+/* taken entry by entry from the third derivatives of det F (products of two  */
+/* permutation symbols).                                                      */
+/* ------------------------------------------------------------------------- */
+static double elu3(double a) { return a > 0.0 ? 0.0 : exp(a); }
+
+/* d2 det / dF_p dF_q and d3 det / dF_p dF_q dF_m at vec indices p = 3 j + i */
+static double d2det(const double* F, int p, int q)
+{
+    int i = p % 3, j = p / 3, k = q % 3, l = q / 3;
+    if (j == l) return 0.0;
+    int c = 3 - j - l;
+    double h = 0.0;
+    for (int m = 0; m < 3; ++m) h += levi(j, l, c) * levi(i, k, m) * F[3 * m + c];
+    return h;
+}
+
+static double d3det(int p, int q, int m)
+{
+    return (double)(levi(p % 3, q % 3, m % 3) * levi(p / 3, q / 3, m / 3));
+}
+
+static void param_offsets(const or_problem* p, size_t* offW, size_t* offb, size_t* total)
+{
+    size_t off = 0;
+    for (int l = 0; l <= p->L; ++l) {
+        int in = l == 0 ? p->r : p->width, out = l == p->L ? p->n_out : p->width;
+        offW[l] = off;
+        off += (size_t)out * in;
+        offb[l] = off;
+        off += out;
+    }
+    *total = off;
+}
+
+static void hess_contract_grad(const or_problem* p, const rest_data* rd, const double* z, const double* C,
+                               double sign, const size_t* offW, const size_t* offb, double* grad)
+{
+    const int r = p->r, w = p->width, L = p->L, n = p->n_out;
+    const int cap = w > r ? w : r;
+    /* layer inputs (h, J, S) of every layer and of the output layer, and pre-activations */
+    double* Hin = (double*)calloc((size_t)(L + 1) * cap, sizeof(double));
+    double* Jin = (double*)calloc((size_t)(L + 1) * cap * r, sizeof(double));
+    double* Sin = (double*)calloc((size_t)(L + 1) * cap, sizeof(double));
+    double* Pa = (double*)calloc((size_t)(L > 0 ? L : 1) * w, sizeof(double));
+    double* PA = (double*)calloc((size_t)(L > 0 ? L : 1) * w * r, sizeof(double));
+    double* PS = (double*)calloc((size_t)(L > 0 ? L : 1) * w, sizeof(double));
+    for (int k = 0; k < r; ++k) { Hin[k] = z[k]; Jin[k * r + k] = 1.0; }
+    for (int l = 0; l < L; ++l) {
+        const int in = l == 0 ? r : w;
+        const double* h0 = Hin + (size_t)l * cap;
+        const double* J0 = Jin + (size_t)l * cap * r;
+        const double* S0 = Sin + (size_t)l * cap;
+        double* h1 = Hin + (size_t)(l + 1) * cap;
+        double* J1 = Jin + (size_t)(l + 1) * cap * r;
+        double* S1 = Sin + (size_t)(l + 1) * cap;
+        for (int u = 0; u < w; ++u) {
+            const double* Wu = p->W[l] + (size_t)u * in;
+            double a = p->b[l][u], aS = 0.0;
+            double* Au = PA + ((size_t)l * w + u) * r;
+            for (int j = 0; j < in; ++j) {
+                a += Wu[j] * h0[j];
+                aS += Wu[j] * S0[j];
+                for (int k = 0; k < r; ++k) Au[k] += Wu[j] * J0[j * r + k];
+            }
+            double qf = 0.0;
+            for (int k = 0; k < r; ++k)
+                for (int k2 = 0; k2 < r; ++k2) qf += Au[k] * C[k * r + k2] * Au[k2];
+            Pa[(size_t)l * w + u] = a;
+            PS[(size_t)l * w + u] = aS;
+            h1[u] = elu(a);
+            for (int k = 0; k < r; ++k) J1[u * r + k] = elu1(a) * Au[k];
+            S1[u] = elu2(a) * qf + elu1(a) * aS;
+        }
+    }
+    const int nin = L > 0 ? w : r;
+    const double* hL = Hin + (size_t)L * cap;
+    const double* JL = Jin + (size_t)L * cap * r;
+    const double* SL = Sin + (size_t)L * cap;
+    /* output rows: u = m (W h + b), dU = m W J, uS = m W S */
+    double* x = (double*)malloc(sizeof(double) * n);
+    double* UJ = (double*)calloc((size_t)n * r, sizeof(double));
+    double* uS = (double*)calloc(n, sizeof(double));
+    const double* Wo = p->W[L];
+    for (int row = 0; row < n; ++row) {
+        double u = 0.0;
+        if (!p->pinned[row / 3]) {
+            u = p->b[L][row];
+            for (int j = 0; j < nin; ++j) {
+                const double wj = Wo[(size_t)row * nin + j];
+                u += wj * hL[j];
+                uS[row] += wj * SL[j];
+                for (int k = 0; k < r; ++k) UJ[(size_t)row * r + k] += wj * JL[j * r + k];
+            }
+        }
+        x[row] = p->X[row] + u;
+    }
+    /* elements: adjoints of the rows */
+    double* ub = (double*)calloc(n, sizeof(double));
+    double* UJb = (double*)calloc((size_t)n * r, sizeof(double));
+    double* uSb = (double*)calloc(n, sizeof(double));
+    double* K = (double*)malloc(sizeof(double) * 9 * r);
+    double* KC = (double*)malloc(sizeof(double) * 9 * r);
+    for (int s = 0; s < p->S; ++s) {
+        const int e = p->cub_elem[s];
+        const int* t = p->tets + 4 * e;
+        const double* Dminv = rd->Dminv + 9 * e;
+        double xe[12], F[9], Dv[12], A[81], P[9], cof[9];
+        gather(p, e, x, xe);
+        deform_grad(Dminv, xe, F);
+        shape_grad(Dminv, Dv);
+        or_dpdf(F, rd->mu, rd->lam, A);
+        or_pk1(F, rd->mu, rd->lam, P);
+        cofactor(F, cof);
+        const double wV = p->cub_w[s] * rd->V[e];
+        const double sfac = rd->lam * (det3(F) - 1.0) - rd->mu;
+        /* K[v][k] and Fdd[v] at vec index v = 3 j + i: sum_a Dv[a][j] (row 3 t_a + i) */
+        double Fdd[9], g[9], Pv[9];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                const int v = 3 * j + i;
+                g[v] = cof[3 * i + j];
+                Pv[v] = P[3 * i + j];
+                Fdd[v] = 0.0;
+                for (int k = 0; k < r; ++k) K[v * r + k] = 0.0;
+                for (int a = 0; a < 4; ++a) {
+                    const int row = 3 * t[a] + i;
+                    Fdd[v] += Dv[3 * a + j] * uS[row];
+                    for (int k = 0; k < r; ++k) K[v * r + k] += Dv[3 * a + j] * UJ[(size_t)row * r + k];
+                }
+            }
+        /* N = K C K^T, KC = K C */
+        double N[81];
+        for (int v = 0; v < 9; ++v)
+            for (int k = 0; k < r; ++k) {
+                double acc = 0.0;
+                for (int k2 = 0; k2 < r; ++k2) acc += K[v * r + k2] * C[k2 * r + k];
+                KC[v * r + k] = acc;
+            }
+        for (int v = 0; v < 9; ++v)
+            for (int v2 = 0; v2 < 9; ++v2) {
+                double acc = 0.0;
+                for (int k = 0; k < r; ++k) acc += KC[v * r + k] * K[v2 * r + k];
+                N[v * 9 + v2] = acc;
+            }
+        /* Fbar = wV (sum_pq N_pq dA_pq/dF + A Fdd), Kbar = 2 wV A K C, Fddbar = wV P */
+        double Fb[9], Fddb[9], Kb[9 * 32];
+        double HJ[81];
+        for (int a = 0; a < 9; ++a)
+            for (int b = 0; b < 9; ++b) HJ[a * 9 + b] = d2det(F, a, b);
+        for (int m = 0; m < 9; ++m) {
+            double acc = 0.0;
+            for (int pp = 0; pp < 9; ++pp)
+                for (int qq = 0; qq < 9; ++qq) {
+                    const double dA = rd->lam * (HJ[pp * 9 + m] * g[qq] + g[pp] * HJ[qq * 9 + m]) +
+                                      rd->lam * g[m] * HJ[pp * 9 + qq] + sfac * d3det(pp, qq, m);
+                    acc += N[pp * 9 + qq] * dA;
+                }
+            double af = 0.0;
+            for (int q = 0; q < 9; ++q) af += A[m * 9 + q] * Fdd[q];
+            Fb[m] = wV * (acc + af);
+            Fddb[m] = wV * Pv[m];
+            for (int k = 0; k < r; ++k) {
+                double ak = 0.0;
+                for (int q = 0; q < 9; ++q) ak += A[m * 9 + q] * KC[q * r + k];
+                Kb[m * r + k] = 2.0 * wV * ak;
+            }
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int i = 0; i < 3; ++i) {
+                const int row = 3 * t[a] + i;
+                for (int j = 0; j < 3; ++j) {
+                    const int v = 3 * j + i;
+                    const double d = Dv[3 * a + j];
+                    ub[row] += d * Fb[v];
+                    uSb[row] += d * Fddb[v];
+                    for (int k = 0; k < r; ++k) UJb[(size_t)row * r + k] += d * Kb[v * r + k];
+                }
+            }
+    }
+    /* output layer (free rows only) */
+    double* hb = (double*)calloc(cap, sizeof(double));
+    double* Jb = (double*)calloc((size_t)cap * r, sizeof(double));
+    double* Sb = (double*)calloc(cap, sizeof(double));
+    for (int row = 0; row < n; ++row) {
+        if (p->pinned[row / 3]) continue;
+        const double* Wr = Wo + (size_t)row * nin;
+        for (int j = 0; j < nin; ++j) {
+            double gw = ub[row] * hL[j] + uSb[row] * SL[j];
+            for (int k = 0; k < r; ++k) gw += UJb[(size_t)row * r + k] * JL[j * r + k];
+            grad[offW[L] + (size_t)row * nin + j] += sign * gw;
+            hb[j] += Wr[j] * ub[row];
+            Sb[j] += Wr[j] * uSb[row];
+            for (int k = 0; k < r; ++k) Jb[j * r + k] += Wr[j] * UJb[(size_t)row * r + k];
+        }
+        grad[offb[L] + row] += sign * ub[row];
+    }
+    /* hidden layers, last to first */
+    double* hb2 = (double*)calloc(cap, sizeof(double));
+    double* Jb2 = (double*)calloc((size_t)cap * r, sizeof(double));
+    double* Sb2 = (double*)calloc(cap, sizeof(double));
+    double* Ab = (double*)malloc(sizeof(double) * r);
+    double* AC = (double*)malloc(sizeof(double) * r);
+    for (int l = L - 1; l >= 0; --l) {
+        const int in = l == 0 ? r : w;
+        const double* h0 = Hin + (size_t)l * cap;
+        const double* J0 = Jin + (size_t)l * cap * r;
+        const double* S0 = Sin + (size_t)l * cap;
+        memset(hb2, 0, sizeof(double) * cap);
+        memset(Jb2, 0, sizeof(double) * (size_t)cap * r);
+        memset(Sb2, 0, sizeof(double) * cap);
+        for (int u = 0; u < w; ++u) {
+            const double a = Pa[(size_t)l * w + u], aS = PS[(size_t)l * w + u];
+            const double* Au = PA + ((size_t)l * w + u) * r;
+            const double s1 = elu1(a), s2 = elu2(a), s3 = elu3(a);
+            double qf = 0.0, AJ = 0.0;
+            for (int k = 0; k < r; ++k) {
+                double acc = 0.0;
+                for (int k2 = 0; k2 < r; ++k2) acc += Au[k2] * C[k2 * r + k];
+                AC[k] = acc;
+                qf += acc * Au[k];
+                AJ += Au[k] * Jb[u * r + k];
+            }
+            const double abar = s1 * hb[u] + s2 * AJ + s3 * qf * Sb[u] + s2 * aS * Sb[u];
+            for (int k = 0; k < r; ++k) Ab[k] = s1 * Jb[u * r + k] + 2.0 * s2 * Sb[u] * AC[k];
+            const double aSbar = s1 * Sb[u];
+            const double* Wu = p->W[l] + (size_t)u * in;
+            for (int j = 0; j < in; ++j) {
+                double gw = abar * h0[j] + aSbar * S0[j];
+                for (int k = 0; k < r; ++k) gw += Ab[k] * J0[j * r + k];
+                grad[offW[l] + (size_t)u * in + j] += sign * gw;
+                hb2[j] += Wu[j] * abar;
+                Sb2[j] += Wu[j] * aSbar;
+                for (int k = 0; k < r; ++k) Jb2[j * r + k] += Wu[j] * Ab[k];
+            }
+            grad[offb[l] + u] += sign * abar;
+        }
+        memcpy(hb, hb2, sizeof(double) * cap);
+        memcpy(Jb, Jb2, sizeof(double) * (size_t)cap * r);
+        memcpy(Sb, Sb2, sizeof(double) * cap);
+    }
+    free(Hin); free(Jin); free(Sin); free(Pa); free(PA); free(PS);
+    free(x); free(UJ); free(uS); free(ub); free(UJb); free(uSb); free(K); free(KC);
+    free(hb); free(Jb); free(Sb); free(hb2); free(Jb2); free(Sb2); free(Ab); free(AC);
+}
+
+int or_lipschitz_param_grad(const or_problem* p, int B, const double* z1, const double* z2,
+                            double* loss, double* grad)
+{
+    const int r = p->r;
+    if (r > 32) return 1;
+    size_t offW[16], offb[16], total;
+    if (p->L + 1 > 16) return 1;
+    param_offsets(p, offW, offb, &total);
+    memset(grad, 0, sizeof(double) * total);
+    rest_data rd;
+    rest_build(p, &rd);
+    int nv = 0;
+    for (int b = 0; b < B; ++b) {
+        double d2 = 0.0;
+        for (int k = 0; k < r; ++k) d2 += (z1[b * r + k] - z2[b * r + k]) * (z1[b * r + k] - z2[b * r + k]);
+        nv += d2 > 0.0;
+    }
+    double sum = 0.0;
+    double* H1 = (double*)malloc(sizeof(double) * r * r);
+    double* H2 = (double*)malloc(sizeof(double) * r * r);
+    double* Cm = (double*)malloc(sizeof(double) * r * r);
+    for (int b = 0; b < B; ++b) {
+        const double* a = z1 + (size_t)b * r;
+        const double* c = z2 + (size_t)b * r;
+        double d2 = 0.0;
+        for (int k = 0; k < r; ++k) d2 += (a[k] - c[k]) * (a[k] - c[k]);
+        if (!(d2 > 0.0)) continue;
+        double E1, E2;
+        item_eval(p, &rd, a, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E1, NULL, H1);
+        item_eval(p, &rd, c, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E2, NULL, H2);
+        double fro = 0.0;
+        for (int k = 0; k < r * r; ++k) fro += (H1[k] - H2[k]) * (H1[k] - H2[k]);
+        sum += fro / d2;
+        /* C = 2 sym(D) / (|dz|^2 n_valid) */
+        for (int k = 0; k < r; ++k)
+            for (int q = 0; q < r; ++q)
+                Cm[k * r + q] = ((H1[k * r + q] - H2[k * r + q]) + (H1[q * r + k] - H2[q * r + k])) / (d2 * nv);
+        hess_contract_grad(p, &rd, a, Cm, 1.0, offW, offb, grad);
+        hess_contract_grad(p, &rd, c, Cm, -1.0, offW, offb, grad);
+    }
+    *loss = nv ? sum / nv : 0.0;
+    free(H1); free(H2); free(Cm);
+    rest_free(&rd);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Supervised construction (Sec. 3.2, Eq. form-vanilla-supervised-construction): */
+/* L_C = mean_i |f(g(q_i)) - q_i|_M^2 with the positions f = X + m (.) decoder  */
+/* and the encoder g fed the displacement q_i - X; gradients of both networks  */
+/* by the chain rule (value passes only).                                     */
+/* ------------------------------------------------------------------------- */
+static void mlp_offsets(int n_in, int L, int width, int n_out, size_t* offW, size_t* offb, size_t* total)
+{
+    size_t off = 0;
+    for (int l = 0; l <= L; ++l) {
+        int in = l == 0 ? n_in : width, out = l == L ? n_out : width;
+        offW[l] = off;
+        off += (size_t)out * in;
+        offb[l] = off;
+        off += out;
+    }
+    *total = off;
+}
+
+/* forward of an ELU MLP keeping every layer's pre-activation (A) and input (Hs) */
+static void mlp_forward(int n_in, int L, int width, int n_out, const double* const* W, const double* const* b,
+                        const double* x, double* A, double* Hs, int cap, double* y)
+{
+    for (int j = 0; j < n_in; ++j) Hs[j] = x[j];
+    for (int l = 0; l <= L; ++l) {
+        const int in = l == 0 ? n_in : width, out = l == L ? n_out : width;
+        const double* h = Hs + (size_t)l * cap;
+        for (int u = 0; u < out; ++u) {
+            double a = b[l][u];
+            for (int j = 0; j < in; ++j) a += W[l][(size_t)u * in + j] * h[j];
+            if (l < L) {
+                A[(size_t)l * width + u] = a;
+                Hs[(size_t)(l + 1) * cap + u] = elu(a);
+            } else {
+                y[u] = a;
+            }
+        }
+    }
+}
+
+/* backward of the same MLP given dL/dy; accumulates parameter gradients and
+ * returns dL/dx in xb (nullable) */
+static void mlp_backward(int n_in, int L, int width, int n_out, const double* const* W, const double* A,
+                         const double* Hs, int cap, const double* yb, const size_t* offW, const size_t* offb,
+                         double* grad, double* xb)
+{
+    double* gb = (double*)calloc(cap, sizeof(double));
+    double* gb2 = (double*)calloc(cap, sizeof(double));
+    for (int l = L; l >= 0; --l) {
+        const int in = l == 0 ? n_in : width, out = l == L ? n_out : width;
+        const double* h = Hs + (size_t)l * cap;
+        memset(gb2, 0, sizeof(double) * cap);
+        for (int u = 0; u < out; ++u) {
+            const double d = l == L ? yb[u] : gb[u] * elu1(A[(size_t)l * width + u]);
+            if (d == 0.0) continue;
+            for (int j = 0; j < in; ++j) {
+                grad[offW[l] + (size_t)u * in + j] += d * h[j];
+                gb2[j] += W[l][(size_t)u * in + j] * d;
+            }
+            grad[offb[l] + u] += d;
+        }
+        memcpy(gb, gb2, sizeof(double) * cap);
+    }
+    if (xb) memcpy(xb, gb, sizeof(double) * n_in);
+    free(gb); free(gb2);
+}
+
+int or_recon_loss_grad(const or_problem* p, const or_mlp* enc, int B, const double* q, double* loss,
+                       double* grad_enc, double* grad_dec)
+{
+    const int n = p->n_out, r = p->r, L = p->L, w = p->width;
+    if (enc->n_in != n || enc->n_out != r) return 1;
+    size_t eW[16], eb[16], etot, dW[16], db[16], dtot;
+    if (enc->L + 1 > 16 || L + 1 > 16) return 1;
+    mlp_offsets(n, enc->L, enc->width, r, eW, eb, &etot);
+    param_offsets(p, dW, db, &dtot);
+    memset(grad_enc, 0, sizeof(double) * etot);
+    memset(grad_dec, 0, sizeof(double) * dtot);
+    rest_data rd;
+    rest_build(p, &rd);
+    const int ecap = n > enc->width ? n : (enc->width > r ? enc->width : r);
+    const int dcap = (w > r ? w : r);
+    double* eA = (double*)malloc(sizeof(double) * (size_t)(enc->L > 0 ? enc->L : 1) * (enc->width > 0 ? enc->width : 1));
+    double* eH = (double*)malloc(sizeof(double) * (size_t)(enc->L + 1) * ecap);
+    double* dA = (double*)malloc(sizeof(double) * (size_t)(L > 0 ? L : 1) * (w > 0 ? w : 1));
+    double* dH = (double*)malloc(sizeof(double) * (size_t)(L + 1) * dcap);
+    double* d = (double*)malloc(sizeof(double) * n);
+    double* z = (double*)malloc(sizeof(double) * r);
+    double* zb = (double*)malloc(sizeof(double) * r);
+    double* u = (double*)malloc(sizeof(double) * n);
+    double* ub = (double*)malloc(sizeof(double) * n);
+    double sum = 0.0;
+    for (int i = 0; i < B; ++i) {
+        const double* qi = q + (size_t)i * n;
+        for (int row = 0; row < n; ++row) d[row] = qi[row] - p->X[row];
+        mlp_forward(n, enc->L, enc->width, r, enc->W, enc->b, d, eA, eH, ecap, z);
+        mlp_forward(r, L, w, n, p->W, p->b, z, dA, dH, dcap, u);
+        /* residual on positions: X + m (.) u - q = m (.) u - d */
+        for (int row = 0; row < n; ++row) {
+            const int fixed = p->pinned[row / 3];
+            const double res = (fixed ? 0.0 : u[row]) - d[row];
+            const double mv = rd.mass[row / 3];
+            sum += mv * res * res;
+            ub[row] = fixed ? 0.0 : 2.0 * mv * res / B;
+        }
+        mlp_backward(r, L, w, n, p->W, dA, dH, dcap, ub, dW, db, grad_dec, zb);
+        mlp_backward(n, enc->L, enc->width, r, enc->W, eA, eH, ecap, zb, eW, eb, grad_enc, NULL);
+    }
+    *loss = B ? sum / B : 0.0;
+    free(eA); free(eH); free(dA); free(dH); free(d); free(z); free(zb); free(u); free(ub);
+    rest_free(&rd);
+    return 0;
+}
+
+int or_encode(const or_mlp* enc, int B, const double* d, double* z)
+{
+    const int cap = enc->n_in > enc->width ? enc->n_in : (enc->width > enc->n_out ? enc->width : enc->n_out);
+    double* A = (double*)malloc(sizeof(double) * (size_t)(enc->L > 0 ? enc->L : 1) * (enc->width > 0 ? enc->width : 1));
+    double* Hs = (double*)malloc(sizeof(double) * (size_t)(enc->L + 1) * cap);
+    for (int i = 0; i < B; ++i)
+        mlp_forward(enc->n_in, enc->L, enc->width, enc->n_out, enc->W, enc->b, d + (size_t)i * enc->n_in, A, Hs, cap,
+                    z + (size_t)i * enc->n_out);
+    free(A); free(Hs);
     return 0;
 }

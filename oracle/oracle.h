@@ -50,7 +50,7 @@ typedef struct {
     double shrink;     /* step factor per trial */
     double rel_tol;    /* stop when |g|_inf <= rel_tol |g_0|_inf */
     double abs_tol;    /* ... or when |g|_inf <= abs_tol */
-    int hess;          /* 0 Gauss-Newton, 1 exact */
+    int hess;          /* bit 0: exact (else Gauss-Newton); bit 1: per-element PSD projection */
     int proj;          /* 0 clamp eigenvalues, 1 absolute eigenvalues, 2 none */
     double eig_floor;  /* eigenvalue floor relative to max |eig| */
 } or_opts;
@@ -136,6 +136,30 @@ int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
  * (nullable).  flags: OR_ELASTIC_ONLY. */
 int or_energy_param_grad(const or_problem* p, int B, const double* z, const double* targets,
                          const double* force, int flags, double* E, double* grad);
+
+/* Gradient of the Lipschitz loss mean_b |H(z1_b) - H(z2_b)|_F^2 / |z1_b - z2_b|^2
+ * (H the exact cubature elastic Hessian, pairs with z1 = z2 excluded) with
+ * respect to every decoder parameter (packed as or_energy_param_grad), by the
+ * chain rule through the value, Jacobian and contracted second derivative of
+ * every layer; loss is its value.  r <= 32.  Serial over pairs. */
+int or_lipschitz_param_grad(const or_problem* p, int B, const double* z1, const double* z2,
+                            double* loss, double* grad);
+
+/* an ELU MLP n_in -> L hidden layers of `width` -> n_out (linear), W[l] (out x in) row-major */
+typedef struct {
+    int n_in, L, width, n_out;
+    const double* const* W;
+    const double* const* b;
+} or_mlp;
+
+/* Supervised reconstruction loss mean_i |X + m (.) f(g(q_i - X)) - q_i|_M^2 over B
+ * positions q (B x n), M the lumped masses, g the encoder (n -> r), f the
+ * problem's decoder; gradients of both networks (packed like
+ * or_energy_param_grad, encoder first argument) are overwritten. */
+int or_recon_loss_grad(const or_problem* p, const or_mlp* enc, int B, const double* q, double* loss,
+                       double* grad_enc, double* grad_dec);
+/* encoder values z (B x n_out) of inputs d (B x n_in) */
+int or_encode(const or_mlp* enc, int B, const double* d, double* z);
 
 /* symmetric eigen-decomposition by cyclic Jacobi (exposed for pins) */
 void or_sym_eig(int n, const double* A, double* evals, double* evecs);

@@ -332,6 +332,35 @@ class Oracle:
         lib().or_energy_param_grad(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.c_int(flags), _d(E), _d(grad))
         return E, grad
 
+    def param_count(self):
+        return sum(ws[0] * ws[1] + bs[0] for ws, bs in self.param_shapes())
+
+    def lipschitz_param_grad(self, z1, z2):
+        """(loss, grad): the Lipschitz loss and its gradient with respect to the
+        packed decoder parameters."""
+        z1, z2 = _c64(np.atleast_2d(z1)), _c64(np.atleast_2d(z2))
+        B = z1.shape[0]
+        loss = C.c_double()
+        grad = np.zeros(self.param_count())
+        rc = lib().or_lipschitz_param_grad(C.byref(self.s), C.c_int(B), _d(z1), _d(z2), C.byref(loss), _d(grad))
+        if rc:
+            raise ValueError("or_lipschitz_param_grad: r > 32 or too many layers")
+        return loss.value, grad
+
+    def recon_loss_grad(self, enc, q):
+        """(loss, grad_enc, grad_dec) of the supervised reconstruction loss for
+        positions q (B x n) with the encoder `enc` (an Mlp)."""
+        q = _c64(np.atleast_2d(q))
+        B = q.shape[0]
+        loss = C.c_double()
+        ge = np.zeros(enc.param_count())
+        gd = np.zeros(self.param_count())
+        rc = lib().or_recon_loss_grad(C.byref(self.s), C.byref(enc.s), C.c_int(B), _d(q), C.byref(loss),
+                                      _d(ge), _d(gd))
+        if rc:
+            raise ValueError("or_recon_loss_grad: encoder shape does not match the problem")
+        return loss.value, ge, gd
+
     def lipschitz(self, z1, z2):
         z1, z2 = _c64(np.atleast_2d(z1)), _c64(np.atleast_2d(z2))
         B = z1.shape[0]
@@ -341,3 +370,31 @@ class Oracle:
         lib().or_lipschitz(C.byref(self.s), C.c_int(B), _d(z1), _d(z2), C.byref(loss), _d(per),
                            C.byref(nval), C.byref(lipmax))
         return dict(loss=loss.value, per_pair=per, n_valid=nval.value, lip_max=lipmax.value)
+
+
+class _Mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int), ("L", C.c_int), ("width", C.c_int), ("n_out", C.c_int),
+                ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp))]
+
+
+class Mlp:
+    """An ELU MLP (W[l] of shape (out, in), hidden layers of one width) for the oracle."""
+
+    def __init__(self, Ws, bs):
+        self.Ws = [_c64(W) for W in Ws]
+        self.bs = [_c64(b) for b in bs]
+        Wp = (_dp * len(self.Ws))(*[_d(W) for W in self.Ws])
+        bp = (_dp * len(self.bs))(*[_d(b) for b in self.bs])
+        self._keep = [Wp, bp]
+        width = self.Ws[0].shape[0] if len(self.Ws) > 1 else 0
+        self.s = _Mlp(self.Ws[0].shape[1], len(self.Ws) - 1, width, self.Ws[-1].shape[0],
+                      C.cast(Wp, C.POINTER(_dp)), C.cast(bp, C.POINTER(_dp)))
+
+    def param_count(self):
+        return sum(W.size + b.size for W, b in zip(self.Ws, self.bs))
+
+    def encode(self, d):
+        d = _c64(np.atleast_2d(d))
+        z = np.zeros((d.shape[0], self.s.n_out))
+        lib().or_encode(C.byref(self.s), C.c_int(d.shape[0]), _d(d), _d(z))
+        return z
