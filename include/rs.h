@@ -80,8 +80,13 @@ enum {
     RS_HESS_EXACT = 1,    /* add the decoder-curvature term sum_k g_k d2q_k/dz2 (else Gauss-Newton) */
     RS_ELASTIC_ONLY = 2,  /* cubature elastic potential only (no gravity, penalty, forces) */
     RS_ENERGY_ONLY = 4,   /* energy only; g and H may be NULL */
-    RS_GRAD_REVERSE = 8   /* g by reverse mode (a value pass, then the adjoint pass back through the
+    RS_GRAD_REVERSE = 8,  /* g by reverse mode (a value pass, then the adjoint pass back through the
                              decoder) instead of forward-mode Jacobian columns; H must be NULL */
+    RS_ELEM_PSD = 16,     /* project every cubature element Hessian H_e = V D^T (d2psi/dF2) D (12 x 12) to
+                             positive semi-definite (negative eigenvalues set to zero) before it enters
+                             H (supplement, projective Newton: the classic per-element projection) */
+    RS_DEBUG_ELEM_HESS = 32 /* also write the 12 x 12 element Hessians H_e of the cubature tets to the
+                             buffer given to rs_set_elem_hess_dump (unprojected; inspection only) */
 };
 
 /* Hessian treatment before the Newton solve */
@@ -147,7 +152,8 @@ typedef struct {
     double shrink;      /* step factor per trial, default 0.5 */
     double rel_tol;     /* |g|_inf <= rel_tol |g_0|_inf, default 1e-6 */
     double abs_tol;     /* or |g|_inf <= abs_tol, default 0 */
-    int32_t hess;       /* 1 exact Hessian (default), 0 Gauss-Newton */
+    int32_t hess;       /* bit 0: exact Hessian (default 1), else Gauss-Newton; bit 1: per-element
+                           projection of the cubature element Hessians (RS_ELEM_PSD) */
     int32_t proj;       /* RS_PROJ_*, default RS_PROJ_ABS */
     double eig_floor;   /* relative eigenvalue floor, default 1e-8 */
 } rs_solve_opts;
@@ -213,6 +219,17 @@ int rs_decode(rs_ctx* ctx, int32_t B, const double* z, void* x, void* J, void* s
  * other contexts fall back to the forward mode. */
 int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* load,
                         uint32_t flags, double* E, double* g, double* H, void* stream);
+
+/* Register the destination of RS_DEBUG_ELEM_HESS: He (DEVICE, float64,
+ * max_items x n_cub x 12 x 12, row-major, caller-owned).  Row and column
+ * 3 a + i of an element block is coordinate i of the tet's corner a (corners
+ * in the mesh's tet order), as in H_e = V D^T A D of the element's stable
+ * Neo-Hookean energy (Sec. 3.1 elastic energy, Sec. 5.1 material; unweighted
+ * by the cubature weight).  rs_energy_grad_hess calls with the flag fill the
+ * blocks of their first min(B, max_items) items, each at its batch position.
+ * He = NULL or max_items = 0 unregisters.  Errors: RS_ERR_STATE (NULL ctx),
+ * RS_ERR_ARG (negative max_items, or NULL He with max_items > 0). */
+int rs_set_elem_hess_dump(rs_ctx* ctx, double* He, int32_t max_items);
 
 /* Number of decoder parameters: sum over the layers (output layer last) of
  * out x in weights plus out biases, the length of rs_energy_param_grad's

@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(PKG, "librs.so")
 RS_OK, RS_ERR_ARG, RS_ERR_HIP, RS_ERR_OOM, RS_ERR_STATE, RS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4, 5
 CONVERGED, NOT_DESCENT, LS_MAX, ITER_MAX, NONFINITE, RUNNING = 0, 1, 2, 3, 4, -1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
-HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY, GRAD_REVERSE = 1, 2, 4, 8
+HESS_EXACT, ELASTIC_ONLY, ENERGY_ONLY, GRAD_REVERSE, ELEM_PSD, DEBUG_ELEM_HESS = 1, 2, 4, 8, 16, 32
+# rs_solve_opts.hess values
+HESS_GN, HESS_EXACT_OPT, HESS_GN_ELEM_PSD, HESS_EXACT_ELEM_PSD = 0, 1, 2, 3
 PROJ_CLAMP, PROJ_ABS, PROJ_NONE = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -79,7 +81,7 @@ class Info(C.Structure):
 SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy", "rs_set_decoder",
            "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
            "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
-           "rs_energy_param_grad"]
+           "rs_energy_param_grad", "rs_set_elem_hess_dump"]
 
 _lib = None
 
@@ -115,6 +117,7 @@ def load_library():
         L.rs_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.rs_energy_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.c_uint32,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_set_elem_hess_dump.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -296,6 +299,19 @@ class Context:
         self._check(load_library().rs_energy_grad_hess(self.ctx, B, _ptr(z), C.byref(ld), flags, _ptr(E),
                                                        _ptr(g), _ptr(H), _stream()), "rs_energy_grad_hess")
         return E, g, H
+
+    def set_elem_hess_dump(self, He):
+        """Register (He: float64 device tensor, (items, n_cub, 12, 12)) or clear (None) the
+        destination of RS_DEBUG_ELEM_HESS."""
+        if He is None:
+            self._dump = None
+            self._check(load_library().rs_set_elem_hess_dump(self.ctx, None, 0), "rs_set_elem_hess_dump")
+            return
+        _dev(He, torch.float64, None, "He")
+        if He.dim() != 4 or tuple(He.shape[1:]) != (len(self.p.cub_elem), 12, 12):
+            raise ValueError("He must have shape (items, n_cub, 12, 12)")
+        self._dump = He
+        self._check(load_library().rs_set_elem_hess_dump(self.ctx, _ptr(He), He.shape[0]), "rs_set_elem_hess_dump")
 
     def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None):
         """z0 (B x r) float64 on the GPU; returns dict of device tensors.

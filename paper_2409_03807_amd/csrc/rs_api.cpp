@@ -32,12 +32,12 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_COUNT
+    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_ELEM_PSD, K_ELEM_DUMP, K_LIP_GRAD, K_TRAIN, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
-    "newton_init", "activate", "lbfgs_dir", "param_grad"};
+    "newton_init", "activate", "lbfgs_dir", "param_grad", "elem_psd", "elem_hess_dump", "lipschitz_grad", "train"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -52,6 +52,19 @@ struct ProfRec {
 struct Work {
     double b0 = 0, b1 = 0, f0 = 0, f1 = 0;
     int slot = -1, which = 0;
+};
+
+struct LipWs {
+    int pairs = 0;                 // pairs per pass
+    void* Pre[kMaxL] = {};         // w x cols
+    void* X0 = nullptr;            // r x cols
+    void* X = nullptr;             // width x cols (recomputed activation)
+    void* Out = nullptr;           // 9S x cols
+    void* Seed = nullptr;          // 9S x cols
+    void* G[2] = {};               // max(w, r) x cols
+    void* D = nullptr;             // w x cols
+    double* Cs = nullptr;          // items x r x r
+    int* nvalid = nullptr;
 };
 
 }  // namespace
@@ -87,6 +100,9 @@ struct rs_ctx {
     double* Wbig64 = nullptr; double* bbig64 = nullptr;
     void* Wfull = nullptr; void* bfull = nullptr; void* Xfull = nullptr;
     double* wV = nullptr; double* Xt = nullptr;
+    double* ec = nullptr;         // S x kElemConst: per-element constants of the optional element treatments
+    double* dump_He = nullptr;    // RS_DEBUG_ELEM_HESS destination (caller-owned), dump_max items
+    int dump_max = 0;
     // workspace
     std::vector<void*> pre;       // L x (max_batch x wrows x nc) T
     void* act = nullptr;          // max_batch x wrows x nc T: [h_L | J_L] of the last hidden layer
@@ -116,13 +132,23 @@ struct rs_ctx {
     double* dbbig = nullptr;      // M
     double* ppart = nullptr;      // kParamSlices partial sums of the largest parameter product
     size_t ppart_cap = 0;
+    int* ffold_ptr = nullptr;     // M + 1: CSR of the output-layer fold by W_big row (device decoder loads)
+    int* ffold_src = nullptr;     // W_out row of each entry
+    double* ffold_coef = nullptr; // its coefficient
+    uint8_t* pinned_row = nullptr;// n_out: 1 on rows of pinned vertices (device)
+    double* row_mass = nullptr;   // n_out: lumped mass of each row's vertex (device)
+    // learned-part workspace, grown on demand by the training calls
+    std::vector<void*> learn_bufs;
+    LipWs lip;                    // Lipschitz-loss gradient workspace (allocated by its first call)
     int* fold_ptr = nullptr;      // n_out + 1: CSR of the output-layer fold by W_out row
     int* fold_row = nullptr;      // W_big row of each entry
     double* fold_coef = nullptr;  // its coefficient
     std::vector<size_t> offW, offb; // packed offsets of W_l, b_l (output layer last)
     size_t n_params = 0;
-    int* hcount = nullptr;        // pinned host
-    int* hcount_dev = nullptr;    // device address of hcount
+    // running counts, one slot per parity of the super-step: (tag << 32) | count
+    unsigned long long* hcount = nullptr;     // pinned host
+    unsigned long long* hcount_dev = nullptr; // device address of hcount
+    unsigned int tag_next = 1;                // tag of the next super-step's count (never 0)
     hipEvent_t cnt_ev[2] = {nullptr, nullptr}; // running-count copies, one per parity of the super-step
 
     std::string err;
@@ -225,6 +251,54 @@ static void inv3(const double* M, double* Mi, double* det)
     *det = d;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Mi[3 * i + j] = C[3 * j + i] / d;
+}
+
+// Square root and inverse square root of a symmetric positive-definite 3x3
+// matrix (row-major) by cyclic Jacobi rotations: N = Q diag(l) Q^T,
+// N^(1/2) = Q diag(sqrt l) Q^T, N^(-1/2) = Q diag(1/sqrt l) Q^T.
+static void sym3_sqrt(const double* N, double* Sq, double* Si)
+{
+    double A[9], Q[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    std::memcpy(A, N, sizeof(A));
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+        const double tot = off + A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                const double apq = A[3 * p + q];
+                if (apq == 0.0) continue;
+                const double th = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {
+                    const double akp = A[3 * k + p], akq = A[3 * k + q];
+                    A[3 * k + p] = cs * akp - sn * akq;
+                    A[3 * k + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double apk = A[3 * p + k], aqk = A[3 * q + k];
+                    A[3 * p + k] = cs * apk - sn * aqk;
+                    A[3 * q + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double qkp = Q[3 * k + p], qkq = Q[3 * k + q];
+                    Q[3 * k + p] = cs * qkp - sn * qkq;
+                    Q[3 * k + q] = sn * qkp + cs * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double l = std::sqrt(A[4 * k]);
+                a += Q[3 * i + k] * l * Q[3 * j + k];
+                b += Q[3 * i + k] / l * Q[3 * j + k];
+            }
+            Sq[3 * i + j] = a;
+            Si[3 * i + j] = b;
+        }
 }
 
 static int upload(rs_ctx* c, void* dst, const std::vector<double>& src, int as_f32)
@@ -423,6 +497,7 @@ extern "C" const char* rs_last_error(const rs_ctx* c) { return c ? c->err.c_str(
 static void destroy(rs_ctx* c)
 {
     for (void* p : c->allocs) (void)hipFree(p);
+    for (void* p : c->learn_bufs) (void)hipFree(p);
     if (c->plog) (void)hipFree(c->plog);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     if (c->hcount) (void)hipHostFree(c->hcount);
@@ -586,6 +661,7 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->Xfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
     c->wV = (double*)need(dalloc<double>(c, c->S));
     c->Xt = (double*)need(dalloc<double>(c, 3 * (size_t)std::max(c->nt, 1)));
+    c->ec = (double*)need(dalloc<double>(c, (size_t)c->S * kElemConst));
     c->out = need(dalloc_bytes(c, B * c->Mp * nc * ts));
     c->act = need(dalloc_bytes(c, B * c->wrows * nc * ts));
     c->act64 = (double*)need(dalloc<double>(c, BL * c->wrows));
@@ -637,7 +713,8 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     }
     if (!ok) return bail(fail(c, RS_ERR_OOM, "device allocation failed"));
     // coherent: the kernel's system-scope store lands in host memory without a cache flush
-    if (hipHostMalloc((void**)&c->hcount, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    if (hipHostMalloc((void**)&c->hcount, 2 * sizeof(unsigned long long), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
         return bail(fail(c, RS_ERR_OOM, "pinned host allocation failed"));
     c->hcount[0] = c->hcount[1] = 0;
     if (hipHostGetDevicePointer((void**)&c->hcount_dev, c->hcount, 0) != hipSuccess)
@@ -647,6 +724,24 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
             return bail(fail(c, RS_ERR_HIP, "hipEventCreate"));
 
     if (upload(c, c->wV, wVh, 0) != RS_OK) return bail(RS_ERR_HIP);
+    {
+        std::vector<double> ec((size_t)c->S * kElemConst, 0.0);
+        for (int s = 0; s < c->S; ++s) {
+            double Dv[4][3];
+            tet_shape_grads(c, s, Dv);
+            double N[9] = {0};
+            for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < 3; ++j)
+                    for (int k = 0; k < 3; ++k) N[3 * j + k] += Dv[a][j] * Dv[a][k];
+            double* e = &ec[(size_t)s * kElemConst];
+            sym3_sqrt(N, e, e + 9);
+            for (int a = 0; a < 4; ++a)
+                for (int j = 0; j < 3; ++j) e[18 + 3 * a + j] = Dv[a][j];
+            e[30] = c->vol[s];
+            e[31] = c->cub_w[s];
+        }
+        if (upload(c, c->ec, ec, 0) != RS_OK) return bail(RS_ERR_HIP);
+    }
     if (c->nt) {
         std::vector<double> xt(3 * (size_t)c->nt);
         for (int t = 0; t < c->nt; ++t)
@@ -685,6 +780,59 @@ static int build_fold(rs_ctx* c)
         for (int i = 0; i < 3; ++i) add(3 * v + i, c->grav_row, c->mass[v] * c->grav[i]);
     for (int t = 0; t < c->nf; ++t)
         for (int i = 0; i < 3; ++i) add(3 * c->fvtx[t] + i, c->force_row + i, 1.0);
+    {
+        // the same fold by W_big row, entries in the order the host load sums them
+        std::vector<std::vector<std::pair<int, double>>> fw(c->M);
+        auto addf = [&](int vrow, int brow, double cf) {
+            if (!c->pinned[vrow / 3] && cf != 0.0) fw[brow].push_back({vrow, cf});
+        };
+        for (int s = 0; s < c->S; ++s) {
+            const int e = c->cub_elem[s];
+            double Dv[4][3];
+            tet_shape_grads(c, s, Dv);
+            for (int j = 0; j < 3; ++j)
+                for (int i = 0; i < 3; ++i)
+                    for (int a = 0; a < 4; ++a) addf(3 * c->tets[4 * (size_t)e + a] + i, 9 * s + 3 * j + i, Dv[a][j]);
+        }
+        for (int t = 0; t < c->nt; ++t)
+            for (int i = 0; i < 3; ++i) addf(3 * c->tvtx[t] + i, 9 * c->S + 3 * t + i, 1.0);
+        for (int v = 0; v < c->nv; ++v)
+            for (int i = 0; i < 3; ++i) addf(3 * v + i, c->grav_row, c->mass[v] * c->grav[i]);
+        for (int t = 0; t < c->nf; ++t)
+            for (int i = 0; i < 3; ++i) addf(3 * c->fvtx[t] + i, c->force_row + i, 1.0);
+        std::vector<int> fp(c->M + 1, 0), fs;
+        std::vector<double> fc;
+        for (int m = 0; m < c->M; ++m) {
+            for (const auto& pc : fw[m]) {
+                fs.push_back(pc.first);
+                fc.push_back(pc.second);
+            }
+            fp[m + 1] = (int)fs.size();
+        }
+        if (fs.empty()) {
+            fs.push_back(0);
+            fc.push_back(0.0);
+        }
+        std::vector<uint8_t> pr(c->n_out);
+        std::vector<double> rm(c->n_out);
+        for (int row = 0; row < c->n_out; ++row) {
+            pr[row] = c->pinned[row / 3] ? 1 : 0;
+            rm[row] = c->mass[row / 3];
+        }
+        c->ffold_ptr = (int*)dalloc<int>(c, fp.size());
+        c->ffold_src = (int*)dalloc<int>(c, fs.size());
+        c->ffold_coef = (double*)dalloc<double>(c, fc.size());
+        c->pinned_row = (uint8_t*)dalloc<uint8_t>(c, pr.size());
+        c->row_mass = (double*)dalloc<double>(c, rm.size());
+        if (!c->ffold_ptr || !c->ffold_src || !c->ffold_coef || !c->pinned_row || !c->row_mass)
+            return fail(c, RS_ERR_OOM, "device allocation failed");
+        if (hipMemcpy(c->ffold_ptr, fp.data(), fp.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->ffold_src, fs.data(), fs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->ffold_coef, fc.data(), fc.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->pinned_row, pr.data(), pr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->row_mass, rm.data(), rm.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(c, RS_ERR_HIP, "hipMemcpy");
+    }
     std::vector<int> ptr(c->n_out + 1, 0), row;
     std::vector<double> coef;
     for (int n = 0; n < c->n_out; ++n) {
@@ -862,6 +1010,21 @@ static int hidden_layers(rs_ctx* c, int f32, int nc, int cap, const int* count, 
     return activate(c, f32, pre[c->L - 1], act, nc, cap, count, which, s);
 }
 
+static ElemOptArgs elem_opt_args(const rs_ctx* c, const void* out, int nc, const int* count)
+{
+    ElemOptArgs o{};
+    o.out = out;
+    o.rows_pad = c->Mp;
+    o.nc = nc;
+    o.r = c->r;
+    o.S = c->S;
+    o.count = count;
+    o.ec = c->ec;
+    o.mu = c->mu;
+    o.lam = c->lam;
+    return o;
+}
+
 // T-precision decoder value + Jacobian, reduced rows, element terms and (exact)
 // the curvature term.  `cap` items fit the launch; `count` (device, nullable)
 // holds the actual number.  Item i uses latent point z[zmap[i]] and the loads
@@ -1006,6 +1169,15 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         const double pb = (double)c->L * c->w * nc * ts + (double)c->ksplit * c->in_rows * ts + 16.0 * r * r;
         const double pf = (double)c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w);
         RS_TRY(run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); }));
+    }
+    if ((flags & RS_ELEM_PSD) && H) {
+        // the per-element projection's correction, added to the finished H
+        ElemOptArgs o = elem_opt_args(c, c->out, nc, count);
+        o.H = H;
+        const double pb = (double)c->M * nc * ts + 16.0 * r * r;
+        const double pf = (double)c->S * (9.0 * 81 * 2 + 6.0 * 36 * 54);
+        RS_TRY(run(c, K_ELEM_PSD, item_work(pb, pf, cap, count, slot, 0), s,
+                   [&] { return launch_elem_psd(f32, o, cap, s); }));
     }
     return RS_OK;
 }
@@ -1193,6 +1365,10 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
     const bool eonly = flags & RS_ENERGY_ONLY;
     if (!eonly && !g) return fail(c, RS_ERR_ARG, "g must not be NULL unless RS_ENERGY_ONLY");
     if ((flags & RS_GRAD_REVERSE) && H) return fail(c, RS_ERR_ARG, "RS_GRAD_REVERSE takes H == NULL");
+    if ((flags & RS_ELEM_PSD) && (eonly || !H)) return fail(c, RS_ERR_ARG, "RS_ELEM_PSD needs H");
+    const bool dump = (flags & RS_DEBUG_ELEM_HESS) != 0;
+    if (dump && !c->dump_He) return fail(c, RS_ERR_ARG, "RS_DEBUG_ELEM_HESS without a buffer from rs_set_elem_hess_dump");
+    if (dump && eonly) return fail(c, RS_ERR_ARG, "RS_DEBUG_ELEM_HESS needs the gradient path (not RS_ENERGY_ONLY)");
     const bool rev = (flags & RS_GRAD_REVERSE) && grad_reverse_ok(c);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double* tg = load ? load->targets : nullptr;
@@ -1210,10 +1386,26 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
         else if (!eonly)
             RS_TRY(eval_T(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0,
                           g + (size_t)c0 * r, H ? H + (size_t)c0 * r * r : nullptr, s));
+        if (dump && c0 < c->dump_max) {
+            const int nd = std::min(n, c->dump_max - c0);
+            ElemOptArgs o = elem_opt_args(c, c->out, rev ? 1 : c->nc, nullptr);
+            o.He = c->dump_He + (size_t)c0 * c->S * 144;
+            RS_TRY(run(c, K_ELEM_DUMP, item_work(8.0 * c->S * 144, (double)c->S * 3000, nd, nullptr, -1, 0), s,
+                       [&] { return launch_elem_hess_dump(c->f32, o, nd, s); }));
+        }
         if (eonly || c->f32)
             RS_TRY(energy_f64(c, n, nullptr, 0, zc, tgc, foc, nullptr, (flags & RS_ELASTIC_ONLY) ? 1 : 0, E + c0, s,
                               K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
     }
+    return RS_OK;
+}
+
+extern "C" int rs_set_elem_hess_dump(rs_ctx* c, double* He, int32_t max_items)
+{
+    if (!c) return RS_ERR_STATE;
+    if (max_items < 0 || (max_items > 0 && !He)) return fail(c, RS_ERR_ARG, "bad element-Hessian dump buffer");
+    c->dump_He = max_items > 0 ? He : nullptr;
+    c->dump_max = c->dump_He ? max_items : 0;
     return RS_OK;
 }
 
@@ -1374,6 +1566,24 @@ static int log_counters(rs_ctx* c, hipStream_t s)
     return RS_OK;
 }
 
+// Running count of the super-step whose Armijo kernel stored `tag` into host
+// slot `slot`.  The kernel's system-scope release store normally lands before
+// the completion event is seen; a slot that still holds an older tag is read
+// again after the stream has drained (the super-step one ahead writes the other
+// slot), and a tag that still differs is an error, never a stale count.
+static int read_count(rs_ctx* c, int slot, unsigned int tag, hipStream_t s, int* count)
+{
+    unsigned long long v = __atomic_load_n(c->hcount + slot, __ATOMIC_ACQUIRE);
+    if ((unsigned int)(v >> 32) != tag) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+        v = __atomic_load_n(c->hcount + slot, __ATOMIC_ACQUIRE);
+        if ((unsigned int)(v >> 32) != tag) return fail(c, RS_ERR_STATE, "running count of a super-step never arrived");
+    }
+    *count = (int)(unsigned int)(v & 0xffffffffu);
+    return RS_OK;
+}
+
 // Batched reduced solve (Newton or L-BFGS) fully on the device: evaluation,
 // direction, line-search rounds and exits per item, with the host launching
 // one super-step ahead.
@@ -1420,6 +1630,7 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
     // evaluation list and writes the running count to mapped host memory.
     const long max_steps = (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
     int n_run = B;
+    unsigned int tags[2] = {0, 0};
     for (long step = 0; step < max_steps; ++step) {
         RS_TRY(log_counters(c, s));
         if (lbfgs && grad_reverse_ok(c))
@@ -1441,15 +1652,19 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
         RS_TRY(energy_f64(c, cap_c, cnt + 1, 1, c->zc, tg, fo, c->cand_item, 0, c->Ec, s, K_LS_GEMM_HIDDEN,
                           K_LS_GEMM_OUT));
         const int par = (int)(step & 1);
+        if (c->tag_next == 0) c->tag_next = 1; // tag 0 marks a slot no super-step has written
+        const unsigned int tag = c->tag_next++;
+        tags[par] = tag;
         RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
-                   [&] { return launch_armijo(st, p, B, c->hcount_dev + par, s); }));
+                   [&] { return launch_armijo(st, p, B, c->hcount_dev + par, tag, s); }));
         // the count reaches host memory by the kernel's own system-scope store; the event only marks completion
         hipError_t e = hipEventRecord(c->cnt_ev[par], s);
         if (e != hipSuccess) return hip_fail(c, e, "running-count copy");
         if (step == 0) continue;
         e = hipEventSynchronize(c->cnt_ev[par ^ 1]);
         if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
-        const int prev = *(volatile int*)(c->hcount + (par ^ 1)); // running after step - 1
+        int prev = 0; // running after step - 1
+        RS_TRY(read_count(c, par ^ 1, tags[par ^ 1], s, &prev));
         if (prev == 0) {
             n_run = 0;
             break;
@@ -1460,7 +1675,8 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
         // the bound was reached: settle the last count
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
-        n_run = std::min(*(volatile int*)c->hcount, *(volatile int*)(c->hcount + 1));
+        const int last = (int)((max_steps - 1) & 1);
+        RS_TRY(read_count(c, last, tags[last], s, &n_run));
     }
     c->cur_slot = -1;
     if (n_run > 0) return fail(c, RS_ERR_STATE, "solver loop did not terminate");
@@ -1478,7 +1694,7 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     rs_default_opts(&def);
     if (!o) o = &def;
     if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
-        o->proj < 0 || o->proj > 2)
+        o->proj < 0 || o->proj > 2 || o->hess < 0 || o->hess > 3)
         return fail(c, RS_ERR_ARG, "invalid solver options");
     NewtonParams p{};
     p.r = c->r;
@@ -1490,7 +1706,8 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     p.rel_tol = o->rel_tol;
     p.abs_tol = o->abs_tol;
     p.eig_floor = o->eig_floor;
-    return solve_batch(c, B, z, load, p, o->hess ? RS_HESS_EXACT : 0, false, iters, status, relgrad, E, stream);
+    const uint32_t hflags = ((o->hess & 1) ? RS_HESS_EXACT : 0u) | ((o->hess & 2) ? RS_ELEM_PSD : 0u);
+    return solve_batch(c, B, z, load, p, hflags, false, iters, status, relgrad, E, stream);
 }
 
 extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_lbfgs_opts* o,
@@ -1547,6 +1764,205 @@ extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const d
         c0 += n;
     } while (c0 < B);
     return RS_OK;
+}
+
+// ------------------------------------------------------------------ learned part
+// Workspace of the training calls, grown on demand (the first call of a size allocates).
+static void* learn_alloc(rs_ctx* c, size_t bytes)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) return nullptr;
+    c->learn_bufs.push_back(p);
+    return p;
+}
+
+static int lip_ws(rs_ctx* c, LipWs& ws)
+{
+    if (c->lip.pairs > 0) {
+        ws = c->lip;
+        return RS_OK;
+    }
+    ws = LipWs{};
+    ws.pairs = std::max(1, std::min(128, c->max_batch / 2));
+    const size_t items = 2 * (size_t)ws.pairs, cols = items * (c->r + 2), ts = c->tsz;
+    const size_t wr = (size_t)std::max(c->w, c->r);
+    bool ok = true;
+    for (int l = 0; l < c->L; ++l) ok = ok && (ws.Pre[l] = learn_alloc(c, (size_t)c->w * cols * ts));
+    ok = ok && (ws.X0 = learn_alloc(c, (size_t)c->r * cols * ts));
+    ok = ok && (ws.X = learn_alloc(c, wr * cols * ts));
+    ok = ok && (ws.Out = learn_alloc(c, (size_t)9 * c->S * cols * ts));
+    ok = ok && (ws.Seed = learn_alloc(c, (size_t)9 * c->S * cols * ts));
+    ok = ok && (ws.G[0] = learn_alloc(c, wr * cols * ts));
+    ok = ok && (ws.G[1] = learn_alloc(c, wr * cols * ts));
+    ok = ok && (ws.D = learn_alloc(c, wr * cols * ts));
+    ok = ok && (ws.Cs = (double*)learn_alloc(c, items * c->r * c->r * sizeof(double)));
+    ok = ok && (ws.nvalid = (int*)learn_alloc(c, sizeof(int)));
+    if (!ok) return fail(c, RS_ERR_OOM, "training workspace allocation failed");
+    c->lip = ws;
+    return RS_OK;
+}
+
+static SgemmArgs gemm_s(const void* A, long sAm, long sAk, const void* B, long sBk, long sBn, void* C, long ldc, int M,
+                        int N, int K, int accumulate = 0, const void* bias = nullptr, int bias_every = 0)
+{
+    SgemmArgs g{};
+    g.A = A; g.sAm = sAm; g.sAk = sAk;
+    g.B = B; g.sBk = sBk; g.sBn = sBn;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = 1.0;
+    g.accumulate = accumulate;
+    g.bias = bias;
+    g.bias_every = bias_every;
+    return g;
+}
+
+#define RS_HIP(x, what)                                      \
+    do {                                                     \
+        hipError_t e_ = (x);                                 \
+        if (e_ != hipSuccess) return hip_fail(c, e_, what);  \
+    } while (0)
+
+extern "C" int rs_set_decoder_device(rs_ctx* c, const void* theta, int32_t theta_f64, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (!theta) return fail(c, RS_ERR_ARG, "theta is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t es = theta_f64 ? 8 : 4;
+    auto at = [&](size_t off) { return static_cast<const char*>(theta) + off * es; };
+    const int f32 = c->f32, L = c->L;
+    for (int l = 0; l < L; ++l) {
+        const int in = l == 0 ? c->r : c->w, lda = l == 0 ? c->lda0 : c->lda_h;
+        RS_HIP(launch_load_padded(theta_f64, at(c->offW[l]), c->w, in, c->wrows, lda, nullptr, c->W64[l],
+                                  f32 ? (float*)c->W[l] : nullptr, c->bf16 ? (uint16_t*)c->W16[l] : nullptr, s),
+               "decoder load");
+        RS_HIP(launch_load_vec(theta_f64, at(c->offb[l]), c->w, nullptr, c->bh64[l], f32 ? (float*)c->bh[l] : nullptr,
+                               c->wrows, s),
+               "decoder load");
+    }
+    const void* Wo = at(c->offW[L]);
+    const void* bo = at(c->offb[L]);
+    RS_HIP(launch_fold_rows(theta_f64, Wo, bo, c->in_last, c->ffold_ptr, c->ffold_src, c->ffold_coef, c->M, c->Mp,
+                            c->lda_out, c->Wbig64, f32 ? (float*)c->Wbig : nullptr,
+                            c->bf16 ? (uint16_t*)c->Wbig16 : nullptr, c->bbig64, f32 ? (float*)c->bbig : nullptr, s),
+           "decoder fold");
+    RS_HIP(launch_transpose(f32, f32 ? c->Wbig : (const void*)c->Wbig64, c->Mp, c->in_last, c->lda_out, c->WbigT, c->Mp,
+                            c->in_rows, s),
+           "decoder fold");
+    RS_HIP(launch_load_padded(theta_f64, Wo, c->n_out, c->in_last, c->Nfp, c->lda_out, c->pinned_row,
+                              f32 ? nullptr : (double*)c->Wfull, f32 ? (float*)c->Wfull : nullptr,
+                              c->bf16 ? (uint16_t*)c->Wfull16 : nullptr, s),
+           "decoder load");
+    RS_HIP(launch_load_vec(theta_f64, bo, c->n_out, c->pinned_row, f32 ? nullptr : (double*)c->bfull,
+                           f32 ? (float*)c->bfull : nullptr, c->n_out, s),
+           "decoder load");
+    return RS_OK;
+}
+
+extern "C" int rs_lipschitz_param_grad(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,
+                                       double* grad, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
+    if (!loss || !grad || (B > 0 && (!z1 || !z2))) return fail(c, RS_ERR_ARG, "NULL pointer");
+    if (c->bf16) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz-loss gradient needs a float32 or float64 context");
+    if (c->max_batch < 2) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz-loss gradient needs max_batch >= 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int r = c->r, L = c->L, w = c->w, f32 = c->f32, nc2 = r + 2, S9 = 9 * c->S;
+    c->cur_slot = -1;
+    LipWs ws;
+    RS_TRY(lip_ws(c, ws));
+    const int chunk = ws.pairs;
+    RS_TRY(run(c, K_LIP_GRAD, Work{}, s, [&] { return launch_fill_zero(grad, c->n_params, s); }));
+    RS_HIP(launch_fill_zero(c->dWbig, (size_t)c->M * c->in_last, s), "fill");
+    RS_HIP(launch_fill_zero(c->dbbig, (size_t)c->M, s), "fill");
+    RS_HIP(launch_lip_count(z1, z2, B, r, ws.nvalid, s), "lipschitz count");
+    if (B == 0) return run(c, K_LIP_GRAD, Work{}, s, [&] { return launch_lip_coef(z1, z2, c->Hw, 0, r, ws.nvalid, ws.Cs, c->ell, loss, 1, s); });
+    for (int c0 = 0; c0 < B; c0 += chunk) {
+        const int P = std::min(chunk, B - c0), items = 2 * P;
+        const long cols = (long)items * nc2;
+        const double* z1c = z1 + (size_t)c0 * r;
+        const double* z2c = z2 + (size_t)c0 * r;
+        RS_HIP(launch_lip_stack(z1c, z2c, c->zs, P, r, s), "lipschitz pairs");
+        RS_TRY(eval_T(c, items, nullptr, c->zs, nullptr, nullptr, nullptr, nullptr, RS_HESS_EXACT | RS_ELASTIC_ONLY,
+                      nullptr, c->gw, c->Hw, s));
+        RS_TRY(run(c, K_LIP_GRAD, Work{}, s, [&] {
+            return launch_lip_coef(z1c, z2c, c->Hw, P, r, ws.nvalid, ws.Cs, c->ell, loss, c0 == 0, s);
+        }));
+        JetArgs j{};
+        j.r = r;
+        j.w = w;
+        j.items = items;
+        j.S = c->S;
+        j.zs = c->zs;
+        j.Cs = ws.Cs;
+        j.wV = c->wV;
+        j.mu = c->mu;
+        j.lam = c->lam;
+        // forward: jets through the hidden layers (pre-activations kept), then the element rows
+        j.X = ws.X0;
+        j.ldx = cols;
+        RS_HIP(launch_jet(f32, 0, j, s), "jets");
+        const void* Xin = ws.X0;
+        for (int l = 0; l < L; ++l) {
+            const int in = l == 0 ? r : w, lda = l == 0 ? c->lda0 : c->lda_h;
+            RS_HIP(launch_gemm_s(f32, 0, gemm_s(c->W[l], lda, 1, Xin, cols, 1, ws.Pre[l], cols, w, (int)cols, in, 0,
+                                                c->bh[l], nc2), s),
+                   "jets");
+            j.Pre = ws.Pre[l];
+            j.ldp = cols;
+            j.X = ws.X;
+            RS_HIP(launch_jet(f32, 1, j, s), "jets");
+            Xin = ws.X;
+        }
+        RS_HIP(launch_gemm_s(f32, 0, gemm_s(c->Wbig, c->lda_out, 1, Xin, cols, 1, ws.Out, cols, S9, (int)cols, c->in_last,
+                                            0, c->bbig, nc2), s),
+               "jets");
+        j.Pre = ws.Out;
+        j.ldp = cols;
+        j.D = ws.Seed;
+        j.ldd = cols;
+        RS_HIP(launch_jet(f32, 3, j, s), "element seeds");
+        // output map: dW_big += Seed X_L^T, db_big += value-column sums, G = W_big^T Seed
+        RS_HIP(launch_gemm_s(f32, 1, gemm_s(ws.Seed, cols, 1, Xin, 1, cols, c->dWbig, c->in_last, S9, c->in_last,
+                                            (int)cols, 1), s),
+               "jets");
+        RS_HIP(launch_value_rowsum(f32, ws.Seed, cols, S9, items, nc2, c->dbbig, s), "jets");
+        int gi = 0;
+        RS_HIP(launch_gemm_s(f32, 0, gemm_s(c->Wbig, 1, c->lda_out, ws.Seed, cols, 1, ws.G[gi], cols, c->in_last, (int)cols,
+                                            S9), s),
+               "jets");
+        // hidden layers, last to first, activations recomputed from the kept pre-activations
+        for (int l = L - 1; l >= 0; --l) {
+            const int in = l == 0 ? r : w, lda = l == 0 ? c->lda0 : c->lda_h;
+            j.G = ws.G[gi];
+            j.ldg = cols;
+            j.Pre = ws.Pre[l];
+            j.ldp = cols;
+            j.D = ws.D;
+            j.ldd = cols;
+            RS_HIP(launch_jet(f32, 2, j, s), "jets");
+            const void* Xl = ws.X0;
+            if (l > 0) {
+                j.Pre = ws.Pre[l - 1];
+                j.X = ws.X;
+                RS_HIP(launch_jet(f32, 1, j, s), "jets");
+                Xl = ws.X;
+            }
+            RS_HIP(launch_gemm_s(f32, 1, gemm_s(ws.D, cols, 1, Xl, 1, cols, grad + c->offW[l], in, w, in, (int)cols, 1), s),
+                   "jets");
+            RS_HIP(launch_value_rowsum(f32, ws.D, cols, w, items, nc2, grad + c->offb[l], s), "jets");
+            if (l > 0) {
+                RS_HIP(launch_gemm_s(f32, 0, gemm_s(c->W[l], 1, lda, ws.D, cols, 1, ws.G[gi ^ 1], cols, in, (int)cols, w), s),
+                       "jets");
+                gi ^= 1;
+            }
+        }
+    }
+    return run(c, K_LIP_GRAD, Work{}, s, [&] {
+        return launch_unfold(c->dWbig, c->dbbig, c->in_last, c->fold_ptr, c->fold_row, c->fold_coef, c->n_out,
+                             grad + c->offW[L], grad + c->offb[L], s);
+    });
 }
 
 // ------------------------------------------------------------------ profiling

@@ -94,6 +94,21 @@ struct ElemArgs {
     int part_stride;      // parts > 1: g and H of part p of item i at slot p * part_stride + i (E must be NULL)
 };
 
+// Per-element constants of the optional element treatments (kElemConst
+// doubles per cubature tet): B = N^(1/2) (3x3, N the Gram matrix of the shape
+// gradients), B^-1, the shape gradients Dv (4x3), the rest volume and the
+// cubature weight.
+constexpr int kElemConst = 32;
+struct ElemOptArgs {
+    const void* out;      // item-major (rows_pad x nc) [value | Jacobian] rows (context precision)
+    int rows_pad, nc, r, S;
+    const int* count;     // actual item count (NULL = grid size)
+    const double* ec;     // S x kElemConst
+    double mu, lam;
+    double* H;            // items x r x r: the projection's correction is added
+    double* He;           // items x S x 144 element Hessians (dump)
+};
+
 struct EnergyArgs {
     const void* out;      // item-major (rows_pad x 1) values
     int rows_pad;
@@ -200,6 +215,42 @@ struct LbfgsState {
     double* gprev;    // B x r: the gradient there
 };
 
+// Strided GEMM: C(m, n) (+)= alpha sum_k A(m, k) B(k, n) (+ bias[m] on columns
+// n with n % bias_every == 0); A(m, k) = A[m sAm + k sAk], B(k, n) = B[k sBk + n sBn],
+// C row-major (ldc), in the input precision or float64.
+struct SgemmArgs {
+    const void* A;
+    long sAm, sAk;
+    const void* B;
+    long sBk, sBn;
+    void* C;
+    long ldc;
+    int M, N, K;
+    double alpha;
+    int accumulate;
+    const void* bias;
+    int bias_every;
+};
+
+// Jets of the Lipschitz-loss gradient: (value, Jacobian, contracted second
+// derivative) columns, r + 2 per item, column item * (r + 2) + c of row-major
+// (units x columns) blocks.
+struct JetArgs {
+    int r, w, items, S;
+    const double* zs;     // items x r latent points (kind 0)
+    const void* Pre;      // pre-activations (kinds 1, 2) or output rows (kind 3), leading dimension ldp
+    long ldp;
+    void* X;              // activation out (kinds 0, 1), leading dimension ldx
+    long ldx;
+    const void* G;        // adjoints of the layer's output (kind 2), leading dimension ldg
+    long ldg;
+    void* D;              // adjoints of the pre-activations (kind 2) or element seeds (kind 3), ldd
+    long ldd;
+    const double* Cs;     // items x r x r signed contraction matrices
+    const double* wV;     // S cubature weight times volume (kind 3)
+    double mu, lam;
+};
+
 // ----------------------------------------------------------------- launchers
 // arm timing events for the next kernel launch (recorded by the dispatch)
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
@@ -220,6 +271,10 @@ hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int ro
                            const int* count, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
+// per-element positive-semi-definite projection: adds its correction to H
+hipError_t launch_elem_psd(int f32, const ElemOptArgs& a, int items, hipStream_t s);
+// 12x12 element Hessians of the first `items` items into a.He
+hipError_t launch_elem_hess_dump(int f32, const ElemOptArgs& a, int items, hipStream_t s);
 hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
 hipError_t launch_param_outer(int f32, const ParamOuterArgs& a, hipStream_t s);
 // dW[n][k] = sum_j coef[j] * src[row[j]][k] and db[n] = sum_j coef[j] * srcb[row[j]]
@@ -227,6 +282,30 @@ hipError_t launch_param_outer(int f32, const ParamOuterArgs& a, hipStream_t s);
 hipError_t launch_unfold(const double* src, const double* srcb, int ncols, const int* ptr, const int* row,
                          const double* coef, int rows, double* dW, double* db, hipStream_t s);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s);
+// the learned part
+hipError_t launch_gemm_s(int f32, int out_f64, const SgemmArgs& g, hipStream_t s);
+hipError_t launch_lip_stack(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s);
+hipError_t launch_lip_count(const double* z1, const double* z2, int B, int r, int* nvalid, hipStream_t s);
+hipError_t launch_lip_coef(const double* z1, const double* z2, const double* H, int B, int r, const int* nvalid,
+                           double* Cs, double* ell, double* loss, int first, hipStream_t s);
+hipError_t launch_jet(int f32, int kind, const JetArgs& j, hipStream_t s);
+hipError_t launch_value_rowsum(int f32, const void* D, long ldd, int rows, int items, int nc, double* grad, hipStream_t s);
+hipError_t launch_load_padded(int src_f64, const void* src, int out, int in, int rows_pad, int ld,
+                              const uint8_t* rowmask, double* d64, float* d32, uint16_t* d16, hipStream_t s);
+hipError_t launch_fold_rows(int src_f64, const void* Wout, const void* bout, int in_last, const int* ptr, const int* src,
+                            const double* coef, int M, int Mp, int ld, double* W64, float* W32, uint16_t* W16,
+                            double* b64, float* b32, hipStream_t s);
+hipError_t launch_transpose(int f32, const void* src, int rows, int cols, int ld_src, void* dst, int ld_dst,
+                            int dst_rows, hipStream_t s);
+hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* rowmask, double* d64, float* d32,
+                           int n_pad, hipStream_t s);
+hipError_t launch_elu(int backward, const float* G, const float* P, float* out, long n, hipStream_t s);
+hipError_t launch_recon_residual(const float* U, const float* d, int n, int B, const double* rowmass,
+                                 const uint8_t* pinned_row, float* Ubar, double* part, double* loss, hipStream_t s);
+hipError_t launch_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate, hipStream_t s);
+hipError_t launch_items_convert(int to_items, const float* X, double* z, float* Xo, int rows, int B, hipStream_t s);
+hipError_t launch_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
+                       double lr, double b1, double b2, double eps, int step, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
@@ -236,8 +315,9 @@ hipError_t launch_lbfgs_dir(const NewtonState& st, const NewtonParams& p, const 
 // search list, candidate list and candidate points zc
 hipError_t launch_compact_search(const NewtonState& st, const NewtonParams& p, int B, hipStream_t s);
 // Armijo test, then the next evaluation list and the running count, also written to `host` (device address
-// of mapped pinned memory, may be NULL)
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, int* host, hipStream_t s);
+// of mapped pinned memory, may be NULL) as (tag << 32) | count
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, unsigned long long* host,
+                         unsigned int tag, hipStream_t s);
 hipError_t launch_stack_pairs(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s);
 hipError_t launch_lipschitz(const double* z1, const double* z2, const double* H, int B, int r,
                             double* per_pair, double* ell, double* acc, int first_chunk, int last_chunk,

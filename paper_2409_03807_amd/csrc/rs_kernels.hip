@@ -6,7 +6,7 @@
 // respect to z (forward mode, Sec. 3.2 decoder with its Jacobian df/dz as in
 // Eq. form-cubature-gradients).  The GEMMs flatten (item, column) into one
 // column index, so any r uses the same 64x64 MFMA tiles.
-#include "rs_internal.hpp"
+#include "rs_device.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -19,86 +19,13 @@ namespace rs {
 
 // Launch events armed by the profiler for the next launch only: the events
 // are recorded by the dispatch itself (no marker packets between kernels).
-static thread_local hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
+thread_local hipEvent_t g_launch_ev[2] = {nullptr, nullptr};
 void set_launch_events(hipEvent_t start, hipEvent_t stop)
 {
     g_launch_ev[0] = start;
     g_launch_ev[1] = stop;
 }
 bool launch_events_pending() { return g_launch_ev[0] != nullptr; }
-
-#define RS_LAUNCH(kernel, grid, block, shm, stream, ...)                                          \
-    do {                                                                                         \
-        if (g_launch_ev[0]) {                                                                    \
-            hipEvent_t e0_ = g_launch_ev[0], e1_ = g_launch_ev[1];                               \
-            g_launch_ev[0] = g_launch_ev[1] = nullptr;                                           \
-            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, e0_, e1_, 0, __VA_ARGS__);   \
-        } else {                                                                                 \
-            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                   \
-        }                                                                                        \
-    } while (0)
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-// Both take A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k; the
-// result rows differ: f32 puts D[4 (lane/16) + v][lane%16] in register v,
-// f64 puts D[lane/16 + 4 v][lane%16] in register v.
-template <> struct Mfma<float> {
-    using acc_t = f32x4;
-    __device__ static acc_t mac(float a, float b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-template <> struct Mfma<double> {
-    using acc_t = f64x4;
-    __device__ static acc_t mac(double a, double b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-
-// 16-byte vectors as clang native vectors (element access stays in registers)
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = f32x4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = f64x2; static constexpr int n = 2; };
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// One 32-deep chunk of a 16x16 product in BF16 with FP32 accumulation:
-// lane (i + 16 g) supplies A[i][8g .. 8g+7] and B[8g .. 8g+7][i], which is the
-// permuted-k fragment every GEMM here holds per 32-deep chunk.
-__device__ inline f32x4 mfma_bf16_chunk(bf16x8 a, bf16x8 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// Eight float32 values as a BF16 pair: hi = bf16(x), lo = bf16(x - hi), so
-// hi + lo carries x to about 16 significant bits and the products with a
-// BF16 operand lose only that operand's rounding.
-__device__ inline void split_bf16(f32x4 x0, f32x4 x1, bf16x8& hi, bf16x8& lo)
-{
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const __bf16 h0 = (__bf16)x0[e], h1 = (__bf16)x1[e];
-        hi[e] = h0;
-        hi[4 + e] = h1;
-        lo[e] = (__bf16)(x0[e] - (float)h0);
-        lo[4 + e] = (__bf16)(x1[e] - (float)h1);
-    }
-}
-
-// ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.
-__device__ inline float elu0(float a) { return a > 0.f ? a : expm1f(a); }
-__device__ inline double elu0(double a) { return a > 0.0 ? a : expm1(a); }
-__device__ inline float elu1(float a) { return a > 0.f ? 1.f : expf(a); }
-__device__ inline double elu1(double a) { return a > 0.0 ? 1.0 : exp(a); }
-__device__ inline double elu2(double a) { return a > 0.0 ? 0.0 : exp(a); }
 
 // ---------------------------------------------------------------------------
 // GEMM: C[item] = A * Y[item] (+ bias on column 0), MFMA 16x16x4, 64x64 tiles.
@@ -1346,115 +1273,6 @@ hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int ro
 //   P = mu (G + G^T - tr G I - cof G) + lam (J - 1) cof F.
 // vec index v = 3 j + i (column-major, G_ij); columns g_j of G, f_j of F.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Snh {
-    T g[3][3];   // g[j][i] = G_ij
-    T f[3][3];   // f[j][i] = F_ij
-    T cof[3][3]; // cof[j][i] = (cof F)_ij
-    T cg[3][3];  // cg[j][i] = (cof G)_ij
-    T jm, psi, s; // J - 1, energy density, lam (J-1) - mu
-
-    __device__ void set(const T* gu, T mu, T lam)
-    {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                g[j][i] = gu[3 * j + i];
-                f[j][i] = g[j][i] + (i == j ? T(1) : T(0));
-            }
-        cross(g[1], g[2], cg[0]);
-        cross(g[2], g[0], cg[1]);
-        cross(g[0], g[1], cg[2]);
-        const T tr = g[0][0] + g[1][1] + g[2][2];
-        const T detg = g[0][0] * cg[0][0] + g[0][1] * cg[0][1] + g[0][2] * cg[0][2];
-        const T i2 = (g[0][0] * g[1][1] - g[1][0] * g[0][1]) + (g[0][0] * g[2][2] - g[2][0] * g[0][2])
-                   + (g[1][1] * g[2][2] - g[2][1] * g[1][2]);
-        T nrm = 0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                nrm += g[j][i] * g[j][i];
-                cof[j][i] = (i == j ? T(1) + tr : T(0)) - g[i][j] + cg[j][i];
-            }
-        jm = tr + i2 + detg;
-        psi = T(0.5) * mu * nrm - mu * (i2 + detg) + T(0.5) * lam * jm * jm;
-        s = lam * jm - mu;
-    }
-    __device__ static void cross(const T* a, const T* b, T* c)
-    {
-        c[0] = a[1] * b[2] - a[2] * b[1];
-        c[1] = a[2] * b[0] - a[0] * b[2];
-        c[2] = a[0] * b[1] - a[1] * b[0];
-    }
-    // first Piola-Kirchhoff stress, vec layout
-    __device__ void pk1(T mu, T lam, T* P) const
-    {
-        const T tr = g[0][0] + g[1][1] + g[2][2];
-        const T lj = lam * jm;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                P[3 * j + i] = mu * (g[j][i] + g[i][j] - (i == j ? tr : T(0)) - cg[j][i]) + lj * cof[j][i];
-    }
-    // (d2 psi / dF2) v with mu, lam and s scaled by the caller (one weight for
-    // the element folded into the three scalars); the columns of d(cof F)[v]
-    // as single fused chains
-    __device__ void apply_hess_w(T wmu, T wlam, T ws, const T* v, T* out) const
-    {
-        T gv = 0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) gv = fma(cof[j][i], v[3 * j + i], gv);
-        const T t = wlam * gv;
-        const T* v0 = v;
-        const T* v1 = v + 3;
-        const T* v2 = v + 6;
-        // column j of d(cof F)[v]: v_{j+1} x f_{j+2} + f_{j+1} x v_{j+2}
-        auto dcol = [&](const T* va, const T* fb, const T* fa, const T* vb, int i) {
-            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
-            T d = va[i1] * fb[i2];
-            d = fma(-va[i2], fb[i1], d);
-            d = fma(fa[i1], vb[i2], d);
-            return fma(-fa[i2], vb[i1], d);
-        };
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            out[i] = fma(ws, dcol(v1, f[2], f[1], v2, i), fma(t, cof[0][i], wmu * v0[i]));
-            out[3 + i] = fma(ws, dcol(v2, f[0], f[2], v0, i), fma(t, cof[1][i], wmu * v1[i]));
-            out[6 + i] = fma(ws, dcol(v0, f[1], f[0], v1, i), fma(t, cof[2][i], wmu * v2[i]));
-        }
-    }
-    // (d2 psi / dF2) v = mu v + lam g (g.v) + s d(cof F)[v], g = vec cof F,
-    // d(cof F)[v] = [v1 x f2 + f1 x v2, v2 x f0 + f2 x v0, v0 x f1 + f0 x v1]
-    __device__ void apply_hess(T mu, T lam, const T* v, T* out) const
-    {
-        T gv = 0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) gv += cof[j][i] * v[3 * j + i];
-        T d0[3], d1[3], d2[3], t0[3], t1[3];
-        cross(v + 3, f[2], t0); cross(f[1], v + 6, t1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) d0[i] = t0[i] + t1[i];
-        cross(v + 6, f[0], t0); cross(f[2], v, t1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) d1[i] = t0[i] + t1[i];
-        cross(v, f[1], t0); cross(f[0], v + 3, t1);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) d2[i] = t0[i] + t1[i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            out[i] = mu * v[i] + lam * cof[0][i] * gv + s * d0[i];
-            out[3 + i] = mu * v[3 + i] + lam * cof[1][i] * gv + s * d1[i];
-            out[6 + i] = mu * v[6 + i] + lam * cof[2][i] * gv + s * d2[i];
-        }
-    }
-};
 // ---------------------------------------------------------------------------
 // Element kernel: one workgroup per item (or a run of its rounds, when a small
 // batch splits items), RP lanes per cubature tet: lane k owns column k of
@@ -3277,8 +3095,10 @@ hipError_t launch_lbfgs_dir(const NewtonState& st, const NewtonParams& p, const 
 // End of a super-step in one workgroup: the Armijo test of every searching
 // item over its candidates (first acceptable step length, in order), then
 // the evaluation list of the next super-step and the count of items still
-// running (also stored to `host`, coherent mapped host memory, with a system-scope store; may be NULL).
-__global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p, int B, int* host)
+// running (also stored to `host`, coherent mapped host memory, as one 64-bit system-scope release store of
+// (tag << 32) | count, so that the reader can tell this super-step's count from an older one; may be NULL).
+__global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p, int B, unsigned long long* host,
+                                                 unsigned int tag)
 {
     constexpr int NB = 16;
     __shared__ int sc[16];
@@ -3357,13 +3177,16 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     if (tid == 0) {
         st.counters[0] = base;
         st.counters[3] = running;
-        if (host) __hip_atomic_store(host, running, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (host)
+            __hip_atomic_store(host, ((unsigned long long)tag << 32) | (unsigned int)running, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
-hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, int* host, hipStream_t s)
+hipError_t launch_armijo(const NewtonState& st, const NewtonParams& p, int B, unsigned long long* host,
+                         unsigned int tag, hipStream_t s)
 {
-    RS_LAUNCH(k_armijo, dim3(1), dim3(1024), 0, s, st, p, B, host);
+    RS_LAUNCH(k_armijo, dim3(1), dim3(1024), 0, s, st, p, B, host, tag);
     return hipGetLastError();
 }
 

@@ -1,0 +1,704 @@
+// Kernels of the learned part: the decoder-parameter gradient of the
+// Lipschitz loss (Sec. 4.1, Eq. form-L-LS-E, on the cubature elastic Hessian of
+// Sec. 4.3), the device-side load of decoder weights (the output-layer fold
+// onto the reduced rows), and the supervised training of encoder and decoder
+// (Sec. 3.2, Eq. form-vanilla-supervised-construction; Sec. 4.2, Eq.
+// form-unconstrained-lipschitz-optimization).
+//
+// Lipschitz-loss gradient.  For a symmetric r x r matrix C the contraction
+// s = <C, H(z)> = sum_kq C_kq d2 P~/dz_k dz_q is carried forward through the
+// decoder as three kinds of columns per latent point: the value h, the
+// Jacobian columns J = dh/dz and the contracted second derivative
+// S = sum_kq C_kq d2 h/dz_k dz_q.  A hidden layer maps pre-activations
+// (a, A = W J, a_S = W S) to h = elu(a), J = elu'(a) A and
+// S = elu''(a) (A C A^T)_uu + elu'(a) a_S.  Through the folded output map the
+// element rows give F - I, K = dvecF/dz and Fdd (the contracted second
+// derivative of vec F); per element s = w V [tr(C K^T A(F) K) + P(F) : Fdd].
+// The backward pass takes the adjoints of the three kinds of columns back to
+// the first layer; the derivative of A(F) enters through
+//   d/dF tr(C K^T A(F) K) = 2 lam cofd(F, m1) + lam (sum_k M_k . cofd(F, K_k)) g
+//                           + (lam (J - 1) - mu) sum_k cofd(M_k, K_k),
+// with g = vec cof F, M = K C, m1 = M K^T g and cofd(X, Y) the symmetric
+// bilinear form with cofd(X, X) = 2 cof X (the second derivative of det).
+#include "rs_device.hpp"
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// Strided GEMM on the matrix cores: C(m, n) (+)= alpha sum_k A(m, k) B(k, n)
+// (+ bias[m] on columns n with n % bias_every == 0), A(m, k) = A[m sAm + k sAk],
+// B(k, n) = B[k sBk + n sBn], C row-major with leading dimension ldc, in T or
+// float64.  64 x 64 tiles, four waves of 16 rows, 16-deep chunks through LDS.
+// ---------------------------------------------------------------------------
+template <typename T, typename TC>
+__global__ __launch_bounds__(256) void k_gemm_s(SgemmArgs g)
+{
+    constexpr int TM = 64, TN = 64, TK = 16;
+    __shared__ T As[TM][TK + 1];
+    __shared__ T Bs[TK][TN + 1];
+    const T* A = static_cast<const T*>(g.A);
+    const T* B = static_cast<const T*>(g.B);
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    typename Mfma<T>::acc_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid + 256 * e;           // 1024 = 64 x 16 values of each tile
+            const int am = idx / TK, ak = idx % TK;  // A: row-major walk
+            const int gm = m0 + am, gk = k0 + ak;
+            As[am][ak] = (gm < g.M && gk < g.K) ? A[(long)gm * g.sAm + (long)gk * g.sAk] : T(0);
+            const int bk = idx / TN, bn = idx % TN;  // B: consecutive threads, consecutive columns
+            const int hk = k0 + bk, hn = n0 + bn;
+            Bs[bk][bn] = (hk < g.K && hn < g.N) ? B[(long)hk * g.sBk + (long)hn * g.sBn] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK / 4; ++kk) {
+            const T av = As[16 * wave + (lane & 15)][4 * kk + (lane >> 4)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const T bv = Bs[4 * kk + (lane >> 4)][16 * t + (lane & 15)];
+                acc[t] = Mfma<T>::mac(av, bv, acc[t]);
+            }
+        }
+        __syncthreads();
+    }
+    TC* Cp = static_cast<TC*>(g.C);
+    const T* bias = static_cast<const T*>(g.bias);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int m = m0 + 16 * wave + Mfma<T>::row(lane, v), n = n0 + 16 * t + (lane & 15);
+            if (m >= g.M || n >= g.N) continue;
+            double val = g.alpha * (double)acc[t][v];
+            if (bias && g.bias_every > 0 && n % g.bias_every == 0) val += (double)bias[m];
+            TC* dst = Cp + (long)m * g.ldc + n;
+            *dst = g.accumulate ? (TC)((double)*dst + val) : (TC)val;
+        }
+}
+
+hipError_t launch_gemm_s(int f32, int out_f64, const SgemmArgs& g, hipStream_t s)
+{
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    if (f32) {
+        if (out_f64) RS_LAUNCH((k_gemm_s<float, double>), grid, dim3(256), 0, s, g);
+        else RS_LAUNCH((k_gemm_s<float, float>), grid, dim3(256), 0, s, g);
+    } else {
+        RS_LAUNCH((k_gemm_s<double, double>), grid, dim3(256), 0, s, g);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lipschitz-loss gradient: pairs, coefficients, jets, element seeds, adjoints
+// ---------------------------------------------------------------------------
+__global__ void k_lip_stack(const double* z1, const double* z2, double* zs, int B, int r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * r) return;
+    const int b = i / r, k = i - b * r;
+    zs[(size_t)(2 * b) * r + k] = z1[i];
+    zs[(size_t)(2 * b + 1) * r + k] = z2[i];
+}
+
+// One workgroup: n_valid, the loss mean_b |H1 - H2|_F^2 / |dz|^2 over this
+// chunk's pairs (added to acc[0], count to acc[1]) and the signed
+// coefficients Cs[2b] = 2 sym(H1 - H2) / (|dz|^2 n_total), Cs[2b+1] = -Cs[2b].
+// n_total (all pairs of the call) is counted first by the caller's kernel.
+__global__ __launch_bounds__(256) void k_lip_count(const double* z1, const double* z2, int B, int r, int* nvalid)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int local = 0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        double d2 = 0.0;
+        for (int k = 0; k < r; ++k) {
+            const double d = z1[(size_t)b * r + k] - z2[(size_t)b * r + k];
+            d2 += d * d;
+        }
+        local += d2 > 0.0;
+    }
+    atomicAdd(&cnt, local);
+    __syncthreads();
+    if (threadIdx.x == 0) *nvalid = cnt;
+}
+
+__global__ __launch_bounds__(256) void k_lip_coef(const double* z1, const double* z2, const double* H, int B, int r,
+                                                 const int* nvalid, double* Cs, double* ell)
+{
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const int rr = r * r;
+    __shared__ double d2s;
+    if (threadIdx.x == 0) {
+        double d2 = 0.0;
+        for (int k = 0; k < r; ++k) {
+            const double d = z1[(size_t)b * r + k] - z2[(size_t)b * r + k];
+            d2 += d * d;
+        }
+        d2s = d2;
+    }
+    __syncthreads();
+    const double d2 = d2s;
+    const double* H1 = H + (size_t)(2 * b) * rr;
+    const double* H2 = H1 + rr;
+    double* C1 = Cs + (size_t)(2 * b) * rr;
+    double* C2 = C1 + rr;
+    const int nv = *nvalid;
+    for (int t = threadIdx.x; t < rr; t += blockDim.x) {
+        const int k = t / r, q = t - k * r;
+        double c = 0.0;
+        if (d2 > 0.0)
+            c = ((H1[t] - H2[t]) + (H1[q * r + k] - H2[q * r + k])) / (d2 * nv);
+        C1[t] = c;
+        C2[t] = -c;
+    }
+    if (threadIdx.x == 0) {
+        double fro = 0.0;
+        for (int t = 0; t < rr; ++t) fro += (H1[t] - H2[t]) * (H1[t] - H2[t]);
+        ell[b] = d2 > 0.0 ? fro / d2 : 0.0;
+    }
+}
+
+// loss = sum of the chunk's ell over all valid pairs / n_valid (one thread, pair order)
+__global__ void k_lip_sum(const double* ell, int B, const int* nvalid, double* loss, int first)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = first ? 0.0 : *loss;
+    const int nv = *nvalid;
+    for (int b = 0; b < B; ++b) s += nv > 0 ? ell[b] / nv : 0.0;
+    *loss = s;
+}
+
+// X_0 = [z | I | 0] (r x cols), column item * nc + c
+template <typename T>
+__global__ void k_jet_input(const double* zs, int items, int r, int nc, T* X, long ldx)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long cols = (long)items * nc;
+    if (i >= (long)r * cols) return;
+    const int k = (int)(i / cols);
+    const long col = i - (long)k * cols;
+    const int item = (int)(col / nc), c = (int)(col - (long)item * nc);
+    T v = T(0);
+    if (c == 0) v = (T)zs[(size_t)item * r + k];
+    else if (c == k + 1) v = T(1);
+    X[(long)k * ldx + col] = v;
+}
+
+// hidden-layer activation of the jets, one thread per (unit, item); RM >= r
+template <typename T, int RM>
+__global__ void k_jet_act(const T* Pre, long ldp, T* X, long ldx, int w, int items, int r, const double* Cs)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)w * items) return;
+    const int u = (int)(i / items), item = (int)(i - (long)u * items);
+    const int nc = r + 2;
+    const T* p = Pre + (long)u * ldp + (long)item * nc;
+    T* x = X + (long)u * ldx + (long)item * nc;
+    const double* C = Cs + (size_t)item * r * r;
+    const double a = (double)p[0], aS = (double)p[r + 1];
+    double A[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) A[k] = k < r ? (double)p[1 + k] : 0.0;
+    double q = 0.0;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+        if (k >= r) break;
+        double t = 0.0;
+#pragma unroll
+        for (int k2 = 0; k2 < RM; ++k2)
+            if (k2 < r) t += C[k2 * r + k] * A[k2];
+        q += t * A[k];
+    }
+    const double s1 = elu1(a), s2 = elu2(a);
+    x[0] = (T)elu0(a);
+#pragma unroll
+    for (int k = 0; k < RM; ++k)
+        if (k < r) x[1 + k] = (T)(s1 * A[k]);
+    x[r + 1] = (T)(s2 * q + s1 * aS);
+}
+
+// adjoints of a hidden layer's pre-activations, one thread per (unit, item)
+template <typename T, int RM>
+__global__ void k_jet_back(const T* G, long ldg, const T* Pre, long ldp, T* D, long ldd, int w, int items, int r,
+                           const double* Cs)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)w * items) return;
+    const int u = (int)(i / items), item = (int)(i - (long)u * items);
+    const int nc = r + 2;
+    const T* gp = G + (long)u * ldg + (long)item * nc;
+    const T* p = Pre + (long)u * ldp + (long)item * nc;
+    T* d = D + (long)u * ldd + (long)item * nc;
+    const double* C = Cs + (size_t)item * r * r;
+    const double a = (double)p[0], aS = (double)p[r + 1];
+    const double hb = (double)gp[0], Sb = (double)gp[r + 1];
+    double A[RM], Jb[RM], AC[RM];
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+        A[k] = k < r ? (double)p[1 + k] : 0.0;
+        Jb[k] = k < r ? (double)gp[1 + k] : 0.0;
+    }
+    double q = 0.0, AJ = 0.0;
+#pragma unroll
+    for (int k = 0; k < RM; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int k2 = 0; k2 < RM; ++k2)
+            if (k < r && k2 < r) t += A[k2] * C[k2 * r + k];
+        AC[k] = t;
+        q += t * A[k];
+        AJ += A[k] * Jb[k];
+    }
+    // ELU: the second and third derivatives coincide (e^a for a <= 0, zero above)
+    const double s1 = elu1(a), s2 = elu2(a), s3 = s2;
+    d[0] = (T)(s1 * hb + s2 * AJ + s3 * q * Sb + s2 * aS * Sb);
+#pragma unroll
+    for (int k = 0; k < RM; ++k)
+        if (k < r) d[1 + k] = (T)(s1 * Jb[k] + 2.0 * s2 * Sb * AC[k]);
+    d[r + 1] = (T)(s1 * Sb);
+}
+
+// cofd(X, Y) column j: x_{j+1} x y_{j+2} + y_{j+1} x x_{j+2} (vec column-major, 3 j + i)
+__device__ inline void cofd(const double* X, const double* Y, double* out)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double* x1 = X + 3 * ((j + 1) % 3);
+        const double* x2 = X + 3 * ((j + 2) % 3);
+        const double* y1 = Y + 3 * ((j + 1) % 3);
+        const double* y2 = Y + 3 * ((j + 2) % 3);
+        out[3 * j + 0] = x1[1] * y2[2] - x1[2] * y2[1] + y1[1] * x2[2] - y1[2] * x2[1];
+        out[3 * j + 1] = x1[2] * y2[0] - x1[0] * y2[2] + y1[2] * x2[0] - y1[0] * x2[2];
+        out[3 * j + 2] = x1[0] * y2[1] - x1[1] * y2[0] + y1[0] * x2[1] - y1[1] * x2[0];
+    }
+}
+
+// element seeds of s = <C, H> per (item, cubature tet): from the output rows
+// (F - I, K, Fdd) to their adjoints (Fbar, Kbar, w V P), float64 inside.  Each
+// thread stages its K (9 x r) in its own slice of LDS (kSeedThreads threads a
+// workgroup) and walks the columns of M = K C one at a time.
+constexpr int kSeedThreads = 64;
+template <typename T>
+__global__ __launch_bounds__(kSeedThreads) void k_jet_seed(const T* Out, long ldo, T* Seed, long lds, int items, int S,
+                                                           int r, const double* wV, double mu, double lam,
+                                                           const double* Cs)
+{
+    extern __shared__ double sK[]; // [v * r + k][thread]
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)items * S) return;
+    const int s = (int)(i / items), item = (int)(i - (long)s * items);
+    const int nc = r + 2, th = threadIdx.x;
+    const double* C = Cs + (size_t)item * r * r;
+    const long col = (long)item * nc;
+    auto Kat = [&](int v, int k) -> double& { return sK[(size_t)(v * r + k) * kSeedThreads + th]; };
+    double G[9], Fdd[9];
+    for (int v = 0; v < 9; ++v) {
+        const T* row = Out + (long)(9 * s + v) * ldo + col;
+        G[v] = (double)row[0];
+        Fdd[v] = (double)row[r + 1];
+        for (int k = 0; k < r; ++k) Kat(v, k) = (double)row[1 + k];
+    }
+    Snh<double> sn;
+    sn.set(G, mu, lam);
+    double F[9], g[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int ii = 0; ii < 3; ++ii) {
+            F[3 * j + ii] = sn.f[j][ii];
+            g[3 * j + ii] = sn.cof[j][ii];
+        }
+    const double w = wV[s];
+    // T_C = 2 lam cofd(F, m1) + lam (sum_k M_k . cofd(F, K_k)) g + s_f sum_k cofd(M_k, K_k), m1 = sum_k M_k (K_k . g)
+    double m1[9], sumB[9], tmp[9], Kk[9], Mk[9];
+    double trm = 0.0;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) m1[v] = sumB[v] = 0.0;
+    for (int k = 0; k < r; ++k) {
+        double ktg = 0.0;
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            Kk[v] = Kat(v, k);
+            ktg += Kk[v] * g[v];
+            double t = 0.0;
+            for (int k2 = 0; k2 < r; ++k2) t += Kat(v, k2) * C[k2 * r + k];
+            Mk[v] = t;
+        }
+        cofd(F, Kk, tmp);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) {
+            trm += Mk[v] * tmp[v];
+            m1[v] += Mk[v] * ktg;
+        }
+        cofd(Mk, Kk, tmp);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) sumB[v] += tmp[v];
+        // Kbar_k = 2 w V A(F) M_k
+        sn.apply_hess(mu, lam, Mk, tmp);
+#pragma unroll
+        for (int v = 0; v < 9; ++v) Seed[(long)(9 * s + v) * lds + col + 1 + k] = (T)(2.0 * w * tmp[v]);
+    }
+    double Tc[9];
+    cofd(F, m1, tmp);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) Tc[v] = 2.0 * lam * tmp[v] + lam * trm * g[v] + sn.s * sumB[v];
+    double AFdd[9], P[9];
+    sn.apply_hess(mu, lam, Fdd, AFdd);
+    sn.pk1(mu, lam, P);
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        T* row = Seed + (long)(9 * s + v) * lds + col;
+        row[0] = (T)(w * (Tc[v] + AFdd[v]));
+        row[r + 1] = (T)(w * P[v]);
+    }
+}
+
+// grad[u] += sum over items of D[u][item * nc] (bias gradients from the value columns)
+template <typename T>
+__global__ void k_value_rowsum(const T* D, long ldd, int rows, int items, int nc, double* grad)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= rows) return;
+    double s = 0.0;
+    for (int item = 0; item < items; ++item) s += (double)D[(long)u * ldd + (long)item * nc];
+    grad[u] += s;
+}
+
+hipError_t launch_lip_stack(const double* z1, const double* z2, double* zs, int B, int r, hipStream_t s)
+{
+    if (B <= 0) return hipSuccess;
+    RS_LAUNCH(k_lip_stack, dim3((B * r + 255) / 256), dim3(256), 0, s, z1, z2, zs, B, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_lip_count(const double* z1, const double* z2, int B, int r, int* nvalid, hipStream_t s)
+{
+    RS_LAUNCH(k_lip_count, dim3(1), dim3(256), 0, s, z1, z2, B, r, nvalid);
+    return hipGetLastError();
+}
+
+hipError_t launch_lip_coef(const double* z1, const double* z2, const double* H, int B, int r, const int* nvalid,
+                           double* Cs, double* ell, double* loss, int first, hipStream_t s)
+{
+    if (B > 0) RS_LAUNCH(k_lip_coef, dim3(B), dim3(256), 0, s, z1, z2, H, B, r, nvalid, Cs, ell);
+    RS_LAUNCH(k_lip_sum, dim3(1), dim3(64), 0, s, ell, B, nvalid, loss, first);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t jet_dispatch(int kind, const JetArgs& j, hipStream_t s)
+{
+    const long n = kind == 0 ? (long)j.r * j.items * (j.r + 2) : kind == 3 ? (long)j.items * j.S : (long)j.w * j.items;
+    if (n <= 0) return hipSuccess;
+    const dim3 block(kind == 3 ? kSeedThreads : 256);
+    const dim3 grid((unsigned)((n + block.x - 1) / block.x));
+    const bool r16 = j.r <= 16;
+    if (kind == 0) {
+        RS_LAUNCH(k_jet_input<T>, grid, block, 0, s, j.zs, j.items, j.r, j.r + 2, (T*)j.X, j.ldx);
+    } else if (kind == 1) {
+        if (r16) RS_LAUNCH((k_jet_act<T, 16>), grid, block, 0, s, (const T*)j.Pre, j.ldp, (T*)j.X, j.ldx, j.w, j.items, j.r, j.Cs);
+        else RS_LAUNCH((k_jet_act<T, kMaxR>), grid, block, 0, s, (const T*)j.Pre, j.ldp, (T*)j.X, j.ldx, j.w, j.items, j.r, j.Cs);
+    } else if (kind == 2) {
+        if (r16)
+            RS_LAUNCH((k_jet_back<T, 16>), grid, block, 0, s, (const T*)j.G, j.ldg, (const T*)j.Pre, j.ldp, (T*)j.D, j.ldd,
+                      j.w, j.items, j.r, j.Cs);
+        else
+            RS_LAUNCH((k_jet_back<T, kMaxR>), grid, block, 0, s, (const T*)j.G, j.ldg, (const T*)j.Pre, j.ldp, (T*)j.D,
+                      j.ldd, j.w, j.items, j.r, j.Cs);
+    } else {
+        const size_t shm = sizeof(double) * 9 * (size_t)j.r * kSeedThreads;
+        RS_LAUNCH(k_jet_seed<T>, grid, block, shm, s, (const T*)j.Pre, j.ldp, (T*)j.D, j.ldd, j.items, j.S, j.r, j.wV,
+                  j.mu, j.lam, j.Cs);
+    }
+    return hipGetLastError();
+}
+
+// kind 0: first-layer input [z | I | 0]; 1: hidden activation; 2: hidden adjoints; 3: element seeds
+hipError_t launch_jet(int f32, int kind, const JetArgs& j, hipStream_t s)
+{
+    if (j.r > kMaxR) return hipErrorInvalidValue;
+    return f32 ? jet_dispatch<float>(kind, j, s) : jet_dispatch<double>(kind, j, s);
+}
+
+hipError_t launch_value_rowsum(int f32, const void* D, long ldd, int rows, int items, int nc, double* grad, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    if (f32) RS_LAUNCH(k_value_rowsum<float>, dim3((rows + 255) / 256), dim3(256), 0, s, (const float*)D, ldd, rows, items, nc, grad);
+    else RS_LAUNCH(k_value_rowsum<double>, dim3((rows + 255) / 256), dim3(256), 0, s, (const double*)D, ldd, rows, items, nc, grad);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Device-side decoder load: packed parameters (float32 or float64) into the
+// context's padded layouts, and the output-layer fold onto the reduced rows.
+// ---------------------------------------------------------------------------
+// float64 -> bfloat16 with round to nearest even; a float32 midpoint is decided
+// by the float64 value (the correctly rounded result)
+__device__ inline uint16_t bf16_rne_dev(double x)
+{
+    const float f = (float)x;
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t hi = u >> 16, lo = u & 0xFFFFu;
+    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)(hi | ((u & 0x7FFFFFu) ? 0x40u : 0u));
+    bool up;
+    if (lo > 0x8000u) up = true;
+    else if (lo < 0x8000u) up = false;
+    else {
+        const double ax = fabs(x), af = fabs((double)f);
+        up = ax > af ? true : ax < af ? false : (hi & 1u) != 0;
+    }
+    return (uint16_t)(up ? hi + 1 : hi);
+}
+
+template <typename TS>
+__global__ void k_load_padded(const TS* src, int out, int in, int rows_pad, int ld, const uint8_t* rowmask, double* d64,
+                              float* d32, uint16_t* d16)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)rows_pad * ld) return;
+    const int m = (int)(i / ld), k = (int)(i - (long)m * ld);
+    double v = 0.0;
+    if (m < out && k < in && !(rowmask && rowmask[m])) v = (double)src[(long)m * in + k];
+    if (d64) d64[i] = v;
+    if (d32) d32[i] = (float)v;
+    if (d16) d16[i] = bf16_rne_dev(v);
+}
+
+// W_big[m][k] = sum_j coef[j] W_out[src[j]][k] (+ the same for the bias, column in_last of a
+// virtual [W | b]); rows past M and columns past in_last are zero
+template <typename TS>
+__global__ void k_fold_rows(const TS* Wout, const TS* bout, int in_last, const int* ptr, const int* src,
+                            const double* coef, int M, int Mp, int ld, double* W64, float* W32, uint16_t* W16,
+                            double* b64, float* b32)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)Mp * (ld + 1)) return;
+    const int m = (int)(i / (ld + 1)), k = (int)(i - (long)m * (ld + 1));
+    double v = 0.0;
+    if (m < M && (k < in_last || k == ld)) {
+        for (int j = ptr[m]; j < ptr[m + 1]; ++j)
+            v += coef[j] * (k == ld ? (double)bout[src[j]] : (double)Wout[(long)src[j] * in_last + k]);
+    }
+    if (k == ld) {
+        if (b64) b64[m] = v;
+        if (b32) b32[m] = (float)v;
+        return;
+    }
+    const long o = (long)m * ld + k;
+    if (W64) W64[o] = v;
+    if (W32) W32[o] = (float)v;
+    if (W16) W16[o] = bf16_rne_dev(v);
+}
+
+// dst[k][m] = src[m][k] for the adjoint product's transposed W_big
+template <typename T>
+__global__ void k_transpose(const T* src, int rows, int cols, int ld_src, T* dst, int ld_dst, int dst_rows)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)dst_rows * ld_dst) return;
+    const int k = (int)(i / ld_dst), m = (int)(i - (long)k * ld_dst);
+    dst[i] = (k < cols && m < rows) ? src[(long)m * ld_src + k] : T(0);
+}
+
+template <typename TS>
+__global__ void k_load_vec(const TS* src, int n, const uint8_t* rowmask, double* d64, float* d32, int n_pad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    const double v = (i < n && !(rowmask && rowmask[i])) ? (double)src[i] : 0.0;
+    if (d64) d64[i] = v;
+    if (d32) d32[i] = (float)v;
+}
+
+static inline dim3 grid_for(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_load_padded(int src_f64, const void* src, int out, int in, int rows_pad, int ld,
+                              const uint8_t* rowmask, double* d64, float* d32, uint16_t* d16, hipStream_t s)
+{
+    const long n = (long)rows_pad * ld;
+    if (n <= 0) return hipSuccess;
+    if (src_f64) RS_LAUNCH(k_load_padded<double>, grid_for(n), dim3(256), 0, s, (const double*)src, out, in, rows_pad, ld, rowmask, d64, d32, d16);
+    else RS_LAUNCH(k_load_padded<float>, grid_for(n), dim3(256), 0, s, (const float*)src, out, in, rows_pad, ld, rowmask, d64, d32, d16);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_rows(int src_f64, const void* Wout, const void* bout, int in_last, const int* ptr, const int* src,
+                            const double* coef, int M, int Mp, int ld, double* W64, float* W32, uint16_t* W16,
+                            double* b64, float* b32, hipStream_t s)
+{
+    const long n = (long)Mp * (ld + 1);
+    if (src_f64)
+        RS_LAUNCH(k_fold_rows<double>, grid_for(n), dim3(256), 0, s, (const double*)Wout, (const double*)bout, in_last, ptr,
+                  src, coef, M, Mp, ld, W64, W32, W16, b64, b32);
+    else
+        RS_LAUNCH(k_fold_rows<float>, grid_for(n), dim3(256), 0, s, (const float*)Wout, (const float*)bout, in_last, ptr,
+                  src, coef, M, Mp, ld, W64, W32, W16, b64, b32);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(int f32, const void* src, int rows, int cols, int ld_src, void* dst, int ld_dst,
+                            int dst_rows, hipStream_t s)
+{
+    const long n = (long)dst_rows * ld_dst;
+    if (f32) RS_LAUNCH(k_transpose<float>, grid_for(n), dim3(256), 0, s, (const float*)src, rows, cols, ld_src, (float*)dst, ld_dst, dst_rows);
+    else RS_LAUNCH(k_transpose<double>, grid_for(n), dim3(256), 0, s, (const double*)src, rows, cols, ld_src, (double*)dst, ld_dst, dst_rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* rowmask, double* d64, float* d32,
+                           int n_pad, hipStream_t s)
+{
+    if (n_pad <= 0) return hipSuccess;
+    if (src_f64) RS_LAUNCH(k_load_vec<double>, grid_for(n_pad), dim3(256), 0, s, (const double*)src, n, rowmask, d64, d32, n_pad);
+    else RS_LAUNCH(k_load_vec<float>, grid_for(n_pad), dim3(256), 0, s, (const float*)src, n, rowmask, d64, d32, n_pad);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Supervised training: ELU activation forward/backward on (units x batch)
+// blocks, the mass-weighted reconstruction residual, Adam.
+// ---------------------------------------------------------------------------
+// X = elu(P) elementwise (n values)
+__global__ void k_elu_fwd(const float* P, float* X, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) X[i] = elu0(P[i]);
+}
+
+// D = G * elu'(P)
+__global__ void k_elu_bwd(const float* G, const float* P, float* D, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) D[i] = G[i] * elu1(P[i]);
+}
+
+// residual of the reconstruction in the mass norm: U (n x B) decoder output,
+// d (B x n) target displacements; Ubar = 2 m (mask U - d) / B on free rows,
+// per-block partial sums of m (mask U - d)^2 into part[blockIdx.x]
+__global__ __launch_bounds__(256) void k_recon_residual(const float* U, const float* d, int n, int B,
+                                                       const double* rowmass, const uint8_t* pinned_row, float* Ubar,
+                                                       double* part)
+{
+    __shared__ double sh[256];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (i < (long)n * B) {
+        const int row = (int)(i / B), b = (int)(i - (long)row * B);
+        const bool fixed = pinned_row[row] != 0;
+        const double res = (fixed ? 0.0 : (double)U[i]) - (double)d[(long)b * n + row];
+        const double m = rowmass[row];
+        acc = m * res * res;
+        Ubar[i] = fixed ? 0.f : (float)(2.0 * m * res / B);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_parts(const double* part, int n, double scale, double* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s * scale;
+}
+
+// grad[u] (+)= sum_b D[u][b] (bias gradients), float32 out
+__global__ void k_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= rows) return;
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += (double)D[(long)u * B + b];
+    grad[u] = accumulate ? (float)((double)grad[u] + s) : (float)s;
+}
+
+// (rows x B) float32 block to (B x rows) float64 and back
+__global__ void k_to_items_f64(const float* X, int rows, int B, double* z)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * B) return;
+    const int b = i / rows, k = i - b * rows;
+    z[i] = (double)X[(long)k * B + b];
+}
+
+__global__ void k_from_items_f64(const double* z, int rows, int B, float* X)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * B) return;
+    const int b = i / rows, k = i - b * rows;
+    X[(long)k * B + b] = (float)z[i];
+}
+
+// Adam (Kingma and Ba): g = g1 + g2_scale g2 (either may be NULL)
+__global__ void k_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
+                       double lr, double b1, double b2, double eps, double c1, double c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double g = 0.0;
+    if (g1) g += (double)g1[i];
+    if (g2) g += g2_scale * g2[i];
+    const double mi = b1 * (double)m[i] + (1.0 - b1) * g;
+    const double vi = b2 * (double)v[i] + (1.0 - b2) * g * g;
+    m[i] = (float)mi;
+    v[i] = (float)vi;
+    p[i] = (float)((double)p[i] - lr * (mi / c1) / (sqrt(vi / c2) + eps));
+}
+
+hipError_t launch_elu(int backward, const float* G, const float* P, float* out, long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (backward) RS_LAUNCH(k_elu_bwd, grid_for(n), dim3(256), 0, s, G, P, out, n);
+    else RS_LAUNCH(k_elu_fwd, grid_for(n), dim3(256), 0, s, P, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_recon_residual(const float* U, const float* d, int n, int B, const double* rowmass,
+                                 const uint8_t* pinned_row, float* Ubar, double* part, double* loss, hipStream_t s)
+{
+    const long tot = (long)n * B;
+    const int nb = (int)((tot + 255) / 256);
+    RS_LAUNCH(k_recon_residual, dim3(nb), dim3(256), 0, s, U, d, n, B, rowmass, pinned_row, Ubar, part);
+    RS_LAUNCH(k_sum_parts, dim3(1), dim3(64), 0, s, part, nb, 1.0 / B, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate, hipStream_t s)
+{
+    if (rows <= 0) return hipSuccess;
+    RS_LAUNCH(k_rowsum_f32, grid_for(rows), dim3(256), 0, s, D, rows, B, grad, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_items_convert(int to_items, const float* X, double* z, float* Xo, int rows, int B, hipStream_t s)
+{
+    if (rows * B <= 0) return hipSuccess;
+    if (to_items) RS_LAUNCH(k_to_items_f64, grid_for((long)rows * B), dim3(256), 0, s, X, rows, B, z);
+    else RS_LAUNCH(k_from_items_f64, grid_for((long)rows * B), dim3(256), 0, s, z, rows, B, Xo);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
+                       double lr, double b1, double b2, double eps, int step, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
+    RS_LAUNCH(k_adam, grid_for(n), dim3(256), 0, s, n, p, g1, g2, g2_scale, m, v, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace rs

@@ -193,7 +193,8 @@ def test_newton_float32_c2_stationary_for_oracle():
     g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
     Eg, gg, _ = o.reduced(r["z"], tg, fo)
     conv = r["status"] == rb.CONVERGED
-    assert np.all(np.abs(gg[conv]).max(axis=1) <= 1e-4 * g0[conv])
+    # 1e-6 on the float32 gradient plus its measured noise floor (5e-7 of |g_0|)
+    assert np.all(np.abs(gg[conv]).max(axis=1) <= 1.5e-6 * g0[conv])
     # its reported energy is the float64 energy of that point
     assert relerr(r["E"][:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
     # and it is no worse than the oracle's own solve from the same start, up to local minima
@@ -299,14 +300,31 @@ def test_lipschitz(name, prec):
     z2[3] = z1[3]
     ctx = rb.Context(p, prec=prec, max_batch=4)  # 2 pairs per pass: 3 chunks
     res = ctx.lipschitz_loss(t64(z1), t64(z2))
-    ores = O.Oracle(p).lipschitz(z1, z2)
+    o = O.Oracle(p)
+    ores = o.lipschitz(z1, z2)
     tol = TOL[prec]
     assert res["n_valid"].item() == ores["n_valid"] == B - 1
     per = res["per_pair"].cpu().numpy()
     assert per[3] == 0.0
-    assert relerr(per[:, None], ores["per_pair"][:, None], tau=1e-300).max() < 10 * tol
-    assert abs(res["loss"].item() - ores["loss"]) <= 10 * tol * ores["loss"]
-    assert abs(res["lip_max"].item() - ores["lip_max"]) <= 10 * tol * ores["lip_max"]
+    # Bars derived from the Hessian's: with |H_gpu(z) - H(z)|_F <= tol |H(z)|_F at
+    # both points of a pair, e_H = tol (|H1|_F + |H2|_F) bounds the error of
+    # D = H1 - H2, and | |a|^2 - |b|^2 | <= |a - b| (2 |b| + |a - b|) gives
+    # |l_gpu - l| <= (2 e_H |D|_F + e_H^2) / |dz|^2 per pair; the mean takes the
+    # mean bound and sqrt(l) (the max-pair estimator) moves by at most e_H / |dz|.
+    fl = O.EXACT | O.ELASTIC_ONLY
+    H1 = o.reduced(z1, flags=fl)[2].reshape(B, -1)
+    H2 = o.reduced(z2, flags=fl)[2].reshape(B, -1)
+    n1, n2, nd = (np.linalg.norm(a, axis=1) for a in (H1, H2, H1 - H2))
+    dz = np.linalg.norm(z1 - z2, axis=1)
+    valid = dz > 0
+    eH = tol * (n1 + n2)
+    bound = np.zeros(B)
+    bound[valid] = (2 * eH[valid] * nd[valid] + eH[valid] ** 2) / dz[valid] ** 2
+    assert np.all(np.abs(per - ores["per_pair"]) <= bound)
+    assert abs(res["loss"].item() - ores["loss"]) <= bound[valid].mean()
+    assert abs(res["lip_max"].item() - ores["lip_max"]) <= (eH[valid] / dz[valid]).max()
+    # for pairs this far apart the bars are a few tol relative, not vacuous
+    assert np.all(bound[valid] <= 50 * tol * ores["per_pair"][valid])
 
 
 # ------------------------------------------------------------------- BF16 decoder
@@ -583,7 +601,8 @@ def test_lbfgs_float32_c2_stationary_for_oracle():
     g0 = np.abs(o.reduced(z0, tg, fo)[1]).max(axis=1)
     Eg, gg, _ = o.reduced(r["z"], tg, fo)
     conv = r["status"] == rb.CONVERGED
-    assert np.all(np.abs(gg[conv]).max(axis=1) <= 1e-4 * g0[conv])
+    # 1e-6 on the float32 reverse-mode gradient plus the float32 noise floor (5e-7 of |g_0|)
+    assert np.all(np.abs(gg[conv]).max(axis=1) <= 1.5e-6 * g0[conv])
     assert relerr(r["E"][:, None], Eg[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
 
 
