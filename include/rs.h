@@ -295,6 +295,40 @@ int rs_lipschitz_loss(rs_ctx* ctx, int32_t B, const double* z1, const double* z2
                       double* loss, double* per_pair, int32_t* n_valid, double* lip_max,
                       void* stream);
 
+/* Replace the decoder weights from a DEVICE buffer, stream-ordered (no host
+ * round trip, no synchronisation): theta holds rs_param_count values packed as
+ * rs_energy_param_grad's gradient (W_1, b_1, ..., W_L, b_L, W_out, b_out, each
+ * W row-major out x in), float64 when theta_f64 != 0, else float32.  The
+ * context converts them to its precision (round to nearest even for BF16
+ * products) and rebuilds the output-layer fold onto the reduced rows, as
+ * rs_set_decoder does from host arrays.  The learned part (Sec. 4.2, Eq.
+ * form-unconstrained-lipschitz-optimization) reloads the decoder after every
+ * optimiser step this way.  theta must stay valid until the work enqueued on
+ * `stream` has run; later calls on other streams must be ordered after it by
+ * the caller.  Errors: RS_ERR_STATE (NULL ctx), RS_ERR_ARG (NULL theta),
+ * RS_ERR_HIP (launch failure). */
+int rs_set_decoder_device(rs_ctx* ctx, const void* theta, int32_t theta_f64, void* stream);
+
+/* Gradient of the Lipschitz loss (Sec. 4.1, Eq. form-L-LS-E, on the cubature
+ * elastic Hessian of Sec. 4.3) with respect to every decoder parameter, the
+ * latent pairs held fixed:
+ *   loss = mean over pairs with z1_b != z2_b of |H(z1_b) - H(z2_b)|_F^2 / |z1_b - z2_b|^2,
+ *   grad = d loss / d theta, packed as rs_energy_param_grad's gradient,
+ * with H the exact reduced Hessian of the weighted cubature elastic energy
+ * (RS_HESS_EXACT | RS_ELASTIC_ONLY).  The derivative is carried forward through
+ * the decoder as value, Jacobian and C-contracted second-derivative columns
+ * (C = 2 sym(H1 - H2) / (|dz|^2 n_valid)) and taken back by reverse mode, with
+ * the hidden activations recomputed from kept pre-activations; the element
+ * term needs the third derivatives of the stable Neo-Hookean energy.  z1, z2
+ * (B x r) float64 device; loss (1) and grad (rs_param_count) float64 device,
+ * overwritten; B = 0 or no valid pair gives zeros.  Float32 and float64
+ * contexts with max_batch >= 2.  The first call allocates the pass workspace
+ * (up to 128 pairs per pass) and keeps it in the context.  Errors:
+ * RS_ERR_STATE, RS_ERR_ARG (B < 0, NULL pointers), RS_ERR_UNSUPPORTED (BF16
+ * context, max_batch < 2), RS_ERR_OOM (workspace). */
+int rs_lipschitz_param_grad(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
+                            double* grad, void* stream);
+
 /* Message of the last error on this context ("" if none); a static message
  * when ctx is NULL. */
 const char* rs_last_error(const rs_ctx* ctx);

@@ -81,7 +81,7 @@ class Info(C.Structure):
 SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy", "rs_set_decoder",
            "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
            "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
-           "rs_energy_param_grad", "rs_set_elem_hess_dump"]
+           "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad"]
 
 _lib = None
 
@@ -118,6 +118,9 @@ def load_library():
         L.rs_energy_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.c_uint32,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_set_elem_hess_dump.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+        L.rs_set_decoder_device.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
+        L.rs_lipschitz_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -257,9 +260,34 @@ class Context:
         return out
 
     def set_decoder_flat(self, theta):
-        """Load the decoder from a packed parameter vector (any device; copied to the host)."""
-        parts = self.unpack_params(theta.detach().to("cpu", torch.float64))
+        """Load the decoder from a packed parameter vector: a float32 or float64
+        device tensor is loaded on the GPU (stream-ordered), anything else is
+        copied to the host and loaded from there."""
+        if isinstance(theta, torch.Tensor) and theta.is_cuda:
+            self.set_decoder_device(theta)
+            return
+        parts = self.unpack_params(torch.as_tensor(theta).detach().to("cpu", torch.float64))
         self.set_decoder([W.numpy() for W, _ in parts], [b.numpy() for _, b in parts])
+
+    def set_decoder_device(self, theta):
+        """Load the decoder from a packed float32/float64 device tensor (rs_set_decoder_device)."""
+        if theta.dtype not in (torch.float32, torch.float64):
+            raise TypeError("theta must be float32 or float64")
+        _dev(theta, theta.dtype, (self.param_count(),), "theta")
+        self._check(load_library().rs_set_decoder_device(self.ctx, _ptr(theta), int(theta.dtype == torch.float64),
+                                                         _stream()), "rs_set_decoder_device")
+
+    def lipschitz_param_grad(self, z1, z2):
+        """(loss (1), grad): the Lipschitz loss over the pairs (z1_b, z2_b) and its
+        gradient with respect to the packed decoder parameters (float64 device tensors)."""
+        B = z1.shape[0]
+        _dev(z1, torch.float64, (B, self.r), "z1")
+        _dev(z2, torch.float64, (B, self.r), "z2")
+        loss = torch.empty(1, dtype=torch.float64, device=z1.device)
+        grad = torch.empty(self.param_count(), dtype=torch.float64, device=z1.device)
+        self._check(load_library().rs_lipschitz_param_grad(self.ctx, B, _ptr(z1), _ptr(z2), _ptr(loss), _ptr(grad),
+                                                           _stream()), "rs_lipschitz_param_grad")
+        return loss, grad
 
     def energy_param_grad(self, z, targets=None, force=None, flags=0, want_E=True, want_g=True):
         """(E (B), g = dE/dz (B x r), grad) with grad the packed gradient of sum_b E(z_b)
