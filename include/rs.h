@@ -329,6 +329,23 @@ int rs_set_decoder_device(rs_ctx* ctx, const void* theta, int32_t theta_f64, voi
 int rs_lipschitz_param_grad(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
                             double* grad, void* stream);
 
+/* rs_lipschitz_param_grad for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving or training loops, harnesses
+ * that forbid hipMalloc): the same arguments, results and errors, but the pass
+ * workspace is carved from a static device array of RS_STATIC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process ends,
+ * instead of being allocated by the first call.  It makes as many pairs per pass
+ * as that array holds (at most the allocating variant's 128), so results can
+ * differ from rs_lipschitz_param_grad's by the order of the float64 sums over
+ * passes.  Calls that overlap on one device (any context, any stream) share the
+ * array and race; the caller orders them.  Nothing has to be cleared between
+ * calls: every pass overwrites what it reads.  Errors: as
+ * rs_lipschitz_param_grad, and RS_ERR_UNSUPPORTED when one pair's workspace
+ * exceeds the array (the message gives both sizes). */
+#define RS_STATIC_SCRATCH_BYTES (64u << 20)
+int rs_lipschitz_param_grad_noalloc(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
+                                    double* grad, void* stream);
+
 /* Message of the last error on this context ("" if none); a static message
  * when ctx is NULL. */
 const char* rs_last_error(const rs_ctx* ctx);

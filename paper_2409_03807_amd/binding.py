@@ -81,7 +81,8 @@ class Info(C.Structure):
 SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy", "rs_set_decoder",
            "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
            "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
-           "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad"]
+           "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
+           "rs_lipschitz_param_grad_noalloc"]
 
 _lib = None
 
@@ -121,6 +122,7 @@ def load_library():
         L.rs_set_decoder_device.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.rs_lipschitz_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p]
+        L.rs_lipschitz_param_grad_noalloc.argtypes = L.rs_lipschitz_param_grad.argtypes
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -277,16 +279,24 @@ class Context:
         self._check(load_library().rs_set_decoder_device(self.ctx, _ptr(theta), int(theta.dtype == torch.float64),
                                                          _stream()), "rs_set_decoder_device")
 
-    def lipschitz_param_grad(self, z1, z2):
+    def lipschitz_param_grad(self, z1, z2, out=None, noalloc=False):
         """(loss (1), grad): the Lipschitz loss over the pairs (z1_b, z2_b) and its
-        gradient with respect to the packed decoder parameters (float64 device tensors)."""
+        gradient with respect to the packed decoder parameters (float64 device tensors).
+        `out` may pass preallocated (loss, grad); noalloc=True calls the variant whose
+        workspace is the library's static device array."""
         B = z1.shape[0]
         _dev(z1, torch.float64, (B, self.r), "z1")
         _dev(z2, torch.float64, (B, self.r), "z2")
-        loss = torch.empty(1, dtype=torch.float64, device=z1.device)
-        grad = torch.empty(self.param_count(), dtype=torch.float64, device=z1.device)
-        self._check(load_library().rs_lipschitz_param_grad(self.ctx, B, _ptr(z1), _ptr(z2), _ptr(loss), _ptr(grad),
-                                                           _stream()), "rs_lipschitz_param_grad")
+        if out is None:
+            loss = torch.empty(1, dtype=torch.float64, device=z1.device)
+            grad = torch.empty(self.param_count(), dtype=torch.float64, device=z1.device)
+        else:
+            loss, grad = out
+            _dev(loss, torch.float64, (1,), "loss")
+            _dev(grad, torch.float64, (self.param_count(),), "grad")
+        fn = "rs_lipschitz_param_grad_noalloc" if noalloc else "rs_lipschitz_param_grad"
+        self._check(getattr(load_library(), fn)(self.ctx, B, _ptr(z1), _ptr(z2), _ptr(loss), _ptr(grad), _stream()),
+                    fn)
         return loss, grad
 
     def energy_param_grad(self, z, targets=None, force=None, flags=0, want_E=True, want_g=True):

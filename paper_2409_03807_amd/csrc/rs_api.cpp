@@ -140,6 +140,7 @@ struct rs_ctx {
     // learned-part workspace, grown on demand by the training calls
     std::vector<void*> learn_bufs;
     LipWs lip;                    // Lipschitz-loss gradient workspace (allocated by its first call)
+    void* scratch = nullptr;      // device address of this device's static scratch array
     int* fold_ptr = nullptr;      // n_out + 1: CSR of the output-layer fold by W_out row
     int* fold_row = nullptr;      // W_big row of each entry
     double* fold_coef = nullptr;  // its coefficient
@@ -541,6 +542,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     if (nt < 0 || nf < 0 || (nt && !con->target_vtx) || (nf && !con->force_vtx))
         return bail(fail(c, RS_ERR_ARG, "bad constraints"));
 
+    {
+        // the device address of this device's static scratch array (allocation-free entry points)
+        const hipError_t e = static_scratch_address(&c->scratch);
+        if (e != hipSuccess) return bail(hip_fail(c, e, "hipGetSymbolAddress(scratch)"));
+    }
     c->prec = prec;
     c->f32 = prec != RS_PREC_F64;
     c->bf16 = prec == RS_PREC_BF16;
@@ -1776,28 +1782,46 @@ static void* learn_alloc(rs_ctx* c, size_t bytes)
     return p;
 }
 
+// Lay the pass workspace of `pairs` pairs out in one block at `base` (NULL
+// only measures); returns its size in bytes.  Every part starts on 256 bytes.
+static size_t lip_ws_layout(const rs_ctx* c, int pairs, char* base, LipWs& ws)
+{
+    ws = LipWs{};
+    ws.pairs = pairs;
+    const size_t items = 2 * (size_t)pairs, cols = items * (c->r + 2), ts = c->tsz;
+    const size_t wr = (size_t)std::max(c->w, c->r);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        return p;
+    };
+    for (int l = 0; l < c->L; ++l) ws.Pre[l] = take((size_t)c->w * cols * ts);
+    ws.X0 = take((size_t)c->r * cols * ts);
+    ws.X = take(wr * cols * ts);
+    ws.Out = take((size_t)9 * c->S * cols * ts);
+    ws.Seed = take((size_t)9 * c->S * cols * ts);
+    ws.G[0] = take(wr * cols * ts);
+    ws.G[1] = take(wr * cols * ts);
+    ws.D = take(wr * cols * ts);
+    ws.Cs = static_cast<double*>(take(items * c->r * c->r * sizeof(double)));
+    ws.nvalid = static_cast<int*>(take(sizeof(int)));
+    return off;
+}
+
+static int lip_pairs_cap(const rs_ctx* c) { return std::max(1, std::min(128, c->max_batch / 2)); }
+
 static int lip_ws(rs_ctx* c, LipWs& ws)
 {
     if (c->lip.pairs > 0) {
         ws = c->lip;
         return RS_OK;
     }
-    ws = LipWs{};
-    ws.pairs = std::max(1, std::min(128, c->max_batch / 2));
-    const size_t items = 2 * (size_t)ws.pairs, cols = items * (c->r + 2), ts = c->tsz;
-    const size_t wr = (size_t)std::max(c->w, c->r);
-    bool ok = true;
-    for (int l = 0; l < c->L; ++l) ok = ok && (ws.Pre[l] = learn_alloc(c, (size_t)c->w * cols * ts));
-    ok = ok && (ws.X0 = learn_alloc(c, (size_t)c->r * cols * ts));
-    ok = ok && (ws.X = learn_alloc(c, wr * cols * ts));
-    ok = ok && (ws.Out = learn_alloc(c, (size_t)9 * c->S * cols * ts));
-    ok = ok && (ws.Seed = learn_alloc(c, (size_t)9 * c->S * cols * ts));
-    ok = ok && (ws.G[0] = learn_alloc(c, wr * cols * ts));
-    ok = ok && (ws.G[1] = learn_alloc(c, wr * cols * ts));
-    ok = ok && (ws.D = learn_alloc(c, wr * cols * ts));
-    ok = ok && (ws.Cs = (double*)learn_alloc(c, items * c->r * c->r * sizeof(double)));
-    ok = ok && (ws.nvalid = (int*)learn_alloc(c, sizeof(int)));
-    if (!ok) return fail(c, RS_ERR_OOM, "training workspace allocation failed");
+    const int pairs = lip_pairs_cap(c);
+    const size_t bytes = lip_ws_layout(c, pairs, nullptr, ws);
+    char* base = static_cast<char*>(learn_alloc(c, bytes));
+    if (!base) return fail(c, RS_ERR_OOM, "training workspace allocation failed");
+    lip_ws_layout(c, pairs, base, ws);
     c->lip = ws;
     return RS_OK;
 }
@@ -1859,19 +1883,22 @@ extern "C" int rs_set_decoder_device(rs_ctx* c, const void* theta, int32_t theta
     return RS_OK;
 }
 
-extern "C" int rs_lipschitz_param_grad(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,
-                                       double* grad, void* stream)
+static int lip_grad_check(rs_ctx* c, int32_t B, const double* z1, const double* z2, const double* loss,
+                          const double* grad)
 {
-    if (!c) return RS_ERR_STATE;
     if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
     if (!loss || !grad || (B > 0 && (!z1 || !z2))) return fail(c, RS_ERR_ARG, "NULL pointer");
     if (c->bf16) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz-loss gradient needs a float32 or float64 context");
     if (c->max_batch < 2) return fail(c, RS_ERR_UNSUPPORTED, "the Lipschitz-loss gradient needs max_batch >= 2");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    return RS_OK;
+}
+
+// The Lipschitz-loss gradient over B pairs with the pass workspace ws (ws.pairs pairs per pass).
+static int lip_param_grad(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss, double* grad,
+                          const LipWs& ws, hipStream_t s)
+{
     const int r = c->r, L = c->L, w = c->w, f32 = c->f32, nc2 = r + 2, S9 = 9 * c->S;
     c->cur_slot = -1;
-    LipWs ws;
-    RS_TRY(lip_ws(c, ws));
     const int chunk = ws.pairs;
     RS_TRY(run(c, K_LIP_GRAD, Work{}, s, [&] { return launch_fill_zero(grad, c->n_params, s); }));
     RS_HIP(launch_fill_zero(c->dWbig, (size_t)c->M * c->in_last, s), "fill");
@@ -1963,6 +1990,36 @@ extern "C" int rs_lipschitz_param_grad(rs_ctx* c, int32_t B, const double* z1, c
         return launch_unfold(c->dWbig, c->dbbig, c->in_last, c->fold_ptr, c->fold_row, c->fold_coef, c->n_out,
                              grad + c->offW[L], grad + c->offb[L], s);
     });
+}
+
+extern "C" int rs_lipschitz_param_grad(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,
+                                       double* grad, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    RS_TRY(lip_grad_check(c, B, z1, z2, loss, grad));
+    LipWs ws;
+    RS_TRY(lip_ws(c, ws));
+    return lip_param_grad(c, B, z1, z2, loss, grad, ws, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int rs_lipschitz_param_grad_noalloc(rs_ctx* c, int32_t B, const double* z1, const double* z2,
+                                               double* loss, double* grad, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    RS_TRY(lip_grad_check(c, B, z1, z2, loss, grad));
+    if (!c->scratch) return fail(c, RS_ERR_STATE, "the static scratch array of this device is not set up");
+    // as many pairs per pass as the static array holds, at most the allocating variant's
+    LipWs ws;
+    int pairs = lip_pairs_cap(c);
+    while (pairs > 0 && lip_ws_layout(c, pairs, nullptr, ws) > kStaticScratchBytes) --pairs;
+    if (pairs == 0) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "one pair needs %zu bytes of scratch, more than the static %zu",
+                      lip_ws_layout(c, 1, nullptr, ws), kStaticScratchBytes);
+        return fail(c, RS_ERR_UNSUPPORTED, msg);
+    }
+    lip_ws_layout(c, pairs, static_cast<char*>(c->scratch), ws);
+    return lip_param_grad(c, B, z1, z2, loss, grad, ws, static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------------ profiling

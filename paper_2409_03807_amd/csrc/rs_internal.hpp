@@ -19,6 +19,12 @@ constexpr int kLsCand = 8;   // step lengths evaluated per line-search round aft
 constexpr int kMaxL = 8;     // largest number of hidden layers
 constexpr int kMaxSplit = 16;// largest split of the adjoint GEMM's reduction
 constexpr int kMaxWidth = 256;// widest hidden layer
+// size of the static device scratch array of the allocation-free entry points
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+
+// Device address of the current device's static scratch array (kStaticScratchBytes),
+// looked up once per device with hipGetSymbolAddress and cached.
+hipError_t static_scratch_address(void** ptr);
 
 // IN_RAW: item-major (y_rows x nc) blocks; IN_RAW_T: item-major (nc x y_rows)
 // blocks (k contiguous, the layout of a layer activation); IN_ELU: IN_RAW

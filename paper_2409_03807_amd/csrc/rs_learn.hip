@@ -22,6 +22,8 @@
 // bilinear form with cofd(X, X) = 2 cof X (the second derivative of det).
 #include "rs_device.hpp"
 
+#include <mutex>
+
 namespace rs {
 
 // ---------------------------------------------------------------------------
@@ -436,6 +438,37 @@ hipError_t launch_value_rowsum(int f32, const void* D, long ldd, int rows, int i
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Static scratch of the allocation-free entry points.  Each device holds its own
+// copy from module load to process end.  In host code `scratch` is a host-side
+// stand-in for the symbol, never a device address: kernels and copies take the
+// address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch_address(void** ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = p;
+    }
+    *ptr = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Device-side decoder load: packed parameters (float32 or float64) into the
