@@ -346,6 +346,66 @@ int rs_lipschitz_param_grad(rs_ctx* ctx, int32_t B, const double* z1, const doub
 int rs_lipschitz_param_grad_noalloc(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
                                     double* grad, void* stream);
 
+/* ---- supervised training of the subspace (the learned part) ----
+ * An autoencoder (Sec. 3.2, Eq. form-vanilla-supervised-construction): an ELU
+ * encoder g: displacements (3 nv) -> r, and the context's decoder f.  One
+ * gradient call on a batch of snapshot displacements d_b = q_b - X takes
+ *   L_C  = mean_b |m (.) f(g(d_b)) - d_b|_M^2      (lumped masses M; m masks pinned rows)
+ *   L_LS = the Lipschitz loss of the decoder (Sec. 4.1, Eq. form-L-LS-E) over the
+ *          pairs (z_2p, z_2p+1), p < n_pairs, of the batch's encodings z_b = g(d_b),
+ *          which are held fixed (the samples of the pull-back distribution, Sec. 4.2)
+ * and the gradients of L_C + lambda_ls L_LS (Sec. 4.2, Eq.
+ * form-unconstrained-lipschitz-optimization) with respect to the encoder and
+ * decoder parameters, by hand-written reverse mode on the matrix cores.  Adam
+ * (Kingma and Ba) then updates both networks and reloads the context's
+ * decoder on the GPU (rs_set_decoder_device), so reduced solves on the context
+ * use the trained subspace.  Parameters and activations are in the context
+ * precision (float32 or float64); losses, bias sums and the Lipschitz
+ * gradient are float64.  The trainer belongs to its context and must be
+ * destroyed before it; one trainer per context at a time. */
+typedef struct {
+    int32_t n_in;        /* input size (3 nv for an encoder) */
+    int32_t n_hidden;    /* ELU hidden layers (0..8) */
+    int32_t width;       /* units per hidden layer */
+    int32_t n_out;       /* output size (r for an encoder), linear */
+    const double* const* W;  /* host, W[l] (out x in) row-major, l = 0..n_hidden */
+    const double* const* b;
+} rs_mlp;
+
+typedef struct rs_trainer rs_trainer;
+
+/* Create a trainer for ctx (float32 or float64, with hidden layers) from host
+ * initial weights of the encoder (n_in = 3 nv, n_out = r) and of the decoder
+ * (the context's shape); the context's decoder is replaced by `dec`.
+ * max_batch (>= 2) bounds B of rs_trainer_grad.  Allocates its workspace here;
+ * synchronous.  Errors: RS_ERR_STATE, RS_ERR_ARG (shapes, NULL pointers),
+ * RS_ERR_UNSUPPORTED (BF16 context, linear decoder, encoder deeper than 8 or
+ * wider than 4096), RS_ERR_OOM. */
+int rs_trainer_create(rs_ctx* ctx, const rs_mlp* encoder, const rs_decoder* dec, int32_t max_batch,
+                      rs_trainer** out);
+int rs_trainer_destroy(rs_trainer* t);
+/* Sizes of the packed encoder parameters (W_1, b_1, ..., W_out, b_out, each W
+ * row-major out x in) and decoder parameters (as rs_param_count). */
+int rs_trainer_param_count(const rs_trainer* t, int64_t* n_enc, int64_t* n_dec);
+/* Copy the current parameters (context precision) into device buffers (either may be NULL). */
+int rs_trainer_params(rs_trainer* t, void* enc, void* dec, void* stream);
+/* Encodings z (B x r, float64 device) of rows idx[b] (device int32, NULL = rows
+ * 0..B-1) of the snapshot store (N x 3 nv displacements, context precision,
+ * device).  Any B >= 0. */
+int rs_trainer_encode(rs_trainer* t, int32_t B, const void* store, const int32_t* idx, double* z, void* stream);
+/* Losses and gradients of one batch: rows idx[b] of `store` (as rs_trainer_encode),
+ * 1 <= B <= max_batch.  lambda_ls = 0 skips the Lipschitz term; otherwise
+ * 1 <= n_pairs <= B/2.  losses (2, float64 device: L_C, L_LS), grad_enc
+ * (n_enc) and grad_dec (n_dec, the gradient of L_C + lambda_ls L_LS), float64
+ * device, may each be NULL; the trainer keeps its own copies for
+ * rs_trainer_adam.  Errors: RS_ERR_STATE, RS_ERR_ARG. */
+int rs_trainer_grad(rs_trainer* t, int32_t B, const void* store, const int32_t* idx, double lambda_ls,
+                    int32_t n_pairs, double* losses, double* grad_enc, double* grad_dec, void* stream);
+/* One Adam step of both networks with the gradients of the last
+ * rs_trainer_grad call (bias-corrected moments, step counted by the trainer),
+ * then the context's decoder is reloaded from the new parameters. */
+int rs_trainer_adam(rs_trainer* t, double lr, double beta1, double beta2, double eps, void* stream);
+
 /* Message of the last error on this context ("" if none); a static message
  * when ctx is NULL. */
 const char* rs_last_error(const rs_ctx* ctx);

@@ -52,6 +52,11 @@ class _Constraints(C.Structure):
                 ("n_force", C.c_int32), ("force_vtx", _ip)]
 
 
+class _Mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("width", C.c_int32), ("n_out", C.c_int32),
+                ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp))]
+
+
 class _Load(C.Structure):
     _fields_ = [("targets", C.c_void_p), ("force", C.c_void_p)]
 
@@ -82,7 +87,8 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_get_info", "rs_decode", "rs_energy_grad_hess", "rs_newton_solve", "rs_lbfgs_solve",
            "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
-           "rs_lipschitz_param_grad_noalloc"]
+           "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
+           "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam"]
 
 _lib = None
 
@@ -123,6 +129,15 @@ def load_library():
         L.rs_lipschitz_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p]
         L.rs_lipschitz_param_grad_noalloc.argtypes = L.rs_lipschitz_param_grad.argtypes
+        L.rs_trainer_create.argtypes = [C.c_void_p, C.POINTER(_Mlp), C.POINTER(_Decoder), C.c_int32,
+                                        C.POINTER(C.c_void_p)]
+        L.rs_trainer_destroy.argtypes = [C.c_void_p]
+        L.rs_trainer_param_count.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.rs_trainer_params.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_trainer_encode.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_trainer_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.rs_trainer_adam.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -424,6 +439,95 @@ class Context:
                                          C.byref(fl)), "rs_profile_get")
             if la.value:
                 out[name.value.decode()] = dict(launches=la.value, ms=ms.value, bytes=by.value, flops=fl.value)
+        return out
+
+
+class Trainer:
+    """The supervised autoencoder trainer of a context (rs_trainer_*): an ELU
+    encoder (Ws, bs: host float64 arrays, W (out x in)) and the context's decoder,
+    trained on a device store of snapshot displacements (N x 3 nv, context dtype)."""
+
+    def __init__(self, ctx: Context, enc_Ws, enc_bs, dec_Ws, dec_bs, max_batch: int = 128):
+        L = load_library()
+        self.ctx = ctx
+        keep = []
+        Ws = [np.ascontiguousarray(W, dtype=np.float64) for W in enc_Ws]
+        bs = [np.ascontiguousarray(b, dtype=np.float64) for b in enc_bs]
+        keep.extend(Ws); keep.extend(bs)
+        Wp = (_dp * len(Ws))(*[W.ctypes.data_as(_dp) for W in Ws])
+        bp = (_dp * len(bs))(*[b.ctypes.data_as(_dp) for b in bs])
+        keep.extend([Wp, bp])
+        mlp = _Mlp(Ws[0].shape[1], len(Ws) - 1, Ws[0].shape[0] if len(Ws) > 1 else 0, Ws[-1].shape[0],
+                   C.cast(Wp, C.POINTER(_dp)), C.cast(bp, C.POINTER(_dp)))
+        dec = ctx._decoder_struct(dec_Ws, dec_bs, keep)
+        t = C.c_void_p()
+        ctx._check(L.rs_trainer_create(ctx.ctx, C.byref(mlp), C.byref(dec), max_batch, C.byref(t)),
+                   "rs_trainer_create")
+        self.t = t
+        self.max_batch = max_batch
+        self.enc_shapes = [(W.shape, b.shape) for W, b in zip(Ws, bs)]
+        ne, nd = C.c_int64(), C.c_int64()
+        ctx._check(L.rs_trainer_param_count(t, C.byref(ne), C.byref(nd)), "rs_trainer_param_count")
+        self.n_enc, self.n_dec = ne.value, nd.value
+
+    def close(self):
+        if getattr(self, "t", None) is not None and _lib is not None:
+            _lib.rs_trainer_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        self.close()
+
+    def _store(self, store, idx, B):
+        _dev(store, self.ctx.tdtype, None, "store")
+        if store.dim() != 2 or store.shape[1] != self.ctx.n:
+            raise ValueError("store must be (N, 3 nv)")
+        if idx is not None:
+            _dev(idx, torch.int32, None, "idx")
+            B = idx.shape[0] if B is None else B
+        elif B is None:
+            B = store.shape[0]
+        if idx is None and B > store.shape[0]:
+            raise ValueError("B exceeds the store")
+        return B
+
+    def encode(self, store, idx=None, B=None):
+        B = self._store(store, idx, B)
+        z = torch.empty((B, self.ctx.r), dtype=torch.float64, device=store.device)
+        self.ctx._check(load_library().rs_trainer_encode(self.t, B, _ptr(store), _ptr(idx), _ptr(z), _stream()),
+                        "rs_trainer_encode")
+        return z
+
+    def grad(self, store, idx=None, B=None, lambda_ls=0.0, n_pairs=0, want_grads=False, losses=None):
+        """Losses (2: L_C, L_LS) and, with want_grads, float64 gradients (encoder, decoder)."""
+        B = self._store(store, idx, B)
+        dev = store.device
+        if losses is None:
+            losses = torch.empty(2, dtype=torch.float64, device=dev)
+        ge = torch.empty(self.n_enc, dtype=torch.float64, device=dev) if want_grads else None
+        gd = torch.empty(self.n_dec, dtype=torch.float64, device=dev) if want_grads else None
+        self.ctx._check(load_library().rs_trainer_grad(self.t, B, _ptr(store), _ptr(idx), float(lambda_ls),
+                                                       int(n_pairs), _ptr(losses), _ptr(ge), _ptr(gd), _stream()),
+                        "rs_trainer_grad")
+        return losses, ge, gd
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx._check(load_library().rs_trainer_adam(self.t, lr, beta1, beta2, eps, _stream()), "rs_trainer_adam")
+
+    def params(self):
+        """(encoder, decoder) packed parameters, context dtype, device."""
+        dev = self.ctx.device
+        e = torch.empty(self.n_enc, dtype=self.ctx.tdtype, device=dev)
+        d = torch.empty(self.n_dec, dtype=self.ctx.tdtype, device=dev)
+        self.ctx._check(load_library().rs_trainer_params(self.t, _ptr(e), _ptr(d), _stream()), "rs_trainer_params")
+        return e, d
+
+    def unpack_encoder(self, flat):
+        out, off = [], 0
+        for ws, bsh in self.enc_shapes:
+            nw, nb = ws[0] * ws[1], bsh[0]
+            out.append((flat[off:off + nw].reshape(ws), flat[off + nw:off + nw + nb]))
+            off += nw + nb
         return out
 
 

@@ -2022,6 +2022,462 @@ extern "C" int rs_lipschitz_param_grad_noalloc(rs_ctx* c, int32_t B, const doubl
     return lip_param_grad(c, B, z1, z2, loss, grad, ws, static_cast<hipStream_t>(stream));
 }
 
+// ------------------------------------------------------------------ supervised training
+// The autoencoder of the supervised construction (Sec. 3.2, Eq.
+// form-vanilla-supervised-construction): an ELU encoder n -> r and the
+// context's decoder, trained on snapshot displacements with the
+// reconstruction loss in the mass norm, plus lambda times the Lipschitz loss
+// of the decoder over pairs of the batch's encodings (Sec. 4.2, Eq.
+// form-unconstrained-lipschitz-optimization).  Activations are (units x batch)
+// blocks; every product runs on the strided matrix-core GEMM.
+struct rs_trainer {
+    rs_ctx* c = nullptr;
+    int f32 = 1;
+    size_t ts = 4;
+    int n = 0, r = 0;                 // decoder output rows (encoder input), latent size
+    int Le = 0, we = 0;               // encoder hidden layers and width
+    int L = 0, w = 0, in_last = 0;    // decoder hidden layers, width, input of its output layer
+    int max_batch = 0;
+    std::vector<size_t> eW, eb;       // packed offsets of the encoder layers
+    size_t n_enc = 0, n_dec = 0;
+    void* enc = nullptr;              // parameters, context precision
+    void* dec = nullptr;
+    void* genc = nullptr;             // gradients of the reconstruction loss
+    void* gdec = nullptr;
+    double* glip = nullptr;           // gradient of the Lipschitz loss (float64)
+    double lambda = 0.0;              // lambda of the last gradient call (0: glip unused)
+    void *m_enc = nullptr, *v_enc = nullptr, *m_dec = nullptr, *v_dec = nullptr;
+    int step = 0;
+    void* Dt = nullptr;               // n x Bm batch displacements
+    void* Pe[kMaxL + 1] = {};         // encoder pre-activations (last: the encodings, r x Bm)
+    void* Xe[kMaxL + 1] = {};         // encoder activations (Xe[0] unused: Dt)
+    void* Pd[kMaxL] = {};             // decoder pre-activations
+    void* Hd[kMaxL + 1] = {};         // decoder activations (Hd[0] aliases the encodings)
+    void* U = nullptr;                // n x Bm decoder output
+    void* Ubar = nullptr;             // its adjoint
+    void* G[2] = {};                  // adjoints of layer outputs, max(we, w, r) x Bm
+    void* D = nullptr;                // adjoints of pre-activations
+    void* part = nullptr;             // split-K partial sums
+    size_t part_elems = 0;
+    double* rpart = nullptr;          // residual partial sums
+    double* zs = nullptr;             // Bm x r encodings (float64)
+    double* z1 = nullptr;
+    double* z2 = nullptr;
+    double* losses = nullptr;         // [L_C, L_LS] of the last gradient call
+    std::vector<void*> bufs;
+};
+
+static void* tr_alloc(rs_trainer* t, size_t bytes)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) return nullptr;
+    t->bufs.push_back(p);
+    return p;
+}
+
+static void tr_free(rs_trainer* t)
+{
+    for (void* p : t->bufs) (void)hipFree(p);
+    delete t;
+}
+
+static inline void* at_off(void* base, size_t off, size_t ts) { return static_cast<char*>(base) + off * ts; }
+
+// C (M x N, row-major, ldc) (+)= A B (+ bias), with a K split when few tiles meet a long reduction
+static int tr_gemm(rs_trainer* t, const void* A, long sAm, long sAk, const void* B, long sBk, long sBn, void* C,
+                   long ldc, int M, int N, int K, int accumulate, const void* bias, hipStream_t s)
+{
+    rs_ctx* c = t->c;
+    SgemmArgs g{};
+    g.A = A; g.sAm = sAm; g.sAk = sAk;
+    g.B = B; g.sBk = sBk; g.sBn = sBn;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = 1.0;
+    g.accumulate = accumulate;
+    g.bias = bias;
+    g.bias_every = bias ? 1 : 0;
+    const long tiles = (long)((M + 63) / 64) * ((N + 63) / 64);
+    int ks = 1;
+    if (tiles < 512 && K >= 2048) ks = (int)std::min<long>({32L, (long)K / 512, std::max(1L, 1024 / tiles)});
+    while (ks > 1 && (size_t)ks * M * N > t->part_elems) --ks;
+    g.ksplit = ks;
+    g.part = t->part;
+    return run(c, K_TRAIN, Work{}, s, [&] { return launch_gemm_s(t->f32, 0, g, s); });
+}
+
+static int tr_op(rs_trainer* t, const TrainOp& o, hipStream_t s)
+{
+    return run(t->c, K_TRAIN, Work{}, s, [&] { return launch_train(t->f32, o, s); });
+}
+
+static TrainOp op_of(int kind)
+{
+    TrainOp o;
+    o.op = kind;
+    return o;
+}
+
+extern "C" int rs_trainer_create(rs_ctx* c, const rs_mlp* enc, const rs_decoder* dec, int32_t max_batch,
+                                 rs_trainer** out)
+{
+    if (!out) return RS_ERR_ARG;
+    *out = nullptr;
+    if (!c) return RS_ERR_STATE;
+    if (c->bf16) return fail(c, RS_ERR_UNSUPPORTED, "training needs a float32 or float64 context");
+    if (c->L < 1) return fail(c, RS_ERR_UNSUPPORTED, "training needs a decoder with hidden layers");
+    if (!enc || !enc->W || !enc->b) return fail(c, RS_ERR_ARG, "encoder is NULL");
+    if (enc->n_in != c->n_out || enc->n_out != c->r)
+        return fail(c, RS_ERR_ARG, "encoder must map 3 nv displacements to the decoder's r latent coordinates");
+    if (enc->n_hidden < 0 || enc->n_hidden > kMaxL || (enc->n_hidden > 0 && (enc->width < 1 || enc->width > 4096)))
+        return fail(c, RS_ERR_UNSUPPORTED, "encoder depth or width out of range");
+    if (max_batch < 2) return fail(c, RS_ERR_ARG, "max_batch must be >= 2");
+    RS_TRY(check_decoder(c, dec, c->nv));
+    if (dec->r != c->r || dec->n_hidden != c->L || dec->width != c->w)
+        return fail(c, RS_ERR_ARG, "decoder shape differs from the context's");
+    rs_trainer* t = new (std::nothrow) rs_trainer();
+    if (!t) return fail(c, RS_ERR_OOM, "host allocation failed");
+    t->c = c;
+    t->f32 = c->f32;
+    t->ts = c->tsz;
+    t->n = c->n_out;
+    t->r = c->r;
+    t->Le = enc->n_hidden;
+    t->we = enc->n_hidden > 0 ? enc->width : 0;
+    t->L = c->L;
+    t->w = c->w;
+    t->in_last = c->in_last;
+    t->max_batch = max_batch;
+    // encoder packed offsets
+    size_t off = 0;
+    for (int l = 0; l <= t->Le; ++l) {
+        const int in = l == 0 ? t->n : t->we, o = l == t->Le ? t->r : t->we;
+        t->eW.push_back(off);
+        off += (size_t)o * in;
+        t->eb.push_back(off);
+        off += o;
+    }
+    t->n_enc = off;
+    t->n_dec = c->n_params;
+    const size_t ts = t->ts, Bm = (size_t)max_batch;
+    const size_t wide = (size_t)std::max({t->we, t->w, t->r});
+    bool ok = true;
+    auto A = [&](size_t bytes) {
+        void* p = tr_alloc(t, bytes);
+        ok = ok && p;
+        return p;
+    };
+    t->enc = A(t->n_enc * ts);
+    t->dec = A(t->n_dec * ts);
+    t->genc = A(t->n_enc * ts);
+    t->gdec = A(t->n_dec * ts);
+    t->glip = static_cast<double*>(A(t->n_dec * sizeof(double)));
+    t->m_enc = A(t->n_enc * ts);
+    t->v_enc = A(t->n_enc * ts);
+    t->m_dec = A(t->n_dec * ts);
+    t->v_dec = A(t->n_dec * ts);
+    t->Dt = A((size_t)t->n * Bm * ts);
+    for (int l = 0; l <= t->Le; ++l) {
+        const int o = l == t->Le ? t->r : t->we;
+        t->Pe[l] = A((size_t)o * Bm * ts);
+        if (l < t->Le) t->Xe[l + 1] = A((size_t)o * Bm * ts);
+    }
+    t->Hd[0] = t->Pe[t->Le];
+    for (int l = 0; l < t->L; ++l) {
+        t->Pd[l] = A((size_t)t->w * Bm * ts);
+        t->Hd[l + 1] = A((size_t)t->w * Bm * ts);
+    }
+    t->U = A((size_t)t->n * Bm * ts);
+    t->Ubar = A((size_t)t->n * Bm * ts);
+    t->G[0] = A(wide * Bm * ts);
+    t->G[1] = A(wide * Bm * ts);
+    t->D = A(wide * Bm * ts);
+    t->part_elems = 32 * wide * Bm;
+    t->part = A(t->part_elems * ts);
+    t->rpart = static_cast<double*>(A(((size_t)t->n * Bm + 255) / 256 * sizeof(double)));
+    t->zs = static_cast<double*>(A(Bm * t->r * sizeof(double)));
+    t->z1 = static_cast<double*>(A(Bm / 2 * t->r * sizeof(double) + 8));
+    t->z2 = static_cast<double*>(A(Bm / 2 * t->r * sizeof(double) + 8));
+    t->losses = static_cast<double*>(A(2 * sizeof(double)));
+    if (!ok) {
+        tr_free(t);
+        return fail(c, RS_ERR_OOM, "trainer allocation failed");
+    }
+    // parameters: packed from the host arrays, converted to the context precision
+    std::vector<double> pe(t->n_enc), pd(t->n_dec);
+    for (int l = 0; l <= t->Le; ++l) {
+        const int in = l == 0 ? t->n : t->we, o = l == t->Le ? t->r : t->we;
+        if (!enc->W[l] || !enc->b[l]) {
+            tr_free(t);
+            return fail(c, RS_ERR_ARG, "encoder layer pointer is NULL");
+        }
+        std::copy(enc->W[l], enc->W[l] + (size_t)o * in, pe.begin() + t->eW[l]);
+        std::copy(enc->b[l], enc->b[l] + o, pe.begin() + t->eb[l]);
+    }
+    for (int l = 0; l <= t->L; ++l) {
+        const int in = l == 0 ? t->r : t->w, o = l == t->L ? t->n : t->w;
+        std::copy(dec->W[l], dec->W[l] + (size_t)o * in, pd.begin() + c->offW[l]);
+        std::copy(dec->b[l], dec->b[l] + o, pd.begin() + c->offb[l]);
+    }
+    int rc = upload(c, t->enc, pe, t->f32);
+    if (rc == RS_OK) rc = upload(c, t->dec, pd, t->f32);
+    const std::vector<double> zero_e(t->n_enc, 0.0), zero_d(t->n_dec, 0.0);
+    if (rc == RS_OK) rc = upload(c, t->m_enc, zero_e, t->f32);
+    if (rc == RS_OK) rc = upload(c, t->v_enc, zero_e, t->f32);
+    if (rc == RS_OK) rc = upload(c, t->m_dec, zero_d, t->f32);
+    if (rc == RS_OK) rc = upload(c, t->v_dec, zero_d, t->f32);
+    // the context evaluates the trainer's decoder from here on
+    if (rc == RS_OK) rc = rs_set_decoder_device(c, t->dec, !t->f32, nullptr);
+    if (rc == RS_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(c, RS_ERR_HIP, "hipDeviceSynchronize");
+    if (rc != RS_OK) {
+        tr_free(t);
+        return rc;
+    }
+    *out = t;
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_destroy(rs_trainer* t)
+{
+    if (!t) return RS_OK;
+    (void)hipDeviceSynchronize();
+    tr_free(t);
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_param_count(const rs_trainer* t, int64_t* n_enc, int64_t* n_dec)
+{
+    if (!t) return RS_ERR_STATE;
+    if (n_enc) *n_enc = (int64_t)t->n_enc;
+    if (n_dec) *n_dec = (int64_t)t->n_dec;
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_params(rs_trainer* t, void* enc, void* dec, void* stream)
+{
+    if (!t) return RS_ERR_STATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (enc && hipMemcpyAsync(enc, t->enc, t->n_enc * t->ts, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(t->c, RS_ERR_HIP, "hipMemcpyAsync");
+    if (dec && hipMemcpyAsync(dec, t->dec, t->n_dec * t->ts, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(t->c, RS_ERR_HIP, "hipMemcpyAsync");
+    return RS_OK;
+}
+
+// encoder forward of B <= max_batch items: Dt from the store, then every layer (Pe[Le] = encodings)
+static int tr_encode(rs_trainer* t, int B, const void* store, const int32_t* idx, hipStream_t s)
+{
+    TrainOp o = op_of(TRAIN_GATHER);
+    o.a = store;
+    o.n = t->n;
+    o.B = B;
+    o.idx = idx;
+    o.out = t->Dt;
+    RS_TRY(tr_op(t, o, s));
+    const void* X = t->Dt;
+    for (int l = 0; l <= t->Le; ++l) {
+        const int in = l == 0 ? t->n : t->we, out = l == t->Le ? t->r : t->we;
+        RS_TRY(tr_gemm(t, at_off(t->enc, t->eW[l], t->ts), in, 1, X, B, 1, t->Pe[l], B, out, B, in, 0,
+                       at_off(t->enc, t->eb[l], t->ts), s));
+        if (l < t->Le) {
+            TrainOp e = op_of(TRAIN_ELU_FWD);
+            e.a = t->Pe[l];
+            e.out = t->Xe[l + 1];
+            e.count = (long)out * B;
+            RS_TRY(tr_op(t, e, s));
+            X = t->Xe[l + 1];
+        }
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_encode(rs_trainer* t, int32_t B, const void* store, const int32_t* idx, double* z,
+                                 void* stream)
+{
+    if (!t) return RS_ERR_STATE;
+    rs_ctx* c = t->c;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
+    if (B > 0 && (!store || !z)) return fail(c, RS_ERR_ARG, "NULL pointer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int b0 = 0; b0 < B; b0 += t->max_batch) {
+        const int nb = std::min(t->max_batch, B - b0);
+        const void* st = idx ? store : static_cast<const char*>(store) + (size_t)b0 * t->n * t->ts;
+        RS_TRY(tr_encode(t, nb, st, idx ? idx + b0 : nullptr, s));
+        TrainOp o = op_of(TRAIN_TO_ITEMS);
+        o.a = t->Pe[t->Le];
+        o.n = t->r;
+        o.B = nb;
+        o.z = z + (size_t)b0 * t->r;
+        RS_TRY(tr_op(t, o, s));
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_grad(rs_trainer* t, int32_t B, const void* store, const int32_t* idx, double lambda_ls,
+                               int32_t n_pairs, double* losses, double* grad_enc, double* grad_dec, void* stream)
+{
+    if (!t) return RS_ERR_STATE;
+    rs_ctx* c = t->c;
+    if (B < 1 || B > t->max_batch) return fail(c, RS_ERR_ARG, "B must be in [1, max_batch]");
+    if (!store) return fail(c, RS_ERR_ARG, "store is NULL");
+    if (lambda_ls < 0.0 || !std::isfinite(lambda_ls)) return fail(c, RS_ERR_ARG, "lambda_ls must be finite and >= 0");
+    if (lambda_ls > 0.0 && (n_pairs < 1 || 2 * n_pairs > B))
+        return fail(c, RS_ERR_ARG, "n_pairs must be in [1, B/2] when lambda_ls > 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t ts = t->ts;
+    const int n = t->n, L = t->L, w = t->w, in_last = t->in_last;
+    RS_TRY(tr_encode(t, B, store, idx, s));
+    // decoder forward
+    for (int l = 0; l < L; ++l) {
+        const int in = l == 0 ? t->r : w;
+        RS_TRY(tr_gemm(t, at_off(t->dec, c->offW[l], ts), in, 1, t->Hd[l], B, 1, t->Pd[l], B, w, B, in, 0,
+                       at_off(t->dec, c->offb[l], ts), s));
+        TrainOp e = op_of(TRAIN_ELU_FWD);
+        e.a = t->Pd[l];
+        e.out = t->Hd[l + 1];
+        e.count = (long)w * B;
+        RS_TRY(tr_op(t, e, s));
+    }
+    RS_TRY(tr_gemm(t, at_off(t->dec, c->offW[L], ts), in_last, 1, t->Hd[L], B, 1, t->U, B, n, B, in_last, 0,
+                   at_off(t->dec, c->offb[L], ts), s));
+    {
+        TrainOp o = op_of(TRAIN_RESIDUAL);
+        o.a = t->U;
+        o.b = t->Dt;
+        o.n = n;
+        o.B = B;
+        o.rowmass = c->row_mass;
+        o.pinned_row = c->pinned_row;
+        o.out = t->Ubar;
+        o.part = t->rpart;
+        o.loss = t->losses;
+        RS_TRY(tr_op(t, o, s));
+    }
+    // decoder backward: output layer, then the hidden layers (adjoints ping-pong through G)
+    RS_TRY(tr_gemm(t, t->Ubar, B, 1, t->Hd[L], 1, B, at_off(t->gdec, c->offW[L], ts), in_last, n, in_last, B, 0,
+                   nullptr, s));
+    {
+        TrainOp o = op_of(TRAIN_ROWSUM);
+        o.a = t->Ubar;
+        o.n = n;
+        o.B = B;
+        o.out = at_off(t->gdec, c->offb[L], ts);
+        RS_TRY(tr_op(t, o, s));
+    }
+    int gi = 0;
+    RS_TRY(tr_gemm(t, at_off(t->dec, c->offW[L], ts), 1, in_last, t->Ubar, B, 1, t->G[gi], B, in_last, B, n, 0, nullptr,
+                   s));
+    for (int l = L - 1; l >= 0; --l) {
+        const int in = l == 0 ? t->r : w;
+        TrainOp e = op_of(TRAIN_ELU_BWD);
+        e.a = t->G[gi];
+        e.b = t->Pd[l];
+        e.out = t->D;
+        e.count = (long)w * B;
+        RS_TRY(tr_op(t, e, s));
+        RS_TRY(tr_gemm(t, t->D, B, 1, t->Hd[l], 1, B, at_off(t->gdec, c->offW[l], ts), in, w, in, B, 0, nullptr, s));
+        TrainOp o = op_of(TRAIN_ROWSUM);
+        o.a = t->D;
+        o.n = w;
+        o.B = B;
+        o.out = at_off(t->gdec, c->offb[l], ts);
+        RS_TRY(tr_op(t, o, s));
+        RS_TRY(tr_gemm(t, at_off(t->dec, c->offW[l], ts), 1, in, t->D, B, 1, t->G[gi ^ 1], B, in, B, w, 0, nullptr, s));
+        gi ^= 1;
+    }
+    // encoder backward: G[gi] is the adjoint of the encodings (its last layer is linear)
+    for (int l = t->Le; l >= 0; --l) {
+        const int in = l == 0 ? n : t->we, out = l == t->Le ? t->r : t->we;
+        const void* Dl = t->G[gi];
+        if (l < t->Le) {
+            TrainOp e = op_of(TRAIN_ELU_BWD);
+            e.a = t->G[gi];
+            e.b = t->Pe[l];
+            e.out = t->D;
+            e.count = (long)out * B;
+            RS_TRY(tr_op(t, e, s));
+            Dl = t->D;
+        }
+        const void* Xin = l == 0 ? t->Dt : t->Xe[l];
+        RS_TRY(tr_gemm(t, Dl, B, 1, Xin, 1, B, at_off(t->genc, t->eW[l], ts), in, out, in, B, 0, nullptr, s));
+        TrainOp o = op_of(TRAIN_ROWSUM);
+        o.a = Dl;
+        o.n = out;
+        o.B = B;
+        o.out = at_off(t->genc, t->eb[l], ts);
+        RS_TRY(tr_op(t, o, s));
+        if (l > 0) {
+            RS_TRY(tr_gemm(t, at_off(t->enc, t->eW[l], ts), 1, in, Dl, B, 1, t->G[gi ^ 1], B, in, B, out, 0, nullptr,
+                           s));
+            gi ^= 1;
+        }
+    }
+    // the Lipschitz term over pairs of this batch's encodings (held fixed), on the context's decoder
+    t->lambda = lambda_ls;
+    if (lambda_ls > 0.0) {
+        TrainOp o = op_of(TRAIN_TO_ITEMS);
+        o.a = t->Pe[t->Le];
+        o.n = t->r;
+        o.B = B;
+        o.z = t->zs;
+        RS_TRY(tr_op(t, o, s));
+        RS_HIP(launch_split_pairs(t->zs, n_pairs, t->r, t->z1, t->z2, s), "training pairs");
+        RS_TRY(rs_lipschitz_param_grad(c, n_pairs, t->z1, t->z2, t->losses + 1, t->glip, s));
+    } else {
+        RS_HIP(launch_fill_zero(t->losses + 1, 1, s), "fill");
+    }
+    if (losses && hipMemcpyAsync(losses, t->losses, 2 * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(c, RS_ERR_HIP, "hipMemcpyAsync");
+    if (grad_enc) {
+        TrainOp o = op_of(TRAIN_GRAD_OUT);
+        o.a = t->genc;
+        o.count = (long)t->n_enc;
+        o.z = grad_enc;
+        RS_TRY(tr_op(t, o, s));
+    }
+    if (grad_dec) {
+        TrainOp o = op_of(TRAIN_GRAD_OUT);
+        o.a = t->gdec;
+        o.g2 = lambda_ls > 0.0 ? t->glip : nullptr;
+        o.scale = lambda_ls;
+        o.count = (long)t->n_dec;
+        o.z = grad_dec;
+        RS_TRY(tr_op(t, o, s));
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_trainer_adam(rs_trainer* t, double lr, double beta1, double beta2, double eps, void* stream)
+{
+    if (!t) return RS_ERR_STATE;
+    rs_ctx* c = t->c;
+    if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0))
+        return fail(c, RS_ERR_ARG, "bad Adam constants");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ++t->step;
+    TrainOp o = op_of(TRAIN_ADAM);
+    o.lr = lr;
+    o.b1 = beta1;
+    o.b2 = beta2;
+    o.eps = eps;
+    o.step = t->step;
+    o.out = t->enc;
+    o.a = t->genc;
+    o.m = t->m_enc;
+    o.v = t->v_enc;
+    o.count = (long)t->n_enc;
+    RS_TRY(tr_op(t, o, s));
+    o.out = t->dec;
+    o.a = t->gdec;
+    o.g2 = t->lambda > 0.0 ? t->glip : nullptr;
+    o.scale = t->lambda;
+    o.m = t->m_dec;
+    o.v = t->v_dec;
+    o.count = (long)t->n_dec;
+    RS_TRY(tr_op(t, o, s));
+    return rs_set_decoder_device(c, t->dec, !t->f32, stream);
+}
+
 // ------------------------------------------------------------------ profiling
 extern "C" int rs_profile(rs_ctx* c, int32_t enable, uint32_t kind_mask)
 {

@@ -236,6 +236,41 @@ struct SgemmArgs {
     int accumulate;
     const void* bias;
     int bias_every;
+    int ksplit;           // > 1: blockIdx.z takes one K slice and writes raw sums to part, then a reduction
+    void* part;           // ksplit x M x N partial sums (output precision)
+};
+
+// One elementwise or reduction step of supervised training (launch_train), in
+// the context precision T; which fields are read depends on op.
+enum TrainOpKind {
+    TRAIN_GATHER = 0,   // out (n x B) = rows idx[b] (or b) of the (N x n) store a
+    TRAIN_ELU_FWD,      // out = elu(a), count values
+    TRAIN_ELU_BWD,      // out = a * elu'(b), count values
+    TRAIN_RESIDUAL,     // out = Ubar of U = a against Dt = b (n x B), loss = mean mass-weighted squared residual
+    TRAIN_ROWSUM,       // out[u] = sum_b a[u][b], u < n
+    TRAIN_TO_ITEMS,     // z (B x n, float64) = a (n x B) transposed
+    TRAIN_GRAD_OUT,     // z = a + scale g2 in float64, count values
+    TRAIN_ADAM          // out (params) -= Adam step of a + scale g2 with moments m, v
+};
+struct TrainOp {
+    int op = 0;
+    const void* a = nullptr;
+    const void* b = nullptr;
+    void* out = nullptr;
+    long count = 0;
+    int n = 0, B = 0;
+    const int* idx = nullptr;
+    const double* rowmass = nullptr;
+    const uint8_t* pinned_row = nullptr;
+    double* part = nullptr;
+    double* loss = nullptr;
+    double* z = nullptr;
+    const double* g2 = nullptr;
+    double scale = 0.0;
+    void* m = nullptr;
+    void* v = nullptr;
+    double lr = 0.0, b1 = 0.0, b2 = 0.0, eps = 0.0;
+    int step = 1;
 };
 
 // Jets of the Lipschitz-loss gradient: (value, Jacobian, contracted second
@@ -305,13 +340,8 @@ hipError_t launch_transpose(int f32, const void* src, int rows, int cols, int ld
                             int dst_rows, hipStream_t s);
 hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* rowmask, double* d64, float* d32,
                            int n_pad, hipStream_t s);
-hipError_t launch_elu(int backward, const float* G, const float* P, float* out, long n, hipStream_t s);
-hipError_t launch_recon_residual(const float* U, const float* d, int n, int B, const double* rowmass,
-                                 const uint8_t* pinned_row, float* Ubar, double* part, double* loss, hipStream_t s);
-hipError_t launch_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate, hipStream_t s);
-hipError_t launch_items_convert(int to_items, const float* X, double* z, float* Xo, int rows, int B, hipStream_t s);
-hipError_t launch_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
-                       double lr, double b1, double b2, double eps, int step, hipStream_t s);
+hipError_t launch_train(int f32, const TrainOp& o, hipStream_t s);
+hipError_t launch_split_pairs(const double* z, int P, int r, double* z1, double* z2, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);

@@ -42,19 +42,26 @@ __global__ __launch_bounds__(256) void k_gemm_s(SgemmArgs g)
     const T* B = static_cast<const T*>(g.B);
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // K slice of this workgroup (the whole K without a split); slices are multiples of TK
+    int kbeg = 0, kend = g.K;
+    if (g.ksplit > 1) {
+        const int kc = ((g.K + g.ksplit - 1) / g.ksplit + TK - 1) / TK * TK;
+        kbeg = blockIdx.z * kc;
+        kend = min(g.K, kbeg + kc);
+    }
     typename Mfma<T>::acc_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int idx = tid + 256 * e;           // 1024 = 64 x 16 values of each tile
             const int am = idx / TK, ak = idx % TK;  // A: row-major walk
             const int gm = m0 + am, gk = k0 + ak;
-            As[am][ak] = (gm < g.M && gk < g.K) ? A[(long)gm * g.sAm + (long)gk * g.sAk] : T(0);
+            As[am][ak] = (gm < g.M && gk < kend) ? A[(long)gm * g.sAm + (long)gk * g.sAk] : T(0);
             const int bk = idx / TN, bn = idx % TN;  // B: consecutive threads, consecutive columns
             const int hk = k0 + bk, hn = n0 + bn;
-            Bs[bk][bn] = (hk < g.K && hn < g.N) ? B[(long)hk * g.sBk + (long)hn * g.sBn] : T(0);
+            Bs[bk][bn] = (hk < kend && hn < g.N) ? B[(long)hk * g.sBk + (long)hn * g.sBn] : T(0);
         }
         __syncthreads();
 #pragma unroll
@@ -70,6 +77,17 @@ __global__ __launch_bounds__(256) void k_gemm_s(SgemmArgs g)
     }
     TC* Cp = static_cast<TC*>(g.C);
     const T* bias = static_cast<const T*>(g.bias);
+    if (g.ksplit > 1) {
+        TC* part = static_cast<TC*>(g.part) + (size_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + 16 * wave + Mfma<T>::row(lane, v), n = n0 + 16 * t + (lane & 15);
+                if (m < g.M && n < g.N) part[(size_t)m * g.N + n] = (TC)acc[t][v];
+            }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -83,17 +101,39 @@ __global__ __launch_bounds__(256) void k_gemm_s(SgemmArgs g)
         }
 }
 
+// C = (accumulate ? C : 0) + alpha sum over the K slices (in slice order) + bias
+template <typename TC, typename T>
+__global__ void k_gemm_s_reduce(SgemmArgs g)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)g.M * g.N) return;
+    const int m = (int)(i / g.N), n = (int)(i - (long)m * g.N);
+    const TC* part = static_cast<const TC*>(g.part);
+    double acc = 0.0;
+    for (int z = 0; z < g.ksplit; ++z) acc += (double)part[(size_t)z * g.M * g.N + i];
+    double val = g.alpha * acc;
+    const T* bias = static_cast<const T*>(g.bias);
+    if (bias && g.bias_every > 0 && n % g.bias_every == 0) val += (double)bias[m];
+    TC* dst = static_cast<TC*>(g.C) + (long)m * g.ldc + n;
+    *dst = g.accumulate ? (TC)((double)*dst + val) : (TC)val;
+}
+
+template <typename T, typename TC>
+static hipError_t gemm_s_launch(const SgemmArgs& g, hipStream_t s)
+{
+    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, g.ksplit > 1 ? g.ksplit : 1);
+    RS_LAUNCH((k_gemm_s<T, TC>), grid, dim3(256), 0, s, g);
+    if (g.ksplit > 1)
+        RS_LAUNCH((k_gemm_s_reduce<TC, T>), dim3((unsigned)(((long)g.M * g.N + 255) / 256)), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_s(int f32, int out_f64, const SgemmArgs& g, hipStream_t s)
 {
     if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    const dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-    if (f32) {
-        if (out_f64) RS_LAUNCH((k_gemm_s<float, double>), grid, dim3(256), 0, s, g);
-        else RS_LAUNCH((k_gemm_s<float, float>), grid, dim3(256), 0, s, g);
-    } else {
-        RS_LAUNCH((k_gemm_s<double, double>), grid, dim3(256), 0, s, g);
-    }
-    return hipGetLastError();
+    if (g.ksplit > 1 && !g.part) return hipErrorInvalidValue;
+    if (f32) return out_f64 ? gemm_s_launch<float, double>(g, s) : gemm_s_launch<float, float>(g, s);
+    return gemm_s_launch<double, double>(g, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -597,40 +637,65 @@ hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* r
 }
 
 // ---------------------------------------------------------------------------
-// Supervised training: ELU activation forward/backward on (units x batch)
-// blocks, the mass-weighted reconstruction residual, Adam.
+// Supervised training (Sec. 3.2, Eq. form-vanilla-supervised-construction):
+// batch gather, ELU forward/backward on (units x batch) blocks, the
+// mass-weighted reconstruction residual, bias sums, Adam.  T is the context
+// precision (float or double); sums run in float64.
 // ---------------------------------------------------------------------------
-// X = elu(P) elementwise (n values)
-__global__ void k_elu_fwd(const float* P, float* X, long n)
+// Dt (n x B) = rows idx[b] (or b) of the (N x n) snapshot store, transposed through LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_batch(const T* store, int n, const int* idx, int B, T* Dt)
+{
+    __shared__ T tile[32][33];
+    const int r0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) {
+        const int b = b0 + k, row = r0 + tx;
+        T v = T(0);
+        if (b < B && row < n) {
+            const long item = idx ? idx[b] : b;
+            v = store[item * n + row];
+        }
+        tile[k][tx] = v;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int row = r0 + k, b = b0 + tx;
+        if (row < n && b < B) Dt[(long)row * B + b] = tile[tx][k];
+    }
+}
+
+template <typename T>
+__global__ void k_elu_fwd(const T* P, T* X, long n)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) X[i] = elu0(P[i]);
 }
 
-// D = G * elu'(P)
-__global__ void k_elu_bwd(const float* G, const float* P, float* D, long n)
+template <typename T>
+__global__ void k_elu_bwd(const T* G, const T* P, T* D, long n)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) D[i] = G[i] * elu1(P[i]);
+    if (i < n) D[i] = G[i] * (T)elu1((double)P[i]);
 }
 
-// residual of the reconstruction in the mass norm: U (n x B) decoder output,
-// d (B x n) target displacements; Ubar = 2 m (mask U - d) / B on free rows,
-// per-block partial sums of m (mask U - d)^2 into part[blockIdx.x]
-__global__ __launch_bounds__(256) void k_recon_residual(const float* U, const float* d, int n, int B,
-                                                       const double* rowmass, const uint8_t* pinned_row, float* Ubar,
-                                                       double* part)
+// residual of the reconstruction in the mass norm, U and Dt (n x B): on free
+// rows res = U - Dt, Ubar = 2 m res / B; pinned rows are not decoded (res = -Dt,
+// no adjoint).  Per-block partial sums of m res^2 into part[blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(256) void k_recon_residual(const T* U, const T* Dt, int n, int B, const double* rowmass,
+                                                       const uint8_t* pinned_row, T* Ubar, double* part)
 {
     __shared__ double sh[256];
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     double acc = 0.0;
     if (i < (long)n * B) {
-        const int row = (int)(i / B), b = (int)(i - (long)row * B);
+        const int row = (int)(i / B);
         const bool fixed = pinned_row[row] != 0;
-        const double res = (fixed ? 0.0 : (double)U[i]) - (double)d[(long)b * n + row];
+        const double res = (fixed ? 0.0 : (double)U[i]) - (double)Dt[i];
         const double m = rowmass[row];
         acc = m * res * res;
-        Ubar[i] = fixed ? 0.f : (float)(2.0 * m * res / B);
+        Ubar[i] = fixed ? T(0) : (T)(2.0 * m * res / B);
     }
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -641,6 +706,7 @@ __global__ __launch_bounds__(256) void k_recon_residual(const float* U, const fl
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// out = scale * sum of the partials (one thread, fixed order)
 __global__ void k_sum_parts(const double* part, int n, double scale, double* out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -649,18 +715,20 @@ __global__ void k_sum_parts(const double* part, int n, double scale, double* out
     *out = s * scale;
 }
 
-// grad[u] (+)= sum_b D[u][b] (bias gradients), float32 out
-__global__ void k_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate)
+// grad[u] = sum_b D[u][b] (bias gradients of a (rows x B) adjoint block)
+template <typename T>
+__global__ void k_rowsum(const T* D, int rows, int B, T* grad)
 {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= rows) return;
     double s = 0.0;
     for (int b = 0; b < B; ++b) s += (double)D[(long)u * B + b];
-    grad[u] = accumulate ? (float)((double)grad[u] + s) : (float)s;
+    grad[u] = (T)s;
 }
 
-// (rows x B) float32 block to (B x rows) float64 and back
-__global__ void k_to_items_f64(const float* X, int rows, int B, double* z)
+// z (B x r, float64) from the (r x B) encoder output block
+template <typename T>
+__global__ void k_to_items(const T* X, int rows, int B, double* z)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * B) return;
@@ -668,69 +736,100 @@ __global__ void k_to_items_f64(const float* X, int rows, int B, double* z)
     z[i] = (double)X[(long)k * B + b];
 }
 
-__global__ void k_from_items_f64(const double* z, int rows, int B, float* X)
+// z1 (P x r) and z2 (P x r): the batch's encodings taken as pairs (z_2p, z_2p+1)
+__global__ void k_split_pairs(const double* z, int P, int r, double* z1, double* z2)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * B) return;
-    const int b = i / rows, k = i - b * rows;
-    X[(long)k * B + b] = (float)z[i];
+    if (i >= P * r) return;
+    const int p = i / r, k = i - p * r;
+    z1[i] = z[(size_t)(2 * p) * r + k];
+    z2[i] = z[(size_t)(2 * p + 1) * r + k];
 }
 
-// Adam (Kingma and Ba): g = g1 + g2_scale g2 (either may be NULL)
-__global__ void k_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
-                       double lr, double b1, double b2, double eps, double c1, double c2)
+// out = g1 + scale g2 in float64 (g2 may be NULL)
+template <typename T>
+__global__ void k_grad_out(long n, const T* g1, const double* g2, double scale, double* out)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double g = 0.0;
-    if (g1) g += (double)g1[i];
+    out[i] = (double)g1[i] + (g2 ? scale * g2[i] : 0.0);
+}
+
+// Adam (Kingma and Ba) on g = g1 + g2_scale g2 (g2 may be NULL); c1, c2 the bias corrections
+template <typename T>
+__global__ void k_adam(long n, T* p, const T* g1, const double* g2, double g2_scale, T* m, T* v, double lr,
+                       double b1, double b2, double eps, double c1, double c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double g = (double)g1[i];
     if (g2) g += g2_scale * g2[i];
     const double mi = b1 * (double)m[i] + (1.0 - b1) * g;
     const double vi = b2 * (double)v[i] + (1.0 - b2) * g * g;
-    m[i] = (float)mi;
-    v[i] = (float)vi;
-    p[i] = (float)((double)p[i] - lr * (mi / c1) / (sqrt(vi / c2) + eps));
+    m[i] = (T)mi;
+    v[i] = (T)vi;
+    p[i] = (T)((double)p[i] - lr * (mi / c1) / (sqrt(vi / c2) + eps));
 }
 
-hipError_t launch_elu(int backward, const float* G, const float* P, float* out, long n, hipStream_t s)
+template <typename T>
+static hipError_t train_dispatch(const TrainOp& o, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    if (backward) RS_LAUNCH(k_elu_bwd, grid_for(n), dim3(256), 0, s, G, P, out, n);
-    else RS_LAUNCH(k_elu_fwd, grid_for(n), dim3(256), 0, s, P, out, n);
+    switch (o.op) {
+    case TRAIN_GATHER:
+        if (o.B <= 0 || o.n <= 0) return hipSuccess;
+        RS_LAUNCH(k_gather_batch<T>, dim3((o.n + 31) / 32, (o.B + 31) / 32), dim3(256), 0, s, (const T*)o.a, o.n,
+                  o.idx, o.B, (T*)o.out);
+        break;
+    case TRAIN_ELU_FWD:
+        if (o.count <= 0) return hipSuccess;
+        RS_LAUNCH(k_elu_fwd<T>, grid_for(o.count), dim3(256), 0, s, (const T*)o.a, (T*)o.out, o.count);
+        break;
+    case TRAIN_ELU_BWD:
+        if (o.count <= 0) return hipSuccess;
+        RS_LAUNCH(k_elu_bwd<T>, grid_for(o.count), dim3(256), 0, s, (const T*)o.a, (const T*)o.b, (T*)o.out, o.count);
+        break;
+    case TRAIN_RESIDUAL: {
+        const long tot = (long)o.n * o.B;
+        const int nb = (int)((tot + 255) / 256);
+        RS_LAUNCH(k_recon_residual<T>, dim3(nb), dim3(256), 0, s, (const T*)o.a, (const T*)o.b, o.n, o.B, o.rowmass,
+                  o.pinned_row, (T*)o.out, o.part);
+        RS_LAUNCH(k_sum_parts, dim3(1), dim3(64), 0, s, o.part, nb, 1.0 / o.B, o.loss);
+        break;
+    }
+    case TRAIN_ROWSUM:
+        if (o.n <= 0) return hipSuccess;
+        RS_LAUNCH(k_rowsum<T>, grid_for(o.n), dim3(256), 0, s, (const T*)o.a, o.n, o.B, (T*)o.out);
+        break;
+    case TRAIN_TO_ITEMS:
+        if (o.n * o.B <= 0) return hipSuccess;
+        RS_LAUNCH(k_to_items<T>, grid_for((long)o.n * o.B), dim3(256), 0, s, (const T*)o.a, o.n, o.B, o.z);
+        break;
+    case TRAIN_GRAD_OUT:
+        if (o.count <= 0) return hipSuccess;
+        RS_LAUNCH(k_grad_out<T>, grid_for(o.count), dim3(256), 0, s, o.count, (const T*)o.a, o.g2, o.scale, o.z);
+        break;
+    case TRAIN_ADAM: {
+        if (o.count <= 0) return hipSuccess;
+        const double c1 = 1.0 - pow(o.b1, (double)o.step), c2 = 1.0 - pow(o.b2, (double)o.step);
+        RS_LAUNCH(k_adam<T>, grid_for(o.count), dim3(256), 0, s, o.count, (T*)o.out, (const T*)o.a, o.g2, o.scale,
+                  (T*)o.m, (T*)o.v, o.lr, o.b1, o.b2, o.eps, c1, c2);
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_recon_residual(const float* U, const float* d, int n, int B, const double* rowmass,
-                                 const uint8_t* pinned_row, float* Ubar, double* part, double* loss, hipStream_t s)
+hipError_t launch_train(int f32, const TrainOp& o, hipStream_t s)
 {
-    const long tot = (long)n * B;
-    const int nb = (int)((tot + 255) / 256);
-    RS_LAUNCH(k_recon_residual, dim3(nb), dim3(256), 0, s, U, d, n, B, rowmass, pinned_row, Ubar, part);
-    RS_LAUNCH(k_sum_parts, dim3(1), dim3(64), 0, s, part, nb, 1.0 / B, loss);
-    return hipGetLastError();
+    return f32 ? train_dispatch<float>(o, s) : train_dispatch<double>(o, s);
 }
 
-hipError_t launch_rowsum_f32(const float* D, int rows, int B, float* grad, int accumulate, hipStream_t s)
+hipError_t launch_split_pairs(const double* z, int P, int r, double* z1, double* z2, hipStream_t s)
 {
-    if (rows <= 0) return hipSuccess;
-    RS_LAUNCH(k_rowsum_f32, grid_for(rows), dim3(256), 0, s, D, rows, B, grad, accumulate);
-    return hipGetLastError();
-}
-
-hipError_t launch_items_convert(int to_items, const float* X, double* z, float* Xo, int rows, int B, hipStream_t s)
-{
-    if (rows * B <= 0) return hipSuccess;
-    if (to_items) RS_LAUNCH(k_to_items_f64, grid_for((long)rows * B), dim3(256), 0, s, X, rows, B, z);
-    else RS_LAUNCH(k_from_items_f64, grid_for((long)rows * B), dim3(256), 0, s, z, rows, B, Xo);
-    return hipGetLastError();
-}
-
-hipError_t launch_adam(long n, float* p, const float* g1, const double* g2, double g2_scale, float* m, float* v,
-                       double lr, double b1, double b2, double eps, int step, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    const double c1 = 1.0 - pow(b1, (double)step), c2 = 1.0 - pow(b2, (double)step);
-    RS_LAUNCH(k_adam, grid_for(n), dim3(256), 0, s, n, p, g1, g2, g2_scale, m, v, lr, b1, b2, eps, c1, c2);
+    if (P * r <= 0) return hipSuccess;
+    RS_LAUNCH(k_split_pairs, grid_for((long)P * r), dim3(256), 0, s, z, P, r, z1, z2);
     return hipGetLastError();
 }
 
