@@ -346,6 +346,47 @@ int rs_lipschitz_param_grad(rs_ctx* ctx, int32_t B, const double* z1, const doub
 int rs_lipschitz_param_grad_noalloc(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
                                     double* grad, void* stream);
 
+/* ---- full-space solver ----
+ * Quasi-static equilibrium over EVERY element of the mesh (Sec. 3.1, Eq.
+ * form-full-space-time-integration without the inertia term): the snapshot
+ * generator of the supervised construction (Sec. 3.2) and the judge of the
+ * reduced solves.  Projective Newton (supplement): each element Hessian
+ * V D^T (d2 psi/dF2) D with its negative eigenvalues set to zero; the Newton
+ * system solved by Jacobi-preconditioned conjugate gradients with matrix-free
+ * element products, stopped at |r|_2 <= eta |g|_2 with
+ * eta = clamp(sqrt(|g|_inf / |g_0|_inf), eta_min, eta_max); Armijo backtracking
+ * on the full energy; exits as rs_newton_solve over the free dofs.  Float64
+ * throughout, whatever the context precision. */
+typedef struct {
+    int32_t max_iter;    /* Newton iterations (exit IV) */
+    int32_t ls_max;      /* backtracking trials (exit III) */
+    int32_t cg_max;      /* CG iterations per Newton step */
+    double c1;           /* Armijo constant */
+    double shrink;       /* step factor per trial */
+    double rel_tol;      /* converged when |g|_inf <= rel_tol |g_0|_inf (free dofs) */
+    double abs_tol;      /* ... or |g|_inf <= abs_tol */
+    double eta_min;      /* CG forcing term bounds */
+    double eta_max;
+} rs_full_opts;
+
+/* max_iter 100, ls_max 128, cg_max 4000, c1 1e-4, shrink 0.5, rel_tol 1e-6,
+ * abs_tol 0, eta_min 1e-4, eta_max 0.1. */
+int rs_default_full_opts(rs_full_opts* o);
+
+/* Solve B independent load cases: u (B x nv x 3, float64 DEVICE, in/out) the
+ * displacements q - X from which each solve starts (pinned vertices keep
+ * theirs), load as in rs_energy_grad_hess (penalty targets and forces of the
+ * context's constraint sets).  Per item: iters, status (RS_CONVERGED ...),
+ * relgrad |g|_inf / |g_0|_inf and the energy E at exit (each DEVICE, may be
+ * NULL); E = sum_e V_e psi_e - sum_v m_v g.u_v + k_c/2 sum_t |x_t - t_t|^2 -
+ * sum_f f.u_f.  The first call builds the mesh tables, and a call with a
+ * batch larger than any before grows the workspace (about 450 B per element and
+ * item, float64).  Synchronises the stream once per Newton iteration, once per
+ * eight CG iterations and once per line-search trial.  Errors: RS_ERR_STATE,
+ * RS_ERR_ARG (B < 0, NULL u or opts, bad options), RS_ERR_OOM, RS_ERR_HIP. */
+int rs_full_solve(rs_ctx* ctx, int32_t B, double* u, const rs_load* load, const rs_full_opts* opts,
+                  int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream);
+
 /* ---- supervised training of the subspace (the learned part) ----
  * An autoencoder (Sec. 3.2, Eq. form-vanilla-supervised-construction): an ELU
  * encoder g: displacements (3 nv) -> r, and the context's decoder f.  One

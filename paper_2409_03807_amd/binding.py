@@ -72,6 +72,12 @@ class LbfgsOpts(C.Structure):
                 ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double)]
 
 
+class FullOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("ls_max", C.c_int32), ("cg_max", C.c_int32), ("c1", C.c_double),
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double),
+                ("eta_min", C.c_double), ("eta_max", C.c_double)]
+
+
 MAX_HISTORY = 16
 
 
@@ -88,7 +94,8 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_lipschitz_loss", "rs_last_error", "rs_profile", "rs_profile_get", "rs_param_count",
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
            "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
-           "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam"]
+           "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam",
+           "rs_default_full_opts", "rs_full_solve"]
 
 _lib = None
 
@@ -138,6 +145,9 @@ def load_library():
         L.rs_trainer_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_trainer_adam.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
+        L.rs_default_full_opts.argtypes = [C.POINTER(FullOpts)]
+        L.rs_full_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.POINTER(FullOpts),
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
         L.rs_profile_get.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_char_p, C.c_int32,
                                      C.POINTER(C.c_int32), _dp, _dp, _dp]
@@ -157,6 +167,14 @@ def default_opts(**kw) -> SolveOpts:
 def default_lbfgs_opts(**kw) -> LbfgsOpts:
     o = LbfgsOpts()
     load_library().rs_default_lbfgs_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def default_full_opts(**kw) -> FullOpts:
+    o = FullOpts()
+    load_library().rs_default_full_opts(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -391,6 +409,23 @@ class Context:
         self._check(getattr(load_library(), fn)(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), _ptr(iters),
                                                 _ptr(status), _ptr(relg), _ptr(E), _stream()), fn)
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
+
+    def full_solve(self, u0, targets=None, force=None, opts: FullOpts | None = None):
+        """Full-space equilibria of B load cases from displacements u0 (B x nv x 3, float64,
+        device); returns dict of device tensors (u, iters, status, relgrad, E)."""
+        B = u0.shape[0]
+        _dev(u0, torch.float64, (B, self.nv, 3), "u0")
+        ld, _keep = self._load(B, targets, force)
+        u = u0.clone()
+        dev = u0.device
+        iters = torch.empty(B, dtype=torch.int32, device=dev)
+        status = torch.empty(B, dtype=torch.int32, device=dev)
+        relg = torch.empty(B, dtype=torch.float64, device=dev)
+        E = torch.empty(B, dtype=torch.float64, device=dev)
+        o = opts or default_full_opts()
+        self._check(load_library().rs_full_solve(self.ctx, B, _ptr(u), C.byref(ld), C.byref(o), _ptr(iters),
+                                                 _ptr(status), _ptr(relg), _ptr(E), _stream()), "rs_full_solve")
+        return dict(u=u, iters=iters, status=status, relgrad=relg, E=E)
 
     def lipschitz_loss(self, z1, z2, want_per_pair=True):
         B = z1.shape[0]

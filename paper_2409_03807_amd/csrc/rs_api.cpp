@@ -141,6 +141,7 @@ struct rs_ctx {
     std::vector<void*> learn_bufs;
     LipWs lip;                    // Lipschitz-loss gradient workspace (allocated by its first call)
     void* scratch = nullptr;      // device address of this device's static scratch array
+    FullSolver* full = nullptr;   // full-space solver (created by its first call)
     int* fold_ptr = nullptr;      // n_out + 1: CSR of the output-layer fold by W_out row
     int* fold_row = nullptr;      // W_big row of each entry
     double* fold_coef = nullptr;  // its coefficient
@@ -499,6 +500,7 @@ static void destroy(rs_ctx* c)
 {
     for (void* p : c->allocs) (void)hipFree(p);
     for (void* p : c->learn_bufs) (void)hipFree(p);
+    full_solver_destroy(c->full);
     if (c->plog) (void)hipFree(c->plog);
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
     if (c->hcount) (void)hipHostFree(c->hcount);
@@ -2020,6 +2022,78 @@ extern "C" int rs_lipschitz_param_grad_noalloc(rs_ctx* c, int32_t B, const doubl
     }
     lip_ws_layout(c, pairs, static_cast<char*>(c->scratch), ws);
     return lip_param_grad(c, B, z1, z2, loss, grad, ws, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ full-space solver
+extern "C" int rs_default_full_opts(rs_full_opts* o)
+{
+    if (!o) return RS_ERR_ARG;
+    o->max_iter = 100;
+    o->ls_max = 128;
+    o->cg_max = 4000;
+    o->c1 = 1e-4;
+    o->shrink = 0.5;
+    o->rel_tol = 1e-6;
+    o->abs_tol = 0.0;
+    o->eta_min = 1e-4;
+    o->eta_max = 0.1;
+    return RS_OK;
+}
+
+extern "C" int rs_full_solve(rs_ctx* c, int32_t B, double* u, const rs_load* load, const rs_full_opts* o,
+                             int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
+    if (B > 0 && !u) return fail(c, RS_ERR_ARG, "u is NULL");
+    if (!o) return fail(c, RS_ERR_ARG, "opts is NULL");
+    if (o->max_iter < 0 || o->ls_max < 1 || o->cg_max < 1 || !(o->shrink > 0.0 && o->shrink < 1.0) ||
+        !(o->c1 > 0.0 && o->c1 < 1.0) || !(o->eta_min > 0.0) || !(o->eta_max >= o->eta_min) || o->rel_tol < 0.0 ||
+        o->abs_tol < 0.0)
+        return fail(c, RS_ERR_ARG, "bad full-space solver options");
+    if (B == 0) return RS_OK;
+    const char* why = "";
+    if (!c->full) {
+        FullSolverDesc d{};
+        d.nv = c->nv;
+        d.ne = c->ne;
+        d.nt = c->nt;
+        d.nf = c->nf;
+        d.X = c->X.data();
+        d.tets = c->tets.data();
+        d.pinned = c->pinned.data();
+        d.mass = c->mass.data();
+        d.tvtx = c->tvtx.data();
+        d.fvtx = c->fvtx.data();
+        d.mu = c->mu;
+        d.lam = c->lam;
+        d.kc = c->k_c;
+        for (int i = 0; i < 3; ++i) d.grav[i] = c->grav[i];
+        const int rc = full_solver_create(d, &c->full, &why);
+        if (rc != RS_OK) return fail(c, rc, why);
+    }
+    FullSolveCall call{};
+    call.B = B;
+    call.u = u;
+    call.targets = load ? load->targets : nullptr;
+    call.force = load ? load->force : nullptr;
+    call.max_iter = o->max_iter;
+    call.ls_max = o->ls_max;
+    call.cg_max = o->cg_max;
+    call.c1 = o->c1;
+    call.shrink = o->shrink;
+    call.rel_tol = o->rel_tol;
+    call.abs_tol = o->abs_tol;
+    call.eta_min = o->eta_min;
+    call.eta_max = o->eta_max;
+    call.iters = iters;
+    call.status = status;
+    call.relgrad = relgrad;
+    call.E = E;
+    if (call.targets && c->nt == 0) call.targets = nullptr;
+    if (call.force && c->nf == 0) call.force = nullptr;
+    const int rc = full_solve(c->full, call, static_cast<hipStream_t>(stream), &why);
+    return rc == RS_OK ? RS_OK : fail(c, rc, std::string("full-space solve: ") + why);
 }
 
 // ------------------------------------------------------------------ supervised training

@@ -341,6 +341,32 @@ hipError_t launch_transpose(int f32, const void* src, int rows, int cols, int ld
 hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* rowmask, double* d64, float* d32,
                            int n_pad, hipStream_t s);
 hipError_t launch_train(int f32, const TrainOp& o, hipStream_t s);
+
+// Full-space quasi-static solver over every element of the mesh (float64)
+struct FullSolverDesc {
+    int nv, ne, nt, nf;
+    const double* X;        // 3 nv rest positions (host)
+    const int* tets;        // 4 ne (host)
+    const uint8_t* pinned;  // nv (host)
+    const double* mass;     // nv lumped masses (host)
+    const int* tvtx;        // nt penalty-targeted vertices (host)
+    const int* fvtx;        // nf force-loaded vertices (host)
+    double mu, lam, kc, grav[3];
+};
+struct FullSolveCall {
+    int B;
+    double* u;              // B x 3 nv displacements (device, in/out)
+    const double* targets;  // B x nt x 3 or NULL
+    const double* force;    // B x 3 or NULL
+    int max_iter, ls_max, cg_max;
+    double c1, shrink, rel_tol, abs_tol, eta_min, eta_max;
+    int32_t *iters, *status;
+    double *relgrad, *E;
+};
+struct FullSolver;
+int full_solver_create(const FullSolverDesc& d, FullSolver** out, const char** why);
+void full_solver_destroy(FullSolver* f);
+int full_solve(FullSolver* f, const FullSolveCall& call, hipStream_t s, const char** why);
 hipError_t launch_split_pairs(const double* z, int P, int r, double* z1, double* z2, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
