@@ -447,6 +447,24 @@ int rs_trainer_grad(rs_trainer* t, int32_t B, const void* store, const int32_t* 
  * then the context's decoder is reloaded from the new parameters. */
 int rs_trainer_adam(rs_trainer* t, double lr, double beta1, double beta2, double eps, void* stream);
 
+/* PCA basis of N snapshot displacements (the linear subspace of Sec. 2's
+ * related work, kept as the baseline of the learned subspace): the mean
+ * displacement (n = 3 nv, float64 DEVICE) and W (n x r, row-major, float64
+ * DEVICE) whose columns span the r leading principal directions of the
+ * centred snapshots in the mass inner product (W^T M W = I, M the lumped
+ * masses), with their captured sums of squares in evals (r, DEVICE, may be
+ * NULL), largest first.  u = mean + W z is then a linear decoder (rs_decoder
+ * with n_hidden = 0, W_out = W, b_out = mean), and z_rest (r, DEVICE, may be
+ * NULL) = -W^T M mean the coordinates of the rest shape's projection onto
+ * that affine subspace.  Subspace iteration on
+ * Dc^T Dc M with r + 8 vectors (iters rounds) and a Rayleigh-Ritz step, float64
+ * on the matrix cores.  store: N x 3 nv in the context precision (DEVICE).
+ * Allocates its workspace for the call (about 8 N n bytes) and frees it;
+ * synchronises the stream.  Errors: RS_ERR_ARG (sizes, r > min(N, 56), fewer
+ * than r + 8 independent snapshots), RS_ERR_OOM, RS_ERR_HIP. */
+int rs_pca(rs_ctx* ctx, int32_t N, const void* store, int32_t r, int32_t iters, double* W, double* mean,
+           double* evals, double* z_rest, void* stream);
+
 /* Message of the last error on this context ("" if none); a static message
  * when ctx is NULL. */
 const char* rs_last_error(const rs_ctx* ctx);

@@ -398,3 +398,17 @@ class Mlp:
         z = np.zeros((d.shape[0], self.s.n_out))
         lib().or_encode(C.byref(self.s), C.c_int(d.shape[0]), _d(d), _d(z))
         return z
+
+
+def pca(D, row_mass, r):
+    """PCA basis of snapshot displacements D (N x n) in the mass inner product
+    (row_mass: the lumped mass of each row's vertex): the mean, W (n x r) with
+    W^T M W = I spanning the r leading principal directions of D - mean, and
+    the captured sums of squares (squared singular values), by the singular
+    value decomposition of M^(1/2) (D - mean)^T."""
+    D = np.asarray(D, dtype=np.float64)
+    mean = D.mean(axis=0)
+    s = np.sqrt(np.asarray(row_mass, dtype=np.float64))
+    U, S, _ = np.linalg.svd(((D - mean) * s).T, full_matrices=False)
+    return U[:, :r] / s[:, None], mean, S[:r] ** 2
+

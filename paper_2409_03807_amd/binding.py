@@ -95,7 +95,7 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
            "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
            "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam",
-           "rs_default_full_opts", "rs_full_solve"]
+           "rs_default_full_opts", "rs_full_solve", "rs_pca"]
 
 _lib = None
 
@@ -146,6 +146,8 @@ def load_library():
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_trainer_adam.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.rs_default_full_opts.argtypes = [C.POINTER(FullOpts)]
+        L.rs_pca.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_full_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.POINTER(FullOpts),
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_profile.argtypes = [C.c_void_p, C.c_int32, C.c_uint32]
@@ -426,6 +428,22 @@ class Context:
         self._check(load_library().rs_full_solve(self.ctx, B, _ptr(u), C.byref(ld), C.byref(o), _ptr(iters),
                                                  _ptr(status), _ptr(relg), _ptr(E), _stream()), "rs_full_solve")
         return dict(u=u, iters=iters, status=status, relgrad=relg, E=E)
+
+    def pca(self, store, r, iters=60):
+        """(W (n x r), mean (n), evals (r), z_rest (r)) float64 device tensors: the
+        mass-orthonormal PCA basis of the snapshot displacements `store` (N x n,
+        context dtype, device) and the coordinates of the rest shape's projection."""
+        _dev(store, self.tdtype, None, "store")
+        if store.dim() != 2 or store.shape[1] != self.n:
+            raise ValueError("store must be (N, 3 nv)")
+        dev = store.device
+        W = torch.empty((self.n, r), dtype=torch.float64, device=dev)
+        mean = torch.empty(self.n, dtype=torch.float64, device=dev)
+        ev = torch.empty(r, dtype=torch.float64, device=dev)
+        zr = torch.empty(r, dtype=torch.float64, device=dev)
+        self._check(load_library().rs_pca(self.ctx, store.shape[0], _ptr(store), r, iters, _ptr(W), _ptr(mean),
+                                          _ptr(ev), _ptr(zr), _stream()), "rs_pca")
+        return W, mean, ev, zr
 
     def lipschitz_loss(self, z1, z2, want_per_pair=True):
         B = z1.shape[0]

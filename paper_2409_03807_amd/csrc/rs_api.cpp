@@ -2552,6 +2552,105 @@ extern "C" int rs_trainer_adam(rs_trainer* t, double lr, double beta1, double be
     return rs_set_decoder_device(c, t->dec, !t->f32, stream);
 }
 
+// ------------------------------------------------------------------ PCA subspace
+// C (M x N) = A B, float64, split over K when few tiles meet a long reduction
+static int gemm64(rs_ctx* c, const double* A, long sAm, long sAk, const double* B, long sBk, long sBn, double* C,
+                  long ldc, int M, int N, int K, double* part, size_t part_elems, hipStream_t s, double alpha = 1.0)
+{
+    SgemmArgs g{};
+    g.A = A; g.sAm = sAm; g.sAk = sAk;
+    g.B = B; g.sBk = sBk; g.sBn = sBn;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = alpha;
+    const long tiles = (long)((M + 63) / 64) * ((N + 63) / 64);
+    int ks = 1;
+    if (tiles < 512 && K >= 2048) ks = (int)std::min<long>({32L, (long)K / 512, std::max(1L, 1024 / tiles)});
+    while (ks > 1 && (size_t)ks * M * N > part_elems) --ks;
+    g.ksplit = ks;
+    g.part = part;
+    return run(c, K_TRAIN, Work{}, s, [&] { return launch_gemm_s(0, 0, g, s); });
+}
+
+extern "C" int rs_pca(rs_ctx* c, int32_t N, const void* store, int32_t r, int32_t iters, double* W, double* mean,
+                      double* evals, double* z_rest, void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (N < 1 || !store || !W || !mean) return fail(c, RS_ERR_ARG, "N < 1 or NULL pointer");
+    if (r < 1 || r > N || r > 56) return fail(c, RS_ERR_ARG, "r must be in [1, min(N, 56)]");
+    if (iters < 1) return fail(c, RS_ERR_ARG, "iters must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = c->n_out, k = std::min(N, r + 8);
+    std::vector<void*> tmp;
+    bool ok = true;
+    auto A = [&](size_t count) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(double)) != hipSuccess) {
+            ok = false;
+            return (double*)nullptr;
+        }
+        tmp.push_back(p);
+        return (double*)p;
+    };
+    auto release = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (void* p : tmp) (void)hipFree(p);
+    };
+    const size_t part_elems = (size_t)32 * std::max(N, k) * k;
+    double* Dc = A((size_t)N * n);
+    double* X = A((size_t)n * k);
+    double* X2 = A((size_t)n * k);
+    double* MX = A((size_t)n * k);
+    double* Y = A((size_t)N * k);
+    double* G = A((size_t)k * k);
+    double* R = A((size_t)k * k);
+    double* V = A((size_t)k * r);
+    double* ev = A(r);
+    double* part = A(part_elems);
+    int* bad = (int*)A(1);
+    if (!ok) {
+        release();
+        return fail(c, RS_ERR_OOM, "PCA workspace allocation failed");
+    }
+    int rc = RS_OK;
+    auto hip = [&](hipError_t e) {
+        if (e != hipSuccess && rc == RS_OK) rc = hip_fail(c, e, "PCA");
+        return rc == RS_OK;
+    };
+    auto orth = [&](double* Xin, double* Xout) {
+        // Xout = Xin R with R = L^-T, G = Xin^T M Xin = L L^T
+        return hip(launch_pca_mass(Xin, c->row_mass, n, k, MX, s)) &&
+               gemm64(c, Xin, 1, k, MX, k, 1, G, k, k, k, n, part, part_elems, s) == RS_OK &&
+               hip(launch_pca_orth(G, k, R, bad, s)) &&
+               gemm64(c, Xin, k, 1, R, k, 1, Xout, k, n, k, k, part, part_elems, s) == RS_OK;
+    };
+    auto power = [&](double* Xin, double* Xout) {
+        // Xout = Dc^T Dc M Xin (Y = Dc M Xin kept)
+        return hip(launch_pca_mass(Xin, c->row_mass, n, k, MX, s)) &&
+               gemm64(c, Dc, n, 1, MX, k, 1, Y, k, N, k, n, part, part_elems, s) == RS_OK &&
+               (Xout == nullptr || gemm64(c, Dc, 1, n, Y, k, 1, Xout, k, n, k, N, part, part_elems, s) == RS_OK);
+    };
+    bool go = hip(launch_pca_center(c->f32, store, N, n, mean, Dc, s)) && hip(launch_pca_start(X2, (long)n * k, s)) &&
+              orth(X2, X);
+    for (int it = 0; go && it < iters; ++it) go = power(X, X2) && orth(X2, X);
+    // Rayleigh-Ritz: T = Y^T Y with Y = Dc M X, its top r eigenvectors V, W = X V
+    go = go && power(X, nullptr) && gemm64(c, Y, 1, k, Y, k, 1, G, k, k, k, N, part, part_elems, s) == RS_OK &&
+         hip(launch_pca_ritz(G, k, r, V, ev, s)) &&
+         gemm64(c, X, k, 1, V, r, 1, W, r, n, r, k, part, part_elems, s) == RS_OK;
+    if (go && evals) go = hip(hipMemcpyAsync(evals, ev, r * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // coordinates of the rest shape's projection: -W^T M mean
+    if (go && z_rest)
+        go = hip(launch_pca_mass(mean, c->row_mass, n, 1, MX, s)) &&
+             gemm64(c, W, 1, r, MX, 1, 1, z_rest, 1, r, 1, n, part, part_elems, s, -1.0) == RS_OK;
+    int hbad = 0;
+    if (go) go = hip(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    release();
+    if (rc != RS_OK) return rc;
+    if (!go) return fail(c, RS_ERR_HIP, "PCA failed");
+    if (hbad) return fail(c, RS_ERR_ARG, "the snapshots span fewer than r + 8 directions (rank-deficient Gram matrix)");
+    return RS_OK;
+}
+
 // ------------------------------------------------------------------ profiling
 extern "C" int rs_profile(rs_ctx* c, int32_t enable, uint32_t kind_mask)
 {

@@ -368,6 +368,12 @@ int full_solver_create(const FullSolverDesc& d, FullSolver** out, const char** w
 void full_solver_destroy(FullSolver* f);
 int full_solve(FullSolver* f, const FullSolveCall& call, hipStream_t s, const char** why);
 hipError_t launch_split_pairs(const double* z, int P, int r, double* z1, double* z2, hipStream_t s);
+// PCA of snapshots (subspace iteration in the mass inner product)
+hipError_t launch_pca_center(int f32, const void* D, int N, int n, double* mean, double* Dc, hipStream_t s);
+hipError_t launch_pca_start(double* X, long count, hipStream_t s);
+hipError_t launch_pca_mass(const double* X, const double* rowmass, int n, int k, double* MX, hipStream_t s);
+hipError_t launch_pca_orth(const double* G, int k, double* R, int* fail, hipStream_t s);
+hipError_t launch_pca_ritz(const double* T, int k, int r, double* V, double* ev, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);

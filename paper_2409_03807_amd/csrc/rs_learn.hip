@@ -826,6 +826,168 @@ hipError_t launch_train(int f32, const TrainOp& o, hipStream_t s)
     return f32 ? train_dispatch<float>(o, s) : train_dispatch<double>(o, s);
 }
 
+// ---------------------------------------------------------------------------
+// PCA of snapshot displacements (the linear subspace baseline): column means,
+// centring, mass scaling and the small k x k steps of a subspace iteration in
+// the mass inner product, float64.
+// ---------------------------------------------------------------------------
+// mean[d] = (1/N) sum_i D[i][d]; Dc64 (N x n) = D - mean, float64
+template <typename T>
+__global__ void k_pca_center(const T* D, int N, int n, double* mean, double* Dc)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += (double)D[(size_t)i * n + d];
+    const double m = s / N;
+    mean[d] = m;
+    for (int i = 0; i < N; ++i) Dc[(size_t)i * n + d] = (double)D[(size_t)i * n + d] - m;
+}
+
+// deterministic start block in [-1, 1) from an integer hash of the index
+__global__ void k_pca_start(double* X, long count)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    h ^= h >> 33;
+    h *= 0xFF51AFD7ED558CCDull;
+    h ^= h >> 33;
+    h *= 0xC4CEB9FE1A85EC53ull;
+    h ^= h >> 33;
+    X[i] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// MX (n x k) = m_row (.) X
+__global__ void k_pca_mass(const double* X, const double* rowmass, int n, int k, double* MX)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)n * k) return;
+    MX[i] = rowmass[i / k] * X[i];
+}
+
+// One thread: the Cholesky factor L of the k x k Gram matrix G (row-major) and
+// R = L^-T (upper triangular) into R, so that X R has orthonormal columns.
+__global__ void k_pca_orth(const double* G, int k, double* R, int* fail)
+{
+    __shared__ double L[64 * 64];
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < k * k; ++i) L[i] = 0.0;
+    int bad = 0;
+    for (int j = 0; j < k; ++j) {
+        double d = G[j * k + j];
+        for (int m = 0; m < j; ++m) d -= L[j * k + m] * L[j * k + m];
+        if (!(d > 0.0)) {
+            bad = 1;
+            d = 1e-300;
+        }
+        const double ljj = sqrt(d);
+        L[j * k + j] = ljj;
+        for (int i = j + 1; i < k; ++i) {
+            double t = G[i * k + j];
+            for (int m = 0; m < j; ++m) t -= L[i * k + m] * L[j * k + m];
+            L[i * k + j] = t / ljj;
+        }
+    }
+    // R = L^-T: solve L^T R = I column by column (back substitution)
+    for (int c = 0; c < k; ++c)
+        for (int i = k - 1; i >= 0; --i) {
+            double t = i == c ? 1.0 : 0.0;
+            for (int m = i + 1; m < k; ++m) t -= L[m * k + i] * R[m * k + c];
+            R[i * k + c] = t / L[i * k + i];
+        }
+    *fail = bad;
+}
+
+// One thread: eigenvectors of the symmetric k x k matrix T (cyclic Jacobi),
+// the r of largest eigenvalue as the columns of V (k x r, row-major), in
+// decreasing order; eigenvalues into ev (r)
+__global__ void k_pca_ritz(const double* T, int k, int r, double* V, double* ev)
+{
+    __shared__ double A[64 * 64];
+    __shared__ double Q[64 * 64];
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            A[i * k + j] = 0.5 * (T[i * k + j] + T[j * k + i]);
+            Q[i * k + j] = i == j ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < k * k; ++i) tot += A[i] * A[i];
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j)
+                if (i != j) off += A[i * k + j] * A[i * k + j];
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = A[p * k + q];
+                if (apq == 0.0) continue;
+                const double th = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                for (int m = 0; m < k; ++m) {
+                    const double mp = A[m * k + p], mq = A[m * k + q];
+                    A[m * k + p] = c * mp - s * mq;
+                    A[m * k + q] = s * mp + c * mq;
+                }
+                for (int m = 0; m < k; ++m) {
+                    const double mp = A[p * k + m], mq = A[q * k + m];
+                    A[p * k + m] = c * mp - s * mq;
+                    A[q * k + m] = s * mp + c * mq;
+                }
+                for (int m = 0; m < k; ++m) {
+                    const double mp = Q[m * k + p], mq = Q[m * k + q];
+                    Q[m * k + p] = c * mp - s * mq;
+                    Q[m * k + q] = s * mp + c * mq;
+                }
+            }
+    }
+    int used[64];
+    for (int i = 0; i < k; ++i) used[i] = 0;
+    for (int c = 0; c < r; ++c) {
+        int best = -1;
+        for (int i = 0; i < k; ++i)
+            if (!used[i] && (best < 0 || A[i * k + i] > A[best * k + best])) best = i;
+        used[best] = 1;
+        ev[c] = A[best * k + best];
+        for (int i = 0; i < k; ++i) V[i * r + c] = Q[i * k + best];
+    }
+}
+
+hipError_t launch_pca_center(int f32, const void* D, int N, int n, double* mean, double* Dc, hipStream_t s)
+{
+    if (f32) RS_LAUNCH(k_pca_center<float>, grid_for(n), dim3(256), 0, s, (const float*)D, N, n, mean, Dc);
+    else RS_LAUNCH(k_pca_center<double>, grid_for(n), dim3(256), 0, s, (const double*)D, N, n, mean, Dc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pca_start(double* X, long count, hipStream_t s)
+{
+    RS_LAUNCH(k_pca_start, grid_for(count), dim3(256), 0, s, X, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pca_mass(const double* X, const double* rowmass, int n, int k, double* MX, hipStream_t s)
+{
+    RS_LAUNCH(k_pca_mass, grid_for((long)n * k), dim3(256), 0, s, X, rowmass, n, k, MX);
+    return hipGetLastError();
+}
+
+hipError_t launch_pca_orth(const double* G, int k, double* R, int* fail, hipStream_t s)
+{
+    if (k > 64) return hipErrorInvalidValue;
+    RS_LAUNCH(k_pca_orth, dim3(1), dim3(64), 0, s, G, k, R, fail);
+    return hipGetLastError();
+}
+
+hipError_t launch_pca_ritz(const double* T, int k, int r, double* V, double* ev, hipStream_t s)
+{
+    if (k > 64 || r > k) return hipErrorInvalidValue;
+    RS_LAUNCH(k_pca_ritz, dim3(1), dim3(64), 0, s, T, k, r, V, ev);
+    return hipGetLastError();
+}
+
 hipError_t launch_split_pairs(const double* z, int P, int r, double* z1, double* z2, hipStream_t s)
 {
     if (P * r <= 0) return hipSuccess;

@@ -12,7 +12,8 @@ Elephant, Bunny); those meshes are not available, so regular beams made of
 cubes split into five tetrahedra stand in for them, with the problem sizes
 (n, E, r, S) of the same order as the quasi-static Twist Bar of Table 1.
 
-Seeds: decoder 0, cubature 1, latent batches 2, loads 3.
+Seeds: decoder 0, cubature 1, latent batches 2, loads 3, train/held-out split
+4, snapshot loads 5, encoder 6.
 """
 from __future__ import annotations
 
@@ -25,6 +26,9 @@ SEED_DECODER = 0
 SEED_CUBATURE = 1
 SEED_LATENT = 2
 SEED_LOADS = 3
+SEED_SPLIT = 4
+SEED_SNAPSHOTS = 5
+SEED_ENCODER = 6
 
 
 # ----------------------------------------------------------------------------
@@ -226,7 +230,8 @@ def config(name: str, **kw) -> Problem:
         cubature tets with weights U[20,80], end twist 0-180 deg as penalty
         targets (k_c = 1e6 N/m) on the x=L face; FP32 path, batch 1024.
     c3: c2 with batch 4096 (BF16 decoder variant).
-    c4: 16^3 block (4913 vertices, 20480 tets), r=12, 4x256, 512 cubature tets.
+    c4: 16^3 block (4913 vertices, 20480 tets), r=12, 4x256, 512 cubature tets
+        with weights U[20,60], end twist and bend loads on the x=L face.
     c5: 50x10x10 beam (6171 vertices, 25000 tets), r=32, 5x256, 1024 cubature tets.
     """
     name = name.lower()
@@ -235,7 +240,8 @@ def config(name: str, **kw) -> Problem:
     if name in ("c2", "c3"):
         return make_problem(name, 40, 8, 8, 16, [128] * 4, 256, **kw)
     if name == "c4":
-        return make_problem("c4", 16, 16, 16, 12, [256] * 4, 512, bend=True, **kw)
+        # weights U[20, 60]: mean 40 = ne / |S|, so the cubature sum has the element count's scale
+        return make_problem("c4", 16, 16, 16, 12, [256] * 4, 512, wlo=20.0, whi=60.0, bend=True, **kw)
     if name == "c5":
         return make_problem("c5", 50, 10, 10, 32, [256] * 5, 1024, **kw)
     if name == "tiny":
@@ -255,3 +261,26 @@ def loads_for(p: Problem, B: int, twist_deg=None, seed: int = SEED_LOADS):
     if len(p.force_vtx):
         force = bend_forces(B, len(p.force_vtx), seed=seed)
     return targets, force
+
+
+def snapshot_loads(p: Problem, N: int, seed: int = SEED_SNAPSHOTS, fmax: float = 2000.0):
+    """Load cases of the snapshot set: end twist U[-180, 180] deg (penalty targets
+    on the x = L face) and a bend load |F| ~ U[0, fmax] N in a random direction of
+    the y-z plane spread over the same face.  Returns (twist (N,), targets
+    (N, nt, 3), force per loaded vertex (N, 3))."""
+    rng = np.random.default_rng(seed)
+    twist = rng.uniform(-180.0, 180.0, size=N)
+    mag = rng.uniform(0.0, fmax, size=N)
+    ang = rng.uniform(0.0, 2 * math.pi, size=N)
+    f = np.zeros((N, 3))
+    nf = max(len(p.force_vtx), 1)
+    f[:, 1] = mag * np.cos(ang) / nf
+    f[:, 2] = mag * np.sin(ang) / nf
+    return twist, twist_targets(p.X, p.target_vtx, twist), f
+
+
+def heldout_split(N: int, n_test: int, seed: int = SEED_SPLIT):
+    """(train indices, held-out indices), a seeded permutation."""
+    perm = np.random.default_rng(seed).permutation(N)
+    return np.sort(perm[n_test:]), np.sort(perm[:n_test])
+
