@@ -429,8 +429,37 @@ static void gather(const or_problem* p, int e, const double* x, double* xe)
 
 /* energy and q-space gradient gq (n) of the reduced objective at positions x:
  * cubature elastic sum (+ gravity, penalty and nodal forces unless elastic-only) */
+/* inertia and ground contact (implicit Euler, Sec. 3.1): energy, gradient
+ * rows, and (H_diag, nullable) the diagonal of their q-Hessian */
+static double dyn_energy(const or_problem* p, const rest_data* rd, const double* x, const double* qb,
+                         double* gq, double* H_diag)
+{
+    double E = 0.0;
+    if (p->dt > 0.0 && qb) {
+        const double c = 1.0 / (p->dt * p->dt);
+        for (int row = 0; row < p->n_out; ++row) {
+            if (p->pinned[row / 3]) continue;
+            const double m = rd->mass[row / 3];
+            const double d = x[row] - p->X[row] - qb[row];
+            E += 0.5 * c * m * d * d;
+            if (gq) gq[row] += c * m * d;
+            if (H_diag) H_diag[row] += c * m;
+        }
+    }
+    for (int k = 0; k < p->nc; ++k) {
+        const int row = 3 * p->contact_vtx[k] + 1;
+        const double d = x[row] - p->ground_y;
+        if (d < 0.0) {
+            E += 0.5 * p->k_ground * d * d;
+            if (gq) gq[row] += p->k_ground * d;
+            if (H_diag) H_diag[row] += p->k_ground;
+        }
+    }
+    return E;
+}
+
 static double q_energy(const or_problem* p, const rest_data* rd, const double* x,
-                       const double* tgt, const double* f, int flags, double* gq)
+                       const double* tgt, const double* f, const double* qb, int flags, double* gq)
 {
     double E = 0.0;
     if (gq) memset(gq, 0, sizeof(double) * p->n_out);
@@ -473,6 +502,7 @@ static double q_energy(const or_problem* p, const rest_data* rd, const double* x
                 if (gq) gq[3 * v + i] -= f[i];
             }
         }
+    E += dyn_energy(p, rd, x, qb, gq, NULL);
     return E;
 }
 
@@ -501,7 +531,7 @@ static void psd_clamp12(double* He)
  * (+ sum_k gq_k d2q_k/dz2 when exact) at one latent point; with OR_ELEM_PSD
  * each element Hessian H_e is first projected to positive semi-definite */
 static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
-                      const double* tgt, const double* f, int flags, double* E,
+                      const double* tgt, const double* f, const double* qb, int flags, double* E,
                       double* g, double* H)
 {
     int r = p->r, n = p->n_out;
@@ -514,7 +544,7 @@ static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
     double* Jq = (want_g || want_H) ? (double*)malloc(sizeof(double) * (size_t)n * r) : NULL;
     double* gq = (want_g || want_H) ? (double*)malloc(sizeof(double) * n) : NULL;
     decoder_output(p, &st, x, Jq);
-    *E = q_energy(p, rd, x, tgt, f, flags, gq);
+    *E = q_energy(p, rd, x, tgt, f, qb, flags, gq);
     if (want_g)
         for (int k = 0; k < r; ++k) {
             double s = 0.0;
@@ -553,6 +583,18 @@ static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
                         for (int q = 0; q < r; ++q) H[k * r + q] += p->k_c * Jr[k] * Jr[q];
                 }
             }
+        if (!(flags & OR_ELASTIC_ONLY) && ((p->dt > 0.0 && qb) || p->nc > 0)) {
+            /* inertia and contact: J_row^T (d2E/dq_row^2) J_row */
+            double* Hd = (double*)calloc(n, sizeof(double));
+            dyn_energy(p, rd, x, qb, NULL, Hd);
+            for (int row = 0; row < n; ++row) {
+                if (Hd[row] == 0.0) continue;
+                const double* Jr = Jq + (size_t)row * r;
+                for (int k = 0; k < r; ++k)
+                    for (int q = 0; q < r; ++q) H[k * r + q] += Hd[row] * Jr[k] * Jr[q];
+            }
+            free(Hd);
+        }
         if (exact) {
             double* Trow = (double*)malloc(sizeof(double) * r * r);
             for (int row = 0; row < n; ++row) {
@@ -568,7 +610,7 @@ static void item_eval(const or_problem* p, const rest_data* rd, const double* z,
 }
 
 int or_reduced(const or_problem* p, int B, const double* z, const double* targets,
-               const double* force, int flags, double* E, double* g, double* H)
+               const double* force, const double* qbar, int flags, double* E, double* g, double* H)
 {
     rest_data rd;
     rest_build(p, &rd);
@@ -576,7 +618,8 @@ int or_reduced(const or_problem* p, int B, const double* z, const double* target
 #pragma omp parallel for schedule(dynamic)
     for (int bi = 0; bi < B; ++bi)
         item_eval(p, &rd, z + (size_t)bi * r, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
-                  force ? force + (size_t)bi * 3 : NULL, flags, E + bi, g ? g + (size_t)bi * r : NULL,
+                  force ? force + (size_t)bi * 3 : NULL, qbar ? qbar + (size_t)bi * p->n_out : NULL, flags,
+                  E + bi, g ? g + (size_t)bi * r : NULL,
                   H ? H + (size_t)bi * r * r : NULL);
     rest_free(&rd);
     return 0;
@@ -662,7 +705,7 @@ static double inf_norm(const double* a, int n)
 }
 
 static void item_newton(const or_problem* p, const rest_data* rd, double* z, const double* tgt,
-                        const double* f, const or_opts* o, int* iters, int* status,
+                        const double* f, const double* qb, const or_opts* o, int* iters, int* status,
                         double* relgrad, double* Eout)
 {
     int r = p->r;
@@ -672,7 +715,7 @@ static void item_newton(const or_problem* p, const rest_data* rd, double* z, con
     double* dz = (double*)malloc(sizeof(double) * r);
     double* zt = (double*)malloc(sizeof(double) * r);
     double E;
-    item_eval(p, rd, z, tgt, f, flags, &E, g, H);
+    item_eval(p, rd, z, tgt, f, qb, flags, &E, g, H);
     double g0 = inf_norm(g, r), gn = g0;
     int it = 0, st;
     for (;;) {
@@ -688,14 +731,14 @@ static void item_newton(const or_problem* p, const rest_data* rd, double* z, con
         int ok = 0;
         for (int t = 0; t < o->ls_max; ++t) {
             for (int k = 0; k < r; ++k) zt[k] = z[k] + alpha * dz[k];
-            item_eval(p, rd, zt, tgt, f, OR_ENERGY_ONLY, &Et, NULL, NULL);
+            item_eval(p, rd, zt, tgt, f, qb, OR_ENERGY_ONLY, &Et, NULL, NULL);
             if (isfinite(Et) && Et - E <= o->c1 * alpha * slope) { ok = 1; break; }
             alpha *= o->shrink;
         }
         if (!ok) { st = OR_LS_MAX; break; }
         memcpy(z, zt, sizeof(double) * r);
         ++it;
-        item_eval(p, rd, z, tgt, f, flags, &E, g, H);
+        item_eval(p, rd, z, tgt, f, qb, flags, &E, g, H);
     }
     *iters = it;
     *status = st;
@@ -705,14 +748,15 @@ static void item_newton(const or_problem* p, const rest_data* rd, double* z, con
 }
 
 int or_newton(const or_problem* p, int B, double* z, const double* targets, const double* force,
-              const or_opts* o, int* iters, int* status, double* relgrad, double* E)
+              const double* qbar, const or_opts* o, int* iters, int* status, double* relgrad, double* E)
 {
     rest_data rd;
     rest_build(p, &rd);
 #pragma omp parallel for schedule(dynamic)
     for (int bi = 0; bi < B; ++bi)
         item_newton(p, &rd, z + (size_t)bi * p->r, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
-                    force ? force + (size_t)bi * 3 : NULL, o, iters + bi, status + bi, relgrad + bi, E + bi);
+                    force ? force + (size_t)bi * 3 : NULL, qbar ? qbar + (size_t)bi * p->n_out : NULL, o,
+                    iters + bi, status + bi, relgrad + bi, E + bi);
     rest_free(&rd);
     return 0;
 }
@@ -760,7 +804,7 @@ void or_lbfgs_dir(int r, int npair, const double* S, const double* Y, const doub
 }
 
 static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, const double* tgt,
-                       const double* f, const or_lbfgs_opts* o, int* iters, int* status,
+                       const double* f, const double* qb, const or_lbfgs_opts* o, int* iters, int* status,
                        double* relgrad, double* Eout)
 {
     int r = p->r, m = o->history;
@@ -774,7 +818,7 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
     double* y_new = (double*)malloc(sizeof(double) * r);
     double E;
     int npair = 0;
-    item_eval(p, rd, z, tgt, f, 0, &E, g, NULL);
+    item_eval(p, rd, z, tgt, f, qb, 0, &E, g, NULL);
     double g0 = inf_norm(g, r), gn = g0;
     int it = 0, st;
     for (;;) {
@@ -789,7 +833,7 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
         int ok = 0;
         for (int t = 0; t < o->ls_max; ++t) {
             for (int k = 0; k < r; ++k) zt[k] = z[k] + alpha * dz[k];
-            item_eval(p, rd, zt, tgt, f, OR_ENERGY_ONLY, &Et, NULL, NULL);
+            item_eval(p, rd, zt, tgt, f, qb, OR_ENERGY_ONLY, &Et, NULL, NULL);
             if (isfinite(Et) && Et - E <= o->c1 * alpha * slope) { ok = 1; break; }
             alpha *= o->shrink;
         }
@@ -800,7 +844,7 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
         memcpy(gold, g, sizeof(double) * r);
         memcpy(z, zt, sizeof(double) * r);
         ++it;
-        item_eval(p, rd, z, tgt, f, 0, &E, g, NULL);
+        item_eval(p, rd, z, tgt, f, qb, 0, &E, g, NULL);
         for (int k = 0; k < r; ++k) y_new[k] = g[k] - gold[k];
         if (m > 0 && dot(s_new, y_new, r) > 0.0) {
             if (npair == m) { /* drop the oldest */
@@ -821,7 +865,7 @@ static void item_lbfgs(const or_problem* p, const rest_data* rd, double* z, cons
 }
 
 int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const double* force,
-             const or_lbfgs_opts* o, int* iters, int* status, double* relgrad, double* E)
+             const double* qbar, const or_lbfgs_opts* o, int* iters, int* status, double* relgrad, double* E)
 {
     if (o->history < 0) return 1;
     rest_data rd;
@@ -829,7 +873,8 @@ int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const
 #pragma omp parallel for schedule(dynamic)
     for (int bi = 0; bi < B; ++bi)
         item_lbfgs(p, &rd, z + (size_t)bi * p->r, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
-                   force ? force + (size_t)bi * 3 : NULL, o, iters + bi, status + bi, relgrad + bi, E + bi);
+                   force ? force + (size_t)bi * 3 : NULL, qbar ? qbar + (size_t)bi * p->n_out : NULL, o,
+                   iters + bi, status + bi, relgrad + bi, E + bi);
     rest_free(&rd);
     return 0;
 }
@@ -838,7 +883,7 @@ int or_lbfgs(const or_problem* p, int B, double* z, const double* targets, const
 /* full-space reference: Newton on the free vertex DOFs over every mesh element */
 /* ------------------------------------------------------------------------- */
 static double full_energy(const or_problem* p, const rest_data* rd, const double* x,
-                          const double* tgt, const double* f, double* grad)
+                          const double* tgt, const double* f, const double* qb, double* grad)
 {
     double E = 0.0;
     if (grad) memset(grad, 0, sizeof(double) * p->n_out);
@@ -876,21 +921,22 @@ static double full_energy(const or_problem* p, const rest_data* rd, const double
                 if (grad) grad[3 * v + i] -= f[i];
             }
         }
+    E += dyn_energy(p, rd, x, qb, grad, NULL);
     return E;
 }
 
 double or_full_energy(const or_problem* p, const double* x, const double* targets,
-                      const double* force, double* grad)
+                      const double* force, const double* qbar, double* grad)
 {
     rest_data rd;
     rest_build(p, &rd);
-    double E = full_energy(p, &rd, x, targets, force, grad);
+    double E = full_energy(p, &rd, x, targets, force, qbar, grad);
     rest_free(&rd);
     return E;
 }
 
 int or_full_newton(const or_problem* p, double* x, const double* tgt, const double* f,
-                   const or_opts* o, int elem_psd, int* iters, int* status, double* relgrad,
+                   const double* qb, const or_opts* o, int elem_psd, int* iters, int* status, double* relgrad,
                    double* Eout)
 {
     rest_data rd;
@@ -908,7 +954,7 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
     double E = 0.0, g0 = 0.0, gn = 0.0;
     int it = 0, st;
     for (;;) {
-        E = full_energy(p, &rd, x, tgt, f, grad);
+        E = full_energy(p, &rd, x, tgt, f, qb, grad);
         for (int row = 0; row < n; ++row)
             if (idx[row] >= 0) gf[idx[row]] = grad[row];
         gn = inf_norm(gf, nf);
@@ -937,6 +983,13 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
                     int rr = idx[3 * p->target_vtx[c] + i];
                     if (rr >= 0) H[(size_t)rr * nf + rr] += p->k_c;
                 }
+        {
+            /* inertia and contact: diagonal in q */
+            memset(xt, 0, sizeof(double) * n);
+            dyn_energy(p, &rd, x, qb, NULL, xt);
+            for (int row = 0; row < n; ++row)
+                if (idx[row] >= 0) H[(size_t)idx[row] * nf + idx[row]] += xt[row];
+        }
         if (newton_dir(nf, H, gf, o->proj, o->eig_floor, dz)) { st = OR_NOT_DESCENT; break; }
         double slope = 0.0;
         for (int k = 0; k < nf; ++k) slope += gf[k] * dz[k];
@@ -945,7 +998,7 @@ int or_full_newton(const or_problem* p, double* x, const double* tgt, const doub
         int ok = 0;
         for (int t = 0; t < o->ls_max; ++t) {
             for (int row = 0; row < n; ++row) xt[row] = x[row] + (idx[row] >= 0 ? alpha * dz[idx[row]] : 0.0);
-            double Et = full_energy(p, &rd, xt, tgt, f, NULL);
+            double Et = full_energy(p, &rd, xt, tgt, f, qb, NULL);
             if (isfinite(Et) && Et - E <= o->c1 * alpha * slope) { ok = 1; break; }
             alpha *= o->shrink;
         }
@@ -1016,7 +1069,7 @@ int or_energy_param_grad(const or_problem* p, int B, const double* z, const doub
             x[row] = p->X[row] + (p->pinned[row / 3] ? 0.0 : u);
         }
         const double Eb = q_energy(p, &rd, x, targets ? targets + (size_t)bi * p->nt * 3 : NULL,
-                                   force ? force + (size_t)bi * 3 : NULL, flags & OR_ELASTIC_ONLY, gq);
+                                   force ? force + (size_t)bi * 3 : NULL, NULL, flags & OR_ELASTIC_ONLY, gq);
         if (E) E[bi] = Eb;
         /* output layer: dE/du_row = gq_row on free rows (pinned rows do not move) */
         for (int j = 0; j < nin_out; ++j) gb[j] = 0.0;
@@ -1070,8 +1123,8 @@ int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,
         double E1, E2;
         double* H1 = (double*)malloc(sizeof(double) * r * r);
         double* H2 = (double*)malloc(sizeof(double) * r * r);
-        item_eval(p, &rd, a, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E1, NULL, H1);
-        item_eval(p, &rd, c, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E2, NULL, H2);
+        item_eval(p, &rd, a, NULL, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E1, NULL, H1);
+        item_eval(p, &rd, c, NULL, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E2, NULL, H2);
         double fro = 0.0;
         for (int k = 0; k < r * r; ++k) fro += (H1[k] - H2[k]) * (H1[k] - H2[k]);
         ell[bi] = fro / dz2;
@@ -1382,8 +1435,8 @@ int or_lipschitz_param_grad(const or_problem* p, int B, const double* z1, const 
         for (int k = 0; k < r; ++k) d2 += (a[k] - c[k]) * (a[k] - c[k]);
         if (!(d2 > 0.0)) continue;
         double E1, E2;
-        item_eval(p, &rd, a, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E1, NULL, H1);
-        item_eval(p, &rd, c, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E2, NULL, H2);
+        item_eval(p, &rd, a, NULL, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E1, NULL, H1);
+        item_eval(p, &rd, c, NULL, NULL, NULL, OR_EXACT | OR_ELASTIC_ONLY, &E2, NULL, H2);
         double fro = 0.0;
         for (int k = 0; k < r * r; ++k) fro += (H1[k] - H2[k]) * (H1[k] - H2[k]);
         sum += fro / d2;

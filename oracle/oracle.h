@@ -41,6 +41,14 @@ typedef struct {
     double k_c;
     int nf;
     const int* force_vtx;
+    /* implicit Euler (Sec. 3.1): time step dt, 0 = quasi-static (no inertia term);
+     * the inertial targets qbar (displacements, n per item) are call arguments */
+    double dt;
+    /* ground contact: one-sided penalty k_ground/2 min(0, x_v,y - ground_y)^2 on
+     * the nc contact vertices */
+    int nc;
+    const int* contact_vtx;
+    double k_ground, ground_y;
 } or_problem;
 
 typedef struct {
@@ -88,9 +96,11 @@ int or_decode(const or_problem* p, int B, const double* z, double* x, double* J)
 int or_decode_hess(const or_problem* p, const double* z, double* T);
 
 /* reduced energy / gradient / Hessian at B latent points.
- * targets (B x nt x 3) and force (B x 3, applied to each force vertex) nullable. */
+ * targets (B x nt x 3) and force (B x 3, applied to each force vertex) nullable;
+ * qbar (B x n inertial target displacements) nullable, used when p->dt > 0:
+ * E += 1/(2 dt^2) sum over free rows m_row (x_row - X_row - qbar_row)^2. */
 int or_reduced(const or_problem* p, int B, const double* z, const double* targets,
-               const double* force, int flags, double* E, double* g, double* H);
+               const double* force, const double* qbar, int flags, double* E, double* g, double* H);
 
 /* Newton direction of one item: dz = -H^-1 g with the Cholesky factor of the
  * symmetrised H when it is positive definite, else with its eigen-projection
@@ -100,7 +110,7 @@ int or_newton_dir(int n, const double* H, const double* g, int proj, double eig_
 
 /* reduced projective Newton with backtracking line search, z in/out */
 int or_newton(const or_problem* p, int B, double* z, const double* targets,
-              const double* force, const or_opts* o, int* iters, int* status,
+              const double* force, const double* qbar, const or_opts* o, int* iters, int* status,
               double* relgrad, double* E);
 
 /* L-BFGS direction d = -H g by the two-loop recursion over npair (s, y)
@@ -111,18 +121,18 @@ void or_lbfgs_dir(int r, int npair, const double* S, const double* Y, const doub
 /* reduced L-BFGS with the same backtracking line search and exits as
  * or_newton (gradient only), z in/out */
 int or_lbfgs(const or_problem* p, int B, double* z, const double* targets,
-             const double* force, const or_lbfgs_opts* o, int* iters, int* status,
+             const double* force, const double* qbar, const or_lbfgs_opts* o, int* iters, int* status,
              double* relgrad, double* E);
 
 /* full-space Newton on the free DOFs over every mesh element (weight 1).
  * elem_psd=1 projects each 12x12 element Hessian to PSD; else the same
  * global policy as or_newton.  x (nv x 3) in/out. */
 int or_full_newton(const or_problem* p, double* x, const double* targets,
-                   const double* force, const or_opts* o, int elem_psd,
+                   const double* force, const double* qbar, const or_opts* o, int elem_psd,
                    int* iters, int* status, double* relgrad, double* E);
-/* full-space energy / gradient (nv x 3) at x */
+/* full-space energy / gradient (nv x 3) at x (qbar: n inertial target displacements, nullable) */
 double or_full_energy(const or_problem* p, const double* x, const double* targets,
-                      const double* force, double* grad);
+                      const double* force, const double* qbar, double* grad);
 
 /* Lipschitz loss of the cubature elastic Hessian over pairs (z1_b, z2_b). */
 int or_lipschitz(const or_problem* p, int B, const double* z1, const double* z2,

@@ -45,7 +45,9 @@ class _Problem(C.Structure):
                 ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp)),
                 ("S", C.c_int), ("cub_elem", _ip), ("cub_w", _dp),
                 ("nt", C.c_int), ("target_vtx", _ip), ("k_c", C.c_double),
-                ("nf", C.c_int), ("force_vtx", _ip)]
+                ("nf", C.c_int), ("force_vtx", _ip),
+                ("dt", C.c_double), ("nc", C.c_int), ("contact_vtx", _ip),
+                ("k_ground", C.c_double), ("ground_y", C.c_double)]
 
 
 class Opts(C.Structure):
@@ -215,6 +217,10 @@ class Oracle:
         s.S, s.cub_elem, s.cub_w = len(ce), _i(ce), _d(cw)
         s.nt, s.target_vtx, s.k_c = len(tv), _i(tv), p.k_c
         s.nf, s.force_vtx = len(fv), _i(fv)
+        cv = np.ascontiguousarray(getattr(p, "contact_vtx", np.zeros(0, np.int32)), dtype=np.int32); k.append(cv)
+        s.dt = float(getattr(p, "dt", 0.0))
+        s.nc, s.contact_vtx = len(cv), _i(cv)
+        s.k_ground, s.ground_y = float(getattr(p, "k_ground", 0.0)), float(getattr(p, "ground_y", 0.0))
         self.s = s
 
     @property
@@ -225,6 +231,12 @@ class Oracle:
         t = None if targets is None else _c64(targets).reshape(B, -1, 3)
         f = None if force is None else _c64(force).reshape(B, 3)
         return t, f, (_d(t) if t is not None else None), (_d(f) if f is not None else None)
+
+    def _qbar(self, B, qbar):
+        if qbar is None:
+            return None, None
+        q = _c64(qbar).reshape(B, -1)
+        return q, _d(q)
 
     def lumped_mass(self):
         m = np.zeros(self.p.X.shape[0])
@@ -246,62 +258,68 @@ class Oracle:
         lib().or_decode_hess(C.byref(self.s), _d(z), _d(T))
         return T
 
-    def reduced(self, z, targets=None, force=None, flags=EXACT):
+    def reduced(self, z, targets=None, force=None, flags=EXACT, qbar=None):
         z = _c64(np.atleast_2d(z))
         B = z.shape[0]
         t, f, tp, fp = self._loads(B, targets, force)
+        q, qp = self._qbar(B, qbar)
         E = np.zeros(B)
         g = np.zeros((B, self.r))
         H = np.zeros((B, self.r, self.r))
-        lib().or_reduced(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.c_int(flags),
+        lib().or_reduced(C.byref(self.s), C.c_int(B), _d(z), tp, fp, qp, C.c_int(flags),
                          _d(E), _d(g), _d(H))
         return E, g, H
 
-    def newton(self, z0, targets=None, force=None, opts=None):
+    def newton(self, z0, targets=None, force=None, opts=None, qbar=None):
         z = _c64(np.atleast_2d(z0)).copy()
         B = z.shape[0]
         t, f, tp, fp = self._loads(B, targets, force)
+        q, qp = self._qbar(B, qbar)
         o = opts or default_opts()
         iters = np.zeros(B, dtype=np.int32)
         status = np.zeros(B, dtype=np.int32)
         relg = np.zeros(B)
         E = np.zeros(B)
-        lib().or_newton(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
+        lib().or_newton(C.byref(self.s), C.c_int(B), _d(z), tp, fp, qp, C.byref(o), _i(iters),
                         _i(status), _d(relg), _d(E))
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
-    def lbfgs(self, z0, targets=None, force=None, opts=None):
+    def lbfgs(self, z0, targets=None, force=None, opts=None, qbar=None):
         z = _c64(np.atleast_2d(z0)).copy()
         B = z.shape[0]
         t, f, tp, fp = self._loads(B, targets, force)
+        q, qp = self._qbar(B, qbar)
         o = opts or default_lbfgs_opts()
         iters = np.zeros(B, dtype=np.int32)
         status = np.zeros(B, dtype=np.int32)
         relg = np.zeros(B)
         E = np.zeros(B)
-        rc = lib().or_lbfgs(C.byref(self.s), C.c_int(B), _d(z), tp, fp, C.byref(o), _i(iters),
+        rc = lib().or_lbfgs(C.byref(self.s), C.c_int(B), _d(z), tp, fp, qp, C.byref(o), _i(iters),
                             _i(status), _d(relg), _d(E))
         if rc:
             raise ValueError("or_lbfgs: negative history")
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
-    def full_energy(self, x, targets=None, force=None):
+    def full_energy(self, x, targets=None, force=None, qbar=None):
         x = _c64(x)
         grad = np.zeros_like(x)
         t = None if targets is None else _c64(targets)
         f = None if force is None else _c64(force)
+        q = None if qbar is None else _c64(qbar)
         E = lib().or_full_energy(C.byref(self.s), _d(x), _d(t) if t is not None else None,
-                                 _d(f) if f is not None else None, _d(grad))
+                                 _d(f) if f is not None else None, _d(q) if q is not None else None, _d(grad))
         return E, grad
 
-    def full_newton(self, x0, targets=None, force=None, opts=None, elem_psd=True):
+    def full_newton(self, x0, targets=None, force=None, opts=None, elem_psd=True, qbar=None):
         x = _c64(x0).copy()
         t = None if targets is None else _c64(targets)
         f = None if force is None else _c64(force)
+        q = None if qbar is None else _c64(qbar)
         o = opts or default_opts(rel_tol=1e-8, max_iter=200)
         it, st, rg, E = C.c_int(), C.c_int(), C.c_double(), C.c_double()
         lib().or_full_newton(C.byref(self.s), _d(x), _d(t) if t is not None else None,
-                             _d(f) if f is not None else None, C.byref(o), C.c_int(int(elem_psd)),
+                             _d(f) if f is not None else None, _d(q) if q is not None else None,
+                             C.byref(o), C.c_int(int(elem_psd)),
                              C.byref(it), C.byref(st), C.byref(rg), C.byref(E))
         return dict(x=x, iters=it.value, status=st.value, relgrad=rg.value, E=E.value)
 

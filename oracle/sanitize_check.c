@@ -119,7 +119,7 @@ int main(void)
     or_decode(&p, B, z, x, J);
     or_decode_hess(&p, z, T);
     const int flag_sets[5] = {0, OR_EXACT, OR_EXACT | OR_ELASTIC_ONLY, OR_ENERGY_ONLY, OR_ELEM_PSD};
-    for (int f = 0; f < 5; ++f) or_reduced(&p, B, z, tg, fo, flag_sets[f], E, g, H);
+    for (int f = 0; f < 5; ++f) or_reduced(&p, B, z, tg, fo, NULL, flag_sets[f], E, g, H);
     double dz[4];
     for (int proj = 0; proj < 3; ++proj) or_newton_dir(r, H, g, proj, 1e-8, dz);
     or_opts o = {20, 64, 1e-4, 0.5, 1e-6, 0.0, 1, 1, 1e-8};
@@ -127,10 +127,10 @@ int main(void)
     double rg[3];
     double zz[3 * 4];
     memcpy(zz, z, sizeof(zz));
-    or_newton(&p, B, zz, tg, fo, &o, it, st, rg, E);
+    or_newton(&p, B, zz, tg, fo, NULL, &o, it, st, rg, E);
     or_lbfgs_opts lo = {40, 64, 5, 1e-4, 0.5, 1e-6, 0.0};
     memcpy(zz, z, sizeof(zz));
-    or_lbfgs(&p, B, zz, tg, fo, &lo, it, st, rg, E);
+    or_lbfgs(&p, B, zz, tg, fo, NULL, &lo, it, st, rg, E);
     double loss, lmax, per[3];
     int nval;
     or_lipschitz(&p, B, z, z2, &loss, per, &nval, &lmax);
@@ -140,11 +140,11 @@ int main(void)
     or_energy_param_grad(&p, B, z, tg, fo, 0, E, grad);
     double xf[36], gradf[36];
     memcpy(xf, x, sizeof(xf));
-    or_full_energy(&p, xf, tg, fo, gradf);
+    or_full_energy(&p, xf, tg, fo, NULL, gradf);
     or_opts fo_opts = {20, 64, 1e-4, 0.5, 1e-8, 0.0, 1, 1, 1e-8};
     int fit, fst;
     double frg, fE;
-    or_full_newton(&p, xf, tg, fo, &fo_opts, 1, &fit, &fst, &frg, &fE);
+    or_full_newton(&p, xf, tg, fo, NULL, &fo_opts, 1, &fit, &fst, &frg, &fE);
 
     /* a linear decoder selecting every free DOF: r = 24 ... and a wider one, r = 40 */
     for (int pass = 0; pass < 2; ++pass) {
@@ -166,11 +166,11 @@ int main(void)
         double* zl = (double*)calloc(rl, sizeof(double));
         for (int k = 0; k < rl; ++k) zl[k] = 0.01 * uniform_pm1();
         double El, *gl = (double*)malloc(sizeof(double) * rl), *Hl = (double*)malloc(sizeof(double) * rl * rl);
-        or_reduced(&q, 1, zl, tg, fo, OR_EXACT, &El, gl, Hl);
+        or_reduced(&q, 1, zl, tg, fo, NULL, OR_EXACT, &El, gl, Hl);
         int itl, stl;
         double rgl;
-        or_lbfgs(&q, 1, zl, tg, fo, &lo, &itl, &stl, &rgl, &El);
-        or_newton(&q, 1, zl, tg, fo, &o, &itl, &stl, &rgl, &El);
+        or_lbfgs(&q, 1, zl, tg, fo, NULL, &lo, &itl, &stl, &rgl, &El);
+        or_newton(&q, 1, zl, tg, fo, NULL, &o, &itl, &stl, &rgl, &El);
         free(free_rows); free(Wl); free(bl); free(zl); free(gl); free(Hl);
     }
     free(grad);

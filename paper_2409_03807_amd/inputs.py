@@ -187,6 +187,11 @@ class Problem:
     k_c: float
     force_vtx: np.ndarray    # (nf,) int32  vertices that receive the bend force
     meta: dict = field(default_factory=dict)
+    # implicit Euler (dt > 0) and ground contact on contact_vtx (plane y = ground_y)
+    dt: float = 0.0
+    contact_vtx: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    k_ground: float = 0.0
+    ground_y: float = 0.0
 
     @property
     def nv(self):
