@@ -127,21 +127,35 @@ typedef struct {
     const double* weight;
 } rs_cubature;
 
-/* Penalty-targeted vertices with stiffness k_c (N/m), and force-loaded vertices. */
+/* Penalty-targeted vertices with stiffness k_c (N/m), force-loaded vertices,
+ * and ground contact: the one-sided penalty k_ground/2 min(0, y_v - ground_y)^2
+ * (N/m, m) on each contact vertex v (the y coordinate is "up"; contact treated
+ * as part of the potential, Sec. 5.2's penalty collisions).  n_contact = 0: no
+ * ground. */
 typedef struct {
     int32_t n_target;
     const int32_t* target_vtx;
     double k_c;
     int32_t n_force;
     const int32_t* force_vtx;
+    int32_t n_contact;
+    const int32_t* contact_vtx;
+    double k_ground;
+    double ground_y;
 } rs_constraints;
 
-/* Per-batch loads (DEVICE pointers, float64, either may be NULL):
+/* Per-batch loads (DEVICE pointers, float64, each may be NULL):
  * targets (B x n_target x 3) positions of the targeted vertices; force (B x 3)
- * the force applied to each force-loaded vertex. */
+ * the force applied to each force-loaded vertex; qbar (B x nv x 3) the
+ * inertial targets of an implicit-Euler step (displacements q_bar - X, Sec.
+ * 3.1, Eq. form-reduced-space-time-integration), used when dt > 0: the
+ * objective gains 1/(2 dt^2) |q(z) - q_bar|_M^2 over the free rows (M the
+ * lumped masses).  qbar = NULL or dt = 0: quasi-static. */
 typedef struct {
     const double* targets;
     const double* force;
+    const double* qbar;
+    double dt;
 } rs_load;
 
 /* Newton options (host struct).  Defaults from rs_default_opts(). */
@@ -345,6 +359,22 @@ int rs_lipschitz_param_grad(rs_ctx* ctx, int32_t B, const double* z1, const doub
 #define RS_STATIC_SCRATCH_BYTES (64u << 20)
 int rs_lipschitz_param_grad_noalloc(rs_ctx* ctx, int32_t B, const double* z1, const double* z2, double* loss,
                                     double* grad, void* stream);
+
+/* Implicit-Euler simulation (Sec. 3.1, Eq. form-reduced-space-time-integration):
+ * `steps` time steps of B independent simulations from z (B x r, DEVICE,
+ * in/out: the start, then the last step's solution) with initial velocities v0
+ * (B x nv x 3 displacement rates, DEVICE; NULL = at rest).  Step k minimises
+ *   1/(2 dt^2) |q(z) - q_bar^(k+1)|_M^2 + P~(q(z)) + gravity, penalty targets,
+ *   forces and ground contact (the load's targets and force, constant in time),
+ * with q_bar^1 = q^0 + dt v0 and q_bar^(k+1) = 2 q^k - q^(k-1) (the positions of
+ * the previous steps; both lie in the decoder's range, so the inertia term is
+ * formed from the last hidden activations), by the projective Newton solve of
+ * rs_newton_solve with `opts` (NULL = defaults).  Per item: iters (the Newton
+ * iterations of all steps) and failed (the steps not ending on RS_CONVERGED),
+ * int32 DEVICE; ztraj (steps x B x r, DEVICE, may be NULL) the solution of every
+ * step.  Errors: as rs_newton_solve, RS_ERR_ARG (steps < 0, dt <= 0). */
+int rs_simulate(rs_ctx* ctx, int32_t B, double* z, const double* v0, const rs_load* load, int32_t steps, double dt,
+                const rs_solve_opts* opts, int32_t* iters, int32_t* failed, double* ztraj, void* stream);
 
 /* ---- full-space solver ----
  * Quasi-static equilibrium over EVERY element of the mesh (Sec. 3.1, Eq.

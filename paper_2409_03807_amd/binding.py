@@ -49,7 +49,9 @@ class _Cubature(C.Structure):
 
 class _Constraints(C.Structure):
     _fields_ = [("n_target", C.c_int32), ("target_vtx", _ip), ("k_c", C.c_double),
-                ("n_force", C.c_int32), ("force_vtx", _ip)]
+                ("n_force", C.c_int32), ("force_vtx", _ip),
+                ("n_contact", C.c_int32), ("contact_vtx", _ip), ("k_ground", C.c_double),
+                ("ground_y", C.c_double)]
 
 
 class _Mlp(C.Structure):
@@ -58,7 +60,7 @@ class _Mlp(C.Structure):
 
 
 class _Load(C.Structure):
-    _fields_ = [("targets", C.c_void_p), ("force", C.c_void_p)]
+    _fields_ = [("targets", C.c_void_p), ("force", C.c_void_p), ("qbar", C.c_void_p), ("dt", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -95,7 +97,7 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
            "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
            "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam",
-           "rs_default_full_opts", "rs_full_solve", "rs_pca"]
+           "rs_default_full_opts", "rs_full_solve", "rs_pca", "rs_simulate"]
 
 _lib = None
 
@@ -146,6 +148,8 @@ def load_library():
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_trainer_adam.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.rs_default_full_opts.argtypes = [C.POINTER(FullOpts)]
+        L.rs_simulate.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(_Load), C.c_int32,
+                                  C.c_double, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_pca.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_full_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.POINTER(FullOpts),
@@ -236,7 +240,10 @@ class Context:
         ce, cw = i32(p.cub_elem), f64(p.cub_w)
         cub = _Cubature(len(ce), ce.ctypes.data_as(_ip), cw.ctypes.data_as(_dp))
         tv, fv = i32(p.target_vtx), i32(p.force_vtx)
-        con = _Constraints(len(tv), tv.ctypes.data_as(_ip), p.k_c, len(fv), fv.ctypes.data_as(_ip))
+        cv = i32(getattr(p, "contact_vtx", np.zeros(0, np.int32)))
+        con = _Constraints(len(tv), tv.ctypes.data_as(_ip), p.k_c, len(fv), fv.ctypes.data_as(_ip),
+                           len(cv), cv.ctypes.data_as(_ip), float(getattr(p, "k_ground", 0.0)),
+                           float(getattr(p, "ground_y", 0.0)))
         ctx = C.c_void_p()
         rc = L.rs_create(C.byref(mesh), C.byref(mat), C.byref(dec), C.byref(cub), C.byref(con),
                          prec, max_batch, C.byref(ctx))
@@ -347,10 +354,12 @@ class Context:
                                                         _ptr(grad), _stream()), "rs_energy_param_grad")
         return E, g, grad
 
-    def _load(self, B, targets, force):
+    def _load(self, B, targets, force, qbar=None, dt=0.0):
         t = _dev(targets, torch.float64, (B, self.nt, 3), "targets")
         f = _dev(force, torch.float64, (B, 3), "force")
-        return _Load(t.data_ptr() if t is not None else None, f.data_ptr() if f is not None else None), (t, f)
+        q = _dev(qbar, torch.float64, (B, self.nv, 3), "qbar")
+        return _Load(t.data_ptr() if t is not None else None, f.data_ptr() if f is not None else None,
+                     q.data_ptr() if q is not None else None, float(dt)), (t, f, q)
 
     def decode(self, z, want_x=True, want_J=True):
         B = z.shape[0]
@@ -360,10 +369,10 @@ class Context:
         self._check(load_library().rs_decode(self.ctx, B, _ptr(z), _ptr(x), _ptr(J), _stream()), "rs_decode")
         return x, J
 
-    def energy_grad_hess(self, z, targets=None, force=None, flags=HESS_EXACT):
+    def energy_grad_hess(self, z, targets=None, force=None, flags=HESS_EXACT, qbar=None, dt=0.0):
         B = z.shape[0]
         _dev(z, torch.float64, (B, self.r), "z")
-        ld, _keep = self._load(B, targets, force)
+        ld, _keep = self._load(B, targets, force, qbar, dt)
         E = torch.empty(B, dtype=torch.float64, device=z.device)
         eonly = bool(flags & ENERGY_ONLY)
         g = None if eonly else torch.empty((B, self.r), dtype=torch.float64, device=z.device)
@@ -386,19 +395,21 @@ class Context:
         self._dump = He
         self._check(load_library().rs_set_elem_hess_dump(self.ctx, _ptr(He), He.shape[0]), "rs_set_elem_hess_dump")
 
-    def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None):
+    def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None, qbar=None,
+                     dt=0.0):
         """z0 (B x r) float64 on the GPU; returns dict of device tensors.
-        `out` may pass preallocated (z, iters, status, relgrad, E) tensors."""
-        return self._solve("rs_newton_solve", z0, targets, force, opts or default_opts(), out)
+        `out` may pass preallocated (z, iters, status, relgrad, E) tensors; qbar
+        (B x nv x 3) and dt > 0 make it one implicit-Euler step."""
+        return self._solve("rs_newton_solve", z0, targets, force, opts or default_opts(), out, qbar, dt)
 
     def lbfgs_solve(self, z0, targets=None, force=None, opts: LbfgsOpts | None = None, out=None):
         """As newton_solve, with the L-BFGS solver."""
         return self._solve("rs_lbfgs_solve", z0, targets, force, opts or default_lbfgs_opts(), out)
 
-    def _solve(self, fn, z0, targets, force, o, out):
+    def _solve(self, fn, z0, targets, force, o, out, qbar=None, dt=0.0):
         B = z0.shape[0]
         _dev(z0, torch.float64, (B, self.r), "z0")
-        ld, _keep = self._load(B, targets, force)
+        ld, _keep = self._load(B, targets, force, qbar, dt)
         if out is None:
             z = z0.clone()
             iters = torch.empty(B, dtype=torch.int32, device=z0.device)
@@ -412,12 +423,31 @@ class Context:
                                                 _ptr(status), _ptr(relg), _ptr(E), _stream()), fn)
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 
-    def full_solve(self, u0, targets=None, force=None, opts: FullOpts | None = None):
+    def simulate(self, z0, steps, dt, v0=None, targets=None, force=None, opts: SolveOpts | None = None,
+                 want_traj=True):
+        """Implicit-Euler simulation of B items (rs_simulate): dict of device tensors
+        z (last step), iters and failed per item, traj (steps x B x r) when wanted."""
+        B = z0.shape[0]
+        _dev(z0, torch.float64, (B, self.r), "z0")
+        _dev(v0, torch.float64, (B, self.nv, 3), "v0")
+        ld, _keep = self._load(B, targets, force)
+        z = z0.clone()
+        dev = z0.device
+        iters = torch.empty(B, dtype=torch.int32, device=dev)
+        failed = torch.empty(B, dtype=torch.int32, device=dev)
+        traj = torch.empty((steps, B, self.r), dtype=torch.float64, device=dev) if want_traj else None
+        o = opts or default_opts()
+        self._check(load_library().rs_simulate(self.ctx, B, _ptr(z), _ptr(v0), C.byref(ld), steps, float(dt),
+                                               C.byref(o), _ptr(iters), _ptr(failed), _ptr(traj), _stream()),
+                    "rs_simulate")
+        return dict(z=z, iters=iters, failed=failed, traj=traj)
+
+    def full_solve(self, u0, targets=None, force=None, opts: FullOpts | None = None, qbar=None, dt=0.0):
         """Full-space equilibria of B load cases from displacements u0 (B x nv x 3, float64,
         device); returns dict of device tensors (u, iters, status, relgrad, E)."""
         B = u0.shape[0]
         _dev(u0, torch.float64, (B, self.nv, 3), "u0")
-        ld, _keep = self._load(B, targets, force)
+        ld, _keep = self._load(B, targets, force, qbar, dt)
         u = u0.clone()
         dev = u0.device
         iters = torch.empty(B, dtype=torch.int32, device=dev)

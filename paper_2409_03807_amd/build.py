@@ -7,7 +7,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "librs.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("rs_api.cpp", "rs_kernels.hip", "rs_elem_opts.hip", "rs_learn.hip", "rs_full.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("rs_api.cpp", "rs_kernels.hip", "rs_elem_opts.hip", "rs_learn.hip", "rs_full.hip", "rs_dyn.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

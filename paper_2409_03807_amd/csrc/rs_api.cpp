@@ -32,12 +32,13 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_ELEM_PSD, K_ELEM_DUMP, K_LIP_GRAD, K_TRAIN, K_COUNT
+    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_ELEM_PSD, K_ELEM_DUMP, K_LIP_GRAD, K_TRAIN, K_DYN, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
-    "newton_init", "activate", "lbfgs_dir", "param_grad", "elem_psd", "elem_hess_dump", "lipschitz_grad", "train"};
+    "newton_init", "activate", "lbfgs_dir", "param_grad", "elem_psd", "elem_hess_dump", "lipschitz_grad", "train",
+    "dynamics"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -99,6 +100,7 @@ struct rs_ctx {
     void* Wfull16 = nullptr;
     double* Wbig64 = nullptr; double* bbig64 = nullptr;
     void* Wfull = nullptr; void* bfull = nullptr; void* Xfull = nullptr;
+    double* Wfull64 = nullptr; double* bfull64 = nullptr; // float64 output layer (the inertia term's G and c)
     double* wV = nullptr; double* Xt = nullptr;
     double* ec = nullptr;         // S x kElemConst: per-element constants of the optional element treatments
     double* dump_He = nullptr;    // RS_DEBUG_ELEM_HESS destination (caller-owned), dump_max items
@@ -142,6 +144,23 @@ struct rs_ctx {
     LipWs lip;                    // Lipschitz-loss gradient workspace (allocated by its first call)
     void* scratch = nullptr;      // device address of this device's static scratch array
     FullSolver* full = nullptr;   // full-space solver (created by its first call)
+    // ground contact and implicit-Euler inertia
+    int ncont = 0, crow = 0;      // contact vertices; first contact row of W_big (the y row of each)
+    double k_ground = 0.0, ground_y = 0.0;
+    std::vector<int> cvtx;
+    double* Xc = nullptr;         // ncont: rest y of the contact vertices
+    double* Gdyn = nullptr;       // in_last x in_last: W_out^T M W_out (free rows), float64
+    bool G_dirty = true;          // the decoder changed since Gdyn was formed
+    double* dyn_c = nullptr;      // max_batch x in_last: W_out^T M (qbar - b_out) per item
+    double* dyn_kappa = nullptr;  // max_batch: |qbar - b_out|_M^2 per item
+    double* dyn_eta = nullptr;    // max_batch x in_last: the target's range coefficients (simulations)
+    int dyn_use_eta = 0;
+    int dyn_inertia = 0;          // the current call has an inertia term
+    double dyn_inv_dt2 = 0.0;
+    // simulation state (rs_simulate), max_batch items each
+    double *sim_h0 = nullptr, *sim_h1 = nullptr, *sim_cv0 = nullptr, *sim_kv0 = nullptr;
+    double *sim_relg = nullptr, *sim_E = nullptr;
+    int *sim_it = nullptr, *sim_st = nullptr;
     int* fold_ptr = nullptr;      // n_out + 1: CSR of the output-layer fold by W_out row
     int* fold_row = nullptr;      // W_big row of each entry
     double* fold_coef = nullptr;  // its coefficient
@@ -234,6 +253,12 @@ static int run(rs_ctx* c, int kind, const Work& w, hipStream_t s, F&& f)
     do {                           \
         int rc_ = (x);             \
         if (rc_ != RS_OK) return rc_; \
+    } while (0)
+
+#define RS_HIP(x, what)                                      \
+    do {                                                     \
+        hipError_t e_ = (x);                                 \
+        if (e_ != hipSuccess) return hip_fail(c, e_, what);  \
     } while (0)
 
 // ------------------------------------------------------------------ layouts
@@ -425,6 +450,12 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
             for (int k = 0; k < in_last; ++k) Wb[(size_t)(c->force_row + i) * lda + k] += wout(vrow, k);
             bb[c->force_row + i] += bout(vrow);
         }
+    for (int t = 0; t < c->ncont; ++t) {
+        const int vrow = 3 * c->cvtx[t] + 1;
+        for (int k = 0; k < in_last; ++k) Wb[(size_t)(c->crow + t) * lda + k] = wout(vrow, k);
+        bb[c->crow + t] = bout(vrow);
+    }
+    c->G_dirty = true;
     RS_TRY(upload(c, c->Wbig64, Wb, 0));
     RS_TRY(upload(c, c->bbig64, bb, 0));
     if (c->f32) {
@@ -445,8 +476,10 @@ static int load_decoder(rs_ctx* c, const rs_decoder* d)
         Xf[row] = c->X[row];
     }
     RS_TRY(upload(c, c->Wfull, Wf, c->f32));
+    if (c->f32) RS_TRY(upload(c, c->Wfull64, Wf, 0));
     if (c->bf16) RS_TRY(upload_bf16(c, c->Wfull16, Wf));
     RS_TRY(upload(c, c->bfull, bf, c->f32));
+    if (c->f32) RS_TRY(upload(c, c->bfull64, bf, 0));
     RS_TRY(upload(c, c->Xfull, Xf, c->f32));
     return RS_OK;
 }
@@ -588,6 +621,19 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
         if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "target vertex out of range"));
     for (int v : c->fvtx)
         if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "force vertex out of range"));
+    {
+        const int ncn = con ? con->n_contact : 0;
+        if (ncn < 0 || (ncn && !con->contact_vtx)) return bail(fail(c, RS_ERR_ARG, "bad contact set"));
+        if (ncn && !(con->k_ground >= 0.0)) return bail(fail(c, RS_ERR_ARG, "negative ground stiffness"));
+        c->ncont = ncn;
+        if (ncn) {
+            c->cvtx.assign(con->contact_vtx, con->contact_vtx + ncn);
+            c->k_ground = con->k_ground;
+            c->ground_y = con->ground_y;
+        }
+        for (int v : c->cvtx)
+            if (v < 0 || v >= c->nv) return bail(fail(c, RS_ERR_ARG, "contact vertex out of range"));
+    }
 
     // rest shape: lumped masses over every tet, Dm^-1 and volume per cubature tet
     c->mass.assign(c->nv, 0.0);
@@ -621,10 +667,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->lda_out = round_up(c->in_last, kTileK);
     c->wrows = round_up(std::max(c->w, 1), kTileM);
     c->in_rows = round_up(c->in_last, kTileM);
-    c->M = 9 * c->S + 3 * c->nt + 4;
+    c->M = 9 * c->S + 3 * c->nt + 4 + c->ncont;
     c->Mp = round_up(c->M, kTileM);
     c->grav_row = 9 * c->S + 3 * c->nt;
     c->force_row = c->grav_row + 1;
+    c->crow = c->force_row + 3;
     c->Nfp = round_up(c->n_out, kTileM);
 
     // device allocations
@@ -653,6 +700,7 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->bbig = c->f32 ? need(dalloc_bytes(c, (size_t)c->Mp * ts)) : c->bbig64;
     c->WbigT = need(dalloc_bytes(c, (size_t)c->in_rows * c->Mp * ts));
     c->Wfull = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * ts));
+    c->Wfull64 = c->f32 ? (double*)need(dalloc<double>(c, (size_t)c->Nfp * c->lda_out)) : (double*)c->Wfull;
     if (c->bf16) {
         // BF16 operands need the fused hidden-layer kernel and a K that fills 32-deep chunks
         if (c->L == 0 || !mlp_fits(1, (int)nc, c->r, c->wrows) || !mlp_fits(1, 1, c->r, c->wrows))
@@ -666,9 +714,23 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
         c->Wfull16 = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * 2));
     }
     c->bfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
+    c->bfull64 = c->f32 ? (double*)need(dalloc<double>(c, (size_t)c->n_out)) : (double*)c->bfull;
     c->Xfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
     c->wV = (double*)need(dalloc<double>(c, c->S));
     c->Xt = (double*)need(dalloc<double>(c, 3 * (size_t)std::max(c->nt, 1)));
+    c->Xc = (double*)need(dalloc<double>(c, (size_t)std::max(c->ncont, 1)));
+    c->Gdyn = (double*)need(dalloc<double>(c, (size_t)c->in_last * c->in_last));
+    c->dyn_c = (double*)need(dalloc<double>(c, B * c->in_last));
+    c->dyn_kappa = (double*)need(dalloc<double>(c, B));
+    c->dyn_eta = (double*)need(dalloc<double>(c, B * c->in_last));
+    c->sim_h0 = (double*)need(dalloc<double>(c, B * c->in_last));
+    c->sim_h1 = (double*)need(dalloc<double>(c, B * c->in_last));
+    c->sim_cv0 = (double*)need(dalloc<double>(c, B * c->in_last));
+    c->sim_kv0 = (double*)need(dalloc<double>(c, B));
+    c->sim_relg = (double*)need(dalloc<double>(c, B));
+    c->sim_E = (double*)need(dalloc<double>(c, B));
+    c->sim_it = (int*)need(dalloc<int>(c, B));
+    c->sim_st = (int*)need(dalloc<int>(c, B));
     c->ec = (double*)need(dalloc<double>(c, (size_t)c->S * kElemConst));
     c->out = need(dalloc_bytes(c, B * c->Mp * nc * ts));
     c->act = need(dalloc_bytes(c, B * c->wrows * nc * ts));
@@ -756,6 +818,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
             for (int i = 0; i < 3; ++i) xt[3 * t + i] = c->X[3 * c->tvtx[t] + i];
         if (upload(c, c->Xt, xt, 0) != RS_OK) return bail(RS_ERR_HIP);
     }
+    if (c->ncont) {
+        std::vector<double> xc(c->ncont);
+        for (int t = 0; t < c->ncont; ++t) xc[t] = c->X[3 * c->cvtx[t] + 1];
+        if (upload(c, c->Xc, xc, 0) != RS_OK) return bail(RS_ERR_HIP);
+    }
     if (load_decoder(c, dec) != RS_OK) return bail(RS_ERR_HIP);
     {
         const int rc = build_fold(c);
@@ -788,6 +855,7 @@ static int build_fold(rs_ctx* c)
         for (int i = 0; i < 3; ++i) add(3 * v + i, c->grav_row, c->mass[v] * c->grav[i]);
     for (int t = 0; t < c->nf; ++t)
         for (int i = 0; i < 3; ++i) add(3 * c->fvtx[t] + i, c->force_row + i, 1.0);
+    for (int t = 0; t < c->ncont; ++t) add(3 * c->cvtx[t] + 1, c->crow + t, 1.0);
     {
         // the same fold by W_big row, entries in the order the host load sums them
         std::vector<std::vector<std::pair<int, double>>> fw(c->M);
@@ -808,6 +876,7 @@ static int build_fold(rs_ctx* c)
             for (int i = 0; i < 3; ++i) addf(3 * v + i, c->grav_row, c->mass[v] * c->grav[i]);
         for (int t = 0; t < c->nf; ++t)
             for (int i = 0; i < 3; ++i) addf(3 * c->fvtx[t] + i, c->force_row + i, 1.0);
+        for (int t = 0; t < c->ncont; ++t) addf(3 * c->cvtx[t] + 1, c->crow + t, 1.0);
         std::vector<int> fp(c->M + 1, 0), fs;
         std::vector<double> fc;
         for (int m = 0; m < c->M; ++m) {
@@ -1037,6 +1106,65 @@ static ElemOptArgs elem_opt_args(const rs_ctx* c, const void* out, int nc, const
 // the curvature term.  `cap` items fit the launch; `count` (device, nullable)
 // holds the actual number.  Item i uses latent point z[zmap[i]] and the loads
 // of batch index imap[i].
+// ------------------------------------------------------------------ dynamics and contact
+// Per call: the inertia term's per-item vectors from the inertial targets of B
+// items (W_out^T M (qbar - b_out) and |qbar - b_out|_M^2), forming G = W_out^T M
+// W_out first when the decoder changed.  No inertia when qbar is NULL or dt <= 0.
+static int dyn_setup(rs_ctx* c, const rs_load* load, int B, int b0, hipStream_t s)
+{
+    c->dyn_inertia = 0;
+    if (!load || !load->qbar || !(load->dt > 0.0)) return RS_OK;
+    if (B > c->max_batch) return fail(c, RS_ERR_ARG, "inertial targets for more than max_batch items");
+    if (c->G_dirty) {
+        RS_HIP(launch_dyn_gram(0, c->Wfull64, c->lda_out, c->n_out, c->row_mass, c->in_last, c->Gdyn, s),
+               "inertia Gram matrix");
+        c->G_dirty = false;
+    }
+    RS_HIP(launch_dyn_prep(0, c->Wfull64, c->lda_out, c->bfull64, c->pinned_row, c->row_mass, c->n_out, c->in_last,
+                           load->qbar + (size_t)b0 * c->n_out, B, c->dyn_c, c->dyn_kappa, s),
+           "inertia targets");
+    c->dyn_inertia = 1;
+    c->dyn_use_eta = 0;
+    c->dyn_inv_dt2 = 1.0 / (load->dt * load->dt);
+    return RS_OK;
+}
+
+static bool dyn_active(const rs_ctx* c, uint32_t flags)
+{
+    return !(flags & RS_ELASTIC_ONLY) && (c->dyn_inertia || c->ncont > 0);
+}
+
+static DynArgs dyn_args(const rs_ctx* c, const int* count, const int* imap, const double* z, const int* zmap,
+                        const void* act, const void* out, int nc)
+{
+    DynArgs a{};
+    a.count = count;
+    a.imap = imap;
+    a.zmap = zmap;
+    a.z = z;
+    a.L = c->L;
+    a.r = c->r;
+    a.in_last = c->in_last;
+    a.nc = nc;
+    a.act = c->L > 0 ? act : nullptr;
+    a.wrows = c->wrows;
+    a.out = out;
+    a.rows_pad = c->Mp;
+    a.crow = c->crow;
+    a.ncont = c->ncont;
+    a.Xc = c->Xc;
+    a.k_ground = c->k_ground;
+    a.ground_y = c->ground_y;
+    a.G = c->Gdyn;
+    a.eta = c->dyn_use_eta ? c->dyn_eta : nullptr;
+    a.cvec = c->dyn_c;
+    a.kappa = c->dyn_kappa;
+    a.inv_dt2 = c->dyn_inv_dt2;
+    a.inertia = c->dyn_inertia;
+    a.in_rows = c->in_rows;
+    return a;
+}
+
 static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const int* zmap, const double* targets,
                   const double* force, const int* imap, uint32_t flags, double* E, double* g, double* H,
                   hipStream_t s)
@@ -1125,6 +1253,12 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         const double pf = (double)c->S * (18.0 * r * r + 80.0 * r + 150.0);
         RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_elem(f32, a, cap, s); }));
     }
+    const bool dyn = dyn_active(c, flags) && (g || H || E);
+    if (dyn && exact && c->ncont > 0) {
+        DynArgs d = dyn_args(c, count, imap, z, zmap, c->act, c->out, nc);
+        d.dseed = c->dseed;
+        RS_TRY(run(c, K_DYN, Work{}, s, [&] { return launch_dyn(f32, 0, d, cap, s); }));
+    }
     if (exact) {
         GemmArgs a{};
         a.A = c->WbigT;
@@ -1145,6 +1279,11 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         a.split_stride = (size_t)c->max_batch * c->in_rows;
         RS_TRY(run(c, K_GEMM_ADJ, gemm_work(ts, c->in_last, c->Mp, cap, 1, count, slot, 0), s,
                    [&] { return launch_gemm(f32, ROLE_ADJ, a, s); }));
+        if (dyn && c->dyn_inertia) {
+            DynArgs d = dyn_args(c, count, imap, z, zmap, c->act, c->out, nc);
+            d.gbar = c->gbar;
+            RS_TRY(run(c, K_DYN, Work{}, s, [&] { return launch_dyn(f32, 1, d, cap, s); }));
+        }
         CurvArgs ca{};
         for (int l = 0; l < c->L; ++l) {
             ca.pre[l] = c->pre[l];
@@ -1186,6 +1325,13 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         const double pf = (double)c->S * (9.0 * 81 * 2 + 6.0 * 36 * 54);
         RS_TRY(run(c, K_ELEM_PSD, item_work(pb, pf, cap, count, slot, 0), s,
                    [&] { return launch_elem_psd(f32, o, cap, s); }));
+    }
+    if (dyn) {
+        DynArgs d = dyn_args(c, count, imap, z, zmap, c->act, c->out, nc);
+        d.E = E;
+        d.g = g;
+        d.H = H;
+        RS_TRY(run(c, K_DYN, Work{}, s, [&] { return launch_dyn(f32, 2, d, cap, s); }));
     }
     return RS_OK;
 }
@@ -1359,8 +1505,14 @@ static int energy_f64(rs_ctx* c, int cap, const int* count, int which, const dou
     e.grav_row = c->grav_row;
     e.force_row = c->force_row;
     e.E = E;
-    return run(c, K_ENERGY, item_work(8.0 * c->M + 8.0, (double)c->S * 60.0, cap, count, slot, which), s,
-               [&] { return launch_energy(e, cap, s); });
+    RS_TRY(run(c, K_ENERGY, item_work(8.0 * c->M + 8.0, (double)c->S * 60.0, cap, count, slot, which), s,
+               [&] { return launch_energy(e, cap, s); }));
+    if (!elastic_only && (c->dyn_inertia || c->ncont > 0)) {
+        DynArgs d = dyn_args(c, count, imap, z, nullptr, c->act64, c->out64, 1);
+        d.E = E;
+        RS_TRY(run(c, K_DYN, Work{}, s, [&] { return launch_dyn(0, 3, d, cap, s); }));
+    }
+    return RS_OK;
 }
 
 extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const rs_load* load,
@@ -1388,6 +1540,9 @@ extern "C" int rs_energy_grad_hess(rs_ctx* c, int32_t B, const double* z, const 
         const double* zc = z + (size_t)c0 * r;
         const double* tgc = tg ? tg + (size_t)c0 * c->nt * 3 : nullptr;
         const double* foc = fo ? fo + (size_t)c0 * 3 : nullptr;
+        RS_TRY(dyn_setup(c, load, n, c0, s));
+        if (!eonly && rev && dyn_active(c, flags))
+            return fail(c, RS_ERR_UNSUPPORTED, "RS_GRAD_REVERSE has no inertia or contact term");
         if (!eonly && rev)
             RS_TRY(eval_grad_rev(c, n, nullptr, zc, nullptr, tgc, foc, nullptr, flags, c->f32 ? nullptr : E + c0,
                                  g + (size_t)c0 * r, s));
@@ -1428,6 +1583,9 @@ extern "C" int rs_param_count(const rs_ctx* c, int64_t* n)
 extern "C" int rs_energy_param_grad(rs_ctx* c, int32_t B, const double* z, const rs_load* load, uint32_t flags,
                                     double* E, double* g, double* grad, void* stream)
 {
+    if (c && (c->ncont > 0 || (load && load->qbar && load->dt > 0.0)))
+        return fail(c, RS_ERR_UNSUPPORTED, "the parameter gradient has no inertia or contact term");
+    if (c) c->dyn_inertia = 0;
     if (!c) return RS_ERR_STATE;
     if (B < 0) return fail(c, RS_ERR_ARG, "B must be >= 0");
     if (!grad) return fail(c, RS_ERR_ARG, "grad is NULL");
@@ -1715,7 +1873,95 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     p.abs_tol = o->abs_tol;
     p.eig_floor = o->eig_floor;
     const uint32_t hflags = ((o->hess & 1) ? RS_HESS_EXACT : 0u) | ((o->hess & 2) ? RS_ELEM_PSD : 0u);
+    RS_TRY(dyn_setup(c, load, B, 0, static_cast<hipStream_t>(stream)));
     return solve_batch(c, B, z, load, p, hflags, false, iters, status, relgrad, E, stream);
+}
+
+// The last hidden activation of B latent points in float64 (the value pass of the
+// line-search energies; z itself for a linear decoder) into h (B x in_last).
+static int h_of_z(rs_ctx* c, int B, const double* z, double* h, hipStream_t s)
+{
+    if (c->L > 0) {
+        std::vector<void*> pre64(c->pre64.begin(), c->pre64.end());
+        std::vector<const void*> W64(c->W64.begin(), c->W64.end()), b64(c->bh64.begin(), c->bh64.end());
+        RS_TRY(hidden_layers(c, 0, 1, B, nullptr, 0, z, nullptr,
+                             mlp_fits(0, 1, c->r, c->wrows) ? nullptr : pre64.data(), c->act64, W64.data(),
+                             b64.data(), K_LS_GEMM_HIDDEN, s));
+    }
+    RS_HIP(launch_dyn_take_h(c->L > 0 ? c->act64 : nullptr, c->wrows, z, c->in_last, B, h, s), "simulation state");
+    return RS_OK;
+}
+
+extern "C" int rs_simulate(rs_ctx* c, int32_t B, double* z, const double* v0, const rs_load* load, int32_t steps,
+                           double dt, const rs_solve_opts* o, int32_t* iters, int32_t* failed, double* ztraj,
+                           void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
+    if (steps < 0 || !(dt > 0.0)) return fail(c, RS_ERR_ARG, "steps must be >= 0 and dt > 0");
+    if (B == 0) return RS_OK;
+    if (!z || !iters || !failed) return fail(c, RS_ERR_ARG, "NULL pointer");
+    rs_solve_opts def;
+    rs_default_opts(&def);
+    if (!o) o = &def;
+    if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
+        o->proj < 0 || o->proj > 2 || o->hess < 0 || o->hess > 3)
+        return fail(c, RS_ERR_ARG, "invalid solver options");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    NewtonParams p{};
+    p.r = c->r;
+    p.max_iter = o->max_iter;
+    p.ls_max = o->ls_max;
+    p.proj = o->proj;
+    p.c1 = o->c1;
+    p.shrink = o->shrink;
+    p.rel_tol = o->rel_tol;
+    p.abs_tol = o->abs_tol;
+    p.eig_floor = o->eig_floor;
+    const uint32_t hflags = ((o->hess & 1) ? RS_HESS_EXACT : 0u) | ((o->hess & 2) ? RS_ELEM_PSD : 0u);
+    rs_load ld{};
+    if (load) {
+        ld.targets = load->targets;
+        ld.force = load->force;
+    }
+    const int m = c->in_last;
+    if (c->G_dirty) {
+        RS_HIP(launch_dyn_gram(0, c->Wfull64, c->lda_out, c->n_out, c->row_mass, m, c->Gdyn, s),
+               "inertia Gram matrix");
+        c->G_dirty = false;
+    }
+    RS_HIP(launch_zero_int(iters, B, s), "fill");
+    RS_HIP(launch_zero_int(failed, B, s), "fill");
+    // first step: the inertial target u^0 + dt v0
+    RS_TRY(h_of_z(c, B, z, c->sim_h0, s));
+    if (v0)
+        RS_HIP(launch_dyn_prep(0, c->Wfull64, c->lda_out, nullptr, c->pinned_row, c->row_mass, c->n_out, m, v0, B,
+                               c->sim_cv0, c->sim_kv0, s),
+               "initial velocity");
+    RS_HIP(launch_dyn_state(m, c->sim_h0, nullptr, v0 ? c->sim_cv0 : nullptr, v0 ? c->sim_kv0 : nullptr, dt, B,
+                            c->dyn_eta, c->dyn_c, c->dyn_kappa, s),
+           "simulation state");
+    double* hp = c->sim_h0;
+    double* hn = c->sim_h1;
+    for (int k = 0; k < steps; ++k) {
+        c->dyn_inertia = 1;
+        c->dyn_use_eta = 1;
+        c->dyn_inv_dt2 = 1.0 / (dt * dt);
+        RS_TRY(solve_batch(c, B, z, &ld, p, hflags, false, c->sim_it, c->sim_st, c->sim_relg, c->sim_E, stream));
+        RS_HIP(launch_sim_count(c->sim_it, c->sim_st, B, iters, failed, s), "simulation counts");
+        if (ztraj &&
+            hipMemcpyAsync(ztraj + (size_t)k * B * c->r, z, sizeof(double) * B * c->r, hipMemcpyDeviceToDevice, s) !=
+                hipSuccess)
+            return fail(c, RS_ERR_HIP, "hipMemcpyAsync");
+        // next inertial target 2 u^(k+1) - u^k, in the decoder's range
+        RS_TRY(h_of_z(c, B, z, hn, s));
+        RS_HIP(launch_dyn_state(m, hp, hn, nullptr, nullptr, dt, B, c->dyn_eta, c->dyn_c, c->dyn_kappa, s),
+               "simulation state");
+        std::swap(hp, hn);
+    }
+    c->dyn_inertia = 0;
+    c->dyn_use_eta = 0;
+    return RS_OK;
 }
 
 extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_lbfgs_opts* o,
@@ -1731,6 +1977,9 @@ extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* lo
     if (o->max_iter < 0 || o->ls_max < 0 || o->history < 0 || o->history > RS_MAX_HISTORY ||
         !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0))
         return fail(c, RS_ERR_ARG, "invalid solver options");
+    c->dyn_inertia = 0;
+    if (c->ncont > 0 || (load && load->qbar && load->dt > 0.0))
+        return fail(c, RS_ERR_UNSUPPORTED, "L-BFGS takes its gradient by reverse mode, which has no inertia or contact term");
     NewtonParams p{};
     p.r = c->r;
     p.max_iter = o->max_iter;
@@ -1746,6 +1995,7 @@ extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* lo
 extern "C" int rs_lipschitz_loss(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss,
                                  double* per_pair, int32_t* n_valid, double* lip_max, void* stream)
 {
+    if (c) c->dyn_inertia = 0;
     if (!c) return RS_ERR_STATE;
     if (B < 0) return fail(c, RS_ERR_ARG, "B < 0");
     if (!loss || !n_valid || (B > 0 && (!z1 || !z2))) return fail(c, RS_ERR_ARG, "NULL pointer");
@@ -1843,11 +2093,6 @@ static SgemmArgs gemm_s(const void* A, long sAm, long sAk, const void* B, long s
     return g;
 }
 
-#define RS_HIP(x, what)                                      \
-    do {                                                     \
-        hipError_t e_ = (x);                                 \
-        if (e_ != hipSuccess) return hip_fail(c, e_, what);  \
-    } while (0)
 
 extern "C" int rs_set_decoder_device(rs_ctx* c, const void* theta, int32_t theta_f64, void* stream)
 {
@@ -1876,12 +2121,13 @@ extern "C" int rs_set_decoder_device(rs_ctx* c, const void* theta, int32_t theta
                             c->in_rows, s),
            "decoder fold");
     RS_HIP(launch_load_padded(theta_f64, Wo, c->n_out, c->in_last, c->Nfp, c->lda_out, c->pinned_row,
-                              f32 ? nullptr : (double*)c->Wfull, f32 ? (float*)c->Wfull : nullptr,
+                              c->Wfull64, f32 ? (float*)c->Wfull : nullptr,
                               c->bf16 ? (uint16_t*)c->Wfull16 : nullptr, s),
            "decoder load");
-    RS_HIP(launch_load_vec(theta_f64, bo, c->n_out, c->pinned_row, f32 ? nullptr : (double*)c->bfull,
+    RS_HIP(launch_load_vec(theta_f64, bo, c->n_out, c->pinned_row, c->bfull64,
                            f32 ? (float*)c->bfull : nullptr, c->n_out, s),
            "decoder load");
+    c->G_dirty = true;
     return RS_OK;
 }
 
@@ -1899,6 +2145,7 @@ static int lip_grad_check(rs_ctx* c, int32_t B, const double* z1, const double* 
 static int lip_param_grad(rs_ctx* c, int32_t B, const double* z1, const double* z2, double* loss, double* grad,
                           const LipWs& ws, hipStream_t s)
 {
+    c->dyn_inertia = 0;
     const int r = c->r, L = c->L, w = c->w, f32 = c->f32, nc2 = r + 2, S9 = 9 * c->S;
     c->cur_slot = -1;
     const int chunk = ws.pairs;

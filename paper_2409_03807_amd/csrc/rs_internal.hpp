@@ -342,6 +342,43 @@ hipError_t launch_load_vec(int src_f64, const void* src, int n, const uint8_t* r
                            int n_pad, hipStream_t s);
 hipError_t launch_train(int f32, const TrainOp& o, hipStream_t s);
 
+// Implicit-Euler inertia and ground contact of one evaluation (launch_dyn)
+struct DynArgs {
+    const int* count;     // actual item count on the device (NULL = the launch's items)
+    const int* imap;      // item -> load index (NULL = identity)
+    const int* zmap;      // item -> row of z (linear decoders; NULL = identity)
+    const double* z;      // latent points (linear decoders: h = z)
+    int L, r, in_last, nc;
+    const void* act;      // item-major (nc x wrows) last activation [h | J_h] (L > 0)
+    int wrows;
+    const void* out;      // item-major (rows_pad x nc) output-map rows
+    int rows_pad;
+    int crow, ncont;      // contact rows and their count
+    const double* Xc;     // rest y of the contact vertices
+    double k_ground, ground_y;
+    const double* G;      // in_last x in_last
+    const double* eta;    // per load index: the target's coefficients in the range (NULL = 0)
+    const double* cvec;   // per load index: W^T M rho, rho the rest of the target
+    const double* kappa;  // per load index: |rho|_M^2
+    double inv_dt2;
+    int inertia;
+    double *E, *g, *H;    // added to (mode 2; E in mode 3)
+    void* dseed;          // mode 0: item-major (rows_pad) seeds, context precision
+    void* gbar;           // mode 1: item-major (in_rows) adjoint of h, context precision
+    int in_rows;
+};
+hipError_t launch_dyn_gram(int f32, const void* W, int ld, int rows, const double* rowmass, int m, double* G,
+                           hipStream_t s);
+hipError_t launch_dyn_prep(int f32, const void* W, int ld, const void* bias, const uint8_t* pinned_row,
+                           const double* rowmass, int rows, int m, const double* qbar, int B, double* cvec,
+                           double* kappa, hipStream_t s);
+hipError_t launch_dyn(int f32, int mode, const DynArgs& a, int cap, hipStream_t s);
+hipError_t launch_dyn_state(int m, const double* h0, const double* h1, const double* cv0, const double* kv0,
+                            double dt, int B, double* eta, double* cvec, double* kappa, hipStream_t s);
+hipError_t launch_dyn_take_h(const double* act64, int wrows, const double* z, int m, int B, double* h, hipStream_t s);
+hipError_t launch_sim_count(const int* it, const int* st, int B, int* iters, int* failed, hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+
 // Full-space quasi-static solver over every element of the mesh (float64)
 struct FullSolverDesc {
     int nv, ne, nt, nf;

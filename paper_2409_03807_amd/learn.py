@@ -21,6 +21,7 @@ This module orchestrates library calls (device buffers, seeds, loops); it holds
 none of the method's arithmetic."""
 from __future__ import annotations
 
+import math
 import time
 
 import numpy as np
@@ -66,16 +67,20 @@ def _epoch_indices(rng, n, B):
 
 
 def run_epochs(tr, store, n, epochs, B, lr, rng, lam=0.0, n_pairs=0, log=print, tag=""):
-    """Adam epochs over the store's rows; returns the last epoch's mean (L_C, L_LS)."""
+    """Adam epochs over the store's rows with a cosine learning-rate decay from lr
+    to 0 over the stage; returns the last epoch's mean (L_C, L_LS)."""
     acc = torch.zeros(2, dtype=torch.float64, device=DEV)
     losses = torch.empty(2, dtype=torch.float64, device=DEV)
     last = (float("nan"), float("nan"))
+    steps = epochs * (n // B)
+    step = 0
     for ep in range(epochs):
         acc.zero_()
         batches = _epoch_indices(rng, n, B)
         for idx in batches:
             tr.grad(store, idx, lambda_ls=lam, n_pairs=n_pairs, losses=losses)
-            tr.adam(lr)
+            tr.adam(lr * 0.5 * (1.0 + math.cos(math.pi * step / max(steps, 1))))
+            step += 1
             acc += losses
         if ep == epochs - 1 or ep % max(1, epochs // 5) == 0:
             v = (acc / len(batches)).cpu().numpy()
