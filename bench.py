@@ -87,16 +87,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c5"],
+                    help="c5 (with --path simulate): implicit-Euler simulations with ground contact")
     ap.add_argument("--batch", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-sample", type=int, default=-1,
                     help="oracle solves timed for cpu_baseline (0 = skip; default 320 Newton, 64 L-BFGS)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket launches with HIP events")
     ap.add_argument("--solver", default="newton", choices=["newton", "lbfgs"],
                     help="projective Newton (default) or L-BFGS (the paper's main solver)")
-    ap.add_argument("--path", default="solve", choices=["solve", "param_grad"],
+    ap.add_argument("--path", default="solve", choices=["solve", "param_grad", "simulate", "learned"],
                     help="solve: the reduced solves (default); param_grad: the decoder-parameter gradient of the "
-                         "summed cubature energy over the batch (the potential loss of unsupervised training)")
+                         "summed cubature energy over the batch (the potential loss of unsupervised training); "
+                         "simulate: implicit-Euler steps of a batch of simulations (c5); learned: snapshots, "
+                         "two-stage training, PCA and held-out solves of the c4 block (Lipschitz vs plain vs PCA)")
+    ap.add_argument("--prec", default="", choices=["", "f64", "f32", "bf16"], help="override the precision")
+    ap.add_argument("--z0", default="random", choices=["random", "zero"], help="start points of the solves")
+    ap.add_argument("--twist", type=float, default=None, help="one twist angle (deg) for every item")
+    ap.add_argument("--epochs", type=int, nargs=2, default=[400, 400], help="learned path: stage epochs")
+    ap.add_argument("--lam-rel", type=float, nargs="+", default=[0.1], help="learned path: lambda_LS factors")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -120,17 +128,25 @@ def main():
     from paper_2409_03807_amd import inputs as I
 
     torch.cuda.set_device(0)
+    if args.path == "learned":
+        return main_learned(args)
+    if args.path == "simulate" or args.config == "c5":
+        return main_simulate(args)
     name = args.config
     p = I.config(name)
     B = args.batch or {"c1": 1024, "c2": 1024, "c3": 4096}[name]
     # c1 float64, c2 float32, c3 the BF16 decoder variant of c2
     prec = {"c1": rb.PREC_F64, "c2": rb.PREC_F32, "c3": rb.PREC_BF16}[name]
+    if args.prec:
+        prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     ctx = rb.Context(p, prec=prec, max_batch=B)
     info = ctx.info()
     dev = "cuda:0"
     z0 = torch.tensor(I.latent_batch(B, p.r), device=dev)
-    tg_np, fo_np = I.loads_for(p, B)
+    if args.z0 == "zero":
+        z0.zero_()
+    tg_np, fo_np = I.loads_for(p, B, twist_deg=args.twist)
     tg = torch.tensor(tg_np, device=dev) if tg_np is not None else None
     fo = torch.tensor(fo_np, device=dev) if fo_np is not None else None
     out = (torch.empty_like(z0), torch.empty(B, dtype=torch.int32, device=dev),
@@ -245,6 +261,15 @@ def main():
         cpu = {"value": int((ores["status"] == O.CONVERGED).sum()) / cdt, "unit": "solves/s", "cores": cores,
                "kind": "oracle", "sample": f"{n} float64 oracle {'L-BFGS' if lbfgs else 'Newton'} solves of the same workload "
                                           f"(first {n} start points), {cdt:.1f} s"}
+        # the same oracle on one thread, on a sixteenth of the sample
+        n1 = max(1, n // 16)
+        O.set_threads(1)
+        t1 = time.perf_counter()
+        ores1 = solve(zs[:n1], tg_np[:n1] if tg_np is not None else None, fo_np[:n1] if fo_np is not None else None)
+        cdt1 = time.perf_counter() - t1
+        O.set_threads(cores)
+        cpu["single_thread"] = {"value": int((ores1["status"] == O.CONVERGED).sum()) / cdt1, "unit": "solves/s",
+                                "cores": 1, "sample": f"first {n1} start points, {cdt1:.1f} s"}
 
     line = {
         "metric": ("potential-loss parameter-gradient items/s" if pgrad else
@@ -263,7 +288,8 @@ def main():
         "config": {
             "workload": f"{name}: {p.meta['nx']}x{p.meta['ny']}x{p.meta['nz']} beam, nv={p.nv}, ne={p.ne}, "
                         f"r={p.r}, hidden={p.hidden}, |S|={len(p.cub_elem)}, B={B}, plain (untrained Glorot) "
-                        f"decoder, twist 0-180 deg penalty targets",
+                        f"decoder, " + (f"twist {args.twist:g} deg" if args.twist is not None else "twist 0-180 deg")
+                        + " penalty targets" + (", z0 = 0" if args.z0 == "zero" else ", z0 ~ N(0, 0.5^2)"),
             "batch": B, "rows": info.rows, "subspace": "plain", "solver": "none" if pgrad else args.solver,
             "path": args.path,
         },
@@ -273,6 +299,105 @@ def main():
         "lipschitz_loss": None if pgrad else float(lip["loss"].item()),
         "roofline": roof,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def profile_line(ctx, dtype):
+    """Every launch kind of a profiled pass against its own bound, and the dominant one."""
+    prof = ctx.profile_read()
+    if not prof:
+        return None
+    kind, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    roof = kernel_roofline(kind, rec, dtype)
+    roof.update(kernel=kind, avg_us=rec["ms"] / rec["launches"] * 1e3, launches=rec["launches"],
+                algorithmic_bytes=rec["bytes"] / rec["launches"], algorithmic_flops=rec["flops"] / rec["launches"],
+                traffic=None)
+    roof["kernels"] = {}
+    for k, v in prof.items():
+        kr = kernel_roofline(k, v, dtype)
+        roof["kernels"][k] = {"ms": round(v["ms"], 3), "launches": v["launches"], "bound": kr["bound"],
+                              "achieved": round(kr["achieved"], 2), "unit": kr["unit"], "frac": round(kr["frac"], 4)}
+    return roof
+
+
+def main_simulate(args):
+    """Implicit-Euler simulations with ground contact (c5): one step of the bench is
+    one time step of every simulation of the batch."""
+    import numpy as np
+    import torch
+
+    from paper_2409_03807_amd import binding as rb
+    from paper_2409_03807_amd import inputs as I
+
+    p = I.config("c5")
+    B = args.batch or 64
+    prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec or "f32"]
+    dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
+    dev = "cuda:0"
+    ctx = rb.Context(p, prec=prec, max_batch=B)
+    z0 = torch.zeros((B, p.r), dtype=torch.float64, device=dev)
+    v0 = torch.tensor(I.swing_velocities(p, B), device=dev)
+    # convergence floor: 1e-6 of the first step's start gradient (largest over the batch)
+    qb1 = (v0 * p.dt).contiguous()
+    _, g1, _ = ctx.energy_grad_hess(z0, qbar=qb1, dt=p.dt, flags=0)
+    opts = rb.default_opts(abs_tol=1e-6 * float(g1.abs().max().item()))
+    if args.warmup:
+        ctx.simulate(z0, args.warmup, p.dt, v0=v0, opts=opts, want_traj=False)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.simulate(z0, 2, p.dt, v0=v0, opts=opts, want_traj=False)
+    ctx.profile(False)
+    roof = profile_line(ctx, dtype)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.simulate(z0, args.steps, p.dt, v0=v0, opts=opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    failed = res["failed"].cpu().numpy()
+    iters = res["iters"].cpu().numpy()
+    conv = B * args.steps - int(failed.sum())
+    x, _ = ctx.decode(res["traj"][-1].contiguous(), want_J=False)
+    line = {
+        "metric": "converged reduced solves/s at rel. grad 1e-6 (implicit-Euler steps)",
+        "value": conv / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / max(args.steps, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"c5: 50x10x10 beam, nv={p.nv}, ne={p.ne}, r={p.r}, hidden={p.hidden}, "
+                               f"|S|={len(p.cub_elem)}, {B} simulations x {args.steps} steps, dt=1/60, ground "
+                               f"y={p.ground_y} m, k_ground={p.k_ground:g} N/m, plain (untrained Glorot) decoder, "
+                               f"seeded swing velocities", "batch": B, "path": "simulate"},
+        "failed_steps": int(failed.sum()), "mean_iters_per_step": float(iters.sum() / (B * max(args.steps, 1))),
+        "min_y_last_step": float(x[..., 1].min().item()),
+        "roofline": roof, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def main_learned(args):
+    """The learned part at the c4 block: full-space snapshots, two-stage training,
+    PCA and held-out reduced solves; value is the Lipschitz subspace's held-out
+    converged solves/s (first lambda factor), beside the plain and PCA subspaces."""
+    import numpy as np  # noqa: F401
+
+    from paper_2409_03807_amd import learn
+
+    t0 = time.perf_counter()
+    out = learn.run(epochs1=args.epochs[0], epochs2=args.epochs[1], lam_rels=tuple(args.lam_rel),
+                    log=lambda *a, **k: print(*a, **k, file=sys.stderr))
+    total = time.perf_counter() - t0
+    lip = f"lipschitz_{args.lam_rel[0]:g}"
+    h = out["heldout"]
+    line = {
+        "metric": "converged reduced solves/s at rel. grad 1e-6, Lipschitz vs plain subspace",
+        "value": h[lip]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": h[lip]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": out["workload"], "path": "learned", "subspace": lip,
+                   "held_out": out["heldout_snapshots"], "train": out["train_snapshots"],
+                   "epochs": out["epochs"], "lambda_ls": out["lambda_ls"]},
+        "comparison": h, "snapshot_solve": out["snapshot_solve"], "pipeline_seconds": total,
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

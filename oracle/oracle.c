@@ -26,6 +26,9 @@
 #include "oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -1578,3 +1581,14 @@ int or_encode(const or_mlp* enc, int B, const double* d, double* z)
     free(A); free(Hs);
     return 0;
 }
+
+/* number of OpenMP threads of the oracle's parallel loops (for timing) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+

@@ -171,6 +171,9 @@ int or_recon_loss_grad(const or_problem* p, const or_mlp* enc, int B, const doub
 /* encoder values z (B x n_out) of inputs d (B x n_in) */
 int or_encode(const or_mlp* enc, int B, const double* d, double* z);
 
+/* number of OpenMP threads of the parallel loops (timing only) */
+void or_set_threads(int n);
+
 /* symmetric eigen-decomposition by cyclic Jacobi (exposed for pins) */
 void or_sym_eig(int n, const double* A, double* evals, double* evecs);
 

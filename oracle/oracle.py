@@ -418,6 +418,11 @@ class Mlp:
         return z
 
 
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (timing of the CPU baseline)."""
+    lib().or_set_threads(C.c_int(int(n)))
+
+
 def pca(D, row_mass, r):
     """PCA basis of snapshot displacements D (N x n) in the mass inner product
     (row_mass: the lumped mass of each row's vertex): the mean, W (n x r) with

@@ -237,7 +237,9 @@ def config(name: str, **kw) -> Problem:
     c3: c2 with batch 4096 (BF16 decoder variant).
     c4: 16^3 block (4913 vertices, 20480 tets), r=12, 4x256, 512 cubature tets
         with weights U[20,60], end twist and bend loads on the x=L face.
-    c5: 50x10x10 beam (6171 vertices, 25000 tets), r=32, 5x256, 1024 cubature tets.
+    c5: 50x10x10 beam (6171 vertices, 25000 tets), r=32, 5x256, 1024 cubature tets
+        (weights with mean ne / |S|); implicit Euler dt = 1/60, ground plane
+        y = -0.25 m with penalty stiffness 1e6 N/m on every vertex.
     """
     name = name.lower()
     if name == "c1":
@@ -248,7 +250,13 @@ def config(name: str, **kw) -> Problem:
         # weights U[20, 60]: mean 40 = ne / |S|, so the cubature sum has the element count's scale
         return make_problem("c4", 16, 16, 16, 12, [256] * 4, 512, wlo=20.0, whi=60.0, bend=True, **kw)
     if name == "c5":
-        return make_problem("c5", 50, 10, 10, 32, [256] * 5, 1024, **kw)
+        # implicit-Euler dynamics: x = 0 face pinned, gravity, ground contact on every vertex
+        p = make_problem("c5", 50, 10, 10, 32, [256] * 5, 1024, wlo=12.5, whi=36.3, twist=False, **kw)
+        p.dt = 1.0 / 60.0
+        p.contact_vtx = np.arange(p.nv, dtype=np.int32)
+        p.k_ground = 1e6
+        p.ground_y = -0.25
+        return p
     if name == "tiny":
         # 2x1x1 beam, r=4, 2x8 hidden, 8 of the 10 tets as cubature, weights U[20,80]
         return make_problem("tiny", 2, 1, 1, 4, [8, 8], 8, **kw)
@@ -288,4 +296,18 @@ def heldout_split(N: int, n_test: int, seed: int = SEED_SPLIT):
     """(train indices, held-out indices), a seeded permutation."""
     perm = np.random.default_rng(seed).permutation(N)
     return np.sort(perm[n_test:]), np.sort(perm[:n_test])
+
+
+def swing_velocities(p: Problem, B: int, seed: int = SEED_LOADS, wmax: float = 6.0):
+    """Initial velocities of B simulations: a rigid rotation about the pinned
+    face's centre with a seeded rate vector (rad/s, components U[-wmax, wmax]
+    about y and z, half that about the beam axis), zero on pinned vertices.
+    Returns (B, nv, 3)."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(-wmax, wmax, size=(B, 3)) * np.array([0.5, 1.0, 1.0])
+    c = p.X[p.pinned.astype(bool)].mean(axis=0)
+    d = p.X - c
+    v = np.cross(w[:, None, :], d[None, :, :])
+    v[:, p.pinned.astype(bool)] = 0.0
+    return v
 

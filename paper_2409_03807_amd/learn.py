@@ -89,18 +89,20 @@ def run_epochs(tr, store, n, epochs, B, lr, rng, lam=0.0, n_pairs=0, log=print, 
     return last
 
 
-def heldout_solves(ctx, z0, targets, force, reps=5, opts=None):
-    """Newton solves of the held-out loads from z0: converged count, mean iterations,
-    median wall time of `reps` calls (after one warm-up), and the final z."""
+def heldout_solves(ctx, z0, targets, force, reps=5, solver="newton"):
+    """Solves (projective Newton or L-BFGS) of the held-out loads from z0: converged
+    count, mean iterations, median wall time of `reps` calls (after one warm-up),
+    and the final z."""
     B = targets.shape[0]
     tg, fo = _t64(targets), _t64(force)
     z0b = z0.reshape(1, -1).expand(B, -1).contiguous()
-    res = ctx.newton_solve(z0b, tg, fo, opts)
+    solve = ctx.newton_solve if solver == "newton" else ctx.lbfgs_solve
+    res = solve(z0b, tg, fo)
     torch.cuda.synchronize()
     times = []
     for _ in range(reps):
         t0 = time.perf_counter()
-        res = ctx.newton_solve(z0b, tg, fo, opts)
+        res = solve(z0b, tg, fo)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     st = res["status"].cpu().numpy()
@@ -211,6 +213,9 @@ def run(n_snap=2048, n_test=256, epochs1=100, epochs2=100, batch=128, pairs=64, 
         z0 = zr if name == "pca" else encs[name][0]
         r_e, sol = heldout_solves(c_e, z0, tg_te, fo_te, reps=reps)
         r_e["subspace_error"] = subspace_error(c_e, sol["z"], u_test)
+        r_l, sol_l = heldout_solves(c_e, z0, tg_te, fo_te, reps=reps, solver="lbfgs")
+        r_e["lbfgs"] = {k: r_l[k] for k in ("converged", "mean_iters", "median_iters", "ms", "solves_per_s",
+                                             "status_counts")}
         if name != "pca":
             r_e.update(lipschitz_estimate(c_e, encs[name][1]))
         res[name] = r_e
