@@ -155,7 +155,8 @@ def main():
     opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor)
     lbfgs = args.solver == "lbfgs"
     lopts = rb.default_lbfgs_opts()
-    z1, z2 = z0[0::2].contiguous(), z0[1::2].contiguous()
+    npair = B // 2
+    z1, z2 = z0[0:2 * npair:2].contiguous(), z0[1:2 * npair:2].contiguous()
 
     # per-step bookkeeping stays on the device (no host sync inside the timed
     # region beyond what the solver itself does)
@@ -173,7 +174,7 @@ def main():
             res = ctx.lbfgs_solve(z0, tg, fo, opts=lopts, out=out)
         else:
             res = ctx.newton_solve(z0, tg, fo, opts=opts, out=out)
-        lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False)
+        lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False) if npair else None
         conv_acc.add_((res["status"] == rb.CONVERGED).sum())
         iter_acc.add_(res["iters"].sum())
         return res, lip
@@ -296,7 +297,7 @@ def main():
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
         "mean_iters": mean_iters,
-        "lipschitz_loss": None if pgrad else float(lip["loss"].item()),
+        "lipschitz_loss": None if (pgrad or lip is None) else float(lip["loss"].item()),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
