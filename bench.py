@@ -32,7 +32,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}
+# "bf16": the BF16 contexts' decoder products take six BF16 MFMAs per float32
+# product (three-part operands), so their float32-equivalent peak is the dense
+# BF16 peak (2.5 PFLOP/s) over six
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0 / 6}
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2409_03807_amd", "csrc", "rs_kernels.hip")
 
@@ -107,6 +110,8 @@ def parse():
     ap.add_argument("--lam-rel", type=float, nargs="+", default=[0.1], help="learned path: lambda_LS factors")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
+    ap.add_argument("--hess", default="exact", choices=["exact", "gn", "gn_psd", "exact_psd"],
+                    help="Newton Hessian: exact or Gauss-Newton, optionally with per-element PSD projection")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -152,7 +157,10 @@ def main():
     out = (torch.empty_like(z0), torch.empty(B, dtype=torch.int32, device=dev),
            torch.empty(B, dtype=torch.int32, device=dev), torch.empty(B, dtype=torch.float64, device=dev),
            torch.empty(B, dtype=torch.float64, device=dev))
-    opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor)
+    hess = {"exact": rb.HESS_EXACT_OPT, "gn": rb.HESS_GN, "gn_psd": rb.HESS_GN_ELEM_PSD,
+            "exact_psd": rb.HESS_EXACT_ELEM_PSD}[args.hess]
+    opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor,
+                           hess=hess)
     lbfgs = args.solver == "lbfgs"
     lopts = rb.default_lbfgs_opts()
     npair = B // 2
@@ -292,7 +300,7 @@ def main():
                         f"decoder, " + (f"twist {args.twist:g} deg" if args.twist is not None else "twist 0-180 deg")
                         + " penalty targets" + (", z0 = 0" if args.z0 == "zero" else ", z0 ~ N(0, 0.5^2)"),
             "batch": B, "rows": info.rows, "subspace": "plain", "solver": "none" if pgrad else args.solver,
-            "path": args.path,
+            "path": args.path, "hessian": args.hess, "projection": args.proj,
         },
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},

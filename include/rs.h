@@ -67,12 +67,14 @@ enum {
 
 /* Context precision of the decoder and element physics.
  * RS_PREC_BF16 is the precision variant of the float32 context: the forward
- * decoder products (hidden layers and output map) take BF16 operands on the
- * matrix cores with float32 accumulation (weights converted from float64 with
- * round-to-nearest-even, each layer input rounded to BF16); pre-activations,
- * element physics, adjoint and curvature run in float32 exactly as in a
- * float32 context; reduced quantities, the r x r solve and the line-search
- * energies stay float64.  It needs at least one hidden layer. */
+ * decoder products (hidden layers and output map) run on the BF16 matrix cores
+ * with float32 accumulation and float32 accuracy.  Every weight is held as three
+ * BF16 parts (hi, mid, lo: round-to-nearest-even from float64), every layer input
+ * is split the same way, and six of the nine part products are summed, so the
+ * decoder is the same function as in the float32 context.  Pre-activations,
+ * element physics, adjoint and curvature run in float32 exactly as in a float32
+ * context; reduced quantities, the r x r solve and the line-search energies stay
+ * float64.  It needs at least one hidden layer. */
 enum { RS_PREC_F64 = 0, RS_PREC_F32 = 1, RS_PREC_BF16 = 2 };
 
 /* rs_energy_grad_hess flags */

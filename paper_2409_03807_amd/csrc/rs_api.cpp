@@ -361,10 +361,28 @@ static uint16_t bf16_rne(double x)
     return (uint16_t)(up ? hi + 1 : hi);
 }
 
+static double bf16_value(uint16_t h)
+{
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, sizeof(f));
+    return (double)f;
+}
+
+// BF16 operand planes of a float64 array: plane 0 holds hi = bf16(x), plane 1
+// mid = bf16(x - hi), plane 2 lo = bf16(x - hi - mid), so that the three parts
+// carry x to float32 accuracy on the BF16 matrix cores.
 static int upload_bf16(rs_ctx* c, void* dst, const std::vector<double>& src)
 {
-    std::vector<uint16_t> t(src.size());
-    for (size_t i = 0; i < src.size(); ++i) t[i] = bf16_rne(src[i]);
+    const size_t n = src.size();
+    std::vector<uint16_t> t(3 * n);
+    for (size_t i = 0; i < n; ++i) {
+        double rem = src[i];
+        for (int p = 0; p < 3; ++p) {
+            t[p * n + i] = bf16_rne(rem);
+            rem -= bf16_value(t[p * n + i]);
+        }
+    }
     hipError_t e = hipMemcpy(dst, t.data(), t.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
     return e == hipSuccess ? RS_OK : hip_fail(c, e, "hipMemcpy");
 }
@@ -708,10 +726,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
         c->W16.resize(c->L);
         for (int l = 0; l < c->L; ++l) {
             const int lda = l == 0 ? c->lda0 : c->lda_h;
-            c->W16[l] = need(dalloc_bytes(c, (size_t)c->wrows * lda * 2));
+            c->W16[l] = need(dalloc_bytes(c, 3 * (size_t)c->wrows * lda * 2));
         }
-        c->Wbig16 = need(dalloc_bytes(c, (size_t)c->Mp * c->lda_out * 2));
-        c->Wfull16 = need(dalloc_bytes(c, (size_t)c->Nfp * c->lda_out * 2));
+        // three BF16 planes (hi, mid, lo) per weight array
+        c->Wbig16 = need(dalloc_bytes(c, 3 * (size_t)c->Mp * c->lda_out * 2));
+        c->Wfull16 = need(dalloc_bytes(c, 3 * (size_t)c->Nfp * c->lda_out * 2));
     }
     c->bfull = need(dalloc_bytes(c, (size_t)c->n_out * ts));
     c->bfull64 = c->f32 ? (double*)need(dalloc<double>(c, (size_t)c->n_out)) : (double*)c->bfull;

@@ -58,27 +58,42 @@ template <> struct Vec16<float> { using type = f32x4; static constexpr int n = 4
 template <> struct Vec16<double> { using type = f64x2; static constexpr int n = 2; };
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// One 32-deep chunk of a 16x16 product in BF16 with FP32 accumulation:
-// lane (i + 16 g) supplies A[i][8g .. 8g+7] and B[8g .. 8g+7][i], which is the
-// permuted-k fragment every GEMM here holds per 32-deep chunk.
-__device__ inline f32x4 mfma_bf16_chunk(bf16x8 a, bf16x8 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// Eight float32 values as a BF16 pair: hi = bf16(x), lo = bf16(x - hi), so
-// hi + lo carries x to about 16 significant bits and the products with a
-// BF16 operand lose only that operand's rounding.
-__device__ inline void split_bf16(f32x4 x0, f32x4 x1, bf16x8& hi, bf16x8& lo)
+// Eight float32 values as three BF16 parts: hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid).  Each difference is exact in float32 (the operands
+// are within a factor of two of each other), so hi + mid + lo carries all 24
+// significant bits of x up to the last part's rounding.
+__device__ inline void split3_bf16(f32x4 x0, f32x4 x1, bf16x8& hi, bf16x8& mid, bf16x8& lo)
 {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const __bf16 h0 = (__bf16)x0[e], h1 = (__bf16)x1[e];
+        const float r0 = x0[e] - (float)h0, r1 = x1[e] - (float)h1;
+        const __bf16 m0 = (__bf16)r0, m1 = (__bf16)r1;
         hi[e] = h0;
         hi[4 + e] = h1;
-        lo[e] = (__bf16)(x0[e] - (float)h0);
-        lo[4 + e] = (__bf16)(x1[e] - (float)h1);
+        mid[e] = m0;
+        mid[4 + e] = m1;
+        lo[e] = (__bf16)(r0 - (float)m0);
+        lo[4 + e] = (__bf16)(r1 - (float)m1);
     }
+}
+
+// Six BF16 products of one 32-deep chunk that give a float32-accurate product
+// of two operands held as three BF16 parts each (hi, mid, lo): the terms whose
+// combined weight is at least 2^-16 of hi*hi (Henry, Tang and Heinecke, "Leveraging
+// the bfloat16 artificial intelligence datatype for higher-precision
+// computations", ARITH 2019).  The dropped terms (mid*lo, lo*mid, lo*lo) are below
+// 2^-24 relative.  The small terms go into `corr`, hi*hi into `acc`.  Lane
+// (i + 16 g) supplies A[i][8g .. 8g+7] and B[8g .. 8g+7][i] of each 16x16x32
+// product: the permuted-k fragment every GEMM here holds per 32-deep chunk.
+__device__ inline void mfma_bf16x6_chunk(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4& acc, f32x4& corr)
+{
+    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], corr, 0, 0, 0);
+    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], corr, 0, 0, 0);
+    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], corr, 0, 0, 0);
+    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], corr, 0, 0, 0);
+    corr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], corr, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
 }
 
 // ELU with alpha = 1 (linear branch for a > 0) and its first two derivatives.

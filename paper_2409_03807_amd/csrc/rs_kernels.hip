@@ -532,19 +532,20 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
     }
 }
 
-// Persistent output map with BF16 operands (FP32 accumulation and output):
-// the workgroup's 64 x K tile of A stays in registers as BF16 fragments; the
-// transposed float32 activation tile is split into a BF16 pair (hi, lo) on
-// its way into LDS, and each 32-deep chunk is two 16x16x32 BF16 MFMAs per
-// 16-column tile.  Same tiling, prefetch and epilogue as k_gemm_p2.
+// Persistent output map on the BF16 matrix cores at float32 accuracy (FP32
+// accumulation and output): A is held as three BF16 planes (hi, mid, lo) of its
+// float64 values, and the workgroup's 64 x K tile of each stays in registers as
+// BF16 fragments; the transposed float32 activation tile is split into three
+// BF16 parts on its way into LDS, and each 32-deep chunk is six 16x16x32 BF16
+// MFMAs per 16-column tile (mfma_bf16x6_chunk).  Same tiling, prefetch and
+// epilogue as k_gemm_p2.
 template <int ROLE, int KCH, int OUTM>
 __global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
 {
     constexpr int KT = KCH * kTileK;
     constexpr int LD = KT + 8;   // BF16 elements per LDS row (16-byte pad)
     constexpr int PER = KT / 4;  // k per thread (4 thread groups per column)
-    __shared__ __align__(16) __bf16 Yh[kTileN * LD];
-    __shared__ __align__(16) __bf16 Yl[kTileN * LD];
+    __shared__ __align__(16) __bf16 Ys[3][kTileN * LD];
     const int items = a.count ? min(*a.count, a.items) : a.items;
     const int ncols = items * a.nc;
     const int ntiles = (ncols + kTileN - 1) / kTileN;
@@ -556,11 +557,14 @@ __global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
     const int nc = a.nc;
     const unsigned ncu = (unsigned)nc;
 
-    bf16x8 af[KCH];
+    bf16x8 af[KCH][3];
     {
+        const size_t plane = (size_t)a.rows_pad * a.lda;
         const __bf16* A = static_cast<const __bf16*>(a.A) + (size_t)(m0 + wave * 16 + li) * a.lda + 8 * lg;
 #pragma unroll
-        for (int c = 0; c < KCH; ++c) af[c] = *reinterpret_cast<const bf16x8*>(A + c * kTileK);
+        for (int c = 0; c < KCH; ++c)
+#pragma unroll
+            for (int p = 0; p < 3; ++p) af[c][p] = *reinterpret_cast<const bf16x8*>(A + p * plane + c * kTileK);
     }
     int mrow[4];
     float brow[4];
@@ -587,14 +591,13 @@ __global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
         }
     };
     auto store = [&]() {
-        bf16x8* dh = reinterpret_cast<bf16x8*>(&Yh[ynn * LD + ykb]);
-        bf16x8* dl = reinterpret_cast<bf16x8*>(&Yl[ynn * LD + ykb]);
 #pragma unroll
         for (int q = 0; q < PER / 8; ++q) {
-            bf16x8 h, l;
-            split_bf16(ry[2 * q], ry[2 * q + 1], h, l);
-            dh[q] = h;
-            dl[q] = l;
+            bf16x8 h, m, l;
+            split3_bf16(ry[2 * q], ry[2 * q + 1], h, m, l);
+            reinterpret_cast<bf16x8*>(&Ys[0][ynn * LD + ykb])[q] = h;
+            reinterpret_cast<bf16x8*>(&Ys[1][ynn * LD + ykb])[q] = m;
+            reinterpret_cast<bf16x8*>(&Ys[2][ynn * LD + ykb])[q] = l;
         }
     };
 
@@ -605,19 +608,21 @@ __global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
         store();
         __syncthreads();
         if (ct + groups < ntiles) load(ct + groups);
-        f32x4 acc[4];
+        f32x4 acc[4], corr[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0, 0, 0, 0};
+        for (int t = 0; t < 4; ++t) acc[t] = corr[t] = f32x4{0, 0, 0, 0};
 #pragma unroll
         for (int c = 0; c < KCH; ++c)
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int off = (t * 16 + li) * LD + c * kTileK + 8 * lg;
-                const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Yh[off]);
-                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Yl[off]);
-                acc[t] = mfma_bf16_chunk(af[c], bh, acc[t]);
-                acc[t] = mfma_bf16_chunk(af[c], bl, acc[t]);
+                bf16x8 b[3];
+#pragma unroll
+                for (int p = 0; p < 3; ++p) b[p] = *reinterpret_cast<const bf16x8*>(&Ys[p][off]);
+                mfma_bf16x6_chunk(af[c], b, acc[t], corr[t]);
             }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] += corr[t];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int n = ct * kTileN + t * 16 + li;
@@ -951,9 +956,10 @@ __device__ inline void lds_barrier()
 template <typename T, int CT, int RT, int NW, typename OP = T, int PF = 1>
 __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
 {
-    // OP: type of the weights and of the MFMA operands (T, or BF16: weights in
-    // BF16 and the FP32 layer input split into a BF16 pair as its fragments are
-    // read, two MFMAs per chunk)
+    // OP: type of the weights and of the MFMA operands (T, or BF16: weights as
+    // three BF16 planes (hi, mid, lo) and the FP32 layer input split into three
+    // BF16 parts as its fragments are read, six MFMAs per chunk at float32
+    // accuracy; mfma_bf16x6_chunk)
     constexpr bool BF = std::is_same<OP, __bf16>::value;
     static_assert(!BF || std::is_same<T, float>::value, "BF16 operands accumulate in float");
     constexpr int NTH = 64 * NW; // NW waves of RT * 16 output rows each
@@ -1009,14 +1015,17 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
     // next block (the same layer's next k-block or the next layer's first),
     // so PF chunks are in flight behind the products.
     V wa[PF][RT][8 / VN];
-    bf16x8 wb[PF][RT];
+    bf16x8 wb[PF][RT][BF ? 3 : 1];
     auto loadw = [&](int l, int k0, auto u) {
         const int lda = l == 0 ? a.lda0 : a.lda;
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
             const size_t off = (size_t)(wave * RT * 16 + i * 16 + li) * lda + k0 + 8 * lg;
             if constexpr (BF) {
-                wb[u][i] = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(a.W[l]) + off);
+                const size_t plane = (size_t)a.wrows * lda;
+#pragma unroll
+                for (int p = 0; p < 3; ++p)
+                    wb[u][i][p] = *reinterpret_cast<const bf16x8*>(static_cast<const __bf16*>(a.W[l]) + p * plane + off);
             } else {
                 const V* src = reinterpret_cast<const V*>(static_cast<const T*>(a.W[l]) + off);
 #pragma unroll
@@ -1049,21 +1058,20 @@ __global__ __launch_bounds__(64 * NW) void k_mlp(MlpArgs a)
                     return;
                 }
                 if constexpr (BF) {
-                    bf16x8 ab[RT];
+                    bf16x8 ab[RT][3];
 #pragma unroll
-                    for (int i = 0; i < RT; ++i) ab[i] = wb[u][i];
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int p = 0; p < 3; ++p) ab[i][p] = wb[u][i][p];
                     loadw(nl, nk, u);
 #pragma unroll
                     for (int t = 0; t < CT; ++t) {
                         const V* sb = reinterpret_cast<const V*>(Ys + (t * 16 + li) * LDY + k0 + 8 * lg);
                         const V x0 = sb[0], x1 = sb[1];
-                        bf16x8 bh, bl;
-                        split_bf16(x0, x1, bh, bl);
+                        bf16x8 b[3];
+                        split3_bf16(x0, x1, b[0], b[1], b[2]);
 #pragma unroll
-                        for (int i = 0; i < RT; ++i) {
-                            acc[i][t] = mfma_bf16_chunk(ab[i], bh, acc[i][t]);
-                            acc[i][t] = mfma_bf16_chunk(ab[i], bl, acc[i][t]);
-                        }
+                        for (int i = 0; i < RT; ++i) mfma_bf16x6_chunk(ab[i], b, acc[i][t], acc[i][t]);
                     }
                 } else {
                     T bf[CT][8];

@@ -532,6 +532,18 @@ __device__ inline uint16_t bf16_rne_dev(double x)
     return (uint16_t)(up ? hi + 1 : hi);
 }
 
+// x as three BF16 parts hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid),
+// written `plane` elements apart (the BF16 contexts' operand planes)
+__device__ inline void bf16_planes_dev(double x, uint16_t* dst, size_t plane)
+{
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const uint16_t h = bf16_rne_dev(x);
+        dst[p * plane] = h;
+        x -= (double)__uint_as_float((uint32_t)h << 16);
+    }
+}
+
 template <typename TS>
 __global__ void k_load_padded(const TS* src, int out, int in, int rows_pad, int ld, const uint8_t* rowmask, double* d64,
                               float* d32, uint16_t* d16)
@@ -543,7 +555,7 @@ __global__ void k_load_padded(const TS* src, int out, int in, int rows_pad, int 
     if (m < out && k < in && !(rowmask && rowmask[m])) v = (double)src[(long)m * in + k];
     if (d64) d64[i] = v;
     if (d32) d32[i] = (float)v;
-    if (d16) d16[i] = bf16_rne_dev(v);
+    if (d16) bf16_planes_dev(v, d16 + i, (size_t)rows_pad * ld);
 }
 
 // W_big[m][k] = sum_j coef[j] W_out[src[j]][k] (+ the same for the bias, column in_last of a
@@ -569,7 +581,7 @@ __global__ void k_fold_rows(const TS* Wout, const TS* bout, int in_last, const i
     const long o = (long)m * ld + k;
     if (W64) W64[o] = v;
     if (W32) W32[o] = (float)v;
-    if (W16) W16[o] = bf16_rne_dev(v);
+    if (W16) bf16_planes_dev(v, W16 + o, (size_t)Mp * ld);
 }
 
 // dst[k][m] = src[m][k] for the adjoint product's transposed W_big
