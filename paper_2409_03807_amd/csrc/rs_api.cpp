@@ -1334,7 +1334,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         }
         const double pb = (double)c->L * c->w * nc * ts + (double)c->ksplit * c->in_rows * ts + 16.0 * r * r;
         const double pf = (double)c->L * (2.0 * r * r * c->w + 2.0 * c->w * c->w);
-        RS_TRY(run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); }));
+        RS_TRY(run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, c->n_cu, s); }));
     }
     if ((flags & RS_ELEM_PSD) && H) {
         // the per-element projection's correction, added to the finished H
@@ -1466,7 +1466,7 @@ static int eval_grad_rev(rs_ctx* c, int cap, const int* count, const double* z, 
     ca.delta = delta;
     const double pb = (double)c->L * c->w * ts + (double)c->ksplit * c->in_rows * ts + 8.0 * r;
     const double pf = (double)c->L * 2.0 * c->w * c->w;
-    return run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, s); });
+    return run(c, K_CURV, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_curv(f32, ca, cap, c->n_cu, s); });
 }
 
 // float64 value-only decoder and energy for `cap` items (count on the device

@@ -316,7 +316,7 @@ hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 hipError_t launch_elem_psd(int f32, const ElemOptArgs& a, int items, hipStream_t s);
 // 12x12 element Hessians of the first `items` items into a.He
 hipError_t launch_elem_hess_dump(int f32, const ElemOptArgs& a, int items, hipStream_t s);
-hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s);
+hipError_t launch_curv(int f32, const CurvArgs& a, int items, int n_cu, hipStream_t s);
 hipError_t launch_param_outer(int f32, const ParamOuterArgs& a, hipStream_t s);
 // dW[n][k] = sum_j coef[j] * src[row[j]][k] and db[n] = sum_j coef[j] * srcb[row[j]]
 // over j in [ptr[n], ptr[n+1]): the transpose of a sparse row fold, n < rows

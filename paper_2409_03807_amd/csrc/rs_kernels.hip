@@ -1984,11 +1984,20 @@ hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 // u = 4t + kq: the A operand of A^T and, scaled by cf[u], the B operand of
 // diag(cf) A), float64 totals per layer, the four waves' sums added in order
 // at the end; and gbar_{l-1} = W_l^T ga, thread (slice, vq) summing rows
-// v of its slice of W_l into 4 adjacent outputs (16-byte loads, all of a
-// slice in flight at once), the 8 slices added in order.
+// v of its slice of W_l into 4 adjacent outputs (16-byte loads), the 8
+// slices added in order.
+// Only gbar -> ga -> gbar is a dependent chain, so the global reads are
+// issued ahead of it: the entries of layer l - 1's [a | A] block that a thread
+// uses are loaded into registers while layer l runs, and the first rows of
+// the thread's W_l slice at the top of layer l (before that prefetch, so that
+// waiting on them leaves it in flight).  Every such load is unconditional, at
+// a clamped in-bounds address.
 constexpr int kCurvMaxW = kMaxWidth;
 
-template <typename T, int RT>
+// KT: 4-row steps per wave held for a layer (w <= 16 KT); WQ: rows of the
+// thread's W_l slice loaded at the top of the layer (0: all in the products'
+// own batches, fewer registers for batches that fill the chip several times)
+template <typename T, int RT, int KT, int WQ>
 __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 {
     extern __shared__ double smem[];
@@ -2004,28 +2013,61 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     double* red = part + 8 * pw;  // [4 waves][RT][RT][4][64] per-wave H partials
     double* hpart = red + 4 * RT * RT * 4 * 64; // parts > 1: the element kernel's H summed over parts
     const int c = lane & 15, kq = lane >> 4;
+    using acc_t = typename Mfma<T>::acc_t;
+    using V4 = T __attribute__((ext_vector_type(4)));
+
+    // a layer's entries used by this thread: a[tid] and A[u][16 ti + c] for
+    // u = 4 (wave + 4 k) + kq (zero past the width or the latent dimension)
+    T pv = T(0);
+    T pj[KT][RT];
+    auto fetch = [&](int l) {
+        const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
+        pv = P[(size_t)min(tid, w - 1) * su];
+        if (!a.H) return; // value-only blocks (nc = 1) have no A
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            const int u = min(4 * (wave + 4 * k) + kq, w - 1);
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+                pj[k][ti] = P[(size_t)u * su + (size_t)(1 + min(16 * ti + c, r - 1)) * sc];
+        }
+    };
+    fetch(a.L - 1);
     if (a.parts > 1) {
-        // summed here, at the start, so that the loads overlap the layer loop
+        // summed here, at the start, so that the loads overlap the layer loop;
+        // every part's load is issued before the sum
         for (int e = tid; e < r * r; e += 256) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                v[q] = q < a.parts ? a.Hp[((size_t)q * a.part_stride + item) * r * r + e] : 0.0;
             double hs = 0.0;
-            for (int q = 0; q < a.parts; ++q) hs += a.Hp[((size_t)q * a.part_stride + item) * r * r + e];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) hs += v[q];
             hpart[e] = hs;
         }
         if (tid < r) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                v[q] = q < a.parts ? a.gp[((size_t)q * a.part_stride + item) * r + tid] : 0.0;
             double gs = 0.0;
-            for (int q = 0; q < a.parts; ++q) gs += a.gp[((size_t)q * a.part_stride + item) * r + tid];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) gs += v[q];
             a.g[(size_t)item * r + tid] = gs;
         }
     }
     for (int u = tid; u < w; u += 256) {
-        double sum = 0.0;
         const T* gp = static_cast<const T*>(a.gbar) + (size_t)item * a.pre_rows + u;
-#pragma unroll 4
-        for (int z = 0; z < a.ksplit; ++z) sum += (double)gp[z * a.split_stride];
+        T v[kMaxSplit];
+#pragma unroll
+        for (int z = 0; z < kMaxSplit; ++z) v[z] = gp[(size_t)min(z, a.ksplit - 1) * a.split_stride];
+        double sum = 0.0;
+#pragma unroll
+        for (int z = 0; z < kMaxSplit; ++z)
+            if (z < a.ksplit) sum += (double)v[z];
         gh[u] = sum;
     }
-    using acc_t = typename Mfma<T>::acc_t;
-    using V4 = T __attribute__((ext_vector_type(4)));
     double Hd[RT][RT][4];
 #pragma unroll
     for (int ti = 0; ti < RT; ++ti)
@@ -2036,15 +2078,35 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     const int slice = tid >> 5, vq = tid & 31;
     const int rows_per = (w + 7) / 8;
     for (int l = a.L - 1; l >= 0; --l) {
-        const T* P = static_cast<const T*>(a.pre[l]) + (size_t)item * a.pre_rows * nc;
+        const bool gemv = l > 0 || a.grev;
+        const int in = l == 0 ? r : w;
+        const int ld = l == 0 ? a.lda0 : a.lda;
+        const T* Wl = static_cast<const T*>(a.W[l]);
+        const int v0 = slice * rows_per, v1 = min(w, v0 + rows_per);
+        const int u00 = 4 * vq;
+        // the first WQ rows of the slice, first column group (clamped rows and columns)
+        V4 wq[WQ > 0 ? WQ : 1];
+        if (WQ > 0) {
+            const T* wp = Wl + min(u00, ld - 4);
+#pragma unroll
+            for (int b = 0; b < WQ; ++b) wq[b] = *reinterpret_cast<const V4*>(wp + (size_t)min(v0 + b, w - 1) * ld);
+        }
+        // this layer's entries, then the next layer's loads behind them
+        const T cv = pv;
+        T cj[KT][RT];
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti) cj[k][ti] = pj[k][ti];
+        if (l > 0) fetch(l - 1);
         __syncthreads(); // gh of this layer visible; cf, ga, part free
-        for (int u = tid; u < w; u += 256) {
-            const double av = (double)P[(size_t)u * su];
+        if (tid < w) {
+            const double av = (double)cv;
             // s'(a) and s''(a) share exp(a) for a <= 0 (1 and 0 above)
             const double ex = exp(fmin(av, 0.0));
-            cf[u] = av > 0.0 ? 0.0 : gh[u] * ex;
-            ga[u] = av > 0.0 ? gh[u] : gh[u] * ex;
-            if (a.delta) a.delta[((size_t)item * a.L + l) * w + u] = ga[u];
+            cf[tid] = av > 0.0 ? 0.0 : gh[tid] * ex;
+            ga[tid] = av > 0.0 ? gh[tid] : gh[tid] * ex;
+            if (a.delta) a.delta[((size_t)item * a.L + l) * w + tid] = ga[tid];
         }
         __syncthreads();
         if (a.H) {
@@ -2053,17 +2115,15 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < RT; ++tj) acc[ti][tj] = acc_t{0, 0, 0, 0};
-            const int nt = (w + 3) / 4;
-#pragma unroll 4
-            for (int t = wave; t < nt; t += 4) {
-                const int u = 4 * t + kq;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) { // steps past the width add zeros (no early exit: the loop stays unrolled)
+                const int u = 4 * (wave + 4 * k) + kq;
                 const bool uok = u < w;
                 const T cfu = uok ? (T)cf[u] : T(0);
                 T av[RT], bv[RT];
 #pragma unroll
                 for (int ti = 0; ti < RT; ++ti) {
-                    const int col = 16 * ti + c;
-                    const T x = (uok && col < r) ? P[(size_t)u * su + (size_t)(1 + col) * sc] : T(0);
+                    const T x = (uok && 16 * ti + c < r) ? cj[k][ti] : T(0);
                     av[ti] = x;
                     bv[ti] = cfu * x;
                 }
@@ -2079,20 +2139,27 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) Hd[ti][tj][v] += (double)acc[ti][tj][v];
         }
-        if (l == 0 && !a.grev) break;
+        if (!gemv) break;
         // gbar_{l-1}[u'] = sum_v W_l[v][u'] ga[v] over the w outputs v of layer l
-        const int in = l == 0 ? r : w;
-        const int ld = l == 0 ? a.lda0 : a.lda;
-        const T* Wl = static_cast<const T*>(a.W[l]);
-        const int v0 = slice * rows_per, v1 = min(w, v0 + rows_per);
 #pragma unroll
         for (int cg = 0; cg < kCurvMaxW / 128; ++cg) {
-            const int u0 = 128 * cg + 4 * vq; // 4 adjacent outputs; ld is a multiple of 32 and zero padded
+            const int u0 = 128 * cg + u00; // 4 adjacent outputs; ld is a multiple of 32 and zero padded
             if (128 * cg >= in) break;
             double sacc[4] = {0.0, 0.0, 0.0, 0.0};
             if (u0 < in) {
+                int vb = v0;
+                if (WQ > 0 && cg == 0) {
+#pragma unroll
+                    for (int b = 0; b < WQ; ++b) {
+                        const double g = v0 + b < v1 ? ga[v0 + b] : 0.0;
+                        asm volatile("" : "+v"(wq[b])); // converted here, not at the load
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) sacc[e] = fma((double)wq[b][e], g, sacc[e]);
+                    }
+                    vb = v0 + WQ;
+                }
                 constexpr int RB = 8; // rows in flight
-                for (int vb = v0; vb < v1; vb += RB) {
+                for (; vb < v1; vb += RB) {
                     V4 x[RB];
 #pragma unroll
                     for (int b = 0; b < RB; ++b)
@@ -2335,21 +2402,31 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_curv(int f32, const CurvArgs& a, int items, hipStream_t s)
+hipError_t launch_curv(int f32, const CurvArgs& a, int items, int n_cu, hipStream_t s)
 {
     if (items <= 0 || a.L <= 0) return hipSuccess;
     if (a.r > kMaxR) return hipErrorInvalidValue;
     if (a.width > kCurvMaxW) return hipErrorInvalidValue;
-    const int rt = a.r <= 16 ? 1 : 2;
+    if (a.ksplit < 1 || a.ksplit > kMaxSplit || a.parts > 8) return hipErrorInvalidValue;
     const size_t pw = (size_t)(a.width > a.r ? a.width : a.r);
+    const int rt = a.r <= 16 ? 1 : 2;
     const size_t sh = sizeof(double) * (3 * (size_t)a.width + 8 * pw + 4 * rt * rt * 4 * 64 + (size_t)a.r * a.r);
-    if (rt == 1) {
-        if (f32) RS_LAUNCH((k_curv<float, 1>), dim3(items), dim3(256), sh, s, a);
-        else RS_LAUNCH((k_curv<double, 1>), dim3(items), dim3(256), sh, s, a);
+#define RS_CURV(RT, KT, WQ)                                                                               \
+    do {                                                                                                  \
+        if (f32) RS_LAUNCH((k_curv<float, RT, KT, WQ * 2>), dim3(items), dim3(256), sh, s, a);           \
+        else RS_LAUNCH((k_curv<double, RT, KT, WQ>), dim3(items), dim3(256), sh, s, a);                  \
+    } while (0)
+    // the weight rows ahead only while a workgroup per item still fits on the chip
+    // at once (their registers halve the workgroups per compute unit)
+    const bool ahead = items <= 2 * n_cu;
+    if (a.width <= 128) {
+        if (rt == 1) { if (ahead) RS_CURV(1, 8, 8); else RS_CURV(1, 8, 0); }
+        else { if (ahead) RS_CURV(2, 8, 8); else RS_CURV(2, 8, 0); }
     } else {
-        if (f32) RS_LAUNCH((k_curv<float, 2>), dim3(items), dim3(256), sh, s, a);
-        else RS_LAUNCH((k_curv<double, 2>), dim3(items), dim3(256), sh, s, a);
+        if (rt == 1) { if (ahead) RS_CURV(1, 16, 8); else RS_CURV(1, 16, 0); }
+        else { if (ahead) RS_CURV(2, 16, 8); else RS_CURV(2, 16, 0); }
     }
+#undef RS_CURV
     return hipGetLastError();
 }
 
