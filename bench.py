@@ -107,6 +107,9 @@ def parse():
     ap.add_argument("--z0", default="random", choices=["random", "zero"], help="start points of the solves")
     ap.add_argument("--twist", type=float, default=None, help="one twist angle (deg) for every item")
     ap.add_argument("--epochs", type=int, nargs=2, default=[400, 400], help="learned path: stage epochs")
+    ap.add_argument("--train-epochs", type=int, default=0,
+                    help="simulate path: train the subspace on static snapshots for this many epochs first (0: untrained)")
+    ap.add_argument("--train-snapshots", type=int, default=512, help="simulate path: snapshots for --train-epochs")
     ap.add_argument("--lam-rel", type=float, nargs="+", default=[0.1], help="learned path: lambda_LS factors")
     ap.add_argument("--proj", default="abs", choices=["clamp", "abs"], help="Hessian eigen-projection")
     ap.add_argument("--eig-floor", type=float, default=1e-8)
@@ -344,12 +347,25 @@ def main_simulate(args):
     prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec or "f32"]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     dev = "cuda:0"
+    subspace = "plain (untrained Glorot) decoder"
+    trained = None
+    if args.train_epochs > 0:
+        from paper_2409_03807_amd import learn
+        trained = learn.train_dynamics_subspace(p, n_snap=args.train_snapshots, epochs=args.train_epochs,
+                                                log=lambda *a, **k: print(*a, **k, file=sys.stderr))
+        p.Ws, p.bs = trained["Ws"], trained["bs"]
+        subspace = (f"decoder trained on {trained['train_snapshots']} static snapshots (gravity, {trained['poses']}), "
+                    f"{args.train_epochs} epochs")
     ctx = rb.Context(p, prec=prec, max_batch=B)
     z0 = torch.zeros((B, p.r), dtype=torch.float64, device=dev)
+    if trained is not None:
+        z0[:] = trained["z_rest"]
     v0 = torch.tensor(I.swing_velocities(p, B), device=dev)
     # convergence floor: 1e-6 of the first step's start gradient (largest over the batch)
-    qb1 = (v0 * p.dt).contiguous()
-    _, g1, _ = ctx.energy_grad_hess(z0, qbar=qb1, dt=p.dt, flags=0)
+    x0, _ = ctx.decode(z0, want_J=False)
+    free = torch.tensor(~p.pinned.astype(bool), device=dev)[None, :, None]
+    qb1 = ((x0.double() - torch.tensor(p.X, device=dev)[None]) + p.dt * v0) * free
+    _, g1, _ = ctx.energy_grad_hess(z0, qbar=qb1.contiguous(), dt=p.dt, flags=0)
     opts = rb.default_opts(abs_tol=1e-6 * float(g1.abs().max().item()))
     if args.warmup:
         ctx.simulate(z0, args.warmup, p.dt, v0=v0, opts=opts, want_traj=False)
@@ -367,6 +383,16 @@ def main_simulate(args):
     iters = res["iters"].cpu().numpy()
     conv = B * args.steps - int(failed.sum())
     x, _ = ctx.decode(res["traj"][-1].contiguous(), want_J=False)
+    # how the simulations move: lowest point and mean end-face displacement every 20 steps
+    tip = torch.tensor(I.face_vertices(p.X, 0, p.X[:, 0].max()), device=dev)
+    Xd = torch.tensor(p.X, device=dev)
+    motion = {"step": [], "min_y": [], "tip_disp_mean": []}
+    for k in list(range(0, args.steps, 20)) + [args.steps - 1]:
+        xk, _ = ctx.decode(res["traj"][k].contiguous(), want_J=False)
+        xk = xk.double()
+        motion["step"].append(k + 1)
+        motion["min_y"].append(round(float(xk[..., 1].min().item()), 4))
+        motion["tip_disp_mean"].append(round(float((xk[:, tip] - Xd[tip]).norm(dim=-1).mean().item()), 4))
     line = {
         "metric": "converged reduced solves/s at rel. grad 1e-6 (implicit-Euler steps)",
         "value": conv / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -374,10 +400,12 @@ def main_simulate(args):
         "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": f"c5: 50x10x10 beam, nv={p.nv}, ne={p.ne}, r={p.r}, hidden={p.hidden}, "
                                f"|S|={len(p.cub_elem)}, {B} simulations x {args.steps} steps, dt=1/60, ground "
-                               f"y={p.ground_y} m, k_ground={p.k_ground:g} N/m, plain (untrained Glorot) decoder, "
+                               f"y={p.ground_y} m, k_ground={p.k_ground:g} N/m, {subspace}, "
                                f"seeded swing velocities", "batch": B, "path": "simulate"},
         "failed_steps": int(failed.sum()), "mean_iters_per_step": float(iters.sum() / (B * max(args.steps, 1))),
-        "min_y_last_step": float(x[..., 1].min().item()),
+        "min_y_last_step": float(x[..., 1].min().item()), "motion": motion,
+        "subspace_training": None if trained is None else {
+            k: trained[k] for k in ("snapshot_solve", "train_snapshots", "epochs", "loss", "train_seconds", "poses")},
         "roofline": roof, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)

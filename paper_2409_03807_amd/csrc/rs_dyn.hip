@@ -84,23 +84,35 @@ __device__ inline double block_sum(double v, double* red)
 }
 
 // One workgroup per item.  MODE 0: contact seeds into dseed.  MODE 1: the
-// inertia adjoint (G h - c) / dt^2 added to the adjoint of h (slice 0 of gbar).
+// inertia adjoint (G d - c) / dt^2 added to the adjoint of h (slice 0 of gbar).
 // MODE 2: inertia and contact added to E, g and the Gauss-Newton part of H.
 // MODE 3: energies only (float64 value pass: act and out with one column).
+// The r x r and r-vector sums run on the float64 matrix cores in 4-row steps
+// (lane (c, kq) holding row 4t + kq, column c of a 16-column tile; the
+// gradient as the product with a B operand that is zero outside column 0),
+// waves taking every fourth step, their partials added in wave order:
+// * contact: the active contact rows (penetration d < 0) of each chunk of 1024,
+//   listed in index order by a wave-ballot compaction, give
+//   k_g sum_k J_k^T J_k and k_g sum_k d_k J_k^T;
+// * inertia: G J_h (m x r, G symmetric) on the matrix cores into LDS, then
+//   J_h^T (G J_h) / dt^2 and J_h^T y / dt^2 with y = G d - c.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_dyn(DynArgs a)
 {
     extern __shared__ double sh[];
     __shared__ double red[256];
-    const int item = blockIdx.x, tid = threadIdx.x;
+    __shared__ int wcnt[4];
+    using acc_t = typename Mfma<double>::acc_t;
+    const int item = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, kq = lane >> 4;
     if (a.count && item >= *a.count) return;
     if (MODE == 1 && !a.inertia) return;
     const int r = a.r, m = a.in_last, nc = a.nc;
+    const int RT = (r + 15) / 16;
     const int b = a.imap ? a.imap[item] : item;
     const T* O = static_cast<const T*>(a.out) + (size_t)item * a.rows_pad * nc;
     const T* act = a.act ? static_cast<const T*>(a.act) + (size_t)item * nc * a.wrows : nullptr;
-    double e_acc = 0.0;
-    // ---- contact rows
+    // ---- contact seeds
     if (MODE == 0) {
         T* ds = static_cast<T*>(a.dseed) + (size_t)item * a.rows_pad;
         for (int k = tid; k < a.ncont; k += 256) {
@@ -109,45 +121,90 @@ __global__ __launch_bounds__(256) void k_dyn(DynArgs a)
         }
         return;
     }
-    double* gl = sh;                  // r gradient accumulators (MODE 2)
-    double* Hl = sh + 32;             // r x r (MODE 2)
-    if (MODE == 2) {
-        for (int t = tid; t < 32 + 32 * 32; t += 256) sh[t] = 0.0;
-        __syncthreads();
+    double* dv = sh;           // m: d = h - eta
+    double* y = dv + 256;      // m: G d - c
+    double* wk = y + 256;      // work area: the contact list, then G J_h (m x 32), then the wave partials
+    double e_acc = 0.0;
+    acc_t aH[2][2], ag[2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+        ag[ti] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) aH[ti][tj] = acc_t{0, 0, 0, 0};
     }
+    // ---- contact rows
     if (MODE == 2 || MODE == 3) {
-        for (int k = 0; k < a.ncont; ++k) {
-            const T* row = O + (size_t)(a.crow + k) * nc;
-            const double d = a.Xc[k] + (double)row[0] - a.ground_y;
-            if (!(d < 0.0)) continue;
-            if (tid == 0) e_acc += 0.5 * a.k_ground * d * d;
-            if (MODE == 2) {
-                // one thread per (k1, k2) entry and per gradient entry; contact rows are few
-                for (int t = tid; t < r * r; t += 256) {
-                    const int k1 = t / r, k2 = t - k1 * r;
-                    Hl[k1 * 32 + k2] += a.k_ground * (double)row[1 + k1] * (double)row[1 + k2];
+        int* list = reinterpret_cast<int*>(wk); // 1024 active indices of a chunk
+        double* dl = wk + 512;                  // and their penetrations
+        for (int k0 = 0; k0 < a.ncont; k0 += 1024) {
+            const int kn = min(1024, a.ncont - k0);
+            int nact = 0;
+            __syncthreads(); // the previous chunk's list is consumed
+            for (int j = 0; j < kn; j += 256) {
+                const int k = k0 + j + tid;
+                double d = 0.0;
+                bool on = false;
+                if (j + tid < kn) {
+                    d = a.Xc[k] + (double)O[(size_t)(a.crow + k) * nc] - a.ground_y;
+                    on = d < 0.0;
                 }
-                if (tid < r) gl[tid] += a.k_ground * d * (double)row[1 + tid];
+                if (on) e_acc += 0.5 * a.k_ground * d * d;
+                if (MODE == 2) {
+                    const unsigned long long bal = __ballot(on);
+                    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+                    if (lane == 0) wcnt[wave] = __popcll(bal);
+                    __syncthreads();
+                    int off = nact;
+                    for (int q = 0; q < wave; ++q) off += wcnt[q];
+                    if (on) {
+                        list[off + below] = k;
+                        dl[off + below] = d;
+                    }
+                    nact += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+                    __syncthreads(); // wcnt is reused
+                }
+            }
+            if (MODE == 2) {
+                __syncthreads(); // the list is complete
+                for (int t = wave; t < (nact + 3) / 4; t += 4) {
+                    const int idx = 4 * t + kq;
+                    const bool ok = idx < nact;
+                    const T* row = O + (size_t)(a.crow + (ok ? list[idx] : 0)) * nc;
+                    double x[2];
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti) {
+                        const int col = 16 * ti + c;
+                        x[ti] = (ok && ti < RT && col < r) ? (double)row[1 + col] : 0.0;
+                    }
+                    const double bg = (ok && c == 0) ? a.k_ground * dl[idx] : 0.0;
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti) {
+                        if (ti >= RT) break;
+                        ag[ti] = Mfma<double>::mac(x[ti], bg, ag[ti]);
+#pragma unroll
+                        for (int tj = 0; tj < 2; ++tj)
+                            if (tj < RT) aH[ti][tj] = Mfma<double>::mac(x[ti], a.k_ground * x[tj], aH[ti][tj]);
+                    }
+                }
             }
         }
     }
     // ---- inertia
     if (a.inertia) {
-        double* h = sh + 32 + 32 * 32;    // m
-        double* y = h + 256;              // m: G h - c
         const double* cv = a.cvec + (size_t)b * m;
         const double* et = a.eta ? a.eta + (size_t)b * m : nullptr;
         for (int u = tid; u < m; u += 256) {
             double hv;
             if (a.L > 0) hv = (double)act[u];
             else hv = a.z[(size_t)(a.zmap ? a.zmap[item] : item) * r + u];
-            h[u] = et ? hv - et[u] : hv;   // d = h - eta
+            dv[u] = et ? hv - et[u] : hv;
         }
         __syncthreads();
+        // y = G d - c, reading G by columns (G symmetric: consecutive threads, consecutive addresses)
         for (int u = tid; u < m; u += 256) {
             double s = 0.0;
-            const double* Gu = a.G + (size_t)u * m;
-            for (int v = 0; v < m; ++v) s += Gu[v] * h[v];
+#pragma unroll 8
+            for (int v = 0; v < m; ++v) s += a.G[(size_t)v * m + u] * dv[v];
             y[u] = s - cv[u];
         }
         __syncthreads();
@@ -157,48 +214,91 @@ __global__ __launch_bounds__(256) void k_dyn(DynArgs a)
             return;
         }
         double e = 0.0;
-        for (int u = tid; u < m; u += 256) e += h[u] * (y[u] - cv[u]);
+        for (int u = tid; u < m; u += 256) e += dv[u] * (y[u] - cv[u]);
         e_acc += 0.5 * a.inv_dt2 * e;
         if (tid == 0) e_acc += 0.5 * a.inv_dt2 * a.kappa[b];
         if (MODE == 2) {
             // J_h (m x r): the Jacobian columns of the activation, or the identity (linear decoder)
-            auto Jh = [&](int u, int k) -> double {
+            auto jh = [&](int u, int k) -> double {
+                if (u >= m || k >= r) return 0.0;
                 if (a.L > 0) return (double)act[(size_t)(1 + k) * a.wrows + u];
                 return u == k ? 1.0 : 0.0;
             };
-            // gradient J_h^T y / dt^2
-            if (tid < r) {
-                double s = 0.0;
-                for (int u = 0; u < m; ++u) s += Jh(u, tid) * y[u];
-                gl[tid] += a.inv_dt2 * s;
-            }
-            // Gauss-Newton J_h^T G J_h / dt^2: thread (k1, k2 block) forms (G J_h)[:, k2] on the fly
-            double* GJ = y + 256;         // m x 32: column k2 of G J_h
-            for (int t = tid; t < m * r; t += 256) {
-                const int u = t / r, k2 = t - u * r;
-                double s = 0.0;
-                const double* Gu = a.G + (size_t)u * m;
-                for (int v = 0; v < m; ++v) s += Gu[v] * Jh(v, k2);
-                GJ[u * 32 + k2] = s;
+            double* GJ = wk; // m x 32
+            const int ks = (m + 3) / 4, mt = (m + 15) / 16;
+            __syncthreads(); // the contact list is no longer read
+            for (int tile = wave; tile < mt * RT; tile += 4) {
+                const int ti = tile / RT, tj = tile - ti * RT;
+                acc_t acc = acc_t{0, 0, 0, 0};
+                const int gi = 16 * ti + c;
+#pragma unroll 4
+                for (int st = 0; st < ks; ++st) {
+                    const int kk = 4 * st + kq;
+                    const double av = (gi < m && kk < m) ? a.G[(size_t)kk * m + gi] : 0.0; // G[gi][kk]
+                    acc = Mfma<double>::mac(av, jh(kk, 16 * tj + c), acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * ti + kq + 4 * v;
+                    if (row < m) GJ[row * 32 + 16 * tj + c] = acc[v];
+                }
             }
             __syncthreads();
-            for (int t = tid; t < r * r; t += 256) {
-                const int k1 = t / r, k2 = t - k1 * r;
-                double s = 0.0;
-                for (int u = 0; u < m; ++u) s += Jh(u, k1) * GJ[u * 32 + k2];
-                Hl[k1 * 32 + k2] += a.inv_dt2 * s;
+            for (int t = wave; t < ks; t += 4) {
+                const int u = 4 * t + kq;
+                const bool ok = u < m;
+                double x[2];
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti) x[ti] = (ok && ti < RT) ? jh(u, 16 * ti + c) : 0.0;
+                const double bg = (ok && c == 0) ? a.inv_dt2 * y[u] : 0.0;
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti) {
+                    if (ti >= RT) break;
+                    ag[ti] = Mfma<double>::mac(x[ti], bg, ag[ti]);
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj)
+                        if (tj < RT) {
+                            const int col = 16 * tj + c;
+                            const double gv = (ok && col < r) ? a.inv_dt2 * GJ[u * 32 + col] : 0.0;
+                            aH[ti][tj] = Mfma<double>::mac(x[ti], gv, aH[ti][tj]);
+                        }
+                }
             }
         }
     }
     const double Et = block_sum(e_acc, red);
     if (tid == 0 && a.E) a.E[item] += Et;
-    if (MODE == 2) {
-        __syncthreads();
-        if (a.g)
-            for (int k = tid; k < r; k += 256) a.g[(size_t)item * r + k] += gl[k];
-        if (a.H)
-            for (int t = tid; t < r * r; t += 256) a.H[(size_t)item * r * r + t] += Hl[(t / r) * 32 + t % r];
-    }
+    if (MODE != 2) return;
+    // the four waves' partials, added in wave order
+    double* part = wk; // [4 waves][2][2 + 1][4][64]
+    __syncthreads();   // G J_h is no longer read
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj) part[((((wave * 2 + ti) * 3 + tj) * 4) + v) * 64 + lane] = aH[ti][tj][v];
+            part[((((wave * 2 + ti) * 3 + 2) * 4) + v) * 64 + lane] = ag[ti][v];
+        }
+    __syncthreads();
+    if (wave != 0) return;
+    auto sum4 = [&](int ti, int tj, int v) {
+        double s = 0.0;
+        for (int q = 0; q < 4; ++q) s += part[((((q * 2 + ti) * 3 + tj) * 4) + v) * 64 + lane];
+        return s;
+    };
+    for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * ti + kq + 4 * v; // float64 result layout: D[lane / 16 + 4 v][lane % 16]
+            if (row >= r) continue;
+            if (a.H)
+                for (int tj = 0; tj < RT; ++tj) {
+                    const int col = 16 * tj + c;
+                    if (col < r) a.H[((size_t)item * r + row) * r + col] += sum4(ti, tj, v);
+                }
+            if (a.g && c == 0) a.g[(size_t)item * r + row] += sum4(ti, 2, v);
+        }
 }
 
 // The inertial target of one step of a simulation, per item: eta = h0 with
@@ -300,7 +400,8 @@ hipError_t launch_dyn(int f32, int mode, const DynArgs& a, int cap, hipStream_t 
 {
     if (cap <= 0) return hipSuccess;
     if (a.r > 32 || a.in_last > 256) return hipErrorInvalidValue;
-    const size_t shm = sizeof(double) * (32 + 32 * 32 + 256 + 256 + 256 * 32);
+    // d, y and the work area (the contact list, G J_h for m <= 256, the waves' partials)
+    const size_t shm = sizeof(double) * (256 + 256 + 256 * 32);
     const dim3 g(cap), blk(256);
     if (mode == 3) {
         RS_LAUNCH((k_dyn<double, 3>), g, blk, shm, s, a);

@@ -292,6 +292,42 @@ def snapshot_loads(p: Problem, N: int, seed: int = SEED_SNAPSHOTS, fmax: float =
     return twist, twist_targets(p.X, p.target_vtx, twist), f
 
 
+def end_pose_problem(p: Problem) -> Problem:
+    """The static snapshot problem of a dynamics workload: the same mesh, material,
+    cubature and decoder, with penalty targets (k_c = 1e6 N/m) on the x = L face
+    and no inertia or contact (the full-space snapshot solver is quasi-static)."""
+    q = Problem(**{**p.__dict__})
+    q.target_vtx = face_vertices(p.X, 0, p.X[:, 0].max())
+    q.k_c = 1e6
+    q.force_vtx = np.zeros(0, np.int32)
+    q.contact_vtx = np.zeros(0, np.int32)
+    q.dt, q.k_ground = 0.0, 0.0
+    return q
+
+
+def end_pose_targets(p: Problem, verts: np.ndarray, N: int, seed: int = SEED_SNAPSHOTS,
+                     bend_deg: float = 60.0, twist_deg: float = 90.0):
+    """Targets of the end-face vertices carried rigidly by a rotation about the
+    pinned face's centroid: bends about y and z U[-bend_deg, bend_deg], then a
+    twist about x U[-twist_deg, twist_deg] through the end face's centroid.
+    Returns (N, len(verts), 3)."""
+    rng = np.random.default_rng(seed)
+    ang = np.deg2rad(rng.uniform(-1.0, 1.0, size=(N, 3)) * np.array([twist_deg, bend_deg, bend_deg]))
+    c0 = p.X[p.pinned.astype(bool)].mean(axis=0)
+    P = p.X[verts]
+    ce = P.mean(axis=0)
+    out = np.empty((N, len(verts), 3))
+    for b in range(N):
+        ax, ay, az = ang[b]
+        Rx = np.array([[1, 0, 0], [0, math.cos(ax), -math.sin(ax)], [0, math.sin(ax), math.cos(ax)]])
+        Ry = np.array([[math.cos(ay), 0, math.sin(ay)], [0, 1, 0], [-math.sin(ay), 0, math.cos(ay)]])
+        Rz = np.array([[math.cos(az), -math.sin(az), 0], [math.sin(az), math.cos(az), 0], [0, 0, 1]])
+        R = Rz @ Ry
+        tw = ce + (P - ce) @ Rx.T
+        out[b] = c0 + (tw - c0) @ R.T
+    return out
+
+
 def heldout_split(N: int, n_test: int, seed: int = SEED_SPLIT):
     """(train indices, held-out indices), a seeded permutation."""
     perm = np.random.default_rng(seed).permutation(N)

@@ -40,7 +40,7 @@ def _t64(a):
 def generate_snapshots(ctx, targets, force, chunk=256, opts=None, log=print):
     """Full-space equilibria (N x nv x 3 displacements, float64 device) of the load
     cases, solved in batches of `chunk` from the rest shape."""
-    N = targets.shape[0]
+    N = (targets if targets is not None else force).shape[0]
     out = torch.empty((N, ctx.nv, 3), dtype=torch.float64, device=DEV)
     status = torch.empty(N, dtype=torch.int32, device=DEV)
     iters = torch.empty(N, dtype=torch.int32, device=DEV)
@@ -48,7 +48,8 @@ def generate_snapshots(ctx, targets, force, chunk=256, opts=None, log=print):
     for c0 in range(0, N, chunk):
         c1 = min(N, c0 + chunk)
         res = ctx.full_solve(torch.zeros((c1 - c0, ctx.nv, 3), dtype=torch.float64, device=DEV),
-                             _t64(targets[c0:c1]), _t64(force[c0:c1]), opts)
+                             None if targets is None else _t64(targets[c0:c1]),
+                             None if force is None else _t64(force[c0:c1]), opts)
         out[c0:c1] = res["u"]
         status[c0:c1] = res["status"]
         iters[c0:c1] = res["iters"]
@@ -222,3 +223,36 @@ def run(n_snap=2048, n_test=256, epochs1=100, epochs2=100, batch=128, pairs=64, 
         log(f"held-out {name}: {r_e}", flush=True)
     out["heldout"] = res
     return out
+
+
+def train_dynamics_subspace(p, n_snap=512, epochs=300, batch=128, lr=1e-3, bend_deg=45.0, twist_deg=60.0,
+                            enc_hidden=(256, 256), log=print):
+    """A subspace for the implicit-Euler workload: full-space static equilibria of
+    the beam under gravity with its end face held by penalty targets in random
+    rigid poses (bends about y and z, twist about x; rs_full_solve), then the
+    supervised construction with the reconstruction loss alone (Sec. 3.2).
+    Returns the trained decoder (Ws, bs), the rest shape's reduced coordinates
+    and the snapshot and training statistics."""
+    torch.cuda.set_device(0)
+    q = I.end_pose_problem(p)
+    ctx = rb.Context(q, prec=rb.PREC_F32, max_batch=max(2 * batch, 256))
+    targets = I.end_pose_targets(p, q.target_vtx, n_snap, bend_deg=bend_deg, twist_deg=twist_deg)
+    u, info = generate_snapshots(ctx, targets, None, log=log)
+    ok = info.pop("status") == rb.CONVERGED
+    idx = torch.tensor(np.nonzero(ok)[0], device=DEV)
+    store = u.reshape(n_snap, -1)[idx].float().contiguous()
+    n = len(idx)
+    eW, eb = I.glorot_decoder(p.n, list(enc_hidden), p.r, seed=I.SEED_ENCODER)
+    tr = rb.Trainer(ctx, eW, eb, p.Ws, p.bs, max_batch=batch)
+    t0 = time.time()
+    loss = run_epochs(tr, store, n, epochs, min(batch, n), lr, np.random.default_rng(7), log=log, tag="c5 subspace")
+    torch.cuda.synchronize()
+    seconds = time.time() - t0
+    z_rest = tr.encode(torch.zeros((1, p.n), dtype=torch.float32, device=DEV))[0].double()
+    _, dec = tr.params()
+    parts = ctx.unpack_params(dec.double().cpu())
+    tr.close()
+    return dict(Ws=[W.numpy() for W, _ in parts], bs=[b.numpy() for _, b in parts], z_rest=z_rest,
+                snapshot_solve=info, train_snapshots=n, epochs=epochs, loss=loss[0], train_seconds=seconds,
+                poses=f"end face bent U[-{bend_deg:g}, {bend_deg:g}] deg about y and z, twisted "
+                      f"U[-{twist_deg:g}, {twist_deg:g}] deg")
