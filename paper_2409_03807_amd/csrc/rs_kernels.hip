@@ -1201,14 +1201,29 @@ static hipError_t mlp_dispatch(const MlpArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-bool mlp_fits(int f32, int nc, int r, int wrows)
+// LDS bytes of the fused kernel with np columns (every layer's bias staged)
+static size_t mlp_lds(int f32, int np, int nc, int r, int wrows)
 {
-    const int np = nc > 1 ? 80 : 16;
     const int kr = (r + kTileK - 1) / kTileK * kTileK;
     const size_t ldy = (size_t)(kr > wrows ? kr : wrows) + (f32 ? 4 : 2);
+    return (np * ldy + (size_t)(np / nc + kMaxL) * wrows) * (f32 ? 4 : 8);
+}
+
+// whether a column tile of np columns (16 CT) holds whole items and fits
+static bool mlp_tile_ok(int f32, int np, int nc, int r, int wrows)
+{
+    // (float64 with five column tiles at width 256 exceeds the registers)
+    if (!f32 && np == 80 && wrows / 64 == 4) return false;
+    return np / nc >= 1 && mlp_lds(f32, np, nc, r, wrows) <= kMlpLds;
+}
+
+bool mlp_fits(int f32, int nc, int r, int wrows)
+{
     const int rt = wrows / 64;
-    return np / nc >= 1 && (rt == 1 || rt == 2 || rt == 4) &&
-           (np * ldy + (size_t)(np / nc + kMaxL) * wrows) * (f32 ? 4 : 8) <= kMlpLds;
+    if (!(rt == 1 || rt == 2 || rt == 4)) return false;
+    if (nc == 1) return mlp_tile_ok(f32, 16, nc, r, wrows);
+    return mlp_tile_ok(f32, 80, nc, r, wrows) || mlp_tile_ok(f32, 48, nc, r, wrows) ||
+           mlp_tile_ok(f32, 32, nc, r, wrows);
 }
 
 template <typename T, typename OP = T>
@@ -1217,12 +1232,17 @@ static hipError_t mlp_dispatch_jac(const MlpArgs& a, int n_cu, hipStream_t s)
     // items per workgroup: the most of 4, 2, 1 that still gives every compute
     // unit two workgroups (a workgroup runs its layers on one compute unit;
     // a second one overlaps its products with the first one's activation
-    // pass, and a small batch is spread thin rather than queued on a few)
+    // pass, and a small batch is spread thin rather than queued on a few);
+    // then the narrowest column tile that holds them, or the widest that fits
+    constexpr int f32 = std::is_same<T, float>::value;
     int ib = 4;
     while (ib > 1 && (a.items + ib - 1) / ib < 2 * n_cu) ib >>= 1;
     const int cols = ib * a.nc;
-    if (cols <= 32) return mlp_dispatch<T, 2, OP>(a, s);
-    if (cols <= 48) return mlp_dispatch<T, 3, OP>(a, s);
+    int np = cols <= 32 ? 32 : cols <= 48 ? 48 : 80;
+    while (np > 32 && !mlp_tile_ok(f32, np, a.nc, a.r, a.wrows)) np = np == 80 ? 48 : 32;
+    if (np == 32 && !mlp_tile_ok(f32, 32, a.nc, a.r, a.wrows)) np = 48;
+    if (np == 32) return mlp_dispatch<T, 2, OP>(a, s);
+    if (np == 48) return mlp_dispatch<T, 3, OP>(a, s);
     return mlp_dispatch<T, 5, OP>(a, s);
 }
 
