@@ -58,6 +58,19 @@ template <> struct Vec16<float> { using type = f32x4; static constexpr int n = 4
 template <> struct Vec16<double> { using type = f64x2; static constexpr int n = 2; };
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations complete
+// (lgkmcnt 0, vector-memory count untouched), then s_barrier.  Global stores
+// may still be in flight; callers read nothing back that another wave of the
+// workgroup stored to global memory.
+__device__ inline void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Eight float32 values as three BF16 parts: hi = bf16(x), mid = bf16(x - hi),
 // lo = bf16(x - hi - mid).  Each difference is exact in float32 (the operands
 // are within a factor of two of each other), so hi + mid + lo carries all 24

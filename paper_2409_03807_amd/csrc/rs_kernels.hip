@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
         }
         if (!more) break;
         store(buf ^ 1);
-        __syncthreads();
+        lds_barrier(); // LDS only: this tile's output stores stay in flight
         buf ^= 1;
         ct = nct;
         c = nchk;
@@ -455,9 +455,10 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
     T* Cout = static_cast<T*>(a.C);
     load(g);
     for (int ct = g; ct < ntiles; ct += groups) {
-        __syncthreads(); // the previous tile's LDS reads are done
+        // LDS-only barriers: the previous tile's output stores stay in flight
+        lds_barrier(); // the previous tile's LDS reads are done
         store();
-        __syncthreads();
+        lds_barrier();
         if (ct + groups < ntiles) load(ct + groups);
         acc_t acc[4];
 #pragma unroll
@@ -604,9 +605,10 @@ __global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
     float* Cout = static_cast<float*>(a.C);
     load(g);
     for (int ct = g; ct < ntiles; ct += groups) {
-        __syncthreads(); // the previous tile's LDS reads are done
+        // LDS-only barriers: the previous tile's output stores stay in flight
+        lds_barrier(); // the previous tile's LDS reads are done
         store();
-        __syncthreads();
+        lds_barrier();
         if (ct + groups < ntiles) load(ct + groups);
         f32x4 acc[4], corr[4];
 #pragma unroll
@@ -931,18 +933,6 @@ __device__ inline void global_store_free4(float* p, f32x4 v)
     asm volatile("global_store_dwordx4 %0, %1, off" : : "v"(p), "v"(v));
 }
 
-// Workgroup barrier for LDS traffic only: this wave's LDS operations complete
-// (lgkmcnt 0, vector-memory count untouched), then s_barrier.  Global stores
-// may still be in flight; callers read nothing back that another wave of the
-// workgroup stored to global memory.
-__device__ inline void lds_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
 
 // ---------------------------------------------------------------------------
 // Fused hidden layers.  A workgroup owns CT*16 columns holding whole items
@@ -2011,7 +2001,8 @@ hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s)
 // uses are loaded into registers while layer l runs, and the first rows of
 // the thread's W_l slice at the top of layer l (before that prefetch, so that
 // waiting on them leaves it in flight).  Every such load is unconditional, at
-// a clamped in-bounds address.
+// a clamped in-bounds address, and the barriers order LDS traffic only
+// (lds_barrier), so the loads stay in flight across them.
 constexpr int kCurvMaxW = kMaxWidth;
 
 // KT: 4-row steps per wave held for a layer (w <= 16 KT); WQ: rows of the
@@ -2119,7 +2110,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
 #pragma unroll
             for (int ti = 0; ti < RT; ++ti) cj[k][ti] = pj[k][ti];
         if (l > 0) fetch(l - 1);
-        __syncthreads(); // gh of this layer visible; cf, ga, part free
+        lds_barrier(); // gh of this layer visible; cf, ga, part free
         if (tid < w) {
             const double av = (double)cv;
             // s'(a) and s''(a) share exp(a) for a <= 0 (1 and 0 above)
@@ -2128,7 +2119,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             ga[tid] = av > 0.0 ? gh[tid] : gh[tid] * ex;
             if (a.delta) a.delta[((size_t)item * a.L + l) * w + tid] = ga[tid];
         }
-        __syncthreads();
+        lds_barrier();
         if (a.H) {
             acc_t acc[RT][RT];
 #pragma unroll
@@ -2197,7 +2188,7 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
             for (int e = 0; e < 4; ++e)
                 if (u0 + e < in) part[slice * pw + u0 + e] = sacc[e];
         }
-        __syncthreads();
+        lds_barrier();
         for (int u = tid; u < in; u += 256) {
             double o = 0.0;
             for (int q = 0; q < 8; ++q) o += part[q * pw + u];
@@ -2207,14 +2198,14 @@ __global__ __launch_bounds__(256) void k_curv(CurvArgs a)
     }
     if (!a.H) return; // gradient only
     // the four waves' partial sums, added in wave order
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int ti = 0; ti < RT; ++ti)
 #pragma unroll
         for (int tj = 0; tj < RT; ++tj)
 #pragma unroll
             for (int v = 0; v < 4; ++v) red[(((wave * RT + ti) * RT + tj) * 4 + v) * 64 + lane] = Hd[ti][tj][v];
-    __syncthreads();
+    lds_barrier();
     if (wave == 0) {
 #pragma unroll
         for (int ti = 0; ti < RT; ++ti)
