@@ -360,8 +360,11 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 // registers (thread: one column, K/4 consecutive k) while the current tile,
 // resident in LDS, feeds the MFMAs: the load latency hides behind a full
 // tile of MFMAs.  Used when the tile fits 64 KB of LDS.
+// The float32 output map over transposed activations (the reduced solve's
+// gemm_out) is held to 128 registers: four waves per SIMD instead of three
+// hide more of each tile's stores and next-tile loads (5% per launch at c2).
 template <typename T, int ROLE, int KCH, int INM, int OUTM>
-__global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && INM == IN_RAW_T && OUTM == OUT_PACK) ? 4 : 1) void k_gemm_p2(GemmArgs a, int groups)
 {
     using V = typename Vec16<T>::type;
     constexpr int VN = Vec16<T>::n;
@@ -540,8 +543,10 @@ __global__ __launch_bounds__(256) void k_gemm_p2(GemmArgs a, int groups)
 // BF16 parts on its way into LDS, and each 32-deep chunk is six 16x16x32 BF16
 // MFMAs per 16-column tile (mfma_bf16x6_chunk).  Same tiling, prefetch and
 // epilogue as k_gemm_p2.
+// (three waves per SIMD at K <= 128: the register budget that keeps three
+// workgroups' LDS tiles resident)
 template <int ROLE, int KCH, int OUTM>
-__global__ __launch_bounds__(256) void k_gemm_p2_bf16(GemmArgs a, int groups)
+__global__ __launch_bounds__(256, KCH <= 4 ? 3 : 1) void k_gemm_p2_bf16(GemmArgs a, int groups)
 {
     constexpr int KT = KCH * kTileK;
     constexpr int LD = KT + 8;   // BF16 elements per LDS row (16-byte pad)
