@@ -157,3 +157,28 @@ def test_lipschitz_param_grad_c4_sampled():
     assert bar < 1e-2
     assert abs(loss.item() - oloss) <= bar * abs(oloss)
     assert np.linalg.norm(grad.cpu().numpy() - ograd) <= bar * np.linalg.norm(ograd)
+
+
+def test_dynamics_subspace_training_small():
+    """The dynamics workload's subspace construction end to end on a small beam:
+    full-space equilibria of end-face poses, reconstruction training, and a
+    context built from the trained decoder evaluates the rest shape's
+    coordinates to a finite energy and a small displacement."""
+    from paper_2409_03807_amd import learn
+
+    p = I.make_problem("small", 6, 2, 2, 4, [32, 32], 48, wlo=1.0, whi=3.0, twist=False)
+    p.dt = 1.0 / 60.0
+    out = learn.train_dynamics_subspace(p, n_snap=32, epochs=60, batch=16, bend_deg=20.0, twist_deg=20.0,
+                                        log=lambda *a, **k: None)
+    assert out["snapshot_solve"]["converged"] == 32 and out["train_snapshots"] == 32
+    assert [W.shape for W in out["Ws"]] == [W.shape for W in p.Ws]
+    assert np.isfinite(out["loss"])
+    q = I.Problem(**{**p.__dict__})
+    q.Ws, q.bs = out["Ws"], out["bs"]
+    ctx = rb.Context(q, prec=rb.PREC_F64, max_batch=4)
+    z = out["z_rest"].reshape(1, -1).contiguous()
+    E, g, H = ctx.energy_grad_hess(z)
+    x, _ = ctx.decode(z, want_J=False)
+    assert torch.isfinite(E).all() and torch.isfinite(g).all() and torch.isfinite(H).all()
+    # the rest shape's coordinates decode to a displacement of the snapshots' size, not a blow-up
+    assert np.abs(x.double().cpu().numpy() - q.X).max() < 0.5

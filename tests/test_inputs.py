@@ -57,3 +57,39 @@ def test_twist_targets_are_rotations():
     # distances to the centroid are preserved and 180 deg mirrors y,z
     assert np.allclose(np.linalg.norm(t[1] - c, axis=1), np.linalg.norm(P - c, axis=1))
     assert np.allclose(t[2][:, 1:] - c[1:], -(P[:, 1:] - c[1:]))
+
+
+def test_c5_contact_set_is_the_free_surface():
+    p = I.config("c5")
+    X = p.X
+    lo, hi = X.min(0), X.max(0)
+    on_surface = np.any(np.isclose(X, lo) | np.isclose(X, hi), axis=1)
+    cv = p.contact_vtx
+    # every contact vertex is a free surface vertex, and every free surface vertex is one
+    assert on_surface[cv].all() and not p.pinned[cv].any()
+    assert len(cv) == int((on_surface & ~p.pinned.astype(bool)).sum())
+    # 50 x 10 x 10 cubes: 51 * 11 * 11 vertices, (49 * 9 * 9) interior, 11 * 11 on the pinned face
+    assert len(cv) == 51 * 11 * 11 - 49 * 9 * 9 - 11 * 11
+
+
+def test_end_pose_targets_are_rigid_motions():
+    p = I.config("c5")
+    q = I.end_pose_problem(p)
+    assert len(q.target_vtx) == 121 and len(q.contact_vtx) == 0 and q.dt == 0.0
+    t = I.end_pose_targets(p, q.target_vtx, 6, bend_deg=45.0, twist_deg=60.0)
+    P = p.X[q.target_vtx]
+    D0 = np.linalg.norm(P[:, None] - P[None], axis=-1)
+    c0 = p.X[p.pinned.astype(bool)].mean(0)
+    for b in range(6):
+        # pairwise distances of the face and its centroid's distance to the pinned face's are kept
+        assert np.allclose(np.linalg.norm(t[b][:, None] - t[b][None], axis=-1), D0)
+        assert np.isclose(np.linalg.norm(t[b].mean(0) - c0), np.linalg.norm(P.mean(0) - c0))
+        # the face's area element is kept (no shear or scaling of the face)
+        e1, e2 = P[1] - P[0], P[11] - P[0]
+        f1, f2 = t[b][1] - t[b][0], t[b][11] - t[b][0]
+        assert np.isclose(np.linalg.norm(np.cross(f1, f2)), np.linalg.norm(np.cross(e1, e2)))
+    # nonzero angles move the face
+    assert np.abs(t - P[None]).max() > 0.1
+    # zero angles leave the face where it is
+    t0 = I.end_pose_targets(p, q.target_vtx, 1, bend_deg=0.0, twist_deg=0.0)
+    assert np.allclose(t0[0], P)
