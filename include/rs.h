@@ -285,6 +285,20 @@ int rs_newton_solve(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
                     const rs_solve_opts* opts, int32_t* iters, int32_t* status,
                     double* relgrad, double* E, void* stream);
 
+/* The same solve, stream-ordered: enqueues exactly `super_steps` super-steps
+ * (each: evaluate the items that need g and H, their directions, one
+ * line-search round) on `stream` and returns without waiting or reading
+ * anything back, so the call can be captured into a HIP graph.  Every launch
+ * is sized for all B items; the kernels read the running counts on the device
+ * and idle workgroups exit at once.  Items that have not exited after
+ * `super_steps` keep status RS_RUNNING (-1) and their current z, iters and E;
+ * an item needs one super-step per accepted Newton step plus one per extra
+ * line-search round.  Outputs, workspace and errors as rs_newton_solve, plus
+ * RS_ERR_ARG for super_steps < 1. */
+int rs_newton_solve_async(rs_ctx* ctx, int32_t B, double* z, const rs_load* load,
+                          const rs_solve_opts* opts, int32_t super_steps, int32_t* iters,
+                          int32_t* status, double* relgrad, double* E, void* stream);
+
 /* L-BFGS with backtracking line search (Sec. 5: the paper's solver for its
  * main results, with exits I converged, II saddle / not a descent direction,
  * III 128 line-search trials, IV iteration limit), for B <= max_batch

@@ -97,7 +97,7 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
            "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
            "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam",
-           "rs_default_full_opts", "rs_full_solve", "rs_pca", "rs_simulate"]
+           "rs_default_full_opts", "rs_full_solve", "rs_pca", "rs_simulate", "rs_newton_solve_async"]
 
 _lib = None
 
@@ -125,6 +125,9 @@ def load_library():
         L.rs_newton_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
                                       C.POINTER(SolveOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p]
+        L.rs_newton_solve_async.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
+                                            C.POINTER(SolveOpts), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p]
         L.rs_lbfgs_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load),
                                      C.POINTER(LbfgsOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p]
@@ -396,17 +399,23 @@ class Context:
         self._check(load_library().rs_set_elem_hess_dump(self.ctx, _ptr(He), He.shape[0]), "rs_set_elem_hess_dump")
 
     def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None, qbar=None,
-                     dt=0.0):
+                     dt=0.0, super_steps=None):
         """z0 (B x r) float64 on the GPU; returns dict of device tensors.
         `out` may pass preallocated (z, iters, status, relgrad, E) tensors; qbar
-        (B x nv x 3) and dt > 0 make it one implicit-Euler step."""
+        (B x nv x 3) and dt > 0 make it one implicit-Euler step.  With
+        super_steps, the stream-ordered solve (rs_newton_solve_async): exactly
+        that many super-steps, no host synchronisation, unfinished items left
+        with status RUNNING."""
+        if super_steps is not None:
+            return self._solve("rs_newton_solve_async", z0, targets, force, opts or default_opts(), out, qbar, dt,
+                               extra=(int(super_steps),))
         return self._solve("rs_newton_solve", z0, targets, force, opts or default_opts(), out, qbar, dt)
 
     def lbfgs_solve(self, z0, targets=None, force=None, opts: LbfgsOpts | None = None, out=None):
         """As newton_solve, with the L-BFGS solver."""
         return self._solve("rs_lbfgs_solve", z0, targets, force, opts or default_lbfgs_opts(), out)
 
-    def _solve(self, fn, z0, targets, force, o, out, qbar=None, dt=0.0):
+    def _solve(self, fn, z0, targets, force, o, out, qbar=None, dt=0.0, extra=()):
         B = z0.shape[0]
         _dev(z0, torch.float64, (B, self.r), "z0")
         ld, _keep = self._load(B, targets, force, qbar, dt)
@@ -419,7 +428,7 @@ class Context:
         else:
             z, iters, status, relg, E = out
             z.copy_(z0)
-        self._check(getattr(load_library(), fn)(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), _ptr(iters),
+        self._check(getattr(load_library(), fn)(self.ctx, B, _ptr(z), C.byref(ld), C.byref(o), *extra, _ptr(iters),
                                                 _ptr(status), _ptr(relg), _ptr(E), _stream()), fn)
         return dict(z=z, iters=iters, status=status, relgrad=relg, E=E)
 

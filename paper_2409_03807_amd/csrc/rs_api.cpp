@@ -1773,7 +1773,8 @@ static int read_count(rs_ctx* c, int slot, unsigned int tag, hipStream_t s, int*
 // direction, line-search rounds and exits per item, with the host launching
 // one super-step ahead.
 static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, const NewtonParams& p, uint32_t flags,
-                       bool lbfgs, int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+                       bool lbfgs, int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream,
+                       int fixed_steps = 0)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double* tg = load ? load->targets : nullptr;
@@ -1813,7 +1814,8 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
     // of step k (counts only fall, so an older count bounds every launch).
     // Each super-step ends with the Armijo kernel, which also builds the next
     // evaluation list and writes the running count to mapped host memory.
-    const long max_steps = (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
+    // fixed_steps > 0: exactly that many super-steps, all sized for B, with no host reads
+    const long max_steps = fixed_steps > 0 ? fixed_steps : (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
     int n_run = B;
     unsigned int tags[2] = {0, 0};
     for (long step = 0; step < max_steps; ++step) {
@@ -1842,6 +1844,7 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
         tags[par] = tag;
         RS_TRY(run(c, K_ARMIJO, item_work(8.0 * kLsCand, 0, n_run, cnt + 2, c->cur_slot, 2), s,
                    [&] { return launch_armijo(st, p, B, c->hcount_dev + par, tag, s); }));
+        if (fixed_steps > 0) continue;
         // the count reaches host memory by the kernel's own system-scope store; the event only marks completion
         hipError_t e = hipEventRecord(c->cnt_ev[par], s);
         if (e != hipSuccess) return hip_fail(c, e, "running-count copy");
@@ -1856,6 +1859,10 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
         }
         n_run = prev;
     }
+    if (fixed_steps > 0) {
+        c->cur_slot = -1;
+        return RS_OK;
+    }
     if (n_run > 0) {
         // the bound was reached: settle the last count
         hipError_t e = hipStreamSynchronize(s);
@@ -1868,8 +1875,26 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
     return RS_OK;
 }
 
+static int newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
+                        int fixed_steps, int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream);
+
 extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
                                int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
+{
+    return newton_solve(c, B, z, load, o, 0, iters, status, relgrad, E, stream);
+}
+
+extern "C" int rs_newton_solve_async(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
+                                     int32_t super_steps, int32_t* iters, int32_t* status, double* relgrad, double* E,
+                                     void* stream)
+{
+    if (!c) return RS_ERR_STATE;
+    if (super_steps < 1) return fail(c, RS_ERR_ARG, "super_steps must be at least 1");
+    return newton_solve(c, B, z, load, o, super_steps, iters, status, relgrad, E, stream);
+}
+
+static int newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, const rs_solve_opts* o,
+                        int fixed_steps, int32_t* iters, int32_t* status, double* relgrad, double* E, void* stream)
 {
     if (!c) return RS_ERR_STATE;
     if (B < 0 || B > c->max_batch) return fail(c, RS_ERR_ARG, "B must be in [0, max_batch]");
@@ -1893,7 +1918,7 @@ extern "C" int rs_newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* l
     p.eig_floor = o->eig_floor;
     const uint32_t hflags = ((o->hess & 1) ? RS_HESS_EXACT : 0u) | ((o->hess & 2) ? RS_ELEM_PSD : 0u);
     RS_TRY(dyn_setup(c, load, B, 0, static_cast<hipStream_t>(stream)));
-    return solve_batch(c, B, z, load, p, hflags, false, iters, status, relgrad, E, stream);
+    return solve_batch(c, B, z, load, p, hflags, false, iters, status, relgrad, E, stream, fixed_steps);
 }
 
 // The last hidden activation of B latent points in float64 (the value pass of the
