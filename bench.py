@@ -17,9 +17,18 @@ reductions, r x r solve, line-search energies and convergence test.
 Metric: converged reduced solves per second (items ending with
 |g|_inf <= 1e-6 |g_0|_inf), whole job, inputs resident in HBM.
 
---path param_grad times instead the gradient of the summed cubature energy of
-the batch with respect to every decoder parameter (the potential loss of the
-unsupervised subspace construction), in items per second.
+Other lines of the same script:
+* --config c1 / c3: the 10x2x2 beam in float64, or c2 at a batch of 4096 with
+  the BF16 decoder (three-part BF16 operands, float32 accuracy);
+* --solver lbfgs: the same solves by L-BFGS; --hess / --proj: other Hessian
+  policies; --z0 zero / --twist T: start points and loads of one kind;
+* --path param_grad: the gradient of the summed cubature energy of the batch
+  with respect to every decoder parameter (the potential loss of the
+  unsupervised subspace construction), in items per second;
+* --path learned: the learned part on the 16^3 block (snapshots, training
+  with and without the Lipschitz term, PCA, held-out solves);
+* --path simulate: implicit-Euler simulations with ground contact (c5), with
+  --train-epochs to train their subspace first.
 """
 import argparse
 import glob

@@ -300,12 +300,12 @@ hipError_t launch_gemm(int f32, int role, const GemmArgs& a, hipStream_t s);
 // persistent variant for IN_RAW / IN_LATENT inputs with K a supported multiple of 32
 hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks, hipStream_t s);
 bool gemm_p_fits(int f32, int K);
-// bf16: BF16 weights, the float32 layer input split into a BF16 pair (f32 must be set; FP32 accumulation,
-// pre-activations and activation)
+// bf16: weights as three BF16 planes, the float32 layer input split into three BF16 parts, six products
+// per chunk (f32 must be set; FP32 accumulation, pre-activations and activation)
 // n_cu: compute units (a small batch takes fewer items per workgroup)
 hipError_t launch_mlp(int f32, const MlpArgs& a, hipStream_t s, int bf16, int n_cu);
-// persistent output map with BF16 A and transposed float32 input (IN_RAW_T, split into a BF16 pair), FP32
-// accumulation and output
+// persistent output map with A as three BF16 planes and transposed float32 input (IN_RAW_T, split into
+// three BF16 parts), six products per chunk, FP32 accumulation and output
 hipError_t launch_gemm_p_bf16(int role, const GemmArgs& a, int target_blocks, hipStream_t s);
 bool mlp_fits(int f32, int nc, int r, int wrows); // the fused kernel's LDS and tiling limits
 hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
