@@ -70,7 +70,7 @@ def recorded_traffic(kind, workload):
 
 # the bound of each launch kind: contractions on the matrix cores, the r x r
 # solves on the float64 vector ALUs, everything else on HBM bandwidth
-MFMA_KINDS = {"gemm_hidden", "gemm_out", "gemm_adjoint", "decode_hidden", "decode_out"}
+MFMA_KINDS = {"gemm_hidden", "gemm_out", "gemm_adjoint", "decode_hidden", "decode_out", "elem_fused"}
 MFMA_F64_KINDS = {"ls_gemm_hidden", "ls_gemm_out"}
 ALU_F64_KINDS = {"newton_dir", "param_grad"}
 VALU_F64_PEAK_TFLOPS = 78.6
@@ -124,6 +124,8 @@ def parse():
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--hess", default="exact", choices=["exact", "gn", "gn_psd", "exact_psd"],
                     help="Newton Hessian: exact or Gauss-Newton, optionally with per-element PSD projection")
+    ap.add_argument("--fused", default="on", choices=["on", "off"],
+                    help="BF16 contexts: output map and element physics in one kernel (on) or two (off)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -158,6 +160,7 @@ def main():
         prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     ctx = rb.Context(p, prec=prec, max_batch=B)
+    fused = ctx.set_fused(args.fused == "on") and args.fused == "on"
     info = ctx.info()
     dev = "cuda:0"
     z0 = torch.tensor(I.latent_batch(B, p.r), device=dev)
@@ -313,6 +316,7 @@ def main():
                         + " penalty targets" + (", z0 = 0" if args.z0 == "zero" else ", z0 ~ N(0, 0.5^2)"),
             "batch": B, "rows": info.rows, "subspace": "plain", "solver": "none" if pgrad else args.solver,
             "path": args.path, "hessian": args.hess, "projection": args.proj,
+            "output_map": "fused with the element physics" if fused else "separate kernel (J_R through HBM)",
         },
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},

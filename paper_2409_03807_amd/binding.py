@@ -97,7 +97,8 @@ SYMBOLS = ["rs_default_opts", "rs_default_lbfgs_opts", "rs_create", "rs_destroy"
            "rs_energy_param_grad", "rs_set_elem_hess_dump", "rs_set_decoder_device", "rs_lipschitz_param_grad",
            "rs_lipschitz_param_grad_noalloc", "rs_trainer_create", "rs_trainer_destroy", "rs_trainer_param_count",
            "rs_trainer_params", "rs_trainer_encode", "rs_trainer_grad", "rs_trainer_adam",
-           "rs_default_full_opts", "rs_full_solve", "rs_pca", "rs_simulate", "rs_newton_solve_async"]
+           "rs_default_full_opts", "rs_full_solve", "rs_pca", "rs_simulate", "rs_newton_solve_async",
+           "rs_set_fused"]
 
 _lib = None
 
@@ -137,6 +138,7 @@ def load_library():
         L.rs_energy_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(_Load), C.c_uint32,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.rs_set_elem_hess_dump.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+        L.rs_set_fused.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
         L.rs_set_decoder_device.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]
         L.rs_lipschitz_param_grad.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_void_p, C.c_void_p]
@@ -397,6 +399,14 @@ class Context:
             raise ValueError("He must have shape (items, n_cub, 12, 12)")
         self._dump = He
         self._check(load_library().rs_set_elem_hess_dump(self.ctx, _ptr(He), He.shape[0]), "rs_set_elem_hess_dump")
+
+    def set_fused(self, on=True):
+        """BF16 contexts: form the rows of J_R and run the element physics in one kernel (True, the
+        default) or in two kernels with J_R through device memory (False).  Returns whether the
+        fused kernel applies to this context (r = 16, last hidden width <= 128)."""
+        applies = C.c_int32(0)
+        self._check(load_library().rs_set_fused(self.ctx, 1 if on else 0, C.byref(applies)), "rs_set_fused")
+        return bool(applies.value)
 
     def newton_solve(self, z0, targets=None, force=None, opts: SolveOpts | None = None, out=None, qbar=None,
                      dt=0.0, super_steps=None):

@@ -32,13 +32,13 @@ int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 enum Kind {
     K_GEMM_HIDDEN, K_GEMM_OUT, K_ELEM, K_GEMM_ADJ, K_CURV, K_COMPACT, K_DIR,
     K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT, K_ENERGY, K_ARMIJO, K_LIPSCHITZ, K_DECODE_HIDDEN, K_DECODE_OUT,
-    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_ELEM_PSD, K_ELEM_DUMP, K_LIP_GRAD, K_TRAIN, K_DYN, K_COUNT
+    K_INIT, K_ACTIVATE, K_LBFGS, K_PARAM_GRAD, K_ELEM_PSD, K_ELEM_DUMP, K_LIP_GRAD, K_TRAIN, K_DYN, K_ELEM_FUSED, K_COUNT
 };
 const char* kKindName[K_COUNT] = {
     "gemm_hidden", "gemm_out", "elem", "gemm_adjoint", "curv", "compact", "newton_dir",
     "ls_gemm_hidden", "ls_gemm_out", "energy_f64", "armijo", "lipschitz", "decode_hidden", "decode_out",
     "newton_init", "activate", "lbfgs_dir", "param_grad", "elem_psd", "elem_hess_dump", "lipschitz_grad", "train",
-    "dynamics"};
+    "dynamics", "elem_fused"};
 
 // One profiled launch.  Its work is b0 + b1 * n bytes and f0 + f1 * n flops,
 // n = 1 for launches sized on the host, else the device counter `which` of
@@ -115,8 +115,11 @@ struct rs_ctx {
     double *Ew = nullptr, *gw = nullptr, *Hw = nullptr;
     double *g0 = nullptr, *dz = nullptr, *slope = nullptr;
     LbfgsState lb{};              // L-BFGS history, max_batch items
-    double* Hpart = nullptr;      // 2 n_cu x r x r: element-kernel partials when an item's rounds are split
-    double* gpart = nullptr;      // 2 n_cu x r
+    double* Hpart = nullptr;      // npart x r x r: element-kernel partials when an item's rounds are split
+    double* gpart = nullptr;      // npart x r
+    size_t npart = 0;             // 2 n_cu (split element kernel), 8 n_cu + max_batch where the fused kernel applies
+    int fused = 0;                // BF16, r = 16, width <= 128: the fused output map + element kernel applies
+    int fused_on = 1;             // ... and is used (rs_set_fused)
     int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
     int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
     int ksplit = 1;               // K slices of the adjoint GEMM
@@ -763,8 +766,11 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
             c->n_cu = ncu;
     }
     c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
-    c->Hpart = (double*)need(dalloc<double>(c, (size_t)2 * c->n_cu * c->r * c->r));
-    c->gpart = (double*)need(dalloc<double>(c, (size_t)2 * c->n_cu * c->r));
+    // the fused kernel's parts times its items stay below 8 n_cu + the items
+    c->fused = c->bf16 && c->L > 0 && c->nc == 17 && elem_fused_fits(c->r, c->lda_out);
+    c->npart = c->fused ? (size_t)8 * c->n_cu + c->max_batch : (size_t)2 * c->n_cu;
+    c->Hpart = (double*)need(dalloc<double>(c, c->npart * c->r * c->r));
+    c->gpart = (double*)need(dalloc<double>(c, c->npart * c->r));
     c->Ew = (double*)need(dalloc<double>(c, B));
     c->gw = (double*)need(dalloc<double>(c, B * c->r));
     c->Hw = (double*)need(dalloc<double>(c, B * c->r * c->r));
@@ -1194,7 +1200,10 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
     const int slot = c->cur_slot;
     RS_TRY(hidden_layers(c, f32, nc, cap, count, 0, z, zmap, c->pre.data(), c->act, c->W.data(), c->bh.data(),
                          K_GEMM_HIDDEN, s));
-    {
+    // the fused kernel stores no J_R rows: only where nothing after the element physics reads them
+    const bool fuse = c->fused && c->fused_on && c->ncont == 0 && !dyn_active(c, flags) &&
+                      !(flags & (RS_ELEM_PSD | RS_DEBUG_ELEM_HESS));
+    if (!fuse) {
         GemmArgs a{};
         a.A = c->Wbig;
         a.lda = c->lda_out;
@@ -1256,9 +1265,12 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         // A small batch splits each item's rounds over several workgroups (the
         // curvature pass sums their partial g and H), so that the element
         // kernel's per-item latency does not set the launch's duration.
+        // (The fused kernel takes four items per workgroup and splits their
+        // rows at batches below eight items per compute unit.)
         a.parts = 1;
         if (exact && !E && g && cap > 0) {
-            const int parts = std::min(8, 2 * c->n_cu / cap);
+            int parts = fuse ? elem_fused_parts(cap, c->n_cu) : std::min(8, 2 * c->n_cu / cap);
+            while (parts > 1 && (size_t)parts * cap > c->npart) --parts;
             if (parts > 1) {
                 a.parts = parts;
                 a.part_stride = cap;
@@ -1267,10 +1279,32 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
             }
         }
         split = a.parts;
-        // algorithmic bytes: read the item's rows once, write seeds and (E, g, H)
-        const double pb = (double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) + 8.0 * (1 + r + r * r);
-        const double pf = (double)c->S * (18.0 * r * r + 80.0 * r + 150.0);
-        RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s, [&] { return launch_elem(f32, a, cap, s); }));
+        if (fuse) {
+            FusedElemArgs f{};
+            f.e = a;
+            f.e.out = nullptr;
+            f.A = c->Wbig16;
+            f.lda = c->lda_out;
+            f.K = c->lda_out;
+            f.rows = c->M;
+            f.bias = static_cast<const float*>(c->bbig);
+            f.Y = static_cast<const float*>(c->act);
+            f.y_rows = c->wrows;
+            f.cap = cap;
+            // algorithmic work: the item's activation columns in, seeds and (E, g, H) out, W_big once
+            // per launch; flops: the output map's products (float32-equivalent: the matrix-core part)
+            Work w = item_work((double)nc * c->lda_out * ts + (exact ? (double)c->Mp * ts : 0.0) +
+                                   8.0 * (1 + r + r * r),
+                               2.0 * c->M * c->in_last * nc, cap, count, slot, 0);
+            w.b0 += 6.0 * c->Mp * c->lda_out;
+            RS_TRY(run(c, K_ELEM_FUSED, w, s, [&] { return launch_elem_fused(f, s); }));
+        } else {
+            // algorithmic bytes: read the item's rows once, write seeds and (E, g, H)
+            const double pb = (double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) + 8.0 * (1 + r + r * r);
+            const double pf = (double)c->S * (18.0 * r * r + 80.0 * r + 150.0);
+            RS_TRY(run(c, K_ELEM, item_work(pb, pf, cap, count, slot, 0), s,
+                       [&] { return launch_elem(f32, a, cap, s); }));
+        }
     }
     const bool dyn = dyn_active(c, flags) && (g || H || E);
     if (dyn && exact && c->ncont > 0) {
@@ -1588,6 +1622,14 @@ extern "C" int rs_set_elem_hess_dump(rs_ctx* c, double* He, int32_t max_items)
     if (max_items < 0 || (max_items > 0 && !He)) return fail(c, RS_ERR_ARG, "bad element-Hessian dump buffer");
     c->dump_He = max_items > 0 ? He : nullptr;
     c->dump_max = c->dump_He ? max_items : 0;
+    return RS_OK;
+}
+
+extern "C" int rs_set_fused(rs_ctx* c, int32_t on, int32_t* applies)
+{
+    if (!c) return RS_ERR_STATE;
+    c->fused_on = on ? 1 : 0;
+    if (applies) *applies = c->fused;
     return RS_OK;
 }
 

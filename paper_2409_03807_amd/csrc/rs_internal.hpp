@@ -100,6 +100,20 @@ struct ElemArgs {
     int part_stride;      // parts > 1: g and H of part p of item i at slot p * part_stride + i (E must be NULL)
 };
 
+// Output map and element physics in one kernel (BF16 context, r == 16): the
+// element part as ElemArgs (its `out` unused: no J_R is stored), plus the
+// output map's operands.
+struct FusedElemArgs {
+    ElemArgs e;
+    const void* A;      // W_big as three BF16 planes (hi, mid, lo), each rows_pad x lda
+    int lda, K;         // K: a multiple of 32 (columns of W_big past the width are zero)
+    int rows;           // rows of W_big (9 per tet, 3 per target, gravity, 3 force)
+    const float* bias;  // rows: the value column's bias
+    const float* Y;     // activations: unit k of column c (0 value, 1 + j Jacobian) of item i at
+    int y_rows;         //   (i * nc + c) * y_rows + k; rows past the width are zero
+    int cap;            // items of the launch (the grid's item groups)
+};
+
 // Per-element constants of the optional element treatments (kElemConst
 // doubles per cubature tet): B = N^(1/2) (3x3, N the Gram matrix of the shape
 // gradients), B^-1, the shape gradients Dv (4x3), the rest volume and the
@@ -311,6 +325,11 @@ bool mlp_fits(int f32, int nc, int r, int wrows); // the fused kernel's LDS and 
 hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int rows_pad, int nc, int items_cap,
                            const int* count, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
+// the fused output map + element kernel: whether it applies (r, K), and the
+// workgroups per item group it splits the rows over at a launch of cap items
+bool elem_fused_fits(int r, int K);
+int elem_fused_parts(int cap, int n_cu);
+hipError_t launch_elem_fused(const FusedElemArgs& a, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 // per-element positive-semi-definite projection: adds its correction to H
 hipError_t launch_elem_psd(int f32, const ElemOptArgs& a, int items, hipStream_t s);

@@ -1453,6 +1453,44 @@ __device__ inline T pair_even(T first, T second) { return dpp_keep<0x118, 0xC>(f
 template <typename T>
 __device__ inline T pair_odd(T first, T second) { return dpp_keep<0x108, 0x3>(second, first); }
 
+// One tet of the two-column float32 element lanes (r == 16, rows of 17
+// values: value, then the 16 Jacobian columns): lane 8 t + k of a wave holds
+// columns k and k + 8 of tet t, whose nine rows start at `row` in LDS, and F,
+// psi and P are formed once for both.  Adds wV K^T (d2psi/dF2) K to hsum (the
+// 16x16 MFMA layout, summed over the wave's 8 tets), wV K[:,k].P and
+// wV K[:,k+8].P to gk and gk2, and wV psi to Ee on lane k == 0; returns P.
+// A lane with wV = 0 adds nothing (lanes past the end repeat a valid tet, so
+// every lane runs the same code).
+__device__ inline void tet_two_col(const float* row, int k, double wV, float mu, float lam, f32x4& hsum, double& gk,
+                                   double& gk2, double& Ee, float (&P)[9])
+{
+    float gu[9], K0[9], K1[9];
+    lds_read9_s17(row, gu);
+    lds_read18_s17(row + 1 + k, K0, K1);
+    Snh<float> m;
+    m.set(gu, mu, lam);
+    m.pk1(mu, lam, P);
+    const float wt = (float)wV;
+    float A0[9], A1[9];
+    const float wmu = wt * mu, wlam = wt * lam, ws = wt * m.s;
+    m.apply_hess_w(wmu, wlam, ws, K0, A0);
+    m.apply_hess_w(wmu, wlam, ws, K1, A1);
+    float gp0 = 0, gp1 = 0;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        gp0 += K0[v] * P[v];
+        gp1 += K1[v] * P[v];
+    }
+    gk += wV * (double)gp0;
+    gk2 += wV * (double)gp1;
+    Ee += k == 0 ? wV * (double)m.psi : 0.0;
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+        hsum = Mfma<float>::mac(pair_even(K0[v], K1[v]), pair_even(A0[v], A1[v]), hsum);
+        hsum = Mfma<float>::mac(pair_odd(K0[v], K1[v]), pair_odd(A0[v], A1[v]), hsum);
+    }
+}
+
 template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
 {
@@ -1642,30 +1680,11 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                 // every lane runs the same code and adds nothing.
                 const bool sok = s < a.S;
                 const int elc = sok ? el : a.S - 1 - rd * EPR;
-                const T* row = tile + elc * (9 * 17);
-                T gu[9], K0[9], K1[9];
-                lds_read9_s17(row, gu);
-                lds_read18_s17(row + 1 + k, K0, K1);
                 const double wv = lds_read_f64(sd + el);
                 const double wV = sok ? wv : 0.0;
-                Snh<T> m;
-                m.set(gu, mu, lam);
                 T P[9];
-                m.pk1(mu, lam, P);
+                tet_two_col(tile + elc * (9 * 17), k, wV, mu, lam, hsum, gk, gk2, Ee, P);
                 const T wt = (T)wV;
-                T A0[9], A1[9];
-                const T wmu = wt * mu, wlam = wt * lam, ws = wt * m.s;
-                m.apply_hess_w(wmu, wlam, ws, K0, A0);
-                m.apply_hess_w(wmu, wlam, ws, K1, A1);
-                T gp0 = 0, gp1 = 0;
-#pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    gp0 += K0[v] * P[v];
-                    gp1 += K1[v] * P[v];
-                }
-                gk += wV * (double)gp0;
-                gk2 += wV * (double)gp1;
-                Ee += k == 0 ? wV * (double)m.psi : 0.0;
                 if (dseed && sok) {
                     // lane c writes seed c; lane 0 also seed 8
                     T pv = P[0];
@@ -1673,11 +1692,6 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a)
                     for (int v = 1; v < 8; ++v) pv = k == v ? P[v] : pv;
                     global_store_asm(dseed + 9 * s + k, wt * pv);
                     if (k == 0) global_store_asm(dseed + 9 * s + 8, wt * P[8]);
-                }
-#pragma unroll
-                for (int v = 0; v < 9; ++v) {
-                    hsum = Mfma<T>::mac(pair_even(K0[v], K1[v]), pair_even(A0[v], A1[v]), hsum);
-                    hsum = Mfma<T>::mac(pair_odd(K0[v], K1[v]), pair_odd(A0[v], A1[v]), hsum);
                 }
             } else if (s < a.S) {
                 const T* row = tile + el * span;
@@ -1921,6 +1935,368 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s)
         }
     }
 #undef RS_ELEM
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Output map and element physics in one kernel (BF16 context, r == 16).  The
+// rows of J_R = W_big [h | J_h] + [b | 0] (Sec. 4.3: the cubature tets' F and
+// the penalty, gravity and force rows, each with its 16 Jacobian columns) are
+// formed in LDS just before the element physics reads them, so J_R never goes
+// through HBM.
+// A workgroup takes a group of four items (and, when the batch is small, a
+// part of their rows).  Its LDS holds the group's activation columns (64
+// Jacobian columns, 4 value columns and a zero column) split once into three
+// BF16 planes, for the whole run.  The rows come in chunks of 16 tets (144
+// rows: nine 16-row tiles), then the rows past the tets in chunks of up to
+// nine tiles.  Per chunk:
+//  * wave w forms the row tiles t = w - ch (mod 4), t + 4, t + 8 (so the SIMDs
+//    take the ninth tile in turn) as five 16x16 output tiles each (tile j < 4:
+//    the Jacobian columns of item j; tile 4: the four value columns), by
+//    six-product BF16 MFMAs over K: A, the three BF16 planes of W_big, from L2
+//    straight into registers, two row tiles at a time; B from the LDS planes,
+//    each fragment read once for both;
+//  * the element physics runs in two passes of two items (the LDS holds the
+//    rows of two items): the outputs of items 0 and 1 go to LDS, those of items
+//    2 and 3 stay in registers until the first pass is done.  In a pass, waves
+//    2s and 2s + 1 take item s of the pair, eight tets each, with the
+//    two-column lanes of the float32 element kernel (H on the FP32 matrix
+//    cores, folded into float64 per pass).
+// At the end the two waves' sums of each item are added in wave order.
+// Outputs as the element kernel's: E, g, H (or per-part partials), and the
+// adjoint seeds dE/d(row value).
+// ---------------------------------------------------------------------------
+constexpr int kFuseG = 4;                           // items per workgroup
+constexpr int kFuseTets = 16;                       // tets per chunk
+constexpr int kFuseRows = 9 * kFuseTets;            // rows per chunk (nine 16-row tiles)
+constexpr int kFuseCols = 16 * kFuseG + kFuseG + 1; // LDS columns: Jacobian, values, zeros
+
+bool elem_fused_fits(int r, int K) { return r == 16 && K > 0 && K % kTileK == 0 && K <= 4 * kTileK; }
+
+int elem_fused_parts(int cap, int n_cu)
+{
+    // at least two workgroups per compute unit, at most eight parts
+    const int groups = (cap + kFuseG - 1) / kFuseG;
+    if (groups <= 0) return 1;
+    return std::max(1, std::min(8, (2 * n_cu + groups - 1) / groups));
+}
+
+template <int KCH>
+__global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
+{
+    constexpr int K = KCH * kTileK;
+    constexpr int LDB = K + 8; // BF16 values per LDS column (16-byte pad: staggered banks)
+    __shared__ __align__(16) __bf16 Yp[3][kFuseCols * LDB];
+    __shared__ __align__(16) float Jl[2 * kFuseRows * 17];
+    __shared__ float Vl[2 * kFuseRows]; // value rows of items 2 and 3 (with the bias)
+    constexpr int RW = 280; // final sums per (wave, pass): H (256), g (16), E
+    static_assert(4 * 2 * RW * sizeof(double) <= sizeof(Jl), "the final sums fit the row buffer");
+    const ElemArgs& e = a.e;
+    const int grp = blockIdx.x / e.parts, part = blockIdx.x - grp * e.parts;
+    const int n_items = e.count ? min(*e.count, a.cap) : a.cap;
+    if (grp * kFuseG >= n_items) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int eg = lane >> 3, k = lane & 7;
+    const int nc = e.nc;
+
+    // the group's activation columns as three BF16 planes
+    {
+        constexpr int Q = K / 8;
+        for (int idx = tid; idx < kFuseCols * Q; idx += 256) {
+            const int n = idx / Q, q = idx - n * Q;
+            int it = n_items, col = 0;
+            if (n < 16 * kFuseG) {
+                it = grp * kFuseG + (n >> 4);
+                col = 1 + (n & 15);
+            } else if (n < 16 * kFuseG + kFuseG) {
+                it = grp * kFuseG + n - 16 * kFuseG;
+            }
+            f32x4 v0 = {0.f, 0.f, 0.f, 0.f}, v1 = v0;
+            if (it < n_items) {
+                const float* src = a.Y + ((size_t)it * nc + col) * a.y_rows + 8 * q;
+                v0 = *reinterpret_cast<const f32x4*>(src);
+                v1 = *reinterpret_cast<const f32x4*>(src + 4);
+            }
+            bf16x8 h, m, l;
+            split3_bf16(v0, v1, h, m, l);
+            *reinterpret_cast<bf16x8*>(&Yp[0][n * LDB + 8 * q]) = h;
+            *reinterpret_cast<bf16x8*>(&Yp[1][n * LDB + 8 * q]) = m;
+            *reinterpret_cast<bf16x8*>(&Yp[2][n * LDB + 8 * q]) = l;
+        }
+    }
+
+    const int S = e.S;
+    const int prow = 9 * S;
+    const int ntc = (S + kFuseTets - 1) / kFuseTets;
+    const int ntl = (a.rows - prow + kFuseRows - 1) / kFuseRows;
+    const int nch = ntc + ntl;
+    const int per = (nch + e.parts - 1) / e.parts;
+    const int cb = min(nch, part * per), ce = min(nch, cb + per);
+    const size_t plane = (size_t)e.rows_pad * a.lda;
+    const __bf16* Ab = static_cast<const __bf16*>(a.A);
+    const float mu = (float)e.mu, lam = (float)e.lam;
+    const bool ext = !e.elastic_only;
+    const double kc = e.k_c;
+    // LDS column of this lane's B fragment in output tile j
+    auto bcol = [&](int j) { return j < kFuseG ? 16 * j + li : (li < kFuseG ? 16 * kFuseG + li : kFuseCols - 1); };
+
+    // pass X of the element physics: item 2 X + (wave >> 1), tets / targets of half wave & 1
+    const int slot = wave >> 1, hf = wave & 1;
+    double Hm[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    double gk[2] = {0.0, 0.0}, gk2[2] = {0.0, 0.0}, Ee[2] = {0.0, 0.0};
+
+    lds_barrier(); // the activation planes
+    for (int ch = cb; ch < ce; ++ch) {
+        const bool tail = ch >= ntc;
+        const int row0 = tail ? prow + kFuseRows * (ch - ntc) : kFuseRows * ch;
+        const int ntile = tail ? min(9, (a.rows - row0 + 15) / 16) : 9;
+        const int t0 = (wave - ch) & 3;
+        const int nw = (t0 < ntile) + (t0 + 4 < ntile) + (t0 + 8 < ntile); // of the tiles t0, t0 + 4, t0 + 8
+        // the Jacobian tiles of items 2 and 3, kept for the second pass
+        f32x4 held[2][3];
+        // row tiles t0 + 4 q of the wave, q = q0 .. q0 + NQ - 1: A fragments of
+        // all of them in registers, loads issued at once (rows past the padded
+        // end re-read the last row: their products are never used); each B
+        // fragment is read from LDS once for all of them.
+        auto tiles = [&](auto Q0, auto NQ) {
+            constexpr int q0 = decltype(Q0)::value, nq = decltype(NQ)::value;
+            auto tile_of = [&](int q) { return t0 + 4 * q; };
+            bf16x8 af[nq][KCH][3];
+#pragma unroll
+            for (int i = 0; i < nq; ++i) {
+                const int row = min(row0 + 16 * tile_of(q0 + i) + li, e.rows_pad - 1);
+                const __bf16* p = Ab + (size_t)row * a.lda + 8 * lg;
+#pragma unroll
+                for (int c = 0; c < KCH; ++c)
+#pragma unroll
+                    for (int pl = 0; pl < 3; ++pl)
+                        af[i][c][pl] = *reinterpret_cast<const bf16x8*>(p + pl * plane + c * kTileK);
+            }
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                f32x4 acc[nq], corr[nq];
+#pragma unroll
+                for (int i = 0; i < nq; ++i) acc[i] = corr[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const int cofs = bcol(j) * LDB + 8 * lg;
+#pragma unroll
+                for (int c = 0; c < KCH; ++c) {
+                    bf16x8 b[3];
+#pragma unroll
+                    for (int pl = 0; pl < 3; ++pl) b[pl] = *reinterpret_cast<const bf16x8*>(&Yp[pl][cofs + c * kTileK]);
+#pragma unroll
+                    for (int i = 0; i < nq; ++i) mfma_bf16x6_chunk(af[i][c], b, acc[i], corr[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < nq; ++i) {
+                    const f32x4 o = acc[i] + corr[i];
+                    if (j == 2 || j == 3) {
+                        held[j - 2][q0 + i] = o;
+                        continue;
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = 16 * tile_of(q0 + i) + 4 * lg + v; // row within the chunk
+                        if (j < 2) {
+                            Jl[(j * kFuseRows + m) * 17 + 1 + li] = o[v];
+                        } else if (li < kFuseG) {
+                            const int rg = row0 + m;
+                            const float val = o[v] + (rg < a.rows ? a.bias[rg] : 0.f);
+                            if (li < 2) Jl[(li * kFuseRows + m) * 17] = val;
+                            else Vl[(li - 2) * kFuseRows + m] = val;
+                        }
+                    }
+                }
+            }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        if (nw >= 2) tiles(I0{}, I2{});
+        else if (nw == 1) tiles(I0{}, I1{});
+        if (nw == 3) tiles(I2{}, I1{});
+        lds_barrier(); // rows of items 0 and 1
+
+#pragma unroll
+        for (int X = 0; X < 2; ++X) {
+            if (X == 1) {
+                lds_barrier(); // the first pass has read its rows
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (q >= nw) break;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = 16 * (t0 + 4 * q) + 4 * lg + v;
+                        Jl[m * 17 + 1 + li] = held[0][q][v];
+                        Jl[(kFuseRows + m) * 17 + 1 + li] = held[1][q][v];
+                    }
+                }
+                for (int i = tid; i < 2 * kFuseRows; i += 256) Jl[i * 17] = Vl[i];
+                lds_barrier(); // rows of items 2 and 3
+            }
+            const int item = grp * kFuseG + 2 * X + slot;
+            if (item >= n_items) continue; // wave-uniform
+            const int bidx = e.imap ? e.imap[item] : item;
+            float* dseed = e.dseed ? static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad : nullptr;
+            const float* Jw = Jl + slot * kFuseRows * 17;
+            f32x4 hs = {0.f, 0.f, 0.f, 0.f};
+            if (!tail) {
+                const int s0 = kFuseTets * ch, ns = min(kFuseTets, S - s0);
+                if (8 * hf < ns) {
+                    const int sl = 8 * hf + eg;
+                    const bool sok = sl < ns;
+                    const int slc = sok ? sl : ns - 1;
+                    const double wV = sok ? e.wV[s0 + sl] : 0.0;
+                    float P[9];
+                    tet_two_col(Jw + 9 * slc * 17, k, wV, mu, lam, hs, gk[X], gk2[X], Ee[X], P);
+                    if (dseed && sok) {
+                        // lane k writes seed k; lane 0 also seed 8
+                        const float wt = (float)wV;
+                        float pv = P[0];
+#pragma unroll
+                        for (int v = 1; v < 8; ++v) pv = k == v ? P[v] : pv;
+                        global_store_asm(dseed + 9 * (s0 + sl) + k, wt * pv);
+                        if (k == 0) global_store_asm(dseed + 9 * (s0 + sl) + 8, wt * P[8]);
+                    }
+                }
+            } else {
+                // penalty k_c/2 |x_t - target_t|^2 of the chunk's targets (three rows each)
+                const double* tg = (ext && e.targets) ? e.targets + (size_t)bidx * e.nt * 3 : nullptr;
+                const int tb = (row0 - prow) / 3;
+                const int ntg = tg ? max(0, min(kFuseRows / 3, e.nt - tb)) : 0;
+                const float kt = (float)kc;
+                for (int q = 0; 16 * q + 8 * hf < ntg; ++q) {
+                    const int tl = 16 * q + 8 * hf + eg, t = tb + tl;
+                    const bool ok = tl < ntg;
+                    const int tc = ok ? t : tb;
+                    double xr[3], tr[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        xr[c] = e.Xt[3 * tc + c];
+                        tr[c] = tg[3 * tc + c];
+                    }
+                    const float* row = Jw + 3 * (ok ? tl : 0) * 17;
+                    float xv[3], jr[3], jr2[3];
+                    lds_read3(row, 17, xv);
+                    lds_read3(row + 1 + k, 17, jr);
+                    lds_read3(row + 9 + k, 17, jr2);
+                    float Jc[3], J2[3];
+                    double d[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        Jc[c] = ok ? jr[c] : 0.f;
+                        J2[c] = ok ? jr2[c] : 0.f;
+                        d[c] = ok ? xr[c] + (double)xv[c] - tr[c] : 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float pe = pair_even(Jc[c], J2[c]), po = pair_odd(Jc[c], J2[c]);
+                        hs = Mfma<float>::mac(pe, kt * pe, hs);
+                        hs = Mfma<float>::mac(po, kt * po, hs);
+                    }
+                    if (ok) {
+                        gk[X] += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
+                        gk2[X] += kc * ((double)J2[0] * d[0] + (double)J2[1] * d[1] + (double)J2[2] * d[2]);
+                        Ee[X] += k == 0 ? 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0;
+                        if (dseed && k < 3) {
+                            const double dv = k == 0 ? d[0] : k == 1 ? d[1] : d[2];
+                            global_store_asm(dseed + prow + 3 * t + k, (float)(kc * dv));
+                        }
+                    }
+                }
+                // gravity (-1 times the row) and force (-f_c times row c) rows of this chunk
+                if (ext && hf == 0 && eg == 0) {
+                    const int nrow = (e.force && e.nf) ? 4 : 1;
+                    for (int c = 0; c < nrow; ++c) {
+                        const int rg = c == 0 ? e.grav_row : e.force_row + c - 1;
+                        if (rg < row0 || rg >= row0 + 16 * ntile) continue;
+                        const double coef = c == 0 ? 1.0 : e.force[(size_t)bidx * 3 + c - 1];
+                        const float* rr = Jw + (rg - row0) * 17;
+                        gk[X] -= coef * (double)rr[1 + k];
+                        gk2[X] -= coef * (double)rr[9 + k];
+                        if (k == 0) Ee[X] -= coef * (double)rr[0];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Hm[X][q] += (double)hs[q];
+        }
+        lds_barrier(); // the second pass has read its rows
+    }
+
+    // each item's two waves: sums over the wave's tet lanes, then the two
+    // waves' sums added in wave order through the (now idle) row buffer
+    double* red = reinterpret_cast<double*>(Jl);
+#pragma unroll
+    for (int X = 0; X < 2; ++X) {
+#pragma unroll
+        for (int off = 8; off < 64; off <<= 1) {
+            gk[X] += __shfl_xor(gk[X], off);
+            gk2[X] += __shfl_xor(gk2[X], off);
+            Ee[X] += __shfl_xor(Ee[X], off);
+        }
+        double* rw = red + (wave * 2 + X) * RW;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rw[q * 64 + lane] = Hm[X][q];
+        if (eg == 0) {
+            rw[256 + k] = gk[X];
+            rw[264 + k] = gk2[X];
+        }
+        if (lane == 0) rw[272] = Ee[X];
+    }
+    lds_barrier();
+    const int item = grp * kFuseG + wave;
+    if (item >= n_items) return;
+    {
+        // item 2 X + s of the group: pass X of waves 2 s and 2 s + 1
+        const int X = wave >> 1, s = wave & 1;
+        const double* r0 = red + ((2 * s) * 2 + X) * RW;
+        const double* r1 = red + ((2 * s + 1) * 2 + X) * RW;
+        const size_t slot_o = (size_t)part * e.part_stride + item;
+        if (e.H) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                e.H[slot_o * 256 + Mfma<float>::row(lane, q) * 16 + li] = r0[q * 64 + lane] + r1[q * 64 + lane];
+        }
+        if (lane < 16 && e.g) e.g[slot_o * 16 + lane] = r0[256 + lane] + r1[256 + lane];
+        if (lane == 0 && e.E) e.E[item] = r0[272] + r1[272];
+    }
+    if (e.dseed && part == 0) {
+        // rows not written above: penalty rows without targets, gravity,
+        // force and padding rows
+        const int bidx = e.imap ? e.imap[item] : item;
+        const bool tgi = ext && e.targets;
+        float* dseed = static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad;
+        for (int row = prow + lane; row < e.rows_pad; row += 64) {
+            double v = 0.0;
+            if (row < e.grav_row) {
+                if (tgi) continue;
+            } else if (row == e.grav_row) {
+                v = ext ? -1.0 : 0.0;
+            } else if (row < e.force_row + 3) {
+                v = (ext && e.force && e.nf) ? -e.force[(size_t)bidx * 3 + (row - e.force_row)] : 0.0;
+            }
+            dseed[row] = (float)v;
+        }
+    }
+}
+
+hipError_t launch_elem_fused(const FusedElemArgs& a, hipStream_t s)
+{
+    if (a.cap <= 0) return hipSuccess;
+    const ElemArgs& e = a.e;
+    if (!elem_fused_fits(e.r, a.K) || e.nc != 17 || a.K > a.lda || a.K > a.y_rows || e.parts < 1 ||
+        (e.parts > 1 && (e.E || e.part_stride < a.cap)) || a.rows > e.rows_pad || 9 * e.S > a.rows)
+        return hipErrorInvalidValue;
+    const int groups = (a.cap + kFuseG - 1) / kFuseG;
+    dim3 grid(groups * e.parts), block(256);
+    switch (a.K / kTileK) {
+    case 1: RS_LAUNCH((k_elem_fused<1>), grid, block, 0, s, a); break;
+    case 2: RS_LAUNCH((k_elem_fused<2>), grid, block, 0, s, a); break;
+    case 3: RS_LAUNCH((k_elem_fused<3>), grid, block, 0, s, a); break;
+    default: RS_LAUNCH((k_elem_fused<4>), grid, block, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 

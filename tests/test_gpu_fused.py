@@ -1,0 +1,176 @@
+"""GPU parity of the fused output-map + element kernel (BF16 contexts, r = 16).
+
+The fused kernel forms the rows of J_R (each cubature tet's F with its 16
+Jacobian columns, then the penalty, gravity and force rows) in on-chip memory
+and runs the element physics on them in the same workgroup.  It is compared
+with the float64 oracle at the BF16 bar (1e-4) and with the two-kernel path
+(J_R through device memory), which computes the same function to float32
+rounding, on: cubature sets that end inside a 16-tet chunk, target counts that
+span several row chunks, force loads with and without targets, Gauss-Newton
+and exact Hessians, elastic-only evaluations, batches whose last group of four
+items is ragged, and batches whose rows are split over several workgroups.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2409_03807_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2409_03807_amd import binding as rb  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-4        # BF16 contexts: float32 accuracy
+TOL_SPLIT = 2e-5  # fused against two-kernel: the same products, summed in another order
+
+
+def energy_scale(p):
+    mu = p.young / (2 * (1 + p.poisson))
+    return mu * p.meta["h"] ** 3 * p.ne / 5
+
+
+def relerr(a, b, tau=0.0):
+    a = np.asarray(a, dtype=np.float64).reshape(len(a), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    den = np.maximum(np.linalg.norm(b, axis=1), tau)
+    return np.linalg.norm(a - b, axis=1) / den
+
+
+def t64(a):
+    return None if a is None else torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _both(ctx, z, tg, fo, flags):
+    """(E, g, H) of the fused kernel, then of the two-kernel path, as numpy arrays."""
+    out = []
+    for on in (True, False):
+        assert ctx.set_fused(on)
+        E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=flags)
+        out.append((E.cpu().numpy(), g.cpu().numpy(), None if H is None else H.cpu().numpy()))
+    ctx.set_fused(True)
+    return out
+
+
+@pytest.mark.parametrize("n_cub", [16, 45, 100])
+@pytest.mark.parametrize("twist", [True, False])
+@pytest.mark.parametrize("flags", [rb.HESS_EXACT, 0, rb.HESS_EXACT | rb.ELASTIC_ONLY])
+def test_fused_small_meshes(n_cub, twist, flags):
+    """8x8x8 block: 81 end-face vertices as targets (two row chunks past the
+    tets) or none, bend forces on the same face, r = 16, 2 x 64 ELU."""
+    p = I.make_problem(f"fu{n_cub}", 8, 8, 8, 16, [64, 64], n_cub, twist=twist, bend=True, bias_scale=0.3)
+    o = O.Oracle(p)
+    oflags = (O.EXACT if flags & rb.HESS_EXACT else 0) | (O.ELASTIC_ONLY if flags & rb.ELASTIC_ONLY else 0)
+    for B in (1, 3, 6):
+        print(f"[fused] n_cub={n_cub} twist={twist} flags={flags} B={B}", flush=True)
+        ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+        z = I.latent_batch(B, p.r)
+        tg, fo = I.loads_for(p, B)
+        (E, g, H), (Es, gs, Hs) = _both(ctx, z, tg, fo, flags)
+        Eo, go, Ho = o.reduced(z, tg, fo, flags=oflags)
+        assert relerr(E[:, None], Eo[:, None], tau=1e-6 * energy_scale(p)).max() < 1e-10
+        assert relerr(g, go).max() < TOL
+        assert relerr(H, Ho).max() < TOL
+        assert relerr(g, gs).max() < TOL_SPLIT
+        assert relerr(H, Hs).max() < TOL_SPLIT
+
+
+def test_fused_not_applicable_runs_split():
+    """r != 16: the context reports that the fused kernel does not apply and the
+    two-kernel path runs."""
+    for p in (I.make_problem("fu_r8", 4, 2, 2, 8, [32, 32], 20, bend=True, bias_scale=0.3),
+              I.make_problem("fu_r12", 4, 2, 2, 12, [64, 64], 20, bend=True, bias_scale=0.3)):
+        ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=2)
+        assert not ctx.set_fused(True)
+        z = I.latent_batch(2, p.r)
+        tg, fo = I.loads_for(p, 2)
+        E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo))
+        Eo, go, Ho = O.Oracle(p).reduced(z, tg, fo)
+        assert relerr(g.cpu().numpy(), go).max() < TOL
+        assert relerr(H.cpu().numpy(), Ho).max() < TOL
+    # a float32 context never fuses
+    p = I.config("c2")
+    assert not rb.Context(p, prec=rb.PREC_F32, max_batch=2).set_fused(True)
+
+
+@pytest.mark.parametrize("B", [40, 1024, 1027])
+def test_fused_c2_batches(B):
+    """c2 (256 tets, 81 targets, r = 16, 4 x 128): batches split over eight and
+    two workgroups per item group and a ragged last group; sampled items
+    against the oracle, every item against the two-kernel path."""
+    p = I.config("c2")
+    print(f"[fused] c2 B={B}", flush=True)
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    (E, g, H), (Es, gs, Hs) = _both(ctx, z, tg, fo, rb.HESS_EXACT)
+    assert np.isfinite(H).all()
+    assert relerr(g, gs).max() < TOL_SPLIT
+    assert relerr(H, Hs).max() < TOL_SPLIT
+    idx = np.unique(np.array([0, 1, 2, 3, 4, B // 2 + 1, B - 2, B - 1]))
+    Eo, go, Ho = O.Oracle(p).reduced(z[idx], tg[idx], None)
+    assert relerr(g[idx], go).max() < TOL
+    assert relerr(H[idx], Ho).max() < TOL
+
+
+def test_fused_c3_full_batch_sampled():
+    """c3: B = 4096 in the benchmark's launch configuration, sampled items."""
+    p = I.config("c3")
+    B = 4096
+    print("[fused] c3 B=4096", flush=True)
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    assert ctx.set_fused(True)
+    z = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo))
+    idx = np.array([0, 1, 17, B // 2 + 3, B - 1])
+    Eo, go, Ho = O.Oracle(p).reduced(z[idx], tg[idx], None)
+    assert relerr(g.cpu().numpy()[idx], go).max() < TOL
+    assert relerr(H.cpu().numpy()[idx], Ho).max() < TOL
+    assert torch.isfinite(H).all()
+
+
+def test_fused_newton_c2_matches_split():
+    """BF16 Newton solves (c2, B = 64) with the fused kernel: every item converges
+    at 1e-6, is stationary for the oracle's float64 gradient, and takes the
+    iterations of the two-kernel path within one."""
+    p = I.config("c2")
+    B = 64
+    print("[fused] c2 newton B=64", flush=True)
+    z0 = I.latent_batch(B, p.r)
+    tg, fo = I.loads_for(p, B)
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    res = {}
+    for on in (True, False):
+        ctx.set_fused(on)
+        r = ctx.newton_solve(t64(z0), t64(tg), t64(fo))
+        res[on] = tuple(r[k].cpu().numpy() for k in ("z", "iters", "status", "E"))
+    z, it, st, E = res[True]
+    assert np.all(st == rb.CONVERGED), st
+    assert np.all(res[False][2] == rb.CONVERGED)
+    assert np.abs(it - res[False][1]).max() <= 1
+    o = O.Oracle(p)
+    idx = np.array([0, 5, 31, 63])
+    g0 = np.abs(o.reduced(z0[idx], tg[idx], fo)[1]).max(axis=1)
+    _, gg, _ = o.reduced(z[idx], tg[idx], fo)
+    assert np.all(np.abs(gg).max(axis=1) <= 1.5e-6 * g0)
+
+
+def test_fused_lipschitz_matches_split():
+    """The Lipschitz loss (elastic-only exact Hessians of stacked pairs) of a
+    BF16 context, fused against two-kernel."""
+    p = I.config("c2")
+    P = 48
+    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=2 * P)
+    z1 = I.latent_batch(P, p.r)
+    z2 = I.latent_batch(P, p.r, seed=11)
+    out = []
+    for on in (True, False):
+        ctx.set_fused(on)
+        out.append(ctx.lipschitz_loss(t64(z1), t64(z2))["per_pair"].cpu().numpy())
+    assert relerr(out[0][:, None], out[1][:, None], tau=1e-12).max() < 1e-3
