@@ -124,8 +124,9 @@ def parse():
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--hess", default="exact", choices=["exact", "gn", "gn_psd", "exact_psd"],
                     help="Newton Hessian: exact or Gauss-Newton, optionally with per-element PSD projection")
-    ap.add_argument("--fused", default="on", choices=["on", "off"],
-                    help="BF16 contexts: output map and element physics in one kernel (on) or two (off)")
+    ap.add_argument("--fused", default="auto", choices=["auto", "on", "off"],
+                    help="output map and element physics in one kernel (on) or two (off); auto: the "
+                         "context's default (on for BF16, off for float32)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -160,7 +161,10 @@ def main():
         prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     ctx = rb.Context(p, prec=prec, max_batch=B)
-    fused = ctx.set_fused(args.fused == "on") and args.fused == "on"
+    if args.fused == "auto":
+        fused = prec == rb.PREC_BF16 and ctx.set_fused(True)
+    else:
+        fused = ctx.set_fused(args.fused == "on") and args.fused == "on"
     info = ctx.info()
     dev = "cuda:0"
     z0 = torch.tensor(I.latent_batch(B, p.r), device=dev)

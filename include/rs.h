@@ -247,19 +247,22 @@ int rs_energy_grad_hess(rs_ctx* ctx, int32_t B, const double* z, const rs_load* 
  * RS_ERR_ARG (negative max_items, or NULL He with max_items > 0). */
 int rs_set_elem_hess_dump(rs_ctx* ctx, double* He, int32_t max_items);
 
-/* Choose how an RS_PREC_BF16 context forms the rows of J_R = W_big [h | J_h]
+/* Choose how a float32 or BF16 context forms the rows of J_R = W_big [h | J_h]
  * (the folded output layer, Sec. 4.3: each cubature tet's F with its r
  * Jacobian columns, and the penalty, gravity and force rows) for the element
- * physics.  on != 0 (the default): one kernel forms each chunk of rows in
- * on-chip memory just before the element physics of the same workgroup reads
- * it, so J_R is never written to device memory.  on == 0: the output map writes
- * J_R to device memory and the element kernel reads it back.  Both give the
- * same function to float32 rounding.  The fused kernel applies when r = 16,
- * the last hidden layer has at most 128 units, and the evaluation has no
- * ground contact, inertia, RS_ELEM_PSD or RS_DEBUG_ELEM_HESS (those read J_R
- * after the element physics); elsewhere the two-kernel path runs whatever
- * `on` says.  *applies (may be NULL) receives 1 if the context meets the first
- * two conditions, else 0.  Errors: RS_ERR_STATE (NULL ctx). */
+ * physics.  on != 0: one kernel forms each chunk of rows in on-chip memory
+ * just before the element physics of the same workgroup reads it, so J_R is
+ * never written to device memory (products on the BF16 matrix cores in BF16
+ * contexts, on the FP32 ones in float32 contexts).  on == 0: the output map
+ * writes J_R to device memory and the element kernel reads it back.  Both give
+ * the same function to float32 rounding.  Default: on in RS_PREC_BF16
+ * contexts, off in RS_PREC_F32 ones (the faster of the two for each).  The
+ * fused kernel applies when r = 16, the last hidden layer has at most 128
+ * units, and the evaluation has no ground contact, inertia, RS_ELEM_PSD or
+ * RS_DEBUG_ELEM_HESS (those read J_R after the element physics); elsewhere the
+ * two-kernel path runs whatever `on` says.  *applies (may be NULL) receives 1
+ * if the context meets the first two conditions and is not float64, else 0.
+ * Errors: RS_ERR_STATE (NULL ctx). */
 int rs_set_fused(rs_ctx* ctx, int32_t on, int32_t* applies);
 
 /* Number of decoder parameters: sum over the layers (output layer last) of

@@ -401,9 +401,10 @@ class Context:
         self._check(load_library().rs_set_elem_hess_dump(self.ctx, _ptr(He), He.shape[0]), "rs_set_elem_hess_dump")
 
     def set_fused(self, on=True):
-        """BF16 contexts: form the rows of J_R and run the element physics in one kernel (True, the
-        default) or in two kernels with J_R through device memory (False).  Returns whether the
-        fused kernel applies to this context (r = 16, last hidden width <= 128)."""
+        """Form the rows of J_R and run the element physics in one kernel (True) or in two kernels
+        with J_R through device memory (False); the default is True in BF16 contexts and False in
+        float32 ones.  Returns whether the fused kernel applies to this context (float32 or BF16,
+        r = 16, last hidden width <= 128)."""
         applies = C.c_int32(0)
         self._check(load_library().rs_set_fused(self.ctx, 1 if on else 0, C.byref(applies)), "rs_set_fused")
         return bool(applies.value)

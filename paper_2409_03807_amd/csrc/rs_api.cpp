@@ -118,8 +118,8 @@ struct rs_ctx {
     double* Hpart = nullptr;      // npart x r x r: element-kernel partials when an item's rounds are split
     double* gpart = nullptr;      // npart x r
     size_t npart = 0;             // 2 n_cu (split element kernel), 8 n_cu + max_batch where the fused kernel applies
-    int fused = 0;                // BF16, r = 16, width <= 128: the fused output map + element kernel applies
-    int fused_on = 1;             // ... and is used (rs_set_fused)
+    int fused = 0;                // float32/BF16, r = 16, width <= 128: the fused output map + element kernel applies
+    int fused_on = 1;             // ... and is used (rs_set_fused; default: BF16 contexts only)
     int *ls_j = nullptr, *eval_list = nullptr, *search_list = nullptr, *search_start = nullptr;
     int *search_ncand = nullptr, *cand_item = nullptr, *cand_j = nullptr, *counters = nullptr;
     int ksplit = 1;               // K slices of the adjoint GEMM
@@ -767,7 +767,10 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     }
     c->gbar = need(dalloc_bytes(c, (size_t)c->ksplit * B * c->in_rows * ts));
     // the fused kernel's parts times its items stay below 8 n_cu + the items
-    c->fused = c->bf16 && c->L > 0 && c->nc == 17 && elem_fused_fits(c->r, c->lda_out);
+    c->fused = c->f32 && c->L > 0 && c->nc == 17 && elem_fused_fits(c->r, c->lda_out);
+    // float32: the two-kernel path is faster (the fused kernel's FP32 products take longer than the
+    // J_R round trip they save); BF16: the fused kernel is
+    c->fused_on = c->bf16;
     c->npart = c->fused ? (size_t)8 * c->n_cu + c->max_batch : (size_t)2 * c->n_cu;
     c->Hpart = (double*)need(dalloc<double>(c, c->npart * c->r * c->r));
     c->gpart = (double*)need(dalloc<double>(c, c->npart * c->r));
@@ -1283,7 +1286,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
             FusedElemArgs f{};
             f.e = a;
             f.e.out = nullptr;
-            f.A = c->Wbig16;
+            f.A = c->bf16 ? c->Wbig16 : c->Wbig;
             f.lda = c->lda_out;
             f.K = c->lda_out;
             f.rows = c->M;
@@ -1292,12 +1295,13 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
             f.y_rows = c->wrows;
             f.cap = cap;
             // algorithmic work: the item's activation columns in, seeds and (E, g, H) out, W_big once
-            // per launch; flops: the output map's products (float32-equivalent: the matrix-core part)
+            // per launch; flops: the output map's products (float32 or float32-equivalent: the
+            // matrix-core part)
             Work w = item_work((double)nc * c->lda_out * ts + (exact ? (double)c->Mp * ts : 0.0) +
                                    8.0 * (1 + r + r * r),
                                2.0 * c->M * c->in_last * nc, cap, count, slot, 0);
-            w.b0 += 6.0 * c->Mp * c->lda_out;
-            RS_TRY(run(c, K_ELEM_FUSED, w, s, [&] { return launch_elem_fused(f, s); }));
+            w.b0 += (c->bf16 ? 6.0 : 4.0) * c->Mp * c->lda_out;
+            RS_TRY(run(c, K_ELEM_FUSED, w, s, [&] { return launch_elem_fused(c->bf16, f, s); }));
         } else {
             // algorithmic bytes: read the item's rows once, write seeds and (E, g, H)
             const double pb = (double)c->M * nc * ts + (exact ? (double)c->Mp * ts : 0.0) + 8.0 * (1 + r + r * r);

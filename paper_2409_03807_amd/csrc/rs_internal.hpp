@@ -100,12 +100,12 @@ struct ElemArgs {
     int part_stride;      // parts > 1: g and H of part p of item i at slot p * part_stride + i (E must be NULL)
 };
 
-// Output map and element physics in one kernel (BF16 context, r == 16): the
-// element part as ElemArgs (its `out` unused: no J_R is stored), plus the
-// output map's operands.
+// Output map and element physics in one kernel (float32 and BF16 contexts,
+// r == 16): the element part as ElemArgs (its `out` unused: no J_R is stored),
+// plus the output map's operands.
 struct FusedElemArgs {
     ElemArgs e;
-    const void* A;      // W_big as three BF16 planes (hi, mid, lo), each rows_pad x lda
+    const void* A;      // W_big: float32 rows_pad x lda, or three BF16 planes (hi, mid, lo) of that
     int lda, K;         // K: a multiple of 32 (columns of W_big past the width are zero)
     int rows;           // rows of W_big (9 per tet, 3 per target, gravity, 3 force)
     const float* bias;  // rows: the value column's bias
@@ -326,10 +326,11 @@ hipError_t launch_activate(int f32, const void* pre, void* act, int rows, int ro
                            const int* count, hipStream_t s);
 hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
 // the fused output map + element kernel: whether it applies (r, K), and the
-// workgroups per item group it splits the rows over at a launch of cap items
+// workgroups per item group it splits the rows over at a launch of cap items;
+// A holds W_big as three BF16 planes (bf16 != 0) or in float32
 bool elem_fused_fits(int r, int K);
 int elem_fused_parts(int cap, int n_cu);
-hipError_t launch_elem_fused(const FusedElemArgs& a, hipStream_t s);
+hipError_t launch_elem_fused(int bf16, const FusedElemArgs& a, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 // per-element positive-semi-definite projection: adds its correction to H
 hipError_t launch_elem_psd(int f32, const ElemOptArgs& a, int items, hipStream_t s);

@@ -1981,6 +1981,124 @@ int elem_fused_parts(int cap, int n_cu)
     return std::max(1, std::min(8, (2 * n_cu + groups - 1) / groups));
 }
 
+// Element physics of one item on one chunk of its rows in LDS (rows of 17
+// values from Jw: the chunk's 16 tets, or for a chunk past the tets its
+// penalty targets and the gravity and force rows), on the two-column lanes of
+// one wave: tets (targets) r0 + rs q + eg of the chunk, q = 0, 1, ...; the
+// gravity and force rows on the wave with r0 == 0.  H goes to hs (float32,
+// matrix-core layout), g and E to the lanes' float64 sums, the adjoint seeds
+// to memory.
+__device__ inline void fused_item_chunk(const ElemArgs& e, const float* Jw, int item, bool tail, int ch, int ntc,
+                                        int row0, int nrows, int r0, int rs, int eg, int k, f32x4& hs, double& gk,
+                                        double& gk2, double& Ee)
+{
+    const float mu = (float)e.mu, lam = (float)e.lam;
+    const bool ext = !e.elastic_only;
+    const double kc = e.k_c;
+    const int prow = 9 * e.S;
+    const int bidx = e.imap ? e.imap[item] : item;
+    float* dseed = e.dseed ? static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad : nullptr;
+    if (!tail) {
+        const int s0 = kFuseTets * ch, ns = min(kFuseTets, e.S - s0);
+        for (int q = 0; r0 + rs * q < ns; ++q) {
+            const int sl = r0 + rs * q + eg;
+            const bool sok = sl < ns;
+            const int slc = sok ? sl : ns - 1;
+            const double wV = sok ? e.wV[s0 + sl] : 0.0;
+            float P[9];
+            tet_two_col(Jw + 9 * slc * 17, k, wV, mu, lam, hs, gk, gk2, Ee, P);
+            if (dseed && sok) {
+                // lane k writes seed k; lane 0 also seed 8
+                const float wt = (float)wV;
+                float pv = P[0];
+#pragma unroll
+                for (int v = 1; v < 8; ++v) pv = k == v ? P[v] : pv;
+                global_store_asm(dseed + 9 * (s0 + sl) + k, wt * pv);
+                if (k == 0) global_store_asm(dseed + 9 * (s0 + sl) + 8, wt * P[8]);
+            }
+        }
+        return;
+    }
+    // penalty k_c/2 |x_t - target_t|^2 of the chunk's targets (three rows each)
+    const double* tg = (ext && e.targets) ? e.targets + (size_t)bidx * e.nt * 3 : nullptr;
+    const int tb = (row0 - prow) / 3;
+    const int ntg = tg ? max(0, min(kFuseRows / 3, e.nt - tb)) : 0;
+    const float kt = (float)kc;
+    for (int q = 0; r0 + rs * q < ntg; ++q) {
+        const int tl = r0 + rs * q + eg, t = tb + tl;
+        const bool ok = tl < ntg;
+        const int tc = ok ? t : tb;
+        double xr[3], tr[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xr[c] = e.Xt[3 * tc + c];
+            tr[c] = tg[3 * tc + c];
+        }
+        const float* row = Jw + 3 * (ok ? tl : 0) * 17;
+        float xv[3], jr[3], jr2[3];
+        lds_read3(row, 17, xv);
+        lds_read3(row + 1 + k, 17, jr);
+        lds_read3(row + 9 + k, 17, jr2);
+        float Jc[3], J2[3];
+        double d[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Jc[c] = ok ? jr[c] : 0.f;
+            J2[c] = ok ? jr2[c] : 0.f;
+            d[c] = ok ? xr[c] + (double)xv[c] - tr[c] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float pe = pair_even(Jc[c], J2[c]), po = pair_odd(Jc[c], J2[c]);
+            hs = Mfma<float>::mac(pe, kt * pe, hs);
+            hs = Mfma<float>::mac(po, kt * po, hs);
+        }
+        if (ok) {
+            gk += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
+            gk2 += kc * ((double)J2[0] * d[0] + (double)J2[1] * d[1] + (double)J2[2] * d[2]);
+            Ee += k == 0 ? 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0;
+            if (dseed && k < 3) {
+                const double dv = k == 0 ? d[0] : k == 1 ? d[1] : d[2];
+                global_store_asm(dseed + prow + 3 * t + k, (float)(kc * dv));
+            }
+        }
+    }
+    // gravity (-1 times the row) and force (-f_c times row c) rows of this chunk
+    if (ext && r0 == 0 && eg == 0) {
+        const int nrow = (e.force && e.nf) ? 4 : 1;
+        for (int c = 0; c < nrow; ++c) {
+            const int rg = c == 0 ? e.grav_row : e.force_row + c - 1;
+            if (rg < row0 || rg >= row0 + nrows) continue;
+            const double coef = c == 0 ? 1.0 : e.force[(size_t)bidx * 3 + c - 1];
+            const float* rr = Jw + (rg - row0) * 17;
+            gk -= coef * (double)rr[1 + k];
+            gk2 -= coef * (double)rr[9 + k];
+            if (k == 0) Ee -= coef * (double)rr[0];
+        }
+    }
+}
+
+// Seeds dE/d(row value) of the rows past the tets that no target writes:
+// penalty rows without targets, gravity (-1), force (-f_c) and padding rows.
+__device__ inline void fused_tail_seeds(const ElemArgs& e, int item, int lane)
+{
+    const bool ext = !e.elastic_only;
+    const int bidx = e.imap ? e.imap[item] : item;
+    const bool tgi = ext && e.targets;
+    float* dseed = static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad;
+    for (int row = 9 * e.S + lane; row < e.rows_pad; row += 64) {
+        double v = 0.0;
+        if (row < e.grav_row) {
+            if (tgi) continue;
+        } else if (row == e.grav_row) {
+            v = ext ? -1.0 : 0.0;
+        } else if (row < e.force_row + 3) {
+            v = (ext && e.force && e.nf) ? -e.force[(size_t)bidx * 3 + (row - e.force_row)] : 0.0;
+        }
+        dseed[row] = (float)v;
+    }
+}
+
 template <int KCH>
 __global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
 {
@@ -2036,9 +2154,6 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
     const int cb = min(nch, part * per), ce = min(nch, cb + per);
     const size_t plane = (size_t)e.rows_pad * a.lda;
     const __bf16* Ab = static_cast<const __bf16*>(a.A);
-    const float mu = (float)e.mu, lam = (float)e.lam;
-    const bool ext = !e.elastic_only;
-    const double kc = e.k_c;
     // LDS column of this lane's B fragment in output tile j
     auto bcol = [&](int j) { return j < kFuseG ? 16 * j + li : (li < kFuseG ? 16 * kFuseG + li : kFuseCols - 1); };
 
@@ -2137,88 +2252,9 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
             }
             const int item = grp * kFuseG + 2 * X + slot;
             if (item >= n_items) continue; // wave-uniform
-            const int bidx = e.imap ? e.imap[item] : item;
-            float* dseed = e.dseed ? static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad : nullptr;
-            const float* Jw = Jl + slot * kFuseRows * 17;
             f32x4 hs = {0.f, 0.f, 0.f, 0.f};
-            if (!tail) {
-                const int s0 = kFuseTets * ch, ns = min(kFuseTets, S - s0);
-                if (8 * hf < ns) {
-                    const int sl = 8 * hf + eg;
-                    const bool sok = sl < ns;
-                    const int slc = sok ? sl : ns - 1;
-                    const double wV = sok ? e.wV[s0 + sl] : 0.0;
-                    float P[9];
-                    tet_two_col(Jw + 9 * slc * 17, k, wV, mu, lam, hs, gk[X], gk2[X], Ee[X], P);
-                    if (dseed && sok) {
-                        // lane k writes seed k; lane 0 also seed 8
-                        const float wt = (float)wV;
-                        float pv = P[0];
-#pragma unroll
-                        for (int v = 1; v < 8; ++v) pv = k == v ? P[v] : pv;
-                        global_store_asm(dseed + 9 * (s0 + sl) + k, wt * pv);
-                        if (k == 0) global_store_asm(dseed + 9 * (s0 + sl) + 8, wt * P[8]);
-                    }
-                }
-            } else {
-                // penalty k_c/2 |x_t - target_t|^2 of the chunk's targets (three rows each)
-                const double* tg = (ext && e.targets) ? e.targets + (size_t)bidx * e.nt * 3 : nullptr;
-                const int tb = (row0 - prow) / 3;
-                const int ntg = tg ? max(0, min(kFuseRows / 3, e.nt - tb)) : 0;
-                const float kt = (float)kc;
-                for (int q = 0; 16 * q + 8 * hf < ntg; ++q) {
-                    const int tl = 16 * q + 8 * hf + eg, t = tb + tl;
-                    const bool ok = tl < ntg;
-                    const int tc = ok ? t : tb;
-                    double xr[3], tr[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        xr[c] = e.Xt[3 * tc + c];
-                        tr[c] = tg[3 * tc + c];
-                    }
-                    const float* row = Jw + 3 * (ok ? tl : 0) * 17;
-                    float xv[3], jr[3], jr2[3];
-                    lds_read3(row, 17, xv);
-                    lds_read3(row + 1 + k, 17, jr);
-                    lds_read3(row + 9 + k, 17, jr2);
-                    float Jc[3], J2[3];
-                    double d[3];
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        Jc[c] = ok ? jr[c] : 0.f;
-                        J2[c] = ok ? jr2[c] : 0.f;
-                        d[c] = ok ? xr[c] + (double)xv[c] - tr[c] : 0.0;
-                    }
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const float pe = pair_even(Jc[c], J2[c]), po = pair_odd(Jc[c], J2[c]);
-                        hs = Mfma<float>::mac(pe, kt * pe, hs);
-                        hs = Mfma<float>::mac(po, kt * po, hs);
-                    }
-                    if (ok) {
-                        gk[X] += kc * ((double)Jc[0] * d[0] + (double)Jc[1] * d[1] + (double)Jc[2] * d[2]);
-                        gk2[X] += kc * ((double)J2[0] * d[0] + (double)J2[1] * d[1] + (double)J2[2] * d[2]);
-                        Ee[X] += k == 0 ? 0.5 * kc * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) : 0.0;
-                        if (dseed && k < 3) {
-                            const double dv = k == 0 ? d[0] : k == 1 ? d[1] : d[2];
-                            global_store_asm(dseed + prow + 3 * t + k, (float)(kc * dv));
-                        }
-                    }
-                }
-                // gravity (-1 times the row) and force (-f_c times row c) rows of this chunk
-                if (ext && hf == 0 && eg == 0) {
-                    const int nrow = (e.force && e.nf) ? 4 : 1;
-                    for (int c = 0; c < nrow; ++c) {
-                        const int rg = c == 0 ? e.grav_row : e.force_row + c - 1;
-                        if (rg < row0 || rg >= row0 + 16 * ntile) continue;
-                        const double coef = c == 0 ? 1.0 : e.force[(size_t)bidx * 3 + c - 1];
-                        const float* rr = Jw + (rg - row0) * 17;
-                        gk[X] -= coef * (double)rr[1 + k];
-                        gk2[X] -= coef * (double)rr[9 + k];
-                        if (k == 0) Ee[X] -= coef * (double)rr[0];
-                    }
-                }
-            }
+            fused_item_chunk(e, Jl + slot * kFuseRows * 17, item, tail, ch, ntc, row0, 16 * ntile, 8 * hf, 16, eg, k,
+                             hs, gk[X], gk2[X], Ee[X]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) Hm[X][q] += (double)hs[q];
         }
@@ -2262,27 +2298,179 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
         if (lane < 16 && e.g) e.g[slot_o * 16 + lane] = r0[256 + lane] + r1[256 + lane];
         if (lane == 0 && e.E) e.E[item] = r0[272] + r1[272];
     }
-    if (e.dseed && part == 0) {
-        // rows not written above: penalty rows without targets, gravity,
-        // force and padding rows
-        const int bidx = e.imap ? e.imap[item] : item;
-        const bool tgi = ext && e.targets;
-        float* dseed = static_cast<float*>(e.dseed) + (size_t)item * e.rows_pad;
-        for (int row = prow + lane; row < e.rows_pad; row += 64) {
-            double v = 0.0;
-            if (row < e.grav_row) {
-                if (tgi) continue;
-            } else if (row == e.grav_row) {
-                v = ext ? -1.0 : 0.0;
-            } else if (row < e.force_row + 3) {
-                v = (ext && e.force && e.nf) ? -e.force[(size_t)bidx * 3 + (row - e.force_row)] : 0.0;
-            }
-            dseed[row] = (float)v;
-        }
-    }
+    if (e.dseed && part == 0) fused_tail_seeds(e, item, lane);
 }
 
-hipError_t launch_elem_fused(const FusedElemArgs& a, hipStream_t s)
+// The same for float32 contexts: the output map on the FP32 matrix cores.
+// With no BF16 parts the group's activation columns take half the LDS, so the
+// rows of all four items fit at once: one element pass per chunk, wave w on
+// item w (16 tets: two rounds).  Row tiles: wave w takes t = w - ch (mod 4)
+// and t + 4 with all five output tiles, and of the ninth row tile the output
+// tile j = w (the value tile on wave ch mod 4), so the four waves' products
+// per chunk differ by at most one output tile.  Per 16x16x4 product, lane
+// (i, g) supplies W_big[row i][K/4 g + s] and the activation column i at the
+// same k (step s): each lane's A and B values are one contiguous run of K/4.
+template <int KCH>
+__global__ __launch_bounds__(256, 2) void k_elem_fused_f32(FusedElemArgs a)
+{
+    constexpr int K = KCH * kTileK;
+    constexpr int KS = K / 4;  // products per output tile (k per lane)
+    constexpr int LDY = K + 4; // floats per LDS column (16-byte rows, staggered banks)
+    __shared__ __align__(16) float Yf[kFuseCols * LDY];
+    __shared__ __align__(16) float Jl[kFuseG * kFuseRows * 17];
+    const ElemArgs& e = a.e;
+    const int grp = blockIdx.x / e.parts, part = blockIdx.x - grp * e.parts;
+    const int n_items = e.count ? min(*e.count, a.cap) : a.cap;
+    if (grp * kFuseG >= n_items) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int eg = lane >> 3, k = lane & 7;
+    const int nc = e.nc;
+
+    // the group's activation columns (Jacobian, values, zeros)
+    {
+        constexpr int Q = K / 4;
+        for (int idx = tid; idx < kFuseCols * Q; idx += 256) {
+            const int n = idx / Q, q = idx - n * Q;
+            int it = n_items, col = 0;
+            if (n < 16 * kFuseG) {
+                it = grp * kFuseG + (n >> 4);
+                col = 1 + (n & 15);
+            } else if (n < 16 * kFuseG + kFuseG) {
+                it = grp * kFuseG + n - 16 * kFuseG;
+            }
+            f32x4 v = {0.f, 0.f, 0.f, 0.f};
+            if (it < n_items) v = *reinterpret_cast<const f32x4*>(a.Y + ((size_t)it * nc + col) * a.y_rows + 4 * q);
+            *reinterpret_cast<f32x4*>(&Yf[n * LDY + 4 * q]) = v;
+        }
+    }
+
+    const int S = e.S;
+    const int prow = 9 * S;
+    const int ntc = (S + kFuseTets - 1) / kFuseTets;
+    const int ntl = (a.rows - prow + kFuseRows - 1) / kFuseRows;
+    const int nch = ntc + ntl;
+    const int per = (nch + e.parts - 1) / e.parts;
+    const int cb = min(nch, part * per), ce = min(nch, cb + per);
+    const float* Af = static_cast<const float*>(a.A);
+    auto bcol = [&](int j) { return j < kFuseG ? 16 * j + li : (li < kFuseG ? 16 * kFuseG + li : kFuseCols - 1); };
+    const int item = grp * kFuseG + wave;
+    const bool iok = item < n_items;
+
+    double Hm[4] = {0.0, 0.0, 0.0, 0.0};
+    double gk = 0.0, gk2 = 0.0, Ee = 0.0;
+
+    lds_barrier(); // the activation columns
+    for (int ch = cb; ch < ce; ++ch) {
+        const bool tail = ch >= ntc;
+        const int row0 = tail ? prow + kFuseRows * (ch - ntc) : kFuseRows * ch;
+        const int ntile = tail ? min(9, (a.rows - row0 + 15) / 16) : 9;
+        const int t0 = (wave - ch) & 3;
+        // row tiles t0, t0 + 4 (all output tiles) and 8 (output tiles in m8)
+        const int m8 = ntile == 9 ? (1 << wave) | (wave == (ch & 3) ? 16 : 0) : 0;
+        const bool u0 = t0 < ntile, u1 = t0 + 4 < ntile;
+        {
+            // A fragments of the three row tiles, all loads issued at once (rows
+            // past the padded end re-read the last row: never used)
+            f32x4 af[3][KS / 4];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int t = i < 2 ? t0 + 4 * i : 8;
+                const int row = min(row0 + 16 * t + li, e.rows_pad - 1);
+                const f32x4* p = reinterpret_cast<const f32x4*>(Af + (size_t)row * a.lda + KS * lg);
+#pragma unroll
+                for (int q = 0; q < KS / 4; ++q) af[i][q] = p[q];
+            }
+            // the products of output tile j for the row tiles in M (bit i: slot
+            // i), one branch per output tile, none per product
+            auto prod = [&](auto MC, int j) {
+                constexpr int M = decltype(MC)::value;
+                f32x4 b[KS / 4];
+                const f32x4* bp = reinterpret_cast<const f32x4*>(&Yf[bcol(j) * LDY + KS * lg]);
+#pragma unroll
+                for (int q = 0; q < KS / 4; ++q) b[q] = bp[q];
+                // every B read issued before the products (their waits then fall
+                // one by one instead of one read per eight products)
+                __builtin_amdgcn_sched_barrier(0);
+                f32x4 acc[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < KS / 4; ++q)
+#pragma unroll
+                    for (int e4 = 0; e4 < 4; ++e4)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            if (((M >> i) & 1) != 0) acc[i] = Mfma<float>::mac(af[i][q][e4], b[q][e4], acc[i]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (((M >> i) & 1) == 0) continue; // folded: the loop is unrolled
+                    const int t = i < 2 ? t0 + 4 * i : 8;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = 16 * t + 4 * lg + v; // row within the chunk
+                        if (j < kFuseG) {
+                            Jl[(j * kFuseRows + m) * 17 + 1 + li] = acc[i][v];
+                        } else if (li < kFuseG) {
+                            const int rg = row0 + m;
+                            Jl[(li * kFuseRows + m) * 17] = acc[i][v] + (rg < a.rows ? a.bias[rg] : 0.f);
+                        }
+                    }
+                }
+            };
+            using M1 = std::integral_constant<int, 1>;
+            using M3 = std::integral_constant<int, 3>;
+            using M4 = std::integral_constant<int, 4>;
+            using M5 = std::integral_constant<int, 5>;
+            using M7 = std::integral_constant<int, 7>;
+#pragma unroll 1
+            for (int j = 0; j < 5; ++j) {
+                // u1 implies u0; tile 8 exists only where u0 and u1 do
+                const int mask = (u0 ? 1 : 0) | (u1 ? 2 : 0) | (((m8 >> j) & 1) ? 4 : 0);
+                switch (mask) {
+                case 1: prod(M1{}, j); break;
+                case 3: prod(M3{}, j); break;
+                case 4: prod(M4{}, j); break;
+                case 5: prod(M5{}, j); break;
+                case 7: prod(M7{}, j); break;
+                default: break;
+                }
+            }
+        }
+        lds_barrier(); // the chunk's rows
+        if (iok) {
+            f32x4 hs = {0.f, 0.f, 0.f, 0.f};
+            fused_item_chunk(e, Jl + wave * kFuseRows * 17, item, tail, ch, ntc, row0, 16 * ntile, 0, 8, eg, k, hs,
+                             gk, gk2, Ee);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Hm[q] += (double)hs[q];
+        }
+        lds_barrier(); // the chunk's rows are read
+    }
+    if (!iok) return;
+
+    // g and E over the wave's 8 tet lanes (lanes k, k + 8, ...); H is whole per wave
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1) {
+        gk += __shfl_xor(gk, off);
+        gk2 += __shfl_xor(gk2, off);
+        Ee += __shfl_xor(Ee, off);
+    }
+    const size_t slot = (size_t)part * e.part_stride + item;
+    if (e.H) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e.H[slot * 256 + Mfma<float>::row(lane, q) * 16 + li] = Hm[q];
+    }
+    if (eg == 0 && e.g) {
+        e.g[slot * 16 + k] = gk;
+        e.g[slot * 16 + 8 + k] = gk2;
+    }
+    if (lane == 0 && e.E) e.E[item] = Ee;
+    if (e.dseed && part == 0) fused_tail_seeds(e, item, lane);
+}
+
+hipError_t launch_elem_fused(int bf16, const FusedElemArgs& a, hipStream_t s)
 {
     if (a.cap <= 0) return hipSuccess;
     const ElemArgs& e = a.e;
@@ -2291,12 +2479,18 @@ hipError_t launch_elem_fused(const FusedElemArgs& a, hipStream_t s)
         return hipErrorInvalidValue;
     const int groups = (a.cap + kFuseG - 1) / kFuseG;
     dim3 grid(groups * e.parts), block(256);
+#define RS_FUSED(KC)                                                                   \
+    do {                                                                               \
+        if (bf16) RS_LAUNCH((k_elem_fused<KC>), grid, block, 0, s, a);                 \
+        else RS_LAUNCH((k_elem_fused_f32<KC>), grid, block, 0, s, a);                  \
+    } while (0)
     switch (a.K / kTileK) {
-    case 1: RS_LAUNCH((k_elem_fused<1>), grid, block, 0, s, a); break;
-    case 2: RS_LAUNCH((k_elem_fused<2>), grid, block, 0, s, a); break;
-    case 3: RS_LAUNCH((k_elem_fused<3>), grid, block, 0, s, a); break;
-    default: RS_LAUNCH((k_elem_fused<4>), grid, block, 0, s, a); break;
+    case 1: RS_FUSED(1); break;
+    case 2: RS_FUSED(2); break;
+    case 3: RS_FUSED(3); break;
+    default: RS_FUSED(4); break;
     }
+#undef RS_FUSED
     return hipGetLastError();
 }
 

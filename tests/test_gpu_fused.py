@@ -1,13 +1,15 @@
-"""GPU parity of the fused output-map + element kernel (BF16 contexts, r = 16).
+"""GPU parity of the fused output-map + element kernel (r = 16; BF16 contexts:
+products on the BF16 matrix cores, float32 contexts: on the FP32 ones).
 
 The fused kernel forms the rows of J_R (each cubature tet's F with its 16
 Jacobian columns, then the penalty, gravity and force rows) in on-chip memory
 and runs the element physics on them in the same workgroup.  It is compared
-with the float64 oracle at the BF16 bar (1e-4) and with the two-kernel path
-(J_R through device memory), which computes the same function to float32
-rounding, on: cubature sets that end inside a 16-tet chunk, target counts that
-span several row chunks, force loads with and without targets, Gauss-Newton
-and exact Hessians, elastic-only evaluations, batches whose last group of four
+with the float64 oracle at the float32 bar (1e-4, also for BF16 contexts: their
+three-part operands carry float32 accuracy) and with the two-kernel path (J_R
+through device memory), which computes the same function to float32 rounding,
+on: cubature sets that end inside a 16-tet chunk, target counts that span
+several row chunks, force loads with and without targets, Gauss-Newton and
+exact Hessians, elastic-only evaluations, batches whose last group of four
 items is ragged, and batches whose rows are split over several workgroups.
 """
 import numpy as np
@@ -26,7 +28,8 @@ if not torch.cuda.is_available():
 from paper_2409_03807_amd import binding as rb  # noqa: E402
 
 DEV = "cuda:0"
-TOL = 1e-4        # BF16 contexts: float32 accuracy
+TOL = 1e-4        # float32 accuracy (BF16 contexts too)
+PRECS = [rb.PREC_BF16, rb.PREC_F32]
 TOL_SPLIT = 2e-5  # fused against two-kernel: the same products, summed in another order
 
 
@@ -57,18 +60,19 @@ def _both(ctx, z, tg, fo, flags):
     return out
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n_cub", [16, 45, 100])
 @pytest.mark.parametrize("twist", [True, False])
 @pytest.mark.parametrize("flags", [rb.HESS_EXACT, 0, rb.HESS_EXACT | rb.ELASTIC_ONLY])
-def test_fused_small_meshes(n_cub, twist, flags):
+def test_fused_small_meshes(n_cub, twist, flags, prec):
     """8x8x8 block: 81 end-face vertices as targets (two row chunks past the
     tets) or none, bend forces on the same face, r = 16, 2 x 64 ELU."""
     p = I.make_problem(f"fu{n_cub}", 8, 8, 8, 16, [64, 64], n_cub, twist=twist, bend=True, bias_scale=0.3)
     o = O.Oracle(p)
     oflags = (O.EXACT if flags & rb.HESS_EXACT else 0) | (O.ELASTIC_ONLY if flags & rb.ELASTIC_ONLY else 0)
     for B in (1, 3, 6):
-        print(f"[fused] n_cub={n_cub} twist={twist} flags={flags} B={B}", flush=True)
-        ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+        print(f"[fused] prec={prec} n_cub={n_cub} twist={twist} flags={flags} B={B}", flush=True)
+        ctx = rb.Context(p, prec=prec, max_batch=B)
         z = I.latent_batch(B, p.r)
         tg, fo = I.loads_for(p, B)
         (E, g, H), (Es, gs, Hs) = _both(ctx, z, tg, fo, flags)
@@ -81,8 +85,8 @@ def test_fused_small_meshes(n_cub, twist, flags):
 
 
 def test_fused_not_applicable_runs_split():
-    """r != 16: the context reports that the fused kernel does not apply and the
-    two-kernel path runs."""
+    """r != 16 or float64: the context reports that the fused kernel does not
+    apply and the two-kernel path runs."""
     for p in (I.make_problem("fu_r8", 4, 2, 2, 8, [32, 32], 20, bend=True, bias_scale=0.3),
               I.make_problem("fu_r12", 4, 2, 2, 12, [64, 64], 20, bend=True, bias_scale=0.3)):
         ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=2)
@@ -93,19 +97,20 @@ def test_fused_not_applicable_runs_split():
         Eo, go, Ho = O.Oracle(p).reduced(z, tg, fo)
         assert relerr(g.cpu().numpy(), go).max() < TOL
         assert relerr(H.cpu().numpy(), Ho).max() < TOL
-    # a float32 context never fuses
+    # a float64 context never fuses
     p = I.config("c2")
-    assert not rb.Context(p, prec=rb.PREC_F32, max_batch=2).set_fused(True)
+    assert not rb.Context(p, prec=rb.PREC_F64, max_batch=2).set_fused(True)
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("B", [40, 1024, 1027])
-def test_fused_c2_batches(B):
+def test_fused_c2_batches(B, prec):
     """c2 (256 tets, 81 targets, r = 16, 4 x 128): batches split over eight and
     two workgroups per item group and a ragged last group; sampled items
     against the oracle, every item against the two-kernel path."""
     p = I.config("c2")
-    print(f"[fused] c2 B={B}", flush=True)
-    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    print(f"[fused] prec={prec} c2 B={B}", flush=True)
+    ctx = rb.Context(p, prec=prec, max_batch=B)
     z = I.latent_batch(B, p.r)
     tg, fo = I.loads_for(p, B)
     (E, g, H), (Es, gs, Hs) = _both(ctx, z, tg, fo, rb.HESS_EXACT)
@@ -135,16 +140,17 @@ def test_fused_c3_full_batch_sampled():
     assert torch.isfinite(H).all()
 
 
-def test_fused_newton_c2_matches_split():
-    """BF16 Newton solves (c2, B = 64) with the fused kernel: every item converges
-    at 1e-6, is stationary for the oracle's float64 gradient, and takes the
+@pytest.mark.parametrize("prec", PRECS)
+def test_fused_newton_c2_matches_split(prec):
+    """Newton solves (c2, B = 64) with the fused kernel: every item converges at
+    1e-6, is stationary for the oracle's float64 gradient, and takes the
     iterations of the two-kernel path within one."""
     p = I.config("c2")
     B = 64
-    print("[fused] c2 newton B=64", flush=True)
+    print(f"[fused] prec={prec} c2 newton B=64", flush=True)
     z0 = I.latent_batch(B, p.r)
     tg, fo = I.loads_for(p, B)
-    ctx = rb.Context(p, prec=rb.PREC_BF16, max_batch=B)
+    ctx = rb.Context(p, prec=prec, max_batch=B)
     res = {}
     for on in (True, False):
         ctx.set_fused(on)

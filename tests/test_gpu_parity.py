@@ -113,13 +113,16 @@ def test_energy_only_and_chunking(name, prec):
 @pytest.mark.parametrize("n_cub", [16, 45, 100])
 @pytest.mark.parametrize("flags", [rb.HESS_EXACT, 0])
 def test_element_two_column_path_ragged_rounds(n_cub, flags):
-    """r = 16 in float32 runs 8 lanes per tet with two columns each, 32 tets a
-    round: cubature sets that end inside a round, and small batches whose items
-    are split over several workgroups."""
+    """r = 16 in float32 with J_R through device memory (the two-kernel path,
+    which ground contact, inertia and the element options use): the element
+    kernel runs 8 lanes per tet with two columns each, 32 tets a round;
+    cubature sets that end inside a round, and small batches whose items are
+    split over several workgroups."""
     p = I.make_problem(f"two{n_cub}", 6, 2, 2, 16, [32, 32], n_cub, bend=True, bias_scale=0.3)
     o = O.Oracle(p)
     for B in (3, 40):
         ctx = rb.Context(p, prec=rb.PREC_F32, max_batch=B)
+        assert ctx.set_fused(False)
         z = I.latent_batch(B, p.r)
         tg, fo = I.loads_for(p, B)
         E, g, H = ctx.energy_grad_hess(t64(z), t64(tg), t64(fo), flags=flags)
