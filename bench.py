@@ -17,6 +17,13 @@ reductions, r x r solve, line-search energies and convergence test.
 Metric: converged reduced solves per second (items ending with
 |g|_inf <= 1e-6 |g_0|_inf), whole job, inputs resident in HBM.
 
+Batching: by default the Newton line streams the timed steps' batches (copies
+of the same batch) through one solve with the batch size (1024) in flight: an
+item that finishes gives its place to the next one, so no super-step runs with
+only the slowest items of a batch (continuous batching; every launch still
+holds at most 1024 items).  --batching per-batch solves each step's batch on
+its own, as the other solvers and paths always do.
+
 Other lines of the same script:
 * --config c1 / c3: the 10x2x2 beam in float64, or c2 at a batch of 4096 with
   the BF16 decoder (three-part BF16 operands, float32 accuracy);
@@ -124,6 +131,11 @@ def parse():
     ap.add_argument("--eig-floor", type=float, default=1e-8)
     ap.add_argument("--hess", default="exact", choices=["exact", "gn", "gn_psd", "exact_psd"],
                     help="Newton Hessian: exact or Gauss-Newton, optionally with per-element PSD projection")
+    ap.add_argument("--batching", default="auto", choices=["auto", "continuous", "per-batch"],
+                    help="continuous (the default for Newton solves): the timed steps' batches (copies of the base "
+                         "batch) go through one solve with the batch size in flight, a finished item's place "
+                         "taken by the next one, plus one Lipschitz evaluation per step; per-batch: one solve per "
+                         "step (the default for the other solvers and paths)")
     ap.add_argument("--fused", default="auto", choices=["auto", "on", "off"],
                     help="output map and element physics in one kernel (on) or two (off); auto: the "
                          "context's default (on for BF16, off for float32)")
@@ -160,7 +172,13 @@ def main():
     if args.prec:
         prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
-    ctx = rb.Context(p, prec=prec, max_batch=B)
+    # continuous batching: the timed steps' batches go through one solve, B items in flight
+    newton_solve_path = args.solver == "newton" and args.path == "solve"
+    if args.batching == "continuous" and not newton_solve_path:
+        raise SystemExit("--batching continuous applies to the Newton solve path")
+    args.stream = args.batching == "continuous" or (args.batching == "auto" and newton_solve_path)
+    nstream = max(args.steps, args.warmup, 1) if args.stream else 1
+    ctx = rb.Context(p, prec=prec, max_batch=B * nstream)
     if args.fused == "auto":
         fused = prec == rb.PREC_BF16 and ctx.set_fused(True)
     else:
@@ -180,6 +198,8 @@ def main():
             "exact_psd": rb.HESS_EXACT_ELEM_PSD}[args.hess]
     opts = rb.default_opts(proj=rb.PROJ_CLAMP if args.proj == "clamp" else rb.PROJ_ABS, eig_floor=args.eig_floor,
                            hess=hess)
+    if args.stream:
+        opts.window = B
     lbfgs = args.solver == "lbfgs"
     lopts = rb.default_lbfgs_opts()
     npair = B // 2
@@ -191,6 +211,22 @@ def main():
     iter_acc = torch.zeros((), dtype=torch.int64, device=dev)
 
     pgrad = args.path == "param_grad"
+
+    def stream_steps(n):
+        """n batches (copies of the base batch) through one solve with B items in flight,
+        plus n Lipschitz evaluations: the work of n steps."""
+        N = n * B
+        zs = z0.repeat(n, 1)
+        tgs = tg.repeat(n, 1, 1) if tg is not None else None
+        fos = fo.repeat(n, 1) if fo is not None else None
+        res = ctx.newton_solve(zs, tgs, fos, opts=opts)
+        lip = None
+        for _ in range(n):
+            lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False) if npair else None
+        conv_acc.add_((res["status"] == rb.CONVERGED).sum())
+        iter_acc.add_(res["iters"].sum())
+        assert res["status"].shape[0] == N
+        return res, lip
 
     def step():
         if pgrad:
@@ -214,15 +250,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
+    if args.stream:
+        if args.warmup:
+            stream_steps(args.warmup)
+    else:
+        for _ in range(args.warmup):
+            step()
     torch.cuda.synchronize()
     dominant = None
     if not args.no_profile:
         # a profiled pass picks the dominant kernel kind; the timed region then
         # brackets only that kind with HIP events (one event pair per launch)
         ctx.profile(True)
-        step()
+        if args.stream:
+            stream_steps(1)
+        else:
+            step()
         ctx.profile(False)
         warm = ctx.profile_read()
         dominant = max(warm.items(), key=lambda kv: kv[1]["ms"])[0]
@@ -231,8 +274,11 @@ def main():
     iter_acc.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res, lip = step()
+    if args.stream:
+        res, lip = stream_steps(args.steps)
+    else:
+        for _ in range(args.steps):
+            res, lip = step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     conv = int(conv_acc.item())
@@ -321,6 +367,8 @@ def main():
             "batch": B, "rows": info.rows, "subspace": "plain", "solver": "none" if pgrad else args.solver,
             "path": args.path, "hessian": args.hess, "projection": args.proj,
             "output_map": "fused with the element physics" if fused else "separate kernel (J_R through HBM)",
+            "batching": (f"continuous: the {args.steps} batches through one solve, {B} items in flight"
+                         if args.stream else "one solve per batch"),
         },
         "converged_frac": float((st == rb.CONVERGED).mean()),
         "status_counts": {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},

@@ -172,6 +172,11 @@ typedef struct {
                            projection of the cubature element Hessians (RS_ELEM_PSD) */
     int32_t proj;       /* RS_PROJ_*, default RS_PROJ_ABS */
     double eig_floor;   /* relative eigenvalue floor, default 1e-8 */
+    int32_t window;     /* items in flight, default 0 (all B at once).  0 < window < B: items 0 .. window-1
+                           start, and item b enters as soon as fewer than `window` items run (continuous
+                           batching: every super-step stays full until the last items).  Each item's
+                           iterates are those of a solve with every item in flight, up to the float32
+                           summation order of the launch sizes */
 } rs_solve_opts;
 
 /* L-BFGS options (host struct).  Defaults from rs_default_lbfgs_opts(). */

@@ -66,7 +66,7 @@ class _Load(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ls_max", C.c_int32), ("c1", C.c_double),
                 ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double),
-                ("hess", C.c_int32), ("proj", C.c_int32), ("eig_floor", C.c_double)]
+                ("hess", C.c_int32), ("proj", C.c_int32), ("eig_floor", C.c_double), ("window", C.c_int32)]
 
 
 class LbfgsOpts(C.Structure):

@@ -532,6 +532,7 @@ extern "C" int rs_default_opts(rs_solve_opts* o)
     o->hess = 1;
     o->proj = RS_PROJ_ABS;
     o->eig_floor = 1e-8;
+    o->window = 0;
     return RS_OK;
 }
 
@@ -794,7 +795,7 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->search_ncand = (int*)need(dalloc<int>(c, B));
     c->cand_item = (int*)need(dalloc<int>(c, BL));
     c->cand_j = (int*)need(dalloc<int>(c, BL));
-    c->counters = (int*)need(dalloc<int>(c, 4));
+    c->counters = (int*)need(dalloc<int>(c, 8));
     c->zc = (double*)need(dalloc<double>(c, BL * c->r));
     c->out64 = (double*)need(dalloc<double>(c, BL * c->Mp));
     c->Ec = (double*)need(dalloc<double>(c, BL));
@@ -1853,16 +1854,20 @@ static int solve_batch(rs_ctx* c, int32_t B, double* z, const rs_load* load, con
     c->cur_slot = -1;
     RS_TRY(run(c, K_INIT, Work{}, s, [&] { return launch_newton_init(st, B, s); }));
     RS_TRY(energy_f64(c, B, nullptr, 0, z, tg, fo, nullptr, 0, E, s, K_LS_GEMM_HIDDEN, K_LS_GEMM_OUT));
-    RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_eval(st, B, s); }));
+    RS_TRY(run(c, K_COMPACT, Work{}, s, [&] { return launch_compact_eval(st, B, p.window, s); }));
     // Every super-step either evaluates an item or advances its line search by
     // at least one trial, so this bounds the loop.  The host runs one
     // super-step ahead: it launches step k+1 before reading the running count
     // of step k (counts only fall, so an older count bounds every launch).
     // Each super-step ends with the Armijo kernel, which also builds the next
     // evaluation list and writes the running count to mapped host memory.
-    // fixed_steps > 0: exactly that many super-steps, all sized for B, with no host reads
-    const long max_steps = fixed_steps > 0 ? fixed_steps : (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
-    int n_run = B;
+    // fixed_steps > 0: exactly that many super-steps, all sized for B (the window), with no host reads.
+    // With a window W < B every admitted item ends within the per-item bound and frees its place,
+    // so ceil(B / W) such bounds cover the whole batch.
+    const int W = p.window > 0 ? p.window : B;
+    const long per_item = (long)(p.max_iter + 1) * (2 + p.ls_max) + 2;
+    const long max_steps = fixed_steps > 0 ? fixed_steps : per_item * ((B + W - 1) / W);
+    int n_run = W;
     unsigned int tags[2] = {0, 0};
     for (long step = 0; step < max_steps; ++step) {
         RS_TRY(log_counters(c, s));
@@ -1950,7 +1955,7 @@ static int newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, co
     rs_default_opts(&def);
     if (!o) o = &def;
     if (o->max_iter < 0 || o->ls_max < 0 || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) ||
-        o->proj < 0 || o->proj > 2 || o->hess < 0 || o->hess > 3)
+        o->proj < 0 || o->proj > 2 || o->hess < 0 || o->hess > 3 || o->window < 0)
         return fail(c, RS_ERR_ARG, "invalid solver options");
     NewtonParams p{};
     p.r = c->r;
@@ -1962,6 +1967,7 @@ static int newton_solve(rs_ctx* c, int32_t B, double* z, const rs_load* load, co
     p.rel_tol = o->rel_tol;
     p.abs_tol = o->abs_tol;
     p.eig_floor = o->eig_floor;
+    p.window = o->window < B ? o->window : 0;
     const uint32_t hflags = ((o->hess & 1) ? RS_HESS_EXACT : 0u) | ((o->hess & 2) ? RS_ELEM_PSD : 0u);
     RS_TRY(dyn_setup(c, load, B, 0, static_cast<hipStream_t>(stream)));
     return solve_batch(c, B, z, load, p, hflags, false, iters, status, relgrad, E, stream, fixed_steps);

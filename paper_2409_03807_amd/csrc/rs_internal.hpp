@@ -210,7 +210,7 @@ struct NewtonState {
     int* search_ncand;// candidates of each searching item
     int* cand_item;   // candidate -> item
     int* cand_j;      // candidate -> trial index
-    int* counters;    // [0] n_eval [1] n_cand [2] n_search [3] n_running
+    int* counters;    // [0] n_eval [1] n_cand [2] n_search [3] n_running [4] n_admitted (items 0 .. n_admitted - 1)
     const double* gw; // eval-list order: g (n_eval x r)
     const double* Hw; // eval-list order: H (n_eval x r x r)
     double* zc;       // candidates x r
@@ -222,6 +222,7 @@ struct NewtonParams {
     int r, max_iter, ls_max, proj;
     double c1, shrink, rel_tol, abs_tol, eig_floor;
     int hist;         // L-BFGS: pairs kept (<= RS_MAX_HISTORY)
+    int window;       // items in flight: item b enters once fewer than `window` run (0: all at once)
 };
 
 // Per-item L-BFGS history: a ring of RS_MAX_HISTORY (s, y) pairs per item.
@@ -432,7 +433,7 @@ hipError_t launch_pca_mass(const double* X, const double* rowmass, int n, int k,
 hipError_t launch_pca_orth(const double* G, int k, double* R, int* fail, hipStream_t s);
 hipError_t launch_pca_ritz(const double* T, int k, int r, double* V, double* ev, hipStream_t s);
 hipError_t launch_newton_init(const NewtonState& st, int B, hipStream_t s);
-hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s);
+hipError_t launch_compact_eval(const NewtonState& st, int B, int window, hipStream_t s);
 hipError_t launch_newton_dir(const NewtonState& st, const NewtonParams& p, int cap, hipStream_t s);
 // L-BFGS: exit tests, history update and the two-loop direction (same outputs as launch_newton_dir)
 hipError_t launch_lbfgs_dir(const NewtonState& st, const NewtonParams& p, const LbfgsState& h, int cap,

@@ -3062,26 +3062,33 @@ __device__ inline int block_scan1024(int v, int* sc, int& total)
     return before + v;
 }
 
-__global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B)
+// The first evaluation list: items 0 .. A - 1 are admitted (A = B, or the
+// window when it is smaller); later items enter in index order as admitted
+// ones finish (k_armijo).
+__global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B, int window)
 {
     __shared__ int sc[16];
     const int tid = threadIdx.x;
+    const int A = (window > 0 && window < B) ? window : B;
     int base = 0;
-    for (int b0 = 0; b0 < B; b0 += 1024) {
+    for (int b0 = 0; b0 < A; b0 += 1024) {
         const int b = b0 + tid;
-        const int f = (b < B && st.status[b] == RS_RUNNING && st.ls_j[b] < 0) ? 1 : 0;
+        const int f = (b < A && st.status[b] == RS_RUNNING && st.ls_j[b] < 0) ? 1 : 0;
         int tot;
         const int inc = block_scan1024(f, sc, tot);
         if (f) st.eval_list[base + inc - 1] = b;
         __syncthreads();
         base += tot;
     }
-    if (tid == 0) st.counters[0] = base;
+    if (tid == 0) {
+        st.counters[0] = base;
+        st.counters[4] = A;
+    }
 }
 
-hipError_t launch_compact_eval(const NewtonState& st, int B, hipStream_t s)
+hipError_t launch_compact_eval(const NewtonState& st, int B, int window, hipStream_t s)
 {
-    RS_LAUNCH(k_compact_eval, dim3(1), dim3(1024), 0, s, st, B);
+    RS_LAUNCH(k_compact_eval, dim3(1), dim3(1024), 0, s, st, B, window);
     return hipGetLastError();
 }
 
@@ -3112,11 +3119,12 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
     __shared__ double ca[1024 * kLsCand];       // chunk candidate -> step length
     const int tid = threadIdx.x, r = p.r;
     const bool lead = blockIdx.x == 0;
+    const int A = min(B, st.counters[4]); // admitted items (the others wait, ls_j < 0)
     int base_s = 0, base_c = 0;
-    for (int b0 = 0; b0 < B; b0 += 1024) {
+    for (int b0 = 0; b0 < A; b0 += 1024) {
         const int b = b0 + tid;
         int f = 0, nc = 0, j = 0;
-        if (b < B && st.status[b] == RS_RUNNING && st.ls_j[b] >= 0) {
+        if (b < A && st.status[b] == RS_RUNNING && st.ls_j[b] >= 0) {
             j = st.ls_j[b];
             f = 1;
             nc = min(j == 0 ? 1 : kLsCand, p.ls_max - j);
@@ -3776,6 +3784,7 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     __shared__ int acc_item[1024], acc_cand[1024]; // accepted candidate per chunk search entry (-1: none)
     const int tid = threadIdx.x, r = p.r;
     const int ns = st.counters[2];
+    const int A = min(B, st.counters[4]); // admitted items
     for (int i0 = 0; i0 < ns; i0 += 1024) {
         const int i = i0 + tid;
         int item = -1, cand = -1;
@@ -3834,9 +3843,9 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     }
     __syncthreads(); // statuses and trial indices of this super-step are final
     int base = 0, running = 0;
-    for (int b0 = 0; b0 < B; b0 += 1024) {
+    for (int b0 = 0; b0 < A; b0 += 1024) {
         const int b = b0 + tid;
-        const int run = (b < B && st.status[b] == RS_RUNNING) ? 1 : 0;
+        const int run = (b < A && st.status[b] == RS_RUNNING) ? 1 : 0;
         const int f = (run && st.ls_j[b] < 0) ? 1 : 0;
         int tot;
         const int inc = block_scan1024((f << 16) | run, sc, tot);
@@ -3845,9 +3854,16 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
         base += tot >> 16;
         running += tot & 0xffff;
     }
+    // items waiting for the window enter in index order (their first evaluation
+    // is next; newton_init set their state and the first energy pass their E)
+    const int adm = (p.window > 0 && A < B) ? max(0, min(p.window - running, B - A)) : 0;
+    for (int t = tid; t < adm; t += 1024) st.eval_list[base + t] = A + t;
+    base += adm;
+    running += adm;
     if (tid == 0) {
         st.counters[0] = base;
         st.counters[3] = running;
+        st.counters[4] = A + adm;
         if (host)
             __hip_atomic_store(host, ((unsigned long long)tag << 32) | (unsigned int)running, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
