@@ -1273,7 +1273,7 @@ static int eval_T(rs_ctx* c, int cap, const int* count, const double* z, const i
         // rows at batches below eight items per compute unit.)
         a.parts = 1;
         if (exact && !E && g && cap > 0) {
-            int parts = fuse ? elem_fused_parts(cap, c->n_cu) : std::min(8, 2 * c->n_cu / cap);
+            int parts = fuse ? elem_fused_parts(c->bf16, cap, c->n_cu) : std::min(8, 2 * c->n_cu / cap);
             while (parts > 1 && (size_t)parts * cap > c->npart) --parts;
             if (parts > 1) {
                 a.parts = parts;

@@ -330,7 +330,7 @@ hipError_t launch_elem(int f32, const ElemArgs& a, int items, hipStream_t s);
 // workgroups per item group it splits the rows over at a launch of cap items;
 // A holds W_big as three BF16 planes (bf16 != 0) or in float32
 bool elem_fused_fits(int r, int K);
-int elem_fused_parts(int cap, int n_cu);
+int elem_fused_parts(int bf16, int cap, int n_cu);
 hipError_t launch_elem_fused(int bf16, const FusedElemArgs& a, hipStream_t s);
 hipError_t launch_energy(const EnergyArgs& a, int items, hipStream_t s);
 // per-element positive-semi-definite projection: adds its correction to H

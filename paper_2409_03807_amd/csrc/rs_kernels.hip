@@ -1973,12 +1973,14 @@ constexpr int kFuseCols = 16 * kFuseG + kFuseG + 1; // LDS columns: Jacobian, va
 
 bool elem_fused_fits(int r, int K) { return r == 16 && K > 0 && K % kTileK == 0 && K <= 4 * kTileK; }
 
-int elem_fused_parts(int cap, int n_cu)
+int elem_fused_parts(int bf16, int cap, int n_cu)
 {
-    // at least two workgroups per compute unit, at most eight parts
+    // at least the workgroups that fit a compute unit at once on each (two BF16 kernels of four
+    // waves, one float32 kernel of eight), at most eight parts
     const int groups = (cap + kFuseG - 1) / kFuseG;
     if (groups <= 0) return 1;
-    return std::max(1, std::min(8, (2 * n_cu + groups - 1) / groups));
+    const int want = (bf16 ? 2 : 1) * n_cu;
+    return std::max(1, std::min(8, (want + groups - 1) / groups));
 }
 
 // Element physics of one item on one chunk of its rows in LDS (rows of 17
@@ -2301,29 +2303,37 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused(FusedElemArgs a)
     if (e.dseed && part == 0) fused_tail_seeds(e, item, lane);
 }
 
-// The same for float32 contexts: the output map on the FP32 matrix cores.
-// With no BF16 parts the group's activation columns take half the LDS, so the
-// rows of all four items fit at once: one element pass per chunk, wave w on
-// item w (16 tets: two rounds).  Row tiles: wave w takes t = w - ch (mod 4)
-// and t + 4 with all five output tiles, and of the ninth row tile the output
-// tile j = w (the value tile on wave ch mod 4), so the four waves' products
-// per chunk differ by at most one output tile.  Per 16x16x4 product, lane
-// (i, g) supplies W_big[row i][K/4 g + s] and the activation column i at the
-// same k (step s): each lane's A and B values are one contiguous run of K/4.
+// The same for float32 contexts: the output map on the FP32 matrix cores,
+// with the waves specialised.  With no BF16 parts the group's activation
+// columns take half the LDS, so the row buffer holds all four items' rows and
+// fits twice: four producer waves form chunk ch + 1 into one buffer while four
+// consumer waves run the element physics of chunk ch from the other (consumer
+// w on item w, 16 tets: two rounds), one barrier per chunk.  The products no
+// longer wait for the element physics (one workgroup of 8 waves per compute
+// unit: a producer and a consumer wave per SIMD).  Row tiles: producer p takes
+// t = p - ch (mod 4) and t + 4 with all five output tiles, and of the ninth
+// row tile the output tile j = p (the value tile on producer ch mod 4), so the
+// four producers' products per chunk differ by at most one output tile.  Per
+// 16x16x4 product, lane (i, g) supplies W_big[row i][K/4 g + s] and the
+// activation column i at the same k (step s): each lane's A and B values are
+// one contiguous run of K/4.
 template <int KCH>
-__global__ __launch_bounds__(256, 2) void k_elem_fused_f32(FusedElemArgs a)
+__global__ __launch_bounds__(512, 1) void k_elem_fused_f32(FusedElemArgs a)
 {
     constexpr int K = KCH * kTileK;
     constexpr int KS = K / 4;  // products per output tile (k per lane)
     constexpr int LDY = K + 4; // floats per LDS column (16-byte rows, staggered banks)
+    constexpr int JL = kFuseG * kFuseRows * 17;
     __shared__ __align__(16) float Yf[kFuseCols * LDY];
-    __shared__ __align__(16) float Jl[kFuseG * kFuseRows * 17];
+    __shared__ __align__(16) float Jl[2 * JL];
     const ElemArgs& e = a.e;
     const int grp = blockIdx.x / e.parts, part = blockIdx.x - grp * e.parts;
     const int n_items = e.count ? min(*e.count, a.cap) : a.cap;
     if (grp * kFuseG >= n_items) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool producer = wave < 4;
+    const int pw = wave & 3; // producer index, or the consumer's item in the group
     const int li = lane & 15, lg = lane >> 4;
     const int eg = lane >> 3, k = lane & 7;
     const int nc = e.nc;
@@ -2331,7 +2341,7 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused_f32(FusedElemArgs a)
     // the group's activation columns (Jacobian, values, zeros)
     {
         constexpr int Q = K / 4;
-        for (int idx = tid; idx < kFuseCols * Q; idx += 256) {
+        for (int idx = tid; idx < kFuseCols * Q; idx += 512) {
             const int n = idx / Q, q = idx - n * Q;
             int it = n_items, col = 0;
             if (n < 16 * kFuseG) {
@@ -2355,100 +2365,136 @@ __global__ __launch_bounds__(256, 2) void k_elem_fused_f32(FusedElemArgs a)
     const int cb = min(nch, part * per), ce = min(nch, cb + per);
     const float* Af = static_cast<const float*>(a.A);
     auto bcol = [&](int j) { return j < kFuseG ? 16 * j + li : (li < kFuseG ? 16 * kFuseG + li : kFuseCols - 1); };
-    const int item = grp * kFuseG + wave;
-    const bool iok = item < n_items;
+    auto chunk_rows = [&](int ch, int& row0, int& ntile) {
+        const bool tail = ch >= ntc;
+        row0 = tail ? prow + kFuseRows * (ch - ntc) : kFuseRows * ch;
+        ntile = tail ? min(9, (a.rows - row0 + 15) / 16) : 9;
+    };
 
+    // producer p: the rows of chunk ch into the row buffer J
+    auto produce = [&](int ch, float* J) {
+        int row0, ntile;
+        chunk_rows(ch, row0, ntile);
+        const int t0 = (pw - ch) & 3;
+        // row tiles t0, t0 + 4 (all output tiles) and 8 (output tiles in m8)
+        const int m8 = ntile == 9 ? (1 << pw) | (pw == (ch & 3) ? 16 : 0) : 0;
+        const bool u0 = t0 < ntile, u1 = t0 + 4 < ntile;
+        // A fragments of the three row tiles, all loads issued at once (rows
+        // past the padded end re-read the last row: never used)
+        f32x4 af[3][KS / 4];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int t = i < 2 ? t0 + 4 * i : 8;
+            const int row = min(row0 + 16 * t + li, e.rows_pad - 1);
+            const f32x4* p = reinterpret_cast<const f32x4*>(Af + (size_t)row * a.lda + KS * lg);
+#pragma unroll
+            for (int q = 0; q < KS / 4; ++q) af[i][q] = p[q];
+        }
+        // the products of output tiles j and j + 1 (NJ = 2) or j alone for the row tiles in M
+        // (bit i: slot i): one branch per pass, none per product, up to six accumulators
+        // in flight
+        auto prod = [&](auto MC, auto NJC, int j) {
+            constexpr int M = decltype(MC)::value, NJ = decltype(NJC)::value;
+            f32x4 b[NJ][KS / 4];
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const f32x4* bp = reinterpret_cast<const f32x4*>(&Yf[bcol(j + jj) * LDY + KS * lg]);
+#pragma unroll
+                for (int q = 0; q < KS / 4; ++q) b[jj][q] = bp[q];
+            }
+            // every B read issued before the products
+            __builtin_amdgcn_sched_barrier(0);
+            f32x4 acc[NJ][3];
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) acc[jj][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < KS / 4; ++q)
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4)
+#pragma unroll
+                    for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+                            if (((M >> i) & 1) != 0) acc[jj][i] = Mfma<float>::mac(af[i][q][e4], b[jj][q][e4], acc[jj][i]);
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (((M >> i) & 1) == 0) continue; // folded: the loop is unrolled
+                    const int t = i < 2 ? t0 + 4 * i : 8, jo = j + jj;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int m = 16 * t + 4 * lg + v; // row within the chunk
+                        if (jo < kFuseG) {
+                            J[(jo * kFuseRows + m) * 17 + 1 + li] = acc[jj][i][v];
+                        } else if (li < kFuseG) {
+                            const int rg = row0 + m;
+                            J[(li * kFuseRows + m) * 17] = acc[jj][i][v] + (rg < a.rows ? a.bias[rg] : 0.f);
+                        }
+                    }
+                }
+        };
+        using M1 = std::integral_constant<int, 1>;
+        using M3 = std::integral_constant<int, 3>;
+        using M4 = std::integral_constant<int, 4>;
+        using M5 = std::integral_constant<int, 5>;
+        using M7 = std::integral_constant<int, 7>;
+        using J1 = std::integral_constant<int, 1>;
+        using J2 = std::integral_constant<int, 2>;
+        // output tiles (0, 1) and (2, 3) in pairs when both have the same row tiles (tile 8's
+        // output tiles are split over the producers), the value tile alone
+        auto mask_of = [&](int j) { return (u0 ? 1 : 0) | (u1 ? 2 : 0) | (((m8 >> j) & 1) ? 4 : 0); };
+        auto one = [&](int j) {
+            switch (mask_of(j)) {
+            case 1: prod(M1{}, J1{}, j); break;
+            case 3: prod(M3{}, J1{}, j); break;
+            case 4: prod(M4{}, J1{}, j); break;
+            case 5: prod(M5{}, J1{}, j); break;
+            case 7: prod(M7{}, J1{}, j); break;
+            default: break;
+            }
+        };
+#pragma unroll 1
+        for (int j = 0; j < 4; j += 2) {
+            const int m0 = mask_of(j), m1 = mask_of(j + 1);
+            if (m0 == m1 && m0 == 3) prod(M3{}, J2{}, j);
+            else if (m0 == m1 && m0 == 1) prod(M1{}, J2{}, j);
+            else {
+                one(j);
+                one(j + 1);
+            }
+        }
+        one(4);
+    };
+
+    const int item = grp * kFuseG + pw;
+    const bool cok = !producer && item < n_items; // a consumer with an item
     double Hm[4] = {0.0, 0.0, 0.0, 0.0};
     double gk = 0.0, gk2 = 0.0, Ee = 0.0;
 
     lds_barrier(); // the activation columns
+    if (producer && cb < ce) produce(cb, Jl);
+    lds_barrier(); // the first chunk's rows
     for (int ch = cb; ch < ce; ++ch) {
-        const bool tail = ch >= ntc;
-        const int row0 = tail ? prow + kFuseRows * (ch - ntc) : kFuseRows * ch;
-        const int ntile = tail ? min(9, (a.rows - row0 + 15) / 16) : 9;
-        const int t0 = (wave - ch) & 3;
-        // row tiles t0, t0 + 4 (all output tiles) and 8 (output tiles in m8)
-        const int m8 = ntile == 9 ? (1 << wave) | (wave == (ch & 3) ? 16 : 0) : 0;
-        const bool u0 = t0 < ntile, u1 = t0 + 4 < ntile;
-        {
-            // A fragments of the three row tiles, all loads issued at once (rows
-            // past the padded end re-read the last row: never used)
-            f32x4 af[3][KS / 4];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int t = i < 2 ? t0 + 4 * i : 8;
-                const int row = min(row0 + 16 * t + li, e.rows_pad - 1);
-                const f32x4* p = reinterpret_cast<const f32x4*>(Af + (size_t)row * a.lda + KS * lg);
-#pragma unroll
-                for (int q = 0; q < KS / 4; ++q) af[i][q] = p[q];
-            }
-            // the products of output tile j for the row tiles in M (bit i: slot
-            // i), one branch per output tile, none per product
-            auto prod = [&](auto MC, int j) {
-                constexpr int M = decltype(MC)::value;
-                f32x4 b[KS / 4];
-                const f32x4* bp = reinterpret_cast<const f32x4*>(&Yf[bcol(j) * LDY + KS * lg]);
-#pragma unroll
-                for (int q = 0; q < KS / 4; ++q) b[q] = bp[q];
-                // every B read issued before the products (their waits then fall
-                // one by one instead of one read per eight products)
-                __builtin_amdgcn_sched_barrier(0);
-                f32x4 acc[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int q = 0; q < KS / 4; ++q)
-#pragma unroll
-                    for (int e4 = 0; e4 < 4; ++e4)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-                            if (((M >> i) & 1) != 0) acc[i] = Mfma<float>::mac(af[i][q][e4], b[q][e4], acc[i]);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (((M >> i) & 1) == 0) continue; // folded: the loop is unrolled
-                    const int t = i < 2 ? t0 + 4 * i : 8;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int m = 16 * t + 4 * lg + v; // row within the chunk
-                        if (j < kFuseG) {
-                            Jl[(j * kFuseRows + m) * 17 + 1 + li] = acc[i][v];
-                        } else if (li < kFuseG) {
-                            const int rg = row0 + m;
-                            Jl[(li * kFuseRows + m) * 17] = acc[i][v] + (rg < a.rows ? a.bias[rg] : 0.f);
-                        }
-                    }
-                }
-            };
-            using M1 = std::integral_constant<int, 1>;
-            using M3 = std::integral_constant<int, 3>;
-            using M4 = std::integral_constant<int, 4>;
-            using M5 = std::integral_constant<int, 5>;
-            using M7 = std::integral_constant<int, 7>;
-#pragma unroll 1
-            for (int j = 0; j < 5; ++j) {
-                // u1 implies u0; tile 8 exists only where u0 and u1 do
-                const int mask = (u0 ? 1 : 0) | (u1 ? 2 : 0) | (((m8 >> j) & 1) ? 4 : 0);
-                switch (mask) {
-                case 1: prod(M1{}, j); break;
-                case 3: prod(M3{}, j); break;
-                case 4: prod(M4{}, j); break;
-                case 5: prod(M5{}, j); break;
-                case 7: prod(M7{}, j); break;
-                default: break;
-                }
-            }
-        }
-        lds_barrier(); // the chunk's rows
-        if (iok) {
+        float* Jc = Jl + ((ch - cb) & 1) * JL;
+        if (producer) {
+            // the next chunk into the other buffer (read by the consumers of chunk ch - 1,
+            // which the previous barrier closed)
+            if (ch + 1 < ce) produce(ch + 1, Jl + ((ch + 1 - cb) & 1) * JL);
+        } else if (cok) {
+            int row0, ntile;
+            chunk_rows(ch, row0, ntile);
             f32x4 hs = {0.f, 0.f, 0.f, 0.f};
-            fused_item_chunk(e, Jl + wave * kFuseRows * 17, item, tail, ch, ntc, row0, 16 * ntile, 0, 8, eg, k, hs,
+            fused_item_chunk(e, Jc + pw * kFuseRows * 17, item, ch >= ntc, ch, ntc, row0, 16 * ntile, 0, 8, eg, k, hs,
                              gk, gk2, Ee);
 #pragma unroll
             for (int q = 0; q < 4; ++q) Hm[q] += (double)hs[q];
         }
-        lds_barrier(); // the chunk's rows are read
+        lds_barrier(); // chunk ch read, chunk ch + 1 formed
     }
-    if (!iok) return;
+    if (!cok) return;
 
     // g and E over the wave's 8 tet lanes (lanes k, k + 8, ...); H is whole per wave
 #pragma unroll
@@ -2478,11 +2524,11 @@ hipError_t launch_elem_fused(int bf16, const FusedElemArgs& a, hipStream_t s)
         (e.parts > 1 && (e.E || e.part_stride < a.cap)) || a.rows > e.rows_pad || 9 * e.S > a.rows)
         return hipErrorInvalidValue;
     const int groups = (a.cap + kFuseG - 1) / kFuseG;
-    dim3 grid(groups * e.parts), block(256);
+    dim3 grid(groups * e.parts);
 #define RS_FUSED(KC)                                                                   \
     do {                                                                               \
-        if (bf16) RS_LAUNCH((k_elem_fused<KC>), grid, block, 0, s, a);                 \
-        else RS_LAUNCH((k_elem_fused_f32<KC>), grid, block, 0, s, a);                  \
+        if (bf16) RS_LAUNCH((k_elem_fused<KC>), grid, dim3(256), 0, s, a);             \
+        else RS_LAUNCH((k_elem_fused_f32<KC>), grid, dim3(512), 0, s, a);              \
     } while (0)
     switch (a.K / kTileK) {
     case 1: RS_FUSED(1); break;
