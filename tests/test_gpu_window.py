@@ -30,7 +30,8 @@ def _solve(ctx, z0, tg, fo, window, **kw):
 
 
 @pytest.mark.parametrize("name,prec,B,windows", [("c1", rb.PREC_F64, 96, (1, 7, 32)),
-                                                 ("c2", rb.PREC_F32, 2048, (1024, 300))])
+                                                 ("c2", rb.PREC_F32, 2048, (1024, 300)),
+                                                 ("c2", rb.PREC_BF16, 512, (100,))])
 def test_window_matches_whole_batch(name, prec, B, windows):
     p = I.config(name)
     print(f"[window] {name} B={B}", flush=True)
