@@ -17,12 +17,12 @@ reductions, r x r solve, line-search energies and convergence test.
 Metric: converged reduced solves per second (items ending with
 |g|_inf <= 1e-6 |g_0|_inf), whole job, inputs resident in HBM.
 
-Batching: by default the Newton line streams the timed steps' batches (copies
-of the same batch) through one solve with the batch size (1024) in flight: an
-item that finishes gives its place to the next one, so no super-step runs with
-only the slowest items of a batch (continuous batching; every launch still
-holds at most 1024 items).  --batching per-batch solves each step's batch on
-its own, as the other solvers and paths always do.
+Batching: by default the solve lines (Newton and L-BFGS) stream the timed
+steps' batches (copies of the same batch) through one solve with the batch size
+(1024) in flight: an item that finishes gives its place to the next one, so no
+super-step runs with only the slowest items of a batch (continuous batching;
+every launch still holds at most 1024 items).  --batching per-batch solves each
+step's batch on its own, as the other paths always do.
 
 Other lines of the same script:
 * --config c1 / c3: the 10x2x2 beam in float64, or c2 at a batch of 4096 with
@@ -132,10 +132,10 @@ def parse():
     ap.add_argument("--hess", default="exact", choices=["exact", "gn", "gn_psd", "exact_psd"],
                     help="Newton Hessian: exact or Gauss-Newton, optionally with per-element PSD projection")
     ap.add_argument("--batching", default="auto", choices=["auto", "continuous", "per-batch"],
-                    help="continuous (the default for Newton solves): the timed steps' batches (copies of the base "
+                    help="continuous (the default for the solves): the timed steps' batches (copies of the base "
                          "batch) go through one solve with the batch size in flight, a finished item's place "
                          "taken by the next one, plus one Lipschitz evaluation per step; per-batch: one solve per "
-                         "step (the default for the other solvers and paths)")
+                         "step (the default for the other paths)")
     ap.add_argument("--fused", default="auto", choices=["auto", "on", "off"],
                     help="output map and element physics in one kernel (on) or two (off); auto: the "
                          "context's default (on for BF16, off for float32)")
@@ -173,10 +173,10 @@ def main():
         prec = {"f64": rb.PREC_F64, "f32": rb.PREC_F32, "bf16": rb.PREC_BF16}[args.prec]
     dtype = {rb.PREC_F64: "f64", rb.PREC_F32: "f32", rb.PREC_BF16: "bf16"}[prec]
     # continuous batching: the timed steps' batches go through one solve, B items in flight
-    newton_solve_path = args.solver == "newton" and args.path == "solve"
-    if args.batching == "continuous" and not newton_solve_path:
-        raise SystemExit("--batching continuous applies to the Newton solve path")
-    args.stream = args.batching == "continuous" or (args.batching == "auto" and newton_solve_path)
+    solve_path = args.path == "solve"
+    if args.batching == "continuous" and not solve_path:
+        raise SystemExit("--batching continuous applies to the solve path")
+    args.stream = args.batching == "continuous" or (args.batching == "auto" and solve_path)
     nstream = max(args.steps, args.warmup, 1) if args.stream else 1
     ctx = rb.Context(p, prec=prec, max_batch=B * nstream)
     if args.fused == "auto":
@@ -202,6 +202,8 @@ def main():
         opts.window = B
     lbfgs = args.solver == "lbfgs"
     lopts = rb.default_lbfgs_opts()
+    if args.stream:
+        lopts.window = B
     npair = B // 2
     z1, z2 = z0[0:2 * npair:2].contiguous(), z0[1:2 * npair:2].contiguous()
 
@@ -219,7 +221,7 @@ def main():
         zs = z0.repeat(n, 1)
         tgs = tg.repeat(n, 1, 1) if tg is not None else None
         fos = fo.repeat(n, 1) if fo is not None else None
-        res = ctx.newton_solve(zs, tgs, fos, opts=opts)
+        res = ctx.lbfgs_solve(zs, tgs, fos, opts=lopts) if lbfgs else ctx.newton_solve(zs, tgs, fos, opts=opts)
         lip = None
         for _ in range(n):
             lip = ctx.lipschitz_loss(z1, z2, want_per_pair=False) if npair else None

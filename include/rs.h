@@ -189,6 +189,8 @@ typedef struct {
     double shrink;      /* step factor per trial, default 0.5 */
     double rel_tol;     /* |g|_inf <= rel_tol |g_0|_inf, default 1e-6 */
     double abs_tol;     /* or |g|_inf <= abs_tol, default 0 */
+    int32_t window;     /* items in flight, default 0 (all B at once); as rs_solve_opts.window (each item's
+                           history starts at its first step) */
 } rs_lbfgs_opts;
 
 /* Static description of a context (sizes used for work accounting). */

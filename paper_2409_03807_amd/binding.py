@@ -71,7 +71,7 @@ class SolveOpts(C.Structure):
 
 class LbfgsOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ls_max", C.c_int32), ("history", C.c_int32), ("c1", C.c_double),
-                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double)]
+                ("shrink", C.c_double), ("rel_tol", C.c_double), ("abs_tol", C.c_double), ("window", C.c_int32)]
 
 
 class FullOpts(C.Structure):

@@ -546,6 +546,7 @@ extern "C" int rs_default_lbfgs_opts(rs_lbfgs_opts* o)
     o->shrink = 0.5;
     o->rel_tol = 1e-6;
     o->abs_tol = 0.0;
+    o->window = 0;
     return RS_OK;
 }
 
@@ -2071,7 +2072,7 @@ extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* lo
     rs_default_lbfgs_opts(&def);
     if (!o) o = &def;
     if (o->max_iter < 0 || o->ls_max < 0 || o->history < 0 || o->history > RS_MAX_HISTORY ||
-        !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0))
+        !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->c1 >= 0.0) || o->window < 0)
         return fail(c, RS_ERR_ARG, "invalid solver options");
     c->dyn_inertia = 0;
     if (c->ncont > 0 || (load && load->qbar && load->dt > 0.0))
@@ -2085,6 +2086,7 @@ extern "C" int rs_lbfgs_solve(rs_ctx* c, int32_t B, double* z, const rs_load* lo
     p.shrink = o->shrink;
     p.rel_tol = o->rel_tol;
     p.abs_tol = o->abs_tol;
+    p.window = o->window < B ? o->window : 0;
     return solve_batch(c, B, z, load, p, 0, true, iters, status, relgrad, E, stream);
 }
 
