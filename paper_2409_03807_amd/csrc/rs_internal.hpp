@@ -211,6 +211,7 @@ struct NewtonState {
     int* cand_item;   // candidate -> item
     int* cand_j;      // candidate -> trial index
     int* counters;    // [0] n_eval [1] n_cand [2] n_search [3] n_running [4] n_admitted (items 0 .. n_admitted - 1)
+                      // [5] lowest admitted item that may still run (every item below it has ended)
     const double* gw; // eval-list order: g (n_eval x r)
     const double* Hw; // eval-list order: H (n_eval x r x r)
     double* zc;       // candidates x r

@@ -3129,6 +3129,7 @@ __global__ __launch_bounds__(1024) void k_compact_eval(NewtonState st, int B, in
     if (tid == 0) {
         st.counters[0] = base;
         st.counters[4] = A;
+        st.counters[5] = 0;
     }
 }
 
@@ -3165,9 +3166,10 @@ __global__ __launch_bounds__(1024) void k_compact_search(NewtonState st, NewtonP
     __shared__ double ca[1024 * kLsCand];       // chunk candidate -> step length
     const int tid = threadIdx.x, r = p.r;
     const bool lead = blockIdx.x == 0;
-    const int A = min(B, st.counters[4]); // admitted items (the others wait, ls_j < 0)
+    // admitted items (the others wait, ls_j < 0) from the lowest one still running
+    const int A = min(B, st.counters[4]), lo = min(st.counters[5], A);
     int base_s = 0, base_c = 0;
-    for (int b0 = 0; b0 < A; b0 += 1024) {
+    for (int b0 = lo; b0 < A; b0 += 1024) {
         const int b = b0 + tid;
         int f = 0, nc = 0, j = 0;
         if (b < A && st.status[b] == RS_RUNNING && st.ls_j[b] >= 0) {
@@ -3830,7 +3832,9 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     __shared__ int acc_item[1024], acc_cand[1024]; // accepted candidate per chunk search entry (-1: none)
     const int tid = threadIdx.x, r = p.r;
     const int ns = st.counters[2];
-    const int A = min(B, st.counters[4]); // admitted items
+    const int A = min(B, st.counters[4]), lo = min(st.counters[5], A); // admitted items, lowest running
+    __shared__ int lo_next;
+    if (tid == 0) lo_next = A;
     for (int i0 = 0; i0 < ns; i0 += 1024) {
         const int i = i0 + tid;
         int item = -1, cand = -1;
@@ -3889,9 +3893,11 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
     }
     __syncthreads(); // statuses and trial indices of this super-step are final
     int base = 0, running = 0;
-    for (int b0 = 0; b0 < A; b0 += 1024) {
+    for (int b0 = lo; b0 < A; b0 += 1024) {
         const int b = b0 + tid;
         const int run = (b < A && st.status[b] == RS_RUNNING) ? 1 : 0;
+        const unsigned long long rm = __ballot(run); // one LDS atomic per wave: its lowest running item
+        if (rm && (tid & 63) == 0) atomicMin(&lo_next, b + __ffsll((long long)rm) - 1);
         const int f = (run && st.ls_j[b] < 0) ? 1 : 0;
         int tot;
         const int inc = block_scan1024((f << 16) | run, sc, tot);
@@ -3910,6 +3916,7 @@ __global__ __launch_bounds__(1024) void k_armijo(NewtonState st, NewtonParams p,
         st.counters[0] = base;
         st.counters[3] = running;
         st.counters[4] = A + adm;
+        st.counters[5] = lo_next; // items below it have all ended (A when none of [lo, A) runs)
         if (host)
             __hip_atomic_store(host, ((unsigned long long)tag << 32) | (unsigned int)running, __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_SYSTEM);
