@@ -363,6 +363,13 @@ __global__ __launch_bounds__(256) void k_gemm_p(GemmArgs a, int groups)
 // The float32 output map over transposed activations (the reduced solve's
 // gemm_out) is held to 128 registers: four waves per SIMD instead of three
 // hide more of each tile's stores and next-tile loads (5% per launch at c2).
+
+// Offset bias (in floats) of a dropped buffer store: the buffer spans at most
+// kDropBias floats, a valid offset within a tile (at most 64 items of
+// rows_pad x nc, which the launcher checks) is below it, and one or two biases
+// keep the byte offset (times 4) within 32 bits.
+constexpr int kDropBias = 0x10000000;
+
 template <typename T, int ROLE, int KCH, int INM, int OUTM>
 __global__ __launch_bounds__(256, (sizeof(T) == 4 && INM == IN_RAW_T && OUTM == OUT_PACK) ? 4 : 1) void k_gemm_p2(GemmArgs a, int groups)
 {
@@ -456,7 +463,26 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && INM == IN_RAW_T && OUTM == 
     };
 
     T* Cout = static_cast<T*>(a.C);
+    // Float32 packed output through raw buffer stores: an output past the last
+    // row or column gets an offset the hardware drops instead of a branch, so
+    // every thread issues exactly 16 stores on every tile, after the next
+    // tile's activation loads, and the compiler's wait for those loads leaves
+    // the stores in flight.
+    constexpr bool BST = std::is_same<T, float>::value && OUTM == OUT_PACK;
+    if constexpr (BST) {
+        // the lane group's four bias values, in the padding of activation
+        // column 4 wave + lg (never written by the tile fills)
+        if (li == 0) {
+            f32x4 bv;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bv[v] = brow[v];
+            *reinterpret_cast<f32x4*>(&Ys[(wave * 4 + lg) * LD + KT]) = bv;
+        }
+    }
     load(g);
+    // the first tile's activations, waited for here: at the loop's LDS fill the
+    // only loads then pending are the prefetch, with this tile's stores after it
+    if constexpr (BST) __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0)
     for (int ct = g; ct < ntiles; ct += groups) {
         // LDS-only barriers: the previous tile's output stores stay in flight
         lds_barrier(); // the previous tile's LDS reads are done
@@ -468,21 +494,39 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && INM == IN_RAW_T && OUTM == 
         for (int t = 0; t < 4; ++t) acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int c = 0; c < KCH; ++c) {
-            T bf[4][8];
+            if constexpr (BST) {
+                // one column tile's fragments at a time (8 registers, not 32):
+                // the prefetch of the next tile stays in registers
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const V* sb = reinterpret_cast<const V*>(&Ys[(t * 16 + li) * LD + c * kTileK + 8 * lg]);
+                for (int t = 0; t < 4; ++t) {
+                    T bt[8];
+                    const V* sb = reinterpret_cast<const V*>(&Ys[(t * 16 + li) * LD + c * kTileK + 8 * lg]);
 #pragma unroll
-                for (int q = 0; q < 8 / VN; ++q) {
-                    const V w = sb[q];
+                    for (int q = 0; q < 8 / VN; ++q) {
+                        const V w = sb[q];
 #pragma unroll
-                    for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
+                        for (int e = 0; e < VN; ++e) bt[q * VN + e] = w[e];
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk) acc[t] = Mfma<T>::mac(af[c][kk], bt[kk], acc[t]);
                 }
+            } else {
+                T bf[4][8];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const V* sb = reinterpret_cast<const V*>(&Ys[(t * 16 + li) * LD + c * kTileK + 8 * lg]);
+#pragma unroll
+                    for (int q = 0; q < 8 / VN; ++q) {
+                        const V w = sb[q];
+#pragma unroll
+                        for (int e = 0; e < VN; ++e) bf[t][q * VN + e] = w[e];
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[c][kk], bf[t][kk], acc[t]);
             }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) acc[t] = Mfma<T>::mac(af[c][kk], bf[t][kk], acc[t]);
         }
         if constexpr (OUTM == OUT_PACK) {
             // the lane's column n0 + 16 t as (item, cidx), stepped from t = 0;
@@ -492,6 +536,38 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 && INM == IN_RAW_T && OUTM == 
             const bool full = m0 + kTileM <= a.rows && (ct + 1) * kTileN <= ncols;
             int item = (int)((unsigned)n0 / ncu);
             int cidx = n0 - item * nc;
+            if constexpr (BST) {
+                // a raw buffer over the items from the tile's first one on, at
+                // most 1 GiB (a tile's outputs lie within its first 64 items):
+                // offsets past its end, and the biased ones, are dropped
+                const int item0 = (int)((unsigned)(ct * kTileN) / ncu);
+                const size_t ext = (size_t)(items - item0) * item_stride * sizeof(float);
+                const f32x4 bv = *reinterpret_cast<const f32x4*>(&Ys[(wave * 4 + lg) * LD + KT]);
+                const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+                    reinterpret_cast<float*>(Cout) + (size_t)item0 * item_stride, (short)0,
+                    (int)(ext < (size_t)kDropBias * 4 ? ext : (size_t)kDropBias * 4), 0x00020000);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (t > 0) {
+                        item += step_q;
+                        cidx += step_r;
+                        if (cidx >= nc) {
+                            cidx -= nc;
+                            ++item;
+                        }
+                    }
+                    const int cb = (n0 + 16 * t < ncols) ? (item - item0) * (int)item_stride + cidx : kDropBias;
+                    // rows m0 + r4 + v of this lane, r4 from the lane id (not kept live)
+                    const int r4 = __builtin_amdgcn_readfirstlane(wave) * 16 + 4 * (__lane_id() >> 4);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int ro = (m0 + r4 + v < a.rows) ? (m0 + r4 + v) * nc : kDropBias;
+                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[t][v] + (cidx == 0 ? bv[v] : 0.f)),
+                                                              rsrc, (int)((unsigned)(cb + ro) * 4u), 0, 0);
+                    }
+                }
+                continue;
+            }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 if (t > 0) {
@@ -754,6 +830,10 @@ hipError_t launch_gemm_p(int f32, int role, const GemmArgs& a, int target_blocks
     if (groups > ntiles) groups = ntiles;
     if (groups < 1) groups = 1;
     if (f32) {
+        // packed float32 output goes through buffer stores whose valid offsets
+        // (within a tile's items) must stay below the drop bias
+        if (a.out_mode == OUT_PACK && (size_t)a.rows_pad * a.nc * kTileN >= (size_t)kDropBias)
+            return hipErrorInvalidValue;
         if (role == ROLE_DECODE) return gemm_p_dispatch<float, ROLE_DECODE>(a, groups, s);
         return gemm_p_dispatch<float, ROLE_OUT>(a, groups, s);
     }
