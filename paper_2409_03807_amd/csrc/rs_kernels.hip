@@ -659,18 +659,15 @@ __global__ __launch_bounds__(256, KCH <= 4 ? 3 : 1) void k_gemm_p2_bf16(GemmArgs
     const int ynn = tid & 63, ykb = (tid >> 6) * PER;
     f32x4 ry[PER / 4];
     auto load = [&](int ct) {
-        const int yn = ct * kTileN + ynn;
-        if (yn < ncols) {
-            const int yitem = (int)((unsigned)yn / ncu);
-            const int yc = yn - yitem * nc;
-            const f32x4* vp = reinterpret_cast<const f32x4*>(static_cast<const float*>(a.Y) +
-                                                             ((size_t)yitem * nc + yc) * a.y_rows + ykb);
+        // columns past the end load the last column (their products are never
+        // stored), so the loads need no predicate
+        const int yn = min(ct * kTileN + ynn, ncols - 1);
+        const int yitem = (int)((unsigned)yn / ncu);
+        const int yc = yn - yitem * nc;
+        const f32x4* vp = reinterpret_cast<const f32x4*>(static_cast<const float*>(a.Y) +
+                                                         ((size_t)yitem * nc + yc) * a.y_rows + ykb);
 #pragma unroll
-            for (int q = 0; q < PER / 4; ++q) ry[q] = vp[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < PER / 4; ++q) ry[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int q = 0; q < PER / 4; ++q) ry[q] = vp[q];
     };
     auto store = [&]() {
 #pragma unroll
@@ -685,6 +682,10 @@ __global__ __launch_bounds__(256, KCH <= 4 ? 3 : 1) void k_gemm_p2_bf16(GemmArgs
 
     float* Cout = static_cast<float*>(a.C);
     load(g);
+    // packed output leaves through buffer stores with a fixed count per tile
+    // (as in k_gemm_p2): the first tile's loads are waited for here, so the
+    // wait before each later LDS fill leaves the previous tile's stores in flight
+    if constexpr (OUTM == OUT_PACK) __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0)
     for (int ct = g; ct < ntiles; ct += groups) {
         // LDS-only barriers: the previous tile's output stores stay in flight
         lds_barrier(); // the previous tile's LDS reads are done
@@ -706,6 +707,28 @@ __global__ __launch_bounds__(256, KCH <= 4 ? 3 : 1) void k_gemm_p2_bf16(GemmArgs
             }
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] += corr[t];
+        if constexpr (OUTM == OUT_PACK) {
+            const size_t item_stride = (size_t)a.rows_pad * nc;
+            const int item0 = (int)((unsigned)(ct * kTileN) / ncu);
+            const size_t ext = (size_t)(items - item0) * item_stride * sizeof(float);
+            const size_t cap = (size_t)kDropBias * sizeof(float);
+            const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+                Cout + (size_t)item0 * item_stride, (short)0, (int)(ext < cap ? ext : cap), 0x00020000);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int n = ct * kTileN + t * 16 + li;
+                const int item = (int)((unsigned)n / ncu);
+                const int cidx = n - item * nc;
+                const int cb = n < ncols ? (item - item0) * (int)item_stride + cidx : kDropBias;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ro = mrow[v] < a.rows ? mrow[v] * nc : kDropBias;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[t][v] + (cidx == 0 ? brow[v] : 0.f)),
+                                                          rsrc, (int)((unsigned)(cb + ro) * 4u), 0, 0);
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int n = ct * kTileN + t * 16 + li;
@@ -739,6 +762,7 @@ hipError_t launch_gemm_p_bf16(int role, const GemmArgs& a, int target_blocks, hi
 {
     if (a.items <= 0) return hipSuccess;
     if (a.in_mode != IN_RAW_T || a.K % kTileK != 0 || a.ksplit > 1) return hipErrorInvalidValue;
+    if (a.out_mode == OUT_PACK && (size_t)a.rows_pad * a.nc * kTileN >= (size_t)kDropBias) return hipErrorInvalidValue;
     const int kch = a.K / kTileK;
     const int rt = a.rows_pad / kTileM;
     const int ntiles = (a.items * a.nc + kTileN - 1) / kTileN;
