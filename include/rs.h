@@ -212,7 +212,9 @@ int rs_default_lbfgs_opts(rs_lbfgs_opts* o);
  * RS_PREC_F32 or RS_PREC_BF16; max_batch bounds B of every later call (the Lipschitz loss
  * handles up to max_batch/2 pairs per internal pass).  Requires 1 <= r <= 32,
  * n_out == 3 nv, every index in range and every cubature tet of positive
- * volume.  Synchronous.  On failure *out is NULL. */
+ * volume; float32 and BF16 contexts also need rows_pad x (r + 1) < 4194304
+ * (rows of the reduced output map, RS_ERR_UNSUPPORTED otherwise).
+ * Synchronous.  On failure *out is NULL. */
 int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_decoder* dec,
               const rs_cubature* cub, const rs_constraints* con, int32_t prec,
               int32_t max_batch, rs_ctx** out);

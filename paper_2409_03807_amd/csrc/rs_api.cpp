@@ -692,6 +692,10 @@ extern "C" int rs_create(const rs_mesh* mesh, const rs_material* mat, const rs_d
     c->in_rows = round_up(c->in_last, kTileM);
     c->M = 9 * c->S + 3 * c->nt + 4 + c->ncont;
     c->Mp = round_up(c->M, kTileM);
+    // float32 and BF16 output maps store their packed rows through 32-bit buffer
+    // offsets that span at most 64 items of rows_pad x (r + 1) values
+    if (c->f32 && (size_t)c->Mp * (c->r + 1) * kTileN >= ((size_t)1 << 28))
+        return bail(fail(c, RS_ERR_UNSUPPORTED, "reduced row set too large: rows_pad x (r + 1) must be below 4194304"));
     c->grav_row = 9 * c->S + 3 * c->nt;
     c->force_row = c->grav_row + 1;
     c->crow = c->force_row + 3;
