@@ -422,7 +422,7 @@ int rs_simulate(rs_ctx* ctx, int32_t B, double* z, const double* v0, const rs_lo
 /* ---- full-space solver ----
  * Quasi-static equilibrium over EVERY element of the mesh (Sec. 3.1, Eq.
  * form-full-space-time-integration without the inertia term): the snapshot
- * generator of the supervised construction (Sec. 3.2) and the judge of the
+ * generator of the supervised construction (Sec. 3.2) and the reference for the
  * reduced solves.  Projective Newton (supplement): each element Hessian
  * V D^T (d2 psi/dF2) D with its negative eigenvalues set to zero; the Newton
  * system solved by Jacobi-preconditioned conjugate gradients with matrix-free
